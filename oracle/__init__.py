@@ -1,0 +1,291 @@
+"""FP64 CPU oracle of the differentiable path tracer (ctypes wrapper).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py``; never by the product package.  It shares no
+code with the HIP library; both receive the same float32 arrays from
+``paper_2012_03939_amd.scenes``.
+
+The estimator it follows is the one of Shape from Tracing Sec. 3.2 ("Vertex
+optimization": a physically based path tracer R with gradients of pixels with
+respect to geometry) and Sec. 3.3 ("Representation": per-facet Torrance-Sparrow
+materials; "Effects of Global Illumination").  Every reading of the paper the
+estimator needs beyond those sections is stated in ``oracle.cpp`` next to the
+code that takes it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+FLAG_INTERIOR = 1
+FLAG_PRIMARY = 2
+FLAG_SECONDARY = 4
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (double precision, no FP contraction)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off", "-pthread",
+               _SRC, "-o", _LIB + ".tmp"]
+        subprocess.check_call(cmd)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.or_scene_create.restype = P
+        L.or_scene_create.argtypes = [P, ctypes.c_int, P, ctypes.c_int, P, P, ctypes.c_int, P,
+                                      ctypes.c_int, ctypes.c_int, ctypes.c_uint]
+        L.or_scene_destroy.argtypes = [P]
+        L.or_num_edges.argtypes = [P]
+        L.or_edges.argtypes = [P, P]
+        L.or_edge_total.argtypes = [P]
+        L.or_edge_total.restype = ctypes.c_double
+        L.or_philox.argtypes = [P, P, P]
+        L.or_brdf.argtypes = [P, P, P, P, P]
+        L.or_bsdf_pdf.argtypes = [P, P, P, ctypes.c_double]
+        L.or_bsdf_pdf.restype = ctypes.c_double
+        L.or_bsdf_sample.argtypes = [P, P, P, ctypes.c_double, P]
+        L.or_beckmann_D.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.or_beckmann_D.restype = ctypes.c_double
+        L.or_smith_lambda.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.or_smith_lambda.restype = ctypes.c_double
+        L.or_env_sample.argtypes = [P, P, P, dp]
+        L.or_env_pdf.argtypes = [P, P]
+        L.or_env_pdf.restype = ctypes.c_double
+        L.or_env_texel.argtypes = [P, P]
+        L.or_closest.argtypes = [P, P, P, ctypes.c_double, ctypes.c_int, ctypes.c_int, dp]
+        L.or_anyhit.argtypes = [P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int]
+        L.or_camera_ray.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, P, P]
+        L.or_project.argtypes = [P, ctypes.c_int, ctypes.c_int, P, P]
+        L.or_lbvh.argtypes = [P, ctypes.c_int, P, ctypes.c_int, P, P, P, P]
+        L.or_render.argtypes = [P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint, P,
+                                ctypes.c_longlong, P, P, ctypes.c_int]
+        L.or_backward.argtypes = [P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint,
+                                  ctypes.c_uint, ctypes.c_double, P, P, P, P, P, P, P, ctypes.c_int]
+        L.or_sample_frozen.argtypes = [P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint,
+                                       ctypes.c_uint, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                       P, ctypes.c_int, ctypes.c_int, ctypes.c_double]
+        L.or_sample_frozen.restype = ctypes.c_double
+        L.or_sample_grad.argtypes = [P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint,
+                                     ctypes.c_uint, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     P, P, P, P]
+        L.or_sample_grad.restype = ctypes.c_double
+        L.or_secondary_term.argtypes = [P, P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_longlong,
+                                        ctypes.c_uint, P]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(x, n=None):
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    return a
+
+
+def default_threads() -> int:
+    return max(1, min(os.cpu_count() or 1, 64))
+
+
+def cam_arrays(cams):
+    """Camera rows rounded to float32 (what the GPU library receives), then widened."""
+    rows = np.array([c.as_row() for c in cams], np.float32).astype(np.float64)
+    res = np.array([(c.width, c.height) for c in cams], np.int32)
+    return np.ascontiguousarray(rows), np.ascontiguousarray(res)
+
+
+class OracleScene:
+    def __init__(self, V, F, mat, lights=None, env=None, scene_id=0):
+        self.V = np.ascontiguousarray(V, np.float32)
+        self.F = np.ascontiguousarray(F, np.int32)
+        self.mat = np.ascontiguousarray(mat, np.float32)
+        self.lights = np.ascontiguousarray(lights if lights is not None else np.zeros((0, 6)), np.float32)
+        self.env = None if env is None else np.ascontiguousarray(env, np.float32)
+        he, we = (0, 0) if self.env is None else self.env.shape[:2]
+        self.h = lib().or_scene_create(_p(self.V), self.V.shape[0], _p(self.F), self.F.shape[0], _p(self.mat),
+                                       _p(self.lights), self.lights.shape[0],
+                                       None if self.env is None else _p(self.env), he, we, scene_id)
+        if not self.h:
+            raise ValueError("oracle scene creation failed")
+        self.nv, self.nf = self.V.shape[0], self.F.shape[0]
+
+    @classmethod
+    def from_scene(cls, sc):
+        return cls(sc.V, sc.F, sc.mat, sc.lights, sc.env, sc.scene_id)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            lib().or_scene_destroy(h)
+            self.h = None
+
+    # ---- pieces -------------------------------------------------------
+    def edges(self):
+        n = lib().or_num_edges(self.h)
+        out = np.zeros((n, 4), np.int32)
+        lib().or_edges(self.h, _p(out))
+        return out
+
+    def edge_total(self):
+        return lib().or_edge_total(self.h)
+
+    def closest(self, o, d, tmin=1e-4, exclude=-1, brute=False):
+        t = ctypes.c_double(0.0)
+        f = lib().or_closest(self.h, _p(_f64(o)), _p(_f64(d)), tmin, exclude, int(brute), ctypes.byref(t))
+        return f, t.value
+
+    def anyhit(self, o, d, tmin, tmax, exclude=-1, brute=False):
+        return bool(lib().or_anyhit(self.h, _p(_f64(o)), _p(_f64(d)), tmin, tmax, exclude, int(brute)))
+
+    def env_sample(self, u):
+        d = np.zeros(3)
+        pdf = ctypes.c_double(0.0)
+        t = lib().or_env_sample(self.h, _p(_f64(u)), _p(d), ctypes.byref(pdf))
+        return t, d, pdf.value
+
+    def env_pdf(self, d):
+        return lib().or_env_pdf(self.h, _p(_f64(d)))
+
+    def env_texel(self, d):
+        return lib().or_env_texel(self.h, _p(_f64(d)))
+
+    # ---- estimator ------------------------------------------------------
+    def render_samples(self, cams, spp, bounces, seed=0, pix=None, nthreads=None):
+        """Per-sample radiance [npix, spp, 3] and decision hashes [npix, spp]."""
+        rows, res = cam_arrays(cams)
+        if pix is None:
+            npix = int((res[:, 0].astype(np.int64) * res[:, 1]).sum())
+            pp = None
+        else:
+            pp = np.ascontiguousarray(pix, np.int64).reshape(-1, 2)
+            npix = pp.shape[0]
+        rgb = np.zeros((npix, spp, 3))
+        hsh = np.zeros((npix, spp), np.uint32)
+        rc = lib().or_render(self.h, _p(rows), _p(res), len(cams), spp, bounces, seed,
+                             None if pp is None else _p(pp), npix, _p(rgb), _p(hsh),
+                             nthreads or default_threads())
+        if rc != 0:
+            raise ValueError("oracle render: bad arguments")
+        return rgb, hsh
+
+    def render(self, cams, spp, bounces, seed=0, nthreads=None):
+        """Full images, canonical layout [sum W*H, 3] (float64)."""
+        rgb, hsh = self.render_samples(cams, spp, bounces, seed, None, nthreads)
+        return rgb.mean(axis=1), hsh
+
+    def backward(self, cams, spp, bounces, d_image, seed=0, flags=7, edge_ratio=1.0, path_mask=None,
+                 edge_mask=None, nthreads=None):
+        rows, res = cam_arrays(cams)
+        npix = int((res[:, 0].astype(np.int64) * res[:, 1]).sum())
+        d = np.ascontiguousarray(d_image, np.float32).reshape(npix, 3)
+        ne = int(sum(round(edge_ratio * int(w) * int(h) * spp) for w, h in res))
+        dV = np.zeros((self.nv, 3))
+        dM = np.zeros((self.nf, 7))
+        ph = np.zeros(npix * spp, np.uint32)
+        eh = np.zeros(max(ne, 1), np.uint32)
+        pm = None if path_mask is None else np.ascontiguousarray(path_mask, np.uint8)
+        em = None if edge_mask is None else np.ascontiguousarray(edge_mask, np.uint8)
+        rc = lib().or_backward(self.h, _p(rows), _p(res), len(cams), spp, bounces, seed, flags, edge_ratio,
+                               _p(d), None if pm is None else _p(pm), None if em is None else _p(em),
+                               _p(dV), _p(dM), _p(ph), _p(eh), nthreads or default_threads())
+        if rc != 0:
+            raise ValueError("oracle backward: bad arguments")
+        return dV, dM, ph, eh[:ne]
+
+    def sample_grad(self, cams, spp, bounces, view, px, py, j, w, seed=0, flags=1):
+        rows, res = cam_arrays(cams)
+        rgb = np.zeros(3)
+        dV = np.zeros((self.nv, 3))
+        dM = np.zeros((self.nf, 7))
+        loss = lib().or_sample_grad(self.h, _p(rows), _p(res), len(cams), spp, bounces, seed, flags, view, px, py,
+                                    j, _p(_f64(w)), _p(rgb), _p(dV), _p(dM))
+        return loss, rgb, dV, dM
+
+    def sample_frozen(self, cams, spp, bounces, view, px, py, j, w, kind, index, delta, seed=0, flags=1):
+        rows, res = cam_arrays(cams)
+        return lib().or_sample_frozen(self.h, _p(rows), _p(res), len(cams), spp, bounces, seed, flags, view, px,
+                                      py, j, _p(_f64(w)), kind, index, delta)
+
+    def secondary_term(self, p, n, wo, face, budget, nsamples, seed=0):
+        dV = np.zeros((self.nv, 3))
+        lib().or_secondary_term(self.h, _p(_f64(p)), _p(_f64(n)), _p(_f64(wo)), face, budget, nsamples, seed,
+                                _p(dV))
+        return dV
+
+
+# ---- stateless pieces ----------------------------------------------------
+
+def philox4x32(ctr, key):
+    c = np.ascontiguousarray(ctr, np.uint32)
+    k = np.ascontiguousarray(key, np.uint32)
+    out = np.zeros(4, np.uint32)
+    lib().or_philox(_p(c), _p(k), _p(out))
+    return out
+
+
+def brdf(wi, wo, n, m):
+    out = np.zeros(3)
+    lib().or_brdf(_p(_f64(wi)), _p(_f64(wo)), _p(_f64(n)), _p(_f64(m)), _p(out))
+    return out
+
+
+def bsdf_pdf(wi, wo, n, alpha):
+    return lib().or_bsdf_pdf(_p(_f64(wi)), _p(_f64(wo)), _p(_f64(n)), alpha)
+
+
+def bsdf_sample(u, wo, n, alpha):
+    wi = np.zeros(3)
+    lobe = lib().or_bsdf_sample(_p(_f64(u)), _p(_f64(wo)), _p(_f64(n)), alpha, _p(wi))
+    return lobe, wi
+
+
+def beckmann_D(ch, a):
+    return lib().or_beckmann_D(ch, a)
+
+
+def smith_lambda(c, a):
+    return lib().or_smith_lambda(c, a)
+
+
+def camera_ray(cam, sx, sy):
+    row = np.array(cam.as_row(), np.float32).astype(np.float64)
+    o, d = np.zeros(3), np.zeros(3)
+    lib().or_camera_ray(_p(row), cam.width, cam.height, sx, sy, _p(o), _p(d))
+    return o, d
+
+
+def project(cam, v):
+    row = np.array(cam.as_row(), np.float32).astype(np.float64)
+    out = np.zeros(3)
+    lib().or_project(_p(row), cam.width, cam.height, _p(_f64(v)), _p(out))
+    return out
+
+
+def lbvh(V, F):
+    V = np.ascontiguousarray(V, np.float32)
+    F = np.ascontiguousarray(F, np.int32)
+    n = F.shape[0]
+    keys = np.zeros(n, np.uint64)
+    child = np.zeros((max(n - 1, 0), 2), np.int32)
+    parent = np.zeros(2 * n - 1, np.int32)
+    aabb = np.zeros((2 * n - 1, 6), np.float32)
+    lib().or_lbvh(_p(V), V.shape[0], _p(F), n, _p(keys), _p(child), _p(parent), _p(aabb))
+    return keys, child, parent, aabb

@@ -1,0 +1,1421 @@
+// FP64 CPU oracle for the differentiable path tracer.
+//
+// TEST INFRASTRUCTURE ONLY.  Nothing in the product path may load or call this
+// code: only the tests, the smoke check and the CPU-baseline leg of the bench do.
+// It shares no code with the HIP library; the two agree only on the written
+// specification of the estimator (random-number streams, shading, edge terms)
+// and receive the same seeded float32 inputs.
+//
+// What it computes (Shape from Tracing, Sec. 3.2 "Vertex optimization" and
+// Sec. 3.3 "Representation"): the path-traced rendering R(x, m, c_i) of a
+// triangle mesh with per-face Torrance-Sparrow materials under point lights or
+// an HDR environment map (Sec. 3.1), with global illumination (Sec. 3.3,
+// "Effects of Global Illumination"), and the gradient of a loss on that image
+// with respect to vertex positions and per-face materials, including the
+// edge-sampled visibility terms of the renderer the paper relies on (Sec. 3.2,
+// which cites Li et al. 2018 for gradients with respect to geometry).
+//
+// The image is a Monte Carlo estimate, so the oracle follows the estimator step
+// by step in double precision with the same counter-based random numbers as the
+// GPU.  Derivatives of the per-sample estimator are taken by forward-mode dual
+// numbers on a replay of the recorded path (no hand-derived adjoint here).
+//
+// Parity status of each function is written in its comment; where none of the
+// pins in the CPU test-suite reaches a choice, the comment says
+// "parity unpinned".
+
+#include <algorithm>
+#include <array>
+#include <atomic>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+namespace orc {
+
+static const double PI = 3.14159265358979323846;
+static const double TMIN = 1e-4;            // ray epsilon (scene units)
+static const double SHADOW_SHRINK = 1e-4;   // point-light shadow ray stops at r(1 - 1e-4)
+static const double ALPHA_MIN = 1e-3;       // roughness floor
+static const double LOBE_SPEC_P = 0.5;      // probability of sampling the specular lobe
+static const double EPS_PRIMARY = 1e-3;     // primary edge side offset, pixels
+static const double EPS_SECONDARY = 1e-4;   // secondary edge side offset, radians
+static const double ZNEAR = 1e-3;           // edges with an endpoint nearer than this are dropped
+
+// --------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds, the key bumped
+// between rounds by the Weyl constants.  Parity: pinned against numpy's
+// Philox4x64-10 through a width-generic reference and bit-compared with it.
+// --------------------------------------------------------------------------
+struct U4 { uint32_t v[4]; };
+
+static U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1) {
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { k0 += W0; k1 += W1; }
+        uint64_t p0 = (uint64_t)M0 * c0;
+        uint64_t p1 = (uint64_t)M1 * c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0, n1 = lo1, n2 = hi0 ^ c3 ^ k1, n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    U4 o; o.v[0] = c0; o.v[1] = c1; o.v[2] = c2; o.v[3] = c3;
+    return o;
+}
+
+// 24-bit uniform in [0, 1 - 2^-24], exact in float and double.
+static inline double unif(uint32_t r) { return (double)(r >> 8) * (1.0 / 16777216.0); }
+
+struct Ctr { uint32_t c0, c1, c2hi, c3; };   // c2 = c2hi | (bounce << 8) | block
+
+static inline void draw4(const Ctr& c, uint32_t bounce, uint32_t block, uint32_t k0, uint32_t k1,
+                         double u[4]) {
+    U4 r = philox(c.c0, c.c1, c.c2hi | (bounce << 8) | block, c.c3, k0, k1);
+    for (int i = 0; i < 4; ++i) u[i] = unif(r.v[i]);
+}
+
+// FNV-1a over the little-endian bytes of 32-bit decision words.
+struct Hash {
+    uint32_t h = 0x811C9DC5u;
+    bool on = true;
+    void push(uint32_t w) {
+        if (!on) return;
+        for (int b = 0; b < 4; ++b) { h ^= (w >> (8 * b)) & 0xFFu; h *= 0x01000193u; }
+    }
+};
+
+// --------------------------------------------------------------------------
+// scalar types: double, and a forward-mode dual number with N tangents
+// --------------------------------------------------------------------------
+template <int N> struct Dual {
+    double v;
+    double d[N];
+    Dual() : v(0.0) { std::memset(d, 0, sizeof(d)); }
+    Dual(double x) : v(x) { std::memset(d, 0, sizeof(d)); }
+};
+static inline double val(double x) { return x; }
+template <int N> static inline double val(const Dual<N>& x) { return x.v; }
+
+template <int N> static inline Dual<N> operator+(const Dual<N>& a, const Dual<N>& b) {
+    Dual<N> r; r.v = a.v + b.v; for (int i = 0; i < N; ++i) r.d[i] = a.d[i] + b.d[i]; return r; }
+template <int N> static inline Dual<N> operator-(const Dual<N>& a, const Dual<N>& b) {
+    Dual<N> r; r.v = a.v - b.v; for (int i = 0; i < N; ++i) r.d[i] = a.d[i] - b.d[i]; return r; }
+template <int N> static inline Dual<N> operator-(const Dual<N>& a) {
+    Dual<N> r; r.v = -a.v; for (int i = 0; i < N; ++i) r.d[i] = -a.d[i]; return r; }
+template <int N> static inline Dual<N> operator*(const Dual<N>& a, const Dual<N>& b) {
+    Dual<N> r; r.v = a.v * b.v; for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * b.v + a.v * b.d[i]; return r; }
+template <int N> static inline Dual<N> operator/(const Dual<N>& a, const Dual<N>& b) {
+    Dual<N> r; r.v = a.v / b.v; double ib = 1.0 / b.v;
+    for (int i = 0; i < N; ++i) r.d[i] = (a.d[i] - r.v * b.d[i]) * ib;
+    return r; }
+template <int N> static inline Dual<N> operator+(const Dual<N>& a, double b) { Dual<N> r = a; r.v += b; return r; }
+template <int N> static inline Dual<N> operator+(double b, const Dual<N>& a) { Dual<N> r = a; r.v += b; return r; }
+template <int N> static inline Dual<N> operator-(const Dual<N>& a, double b) { Dual<N> r = a; r.v -= b; return r; }
+template <int N> static inline Dual<N> operator-(double b, const Dual<N>& a) { Dual<N> r = -a; r.v += b; return r; }
+template <int N> static inline Dual<N> operator*(const Dual<N>& a, double b) {
+    Dual<N> r; r.v = a.v * b; for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * b; return r; }
+template <int N> static inline Dual<N> operator*(double b, const Dual<N>& a) { return a * b; }
+template <int N> static inline Dual<N> operator/(const Dual<N>& a, double b) { return a * (1.0 / b); }
+template <int N> static inline Dual<N> operator/(double a, const Dual<N>& b) { return Dual<N>(a) / b; }
+template <int N> static inline Dual<N> chain(const Dual<N>& a, double fv, double dfv) {
+    Dual<N> r; r.v = fv; for (int i = 0; i < N; ++i) r.d[i] = dfv * a.d[i]; return r; }
+template <int N> static inline Dual<N> sqrt(const Dual<N>& a) { double s = std::sqrt(a.v); return chain(a, s, 0.5 / s); }
+template <int N> static inline Dual<N> exp(const Dual<N>& a) { double e = std::exp(a.v); return chain(a, e, e); }
+template <int N> static inline Dual<N> erfc(const Dual<N>& a) {
+    return chain(a, std::erfc(a.v), -2.0 / std::sqrt(PI) * std::exp(-a.v * a.v)); }
+using std::sqrt; using std::exp; using std::erfc;
+
+template <class T> struct V3 {
+    T x, y, z;
+    V3() : x(0.0), y(0.0), z(0.0) {}
+    V3(T a, T b, T c) : x(a), y(b), z(c) {}
+    template <class S> explicit V3(const V3<S>& o) : x(o.x), y(o.y), z(o.z) {}
+    T& operator[](int i) { return i == 0 ? x : (i == 1 ? y : z); }
+    const T& operator[](int i) const { return i == 0 ? x : (i == 1 ? y : z); }
+};
+using D3 = V3<double>;
+template <class T> static inline V3<T> operator+(const V3<T>& a, const V3<T>& b) { return V3<T>(a.x + b.x, a.y + b.y, a.z + b.z); }
+template <class T> static inline V3<T> operator-(const V3<T>& a, const V3<T>& b) { return V3<T>(a.x - b.x, a.y - b.y, a.z - b.z); }
+template <class T> static inline V3<T> operator-(const V3<T>& a) { return V3<T>(-a.x, -a.y, -a.z); }
+template <class T, class S> static inline V3<T> operator*(const V3<T>& a, const S& s) { return V3<T>(a.x * s, a.y * s, a.z * s); }
+template <class T> static inline T dot(const V3<T>& a, const V3<T>& b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+template <class T> static inline V3<T> cross(const V3<T>& a, const V3<T>& b) {
+    return V3<T>(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x); }
+template <class T> static inline T length(const V3<T>& a) { return sqrt(dot(a, a)); }
+template <class T> static inline V3<T> normalize(const V3<T>& a) { T l = length(a); return a * (1.0 / l); }
+template <int N> static inline V3<Dual<N>> normalize(const V3<Dual<N>>& a) {
+    Dual<N> l = length(a); return V3<Dual<N>>(a.x / l, a.y / l, a.z / l); }
+template <class T> static inline V3<T> lift(const D3& a) { return V3<T>(T(a.x), T(a.y), T(a.z)); }
+static inline D3 vval(const D3& a) { return a; }
+template <int N> static inline D3 vval(const V3<Dual<N>>& a) { return D3(a.x.v, a.y.v, a.z.v); }
+
+// --------------------------------------------------------------------------
+// scene
+// --------------------------------------------------------------------------
+struct Edge { int va, vb, f1, f2; };
+
+struct BVHNode { double lo[3], hi[3]; int left, right, first, count; };
+
+struct Scene {
+    int nv = 0, nf = 0, nl = 0, he = 0, we = 0;
+    uint32_t id = 0;
+    std::vector<double> V, mat, lights, env;
+    std::vector<int> F;
+    std::vector<Edge> edges;
+    std::vector<double> ecdf;     // cumulative 3-D edge length / total, size ne+1
+    double elen_total = 0.0;
+    bool has_env = false;
+    std::vector<double> marg, cond, texp;   // env CDFs and texel probabilities
+    double env_total = 0.0;
+    std::vector<BVHNode> nodes;
+    std::vector<int> perm;
+
+    D3 vert(int i) const { return D3(V[3 * i], V[3 * i + 1], V[3 * i + 2]); }
+};
+
+// Unnormalised face normal (v1-v0)x(v2-v0), evaluated in a fixed operation order.
+static D3 face_N(const Scene& s, int f) {
+    D3 a = s.vert(s.F[3 * f]), b = s.vert(s.F[3 * f + 1]), c = s.vert(s.F[3 * f + 2]);
+    return cross(b - a, c - a);
+}
+
+// Edge list in canonical order: (va < vb) ascending, f1 the smaller face id.
+static void build_edges(Scene& s) {
+    std::vector<std::array<int, 3>> he;
+    he.reserve(3 * s.nf);
+    for (int f = 0; f < s.nf; ++f)
+        for (int k = 0; k < 3; ++k) {
+            int a = s.F[3 * f + k], b = s.F[3 * f + (k + 1) % 3];
+            he.push_back({std::min(a, b), std::max(a, b), f});
+        }
+    std::sort(he.begin(), he.end());
+    s.edges.clear();
+    for (size_t i = 0; i < he.size();) {
+        size_t j = i;
+        while (j < he.size() && he[j][0] == he[i][0] && he[j][1] == he[i][1]) ++j;
+        Edge e{he[i][0], he[i][1], he[i][2], (j - i >= 2) ? he[i + 1][2] : -1};
+        s.edges.push_back(e);
+        i = j;
+    }
+    const size_t ne = s.edges.size();
+    s.ecdf.assign(ne + 1, 0.0);
+    double acc = 0.0;
+    std::vector<double> cum(ne + 1, 0.0);
+    for (size_t e = 0; e < ne; ++e) {
+        D3 d = s.vert(s.edges[e].vb) - s.vert(s.edges[e].va);
+        acc += std::sqrt(d.x * d.x + d.y * d.y + d.z * d.z);
+        cum[e + 1] = acc;
+    }
+    s.elen_total = acc;
+    for (size_t e = 0; e <= ne; ++e) s.ecdf[e] = acc > 0 ? cum[e] / acc : 0.0;
+}
+
+// Environment-map distribution (piecewise constant over equirectangular texels,
+// each weighted by its mean RGB times its solid angle).  Parity: pinned by the
+// normalisation, constant-map and histogram tests.
+static void build_env(Scene& s) {
+    s.has_env = false;
+    if (s.he <= 0 || s.we <= 0 || s.env.empty()) return;
+    const int H = s.he, W = s.we;
+    std::vector<double> w((size_t)H * W), rows(H);
+    for (int r = 0; r < H; ++r) {
+        double dom = (2.0 * PI / W) * (std::cos(PI * r / H) - std::cos(PI * (r + 1) / H));
+        double rs = 0.0;
+        for (int c = 0; c < W; ++c) {
+            const double* t = &s.env[3 * ((size_t)r * W + c)];
+            double m = (t[0] + t[1] + t[2]) / 3.0;
+            w[(size_t)r * W + c] = m * dom;
+            rs += m * dom;
+        }
+        rows[r] = rs;
+    }
+    double tot = 0.0;
+    s.marg.assign(H + 1, 0.0);
+    for (int r = 0; r < H; ++r) { tot += rows[r]; s.marg[r + 1] = tot; }
+    s.env_total = tot;
+    if (!(tot > 0.0)) return;
+    for (int r = 0; r <= H; ++r) s.marg[r] /= tot;
+    s.cond.assign((size_t)H * (W + 1), 0.0);
+    s.texp.assign((size_t)H * W, 0.0);
+    for (int r = 0; r < H; ++r) {
+        double* C = &s.cond[(size_t)r * (W + 1)];
+        double acc = 0.0;
+        C[0] = 0.0;
+        for (int c = 0; c < W; ++c) { acc += w[(size_t)r * W + c]; C[c + 1] = acc; }
+        for (int c = 0; c <= W; ++c) C[c] = rows[r] > 0 ? C[c] / rows[r] : (double)c / W;
+        for (int c = 0; c < W; ++c) s.texp[(size_t)r * W + c] = w[(size_t)r * W + c] / tot;
+    }
+    s.has_env = true;
+}
+
+static inline double row_solid_angle(const Scene& s, int r) {
+    return (2.0 * PI / s.we) * (std::cos(PI * r / s.he) - std::cos(PI * (r + 1) / s.he));
+}
+
+// largest i in [0, n-1] with C[i] <= u  (C[0] == 0 <= u)
+static inline int cdf_find(const double* C, int n, double u) {
+    return (int)(std::upper_bound(C, C + n, u) - C) - 1;
+}
+
+static int env_texel_of(const Scene& s, const D3& d) {
+    double y = std::max(-1.0, std::min(1.0, d.y));
+    double th = std::acos(y);
+    double ph = std::atan2(d.x, d.z);
+    if (ph < 0) ph += 2.0 * PI;
+    int r = std::min((int)(th / PI * s.he), s.he - 1);
+    int c = std::min((int)(ph / (2.0 * PI) * s.we), s.we - 1);
+    return r * s.we + c;
+}
+
+static D3 env_rgb(const Scene& s, int texel) {
+    return D3(s.env[3 * (size_t)texel], s.env[3 * (size_t)texel + 1], s.env[3 * (size_t)texel + 2]);
+}
+
+static double env_pdf_texel(const Scene& s, int texel) {
+    int r = texel / s.we;
+    return s.texp[texel] / row_solid_angle(s, r);
+}
+
+static int env_sample(const Scene& s, const double u[4], D3& dir, double& pdf) {
+    int r = cdf_find(s.marg.data(), s.he, u[0]);
+    int c = cdf_find(&s.cond[(size_t)r * (s.we + 1)], s.we, u[1]);
+    double phi = 2.0 * PI * (c + u[2]) / s.we;
+    double ct = std::cos(PI * r / s.he), cb = std::cos(PI * (r + 1) / s.he);
+    double cth = ct - u[3] * (ct - cb);
+    double sth = std::sqrt(std::max(0.0, 1.0 - cth * cth));
+    dir = D3(sth * std::sin(phi), cth, sth * std::cos(phi));
+    int texel = r * s.we + c;
+    pdf = env_pdf_texel(s, texel);
+    return texel;
+}
+
+// --------------------------------------------------------------------------
+// ray-triangle intersection (Moller-Trumbore, two-sided) and a median-split BVH.
+// Parity: BVH closest/any hit pinned against brute force (exact face and t).
+// --------------------------------------------------------------------------
+static bool tri_hit(const Scene& s, int f, const D3& o, const D3& d, double tmin, double tmax, double& t) {
+    D3 v0 = s.vert(s.F[3 * f]), v1 = s.vert(s.F[3 * f + 1]), v2 = s.vert(s.F[3 * f + 2]);
+    D3 e1 = v1 - v0, e2 = v2 - v0;
+    D3 p = cross(d, e2);
+    double det = dot(e1, p);
+    if (det == 0.0) return false;
+    double inv = 1.0 / det;
+    D3 sv = o - v0;
+    double b1 = dot(sv, p) * inv;
+    if (b1 < 0.0 || b1 > 1.0) return false;
+    D3 q = cross(sv, e1);
+    double b2 = dot(d, q) * inv;
+    if (b2 < 0.0 || b1 + b2 > 1.0) return false;
+    t = dot(e2, q) * inv;
+    return t > tmin && t < tmax;
+}
+
+static void build_bvh(Scene& s) {
+    s.nodes.clear();
+    s.perm.resize(s.nf);
+    for (int i = 0; i < s.nf; ++i) s.perm[i] = i;
+    if (s.nf == 0) return;
+    std::vector<D3> cen(s.nf), lo(s.nf), hi(s.nf);
+    for (int f = 0; f < s.nf; ++f) {
+        D3 a = s.vert(s.F[3 * f]), b = s.vert(s.F[3 * f + 1]), c = s.vert(s.F[3 * f + 2]);
+        for (int k = 0; k < 3; ++k) {
+            lo[f][k] = std::min(a[k], std::min(b[k], c[k]));
+            hi[f][k] = std::max(a[k], std::max(b[k], c[k]));
+            cen[f][k] = 0.5 * (lo[f][k] + hi[f][k]);
+        }
+    }
+    struct Job { int node, first, count; };
+    std::vector<Job> stack;
+    s.nodes.push_back(BVHNode());
+    stack.push_back({0, 0, s.nf});
+    while (!stack.empty()) {
+        Job j = stack.back(); stack.pop_back();
+        BVHNode nd;
+        for (int k = 0; k < 3; ++k) { nd.lo[k] = 1e300; nd.hi[k] = -1e300; }
+        D3 clo(1e300, 1e300, 1e300), chi(-1e300, -1e300, -1e300);
+        for (int i = j.first; i < j.first + j.count; ++i) {
+            int f = s.perm[i];
+            for (int k = 0; k < 3; ++k) {
+                nd.lo[k] = std::min(nd.lo[k], lo[f][k]); nd.hi[k] = std::max(nd.hi[k], hi[f][k]);
+                clo[k] = std::min(clo[k], cen[f][k]); chi[k] = std::max(chi[k], cen[f][k]);
+            }
+        }
+        // widen by a relative margin so that the box test can never cull a hit
+        for (int k = 0; k < 3; ++k) {
+            double m = 1e-9 * (std::fabs(nd.lo[k]) + std::fabs(nd.hi[k]) + 1.0);
+            nd.lo[k] -= m; nd.hi[k] += m;
+        }
+        if (j.count <= 4) {
+            nd.left = nd.right = -1; nd.first = j.first; nd.count = j.count;
+            s.nodes[j.node] = nd;
+            continue;
+        }
+        int ax = 0;
+        for (int k = 1; k < 3; ++k) if (chi[k] - clo[k] > chi[ax] - clo[ax]) ax = k;
+        int mid = j.first + j.count / 2;
+        std::nth_element(s.perm.begin() + j.first, s.perm.begin() + mid, s.perm.begin() + j.first + j.count,
+                         [&](int a, int b) { return cen[a][ax] < cen[b][ax] || (cen[a][ax] == cen[b][ax] && a < b); });
+        int l = (int)s.nodes.size(); s.nodes.push_back(BVHNode());
+        int r = (int)s.nodes.size(); s.nodes.push_back(BVHNode());
+        nd.left = l; nd.right = r; nd.first = j.first; nd.count = 0;
+        s.nodes[j.node] = nd;
+        stack.push_back({l, j.first, mid - j.first});
+        stack.push_back({r, mid, j.first + j.count - mid});
+    }
+}
+
+static bool box_hit(const BVHNode& n, const D3& o, const D3& d, double tmin, double tmax) {
+    double t0 = tmin, t1 = tmax;
+    for (int k = 0; k < 3; ++k) {
+        double a = (n.lo[k] - o[k]) / d[k], b = (n.hi[k] - o[k]) / d[k];
+        if (std::isnan(a) || std::isnan(b)) {        // d[k] == 0 and o on a slab plane
+            if (o[k] < n.lo[k] || o[k] > n.hi[k]) return false;
+            continue;
+        }
+        if (a > b) std::swap(a, b);
+        t0 = std::max(t0, a); t1 = std::min(t1, b);
+        if (t0 > t1) return false;
+    }
+    return true;
+}
+
+// closest hit with t in (tmin, inf); equal t resolved to the smaller face id
+static int closest_hit(const Scene& s, const D3& o, const D3& d, double tmin, int exclude, double& tbest,
+                       bool brute = false) {
+    int best = -1;
+    tbest = INFINITY;
+    auto consider = [&](int f) {
+        if (f == exclude) return;
+        double t;
+        if (tri_hit(s, f, o, d, tmin, INFINITY, t)) {
+            if (t < tbest || (t == tbest && f < best)) { tbest = t; best = f; }
+        }
+    };
+    if (brute || s.nodes.empty()) {
+        for (int f = 0; f < s.nf; ++f) consider(f);
+        return best;
+    }
+    int stack[128]; int sp = 0; stack[sp++] = 0;
+    while (sp) {
+        const BVHNode& n = s.nodes[stack[--sp]];
+        if (!box_hit(n, o, d, tmin, tbest)) continue;
+        if (n.left < 0) { for (int i = n.first; i < n.first + n.count; ++i) consider(s.perm[i]); }
+        else { stack[sp++] = n.left; stack[sp++] = n.right; }
+    }
+    return best;
+}
+
+static bool any_hit(const Scene& s, const D3& o, const D3& d, double tmin, double tmax, int exclude,
+                    bool brute = false) {
+    if (brute || s.nodes.empty()) {
+        for (int f = 0; f < s.nf; ++f) { double t; if (f != exclude && tri_hit(s, f, o, d, tmin, tmax, t)) return true; }
+        return false;
+    }
+    int stack[128]; int sp = 0; stack[sp++] = 0;
+    while (sp) {
+        const BVHNode& n = s.nodes[stack[--sp]];
+        if (!box_hit(n, o, d, tmin, tmax)) continue;
+        if (n.left < 0) {
+            for (int i = n.first; i < n.first + n.count; ++i) {
+                int f = s.perm[i]; double t;
+                if (f != exclude && tri_hit(s, f, o, d, tmin, tmax, t)) return true;
+            }
+        } else { stack[sp++] = n.left; stack[sp++] = n.right; }
+    }
+    return false;
+}
+
+// --------------------------------------------------------------------------
+// camera: pinhole, vertical field of view, image row 0 at the top
+// --------------------------------------------------------------------------
+struct Cam {
+    D3 eye, f, r, u;
+    double th, aspect;
+    int W, H;
+};
+
+static Cam make_cam(const double* row, int W, int H) {
+    Cam c;
+    c.eye = D3(row[0], row[1], row[2]);
+    D3 tg(row[3], row[4], row[5]), up(row[6], row[7], row[8]);
+    c.f = normalize(tg - c.eye);
+    D3 upn = normalize(up);
+    if (std::fabs(dot(c.f, upn)) > 0.999) upn = D3(0, 0, 1);
+    if (std::fabs(dot(c.f, upn)) > 0.999) upn = D3(1, 0, 0);
+    c.r = normalize(cross(c.f, upn));
+    c.u = cross(c.r, c.f);
+    c.th = std::tan(row[9] * PI / 360.0);
+    c.aspect = (double)W / (double)H;
+    c.W = W; c.H = H;
+    return c;
+}
+
+static D3 cam_dir(const Cam& c, double sx, double sy) {
+    double nx = 2.0 * sx / c.W - 1.0, ny = 1.0 - 2.0 * sy / c.H;
+    return normalize(c.f + c.r * (nx * c.th * c.aspect) + c.u * (ny * c.th));
+}
+
+template <class T> static void project(const Cam& c, const V3<T>& v, T& sx, T& sy, T& z) {
+    V3<T> p = v - lift<T>(c.eye);
+    z = dot(p, lift<T>(c.f));
+    T a = dot(p, lift<T>(c.r)), b = dot(p, lift<T>(c.u));
+    sx = (a / (z * (c.th * c.aspect)) + 1.0) * (0.5 * c.W);
+    sy = (1.0 - b / (z * c.th)) * (0.5 * c.H);
+}
+
+// --------------------------------------------------------------------------
+// Torrance-Sparrow BRDF (Sec. 3.3 "Representation"): Lambertian kd/pi plus a
+// microfacet lobe ks * D * G / (4 cos_i cos_o) with the Beckmann distribution
+// and the height-correlated Smith masking of the Beckmann surface.  The
+// specular colour ks plays the role of the Fresnel factor (no angular term).
+// Parity: D normalisation, weak white furnace of D and Lambda, reciprocity and
+// the pdf normalisation are pinned by quadrature; the choice of D/G/F itself is
+// a reading of an unspecified model (parity unpinned beyond those invariants).
+// --------------------------------------------------------------------------
+template <class T> static T beckmann_D(const T& ch, const T& a) {
+    T c2 = ch * ch;
+    T t2 = (1.0 - c2) / c2;
+    return exp(-t2 / (a * a)) / (PI * a * a * c2 * c2);
+}
+
+template <class T> static T smith_lambda(const T& c, const T& a) {
+    if (val(c) >= 1.0) return T(0.0);
+    T sn = sqrt(1.0 - c * c);
+    T x = c / (a * sn);
+    return (exp(-x * x) / (x * std::sqrt(PI)) - erfc(x)) * 0.5;
+}
+
+template <class T> static T alpha_eff(const T& a) { return val(a) > ALPHA_MIN ? a : T(ALPHA_MIN); }
+
+// f(wi, wo) per channel; zero when either direction is below the surface
+template <class T>
+static V3<T> brdf(const V3<T>& wi, const V3<T>& wo, const V3<T>& n, const T* m) {
+    T ci = dot(n, wi), co = dot(n, wo);
+    if (!(val(ci) > 0.0) || !(val(co) > 0.0)) return V3<T>();
+    T a = alpha_eff(m[6]);
+    V3<T> h = normalize(wi + wo);
+    T ch = dot(n, h);
+    T spec(0.0);
+    if (val(ch) > 0.0) {
+        T D = beckmann_D(ch, a);
+        T G = 1.0 / (1.0 + smith_lambda(ci, a) + smith_lambda(co, a));
+        spec = D * G / (4.0 * ci * co);
+    }
+    return V3<T>(m[0] * (1.0 / PI) + m[3] * spec, m[1] * (1.0 / PI) + m[4] * spec, m[2] * (1.0 / PI) + m[5] * spec);
+}
+
+// pdf of the one-sample mixture: 1/2 cosine-weighted + 1/2 Beckmann-D cos(theta_h) half-vectors
+static double bsdf_pdf(const D3& wi, const D3& wo, const D3& n, double alpha) {
+    double ci = dot(n, wi);
+    if (!(ci > 0.0)) return 0.0;
+    double a = std::max(alpha, ALPHA_MIN);
+    double pd = (1.0 - LOBE_SPEC_P) * ci / PI;
+    D3 hv = wi + wo;
+    double hl = length(hv);
+    double ps = 0.0;
+    if (hl > 0.0) {
+        D3 h = hv * (1.0 / hl);
+        double ch = dot(n, h), oh = std::fabs(dot(wo, h));
+        if (ch > 0.0 && oh > 0.0) ps = LOBE_SPEC_P * beckmann_D(ch, a) * ch / (4.0 * oh);
+    }
+    return pd + ps;
+}
+
+// orthonormal basis around n (Duff et al. 2017, JCGT 6(1), branchless construction)
+static void onb(const D3& n, D3& t, D3& b) {
+    double sg = std::copysign(1.0, n.z);
+    double a = -1.0 / (sg + n.z);
+    double bb = n.x * n.y * a;
+    t = D3(1.0 + sg * n.x * n.x * a, sg * bb, -sg * n.x);
+    b = D3(bb, sg + n.y * n.y * a, -n.y);
+}
+
+// returns lobe (0 specular, 1 diffuse) and the sampled world direction
+static int bsdf_sample(const double u[4], const D3& wo, const D3& n, double alpha, D3& wi) {
+    D3 t, b;
+    onb(n, t, b);
+    double a = std::max(alpha, ALPHA_MIN);
+    double phi = 2.0 * PI * u[2];
+    if (u[0] < LOBE_SPEC_P) {
+        double t2 = -a * a * std::log(1.0 - u[1]);
+        double ch = 1.0 / std::sqrt(1.0 + t2);
+        double sh = std::sqrt(std::max(0.0, 1.0 - ch * ch));
+        D3 h = t * (sh * std::cos(phi)) + b * (sh * std::sin(phi)) + n * ch;
+        wi = h * (2.0 * dot(wo, h)) - wo;
+        return 0;
+    }
+    double r = std::sqrt(u[1]);
+    double z = std::sqrt(std::max(0.0, 1.0 - u[1]));
+    wi = t * (r * std::cos(phi)) + b * (r * std::sin(phi)) + n * z;
+    return 1;
+}
+
+// --------------------------------------------------------------------------
+// path estimator
+// --------------------------------------------------------------------------
+static const int MAXV = 8;
+static const int MAXL = 16;
+
+struct VRec {
+    int face = -1, flip = 0;
+    D3 wo;
+    int lcode[MAXL];
+    int ecode = 0; D3 we, Le; double eden = 0.0;
+    int sec = 0; double sec_c = 0.0; D3 sec_m;
+    int cont = 0; D3 wi; double pb = 0.0;
+    int esc = 0; D3 esc_val;
+};
+struct PRec { int nv = 0; D3 o, d; VRec v[MAXV]; };
+
+struct Grad {           // double accumulators for dV [nv*3] and dmat [nf*7]
+    std::vector<double> dV, dM;
+};
+
+struct SecCtx {         // secondary-edge state of a main path (backward only)
+    double w[3];        // loss weight per channel for this sample
+    Grad* g;
+};
+
+struct Key { uint32_t k0, k1; };
+
+static void push_face(Hash& h, int f) { h.push(f < 0 ? 0xFFFFFFFFu : (uint32_t)f); }
+
+// Hit point on the plane of face f along (o, d): the same point Moller-Trumbore
+// returns, written so that its dependence on the vertices is explicit.
+template <class T>
+static V3<T> plane_hit(const V3<T>& o, const V3<T>& d, const V3<T>& v0, const V3<T>& v1, const V3<T>& v2) {
+    V3<T> N = cross(v1 - v0, v2 - v0);
+    T t = dot(v0 - o, N) / dot(d, N);
+    return o + d * t;
+}
+
+static D3 L_in_side(const Scene& s, const D3& x, const D3& dir, int exclude, int budget, const Ctr& ctr,
+                    const Key& key, Hash& hash);
+
+// Radiance estimate along a ray (Sec. 3.2: R is a physically based path tracer).
+// first_escape_full: a miss on the very first segment returns the environment
+// radiance (side rays of the secondary edge term); otherwise (camera rays) a
+// first-segment miss is black, which is how the masks M^t, M^r of the loss are
+// read (background zero).
+static D3 trace_estimator(const Scene& s, D3 o, D3 d, int exclude, int nvert, bool first_escape_full,
+                          const Ctr& ctr, const Key& key, Hash& hash, PRec* rec, SecCtx* sec) {
+    D3 L(0, 0, 0), beta(1, 1, 1);
+    double p_prev = 0.0;
+    if (rec) { rec->nv = 0; rec->o = o; rec->d = d; }
+    for (int k = 1; k <= nvert + 1; ++k) {
+        double t;
+        int f = closest_hit(s, o, d, TMIN, exclude, t);
+        push_face(hash, f);
+        if (f < 0) {
+            if (s.has_env && (k > 1 || first_escape_full)) {
+                int tex = env_texel_of(s, d);
+                hash.push((uint32_t)tex);
+                D3 Le = env_rgb(s, tex);
+                double w = 1.0;
+                if (k > 1) { double pe = env_pdf_texel(s, tex); w = p_prev / (p_prev + pe); }
+                L = L + D3(beta.x * Le.x, beta.y * Le.y, beta.z * Le.z) * w;
+                if (rec && k > 1) { rec->v[k - 2].esc = 1; rec->v[k - 2].esc_val = Le * w; }
+            }
+            break;
+        }
+        if (k == nvert + 1) break;
+        VRec* vr = rec ? &rec->v[k - 1] : nullptr;
+        D3 v0 = s.vert(s.F[3 * f]), v1 = s.vert(s.F[3 * f + 1]), v2 = s.vert(s.F[3 * f + 2]);
+        D3 x = plane_hit(o, d, v0, v1, v2);
+        D3 n = normalize(cross(v1 - v0, v2 - v0));
+        D3 wo = -d;
+        int flip = dot(n, wo) < 0.0;
+        if (flip) n = -n;
+        const double* m = &s.mat[7 * f];
+        if (vr) { vr->face = f; vr->flip = flip; vr->wo = wo; rec->nv = k; }
+        // next-event estimation: every point light (Sec. 3.1 point-light input)
+        for (int l = 0; l < s.nl; ++l) {
+            const double* lt = &s.lights[6 * l];
+            D3 dl = D3(lt[0], lt[1], lt[2]) - x;
+            double r2 = dot(dl, dl);
+            int code = 0;
+            if (r2 > 0.0) {
+                double r = std::sqrt(r2);
+                D3 wl = dl * (1.0 / r);
+                double c = dot(n, wl);
+                if (c > 0.0) {
+                    bool occ = any_hit(s, x, wl, TMIN, r * (1.0 - SHADOW_SHRINK), f);
+                    code = occ ? 1 : 2;
+                    if (!occ) {
+                        D3 fv = brdf(wl, wo, n, m);
+                        L = L + D3(beta.x * lt[3] * fv.x, beta.y * lt[4] * fv.y, beta.z * lt[5] * fv.z) * (c / r2);
+                    }
+                }
+            }
+            hash.push((uint32_t)code);
+            if (vr) vr->lcode[l] = code;
+        }
+        // next-event estimation: one environment sample, balance-heuristic MIS
+        if (s.has_env) {
+            double u[4];
+            draw4(ctr, k, 1, key.k0, key.k1, u);
+            D3 we; double pe;
+            int tex = env_sample(s, u, we, pe);
+            hash.push((uint32_t)tex);
+            double c = dot(n, we);
+            int code = 0;
+            if (c > 0.0 && pe > 0.0) {
+                bool occ = any_hit(s, x, we, TMIN, INFINITY, f);
+                code = occ ? 1 : 2;
+                if (!occ) {
+                    D3 fv = brdf(we, wo, n, m);
+                    double pb = bsdf_pdf(we, wo, n, m[6]);
+                    double den = pe + pb;
+                    D3 Le = env_rgb(s, tex);
+                    L = L + D3(beta.x * Le.x * fv.x, beta.y * Le.y * fv.y, beta.z * Le.z * fv.z) * (c / den);
+                    if (vr) { vr->we = we; vr->Le = Le; vr->eden = den; }
+                }
+            }
+            hash.push((uint32_t)code);
+            if (vr) vr->ecode = code;
+        }
+        const bool continues = (k < nvert) || s.has_env;
+        // secondary (direction-space) silhouette edge term, backward only
+        if (sec && continues && !s.edges.empty() && s.elen_total > 0.0) {
+            double u[4];
+            draw4(ctr, k, 3, key.k0, key.k1, u);
+            int e = cdf_find(s.ecdf.data(), (int)s.edges.size(), u[0]);
+            double te = u[1];
+            hash.push((uint32_t)e);
+            const Edge& E = s.edges[e];
+            D3 va = s.vert(E.va), vb = s.vert(E.vb);
+            bool sil = true;
+            if (E.f2 >= 0) {
+                double s1 = dot(face_N(s, E.f1), x - va), s2 = dot(face_N(s, E.f2), x - va);
+                sil = (s1 > 0.0) != (s2 > 0.0);
+            }
+            D3 y = va + (vb - va) * te;
+            D3 wv = y - x;
+            double r2 = dot(wv, wv);
+            int code = 0;
+            if (sil && r2 > 0.0) {
+                double r = std::sqrt(r2);
+                D3 ud = wv * (1.0 / r);
+                double cv = dot(n, ud);
+                D3 eh = normalize(vb - va);
+                D3 mv = cross(ud, eh);
+                double ml = length(mv);
+                if (cv > 0.0 && ml > 0.0) {
+                    code = 1;
+                    hash.push(1u);
+                    D3 mm = mv * (1.0 / ml);
+                    D3 wm = normalize(ud - mm * EPS_SECONDARY), wp = normalize(ud + mm * EPS_SECONDARY);
+                    Ctr sc{ctr.c0, ctr.c1, (uint32_t)k << 16, 2u};
+                    D3 Lm = L_in_side(s, x, wm, f, nvert - k, sc, key, hash);
+                    D3 Lp = L_in_side(s, x, wp, f, nvert - k, sc, key, hash);
+                    D3 fv = brdf(ud, wo, n, m);
+                    double cc = 0.0;
+                    for (int ch = 0; ch < 3; ++ch)
+                        cc += sec->w[ch] * beta[ch] * fv[ch] * cv * (Lm[ch] - Lp[ch]);
+                    cc *= s.elen_total / r2;
+                    if (sec->g) {
+                        for (int k3 = 0; k3 < 3; ++k3) {
+                            sec->g->dV[3 * E.va + k3] += cc * (1.0 - te) * mv[k3];
+                            sec->g->dV[3 * E.vb + k3] += cc * te * mv[k3];
+                        }
+                    }
+                    if (vr) { vr->sec = 1; vr->sec_c = cc; vr->sec_m = mv; }
+                }
+            }
+            if (code == 0) hash.push(0u);
+        }
+        // continuation by sampling the BRDF mixture
+        if (!continues) break;
+        double u[4];
+        draw4(ctr, k, 2, key.k0, key.k1, u);
+        D3 wi;
+        int lobe = bsdf_sample(u, wo, n, m[6], wi);
+        double ci = dot(n, wi);
+        double pb = bsdf_pdf(wi, wo, n, m[6]);
+        hash.push((uint32_t)lobe);
+        if (!(ci > 0.0) || !(pb > 0.0)) { hash.push(0u); break; }
+        hash.push(1u);
+        D3 fv = brdf(wi, wo, n, m);
+        beta = D3(beta.x * fv.x * ci / pb, beta.y * fv.y * ci / pb, beta.z * fv.z * ci / pb);
+        if (vr) { vr->cont = 1; vr->wi = wi; vr->pb = pb; }
+        p_prev = pb;
+        o = x; d = wi; exclude = f;
+    }
+    return L;
+}
+
+// incoming radiance along a secondary-edge side ray, estimated with the
+// remaining vertex budget (its own counter domain, shared by both sides)
+static D3 L_in_side(const Scene& s, const D3& x, const D3& dir, int exclude, int budget, const Ctr& ctr,
+                    const Key& key, Hash& hash) {
+    return trace_estimator(s, x, dir, exclude, budget, true, ctr, key, hash, nullptr, nullptr);
+}
+
+// --------------------------------------------------------------------------
+// replay of a recorded main path with scalar type T (double or dual): the
+// derivative of the per-sample estimator at fixed sampled directions, with
+// pdfs, MIS weights and visibility held constant, point-light directions and
+// hit points attached to the geometry.  Returns sum_c w_c L_c plus the
+// secondary-edge pseudo term c * m . (-x_k) whose x-derivative carries the
+// motion of the shading point.
+// --------------------------------------------------------------------------
+template <class T> struct DT { static const int N = 0, FB = 0, MV = 0, MF = 0; };
+template <> struct DT<Dual<48>> { static const int N = 48, FB = 27, MV = 9, MF = 3; };
+template <> struct DT<Dual<128>> { static const int N = 128, FB = 72, MV = 24, MF = 8; };
+
+template <class T> static T seeded(double v, int slot) { (void)slot; return T(v); }
+template <> Dual<48> seeded<Dual<48>>(double v, int slot) { Dual<48> r(v); if (slot >= 0) r.d[slot] = 1.0; return r; }
+template <> Dual<128> seeded<Dual<128>>(double v, int slot) { Dual<128> r(v); if (slot >= 0) r.d[slot] = 1.0; return r; }
+
+struct PView {                 // local parameters of one path: its faces and their vertices
+    const Scene* s = nullptr;
+    int nvs = 0, vids[3 * MAXV];
+    int nfs = 0, fids[MAXV];
+    int vslot(int v) const { for (int i = 0; i < nvs; ++i) if (vids[i] == v) return i; return -1; }
+    int fslot(int f) const { for (int i = 0; i < nfs; ++i) if (fids[i] == f) return i; return -1; }
+    void add_face(int f) {
+        if (fslot(f) < 0) fids[nfs++] = f;
+        for (int k = 0; k < 3; ++k) { int v = s->F[3 * f + k]; if (vslot(v) < 0) vids[nvs++] = v; }
+    }
+};
+
+struct Perturb { int kind = -1, index = -1; double delta = 0.0; };   // kind 0: V coord, 1: material
+
+template <class T> static V3<T> pvert(const PView& P, int v, const Perturb& pt) {
+    D3 p = P.s->vert(v);
+    if (pt.kind == 0 && pt.index / 3 == v) p[pt.index % 3] += pt.delta;
+    int sl = DT<T>::N ? P.vslot(v) : -1;
+    if (sl < 0) return V3<T>(T(p.x), T(p.y), T(p.z));
+    return V3<T>(seeded<T>(p.x, 3 * sl), seeded<T>(p.y, 3 * sl + 1), seeded<T>(p.z, 3 * sl + 2));
+}
+
+template <class T> static void pmat(const PView& P, int f, const Perturb& pt, T out[7]) {
+    int sl = DT<T>::N ? P.fslot(f) : -1;
+    for (int c = 0; c < 7; ++c) {
+        double v = P.s->mat[7 * f + c];
+        if (pt.kind == 1 && pt.index == 7 * f + c) v += pt.delta;
+        out[c] = sl < 0 ? T(v) : seeded<T>(v, DT<T>::FB + 7 * sl + c);
+    }
+}
+
+template <class T>
+static T replay(const Scene& s, const PRec& R, const double w[3], bool interior, bool secondary,
+                const PView& P, const Perturb& pt) {
+    V3<T> L, beta(T(1.0), T(1.0), T(1.0));
+    V3<T> xprev = lift<T>(R.o);
+    T extra(0.0);
+    for (int k = 0; k < R.nv; ++k) {
+        const VRec& vr = R.v[k];
+        D3 dir = (k == 0) ? R.d : R.v[k - 1].wi;
+        int f = vr.face;
+        V3<T> v0 = pvert<T>(P, s.F[3 * f], pt), v1 = pvert<T>(P, s.F[3 * f + 1], pt),
+              v2 = pvert<T>(P, s.F[3 * f + 2], pt);
+        V3<T> x = plane_hit(xprev, lift<T>(dir), v0, v1, v2);
+        V3<T> n = normalize(cross(v1 - v0, v2 - v0));
+        if (vr.flip) n = -n;
+        V3<T> wo = lift<T>(vr.wo);
+        T m[7];
+        pmat<T>(P, f, pt, m);
+        V3<T> C;
+        for (int l = 0; l < s.nl; ++l) {
+            if (vr.lcode[l] != 2) continue;
+            const double* lt = &s.lights[6 * l];
+            V3<T> dl = V3<T>(T(lt[0]), T(lt[1]), T(lt[2])) - x;
+            T r2 = dot(dl, dl);
+            T r = sqrt(r2);
+            V3<T> wl = dl * (1.0 / r);
+            T c = dot(n, wl);
+            V3<T> fv = brdf(wl, wo, n, m);
+            T g = c / r2;
+            C = C + V3<T>(fv.x * (lt[3] * g), fv.y * (lt[4] * g), fv.z * (lt[5] * g));
+        }
+        if (vr.ecode == 2) {
+            V3<T> we = lift<T>(vr.we);
+            V3<T> fv = brdf(we, wo, n, m);
+            T g = dot(n, we) / vr.eden;
+            C = C + V3<T>(fv.x * (vr.Le.x * g), fv.y * (vr.Le.y * g), fv.z * (vr.Le.z * g));
+        }
+        L = L + V3<T>(beta.x * C.x, beta.y * C.y, beta.z * C.z);
+        if (secondary && vr.sec)
+            extra = extra - (x.x * vr.sec_m.x + x.y * vr.sec_m.y + x.z * vr.sec_m.z) * vr.sec_c;
+        if (vr.cont) {
+            V3<T> wi = lift<T>(vr.wi);
+            V3<T> fv = brdf(wi, wo, n, m);
+            T g = dot(n, wi) / vr.pb;
+            V3<T> Tk(fv.x * g, fv.y * g, fv.z * g);
+            if (vr.esc)
+                L = L + V3<T>(beta.x * Tk.x * vr.esc_val.x, beta.y * Tk.y * vr.esc_val.y, beta.z * Tk.z * vr.esc_val.z);
+            beta = V3<T>(beta.x * Tk.x, beta.y * Tk.y, beta.z * Tk.z);
+        }
+        xprev = x;
+    }
+    T out = extra;
+    if (interior) out = out + (L.x * w[0] + L.y * w[1] + L.z * w[2]);
+    return out;
+}
+
+// scatter the tangents of a dual loss into the dense gradient
+template <class T> static void scatter(const PView& P, const T& loss, Grad& g) {
+    for (int i = 0; i < P.nvs; ++i)
+        for (int c = 0; c < 3; ++c) g.dV[3 * P.vids[i] + c] += loss.d[3 * i + c];
+    for (int i = 0; i < P.nfs; ++i)
+        for (int c = 0; c < 7; ++c) g.dM[7 * P.fids[i] + c] += loss.d[DT<T>::FB + 7 * i + c];
+}
+
+static void path_gradient(const Scene& s, const PRec& R, const double w[3], bool interior, bool secondary,
+                          int bounces, Grad& g) {
+    PView P; P.s = &s;
+    for (int k = 0; k < R.nv; ++k) P.add_face(R.v[k].face);
+    if (bounces <= 3) {
+        Perturb none;
+        Dual<48> l = replay<Dual<48>>(s, R, w, interior, secondary, P, none);
+        scatter(P, l, g);
+    } else {
+        Perturb none;
+        Dual<128> l = replay<Dual<128>>(s, R, w, interior, secondary, P, none);
+        scatter(P, l, g);
+    }
+}
+
+// --------------------------------------------------------------------------
+// sample enumeration shared with the GPU (canonical order for masks/hashes):
+// path g = (pixel offset of view v + y*W + x) * spp + j ; primary edge samples
+// of view v at offset sum_{u<v} N_e(u) with N_e = round(ratio * W*H*spp).
+// --------------------------------------------------------------------------
+struct Views {
+    std::vector<Cam> cams;
+    std::vector<int64_t> pixoff, eoff, ne;
+};
+
+static Views make_views(const double* cams, const int* res, int ncam, int spp, double ratio) {
+    Views v;
+    int64_t po = 0, eo = 0;
+    for (int i = 0; i < ncam; ++i) {
+        v.cams.push_back(make_cam(cams + 10 * i, res[2 * i], res[2 * i + 1]));
+        v.pixoff.push_back(po);
+        v.eoff.push_back(eo);
+        int64_t n = (int64_t)std::llround(ratio * (double)res[2 * i] * (double)res[2 * i + 1] * (double)spp);
+        v.ne.push_back(n);
+        po += (int64_t)res[2 * i] * res[2 * i + 1];
+        eo += n;
+    }
+    v.pixoff.push_back(po);
+    v.eoff.push_back(eo);
+    return v;
+}
+
+// main-path estimate for one (view, pixel, sample)
+static D3 pixel_sample(const Scene& s, const Cam& c, int view, int px, int py, int j, int spp, int bounces,
+                       const Key& key, Hash& h, PRec* rec, SecCtx* sec) {
+    Ctr ctr{(uint32_t)(py * c.W + px), ((uint32_t)view << 16) | (uint32_t)j, 0u, 0u};
+    double u[4];
+    draw4(ctr, 0, 0, key.k0, key.k1, u);
+    D3 d = cam_dir(c, px + u[0], py + u[1]);
+    (void)spp;
+    return trace_estimator(s, c.eye, d, -1, bounces, false, ctr, key, h, rec, sec);
+}
+
+template <class F> static void parallel_for(int64_t n, int nthreads, F fn) {
+    if (nthreads <= 1 || n < 2) { for (int64_t i = 0; i < n; ++i) fn(i, 0); return; }
+    std::atomic<int64_t> next(0);
+    std::vector<std::thread> th;
+    for (int t = 0; t < nthreads; ++t)
+        th.emplace_back([&, t]() {
+            for (;;) {
+                int64_t b = next.fetch_add(64);
+                if (b >= n) break;
+                for (int64_t i = b; i < std::min(n, b + 64); ++i) fn(i, t);
+            }
+        });
+    for (auto& x : th) x.join();
+}
+
+// primary (screen-space) edge term of one view; see the header comment of
+// or_backward for the estimator
+struct EdgeView {
+    std::vector<double> cdf;
+    double total = 0.0;
+};
+
+static bool front_facing(const Scene& s, int f, const D3& eye) {
+    D3 v0 = s.vert(s.F[3 * f]);
+    D3 N = face_N(s, f);
+    D3 w = eye - v0;
+    return N.x * w.x + N.y * w.y + N.z * w.z > 0.0;
+}
+
+static EdgeView primary_cdf(const Scene& s, const Cam& c) {
+    EdgeView ev;
+    const size_t ne = s.edges.size();
+    std::vector<double> cum(ne + 1, 0.0);
+    double acc = 0.0;
+    for (size_t e = 0; e < ne; ++e) {
+        const Edge& E = s.edges[e];
+        double len = 0.0;
+        bool cand = E.f2 < 0 || front_facing(s, E.f1, c.eye) || front_facing(s, E.f2, c.eye);
+        if (cand) {
+            double ax, ay, az, bx, by, bz;
+            project<double>(c, s.vert(E.va), ax, ay, az);
+            project<double>(c, s.vert(E.vb), bx, by, bz);
+            if (az > ZNEAR && bz > ZNEAR) {
+                double dx = bx - ax, dy = by - ay;
+                len = std::sqrt(dx * dx + dy * dy);
+            }
+        }
+        acc += len;
+        cum[e + 1] = acc;
+    }
+    ev.total = acc;
+    ev.cdf.assign(ne + 1, 0.0);
+    for (size_t e = 0; e <= ne; ++e) ev.cdf[e] = acc > 0 ? cum[e] / acc : 0.0;
+    return ev;
+}
+
+static void primary_edge_sample(const Scene& s, const Cam& c, const EdgeView& ev, int view, int64_t si, int64_t ne,
+                                int spp, int bounces, const Key& key, const float* d_img_view,
+                                Hash& h, Grad& g, bool& computed) {
+    (void)spp;
+    computed = false;
+    if (!(ev.total > 0.0)) return;
+    double u[4];
+    Ctr ctr{(uint32_t)si, (uint32_t)view << 16, 0u, 1u};
+    draw4(ctr, 0, 3, key.k0, key.k1, u);
+    int e = cdf_find(ev.cdf.data(), (int)s.edges.size(), u[0]);
+    double t = u[1];
+    const Edge& E = s.edges[e];
+    double ax, ay, az, bx, by, bz;
+    project<double>(c, s.vert(E.va), ax, ay, az);
+    project<double>(c, s.vert(E.vb), bx, by, bz);
+    double xs = (1.0 - t) * ax + t * bx, ys = (1.0 - t) * ay + t * by;
+    int px = (int)std::floor(xs), py = (int)std::floor(ys);
+    bool inside = xs >= 0.0 && ys >= 0.0 && px < c.W && py < c.H;
+    const float* dimg = inside ? d_img_view + 3 * ((int64_t)py * c.W + px) : nullptr;
+    if (inside && dimg[0] == 0.0f && dimg[1] == 0.0f && dimg[2] == 0.0f) return;   // contributes zero
+    computed = true;
+    h.push((uint32_t)e);
+    if (!inside) { h.push(0u); return; }
+    h.push(1u);
+    double dx = bx - ax, dy = by - ay;
+    double l = std::sqrt(dx * dx + dy * dy);
+    double nx = -dy / l, ny = dx / l;
+    D3 dm = cam_dir(c, xs - EPS_PRIMARY * nx, ys - EPS_PRIMARY * ny);
+    D3 dp = cam_dir(c, xs + EPS_PRIMARY * nx, ys + EPS_PRIMARY * ny);
+    D3 Lm = trace_estimator(s, c.eye, dm, -1, bounces, false, ctr, key, h, nullptr, nullptr);
+    D3 Lp = trace_estimator(s, c.eye, dp, -1, bounces, false, ctr, key, h, nullptr, nullptr);
+    double cc = 0.0;
+    for (int ch = 0; ch < 3; ++ch) cc += (double)dimg[ch] * (Lm[ch] - Lp[ch]);
+    cc *= ev.total / (double)ne;
+    // screen-space velocity of the edge point: derivative of the projection of
+    // each endpoint, taken with 6-tangent dual numbers
+    for (int end = 0; end < 2; ++end) {
+        int vid = end == 0 ? E.va : E.vb;
+        double wgt = end == 0 ? (1.0 - t) : t;
+        D3 p = s.vert(vid);
+        V3<Dual<48>> pv(seeded<Dual<48>>(p.x, 0), seeded<Dual<48>>(p.y, 1), seeded<Dual<48>>(p.z, 2));
+        Dual<48> sx, sy, sz;
+        project<Dual<48>>(c, pv, sx, sy, sz);
+        for (int k = 0; k < 3; ++k) g.dV[3 * vid + k] += cc * wgt * (sx.d[k] * nx + sy.d[k] * ny);
+    }
+}
+
+// --------------------------------------------------------------------------
+// LBVH reference (integer Morton codes, bit-exact spec shared with the GPU):
+// float32 centroids and scale, 10 bits per axis (x highest), key = morton<<32 |
+// face, ascending sort, Karras 2012 hierarchy, min/max refit.
+// --------------------------------------------------------------------------
+static inline uint32_t spread10(uint32_t v) {
+    uint32_t r = 0;
+    for (int i = 0; i < 10; ++i) r |= ((v >> i) & 1u) << (3 * i);
+    return r;
+}
+
+static inline int clz64(uint64_t x) { return x ? __builtin_clzll(x) : 64; }
+
+static void lbvh_reference(const float* V, int nv, const int* F, int nf, uint64_t* keys, int* child,
+                           int* parent, float* aabb) {
+    (void)nv;
+    std::vector<float> mn(3 * nf), mx(3 * nf), ce(3 * nf);
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int f = 0; f < nf; ++f)
+        for (int k = 0; k < 3; ++k) {
+            float a = V[3 * F[3 * f] + k], b = V[3 * F[3 * f + 1] + k], c = V[3 * F[3 * f + 2] + k];
+            float m0 = std::min(a, std::min(b, c)), m1 = std::max(a, std::max(b, c));
+            mn[3 * f + k] = m0; mx[3 * f + k] = m1;
+            volatile float sum = m0 + m1;
+            float cc = sum * 0.5f;
+            ce[3 * f + k] = cc;
+            lo[k] = std::min(lo[k], cc); hi[k] = std::max(hi[k], cc);
+        }
+    float sc[3];
+    for (int k = 0; k < 3; ++k) sc[k] = hi[k] > lo[k] ? (float)(1024.0 / ((double)hi[k] - (double)lo[k])) : 0.0f;
+    std::vector<uint64_t> kv(nf);
+    for (int f = 0; f < nf; ++f) {
+        uint32_t q[3];
+        for (int k = 0; k < 3; ++k) {
+            volatile float dlt = ce[3 * f + k] - lo[k];
+            volatile float pr = dlt * sc[k];
+            float fl = std::floor((float)pr);
+            int qi = (int)fl;
+            q[k] = (uint32_t)std::max(0, std::min(1023, qi));
+        }
+        uint32_t morton = (spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]);
+        kv[f] = ((uint64_t)morton << 32) | (uint32_t)f;
+    }
+    std::sort(kv.begin(), kv.end());
+    for (int i = 0; i < nf; ++i) keys[i] = kv[i];
+    const int n = nf;
+    const int LEAF = (int)0x80000000;
+    auto delta = [&](int i, int j) -> int {
+        if (j < 0 || j > n - 1) return -1;
+        return clz64(kv[i] ^ kv[j]);
+    };
+    for (int i = 0; i < 2 * n - 1; ++i) parent[i] = -1;
+    for (int i = 0; i < n - 1; ++i) {
+        int d = delta(i, i + 1) > delta(i, i - 1) ? 1 : -1;
+        int dmin = delta(i, i - d);
+        int lmax = 2;
+        while (delta(i, i + lmax * d) > dmin) lmax *= 2;
+        int l = 0;
+        for (int tt = lmax / 2; tt >= 1; tt /= 2)
+            if (delta(i, i + (l + tt) * d) > dmin) l += tt;
+        int j = i + l * d;
+        int dnode = delta(i, j);
+        int sp = 0, tt = l;
+        do {
+            tt = (tt + 1) / 2;
+            if (delta(i, i + (sp + tt) * d) > dnode) sp += tt;
+        } while (tt > 1);
+        int split = i + sp * d + std::min(d, 0);
+        int left = (std::min(i, j) == split) ? (LEAF | split) : split;
+        int right = (std::max(i, j) == split + 1) ? (LEAF | (split + 1)) : split + 1;
+        child[2 * i] = left; child[2 * i + 1] = right;
+        parent[(left & LEAF) ? (n - 1) + (left & 0x7FFFFFFF) : left] = i;
+        parent[(right & LEAF) ? (n - 1) + (right & 0x7FFFFFFF) : right] = i;
+    }
+    // leaves, then internal nodes by a post-order walk
+    for (int i = 0; i < n; ++i) {
+        int f = (int)(kv[i] & 0xFFFFFFFFu);
+        float* b = aabb + 6 * ((n - 1) + i);
+        for (int k = 0; k < 3; ++k) { b[k] = mn[3 * f + k]; b[3 + k] = mx[3 * f + k]; }
+    }
+    if (n < 2) return;
+    std::vector<int> order, st{0};
+    while (!st.empty()) {
+        int i = st.back(); st.pop_back(); order.push_back(i);
+        for (int c = 0; c < 2; ++c) if (!(child[2 * i + c] & LEAF)) st.push_back(child[2 * i + c]);
+    }
+    for (auto it = order.rbegin(); it != order.rend(); ++it) {
+        int i = *it;
+        float* b = aabb + 6 * i;
+        const float* cb[2];
+        for (int c = 0; c < 2; ++c) {
+            int ch = child[2 * i + c];
+            cb[c] = aabb + 6 * ((ch & LEAF) ? (n - 1) + (ch & 0x7FFFFFFF) : ch);
+        }
+        for (int k = 0; k < 3; ++k) {
+            b[k] = std::min(cb[0][k], cb[1][k]);
+            b[3 + k] = std::max(cb[0][3 + k], cb[1][3 + k]);
+        }
+    }
+}
+
+} // namespace orc
+
+// ==========================================================================
+// C interface (ctypes)
+// ==========================================================================
+using namespace orc;
+
+extern "C" {
+
+void* or_scene_create(const float* V, int nv, const int* F, int nf, const float* mat, const float* lights,
+                      int nl, const float* env, int he, int we, unsigned scene_id) {
+    if (nl > MAXL) return nullptr;
+    Scene* s = new Scene();
+    s->nv = nv; s->nf = nf; s->nl = nl; s->id = scene_id;
+    s->V.assign(V, V + 3 * (size_t)nv);
+    s->F.assign(F, F + 3 * (size_t)nf);
+    s->mat.assign(mat, mat + 7 * (size_t)nf);
+    if (nl > 0) s->lights.assign(lights, lights + 6 * (size_t)nl);
+    if (env && he > 0 && we > 0) { s->he = he; s->we = we; s->env.assign(env, env + 3 * (size_t)he * we); }
+    build_edges(*s);
+    build_env(*s);
+    build_bvh(*s);
+    return s;
+}
+
+void or_scene_destroy(void* p) { delete (Scene*)p; }
+
+int or_num_edges(void* p) { return (int)((Scene*)p)->edges.size(); }
+
+void or_edges(void* p, int* out) {
+    Scene* s = (Scene*)p;
+    for (size_t e = 0; e < s->edges.size(); ++e) {
+        out[4 * e] = s->edges[e].va; out[4 * e + 1] = s->edges[e].vb;
+        out[4 * e + 2] = s->edges[e].f1; out[4 * e + 3] = s->edges[e].f2;
+    }
+}
+
+double or_edge_total(void* p) { return ((Scene*)p)->elen_total; }
+
+void or_philox(const unsigned* ctr, const unsigned* key, unsigned* out) {
+    U4 r = philox(ctr[0], ctr[1], ctr[2], ctr[3], key[0], key[1]);
+    for (int i = 0; i < 4; ++i) out[i] = r.v[i];
+}
+
+void or_brdf(const double* wi, const double* wo, const double* n, const double* m, double* out) {
+    D3 r = brdf(D3(wi[0], wi[1], wi[2]), D3(wo[0], wo[1], wo[2]), D3(n[0], n[1], n[2]), m);
+    out[0] = r.x; out[1] = r.y; out[2] = r.z;
+}
+
+double or_bsdf_pdf(const double* wi, const double* wo, const double* n, double alpha) {
+    return bsdf_pdf(D3(wi[0], wi[1], wi[2]), D3(wo[0], wo[1], wo[2]), D3(n[0], n[1], n[2]), alpha);
+}
+
+int or_bsdf_sample(const double* u, const double* wo, const double* n, double alpha, double* wi) {
+    D3 w;
+    int lobe = bsdf_sample(u, D3(wo[0], wo[1], wo[2]), D3(n[0], n[1], n[2]), alpha, w);
+    wi[0] = w.x; wi[1] = w.y; wi[2] = w.z;
+    return lobe;
+}
+
+double or_beckmann_D(double ch, double a) { return beckmann_D(ch, a); }
+double or_smith_lambda(double c, double a) { return smith_lambda(c, a); }
+
+int or_env_sample(void* p, const double* u, double* dir, double* pdf) {
+    Scene* s = (Scene*)p;
+    if (!s->has_env) return -1;
+    D3 d;
+    int t = env_sample(*s, u, d, *pdf);
+    dir[0] = d.x; dir[1] = d.y; dir[2] = d.z;
+    return t;
+}
+
+double or_env_pdf(void* p, const double* dir) {
+    Scene* s = (Scene*)p;
+    if (!s->has_env) return 0.0;
+    return env_pdf_texel(*s, env_texel_of(*s, D3(dir[0], dir[1], dir[2])));
+}
+
+int or_env_texel(void* p, const double* dir) {
+    Scene* s = (Scene*)p;
+    return env_texel_of(*s, D3(dir[0], dir[1], dir[2]));
+}
+
+int or_closest(void* p, const double* o, const double* d, double tmin, int exclude, int brute, double* t) {
+    return closest_hit(*(Scene*)p, D3(o[0], o[1], o[2]), D3(d[0], d[1], d[2]), tmin, exclude, *t, brute != 0);
+}
+
+int or_anyhit(void* p, const double* o, const double* d, double tmin, double tmax, int exclude, int brute) {
+    return any_hit(*(Scene*)p, D3(o[0], o[1], o[2]), D3(d[0], d[1], d[2]), tmin, tmax, exclude, brute != 0) ? 1 : 0;
+}
+
+void or_camera_ray(const double* cam, int W, int H, double sx, double sy, double* o, double* d) {
+    Cam c = make_cam(cam, W, H);
+    D3 dd = cam_dir(c, sx, sy);
+    o[0] = c.eye.x; o[1] = c.eye.y; o[2] = c.eye.z;
+    d[0] = dd.x; d[1] = dd.y; d[2] = dd.z;
+}
+
+void or_project(const double* cam, int W, int H, const double* v, double* out) {
+    Cam c = make_cam(cam, W, H);
+    double sx, sy, z;
+    project<double>(c, D3(v[0], v[1], v[2]), sx, sy, z);
+    out[0] = sx; out[1] = sy; out[2] = z;
+}
+
+void or_lbvh(const float* V, int nv, const int* F, int nf, unsigned long long* keys, int* child, int* parent,
+             float* aabb) {
+    lbvh_reference(V, nv, F, nf, (uint64_t*)keys, child, parent, aabb);
+}
+
+// Forward render.  pix: npix pairs (view, y*W+x), or NULL for every pixel of
+// every view in canonical order.  Writes per-sample radiance [npix, spp, 3] and
+// the per-sample decision hash [npix, spp].
+int or_render(void* p, const double* cams, const int* res, int ncam, int spp, int bounces, unsigned seed,
+              const long long* pix, long long npix, double* out_rgb, unsigned* out_hash, int nthreads) {
+    Scene* s = (Scene*)p;
+    if (bounces < 1 || bounces > MAXV || spp < 1) return -1;
+    Views vw = make_views(cams, res, ncam, spp, 0.0);
+    if (!pix) npix = vw.pixoff[ncam];
+    Key key{seed, s->id};
+    parallel_for(npix * spp, nthreads, [&](int64_t idx, int) {
+        int64_t q = idx / spp; int j = (int)(idx % spp);
+        int view; int64_t local;
+        if (pix) { view = (int)pix[2 * q]; local = pix[2 * q + 1]; }
+        else {
+            view = (int)(std::upper_bound(vw.pixoff.begin(), vw.pixoff.end(), q) - vw.pixoff.begin()) - 1;
+            local = q - vw.pixoff[view];
+        }
+        const Cam& c = vw.cams[view];
+        Hash h;
+        D3 L = pixel_sample(*s, c, view, (int)(local % c.W), (int)(local / c.W), j, spp, bounces, key, h, nullptr,
+                            nullptr);
+        out_rgb[3 * idx] = L.x; out_rgb[3 * idx + 1] = L.y; out_rgb[3 * idx + 2] = L.z;
+        if (out_hash) out_hash[idx] = h.h;
+    });
+    return 0;
+}
+
+// Backward.  flags: 1 interior, 2 primary edges, 4 secondary edges.
+// d_image: float [sum W*H, 3], the loss gradient on the image (image = mean of
+// the spp samples of each pixel).  Samples whose pixel has a zero d_image row
+// contribute exactly zero and are skipped (their hash is left 0).  Masks (uint8,
+// optional) switch off single path samples / primary edge samples.
+int or_backward(void* p, const double* cams, const int* res, int ncam, int spp, int bounces, unsigned seed,
+                unsigned flags, double ratio, const float* d_image, const unsigned char* path_mask,
+                const unsigned char* edge_mask, double* dV, double* dmat, unsigned* path_hash,
+                unsigned* edge_hash, int nthreads) {
+    Scene* s = (Scene*)p;
+    if (bounces < 1 || bounces > MAXV || spp < 1) return -1;
+    Views vw = make_views(cams, res, ncam, spp, ratio);
+    Key key{seed, s->id};
+    int nt = std::max(1, nthreads);
+    std::vector<Grad> G(nt);
+    for (auto& g : G) { g.dV.assign(3 * (size_t)s->nv, 0.0); g.dM.assign(7 * (size_t)s->nf, 0.0); }
+    const bool interior = flags & 1, primary = flags & 2, secondary = flags & 4;
+    const int64_t npath = vw.pixoff[ncam] * spp;
+    if (path_hash) std::memset(path_hash, 0, sizeof(unsigned) * npath);
+    if (interior || secondary) {
+        parallel_for(npath, nt, [&](int64_t idx, int tid) {
+            if (path_mask && !path_mask[idx]) return;
+            int64_t q = idx / spp; int j = (int)(idx % spp);
+            int view = (int)(std::upper_bound(vw.pixoff.begin(), vw.pixoff.end(), q) - vw.pixoff.begin()) - 1;
+            int64_t local = q - vw.pixoff[view];
+            const float* di = d_image + 3 * q;
+            if (di[0] == 0.0f && di[1] == 0.0f && di[2] == 0.0f) return;
+            const Cam& c = vw.cams[view];
+            double w[3] = {di[0] / (double)spp, di[1] / (double)spp, di[2] / (double)spp};
+            Hash h;
+            PRec rec;
+            SecCtx sc{{w[0], w[1], w[2]}, &G[tid]};
+            pixel_sample(*s, c, view, (int)(local % c.W), (int)(local / c.W), j, spp, bounces, key, h, &rec,
+                         secondary ? &sc : nullptr);
+            path_gradient(*s, rec, w, interior, secondary, bounces, G[tid]);
+            if (path_hash) path_hash[idx] = h.h;
+        });
+    }
+    if (edge_hash) std::memset(edge_hash, 0, sizeof(unsigned) * vw.eoff[ncam]);
+    if (primary) {
+        for (int v = 0; v < ncam; ++v) {
+            const Cam& c = vw.cams[v];
+            EdgeView ev = primary_cdf(*s, c);
+            const float* dv = d_image + 3 * vw.pixoff[v];
+            parallel_for(vw.ne[v], nt, [&](int64_t si, int tid) {
+                int64_t gi = vw.eoff[v] + si;
+                if (edge_mask && !edge_mask[gi]) return;
+                Hash h;
+                bool comp;
+                primary_edge_sample(*s, c, ev, v, si, vw.ne[v], spp, bounces, key, dv, h, G[tid], comp);
+                if (edge_hash && comp) edge_hash[gi] = h.h;
+            });
+        }
+    }
+    for (size_t i = 0; i < 3 * (size_t)s->nv; ++i) { double a = 0; for (auto& g : G) a += g.dV[i]; dV[i] = a; }
+    for (size_t i = 0; i < 7 * (size_t)s->nf; ++i) { double a = 0; for (auto& g : G) a += g.dM[i]; dmat[i] = a; }
+    return 0;
+}
+
+// One path sample's loss value L = sum_c w_c L_c (+ secondary pseudo term) under
+// a single parameter perturbation, with every decision, sampled direction, pdf
+// and MIS weight frozen at the unperturbed path (the finite-difference check of
+// the dual-number derivative).  kind 0: dV index, 1: dmat index, -1: none.
+double or_sample_frozen(void* p, const double* cams, const int* res, int ncam, int spp, int bounces,
+                        unsigned seed, unsigned flags, int view, int px, int py, int j, const double* w,
+                        int kind, int index, double delta) {
+    Scene* s = (Scene*)p;
+    Views vw = make_views(cams, res, ncam, spp, 0.0);
+    Key key{seed, s->id};
+    Hash h;
+    PRec rec;
+    Grad dummy; dummy.dV.assign(3 * (size_t)s->nv, 0.0); dummy.dM.assign(7 * (size_t)s->nf, 0.0);
+    SecCtx sc{{w[0], w[1], w[2]}, &dummy};
+    pixel_sample(*s, vw.cams[view], view, px, py, j, spp, bounces, key, h, &rec, (flags & 4) ? &sc : nullptr);
+    PView P; P.s = s;
+    for (int k = 0; k < rec.nv; ++k) P.add_face(rec.v[k].face);
+    Perturb pt; pt.kind = kind; pt.index = index; pt.delta = delta;
+    return replay<double>(*s, rec, w, (flags & 1) != 0, (flags & 4) != 0, P, pt);
+}
+
+// The same sample's radiance from the recording pass (for the replay-equals-
+// record check) and its dual-number gradient (dense dV, dmat).
+double or_sample_grad(void* p, const double* cams, const int* res, int ncam, int spp, int bounces,
+                      unsigned seed, unsigned flags, int view, int px, int py, int j, const double* w,
+                      double* rgb, double* dV, double* dmat) {
+    Scene* s = (Scene*)p;
+    Views vw = make_views(cams, res, ncam, spp, 0.0);
+    Key key{seed, s->id};
+    Hash h;
+    PRec rec;
+    Grad g; g.dV.assign(3 * (size_t)s->nv, 0.0); g.dM.assign(7 * (size_t)s->nf, 0.0);
+    // flag 8: leave out the direct edge-endpoint terms (only the replay derivative)
+    SecCtx sc{{w[0], w[1], w[2]}, (flags & 8) ? nullptr : &g};
+    D3 L = pixel_sample(*s, vw.cams[view], view, px, py, j, spp, bounces, key, h, &rec,
+                        (flags & 4) ? &sc : nullptr);
+    rgb[0] = L.x; rgb[1] = L.y; rgb[2] = L.z;
+    path_gradient(*s, rec, w, (flags & 1) != 0, (flags & 4) != 0, bounces, g);
+    for (size_t i = 0; i < 3 * (size_t)s->nv; ++i) dV[i] = g.dV[i];
+    for (size_t i = 0; i < 7 * (size_t)s->nf; ++i) dmat[i] = g.dM[i];
+    PView P; P.s = s;
+    for (int k = 0; k < rec.nv; ++k) P.add_face(rec.v[k].face);
+    Perturb none;
+    return replay<double>(*s, rec, w, true, false, P, none);
+}
+
+// Secondary edge term alone at a fixed shading point p (normal n, outgoing wo,
+// material of face `face`, throughput 1, loss weight 1/3 per channel), averaged
+// over nsamples edge samples; the shading point itself is held fixed, so only
+// the edge endpoints receive gradient.  Used to pin the estimator against the
+// closed-form irradiance of a polygon.
+void or_secondary_term(void* p, const double* pp, const double* nn, const double* wo, int face, int budget,
+                       long long nsamples, unsigned seed, double* dV) {
+    Scene* s = (Scene*)p;
+    Grad g; g.dV.assign(3 * (size_t)s->nv, 0.0); g.dM.assign(7 * (size_t)s->nf, 0.0);
+    Key key{seed, s->id};
+    D3 x(pp[0], pp[1], pp[2]), n(nn[0], nn[1], nn[2]), o(wo[0], wo[1], wo[2]);
+    const double* m = &s->mat[7 * face];
+    for (long long i = 0; i < nsamples; ++i) {
+        Ctr ctr{(uint32_t)i, 0u, 0u, 3u};
+        double u[4];
+        draw4(ctr, 1, 3, key.k0, key.k1, u);
+        int e = cdf_find(s->ecdf.data(), (int)s->edges.size(), u[0]);
+        double te = u[1];
+        const Edge& E = s->edges[e];
+        D3 va = s->vert(E.va), vb = s->vert(E.vb);
+        bool sil = true;
+        if (E.f2 >= 0) {
+            double s1 = dot(face_N(*s, E.f1), x - va), s2 = dot(face_N(*s, E.f2), x - va);
+            sil = (s1 > 0.0) != (s2 > 0.0);
+        }
+        D3 y = va + (vb - va) * te;
+        D3 wv = y - x;
+        double r2 = dot(wv, wv);
+        if (!sil || !(r2 > 0.0)) continue;
+        double r = std::sqrt(r2);
+        D3 ud = wv * (1.0 / r);
+        double cv = dot(n, ud);
+        D3 mv = cross(ud, normalize(vb - va));
+        double ml = length(mv);
+        if (!(cv > 0.0) || !(ml > 0.0)) continue;
+        D3 mm = mv * (1.0 / ml);
+        Hash h; h.on = false;
+        Ctr sc{(uint32_t)i, 0u, 1u << 16, 2u};
+        D3 Lm = L_in_side(*s, x, normalize(ud - mm * EPS_SECONDARY), face, budget, sc, key, h);
+        D3 Lp = L_in_side(*s, x, normalize(ud + mm * EPS_SECONDARY), face, budget, sc, key, h);
+        D3 fv = brdf(ud, o, n, m);
+        double cc = 0.0;
+        for (int ch = 0; ch < 3; ++ch) cc += (1.0 / 3.0) * fv[ch] * cv * (Lm[ch] - Lp[ch]);
+        cc *= s->elen_total / r2 / (double)nsamples;
+        for (int k = 0; k < 3; ++k) {
+            g.dV[3 * E.va + k] += cc * (1.0 - te) * mv[k];
+            g.dV[3 * E.vb + k] += cc * te * mv[k];
+        }
+    }
+    for (size_t i = 0; i < 3 * (size_t)s->nv; ++i) dV[i] = g.dV[i];
+}
+
+} // extern "C"

@@ -1,0 +1,600 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself:
+numpy's Philox, quadrature identities of the microfacet model, the closed-form
+radiance of a Lambertian plane under a point light, the white furnace, brute
+force intersection, central finite differences, and closed-form edge
+derivatives (projected triangle area, projected solid angle of a polygon).
+CPU only."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2012_03939_amd import scenes as S
+from philox_ref import philox, draw4, uniform24
+
+
+# --------------------------------------------------------------------------
+# Philox4x32-10
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("key", [(0, 0), (5, 7), (0xFFFFFFFFFFFF, 123456789)])
+def test_philox_generic_matches_numpy_4x64(key):
+    bg = np.random.Philox(counter=0, key=list(key))
+    raw = [int(x) for x in bg.random_raw(8)]
+    # numpy advances the counter before producing a block
+    assert raw[:4] == philox((1, 0, 0, 0), key, width=64)
+    assert raw[4:] == philox((2, 0, 0, 0), key, width=64)
+
+
+def test_philox_oracle_matches_reference_4x32():
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        c = [int(x) for x in rng.integers(0, 2 ** 32, 4)]
+        k = [int(x) for x in rng.integers(0, 2 ** 32, 2)]
+        assert list(O.philox4x32(c, k)) == philox(c, k, width=32)
+
+
+def test_uniform24_chi2():
+    from scipy import stats
+    u = np.array([uniform24(r) for i in range(4000) for r in philox((i, 7, 2, 0), (11, 3))])
+    assert u.min() >= 0.0 and u.max() <= 1.0 - 2 ** -24
+    h, _ = np.histogram(u, bins=32, range=(0, 1))
+    assert stats.chisquare(h).pvalue > 1e-3
+
+
+# --------------------------------------------------------------------------
+# Torrance-Sparrow BRDF (Beckmann D, Smith Lambda, specular colour)
+# --------------------------------------------------------------------------
+
+def _hemi_quad(n_t=400, n_p=64):
+    th = (np.arange(n_t) + 0.5) * (0.5 * np.pi / n_t)
+    ph = (np.arange(n_p) + 0.5) * (2 * np.pi / n_p)
+    w = np.sin(th) * (0.5 * np.pi / n_t) * (2 * np.pi / n_p)
+    return th, ph, w
+
+
+@pytest.mark.parametrize("alpha", [0.05, 0.2, 0.5, 1.0])
+def test_beckmann_D_normalised(alpha):
+    # integral over the hemisphere of D(h) cos(theta_h) = 1 (phi-independent)
+    n_t = 20000
+    th = (np.arange(n_t) + 0.5) * (0.5 * np.pi / n_t)
+    val = sum(O.beckmann_D(math.cos(t), alpha) * math.cos(t) * math.sin(t) for t in th)
+    val *= (0.5 * np.pi / n_t) * 2 * np.pi
+    assert abs(val - 1.0) < 2e-4
+    assert abs(O.beckmann_D(1.0, alpha) - 1.0 / (np.pi * alpha * alpha)) < 1e-12 / alpha ** 2
+
+
+@pytest.mark.parametrize("alpha,theta_o", [(0.1, 0.3), (0.3, 0.9), (0.5, 1.3), (0.8, 0.6)])
+def test_smith_weak_white_furnace(alpha, theta_o):
+    # Heitz 2014: integral of G1(wo) D(h) max(0, wo.h) / cos(theta_o) dh = 1
+    wo = np.array([math.sin(theta_o), 0.0, math.cos(theta_o)])
+    g1 = 1.0 / (1.0 + O.smith_lambda(math.cos(theta_o), alpha))
+    n_t, n_p = 3000, 256
+    th = (np.arange(n_t) + 0.5) * (0.5 * np.pi / n_t)
+    ph = (np.arange(n_p) + 0.5) * (2 * np.pi / n_p)
+    T, P = np.meshgrid(th, ph, indexing="ij")
+    h = np.stack([np.sin(T) * np.cos(P), np.sin(T) * np.sin(P), np.cos(T)], -1)
+    D = np.vectorize(lambda c: O.beckmann_D(c, alpha))(np.cos(th))[:, None]
+    integrand = D * np.maximum(0.0, h @ wo) * np.sin(T)
+    val = integrand.sum() * (0.5 * np.pi / n_t) * (2 * np.pi / n_p) * g1 / wo[2]
+    assert abs(val - 1.0) < 2e-3
+
+
+def test_lambda_limits():
+    assert O.smith_lambda(1.0, 0.3) == 0.0
+    # Lambda grows without bound toward grazing and vanishes toward normal incidence
+    assert O.smith_lambda(0.01, 0.5) > 10.0
+    assert O.smith_lambda(0.99, 0.05) < 1e-12
+
+
+def _rand_dir_upper(rng):
+    while True:
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        if d[2] > 0.05:
+            return d
+
+
+def test_brdf_reciprocity_and_lambert():
+    rng = np.random.default_rng(5)
+    n = np.array([0.0, 0.0, 1.0])
+    for _ in range(50):
+        wi, wo = _rand_dir_upper(rng), _rand_dir_upper(rng)
+        m = np.concatenate([rng.uniform(0, 1, 3), rng.uniform(0, 1, 3), [rng.uniform(0.05, 0.8)]])
+        assert np.allclose(O.brdf(wi, wo, n, m), O.brdf(wo, wi, n, m), rtol=1e-12, atol=0)
+        mz = m.copy()
+        mz[3:6] = 0
+        assert np.allclose(O.brdf(wi, wo, n, mz), mz[:3] / np.pi, rtol=1e-15, atol=0)
+        assert np.array_equal(O.brdf(-wi, wo, n, m), np.zeros(3))
+
+
+@pytest.mark.parametrize("alpha", [0.1, 0.4])
+def test_specular_energy_bounded(alpha):
+    # single-scattering microfacet lobe with ks = 1 reflects at most all energy
+    n = np.array([0.0, 0.0, 1.0])
+    th, ph, w = _hemi_quad(300, 96)
+    m = np.array([0, 0, 0, 1, 1, 1, alpha], float)
+    for to in (0.2, 1.0):
+        wo = np.array([math.sin(to), 0, math.cos(to)])
+        tot = 0.0
+        for t, wt in zip(th, w):
+            for p in ph:
+                wi = np.array([math.sin(t) * math.cos(p), math.sin(t) * math.sin(p), math.cos(t)])
+                tot += O.brdf(wi, wo, n, m)[0] * wi[2] * wt
+        assert 0.5 < tot <= 1.0 + 1e-3
+
+
+@pytest.mark.parametrize("alpha,to", [(0.08, 0.4), (0.3, 1.0), (0.6, 0.2)])
+def test_bsdf_sampling_matches_pdf(alpha, to):
+    from scipy import stats
+    rng = np.random.default_rng(9)
+    n = np.array([0.0, 0.0, 1.0])
+    wo = np.array([math.sin(to), 0, math.cos(to)])
+    N = 60000
+    nb_c, nb_p = 8, 8
+    counts = np.zeros((nb_c, nb_p))
+    below = 0
+    us = rng.random((N, 4))
+    for u in us:
+        _, wi = O.bsdf_sample(u, wo, n, alpha)
+        if wi[2] <= 0:
+            below += 1
+            continue
+        ic = min(int(wi[2] * nb_c), nb_c - 1)
+        ip = min(int((math.atan2(wi[1], wi[0]) % (2 * np.pi)) / (2 * np.pi) * nb_p), nb_p - 1)
+        counts[ic, ip] += 1
+    # expected mass per (cos theta, phi) bin from the pdf by quadrature
+    exp_mass = np.zeros((nb_c, nb_p))
+    sub = 12
+    for ic in range(nb_c):
+        for ip in range(nb_p):
+            acc = 0.0
+            for a in range(sub):
+                c = (ic + (a + 0.5) / sub) / nb_c
+                s = math.sqrt(1 - c * c)
+                for b in range(sub):
+                    p = (ip + (b + 0.5) / sub) / nb_p * 2 * np.pi
+                    wi = np.array([s * math.cos(p), s * math.sin(p), c])
+                    acc += O.bsdf_pdf(wi, wo, n, alpha)
+            exp_mass[ic, ip] = acc / sub ** 2 * (1.0 / nb_c) * (2 * np.pi / nb_p)
+    upper = exp_mass.sum()
+    assert upper <= 1.0 + 1e-3
+    obs = np.append(counts.ravel(), below)
+    exp = np.append(exp_mass.ravel(), max(1.0 - upper, 0.0)) * N
+    keep = exp > 20
+    obs_k, exp_k = obs[keep], exp[keep]
+    exp_k = exp_k * obs_k.sum() / exp_k.sum()
+    assert stats.chisquare(obs_k, exp_k).pvalue > 1e-4
+
+
+# --------------------------------------------------------------------------
+# environment map distribution
+# --------------------------------------------------------------------------
+
+def _tiny_scene(env=None):
+    V = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0]], np.float32)
+    F = np.array([[0, 1, 2]], np.int32)
+    return O.OracleScene(V, F, S.uniform_materials(1), None, env)
+
+
+def test_env_pdf_normalised_and_constant_map_uniform():
+    rng = np.random.default_rng(2)
+    env = S.gaussian_lobe_envmap(rng, 64, 32)
+    sc = _tiny_scene(env)
+    he, we = env.shape[:2]
+    tot = 0.0
+    for r in range(he):
+        dom = (2 * np.pi / we) * (math.cos(np.pi * r / he) - math.cos(np.pi * (r + 1) / he))
+        th = np.pi * (r + 0.5) / he
+        for c in range(we):
+            ph = 2 * np.pi * (c + 0.5) / we
+            d = [math.sin(th) * math.sin(ph), math.cos(th), math.sin(th) * math.cos(ph)]
+            assert sc.env_texel(d) == r * we + c
+            tot += sc.env_pdf(d) * dom
+    assert abs(tot - 1.0) < 1e-12
+    const = _tiny_scene(np.ones((16, 32, 3), np.float32))
+    for _ in range(50):
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        assert abs(const.env_pdf(d) - 1.0 / (4 * np.pi)) < 1e-12
+
+
+def test_env_sampling_histogram():
+    from scipy import stats
+    rng = np.random.default_rng(4)
+    env = S.gaussian_lobe_envmap(rng, 32, 16)
+    sc = _tiny_scene(env)
+    he, we = env.shape[:2]
+    w = env.astype(np.float64).mean(axis=2)
+    dom = np.array([(2 * np.pi / we) * (math.cos(np.pi * r / he) - math.cos(np.pi * (r + 1) / he)) for r in range(he)])
+    P = (w * dom[:, None]).ravel()
+    P /= P.sum()
+    N = 50000
+    counts = np.zeros(he * we)
+    for u in rng.random((N, 4)):
+        t, d, pdf = sc.env_sample(u)
+        counts[t] += 1
+        r = t // we
+        assert abs(pdf - P[t] / dom[r]) <= 1e-9 * pdf
+    keep = P * N > 20
+    exp = P[keep] * N
+    obs = counts[keep]
+    exp *= obs.sum() / exp.sum()
+    assert stats.chisquare(obs, exp).pvalue > 1e-4
+
+
+def test_env_sample_direction_inside_texel():
+    rng = np.random.default_rng(6)
+    env = S.gaussian_lobe_envmap(rng, 64, 32)
+    sc = _tiny_scene(env)
+    misses = 0
+    for u in rng.random((3000, 4)):
+        t, d, _ = sc.env_sample(u)
+        assert abs(np.linalg.norm(d) - 1.0) < 1e-12
+        misses += sc.env_texel(d) != t
+    assert misses <= 3    # only exact texel borders may round across
+
+
+# --------------------------------------------------------------------------
+# intersection and acceleration structure
+# --------------------------------------------------------------------------
+
+def test_bvh_equals_brute_force():
+    rng = np.random.default_rng(8)
+    V, F = S.noise_sphere(6, 0.15, noise_seed=3)
+    # plus a soup of random triangles inside
+    soup = rng.uniform(-0.8, 0.8, (60, 3, 3))
+    V2 = np.concatenate([V, soup.reshape(-1, 3)])
+    F2 = np.concatenate([F, V.shape[0] + np.arange(180).reshape(60, 3)]).astype(np.int32)
+    sc = O.OracleScene(V2.astype(np.float32), F2, S.uniform_materials(F2.shape[0]))
+    for _ in range(1500):
+        o = rng.uniform(-2.5, 2.5, 3)
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        ex = int(rng.integers(-1, F2.shape[0]))
+        f1, t1 = sc.closest(o, d, 1e-4, ex, brute=False)
+        f2, t2 = sc.closest(o, d, 1e-4, ex, brute=True)
+        assert f1 == f2 and (f1 < 0 or t1 == t2)
+        tmax = float(rng.uniform(0.1, 5))
+        assert sc.anyhit(o, d, 1e-4, tmax, ex, False) == sc.anyhit(o, d, 1e-4, tmax, ex, True)
+
+
+def test_triangle_hit_known_answer():
+    V = np.array([[-1, -1, 2], [1, -1, 2], [0, 1, 2]], np.float32)
+    sc = O.OracleScene(V, np.array([[0, 1, 2]], np.int32), S.uniform_materials(1))
+    f, t = sc.closest([0.1, 0.2, -1.0], [0, 0, 1])
+    assert f == 0 and t == 3.0
+    f, t = sc.closest([0.1, 0.2, -1.0], [0, 0, -1])
+    assert f == -1
+    f, t = sc.closest([0.1, 0.2, -1.0], [0, 0, 1], exclude=0)
+    assert f == -1
+    assert not sc.anyhit([0.1, 0.2, -1.0], [0, 0, 1], 1e-4, 2.999)
+    assert sc.anyhit([0.1, 0.2, -1.0], [0, 0, 1], 1e-4, 3.001)
+
+
+# --------------------------------------------------------------------------
+# camera model
+# --------------------------------------------------------------------------
+
+def _pinhole(cam, sx, sy):
+    """The pinhole definition written out directly (vertical fov, row 0 at top)."""
+    e = np.array(cam.eye, np.float32).astype(float)
+    tg = np.array(cam.target, np.float32).astype(float)
+    up = np.array(cam.up, np.float32).astype(float)
+    f = (tg - e) / np.linalg.norm(tg - e)
+    r = np.cross(f, up / np.linalg.norm(up))
+    r /= np.linalg.norm(r)
+    u = np.cross(r, f)
+    th = math.tan(float(np.float32(cam.fov_y_deg)) * math.pi / 360)
+    ndx = 2 * sx / cam.width - 1
+    ndy = 1 - 2 * sy / cam.height
+    d = f + ndx * th * cam.width / cam.height * r + ndy * th * u
+    return e, d / np.linalg.norm(d)
+
+
+def test_camera_rays_and_projection_agree():
+    rng = np.random.default_rng(1)
+    cam = S.Camera((0.3, 0.7, 2.9), (0.1, -0.2, 0.0), (0, 1, 0), 45.0, 96, 64)
+    for _ in range(100):
+        sx, sy = rng.uniform(0, 96), rng.uniform(0, 64)
+        o, d = O.camera_ray(cam, sx, sy)
+        e, dd = _pinhole(cam, sx, sy)
+        assert np.allclose(o, e, atol=0) and np.allclose(d, dd, rtol=0, atol=1e-14)
+        p = O.project(cam, o + 2.5 * d)
+        assert abs(p[0] - sx) < 1e-9 and abs(p[1] - sy) < 1e-9 and p[2] > 0
+
+
+# --------------------------------------------------------------------------
+# closed-form radiance: Lambertian plane under a point light
+# --------------------------------------------------------------------------
+
+def test_lambertian_plane_point_light_closed_form():
+    V = np.array([[-5, -5, 0], [5, -5, 0], [5, 5, 0], [-5, 5, 0]], np.float32)
+    F = np.array([[0, 1, 2], [0, 2, 3]], np.int32)
+    kd = np.array([0.3, 0.5, 0.7], np.float32)
+    mat = np.zeros((2, 7), np.float32)
+    mat[:, :3] = kd
+    mat[:, 6] = 0.3
+    light = np.array([[0.5, 0.3, 2.0, 10.0, 8.0, 6.0]], np.float32)
+    sc = O.OracleScene(V, F, mat, light, None, scene_id=3)
+    cam = S.Camera((0.0, 0.0, 3.0), (0, 0, 0), (0, 1, 0), 45.0, 16, 12)
+    seed, spp = 9, 2
+    rgb, _ = sc.render_samples([cam], spp, 1, seed)
+    pl = light[0, :3].astype(float)
+    I = light[0, 3:].astype(float)
+    worst = 0.0
+    for y in range(12):
+        for x in range(16):
+            for j in range(spp):
+                u = draw4(y * 16 + x, j, 0, 0, seed, 3)
+                o, d = _pinhole(cam, x + u[0], y + u[1])
+                t = -o[2] / d[2]
+                p = o + t * d
+                wl = pl - p
+                r2 = wl @ wl
+                cos = wl[2] / math.sqrt(r2)
+                expect = kd.astype(float) / np.pi * I * cos / r2
+                got = rgb[y * 16 + x, j]
+                worst = max(worst, np.abs(got - expect).max() / expect.max())
+    assert worst < 1e-12
+
+
+# --------------------------------------------------------------------------
+# white furnace: convex Lambertian object under a constant environment
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("bounces,kd", [(1, 1.0), (2, 1.0), (3, 0.5)])
+def test_white_furnace(bounces, kd):
+    V, F = S.geodesic_sphere(3)
+    mat = S.uniform_materials(F.shape[0], kd=kd, ks=0.0, rough=0.3)
+    sc = O.OracleScene(V.astype(np.float32), F, mat, None, np.full((16, 32, 3), 1.0, np.float32))
+    cam = S.Camera((0.0, 0.0, 3.0), (0, 0, 0), (0, 1, 0), 30.0, 24, 24)
+    rgb, hsh = sc.render_samples([cam], 16, bounces, seed=1)
+    hit = rgb.reshape(-1, 3)[:, 0] > 0
+    vals = rgb.reshape(-1, 3)[hit]
+    assert hit.sum() > 2000
+    m = vals.mean(axis=0)
+    se = vals.std(axis=0) / math.sqrt(vals.shape[0])
+    assert np.all(np.abs(m - kd) < 4 * se + 1e-9), (m, se)
+
+
+# --------------------------------------------------------------------------
+# interior derivative: dual numbers vs central differences on the frozen path
+# --------------------------------------------------------------------------
+
+def _fd_check(sc, cams, spp, B, samples, flags, seed=0):
+    rng = np.random.default_rng(12)
+    checked = 0
+    for (view, px, py, j) in samples:
+        w = rng.uniform(0.2, 1.0, 3)
+        loss, rgb, dV, dM = sc.sample_grad(cams, spp, B, view, px, py, j, w, seed, flags | 8)
+        if flags & 1:
+            assert abs(loss - (rgb @ w)) <= 1e-12 * max(1.0, abs(loss))   # replay == record
+        base = sc.sample_frozen(cams, spp, B, view, px, py, j, w, -1, -1, 0.0, seed, flags)
+        if flags == 1:
+            assert abs(base - loss) <= 1e-12 * max(1.0, abs(loss))
+        nz_v = np.argwhere(np.abs(dV.ravel()) > 0).ravel()
+        nz_m = np.argwhere(np.abs(dM.ravel()) > 0).ravel()
+        scale = max(np.abs(dV).max(initial=0), np.abs(dM).max(initial=0), 1e-12)
+        h = 1e-6
+        for kind, idxs, g in ((0, nz_v, dV.ravel()), (1, nz_m, dM.ravel())):
+            for i in idxs:
+                fp = sc.sample_frozen(cams, spp, B, view, px, py, j, w, kind, int(i), h, seed, flags)
+                fm = sc.sample_frozen(cams, spp, B, view, px, py, j, w, kind, int(i), -h, seed, flags)
+                fd = (fp - fm) / (2 * h)
+                assert abs(fd - g[i]) <= 2e-6 * scale + 1e-6 * abs(g[i]), (kind, i, fd, g[i])
+                checked += 1
+    return checked
+
+
+def test_fd_frozen_point_light_direct():
+    wl = S.small_sphere(res=16, spp=2)
+    sc = O.OracleScene.from_scene(wl.scenes[0])
+    samples = [(0, x, y, j) for (x, y) in [(8, 8), (5, 9), (10, 4), (7, 12)] for j in range(2)]
+    assert _fd_check(sc, wl.cams, 2, 1, samples, flags=1) > 50
+
+
+def test_fd_frozen_envmap_multibounce():
+    rng = np.random.default_rng(21)
+    V, F = S.noise_sphere(4, 0.2, noise_seed=5)
+    # a floor plane under the object so that continuation rays hit surfaces
+    floor = np.array([[-3, -1.2, -3], [3, -1.2, -3], [3, -1.2, 3], [-3, -1.2, 3]], np.float32)
+    Vf = np.concatenate([V, floor]).astype(np.float32)
+    nv = V.shape[0]
+    Ff = np.concatenate([F, [[nv, nv + 2, nv + 1], [nv, nv + 3, nv + 2]]]).astype(np.int32)
+    mat = S.random_materials(Ff.shape[0], rng)
+    env = S.gaussian_lobe_envmap(rng, 32, 16)
+    lights = np.array([[1.0, 2.0, 1.5, 6, 6, 6]], np.float32)
+    sc = O.OracleScene(Vf, Ff, mat, lights, env)
+    cams = [S.Camera((0.0, 0.4, 3.2), (0, -0.2, 0), (0, 1, 0), 40.0, 20, 20)]
+    samples = [(0, x, y, j) for (x, y) in [(10, 10), (6, 14), (13, 8), (9, 17), (4, 10)] for j in range(3)]
+    assert _fd_check(sc, cams, 3, 3, samples, flags=1) > 100
+
+
+def test_fd_frozen_secondary_pseudo_term():
+    # the secondary edge pseudo term carries the shading-point motion; its
+    # dual derivative must match finite differences of the frozen replay too
+    rng = np.random.default_rng(22)
+    V, F = S.noise_sphere(3, 0.3, noise_seed=9)
+    floor = np.array([[-3, -1.3, -3], [3, -1.3, -3], [3, -1.3, 3], [-3, -1.3, 3]], np.float32)
+    Vf = np.concatenate([V, floor]).astype(np.float32)
+    nv = V.shape[0]
+    Ff = np.concatenate([F, [[nv, nv + 2, nv + 1], [nv, nv + 3, nv + 2]]]).astype(np.int32)
+    sc = O.OracleScene(Vf, Ff, S.random_materials(Ff.shape[0], rng), None, S.gaussian_lobe_envmap(rng, 32, 16))
+    cams = [S.Camera((0.0, 0.5, 3.0), (0, -0.3, 0), (0, 1, 0), 45.0, 16, 16)]
+    samples = [(0, x, y, j) for x in range(2, 14, 3) for y in range(2, 14, 3) for j in range(2)]
+    assert _fd_check(sc, cams, 2, 2, samples, flags=5) > 50
+
+
+# --------------------------------------------------------------------------
+# primary edge term: closed-form derivative of the projected area of a triangle
+# --------------------------------------------------------------------------
+
+def _screen_area(cam, P):
+    pts = []
+    for v in P:
+        e, f = None, None
+        eye = np.array(cam.eye, np.float32).astype(float)
+        tg = np.array(cam.target, np.float32).astype(float)
+        up = np.array(cam.up, np.float32).astype(float)
+        f = (tg - eye) / np.linalg.norm(tg - eye)
+        r = np.cross(f, up / np.linalg.norm(up))
+        r /= np.linalg.norm(r)
+        u = np.cross(r, f)
+        th = math.tan(float(np.float32(cam.fov_y_deg)) * math.pi / 360)
+        p = v - eye
+        z = p @ f
+        sx = (p @ r / (z * th * cam.width / cam.height) + 1) * 0.5 * cam.width
+        sy = (1 - p @ u / (z * th)) * 0.5 * cam.height
+        pts.append((sx, sy))
+    (ax, ay), (bx, by), (cx, cy) = pts
+    return 0.5 * abs((bx - ax) * (cy - ay) - (by - ay) * (cx - ax))
+
+
+def test_primary_edges_projected_area_derivative():
+    V = np.array([[-0.5, -0.4, 0.1], [0.6, -0.3, -0.2], [0.0, 0.55, 0.0]], np.float32)
+    F = np.array([[0, 1, 2]], np.int32)
+    mat = S.uniform_materials(1, kd=1.0, ks=0.0, rough=0.3)
+    sc = O.OracleScene(V, F, mat, None, np.ones((8, 16, 3), np.float32))
+    cam = S.Camera((0.0, 0.0, 3.0), (0, 0, 0), (0, 1, 0), 45.0, 48, 48)
+    spp = 48
+    d_img = np.ones((48 * 48, 3), np.float32)
+    dV, dM, _, _ = sc.backward([cam], spp, 1, d_img, seed=4, flags=O.FLAG_PRIMARY)
+    # closed form: sum of the image = L0 * (projected area in pixels); 3 channels
+    Vd = V.astype(float)
+    ref = np.zeros_like(Vd)
+    h = 1e-6
+    for i in range(3):
+        for k in range(3):
+            Vp, Vm = Vd.copy(), Vd.copy()
+            Vp[i, k] += h
+            Vm[i, k] -= h
+            ref[i, k] = 3.0 * (_screen_area(cam, Vp) - _screen_area(cam, Vm)) / (2 * h)
+    rel = np.linalg.norm(dV - ref) / np.linalg.norm(ref)
+    assert rel < 0.04, (rel, dV, ref)
+    assert np.all(dM == 0)
+
+
+# --------------------------------------------------------------------------
+# secondary edge term: closed-form projected solid angle of an occluder
+# --------------------------------------------------------------------------
+
+def _psa(p, n, tri):
+    """Projected solid angle of a spherical triangle seen from p (Lambert's formula)."""
+    u = [(v - p) / np.linalg.norm(v - p) for v in tri]
+    tot = 0.0
+    for i in range(3):
+        a, b = u[i], u[(i + 1) % 3]
+        g = np.cross(a, b)
+        g /= np.linalg.norm(g)
+        tot += math.acos(np.clip(a @ b, -1, 1)) * (g @ n)
+    return abs(tot) / 2
+
+
+def test_secondary_edges_polygon_irradiance_derivative():
+    tri = np.array([[-0.3, 0.8, -0.2], [0.4, 0.9, -0.1], [0.05, 0.7, 0.45]], np.float32)
+    floor = np.array([[-0.05, 0.0, -0.05], [0.05, 0.0, -0.05], [0.0, 0.0, 0.06]], np.float32)
+    V = np.concatenate([floor, tri])
+    F = np.array([[0, 2, 1], [3, 4, 5]], np.int32)
+    mat = S.uniform_materials(2, kd=1.0, ks=0.0, rough=0.3)
+    sc = O.OracleScene(V, F, mat, None, np.ones((8, 16, 3), np.float32))
+    p = np.array([0.0, 0.0, 0.0])
+    n = np.array([0.0, 1.0, 0.0])
+    wo = np.array([0.3, 1.0, 0.2]) / np.linalg.norm([0.3, 1.0, 0.2])
+    dV = sc.secondary_term(p, n, wo, face=0, budget=0, nsamples=400000, seed=2)
+    # E(p) = kd/pi * L0 * (pi - PSA(triangle)), so dE/dv = -(1/pi) dPSA/dv
+    T = tri.astype(float)
+    ref = np.zeros((3, 3))
+    h = 1e-6
+    for i in range(3):
+        for k in range(3):
+            Tp, Tm = T.copy(), T.copy()
+            Tp[i, k] += h
+            Tm[i, k] -= h
+            ref[i, k] = -(_psa(p, n, Tp) - _psa(p, n, Tm)) / (2 * h) / np.pi
+    got = dV[3:]
+    rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    assert rel < 0.05, (rel, got, ref)
+    assert np.abs(dV[:3]).max() == 0.0
+
+
+# --------------------------------------------------------------------------
+# edge list and LBVH reference
+# --------------------------------------------------------------------------
+
+def test_edge_list_canonical_closed_mesh():
+    V, F = S.geodesic_sphere(4)
+    sc = O.OracleScene(V.astype(np.float32), F, S.uniform_materials(F.shape[0]))
+    E = sc.edges()
+    assert E.shape[0] == 480
+    assert np.all(E[:, 0] < E[:, 1])
+    keys = E[:, 0].astype(np.int64) * 100000 + E[:, 1]
+    assert np.all(np.diff(keys) > 0)
+    assert np.all(E[:, 3] > E[:, 2])          # closed: two faces, f1 < f2
+    for va, vb, f1, f2 in E[:50]:
+        for f in (f1, f2):
+            assert va in F[f] and vb in F[f]
+    V32 = V.astype(np.float32).astype(np.float64)
+    total = sum(np.linalg.norm(V32[b] - V32[a]) for a, b, _, _ in E)
+    assert abs(sc.edge_total() - total) < 1e-9
+
+
+def _spread(v):
+    r = 0
+    for i in range(10):
+        r |= ((v >> i) & 1) << (3 * i)
+    return r
+
+
+@pytest.mark.parametrize("k", [1, 3, 9])
+def test_lbvh_reference_definition(k):
+    V, F = S.noise_sphere(k, 0.1, noise_seed=1)
+    V = V.astype(np.float32)
+    keys, child, parent, aabb = O.lbvh(V, F)
+    n = F.shape[0]
+    # Morton codes from the definition, in float32
+    tri = V[F]
+    mn, mx = tri.min(axis=1), tri.max(axis=1)
+    c = ((mn + mx) * np.float32(0.5)).astype(np.float32)
+    lo, hi = c.min(axis=0), c.max(axis=0)
+    s = np.array([np.float32(1024.0 / (float(h) - float(l))) if h > l else np.float32(0) for l, h in zip(lo, hi)],
+                 np.float32)
+    q = np.clip(np.floor((c - lo).astype(np.float32) * s).astype(np.int64), 0, 1023)
+    mort = np.array([(_spread(a) << 2) | (_spread(b) << 1) | _spread(cc) for a, b, cc in q], np.uint64)
+    ref = np.sort((mort << np.uint64(32)) | np.arange(n, dtype=np.uint64))
+    assert np.array_equal(keys, ref)
+    LEAF = 0x80000000
+    seen = np.zeros(n, int)
+
+    def rng_of(code):
+        if code & LEAF:
+            i = code & 0x7FFFFFFF
+            seen[i] += 1
+            return i, i, aabb[n - 1 + i]
+        a0, b0, box0 = rng_of(int(child[code, 0]) & 0xFFFFFFFF)
+        a1, b1, box1 = rng_of(int(child[code, 1]) & 0xFFFFFFFF)
+        assert b0 + 1 == a1                      # contiguous leaf ranges
+        box = aabb[code]
+        for bb in (box0, box1):
+            assert np.all(box[:3] <= bb[:3]) and np.all(box[3:] >= bb[3:])
+        assert np.array_equal(box[:3], np.minimum(box0[:3], box1[:3]))
+        assert np.array_equal(box[3:], np.maximum(box0[3:], box1[3:]))
+        # radix-tree property: the split sits at the first differing bit of the range
+        pre = 64 - int(keys[a0] ^ keys[b1]).bit_length()
+        assert 64 - int(keys[b0] ^ keys[a1]).bit_length() == pre
+        return a0, b1, box
+
+    if n > 1:
+        a, b, _ = rng_of(0)
+        assert (a, b) == (0, n - 1)
+        assert parent[0] == -1
+        for i in range(n - 1):
+            for cc in child[i]:
+                cc = int(cc) & 0xFFFFFFFF
+                idx = (n - 1 + (cc & 0x7FFFFFFF)) if cc & LEAF else cc
+                assert parent[idx] == i
+    assert np.all(seen <= 1) and (n == 1 or np.all(seen == 1))
+    for i in range(n):
+        f = int(keys[i] & np.uint64(0xFFFFFFFF))
+        assert np.array_equal(aabb[n - 1 + i, :3], mn[f]) and np.array_equal(aabb[n - 1 + i, 3:], mx[f])
