@@ -1,0 +1,149 @@
+/*
+ * shapetrace: MI355X (gfx950) differentiable path tracer, C ABI.
+ *
+ * The operation is the rendering function R(x, m, c_i) of Shape from Tracing
+ * (Sec. 3.2, "Vertex optimization": a physically based path tracer that also
+ * returns gradients of the pixels with respect to the mesh vertices x) with the
+ * per-facet Torrance-Sparrow materials m of Sec. 3.3 ("Representation": diffuse
+ * albedo, specular colour, roughness; mesh colours at resolution 0, i.e. one
+ * texel per triangle), global illumination (Sec. 3.3, "Effects of Global
+ * Illumination"), and the two lighting inputs of Sec. 3.1: point lights or an
+ * HDR environment map.  The loss of Sec. 3.2 (masked mean squared error) is left
+ * to the caller: st_render_backward receives dLoss/dImage and returns dLoss/dV
+ * and dLoss/dMaterial, including the silhouette-edge visibility terms.
+ *
+ * Conventions shared by every entry point:
+ *  - Array arguments (V, F, materials, lights, envmap, images, gradients) are
+ *    DEVICE pointers owned by the caller, row-major and contiguous.  Camera
+ *    records, cam_scene and the options struct are HOST memory.
+ *  - All work is enqueued on the given HIP stream and returns before it
+ *    finishes; outputs are complete when the stream is.  st_scene_create also
+ *    synchronises the stream (it validates the face indices on the host).
+ *  - st_scene_create / st_scene_update copy their inputs; the caller may free
+ *    them afterwards.  The library owns the BVH, CDFs, queues and workspace until
+ *    st_scene_destroy.  Render calls may grow the library workspace (the first
+ *    call with a larger shape allocates); identical later calls allocate nothing.
+ *  - Outputs are overwritten, never accumulated.
+ *  - Return value 0 on success, a negative ST_ERR_* code otherwise; the message
+ *    of the last failure on the calling thread is returned by st_last_error().
+ *  - Limits: 1 <= spp < 65536, 1 <= bounces <= 8, 1 <= ncam < 65536, at most 16
+ *    point lights, fewer than 2^31 path samples per call (the counter layout of
+ *    the random streams needs these).
+ */
+#ifndef SHAPETRACE_H
+#define SHAPETRACE_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ST_OK 0
+#define ST_ERR_INVALID_ARG (-1)
+#define ST_ERR_HIP (-2)
+#define ST_ERR_OOM (-3)
+#define ST_ERR_QUEUE_OVERFLOW (-4)
+#define ST_ERR_DEVICE_FAULT (-5)
+
+/* gradient terms of st_render_backward, and forward-pass switches */
+#define ST_GRAD_INTERIOR 1u        /* derivative of the estimator at fixed sampled directions */
+#define ST_EDGE_PRIMARY 2u         /* screen-space silhouette / crease edges (camera visibility) */
+#define ST_EDGE_SECONDARY 4u       /* direction-space silhouette edges at every path vertex */
+#define ST_FORWARD_MEGAKERNEL 16u  /* forward as one kernel per path sample instead of the wavefront */
+
+typedef struct st_scene st_scene;
+
+/* Pinhole camera (the calibrated cameras c_i of Sec. 3.2): vertical field of
+ * view in degrees, image row 0 at the top; width x height pixels. */
+typedef struct {
+    float eye[3], target[3], up[3];
+    float fov_y_deg;
+    int32_t width, height;
+} st_camera;
+
+typedef struct {
+    uint32_t flags;                  /* ST_GRAD_* | ST_EDGE_* | ST_FORWARD_MEGAKERNEL */
+    float edge_spp_ratio;            /* primary edge samples per (pixel x spp) of each view */
+    int64_t queue_capacity;          /* wavefront chunk size in path samples (0: library default) */
+    uint32_t* debug_decision_hash;   /* device, optional: one FNV-1a hash of the discrete decisions per
+                                        path sample, index ((pixel offset of view + y*W + x) * spp + j) */
+    uint32_t* debug_edge_hash;       /* device, optional (backward): one hash per primary edge sample */
+    float* debug_sample_radiance;    /* device, optional (forward): per path sample rgb, same index */
+    const uint8_t* path_mask;        /* device, optional (backward): 0 skips a path sample */
+    const uint8_t* edge_mask;        /* device, optional (backward): 0 skips a primary edge sample */
+} st_render_opts;
+
+/* Default options: all three gradient terms, one primary edge sample per
+ * pixel sample, default queue capacity, no debug outputs. */
+st_render_opts st_render_opts_default(void);
+
+/* Create a scene (Sec. 3.2 triangle mesh x with faces; Sec. 3.3 per-face
+ * material; Sec. 3.1 lights).
+ *   V: float [nv,3] vertex positions.  F: int32 [nf,3] vertex indices
+ *   (validated: 0 <= index < nv, else ST_ERR_INVALID_ARG).
+ *   face_materials: float [nf,7] = kd rgb, ks rgb, roughness (roughness floor 1e-3).
+ *   lights: float [nl,6] = position xyz, radiant intensity rgb (W/sr); NULL when nl == 0.
+ *   envmap: float [he,we,3] equirectangular, +y up, row 0 looking along +y; NULL for none.
+ *   scene_id: second word of the Philox key of this scene's random streams.
+ *   out: receives the handle.  Allocates, copies, builds the BVH and CDFs, and
+ *   synchronises stream s. */
+int st_scene_create(const float* V, int32_t nv, const int32_t* F, int32_t nf, const float* face_materials,
+                    const float* lights, int32_t nl, const float* envmap, int32_t he, int32_t we,
+                    uint32_t scene_id, hipStream_t s, st_scene** out);
+
+/* Replace vertex positions (float [nv,3]) and/or materials (float [nf,7]); either
+ * may be NULL.  Rebuilds the LBVH and edge CDF on the stream; allocates nothing. */
+int st_scene_update(st_scene* scene, const float* V, const float* face_materials, hipStream_t s);
+
+/* Forward render (Sec. 3.2, R(x, c_i)).  cams: host array of ncam cameras.
+ * out: device float [sum_i width_i*height_i, 3], views concatenated, each row-major;
+ * every pixel is the mean of spp path samples with a one-pixel box filter.
+ * bounces: number of surface vertices with next-event estimation (1 = direct light).
+ * seed: first word of the Philox key.  opts may be NULL (defaults). */
+int st_render(st_scene* scene, const st_camera* cams, int32_t ncam, int32_t spp, int32_t bounces, uint32_t seed,
+              const st_render_opts* opts, float* out, hipStream_t s);
+
+/* Adjoint of st_render (Sec. 3.2 gradients w.r.t. geometry; Sec. 3.3 materials).
+ * Must be called with the same (cams, spp, bounces, seed) as the forward pass
+ * whose image gradient it receives; it replays every path from its random
+ * counters and keeps no state from st_render.
+ *   d_image: device float, same layout as st_render's out.
+ *   out_dV: device float [nv,3]; out_dmat: device float [nf,7]; both overwritten. */
+int st_render_backward(st_scene* scene, const st_camera* cams, int32_t ncam, int32_t spp, int32_t bounces,
+                       uint32_t seed, const st_render_opts* opts, const float* d_image, float* out_dV,
+                       float* out_dmat, hipStream_t s);
+
+/* Several independent scenes in one pass: camera i renders scene cam_scene[i]
+ * (host int32 [ncam]).  Output layout as st_render over the concatenated views. */
+int st_render_batch(st_scene* const* scenes, int32_t nscenes, const st_camera* cams, const int32_t* cam_scene,
+                    int32_t ncam, int32_t spp, int32_t bounces, uint32_t seed, const st_render_opts* opts,
+                    float* out, hipStream_t s);
+
+/* Wait for stream s and report device-side faults recorded by earlier calls on
+ * this scene (traversal stack overflow): ST_ERR_DEVICE_FAULT, and clears them. */
+int st_check_errors(st_scene* scene, hipStream_t s);
+
+/* Introspection for tests (device outputs, caller-allocated):
+ *  st_scene_info: host int64 [6] = nv, nf, number of edges, nl, he, we.
+ *  st_scene_edges: int32 [ne,4] = (va < vb, f1, f2 or -1), canonical order.
+ *  st_scene_lbvh: keys uint64 [nf] (morton << 32 | face, ascending), child int32
+ *    [nf-1,2] (bit 31 marks a leaf index), parent int32 [2nf-1] (internal nodes,
+ *    then leaves; -1 at the root), aabb float [2nf-1,6] (min xyz, max xyz).
+ *  st_trace_rays: closest hit of n rays o,d (float [n,3]) with t > tmin, through
+ *    the BVH or by brute force; out_face int32 [n] (-1 miss), out_t float [n]. */
+int st_scene_info(const st_scene* scene, int64_t* out6);
+int st_scene_edges(st_scene* scene, int32_t* out_edges, hipStream_t s);
+int st_scene_lbvh(st_scene* scene, uint64_t* keys, int32_t* child, int32_t* parent, float* aabb, hipStream_t s);
+int st_trace_rays(st_scene* scene, const float* o, const float* d, int32_t n, float tmin, int32_t brute,
+                  int32_t* out_face, float* out_t, hipStream_t s);
+
+void st_scene_destroy(st_scene* scene);
+const char* st_last_error(void);
+int st_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -82,8 +82,10 @@ static inline void draw4(const Ctr& c, uint32_t bounce, uint32_t block, uint32_t
 struct Hash {
     uint32_t h = 0x811C9DC5u;
     bool on = true;
+    std::vector<uint32_t>* buf = nullptr;   // when set, words are queued instead of hashed
     void push(uint32_t w) {
         if (!on) return;
+        if (buf) { buf->push_back(w); return; }
         for (int b = 0; b < 4; ++b) { h ^= (w >> (8 * b)) & 0xFFu; h *= 0x01000193u; }
     }
 };
@@ -606,6 +608,11 @@ static D3 trace_estimator(const Scene& s, D3 o, D3 d, int exclude, int nvert, bo
     D3 L(0, 0, 0), beta(1, 1, 1);
     double p_prev = 0.0;
     if (rec) { rec->nv = 0; rec->o = o; rec->d = d; }
+    // decision words of the secondary edge samples follow all main-path words
+    std::vector<uint32_t> secbuf;
+    Hash sech;
+    sech.on = hash.on;
+    sech.buf = &secbuf;
     for (int k = 1; k <= nvert + 1; ++k) {
         double t;
         int f = closest_hit(s, o, d, TMIN, exclude, t);
@@ -685,7 +692,7 @@ static D3 trace_estimator(const Scene& s, D3 o, D3 d, int exclude, int nvert, bo
             draw4(ctr, k, 3, key.k0, key.k1, u);
             int e = cdf_find(s.ecdf.data(), (int)s.edges.size(), u[0]);
             double te = u[1];
-            hash.push((uint32_t)e);
+            sech.push((uint32_t)e);
             const Edge& E = s.edges[e];
             D3 va = s.vert(E.va), vb = s.vert(E.vb);
             bool sil = true;
@@ -706,12 +713,12 @@ static D3 trace_estimator(const Scene& s, D3 o, D3 d, int exclude, int nvert, bo
                 double ml = length(mv);
                 if (cv > 0.0 && ml > 0.0) {
                     code = 1;
-                    hash.push(1u);
+                    sech.push(1u);
                     D3 mm = mv * (1.0 / ml);
                     D3 wm = normalize(ud - mm * EPS_SECONDARY), wp = normalize(ud + mm * EPS_SECONDARY);
                     Ctr sc{ctr.c0, ctr.c1, (uint32_t)k << 16, 2u};
-                    D3 Lm = L_in_side(s, x, wm, f, nvert - k, sc, key, hash);
-                    D3 Lp = L_in_side(s, x, wp, f, nvert - k, sc, key, hash);
+                    D3 Lm = L_in_side(s, x, wm, f, nvert - k, sc, key, sech);
+                    D3 Lp = L_in_side(s, x, wp, f, nvert - k, sc, key, sech);
                     D3 fv = brdf(ud, wo, n, m);
                     double cc = 0.0;
                     for (int ch = 0; ch < 3; ++ch)
@@ -726,7 +733,7 @@ static D3 trace_estimator(const Scene& s, D3 o, D3 d, int exclude, int nvert, bo
                     if (vr) { vr->sec = 1; vr->sec_c = cc; vr->sec_m = mv; }
                 }
             }
-            if (code == 0) hash.push(0u);
+            if (code == 0) sech.push(0u);
         }
         // continuation by sampling the BRDF mixture
         if (!continues) break;
@@ -745,6 +752,7 @@ static D3 trace_estimator(const Scene& s, D3 o, D3 d, int exclude, int nvert, bo
         p_prev = pb;
         o = x; d = wi; exclude = f;
     }
+    for (uint32_t w : secbuf) hash.push(w);
     return L;
 }
 

@@ -1,0 +1,239 @@
+"""Thin ctypes binding of libshapetrace.so (the C ABI in include/shapetrace.h).
+
+Argument marshalling only: torch supplies device memory and the current HIP
+stream; every step of rendering and differentiation runs in the HIP kernels of
+the library.  There is no fallback: if the library is missing or no GPU is
+present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libshapetrace.so")
+
+ST_GRAD_INTERIOR = 1
+ST_EDGE_PRIMARY = 2
+ST_EDGE_SECONDARY = 4
+ST_FORWARD_MEGAKERNEL = 16
+ST_ALL_GRADS = 7
+
+EXPORTED = ["st_render_opts_default", "st_scene_create", "st_scene_update", "st_render", "st_render_backward",
+            "st_render_batch", "st_check_errors", "st_scene_info", "st_scene_edges", "st_scene_lbvh",
+            "st_trace_rays", "st_scene_destroy", "st_last_error", "st_version"]
+
+
+class StCamera(ctypes.Structure):
+    _fields_ = [("eye", ctypes.c_float * 3), ("target", ctypes.c_float * 3), ("up", ctypes.c_float * 3),
+                ("fov_y_deg", ctypes.c_float), ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
+class StOpts(ctypes.Structure):
+    _fields_ = [("flags", ctypes.c_uint32), ("edge_spp_ratio", ctypes.c_float), ("queue_capacity", ctypes.c_int64),
+                ("debug_decision_hash", ctypes.c_void_p), ("debug_edge_hash", ctypes.c_void_p),
+                ("debug_sample_radiance", ctypes.c_void_p), ("path_mask", ctypes.c_void_p),
+                ("edge_mask", ctypes.c_void_p)]
+
+
+class StError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the library (no GPU needed) and declare every exported symbol."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise StError(f"{path} is missing: build it with __graft_entry__.build() (hipcc, gfx950)")
+    L = ctypes.CDLL(path)
+    P, I32, U32, F32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_float
+    L.st_render_opts_default.restype = StOpts
+    L.st_scene_create.argtypes = [P, I32, P, I32, P, P, I32, P, I32, I32, U32, P, ctypes.POINTER(P)]
+    L.st_scene_update.argtypes = [P, P, P, P]
+    L.st_render.argtypes = [P, P, I32, I32, I32, U32, ctypes.POINTER(StOpts), P, P]
+    L.st_render_backward.argtypes = [P, P, I32, I32, I32, U32, ctypes.POINTER(StOpts), P, P, P, P]
+    L.st_render_batch.argtypes = [P, I32, P, P, I32, I32, I32, U32, ctypes.POINTER(StOpts), P, P]
+    L.st_check_errors.argtypes = [P, P]
+    L.st_scene_info.argtypes = [P, P]
+    L.st_scene_edges.argtypes = [P, P, P]
+    L.st_scene_lbvh.argtypes = [P, P, P, P, P, P]
+    L.st_trace_rays.argtypes = [P, P, P, I32, F32, I32, P, P, P]
+    L.st_scene_destroy.argtypes = [P]
+    L.st_last_error.restype = ctypes.c_char_p
+    L.st_version.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise StError(f"shapetrace error {rc}: {load().st_last_error().decode()}")
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    import torch
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA (HIP) tensors"
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def make_cameras(cams) -> ctypes.Array:
+    """cams: objects with eye, target, up, fov_y_deg, width, height."""
+    arr = (StCamera * len(cams))()
+    for i, c in enumerate(cams):
+        arr[i].eye[:] = [float(x) for x in c.eye]
+        arr[i].target[:] = [float(x) for x in c.target]
+        arr[i].up[:] = [float(x) for x in c.up]
+        arr[i].fov_y_deg = float(c.fov_y_deg)
+        arr[i].width = int(c.width)
+        arr[i].height = int(c.height)
+    return arr
+
+
+def num_pixels(cams) -> int:
+    return int(sum(int(c.width) * int(c.height) for c in cams))
+
+
+def num_edge_samples(cams, spp: int, ratio: float) -> int:
+    return int(sum(round(ratio * int(c.width) * int(c.height) * spp) for c in cams))
+
+
+def make_opts(flags=ST_ALL_GRADS, edge_ratio=1.0, queue_capacity=0, dbg_hash=None, dbg_edge_hash=None,
+              dbg_radiance=None, path_mask=None, edge_mask=None) -> StOpts:
+    o = StOpts()
+    o.flags = flags
+    o.edge_spp_ratio = edge_ratio
+    o.queue_capacity = queue_capacity
+    o.debug_decision_hash = _ptr(dbg_hash)
+    o.debug_edge_hash = _ptr(dbg_edge_hash)
+    o.debug_sample_radiance = _ptr(dbg_radiance)
+    o.path_mask = _ptr(path_mask)
+    o.edge_mask = _ptr(edge_mask)
+    return o
+
+
+class GPUScene:
+    """One library scene (mesh, per-face materials, lights, environment map)."""
+
+    def __init__(self, V, F, mat, lights=None, env=None, scene_id: int = 0):
+        import torch
+        dev = torch.device("cuda")
+        L = load()
+        self.V = torch.as_tensor(V, dtype=torch.float32, device=dev).contiguous()
+        self.F = torch.as_tensor(F, dtype=torch.int32, device=dev).contiguous()
+        self.mat = torch.as_tensor(mat, dtype=torch.float32, device=dev).contiguous()
+        lt = None if lights is None or len(lights) == 0 else torch.as_tensor(lights, dtype=torch.float32,
+                                                                              device=dev).contiguous()
+        ev = None if env is None else torch.as_tensor(env, dtype=torch.float32, device=dev).contiguous()
+        self.nv, self.nf = int(self.V.shape[0]), int(self.F.shape[0])
+        nl = 0 if lt is None else int(lt.shape[0])
+        he, we = (0, 0) if ev is None else (int(ev.shape[0]), int(ev.shape[1]))
+        h = ctypes.c_void_p()
+        _check(L.st_scene_create(_ptr(self.V), self.nv, _ptr(self.F), self.nf, _ptr(self.mat), _ptr(lt), nl,
+                                 _ptr(ev), he, we, scene_id, _stream(), ctypes.byref(h)))
+        self.h = h
+        self.scene_id = scene_id
+        info = (ctypes.c_int64 * 6)()
+        _check(L.st_scene_info(self.h, info))
+        self.ne = int(info[2])
+
+    @classmethod
+    def from_scene(cls, sc):
+        return cls(sc.V, sc.F, sc.mat, sc.lights, sc.env, sc.scene_id)
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().st_scene_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def update(self, V=None, mat=None):
+        _check(load().st_scene_update(self.h, _ptr(V), _ptr(mat), _stream()))
+
+    def render(self, cams, spp: int, bounces: int, seed: int = 0, out=None, flags: int = 0, queue_capacity: int = 0,
+               debug_hash=None, debug_radiance=None):
+        import torch
+        cam = make_cameras(cams)
+        if out is None:
+            out = torch.empty((num_pixels(cams), 3), dtype=torch.float32, device="cuda")
+        o = make_opts(flags=flags, queue_capacity=queue_capacity, dbg_hash=debug_hash, dbg_radiance=debug_radiance)
+        _check(load().st_render(self.h, cam, len(cams), spp, bounces, seed, ctypes.byref(o), _ptr(out), _stream()))
+        return out
+
+    def backward(self, cams, spp: int, bounces: int, d_image, seed: int = 0, flags: int = ST_ALL_GRADS,
+                 edge_ratio: float = 1.0, dV=None, dmat=None, path_mask=None, edge_mask=None, debug_hash=None,
+                 debug_edge_hash=None):
+        import torch
+        cam = make_cameras(cams)
+        if dV is None:
+            dV = torch.empty((self.nv, 3), dtype=torch.float32, device="cuda")
+        if dmat is None:
+            dmat = torch.empty((self.nf, 7), dtype=torch.float32, device="cuda")
+        o = make_opts(flags=flags, edge_ratio=edge_ratio, dbg_hash=debug_hash, dbg_edge_hash=debug_edge_hash,
+                      path_mask=path_mask, edge_mask=edge_mask)
+        d = d_image.contiguous()
+        _check(load().st_render_backward(self.h, cam, len(cams), spp, bounces, seed, ctypes.byref(o), _ptr(d),
+                                         _ptr(dV), _ptr(dmat), _stream()))
+        return dV, dmat
+
+    def check_errors(self):
+        _check(load().st_check_errors(self.h, _stream()))
+
+    def edges(self):
+        import torch
+        out = torch.empty((self.ne, 4), dtype=torch.int32, device="cuda")
+        _check(load().st_scene_edges(self.h, _ptr(out), _stream()))
+        return out
+
+    def lbvh(self):
+        import torch
+        n = self.nf
+        keys = torch.empty(n, dtype=torch.int64, device="cuda")
+        child = torch.empty((max(n - 1, 0), 2), dtype=torch.int32, device="cuda")
+        parent = torch.empty(2 * n - 1, dtype=torch.int32, device="cuda")
+        aabb = torch.empty((2 * n - 1, 6), dtype=torch.float32, device="cuda")
+        _check(load().st_scene_lbvh(self.h, _ptr(keys), _ptr(child) if n > 1 else None, _ptr(parent), _ptr(aabb),
+                                    _stream()))
+        return keys, child, parent, aabb
+
+    def trace(self, o, d, tmin: float = 1e-4, brute: bool = False):
+        import torch
+        n = int(o.shape[0])
+        f = torch.empty(n, dtype=torch.int32, device="cuda")
+        t = torch.empty(n, dtype=torch.float32, device="cuda")
+        _check(load().st_trace_rays(self.h, _ptr(o.contiguous()), _ptr(d.contiguous()), n, tmin, int(brute),
+                                    _ptr(f), _ptr(t), _stream()))
+        return f, t
+
+
+def render_batch(scenes: Sequence[GPUScene], cams, cam_scene, spp: int, bounces: int, seed: int = 0, out=None,
+                 flags: int = 0, queue_capacity: int = 0):
+    import torch
+    arr = (ctypes.c_void_p * len(scenes))(*[s.h.value for s in scenes])
+    cs = (ctypes.c_int32 * len(cams))(*[int(x) for x in cam_scene])
+    cam = make_cameras(cams)
+    if out is None:
+        out = torch.empty((num_pixels(cams), 3), dtype=torch.float32, device="cuda")
+    o = make_opts(flags=flags, queue_capacity=queue_capacity)
+    _check(load().st_render_batch(arr, len(scenes), cam, cs, len(cams), spp, bounces, seed, ctypes.byref(o),
+                                  _ptr(out), _stream()))
+    return out

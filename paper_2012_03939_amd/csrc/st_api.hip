@@ -1,0 +1,552 @@
+// Host side of the C ABI: validation, allocation, camera set-up, workspace
+// management and kernel sequencing on the caller's stream.
+#include "st_internal.h"
+#include "../../include/shapetrace.h"
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace st;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(x)                                                                                     \
+    do {                                                                                              \
+        hipError_t e_ = (x);                                                                          \
+        if (e_ != hipSuccess) return fail(ST_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+struct GrowBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+    int ensure(size_t bytes) {
+        if (bytes <= cap && p) return ST_OK;
+        if (p) { hipFree(p); p = nullptr; cap = 0; }
+        const size_t want = std::max<size_t>(bytes + bytes / 8, 256);
+        if (hipMalloc(&p, want) != hipSuccess) { p = nullptr; return fail(ST_ERR_OOM, "device allocation failed"); }
+        cap = want;
+        return ST_OK;
+    }
+    void release() { if (p) hipFree(p); p = nullptr; cap = 0; }
+};
+
+// carve aligned sub-arrays out of one allocation
+struct Carver {
+    char* base;
+    size_t off = 0;
+    template <class T> T* take(size_t n) {
+        off = (off + 255) & ~(size_t)255;
+        T* r = (T*)(base + off);
+        off += n * sizeof(T);
+        return r;
+    }
+};
+
+template <class T> int dalloc(T** p, size_t n) {
+    if (n == 0) n = 1;
+    if (hipMalloc((void**)p, n * sizeof(T)) != hipSuccess) { *p = nullptr; return fail(ST_ERR_OOM, "device allocation failed"); }
+    return ST_OK;
+}
+
+// camera basis, written exactly like the specification (double precision)
+struct D3 { double x, y, z; };
+D3 sub(D3 a, D3 b) { return D3{a.x - b.x, a.y - b.y, a.z - b.z}; }
+double dotd(D3 a, D3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+D3 scal(D3 a, double s) { return D3{a.x * s, a.y * s, a.z * s}; }
+D3 crossd(D3 a, D3 b) { return D3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+D3 normd(D3 a) { double l = std::sqrt(dotd(a, a)); return scal(a, 1.0 / l); }
+
+bool make_devcam(const st_camera& c, DevCam& o) {
+    if (c.width < 1 || c.height < 1) return false;
+    D3 eye{c.eye[0], c.eye[1], c.eye[2]}, tg{c.target[0], c.target[1], c.target[2]}, up{c.up[0], c.up[1], c.up[2]};
+    D3 fv = sub(tg, eye);
+    if (dotd(fv, fv) == 0.0 || dotd(up, up) == 0.0) return false;
+    D3 f = normd(fv);
+    D3 upn = normd(up);
+    if (std::fabs(dotd(f, upn)) > 0.999) upn = D3{0, 0, 1};
+    if (std::fabs(dotd(f, upn)) > 0.999) upn = D3{1, 0, 0};
+    D3 r = normd(crossd(f, upn));
+    D3 u = crossd(r, f);
+    const double th = std::tan((double)c.fov_y_deg * 3.14159265358979323846 / 360.0);
+    const double aspect = (double)c.width / (double)c.height;
+    if (!(th > 0.0) || !std::isfinite(th)) return false;
+    const double rs = th * aspect;
+    o.eye[0] = c.eye[0]; o.eye[1] = c.eye[1]; o.eye[2] = c.eye[2];
+    o.f[0] = (float)f.x; o.f[1] = (float)f.y; o.f[2] = (float)f.z;
+    o.rs[0] = (float)(r.x * rs); o.rs[1] = (float)(r.y * rs); o.rs[2] = (float)(r.z * rs);
+    o.us[0] = (float)(u.x * th); o.us[1] = (float)(u.y * th); o.us[2] = (float)(u.z * th);
+    o.deye[0] = eye.x; o.deye[1] = eye.y; o.deye[2] = eye.z;
+    o.df[0] = f.x; o.df[1] = f.y; o.df[2] = f.z;
+    o.dr[0] = r.x; o.dr[1] = r.y; o.dr[2] = r.z;
+    o.du[0] = u.x; o.du[1] = u.y; o.du[2] = u.z;
+    o.dth = th;
+    o.daspect = aspect;
+    o.W = c.width;
+    o.H = c.height;
+    o.scene = 0;
+    o.pad = 0;
+    return true;
+}
+
+} // namespace
+
+struct st_scene {
+    SceneDev d;
+    GrowBuf camsbuf, Lbuf, qbuf, spillbuf, primbuf, scenesbuf;
+    void* pinned = nullptr;
+    size_t pinned_cap = 0;
+    hipEvent_t staged = nullptr;
+    bool staged_valid = false;
+};
+
+namespace {
+
+int check_scene(const st_scene* s) {
+    if (!s) return fail(ST_ERR_INVALID_ARG, "scene is NULL");
+    return ST_OK;
+}
+
+// stage camera records and offset tables into device memory on stream s
+struct CamSetup {
+    DevCam* cams = nullptr;
+    long long* qoff = nullptr;
+    long long* pixoff = nullptr;
+    long long* eoff = nullptr;
+    long long total_paths = 0, total_pix = 0, total_edges = 0;
+};
+
+int setup_cams(st_scene* owner, const st_camera* cams, const int32_t* cam_scene, int32_t ncam, int32_t spp,
+               double ratio, int nscenes, hipStream_t s, CamSetup& out) {
+    if (!cams) return fail(ST_ERR_INVALID_ARG, "cams is NULL");
+    if (ncam < 1 || ncam > 65535) return fail(ST_ERR_INVALID_ARG, "ncam must be in [1, 65535]");
+    if (spp < 1 || spp > 65535) return fail(ST_ERR_INVALID_ARG, "spp must be in [1, 65535]");
+    std::vector<DevCam> dc(ncam);
+    std::vector<long long> qoff(ncam + 1), pix(ncam + 1), eoff(ncam + 1);
+    long long q = 0, p = 0, e = 0;
+    for (int i = 0; i < ncam; ++i) {
+        if (!make_devcam(cams[i], dc[i])) return fail(ST_ERR_INVALID_ARG, "invalid camera " + std::to_string(i));
+        const long long hw = (long long)cams[i].width * cams[i].height;
+        if (hw >= (1ll << 31)) return fail(ST_ERR_INVALID_ARG, "image too large");
+        dc[i].scene = cam_scene ? cam_scene[i] : 0;
+        if (dc[i].scene < 0 || dc[i].scene >= nscenes) return fail(ST_ERR_INVALID_ARG, "cam_scene out of range");
+        const long long ne = (long long)std::llround(ratio * (double)cams[i].width * (double)cams[i].height * (double)spp);
+        dc[i].qoff = q; dc[i].pixoff = p; dc[i].eoff = e; dc[i].ne = ne;
+        qoff[i] = q; pix[i] = p; eoff[i] = e;
+        q += hw * spp; p += hw; e += ne;
+    }
+    qoff[ncam] = q; pix[ncam] = p; eoff[ncam] = e;
+    if (q >= (1ll << 31)) return fail(ST_ERR_INVALID_ARG, "more than 2^31 path samples in one call");
+    if (e >= (1ll << 40)) return fail(ST_ERR_INVALID_ARG, "too many edge samples");
+    const size_t bytes = 256 + sizeof(DevCam) * ncam + 3 * 256 + 3 * sizeof(long long) * (ncam + 1);
+    int rc = owner->camsbuf.ensure(bytes);
+    if (rc) return rc;
+    if (owner->pinned_cap < bytes) {
+        if (owner->staged_valid) HIPCHK(hipEventSynchronize(owner->staged));
+        if (owner->pinned) hipHostFree(owner->pinned);
+        owner->pinned = nullptr;
+        HIPCHK(hipHostMalloc(&owner->pinned, bytes, hipHostMallocDefault));
+        owner->pinned_cap = bytes;
+    } else if (owner->staged_valid) {
+        HIPCHK(hipEventSynchronize(owner->staged));
+    }
+    Carver hc{(char*)owner->pinned};
+    Carver dcv{(char*)owner->camsbuf.p};
+    DevCam* hcam = hc.take<DevCam>(ncam);
+    long long* hq = hc.take<long long>(ncam + 1);
+    long long* hp = hc.take<long long>(ncam + 1);
+    long long* he = hc.take<long long>(ncam + 1);
+    std::memcpy(hcam, dc.data(), sizeof(DevCam) * ncam);
+    std::memcpy(hq, qoff.data(), sizeof(long long) * (ncam + 1));
+    std::memcpy(hp, pix.data(), sizeof(long long) * (ncam + 1));
+    std::memcpy(he, eoff.data(), sizeof(long long) * (ncam + 1));
+    out.cams = dcv.take<DevCam>(ncam);
+    out.qoff = dcv.take<long long>(ncam + 1);
+    out.pixoff = dcv.take<long long>(ncam + 1);
+    out.eoff = dcv.take<long long>(ncam + 1);
+    HIPCHK(hipMemcpyAsync(owner->camsbuf.p, owner->pinned, hc.off, hipMemcpyHostToDevice, s));
+    if (!owner->staged) HIPCHK(hipEventCreateWithFlags(&owner->staged, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(owner->staged, s));
+    owner->staged_valid = true;
+    out.total_paths = q;
+    out.total_pix = p;
+    out.total_edges = e;
+    return ST_OK;
+}
+
+int ensure_spill(st_scene* sc) {
+    return sc->spillbuf.ensure((size_t)SPILL_STACK * TRACE_GRID * TRACE_BLOCK * sizeof(uint32_t));
+}
+
+int make_queues(st_scene* sc, int cap, int nent, float* L, Queues& q) {
+    const size_t per = 256;
+    size_t bytes = 0;
+    bytes += (size_t)cap * 4 * (2 * 9 + 3 + 3 + 1 + 2 + 3 + 3 + 7 * std::max(nent, 1)) + 40 * per + 64 * 4;
+    int rc = sc->qbuf.ensure(bytes);
+    if (rc) return rc;
+    Carver c{(char*)sc->qbuf.p};
+    for (int b = 0; b < 2; ++b)
+        for (int i = 0; i < 9; ++i) q.ray[b][i] = c.take<float>(cap);
+    q.pq = c.take<uint32_t>(cap);
+    q.pc0 = c.take<uint32_t>(cap);
+    q.pc1 = c.take<uint32_t>(cap);
+    for (int i = 0; i < 3; ++i) q.pbeta[i] = c.take<float>(cap);
+    q.phash = c.take<uint32_t>(cap);
+    q.ht = c.take<float>(cap);
+    q.hf = c.take<int>(cap);
+    for (int i = 0; i < 3; ++i) q.sx[i] = c.take<float>(cap);
+    q.sface = c.take<int>(cap);
+    q.sinfo = c.take<uint32_t>(cap);
+    q.stex = c.take<int>(cap);
+    for (int i = 0; i < 7; ++i) q.sh[i] = c.take<float>((size_t)cap * std::max(nent, 1));
+    q.cnt = c.take<int>(64);
+    q.spill = (uint32_t*)sc->spillbuf.p;
+    q.L = L;
+    q.cap = cap;
+    q.nent = nent;
+    return ST_OK;
+}
+
+int render_impl(st_scene* owner, st_scene* const* scenes, int nscenes, const st_camera* cams, const int32_t* cam_scene,
+                int32_t ncam, int32_t spp, int32_t bounces, uint32_t seed, const st_render_opts* opts, float* out,
+                hipStream_t s) {
+    if (!out) return fail(ST_ERR_INVALID_ARG, "out is NULL");
+    if (bounces < 1 || bounces > 8) return fail(ST_ERR_INVALID_ARG, "bounces must be in [1, 8]");
+    st_render_opts o = opts ? *opts : st_render_opts_default();
+    CamSetup cs;
+    int rc = setup_cams(owner, cams, cam_scene, ncam, spp, 0.0, nscenes, s, cs);
+    if (rc) return rc;
+    const DevScene* dscenes = owner->d.dscene;
+    int nent = 0, has_env_any = 0;
+    for (int i = 0; i < nscenes; ++i) {
+        nent = std::max(nent, scenes[i]->d.nl + (scenes[i]->d.has_env ? 1 : 0));
+        has_env_any |= scenes[i]->d.has_env ? 1 : 0;
+    }
+    if (nscenes > 1) {
+        rc = owner->scenesbuf.ensure(sizeof(DevScene) * nscenes);
+        if (rc) return rc;
+        std::vector<DevScene> hs(nscenes);
+        for (int i = 0; i < nscenes; ++i) hs[i] = scenes[i]->d.hscene;
+        HIPCHK(hipMemcpyAsync(owner->scenesbuf.p, hs.data(), sizeof(DevScene) * nscenes, hipMemcpyHostToDevice, s));
+        dscenes = (const DevScene*)owner->scenesbuf.p;
+    }
+    rc = owner->Lbuf.ensure((size_t)cs.total_paths * 3 * sizeof(float));
+    if (rc) return rc;
+    rc = ensure_spill(owner);
+    if (rc) return rc;
+    FwdParams p;
+    p.scenes = dscenes;
+    p.cams = cs.cams;
+    p.qoff = cs.qoff;
+    p.ncam = ncam;
+    p.spp = spp;
+    p.B = bounces;
+    p.seed = seed;
+    p.dbg_hash = o.debug_decision_hash;
+    p.err = owner->d.err;
+    float* L = (float*)owner->Lbuf.p;
+    if (o.flags & ST_FORWARD_MEGAKERNEL) {
+        launch_forward_mega(p, L, cs.total_paths, (uint32_t*)owner->spillbuf.p, TRACE_GRID, s);
+    } else {
+        long long cap = o.queue_capacity > 0 ? o.queue_capacity : (1ll << 22);
+        cap = std::min<long long>(cap, std::max<long long>(cs.total_paths, 1));
+        cap = std::min<long long>(cap, 1ll << 28);
+        Queues q;
+        rc = make_queues(owner, (int)cap, nent, L, q);
+        if (rc) return rc;
+        launch_forward_wavefront(p, q, cs.total_paths, has_env_any, nent, s);
+    }
+    launch_film(cs.cams, cs.pixoff, ncam, spp, L, cs.total_pix, out, s);
+    if (o.debug_sample_radiance) launch_sample_radiance(p, L, cs.total_paths, o.debug_sample_radiance, s);
+    HIPCHK(hipGetLastError());
+    return ST_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+st_render_opts st_render_opts_default(void) {
+    st_render_opts o;
+    std::memset(&o, 0, sizeof(o));
+    o.flags = ST_GRAD_INTERIOR | ST_EDGE_PRIMARY | ST_EDGE_SECONDARY;
+    o.edge_spp_ratio = 1.0f;
+    return o;
+}
+
+int st_version(void) { return 1; }
+
+const char* st_last_error(void) { return g_err.c_str(); }
+
+int st_scene_create(const float* V, int32_t nv, const int32_t* F, int32_t nf, const float* mat, const float* lights,
+                    int32_t nl, const float* env, int32_t he, int32_t we, uint32_t scene_id, hipStream_t s,
+                    st_scene** out) {
+    if (!out) return fail(ST_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!V || !F || !mat) return fail(ST_ERR_INVALID_ARG, "V, F and face_materials must be non-NULL");
+    if (nv < 3 || nf < 1) return fail(ST_ERR_INVALID_ARG, "need nv >= 3 and nf >= 1");
+    if (nl < 0 || nl > MAX_LIGHTS) return fail(ST_ERR_INVALID_ARG, "nl must be in [0, 16]");
+    if (nl > 0 && !lights) return fail(ST_ERR_INVALID_ARG, "lights is NULL");
+    if (env && (he < 1 || we < 1)) return fail(ST_ERR_INVALID_ARG, "envmap needs he, we >= 1");
+    if (!env) he = we = 0;
+    // topology on the host: validate indices and build the canonical edge list
+    std::vector<int32_t> Fh(3 * (size_t)nf);
+    HIPCHK(hipMemcpyAsync(Fh.data(), F, sizeof(int32_t) * Fh.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int32_t v : Fh)
+        if (v < 0 || v >= nv) return fail(ST_ERR_INVALID_ARG, "face index out of range");
+    std::vector<std::array<int, 3>> hes;
+    hes.reserve(3 * (size_t)nf);
+    for (int f = 0; f < nf; ++f)
+        for (int k = 0; k < 3; ++k) {
+            const int a = Fh[3 * f + k], b = Fh[3 * f + (k + 1) % 3];
+            hes.push_back({std::min(a, b), std::max(a, b), f});
+        }
+    std::sort(hes.begin(), hes.end());
+    std::vector<int4> edges;
+    for (size_t i = 0; i < hes.size();) {
+        size_t j = i;
+        while (j < hes.size() && hes[j][0] == hes[i][0] && hes[j][1] == hes[i][1]) ++j;
+        if (hes[i][0] != hes[i][1]) edges.push_back(make_int4(hes[i][0], hes[i][1], hes[i][2], j - i >= 2 ? hes[i + 1][2] : -1));
+        i = j;
+    }
+
+    st_scene* sc = new st_scene();
+    SceneDev& d = sc->d;
+    d.nv = nv; d.nf = nf; d.nl = nl; d.he = he; d.we = we; d.ne = (int)edges.size(); d.scene_id = scene_id;
+    int rc = ST_OK;
+    auto A = [&](int r) { if (r && !rc) rc = r; };
+    A(dalloc(&d.V, 3 * (size_t)nv)); A(dalloc(&d.F, 3 * (size_t)nf)); A(dalloc(&d.mat, 7 * (size_t)nf));
+    A(dalloc(&d.lights, 6 * (size_t)std::max(nl, 1)));
+    A(dalloc(&d.fnorm, nf)); A(dalloc(&d.bmin, nf)); A(dalloc(&d.bmax, nf)); A(dalloc(&d.cen, nf));
+    A(dalloc(&d.bounds, 16));
+    for (int b = 0; b < 2; ++b) { A(dalloc(&d.mkeys[b], nf)); A(dalloc(&d.mvals[b], nf)); }
+    A(dalloc(&d.rs_hist, 256 * (size_t)((nf + 1023) / 1024)));
+    A(dalloc(&d.keys64, nf));
+    A(dalloc(&d.child, 2 * (size_t)std::max(nf - 1, 1)));
+    A(dalloc(&d.parent, 2 * (size_t)nf));
+    A(dalloc(&d.aabb, 6 * (size_t)(2 * nf)));
+    A(dalloc(&d.refit_cnt, (size_t)nf));
+    A(dalloc(&d.nodes, 4 * (size_t)std::max(nf - 1, 1)));
+    A(dalloc(&d.tri, 3 * (size_t)nf));
+    A(dalloc(&d.edges, edges.size()));
+    A(dalloc(&d.edge_w, edges.size()));
+    A(dalloc(&d.ecdf, edges.size() + 1));
+    A(dalloc(&d.etotal_d, 1));
+    A(dalloc(&d.etotal_f, 1));
+    A(dalloc(&d.err, 1));
+    A(dalloc(&d.dscene, 1));
+    if (he > 0) {
+        A(dalloc(&d.env, 3 * (size_t)he * we));
+        A(dalloc(&d.row_dom, he));
+        A(dalloc(&d.rowcos, he + 1));
+        A(dalloc(&d.cond, (size_t)he * (we + 1)));
+        A(dalloc(&d.marg, he + 1));
+        A(dalloc(&d.env_rows, he));
+        A(dalloc(&d.env_total, 1));
+        A(dalloc(&d.texpdf, (size_t)he * we));
+    }
+    if (rc) { st_scene_destroy(sc); return rc; }
+    auto cleanup_fail = [&](int code, const std::string& m) { st_scene_destroy(sc); return fail(code, m); };
+#define HIPCHK2(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) return cleanup_fail(ST_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); } while (0)
+    HIPCHK2(hipMemcpyAsync(d.V, V, sizeof(float) * 3 * nv, hipMemcpyDeviceToDevice, s));
+    HIPCHK2(hipMemcpyAsync(d.F, F, sizeof(int) * 3 * nf, hipMemcpyDeviceToDevice, s));
+    HIPCHK2(hipMemcpyAsync(d.mat, mat, sizeof(float) * 7 * nf, hipMemcpyDeviceToDevice, s));
+    if (nl > 0) HIPCHK2(hipMemcpyAsync(d.lights, lights, sizeof(float) * 6 * nl, hipMemcpyDeviceToDevice, s));
+    if (!edges.empty())
+        HIPCHK2(hipMemcpyAsync(d.edges, edges.data(), sizeof(int4) * edges.size(), hipMemcpyHostToDevice, s));
+    launch_fill_u32(d.err, 1, 0u, s);
+    std::vector<double> dom(std::max(he, 1));
+    std::vector<float> rowcos(he + 1);
+    if (he > 0) {
+        HIPCHK2(hipMemcpyAsync(d.env, env, sizeof(float) * 3 * (size_t)he * we, hipMemcpyDeviceToDevice, s));
+        const double PI = 3.14159265358979323846;
+        for (int r = 0; r < he; ++r) dom[r] = (2.0 * PI / we) * (std::cos(PI * r / he) - std::cos(PI * (r + 1) / he));
+        for (int r = 0; r <= he; ++r) rowcos[r] = (float)std::cos(PI * r / he);
+        HIPCHK2(hipMemcpyAsync(d.row_dom, dom.data(), sizeof(double) * he, hipMemcpyHostToDevice, s));
+        HIPCHK2(hipMemcpyAsync(d.rowcos, rowcos.data(), sizeof(float) * (he + 1), hipMemcpyHostToDevice, s));
+        launch_env_build(d, s);
+    }
+    launch_scene_geometry(d, s);
+    HIPCHK2(hipGetLastError());
+    double etot = 0.0;
+    if (he > 0) HIPCHK2(hipMemcpyAsync(&etot, d.env_total, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK2(hipStreamSynchronize(s));
+    d.has_env = he > 0 && etot > 0.0;
+    DevScene& h = d.hscene;
+    h.V = d.V; h.F = d.F; h.mat = d.mat; h.lights = d.lights; h.fnorm = d.fnorm; h.tri = d.tri; h.nodes = d.nodes;
+    h.env = d.env; h.marg = d.marg; h.cond = d.cond; h.texpdf = d.texpdf; h.rowcos = d.rowcos;
+    h.edges = d.edges; h.ecdf = d.ecdf; h.etotal = d.etotal_f;
+    h.nv = nv; h.nf = nf; h.nl = nl; h.he = he; h.we = we; h.ne = d.ne; h.has_env = d.has_env ? 1 : 0;
+    h.scene_id = scene_id;
+    HIPCHK2(hipMemcpyAsync(d.dscene, &h, sizeof(DevScene), hipMemcpyHostToDevice, s));
+    HIPCHK2(hipStreamSynchronize(s));
+#undef HIPCHK2
+    *out = sc;
+    return ST_OK;
+}
+
+int st_scene_update(st_scene* sc, const float* V, const float* mat, hipStream_t s) {
+    int rc = check_scene(sc);
+    if (rc) return rc;
+    if (V) HIPCHK(hipMemcpyAsync(sc->d.V, V, sizeof(float) * 3 * sc->d.nv, hipMemcpyDeviceToDevice, s));
+    if (mat) HIPCHK(hipMemcpyAsync(sc->d.mat, mat, sizeof(float) * 7 * sc->d.nf, hipMemcpyDeviceToDevice, s));
+    if (V) launch_scene_geometry(sc->d, s);
+    HIPCHK(hipGetLastError());
+    return ST_OK;
+}
+
+int st_render(st_scene* sc, const st_camera* cams, int32_t ncam, int32_t spp, int32_t bounces, uint32_t seed,
+              const st_render_opts* opts, float* out, hipStream_t s) {
+    int rc = check_scene(sc);
+    if (rc) return rc;
+    st_scene* list[1] = {sc};
+    return render_impl(sc, list, 1, cams, nullptr, ncam, spp, bounces, seed, opts, out, s);
+}
+
+int st_render_batch(st_scene* const* scenes, int32_t nscenes, const st_camera* cams, const int32_t* cam_scene,
+                    int32_t ncam, int32_t spp, int32_t bounces, uint32_t seed, const st_render_opts* opts,
+                    float* out, hipStream_t s) {
+    if (!scenes || nscenes < 1) return fail(ST_ERR_INVALID_ARG, "need at least one scene");
+    for (int i = 0; i < nscenes; ++i)
+        if (!scenes[i]) return fail(ST_ERR_INVALID_ARG, "scene is NULL");
+    if (!cam_scene) return fail(ST_ERR_INVALID_ARG, "cam_scene is NULL");
+    return render_impl(scenes[0], scenes, nscenes, cams, cam_scene, ncam, spp, bounces, seed, opts, out, s);
+}
+
+int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_t spp, int32_t bounces,
+                       uint32_t seed, const st_render_opts* opts, const float* d_image, float* out_dV,
+                       float* out_dmat, hipStream_t s) {
+    int rc = check_scene(sc);
+    if (rc) return rc;
+    if (!d_image || !out_dV || !out_dmat) return fail(ST_ERR_INVALID_ARG, "d_image, out_dV and out_dmat must be non-NULL");
+    if (bounces < 1 || bounces > 8) return fail(ST_ERR_INVALID_ARG, "bounces must be in [1, 8]");
+    st_render_opts o = opts ? *opts : st_render_opts_default();
+    if (!(o.edge_spp_ratio >= 0.0f) || o.edge_spp_ratio > 64.0f) return fail(ST_ERR_INVALID_ARG, "edge_spp_ratio must be in [0, 64]");
+    CamSetup cs;
+    rc = setup_cams(sc, cams, nullptr, ncam, spp, (double)o.edge_spp_ratio, 1, s, cs);
+    if (rc) return rc;
+    rc = ensure_spill(sc);
+    if (rc) return rc;
+    const int ne = sc->d.ne;
+    const size_t pbytes = sizeof(double) * ((size_t)ncam * ne + (size_t)ncam * (ne + 1) + ncam) + 3 * 256;
+    rc = sc->primbuf.ensure(pbytes);
+    if (rc) return rc;
+    Carver c{(char*)sc->primbuf.p};
+    BwdParams p;
+    p.scenes = sc->d.dscene;
+    p.cams = cs.cams;
+    p.qoff = cs.qoff;
+    p.eoff = cs.eoff;
+    p.ncam = ncam;
+    p.spp = spp;
+    p.B = bounces;
+    p.seed = seed;
+    p.flags = o.flags & 7u;
+    p.d_image = d_image;
+    p.path_mask = o.path_mask;
+    p.edge_mask = o.edge_mask;
+    p.dV = out_dV;
+    p.dmat = out_dmat;
+    p.dbg_hash = o.debug_decision_hash;
+    p.dbg_edge_hash = o.debug_edge_hash;
+    p.err = sc->d.err;
+    p.spill = (uint32_t*)sc->spillbuf.p;
+    p.pw = c.take<double>((size_t)ncam * ne);
+    p.pcdf = c.take<double>((size_t)ncam * (ne + 1));
+    p.ptotal = c.take<double>(ncam);
+    p.ne = ne;
+    launch_fill_f32(out_dV, 3ll * sc->d.nv, 0.0f, s);
+    launch_fill_f32(out_dmat, 7ll * sc->d.nf, 0.0f, s);
+    if (o.debug_decision_hash) launch_fill_u32(o.debug_decision_hash, cs.total_paths, 0u, s);
+    if (o.debug_edge_hash) launch_fill_u32(o.debug_edge_hash, cs.total_edges, 0u, s);
+    launch_backward(p, cs.total_paths, cs.total_edges, TRACE_GRID, s);
+    HIPCHK(hipGetLastError());
+    return ST_OK;
+}
+
+int st_check_errors(st_scene* sc, hipStream_t s) {
+    int rc = check_scene(sc);
+    if (rc) return rc;
+    uint32_t e = 0;
+    HIPCHK(hipMemcpyAsync(&e, sc->d.err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (e) {
+        launch_fill_u32(sc->d.err, 1, 0u, s);
+        HIPCHK(hipStreamSynchronize(s));
+        return fail(ST_ERR_DEVICE_FAULT, "device error word " + std::to_string(e) + " (1: traversal stack overflow, 8: traversal iteration cap)");
+    }
+    return ST_OK;
+}
+
+int st_scene_info(const st_scene* sc, int64_t* out6) {
+    int rc = check_scene(sc);
+    if (rc) return rc;
+    if (!out6) return fail(ST_ERR_INVALID_ARG, "out is NULL");
+    out6[0] = sc->d.nv; out6[1] = sc->d.nf; out6[2] = sc->d.ne; out6[3] = sc->d.nl; out6[4] = sc->d.he; out6[5] = sc->d.we;
+    return ST_OK;
+}
+
+int st_scene_edges(st_scene* sc, int32_t* out, hipStream_t s) {
+    int rc = check_scene(sc);
+    if (rc) return rc;
+    if (!out) return fail(ST_ERR_INVALID_ARG, "out is NULL");
+    if (sc->d.ne > 0) HIPCHK(hipMemcpyAsync(out, sc->d.edges, sizeof(int4) * sc->d.ne, hipMemcpyDeviceToDevice, s));
+    return ST_OK;
+}
+
+int st_scene_lbvh(st_scene* sc, uint64_t* keys, int32_t* child, int32_t* parent, float* aabb, hipStream_t s) {
+    int rc = check_scene(sc);
+    if (rc) return rc;
+    const size_t n = sc->d.nf;
+    if (keys) HIPCHK(hipMemcpyAsync(keys, sc->d.keys64, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s));
+    if (child && n > 1) HIPCHK(hipMemcpyAsync(child, sc->d.child, sizeof(int) * 2 * (n - 1), hipMemcpyDeviceToDevice, s));
+    if (parent) {
+        if (n == 1) launch_fill_u32((uint32_t*)parent, 1, 0xFFFFFFFFu, s);
+        else HIPCHK(hipMemcpyAsync(parent, sc->d.parent, sizeof(int) * (2 * n - 1), hipMemcpyDeviceToDevice, s));
+    }
+    if (aabb) HIPCHK(hipMemcpyAsync(aabb, sc->d.aabb, sizeof(float) * 6 * (2 * n - 1), hipMemcpyDeviceToDevice, s));
+    return ST_OK;
+}
+
+int st_trace_rays(st_scene* sc, const float* o, const float* d, int32_t n, float tmin, int32_t brute, int32_t* of,
+                  float* ot, hipStream_t s) {
+    int rc = check_scene(sc);
+    if (rc) return rc;
+    if (n < 0 || (long long)n > (long long)TRACE_GRID * TRACE_BLOCK) return fail(ST_ERR_INVALID_ARG, "n out of range");
+    if (n > 0 && (!o || !d || !of || !ot)) return fail(ST_ERR_INVALID_ARG, "NULL array");
+    rc = ensure_spill(sc);
+    if (rc) return rc;
+    launch_trace_debug(sc->d.dscene, o, d, n, tmin, brute, of, ot, (uint32_t*)sc->spillbuf.p, sc->d.err, s);
+    HIPCHK(hipGetLastError());
+    return ST_OK;
+}
+
+void st_scene_destroy(st_scene* sc) {
+    if (!sc) return;
+    hipDeviceSynchronize();
+    SceneDev& d = sc->d;
+    void* ptrs[] = {d.V, d.F, d.mat, d.lights, d.env, d.fnorm, d.bmin, d.bmax, d.cen, d.bounds, d.mkeys[0], d.mkeys[1],
+                    d.mvals[0], d.mvals[1], d.rs_hist, d.keys64, d.child, d.parent, d.aabb, d.refit_cnt, d.nodes,
+                    d.tri, d.edges, d.edge_w, d.ecdf, d.etotal_d, d.etotal_f, d.row_dom, d.rowcos, d.cond, d.marg,
+                    d.env_rows, d.env_total, d.texpdf, d.err, d.dscene};
+    for (void* p : ptrs)
+        if (p) hipFree(p);
+    sc->camsbuf.release(); sc->Lbuf.release(); sc->qbuf.release(); sc->spillbuf.release(); sc->primbuf.release();
+    sc->scenesbuf.release();
+    if (sc->pinned) hipHostFree(sc->pinned);
+    if (sc->staged) hipEventDestroy(sc->staged);
+    delete sc;
+}
+
+} // extern "C"

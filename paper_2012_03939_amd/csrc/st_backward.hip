@@ -1,0 +1,501 @@
+// Adjoint of the path tracer (Shape from Tracing, Sec. 3.2: gradients of the
+// rendered pixels with respect to vertex positions, and Sec. 3.3 per-facet
+// materials; the edge-sampled visibility terms follow the renderer the paper
+// cites for geometry gradients).
+//
+// Interior term: every path sample is replayed from its Philox counters (no
+// state is kept from the forward pass), its at most B vertices are recorded in
+// registers, and a reverse sweep differentiates the estimator at fixed sampled
+// directions with pdfs, MIS weights and visibility held constant; hit points
+// move with the hit face's vertices and the previous vertex, point-light
+// directions move with the hit point.
+//
+// Secondary edges: at each vertex one mesh edge is drawn in proportion to its
+// length; if it is a silhouette seen from the shading point, two side rays
+// bracket it and the jump of incoming radiance times the normal velocity of
+// the edge on the sphere of directions is scattered to the edge endpoints and
+// to the shading point.
+//
+// Primary edges: per view, edges are drawn in proportion to their projected
+// length (candidates: boundary edges and edges with a front-facing face), a
+// point on the edge gets two side camera paths, and the radiance jump times the
+// screen-space normal velocity is scattered to the two endpoints.
+#include "st_internal.h"
+
+namespace st {
+
+__device__ __forceinline__ TravStack make_stack_b(uint32_t* lds, uint32_t* spill, uint32_t* err) {
+    TravStack s;
+    s.lds = lds;
+    s.spill = spill;
+    s.bs = blockDim.x;
+    s.tid = threadIdx.x;
+    s.gstride = gridDim.x * blockDim.x;
+    s.gid = blockIdx.x * blockDim.x + threadIdx.x;
+    s.err = err;
+    return s;
+}
+
+template <class T, int N> __device__ __forceinline__ T sel(const T (&a)[N], int k) {
+    T r = a[0];
+#pragma unroll
+    for (int i = 1; i < N; ++i)
+        if (i == k) r = a[i];
+    return r;
+}
+template <class T, int N> __device__ __forceinline__ void put(T (&a)[N], int k, const T& v) {
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+        if (i == k) a[i] = v;
+}
+
+__device__ __forceinline__ void atomic_add3(float* p, V3 g) {
+    atomicAdd(p, g.x);
+    atomicAdd(p + 1, g.y);
+    atomicAdd(p + 2, g.z);
+}
+
+// unnormalised face normal in double, fixed operation order
+__device__ __forceinline__ void face_N_d(const DevScene& S, int f, double N[3], double v0[3]) {
+#pragma clang fp contract(off)
+    const float* a = S.V + 3 * S.F[3 * f];
+    const float* b = S.V + 3 * S.F[3 * f + 1];
+    const float* c = S.V + 3 * S.F[3 * f + 2];
+    const double e1x = (double)b[0] - (double)a[0], e1y = (double)b[1] - (double)a[1], e1z = (double)b[2] - (double)a[2];
+    const double e2x = (double)c[0] - (double)a[0], e2y = (double)c[1] - (double)a[1], e2z = (double)c[2] - (double)a[2];
+    N[0] = e1y * e2z - e1z * e2y;
+    N[1] = e1z * e2x - e1x * e2z;
+    N[2] = e1x * e2y - e1y * e2x;
+    v0[0] = a[0]; v0[1] = a[1]; v0[2] = a[2];
+}
+
+__device__ __forceinline__ bool silhouette(const DevScene& S, int4 E, V3 x) {
+#pragma clang fp contract(off)
+    if (E.w < 0) return true;
+    const double xa[3] = {(double)x.x - (double)S.V[3 * E.x], (double)x.y - (double)S.V[3 * E.x + 1],
+                          (double)x.z - (double)S.V[3 * E.x + 2]};
+    double N1[3], N2[3], t[3];
+    face_N_d(S, E.z, N1, t);
+    face_N_d(S, E.w, N2, t);
+    const double s1 = N1[0] * xa[0] + N1[1] * xa[1] + N1[2] * xa[2];
+    const double s2 = N2[0] * xa[0] + N2[1] * xa[1] + N2[2] * xa[2];
+    return (s1 > 0.0) != (s2 > 0.0);
+}
+
+constexpr uint32_t R_FLIP = 1u, R_ENV = 2u, R_CONT = 4u, R_ESC = 8u, R_SEC = 16u;
+
+template <int BM>
+__global__ void __launch_bounds__(TRACE_BLOCK) k_adjoint(BwdParams p, long long total) {
+    __shared__ uint32_t lds[LDS_STACK * TRACE_BLOCK];
+    TravStack st = make_stack_b(lds, p.spill, p.err);
+    const bool want_interior = p.flags & 1u, want_secondary = p.flags & 4u;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long qq = blockIdx.x * (long long)blockDim.x + threadIdx.x; qq < total; qq += stride) {
+        const int vw = find_view(p.qoff, p.ncam, qq);
+        const DevCam& c = p.cams[vw];
+        const DevScene& S = p.scenes[c.scene];
+        int x, y, j;
+        decode_path(c, qq - c.qoff, p.spp, x, y, j);
+        const long long g = (c.pixoff + (long long)y * c.W + x) * p.spp + j;
+        if (p.path_mask && !p.path_mask[g]) continue;
+        const float* di = p.d_image + 3 * (c.pixoff + (long long)y * c.W + x);
+        if (di[0] == 0.0f && di[1] == 0.0f && di[2] == 0.0f) continue;
+        const V3 w = V3{di[0], di[1], di[2]} * (1.0f / (float)p.spp);
+        const Key key{p.seed, S.scene_id};
+        const Ctr ctr{(uint32_t)(y * c.W + x), ((uint32_t)vw << 16) | (uint32_t)j, 0u, 0u};
+        const float4 u0 = draw4(ctr, 0, 0, key);
+        const V3 d0 = cam_dir(c, (float)x + u0.x, (float)y + u0.y);
+        Hash h{FNV_INIT, p.dbg_hash != nullptr};
+
+        // ---- replay, recording each vertex --------------------------------
+        int rf[BM], rtex[BM], rse[BM];
+        uint32_t rfl[BM];
+        V3 rx[BM], rwe[BM], rwi[BM], resc[BM], rbeta[BM], rsecm[BM];
+        float rden[BM], rpb[BM], rte[BM], rsecc[BM];
+#pragma unroll
+        for (int i = 0; i < BM; ++i) {
+            rf[i] = -1; rtex[i] = 0; rse[i] = -1; rfl[i] = 0;
+            rx[i] = rwe[i] = rwi[i] = resc[i] = rbeta[i] = rsecm[i] = V3{0.f, 0.f, 0.f};
+            rden[i] = rpb[i] = rte[i] = rsecc[i] = 0.0f;
+        }
+        int nvtx = 0;
+        {
+            V3 o = ld3(c.eye), d = d0, beta{1.f, 1.f, 1.f};
+            int excl = -1;
+            float pprev = 0.0f;
+            for (int k = 1; k <= p.B + 1; ++k) {
+                float t;
+                const int f = trace_closest(S, o, d, TMIN, excl, t, st);
+                push_face(h, f);
+                if (f < 0) {
+                    if (S.has_env && k > 1) {
+                        const int tex = env_texel_of(S, d);
+                        h.push((uint32_t)tex);
+                        const float wv = pprev / (pprev + S.texpdf[tex]);
+                        put(resc, k - 2, env_rgb(S, tex) * wv);
+                        put(rfl, k - 2, sel(rfl, k - 2) | R_ESC);
+                    }
+                    break;
+                }
+                if (k == p.B + 1) break;
+                const V3 xh = o + d * t;
+                V3 n = xyz(S.fnorm[f]);
+                const V3 wo = -d;
+                uint32_t fl = 0;
+                if (dot(n, wo) < 0.0f) { n = -n; fl |= R_FLIP; }
+                const Mat m = load_mat(S.mat + 7 * (size_t)f);
+                for (int l = 0; l < S.nl; ++l) {
+                    const float* lt = S.lights + 6 * l;
+                    const V3 dl = ld3(lt) - xh;
+                    const float r2 = dot(dl, dl);
+                    uint32_t code = 0;
+                    if (r2 > 0.0f) {
+                        const float rr = sqrtf(r2);
+                        const V3 wl = dl * (1.0f / rr);
+                        if (dot(n, wl) > 0.0f) {
+                            const bool occ = trace_any(S, xh, wl, TMIN, rr * (1.0f - SHADOW_SHRINK), f, st);
+                            code = occ ? 1u : 2u;
+                            if (!occ) fl |= 1u << (8 + l);
+                        }
+                    }
+                    h.push(code);
+                }
+                if (S.has_env) {
+                    const float4 u = draw4(ctr, k, 1, key);
+                    V3 we; float pe;
+                    const int tex = env_sample(S, u, we, pe);
+                    h.push((uint32_t)tex);
+                    const float ce = dot(n, we);
+                    uint32_t code = 0;
+                    if (ce > 0.0f && pe > 0.0f) {
+                        const bool occ = trace_any(S, xh, we, TMIN, __int_as_float(0x7f800000), f, st);
+                        code = occ ? 1u : 2u;
+                        if (!occ) {
+                            fl |= R_ENV;
+                            put(rwe, k - 1, we);
+                            put(rden, k - 1, pe + bsdf_pdf(we, wo, n, m.a));
+                            put(rtex, k - 1, tex);
+                        }
+                    }
+                    h.push(code);
+                }
+                const bool continues = (k < p.B) || S.has_env;
+                if (want_secondary && continues && S.ne > 0 && *S.etotal > 0.0f) {
+                    const float4 u = draw4(ctr, k, 3, key);
+                    put(rse, k - 1, cdf_find(S.ecdf, S.ne, (double)u.x));
+                    put(rte, k - 1, u.y);
+                }
+                put(rf, k - 1, f);
+                put(rx, k - 1, xh);
+                put(rbeta, k - 1, beta);
+                nvtx = k;
+                if (!continues) { put(rfl, k - 1, fl); break; }
+                const float4 u = draw4(ctr, k, 2, key);
+                V3 wi;
+                const int lobe = bsdf_sample(u, wo, n, m.a, wi);
+                const float ci = dot(n, wi);
+                const float pb = bsdf_pdf(wi, wo, n, m.a);
+                h.push((uint32_t)lobe);
+                if (!(ci > 0.0f) || !(pb > 0.0f)) { h.push(0u); put(rfl, k - 1, fl); break; }
+                h.push(1u);
+                fl |= R_CONT;
+                put(rfl, k - 1, fl);
+                put(rwi, k - 1, wi);
+                put(rpb, k - 1, pb);
+                beta = mul(beta, brdf_eval(wi, wo, n, m)) * (ci / pb);
+                pprev = pb;
+                o = xh; d = wi; excl = f;
+            }
+        }
+
+        // ---- secondary edge samples (side paths in their own stream) --------
+        if (want_secondary) {
+            for (int k = 0; k < nvtx; ++k) {
+                const int e = sel(rse, k);
+                if (e < 0) continue;
+                h.push((uint32_t)e);
+                const int f = sel(rf, k);
+                const V3 xh = sel(rx, k);
+                const int4 E = S.edges[e];
+                const V3 va = ld3(S.V + 3 * E.x), vb = ld3(S.V + 3 * E.y);
+                const float te = sel(rte, k);
+                const V3 yv = va + (vb - va) * te;
+                const V3 wv = yv - xh;
+                const float r2 = dot(wv, wv);
+                bool ok = silhouette(S, E, xh) && r2 > 0.0f;
+                V3 n = xyz(S.fnorm[f]);
+                if (sel(rfl, k) & R_FLIP) n = -n;
+                V3 ud{0.f, 0.f, 0.f}, mv{0.f, 0.f, 0.f};
+                float cv = 0.0f, ml = 0.0f;
+                if (ok) {
+                    ud = wv * (1.0f / sqrtf(r2));
+                    cv = dot(n, ud);
+                    mv = cross(ud, normalize(vb - va));
+                    ml = len(mv);
+                    ok = cv > 0.0f && ml > 0.0f;
+                }
+                if (!ok) { h.push(0u); continue; }
+                h.push(1u);
+                const V3 mm = mv * (1.0f / ml);
+                const Ctr sc{ctr.c0, ctr.c1, (uint32_t)(k + 1) << 16, 2u};
+                V3 Ls[2];
+                for (int side = 0; side < 2; ++side) {
+                    const V3 dir = normalize(ud + mm * (side == 0 ? -EPS_SECONDARY : EPS_SECONDARY));
+                    Ls[side] = trace_estimator(S, xh, dir, f, p.B - (k + 1), true, sc, key, h, st);
+                }
+                const V3 dirk = k == 0 ? d0 : sel(rwi, k - 1);
+                const Mat m = load_mat(S.mat + 7 * (size_t)f);
+                const V3 fv = brdf_eval(ud, -dirk, n, m);
+                const float cc = dot(mul(w, mul(sel(rbeta, k), fv)), Ls[0] - Ls[1]) * cv * (*S.etotal / r2);
+                put(rsecc, k, cc);
+                put(rsecm, k, mv);
+                put(rfl, k, sel(rfl, k) | R_SEC);
+                atomic_add3(p.dV + 3 * (size_t)E.x, mv * (cc * (1.0f - te)));
+                atomic_add3(p.dV + 3 * (size_t)E.y, mv * (cc * te));
+            }
+        }
+
+        // ---- reverse sweep ------------------------------------------------
+        {
+            V3 Snext{0.f, 0.f, 0.f}, gxnext{0.f, 0.f, 0.f};
+            for (int k = nvtx - 1; k >= 0; --k) {
+                const int f = sel(rf, k);
+                const uint32_t fl = sel(rfl, k);
+                const V3 xh = sel(rx, k);
+                const V3 dir = k == 0 ? d0 : sel(rwi, k - 1);
+                const V3 wo = -dir;
+                const int i0 = S.F[3 * f], i1 = S.F[3 * f + 1], i2 = S.F[3 * f + 2];
+                const V3 v0 = ld3(S.V + 3 * i0), v1 = ld3(S.V + 3 * i1), v2 = ld3(S.V + 3 * i2);
+                const V3 e1 = v1 - v0, e2 = v2 - v0;
+                const V3 N = cross(e1, e2);
+                const float Nl = len(N);
+                const V3 nu = N * (1.0f / Nl);
+                const float sg = (fl & R_FLIP) ? -1.0f : 1.0f;
+                const V3 n = nu * sg;
+                const Mat m = load_mat(S.mat + 7 * (size_t)f);
+                const V3 a = want_interior ? mul(w, sel(rbeta, k)) : V3{0.f, 0.f, 0.f};
+                V3 C{0.f, 0.f, 0.f}, gn{0.f, 0.f, 0.f}, gx = gxnext, gdummy{0.f, 0.f, 0.f};
+                float gm[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                for (int l = 0; l < S.nl; ++l) {
+                    if (!((fl >> (8 + l)) & 1u)) continue;
+                    const float* lt = S.lights + 6 * l;
+                    const V3 I = ld3(lt + 3);
+                    const V3 dl = ld3(lt) - xh;
+                    const float r2 = dot(dl, dl);
+                    const float rr = sqrtf(r2);
+                    const V3 wl = dl * (1.0f / rr);
+                    const float cl = dot(n, wl);
+                    const V3 fv = brdf_eval(wl, wo, n, m);
+                    const V3 If = mul(I, fv);
+                    C = C + If * (cl / r2);
+                    const V3 aI = mul(a, I);
+                    const float gcl = dot(aI, fv) / r2;
+                    const float gr2 = -dot(aI, fv) * cl / (r2 * r2);
+                    V3 gwl{0.f, 0.f, 0.f};
+                    brdf_backward(wl, wo, n, m, aI * (cl / r2), gn, gwl, gm);
+                    gn = gn + wl * gcl;
+                    gwl = gwl + n * gcl;
+                    const V3 gd = (gwl - wl * dot(wl, gwl)) * (1.0f / rr) + dl * (2.0f * gr2);
+                    gx = gx - gd;
+                }
+                if (fl & R_ENV) {
+                    const V3 we = sel(rwe, k);
+                    const float den = sel(rden, k);
+                    const V3 Le = env_rgb(S, sel(rtex, k));
+                    const float ce = dot(n, we);
+                    const V3 fv = brdf_eval(we, wo, n, m);
+                    C = C + mul(Le, fv) * (ce / den);
+                    const V3 aL = mul(a, Le);
+                    brdf_backward(we, wo, n, m, aL * (ce / den), gn, gdummy, gm);
+                    gn = gn + we * (dot(aL, fv) / den);
+                }
+                V3 Sk = C;
+                if (fl & R_CONT) {
+                    const V3 wi = sel(rwi, k);
+                    const float pb = sel(rpb, k);
+                    const V3 S1 = (fl & R_ESC) ? sel(resc, k) : Snext;
+                    const float ci = dot(n, wi);
+                    const V3 fv = brdf_eval(wi, wo, n, m);
+                    const V3 uu = mul(a, S1);
+                    brdf_backward(wi, wo, n, m, uu * (ci / pb), gn, gdummy, gm);
+                    gn = gn + wi * (dot(uu, fv) / pb);
+                    Sk = Sk + mul(fv, S1) * (ci / pb);
+                }
+                if (fl & R_SEC) gx = gx - sel(rsecm, k) * sel(rsecc, k);
+                // normal n = sg * N / |N|
+                const V3 gnu = gn * sg;
+                V3 gN = (gnu - nu * dot(nu, gnu)) * (1.0f / Nl);
+                // hit point x = o + t dir, t = ((v0 - o) . N) / (dir . N)
+                const float dN = dot(dir, N);
+                const float gt = dot(gx, dir) / dN;
+                const V3 go = gx - N * gt;
+                V3 gv0 = N * gt;
+                gN = gN + (v0 - xh) * gt;
+                const V3 ge1 = cross(e2, gN), ge2 = cross(gN, e1);
+                gv0 = gv0 - ge1 - ge2;
+                if (want_interior || want_secondary) {
+                    atomic_add3(p.dV + 3 * (size_t)i0, gv0);
+                    atomic_add3(p.dV + 3 * (size_t)i1, ge1);
+                    atomic_add3(p.dV + 3 * (size_t)i2, ge2);
+                }
+                if (want_interior) {
+                    float* dm = p.dmat + 7 * (size_t)f;
+                    for (int i = 0; i < 7; ++i) atomicAdd(dm + i, gm[i]);
+                }
+                Snext = Sk;
+                gxnext = go;
+            }
+        }
+        if (p.dbg_hash) p.dbg_hash[g] = h.h;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// primary edges
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void project_d(const DevCam& c, double vx, double vy, double vz, double& sx, double& sy,
+                                          double& z) {
+#pragma clang fp contract(off)
+    const double px = vx - c.deye[0], py = vy - c.deye[1], pz = vz - c.deye[2];
+    z = px * c.df[0] + py * c.df[1] + pz * c.df[2];
+    const double a = px * c.dr[0] + py * c.dr[1] + pz * c.dr[2];
+    const double b = px * c.du[0] + py * c.du[1] + pz * c.du[2];
+    sx = (a / (z * (c.dth * c.daspect)) + 1.0) * (0.5 * c.W);
+    sy = (1.0 - b / (z * c.dth)) * (0.5 * c.H);
+}
+
+__device__ __forceinline__ bool front_facing_d(const DevScene& S, int f, const DevCam& c) {
+#pragma clang fp contract(off)
+    double N[3], v0[3];
+    face_N_d(S, f, N, v0);
+    const double wx = c.deye[0] - v0[0], wy = c.deye[1] - v0[1], wz = c.deye[2] - v0[2];
+    return N[0] * wx + N[1] * wy + N[2] * wz > 0.0;
+}
+
+__global__ void k_prim_weights(BwdParams p) {
+#pragma clang fp contract(off)
+    const int v = blockIdx.y;
+    const DevCam& c = p.cams[v];
+    const DevScene& S = p.scenes[c.scene];
+    const int ne = S.ne;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += gridDim.x * blockDim.x) {
+        const int4 E = S.edges[e];
+        double lenv = 0.0;
+        const bool cand = E.w < 0 || front_facing_d(S, E.z, c) || front_facing_d(S, E.w, c);
+        if (cand) {
+            double ax, ay, az, bx, by, bz;
+            project_d(c, S.V[3 * E.x], S.V[3 * E.x + 1], S.V[3 * E.x + 2], ax, ay, az);
+            project_d(c, S.V[3 * E.y], S.V[3 * E.y + 1], S.V[3 * E.y + 2], bx, by, bz);
+            if (az > ZNEAR && bz > ZNEAR) {
+                const double dx = bx - ax, dy = by - ay;
+                lenv = sqrt(dx * dx + dy * dy);
+            }
+        }
+        p.pw[(size_t)v * p.ne + e] = lenv;
+    }
+}
+
+__global__ void k_prim_cdf(BwdParams p) {
+    const int v = blockIdx.x;
+    const DevScene& S = p.scenes[p.cams[v].scene];
+    block_scan_normalise(p.pw + (size_t)v * p.ne, S.ne, p.pcdf + (size_t)v * (p.ne + 1), p.ptotal + v);
+}
+
+__global__ void __launch_bounds__(TRACE_BLOCK) k_prim_samples(BwdParams p, long long total) {
+    __shared__ uint32_t lds[LDS_STACK * TRACE_BLOCK];
+    TravStack st = make_stack_b(lds, p.spill, p.err);
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long ge = blockIdx.x * (long long)blockDim.x + threadIdx.x; ge < total; ge += stride) {
+        if (p.edge_mask && !p.edge_mask[ge]) continue;
+        const int v = find_view(p.eoff, p.ncam, ge);
+        const DevCam& c = p.cams[v];
+        const DevScene& S = p.scenes[c.scene];
+        const double tot = p.ptotal[v];
+        if (!(tot > 0.0)) continue;
+        const long long si = ge - c.eoff;
+        const Key key{p.seed, S.scene_id};
+        const Ctr ctr{(uint32_t)si, (uint32_t)v << 16, 0u, 1u};
+        const float4 u = draw4(ctr, 0, 3, key);
+        const int e = cdf_find(p.pcdf + (size_t)v * (p.ne + 1), S.ne, (double)u.x);
+        const double t = u.y;
+        const int4 E = S.edges[e];
+        double ax, ay, az, bx, by, bz;
+        project_d(c, S.V[3 * E.x], S.V[3 * E.x + 1], S.V[3 * E.x + 2], ax, ay, az);
+        project_d(c, S.V[3 * E.y], S.V[3 * E.y + 1], S.V[3 * E.y + 2], bx, by, bz);
+        const double xs = (1.0 - t) * ax + t * bx, ys = (1.0 - t) * ay + t * by;
+        const int px = (int)floor(xs), py = (int)floor(ys);
+        const bool inside = xs >= 0.0 && ys >= 0.0 && px < c.W && py < c.H;
+        const float* di = inside ? p.d_image + 3 * (c.pixoff + (long long)py * c.W + px) : nullptr;
+        if (inside && di[0] == 0.0f && di[1] == 0.0f && di[2] == 0.0f) continue;
+        Hash h{FNV_INIT, p.dbg_edge_hash != nullptr};
+        h.push((uint32_t)e);
+        if (!inside) {
+            h.push(0u);
+            if (p.dbg_edge_hash) p.dbg_edge_hash[ge] = h.h;
+            continue;
+        }
+        h.push(1u);
+        const double dx = bx - ax, dy = by - ay;
+        const double l = sqrt(dx * dx + dy * dy);
+        const double nx = -dy / l, ny = dx / l;
+        V3 Ls[2];
+        for (int side = 0; side < 2; ++side) {
+            const double sgn = side == 0 ? -1.0 : 1.0;
+            const double sx = xs + sgn * EPS_PRIMARY * nx, sy = ys + sgn * EPS_PRIMARY * ny;
+            const double ndx = 2.0 * sx / c.W - 1.0, ndy = 1.0 - 2.0 * sy / c.H;
+            const double kx = ndx * c.dth * c.daspect, ky = ndy * c.dth;
+            double ddx = c.df[0] + c.dr[0] * kx + c.du[0] * ky;
+            double ddy = c.df[1] + c.dr[1] * kx + c.du[1] * ky;
+            double ddz = c.df[2] + c.dr[2] * kx + c.du[2] * ky;
+            const double il = 1.0 / sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
+            const V3 dir{(float)(ddx * il), (float)(ddy * il), (float)(ddz * il)};
+            Ls[side] = trace_estimator(S, ld3(c.eye), dir, -1, p.B, false, ctr, key, h, st);
+        }
+        const double cc = ((double)di[0] * (Ls[0].x - Ls[1].x) + (double)di[1] * (Ls[0].y - Ls[1].y) +
+                           (double)di[2] * (Ls[0].z - Ls[1].z)) * (tot / (double)c.ne);
+        for (int end = 0; end < 2; ++end) {
+            const int vid = end == 0 ? E.x : E.y;
+            const double wgt = end == 0 ? (1.0 - t) : t;
+            const double qx = (double)S.V[3 * vid] - c.deye[0], qy = (double)S.V[3 * vid + 1] - c.deye[1],
+                         qz = (double)S.V[3 * vid + 2] - c.deye[2];
+            const double z = qx * c.df[0] + qy * c.df[1] + qz * c.df[2];
+            const double aa = qx * c.dr[0] + qy * c.dr[1] + qz * c.dr[2];
+            const double bb = qx * c.du[0] + qy * c.du[1] + qz * c.du[2];
+            const double kx = (0.5 * c.W) / (c.dth * c.daspect) / (z * z);
+            const double ky = -(0.5 * c.H) / c.dth / (z * z);
+            double gv[3];
+            for (int k3 = 0; k3 < 3; ++k3) {
+                const double dsx = kx * (c.dr[k3] * z - aa * c.df[k3]);
+                const double dsy = ky * (c.du[k3] * z - bb * c.df[k3]);
+                gv[k3] = cc * wgt * (dsx * nx + dsy * ny);
+            }
+            atomic_add3(p.dV + 3 * (size_t)vid, V3{(float)gv[0], (float)gv[1], (float)gv[2]});
+        }
+        if (p.dbg_edge_hash) p.dbg_edge_hash[ge] = h.h;
+    }
+}
+
+// ---------------------------------------------------------------------------
+static inline unsigned gridb(long long n, int bs, int cap) {
+    long long g = (n + bs - 1) / bs;
+    if (g < 1) g = 1;
+    return (unsigned)(g < cap ? g : cap);
+}
+
+void launch_backward(const BwdParams& p, long long total_paths, long long total_edges, int grid, hipStream_t st) {
+    if ((p.flags & 5u) && total_paths > 0) {
+        const dim3 gd(gridb(total_paths, TRACE_BLOCK, grid)), bd(TRACE_BLOCK);
+        if (p.B <= 1) hipLaunchKernelGGL(k_adjoint<1>, gd, bd, 0, st, p, total_paths);
+        else if (p.B <= 2) hipLaunchKernelGGL(k_adjoint<2>, gd, bd, 0, st, p, total_paths);
+        else if (p.B <= 3) hipLaunchKernelGGL(k_adjoint<3>, gd, bd, 0, st, p, total_paths);
+        else hipLaunchKernelGGL(k_adjoint<8>, gd, bd, 0, st, p, total_paths);
+    }
+    if ((p.flags & 2u) && total_edges > 0 && p.ne > 0) {
+        hipLaunchKernelGGL(k_prim_weights, dim3(gridb(p.ne, 256, 1024), p.ncam), dim3(256), 0, st, p);
+        hipLaunchKernelGGL(k_prim_cdf, dim3(p.ncam), dim3(1024), 0, st, p);
+        hipLaunchKernelGGL(k_prim_samples, dim3(gridb(total_edges, TRACE_BLOCK, grid)), dim3(TRACE_BLOCK), 0, st, p,
+                           total_edges);
+    }
+}
+
+} // namespace st

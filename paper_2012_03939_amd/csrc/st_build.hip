@@ -1,0 +1,385 @@
+// Scene build on the GPU: per-face normals and bounds, the LBVH (30-bit Morton
+// codes, stable LSD radix sort, Karras 2012 radix-tree hierarchy, bottom-up
+// min/max refit), the leaf-ordered triangle records, the 3-D edge-length CDF of
+// the secondary edge term, and the environment-map CDFs.
+//
+// The paper (Sec. 3.2, "Representation") relies on fast ray-surface
+// intersection as the bulk of the cost without naming a structure; the LBVH is
+// this library's choice.  Its integer part is bit-exact by specification:
+// float32 centroids (min+max)*0.5, scale = float(1024 / (hi - lo)) evaluated in
+// double, q = clamp(floor((c - lo) * s), 0, 1023), 10 bits per axis with x
+// highest, key = morton << 32 | face, ascending.
+#include "st_internal.h"
+
+namespace st {
+
+// ---------------------------------------------------------------------------
+__global__ void k_face_prep(const float* __restrict__ V, const int* __restrict__ F, int nf, float4* fnorm,
+                            float4* bmin, float4* bmax, float4* cen) {
+#pragma clang fp contract(off)
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    const V3 a = ld3(V + 3 * F[3 * f]), b = ld3(V + 3 * F[3 * f + 1]), c = ld3(V + 3 * F[3 * f + 2]);
+    const V3 N = cross(b - a, c - a);
+    const float l = len(N);
+    const V3 n = l > 0.0f ? N * (1.0f / l) : V3{0.f, 0.f, 0.f};
+    fnorm[f] = make_float4(n.x, n.y, n.z, 0.5f * l);
+    const V3 mn{fminf(a.x, fminf(b.x, c.x)), fminf(a.y, fminf(b.y, c.y)), fminf(a.z, fminf(b.z, c.z))};
+    const V3 mx{fmaxf(a.x, fmaxf(b.x, c.x)), fmaxf(a.y, fmaxf(b.y, c.y)), fmaxf(a.z, fmaxf(b.z, c.z))};
+    bmin[f] = make_float4(mn.x, mn.y, mn.z, 0.f);
+    bmax[f] = make_float4(mx.x, mx.y, mx.z, 0.f);
+    const float cx = mn.x + mx.x, cy = mn.y + mx.y, cz = mn.z + mx.z;
+    cen[f] = make_float4(cx * 0.5f, cy * 0.5f, cz * 0.5f, 0.f);
+}
+
+// single block: centroid bounds and the per-axis Morton scale
+__global__ void k_bounds(const float4* __restrict__ cen, int nf, float* out /* lo[3], hi[3], s[3] */) {
+    __shared__ float smin[3][1024], smax[3][1024];
+    const int t = threadIdx.x;
+    float lo[3] = {__int_as_float(0x7f800000), __int_as_float(0x7f800000), __int_as_float(0x7f800000)};
+    float hi[3] = {-__int_as_float(0x7f800000), -__int_as_float(0x7f800000), -__int_as_float(0x7f800000)};
+    for (int i = t; i < nf; i += blockDim.x) {
+        const float4 c = cen[i];
+        lo[0] = fminf(lo[0], c.x); lo[1] = fminf(lo[1], c.y); lo[2] = fminf(lo[2], c.z);
+        hi[0] = fmaxf(hi[0], c.x); hi[1] = fmaxf(hi[1], c.y); hi[2] = fmaxf(hi[2], c.z);
+    }
+    for (int k = 0; k < 3; ++k) { smin[k][t] = lo[k]; smax[k][t] = hi[k]; }
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (t < s)
+            for (int k = 0; k < 3; ++k) {
+                smin[k][t] = fminf(smin[k][t], smin[k][t + s]);
+                smax[k][t] = fmaxf(smax[k][t], smax[k][t + s]);
+            }
+        __syncthreads();
+    }
+    if (t == 0)
+        for (int k = 0; k < 3; ++k) {
+            const float l = smin[k][0], h = smax[k][0];
+            out[k] = l;
+            out[3 + k] = h;
+            out[6 + k] = h > l ? (float)(1024.0 / ((double)h - (double)l)) : 0.0f;
+        }
+}
+
+__device__ __forceinline__ uint32_t spread10(uint32_t v) {
+    v &= 0x3FFu;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+__global__ void k_morton(const float4* __restrict__ cen, int nf, const float* __restrict__ bnd, uint32_t* keys,
+                         uint32_t* vals) {
+#pragma clang fp contract(off)
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    const float4 c = cen[f];
+    const float cc[3] = {c.x, c.y, c.z};
+    uint32_t q[3];
+    for (int k = 0; k < 3; ++k) {
+        const float d = cc[k] - bnd[k];
+        const float p = d * bnd[6 + k];
+        const int qi = (int)floorf(p);
+        q[k] = (uint32_t)min(1023, max(0, qi));
+    }
+    keys[f] = (spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]);
+    vals[f] = (uint32_t)f;
+}
+
+// ---------------------------------------------------------------------------
+// stable LSD radix sort of (u32 key, u32 value), 8-bit digits, tiles of 1024
+// ---------------------------------------------------------------------------
+constexpr int RS_THREADS = 256;
+constexpr int RS_ITEMS = 4;
+constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
+
+__global__ void k_rs_hist(const uint32_t* __restrict__ keys, int n, int shift, uint32_t* hist, int nblocks) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int base = blockIdx.x * RS_TILE;
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        const int i = base + r * RS_THREADS + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 0xFFu], 1u);
+    }
+    __syncthreads();
+    hist[threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// exclusive scan of hist[256 * nblocks] (digit-major) in one block
+__global__ void k_rs_scan(uint32_t* hist, int total) {
+    __shared__ uint32_t part[1024];
+    const int t = threadIdx.x;
+    const int per = (total + 1023) / 1024;
+    const int b = t * per, e = min(total, b + per);
+    uint32_t s = 0;
+    for (int i = b; i < e; ++i) s += hist[i];
+    part[t] = s;
+    __syncthreads();
+    if (t == 0) {
+        uint32_t acc = 0;
+        for (int i = 0; i < 1024; ++i) { const uint32_t v = part[i]; part[i] = acc; acc += v; }
+    }
+    __syncthreads();
+    uint32_t acc = part[t];
+    for (int i = b; i < e; ++i) { const uint32_t v = hist[i]; hist[i] = acc; acc += v; }
+}
+
+__global__ void k_rs_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* kout,
+                             uint32_t* vout, int n, int shift, const uint32_t* __restrict__ hist, int nblocks) {
+    constexpr int NW = RS_THREADS / 64;
+    __shared__ uint32_t wcount[NW][256];
+    __shared__ uint32_t running[256];
+    __shared__ uint32_t gbase[256];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    running[t] = 0;
+    gbase[t] = hist[t * nblocks + blockIdx.x];
+    for (int k = 0; k < NW; ++k) wcount[k][t] = 0;
+    __syncthreads();
+    const int base = blockIdx.x * RS_TILE;
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        const int i = base + r * RS_THREADS + t;
+        const bool valid = i < n;
+        const uint32_t key = valid ? kin[i] : 0u;
+        const uint32_t val = valid ? vin[i] : 0u;
+        const uint32_t dg = (key >> shift) & 0xFFu;
+        // lanes of this wave holding the same digit
+        uint64_t peers = __ballot(valid);
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t bal = __ballot((dg >> b) & 1u);
+            peers &= ((dg >> b) & 1u) ? bal : ~bal;
+        }
+        const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+        const uint32_t rank = (uint32_t)__popcll(peers & lt);
+        if (valid && rank == 0) wcount[w][dg] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        {   // per digit: offsets of each wave inside this round
+            uint32_t acc = running[t];
+            for (int k = 0; k < NW; ++k) { const uint32_t c = wcount[k][t]; wcount[k][t] = acc; acc += c; }
+            running[t] = acc;
+        }
+        __syncthreads();
+        if (valid) {
+            const uint32_t pos = gbase[dg] + wcount[w][dg] + rank;
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+        for (int k = 0; k < NW; ++k) wcount[k][t] = 0;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Karras 2012 hierarchy over the sorted 64-bit keys (morton << 32 | face)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int kdelta(const uint32_t* m, const uint32_t* fa, int n, int i, int j) {
+    if (j < 0 || j > n - 1) return -1;
+    const uint64_t a = ((uint64_t)m[i] << 32) | fa[i];
+    const uint64_t b = ((uint64_t)m[j] << 32) | fa[j];
+    return __clzll(a ^ b);
+}
+
+__global__ void k_karras(const uint32_t* __restrict__ m, const uint32_t* __restrict__ fa, int n, int* child,
+                         int* parent) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n - 1) return;
+    const int d = kdelta(m, fa, n, i, i + 1) > kdelta(m, fa, n, i, i - 1) ? 1 : -1;
+    const int dmin = kdelta(m, fa, n, i, i - d);
+    int lmax = 2;
+    while (kdelta(m, fa, n, i, i + lmax * d) > dmin) lmax <<= 1;
+    int l = 0;
+    for (int t = lmax >> 1; t >= 1; t >>= 1)
+        if (kdelta(m, fa, n, i, i + (l + t) * d) > dmin) l += t;
+    const int j = i + l * d;
+    const int dnode = kdelta(m, fa, n, i, j);
+    int s = 0, t = l;
+    do {
+        t = (t + 1) >> 1;
+        if (kdelta(m, fa, n, i, i + (s + t) * d) > dnode) s += t;
+    } while (t > 1);
+    const int split = i + s * d + min(d, 0);
+    const int left = (min(i, j) == split) ? (int)(LEAF_BIT | (uint32_t)split) : split;
+    const int right = (max(i, j) == split + 1) ? (int)(LEAF_BIT | (uint32_t)(split + 1)) : split + 1;
+    child[2 * i] = left;
+    child[2 * i + 1] = right;
+    parent[(left & (int)LEAF_BIT) ? (n - 1) + (left & 0x7FFFFFFF) : left] = i;
+    parent[(right & (int)LEAF_BIT) ? (n - 1) + (right & 0x7FFFFFFF) : right] = i;
+    if (i == 0) parent[0] = -1;
+}
+
+__global__ void k_leaf_init(const uint32_t* __restrict__ sface, const float4* __restrict__ bmin,
+                            const float4* __restrict__ bmax, const float* __restrict__ V, const int* __restrict__ F,
+                            int n, float* aabb, float4* tri, int* cnt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n - 1) cnt[i] = 0;
+    if (i >= n) return;
+    const int f = (int)sface[i];
+    float* b = aabb + 6 * ((size_t)(n - 1) + i);
+    const float4 mn = bmin[f], mx = bmax[f];
+    b[0] = mn.x; b[1] = mn.y; b[2] = mn.z; b[3] = mx.x; b[4] = mx.y; b[5] = mx.z;
+    const V3 a = ld3(V + 3 * F[3 * f]), bb = ld3(V + 3 * F[3 * f + 1]), c = ld3(V + 3 * F[3 * f + 2]);
+    const V3 e1 = bb - a, e2 = c - a;
+    tri[3 * i] = make_float4(a.x, a.y, a.z, __int_as_float(f));
+    tri[3 * i + 1] = make_float4(e1.x, e1.y, e1.z, 0.f);
+    tri[3 * i + 2] = make_float4(e2.x, e2.y, e2.z, 0.f);
+}
+
+__device__ __forceinline__ float aload(const float* p) {
+    return __uint_as_float(__hip_atomic_load((const uint32_t*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+__global__ void k_refit(const int* __restrict__ parent, const int* __restrict__ child, int n, float* aabb,
+                        int* cnt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int node = parent[(n - 1) + i];
+    for (int depth = 0; node >= 0 && depth < 128; ++depth) {
+        __threadfence();
+        if (atomicAdd(&cnt[node], 1) == 0) return;    // the other child is not done yet
+        __threadfence();
+        float box[6];
+        const int c0 = child[2 * node], c1 = child[2 * node + 1];
+        const size_t i0 = (c0 & (int)LEAF_BIT) ? (size_t)(n - 1) + (c0 & 0x7FFFFFFF) : (size_t)c0;
+        const size_t i1 = (c1 & (int)LEAF_BIT) ? (size_t)(n - 1) + (c1 & 0x7FFFFFFF) : (size_t)c1;
+        for (int k = 0; k < 3; ++k) {
+            box[k] = fminf(aload(aabb + 6 * i0 + k), aload(aabb + 6 * i1 + k));
+            box[3 + k] = fmaxf(aload(aabb + 6 * i0 + 3 + k), aload(aabb + 6 * i1 + 3 + k));
+        }
+        for (int k = 0; k < 6; ++k)
+            __hip_atomic_store((uint32_t*)(aabb + 6 * (size_t)node + k), __float_as_uint(box[k]), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        node = parent[node];
+    }
+}
+
+__global__ void k_pack_nodes(const int* __restrict__ child, const float* __restrict__ aabb, int n, float4* nodes) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n - 1) return;
+    const int c0 = child[2 * i], c1 = child[2 * i + 1];
+    const size_t i0 = (c0 & (int)LEAF_BIT) ? (size_t)(n - 1) + (c0 & 0x7FFFFFFF) : (size_t)c0;
+    const size_t i1 = (c1 & (int)LEAF_BIT) ? (size_t)(n - 1) + (c1 & 0x7FFFFFFF) : (size_t)c1;
+    const float* L = aabb + 6 * i0;
+    const float* R = aabb + 6 * i1;
+    nodes[4 * i] = make_float4(L[0], L[1], L[2], R[0]);
+    nodes[4 * i + 1] = make_float4(L[3], L[4], L[5], R[1]);
+    nodes[4 * i + 2] = make_float4(R[3], R[4], R[5], R[2]);
+    nodes[4 * i + 3] = make_float4(__int_as_float(c0), __int_as_float(c1), 0.f, 0.f);
+}
+
+__global__ void k_keys64(const uint32_t* __restrict__ m, const uint32_t* __restrict__ fa, int n, uint64_t* out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = ((uint64_t)m[i] << 32) | fa[i];
+}
+
+__global__ void k_edge_len(const int4* __restrict__ edges, int ne, const float* __restrict__ V, double* w) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ne) return;
+    const int4 E = edges[e];
+    const double dx = (double)V[3 * E.y] - (double)V[3 * E.x];
+    const double dy = (double)V[3 * E.y + 1] - (double)V[3 * E.x + 1];
+    const double dz = (double)V[3 * E.y + 2] - (double)V[3 * E.x + 2];
+    w[e] = sqrt(dx * dx + dy * dy + dz * dz);
+}
+
+__global__ void k_edge_cdf(const double* w, int ne, double* cdf, double* total, float* ftotal) {
+    block_scan_normalise(w, ne, cdf, total);
+    if (threadIdx.x == 0) *ftotal = (float)*total;
+}
+
+// environment map: per-row texel weights (mean rgb times row solid angle) and
+// conditional CDFs, summed serially per row; marginal over rows serially.
+__global__ void k_env_rows(const float* __restrict__ env, int he, int we, const double* __restrict__ dom,
+                           double* cond, double* rows) {
+#pragma clang fp contract(off)
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= he) return;
+    double acc = 0.0;
+    double* C = cond + (size_t)r * (we + 1);
+    C[0] = 0.0;
+    for (int c = 0; c < we; ++c) {
+        const float* t = env + 3 * ((size_t)r * we + c);
+        const double m = ((double)t[0] + (double)t[1] + (double)t[2]) / 3.0;
+        acc += m * dom[r];
+        C[c + 1] = acc;
+    }
+    rows[r] = acc;
+    for (int c = 0; c <= we; ++c) C[c] = acc > 0.0 ? C[c] / acc : (double)c / we;
+}
+
+__global__ void k_env_marg(const double* rows, int he, double* marg, double* total) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double acc = 0.0;
+    marg[0] = 0.0;
+    for (int r = 0; r < he; ++r) { acc += rows[r]; marg[r + 1] = acc; }
+    *total = acc;
+    for (int r = 0; r <= he; ++r) marg[r] = acc > 0.0 ? marg[r] / acc : 0.0;
+}
+
+__global__ void k_env_pdf(const float* __restrict__ env, int he, int we, const double* __restrict__ dom,
+                          const double* __restrict__ total, float* texpdf) {
+#pragma clang fp contract(off)
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= he * we) return;
+    const int r = i / we;
+    const float* t = env + 3 * (size_t)i;
+    const double m = ((double)t[0] + (double)t[1] + (double)t[2]) / 3.0;
+    const double tot = *total;
+    texpdf[i] = tot > 0.0 ? (float)((m * dom[r]) / tot / dom[r]) : 0.0f;
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+static inline unsigned nb(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+void launch_scene_geometry(SceneDev& s, hipStream_t st) {
+    const int nf = s.nf;
+    if (nf <= 0) return;
+    hipLaunchKernelGGL(k_face_prep, dim3(nb(nf, 256)), dim3(256), 0, st, s.V, s.F, nf, s.fnorm, s.bmin, s.bmax,
+                       s.cen);
+    hipLaunchKernelGGL(k_bounds, dim3(1), dim3(1024), 0, st, s.cen, nf, s.bounds);
+    hipLaunchKernelGGL(k_morton, dim3(nb(nf, 256)), dim3(256), 0, st, s.cen, nf, s.bounds, s.mkeys[0], s.mvals[0]);
+    const int nblocks = (nf + RS_TILE - 1) / RS_TILE;
+    int cur = 0;
+    for (int shift = 0; shift < 32; shift += 8) {
+        hipLaunchKernelGGL(k_rs_hist, dim3(nblocks), dim3(RS_THREADS), 0, st, s.mkeys[cur], nf, shift, s.rs_hist,
+                           nblocks);
+        hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, st, s.rs_hist, 256 * nblocks);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(nblocks), dim3(RS_THREADS), 0, st, s.mkeys[cur], s.mvals[cur],
+                           s.mkeys[cur ^ 1], s.mvals[cur ^ 1], nf, shift, s.rs_hist, nblocks);
+        cur ^= 1;
+    }
+    // after 4 passes the sorted data is back in buffer 0
+    const uint32_t* sm = s.mkeys[cur];
+    const uint32_t* sf = s.mvals[cur];
+    hipLaunchKernelGGL(k_keys64, dim3(nb(nf, 256)), dim3(256), 0, st, sm, sf, nf, s.keys64);
+    if (nf > 1)
+        hipLaunchKernelGGL(k_karras, dim3(nb(nf - 1, 256)), dim3(256), 0, st, sm, sf, nf, s.child, s.parent);
+    hipLaunchKernelGGL(k_leaf_init, dim3(nb(nf, 256)), dim3(256), 0, st, sf, s.bmin, s.bmax, s.V, s.F, nf, s.aabb,
+                       s.tri, s.refit_cnt);
+    if (nf > 1) {
+        hipLaunchKernelGGL(k_refit, dim3(nb(nf, 256)), dim3(256), 0, st, s.parent, s.child, nf, s.aabb,
+                           s.refit_cnt);
+        hipLaunchKernelGGL(k_pack_nodes, dim3(nb(nf - 1, 256)), dim3(256), 0, st, s.child, s.aabb, nf, s.nodes);
+    }
+    if (s.ne > 0) {
+        hipLaunchKernelGGL(k_edge_len, dim3(nb(s.ne, 256)), dim3(256), 0, st, s.edges, s.ne, s.V, s.edge_w);
+        hipLaunchKernelGGL(k_edge_cdf, dim3(1), dim3(1024), 0, st, s.edge_w, s.ne, s.ecdf, s.etotal_d,
+                           s.etotal_f);
+    }
+}
+
+void launch_env_build(SceneDev& s, hipStream_t st) {
+    if (s.he <= 0) return;
+    hipLaunchKernelGGL(k_env_rows, dim3(nb(s.he, 64)), dim3(64), 0, st, s.env, s.he, s.we, s.row_dom, s.cond,
+                       s.env_rows);
+    hipLaunchKernelGGL(k_env_marg, dim3(1), dim3(64), 0, st, s.env_rows, s.he, s.marg, s.env_total);
+    hipLaunchKernelGGL(k_env_pdf, dim3(nb((long long)s.he * s.we, 256)), dim3(256), 0, st, s.env, s.he, s.we,
+                       s.row_dom, s.env_total, s.texpdf);
+}
+
+} // namespace st

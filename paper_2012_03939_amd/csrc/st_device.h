@@ -1,0 +1,596 @@
+// Device-side building blocks of the gfx950 path tracer: vector math, Philox
+// streams, decision hash, BVH traversal with LDS-staged stacks, the
+// Torrance-Sparrow BRDF (evaluation, sampling, pdf and reverse-mode
+// derivative), environment-map sampling, and the path estimator used by the
+// adjoint replay and by the edge side paths.
+//
+// Method: Shape from Tracing, Sec. 3.2 (a differentiable physically based path
+// tracer R(x, c_i) with gradients of pixels w.r.t. geometry) and Sec. 3.3
+// (per-facet Torrance-Sparrow materials; global illumination).  The estimator is
+// fixed by the library's stream and shading specification: point lights are
+// all sampled at every vertex, one environment sample per vertex is combined
+// with BRDF sampling by the balance heuristic, the BRDF is a Lambertian term
+// plus a Beckmann / Smith microfacet lobe scaled by the specular colour.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace st {
+
+constexpr float PI_F = 3.14159265358979323846f;
+constexpr float INV_PI_F = 0.318309886183790671538f;
+constexpr float INV_SQRT_PI_F = 0.564189583547756286948f;
+constexpr float TMIN = 1e-4f;
+constexpr float SHADOW_SHRINK = 1e-4f;
+constexpr float ALPHA_MIN = 1e-3f;
+constexpr float LOBE_SPEC_P = 0.5f;
+constexpr double EPS_PRIMARY = 1e-3;    // pixels
+constexpr float EPS_SECONDARY = 1e-4f;  // radians
+constexpr double ZNEAR = 1e-3;
+constexpr float BOX_GROW = 1.0000004f;  // 1 + 2*gamma(3): conservative slab exit distance
+constexpr int LDS_STACK = 32;           // per-lane traversal stack entries held in LDS
+constexpr int SPILL_STACK = 32;         // further entries spilled to HBM
+constexpr uint32_t LEAF_BIT = 0x80000000u;
+constexpr int MAX_LIGHTS = 16;
+
+// error word bits (device -> host)
+constexpr uint32_t ERR_STACK = 1u;
+constexpr uint32_t ERR_NAN = 2u;
+constexpr uint32_t ERR_QUEUE = 4u;
+constexpr uint32_t ERR_LOOP = 8u;
+constexpr int TRAVERSAL_CAP = 1 << 22;   // node visits per ray before the traversal gives up
+
+// ---------------------------------------------------------------------------
+struct V3 { float x, y, z; };
+__device__ __forceinline__ V3 mk(float x, float y, float z) { return V3{x, y, z}; }
+__device__ __forceinline__ V3 operator+(V3 a, V3 b) { return V3{a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ V3 operator-(V3 a, V3 b) { return V3{a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ V3 operator-(V3 a) { return V3{-a.x, -a.y, -a.z}; }
+__device__ __forceinline__ V3 operator*(V3 a, float s) { return V3{a.x * s, a.y * s, a.z * s}; }
+__device__ __forceinline__ V3 mul(V3 a, V3 b) { return V3{a.x * b.x, a.y * b.y, a.z * b.z}; }
+__device__ __forceinline__ float dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ V3 cross(V3 a, V3 b) {
+    return V3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ float len(V3 a) { return sqrtf(dot(a, a)); }
+__device__ __forceinline__ V3 normalize(V3 a) { return a * (1.0f / len(a)); }
+__device__ __forceinline__ float hsum(V3 a) { return a.x + a.y + a.z; }
+__device__ __forceinline__ V3 ld3(const float* p) { return V3{p[0], p[1], p[2]}; }
+__device__ __forceinline__ V3 xyz(float4 a) { return V3{a.x, a.y, a.z}; }
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                        uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+__device__ __forceinline__ float unif(uint32_t r) { return (float)(r >> 8) * (1.0f / 16777216.0f); }
+
+struct Ctr { uint32_t c0, c1, c2hi, c3; };
+struct Key { uint32_t k0, k1; };
+
+__device__ __forceinline__ float4 draw4(const Ctr& c, uint32_t bounce, uint32_t block, const Key& k) {
+    uint4 r = philox(c.c0, c.c1, c.c2hi | (bounce << 8) | block, c.c3, k.k0, k.k1);
+    return make_float4(unif(r.x), unif(r.y), unif(r.z), unif(r.w));
+}
+
+// FNV-1a over the little-endian bytes of 32-bit decision words
+struct Hash {
+    uint32_t h;
+    bool on;
+    __device__ void push(uint32_t w) {
+        if (!on) return;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) { h ^= (w >> (8 * b)) & 0xFFu; h *= 0x01000193u; }
+    }
+};
+constexpr uint32_t FNV_INIT = 0x811C9DC5u;
+
+// ---------------------------------------------------------------------------
+// scene as the kernels see it
+// ---------------------------------------------------------------------------
+struct DevScene {
+    const float* V;       // [nv,3]
+    const int* F;         // [nf,3]
+    const float* mat;     // [nf,7]
+    const float* lights;  // [nl,6]
+    const float4* fnorm;  // [nf] unit geometric normal
+    const float4* tri;    // [nf*3] leaf-ordered (v0, face bits) (e1) (e2)
+    const float4* nodes;  // [(nf-1)*4] two child boxes + child codes
+    const float* env;     // [he,we,3]
+    const double* marg;   // [he+1]
+    const double* cond;   // [he,we+1]
+    const float* texpdf;  // [he*we] solid-angle pdf of each texel
+    const float* rowcos;  // [he+1] cos(pi r / he)
+    const int4* edges;    // [ne] (va, vb, f1, f2)
+    const double* ecdf;   // [ne+1] cumulative 3-D length / total
+    const float* etotal;  // total 3-D edge length
+    int nv, nf, nl, he, we, ne, has_env;
+    uint32_t scene_id;
+};
+
+// per-lane traversal stack: LDS_STACK entries in LDS (lane-interleaved), the
+// rest in a per-thread HBM spill region
+struct TravStack {
+    uint32_t* lds;     // base of this block's LDS stack area; entry i of lane t at lds[i*bs + t]
+    uint32_t* spill;   // spill base; entry i of thread g at spill[i*gstride + g]
+    uint32_t bs, tid, gstride, gid;
+    uint32_t* err;
+    __device__ __forceinline__ void put(int i, uint32_t v) {
+        if (i < LDS_STACK) lds[i * bs + tid] = v;
+        else spill[(i - LDS_STACK) * gstride + gid] = v;
+    }
+    __device__ __forceinline__ uint32_t get(int i) const {
+        return i < LDS_STACK ? lds[i * bs + tid] : spill[(i - LDS_STACK) * gstride + gid];
+    }
+};
+
+// Moller-Trumbore, two-sided, on the leaf-ordered triangle record
+__device__ __forceinline__ bool tri_test(const float4* tri, uint32_t leaf, V3 o, V3 d, float tmin, float tmax,
+                                         float& t, int& face) {
+    const float4 a = tri[3 * leaf], b = tri[3 * leaf + 1], c = tri[3 * leaf + 2];
+    const V3 e1 = xyz(b), e2 = xyz(c);
+    const V3 p = cross(d, e2);
+    const float det = dot(e1, p);
+    if (det == 0.0f) return false;
+    const float inv = 1.0f / det;
+    const V3 s = o - xyz(a);
+    const float b1 = dot(s, p) * inv;
+    if (b1 < 0.0f || b1 > 1.0f) return false;
+    const V3 q = cross(s, e1);
+    const float b2 = dot(d, q) * inv;
+    if (b2 < 0.0f || b1 + b2 > 1.0f) return false;
+    t = dot(e2, q) * inv;
+    face = __float_as_int(a.w);
+    return t > tmin && t < tmax;
+}
+
+__device__ __forceinline__ V3 safe_inv(V3 d) {
+    auto f = [](float v) { return 1.0f / (fabsf(v) > 1e-30f ? v : copysignf(1e-30f, v)); };
+    return V3{f(d.x), f(d.y), f(d.z)};
+}
+
+// slab test of both children of one node; returns entry distances
+__device__ __forceinline__ void node_test(const float4* nodes, uint32_t node, V3 o, V3 inv, float tmin, float tmax,
+                                          bool& hl, bool& hr, float& tl, float& tr, uint32_t& cl, uint32_t& cr) {
+    const float4 n0 = nodes[4 * node], n1 = nodes[4 * node + 1], n2 = nodes[4 * node + 2],
+                 n3 = nodes[4 * node + 3];
+    // left box (n0.xyz, n1.xyz), right box (n0.w, n1.w, n2.w) - (n2.xyz)
+    {
+        float ax = (n0.x - o.x) * inv.x, bx = (n1.x - o.x) * inv.x;
+        float ay = (n0.y - o.y) * inv.y, by = (n1.y - o.y) * inv.y;
+        float az = (n0.z - o.z) * inv.z, bz = (n1.z - o.z) * inv.z;
+        float t0 = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), tmin));
+        float t1 = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), tmax)) * BOX_GROW;
+        hl = t0 <= t1;
+        tl = t0;
+    }
+    {
+        float ax = (n0.w - o.x) * inv.x, bx = (n2.x - o.x) * inv.x;
+        float ay = (n1.w - o.y) * inv.y, by = (n2.y - o.y) * inv.y;
+        float az = (n2.w - o.z) * inv.z, bz = (n2.z - o.z) * inv.z;
+        float t0 = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), tmin));
+        float t1 = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), tmax)) * BOX_GROW;
+        hr = t0 <= t1;
+        tr = t0;
+    }
+    cl = __float_as_uint(n3.x);
+    cr = __float_as_uint(n3.y);
+}
+
+// closest hit with t in (tmin, inf) excluding one face; ties go to the smaller face id
+__device__ int trace_closest(const DevScene& S, V3 o, V3 d, float tmin, int exclude, float& thit, TravStack& st) {
+    float tbest = __int_as_float(0x7f800000);
+    int best = -1;
+    if (S.nf <= 0) return -1;
+    auto leaf = [&](uint32_t l) {
+        float t; int f;
+        if (tri_test(S.tri, l, o, d, tmin, __int_as_float(0x7f800000), t, f) && f != exclude) {
+            if (t < tbest || (t == tbest && f < best)) { tbest = t; best = f; }
+        }
+    };
+    if (S.nf == 1) { leaf(0); thit = tbest; return best; }
+    const V3 inv = safe_inv(d);
+    uint32_t node = 0;
+    int sp = 0;
+    for (int iter = 0;; ++iter) {
+        if (iter >= TRAVERSAL_CAP) { atomicOr(st.err, ERR_LOOP); break; }
+        bool hl, hr; float tl, tr; uint32_t cl, cr;
+        node_test(S.nodes, node, o, inv, tmin, tbest, hl, hr, tl, tr, cl, cr);
+        if (hl && (cl & LEAF_BIT)) { leaf(cl & ~LEAF_BIT); hl = false; }
+        if (hr && (cr & LEAF_BIT)) { leaf(cr & ~LEAF_BIT); hr = false; }
+        if (hl && hr) {
+            uint32_t nearc = tl <= tr ? cl : cr, farc = tl <= tr ? cr : cl;
+            if (sp >= LDS_STACK + SPILL_STACK) { atomicOr(st.err, ERR_STACK); break; }
+            st.put(sp++, farc);
+            node = nearc;
+        } else if (hl) {
+            node = cl;
+        } else if (hr) {
+            node = cr;
+        } else {
+            if (sp == 0) break;
+            node = st.get(--sp);
+        }
+    }
+    thit = tbest;
+    return best;
+}
+
+__device__ bool trace_any(const DevScene& S, V3 o, V3 d, float tmin, float tmax, int exclude, TravStack& st) {
+    if (S.nf <= 0) return false;
+    auto leaf = [&](uint32_t l) -> bool {
+        float t; int f;
+        return tri_test(S.tri, l, o, d, tmin, tmax, t, f) && f != exclude;
+    };
+    if (S.nf == 1) return leaf(0);
+    const V3 inv = safe_inv(d);
+    uint32_t node = 0;
+    int sp = 0;
+    for (int iter = 0;; ++iter) {
+        if (iter >= TRAVERSAL_CAP) { atomicOr(st.err, ERR_LOOP); return false; }
+        bool hl, hr; float tl, tr; uint32_t cl, cr;
+        node_test(S.nodes, node, o, inv, tmin, tmax, hl, hr, tl, tr, cl, cr);
+        if (hl && (cl & LEAF_BIT)) { if (leaf(cl & ~LEAF_BIT)) return true; hl = false; }
+        if (hr && (cr & LEAF_BIT)) { if (leaf(cr & ~LEAF_BIT)) return true; hr = false; }
+        if (hl && hr) {
+            if (sp >= LDS_STACK + SPILL_STACK) { atomicOr(st.err, ERR_STACK); return false; }
+            st.put(sp++, tl <= tr ? cr : cl);
+            node = tl <= tr ? cl : cr;
+        } else if (hl) {
+            node = cl;
+        } else if (hr) {
+            node = cr;
+        } else {
+            if (sp == 0) return false;
+            node = st.get(--sp);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Torrance-Sparrow BRDF: kd/pi + ks * D * G / (4 cos_i cos_o), Beckmann D,
+// height-correlated Smith G of the Beckmann surface.
+// ---------------------------------------------------------------------------
+struct Mat { V3 kd, ks; float a; };
+__device__ __forceinline__ Mat load_mat(const float* m) {
+    Mat r;
+    r.kd = V3{m[0], m[1], m[2]};
+    r.ks = V3{m[3], m[4], m[5]};
+    r.a = m[6];
+    return r;
+}
+__device__ __forceinline__ float alpha_eff(float a) { return a > ALPHA_MIN ? a : ALPHA_MIN; }
+
+__device__ __forceinline__ float beckmann_D(float ch, float a) {
+    const float c2 = ch * ch;
+    const float t2 = (1.0f - c2) / c2;
+    return expf(-t2 / (a * a)) / (PI_F * a * a * c2 * c2);
+}
+
+__device__ __forceinline__ float smith_lambda(float c, float a) {
+    if (c >= 1.0f) return 0.0f;
+    const float s = sqrtf(1.0f - c * c);
+    const float x = c / (a * s);
+    return (expf(-x * x) * INV_SQRT_PI_F / x - erfcf(x)) * 0.5f;
+}
+
+__device__ __forceinline__ V3 brdf_eval(V3 wi, V3 wo, V3 n, const Mat& m) {
+    const float ci = dot(n, wi), co = dot(n, wo);
+    if (!(ci > 0.0f) || !(co > 0.0f)) return V3{0.f, 0.f, 0.f};
+    const float a = alpha_eff(m.a);
+    const V3 h = normalize(wi + wo);
+    const float ch = dot(n, h);
+    float spec = 0.0f;
+    if (ch > 0.0f) {
+        const float D = beckmann_D(ch, a);
+        const float G = 1.0f / (1.0f + smith_lambda(ci, a) + smith_lambda(co, a));
+        spec = D * G / (4.0f * ci * co);
+    }
+    return m.kd * INV_PI_F + m.ks * spec;
+}
+
+__device__ __forceinline__ float bsdf_pdf(V3 wi, V3 wo, V3 n, float alpha) {
+    const float ci = dot(n, wi);
+    if (!(ci > 0.0f)) return 0.0f;
+    const float a = alpha_eff(alpha);
+    const float pd = (1.0f - LOBE_SPEC_P) * ci * INV_PI_F;
+    const V3 hv = wi + wo;
+    const float hl = len(hv);
+    float ps = 0.0f;
+    if (hl > 0.0f) {
+        const V3 h = hv * (1.0f / hl);
+        const float ch = dot(n, h), oh = fabsf(dot(wo, h));
+        if (ch > 0.0f && oh > 0.0f) ps = LOBE_SPEC_P * beckmann_D(ch, a) * ch / (4.0f * oh);
+    }
+    return pd + ps;
+}
+
+// orthonormal basis around n (Duff et al. 2017, branchless)
+__device__ __forceinline__ void onb(V3 n, V3& t, V3& b) {
+    const float sg = copysignf(1.0f, n.z);
+    const float a = -1.0f / (sg + n.z);
+    const float bb = n.x * n.y * a;
+    t = V3{1.0f + sg * n.x * n.x * a, sg * bb, -sg * n.x};
+    b = V3{bb, sg + n.y * n.y * a, -n.y};
+}
+
+__device__ __forceinline__ int bsdf_sample(float4 u, V3 wo, V3 n, float alpha, V3& wi) {
+    V3 t, b;
+    onb(n, t, b);
+    const float a = alpha_eff(alpha);
+    const float phi = 2.0f * PI_F * u.z;
+    float sp, cp;
+    sincosf(phi, &sp, &cp);
+    if (u.x < LOBE_SPEC_P) {
+        const float t2 = -a * a * logf(1.0f - u.y);
+        const float ch = 1.0f / sqrtf(1.0f + t2);
+        const float sh = sqrtf(fmaxf(0.0f, 1.0f - ch * ch));
+        const V3 h = t * (sh * cp) + b * (sh * sp) + n * ch;
+        wi = h * (2.0f * dot(wo, h)) - wo;
+        return 0;
+    }
+    const float r = sqrtf(u.y);
+    const float z = sqrtf(fmaxf(0.0f, 1.0f - u.y));
+    wi = t * (r * cp) + b * (r * sp) + n * z;
+    return 1;
+}
+
+// Reverse-mode derivative of f(wi, wo, n, m) contracted with gf (rgb):
+// accumulates into gn, gwi (only needed when wi depends on the geometry) and gm[7].
+__device__ __forceinline__ float dlambda_dc(float c, float a, float& dla) {
+    // Lambda(x), x = c / (a sqrt(1-c^2)); dLambda/dx = -exp(-x^2) / (2 sqrt(pi) x^2)
+    dla = 0.0f;
+    if (c >= 1.0f) return 0.0f;
+    const float s = sqrtf(1.0f - c * c);
+    const float x = c / (a * s);
+    if (x > 12.0f) return 0.0f;
+    const float dldx = -expf(-x * x) * (0.5f * INV_SQRT_PI_F) / (x * x);
+    dla = dldx * (-x / a);
+    return dldx / (a * s * s * s);
+}
+
+__device__ __forceinline__ void brdf_backward(V3 wi, V3 wo, V3 n, const Mat& m, V3 gf, V3& gn, V3& gwi,
+                                              float* gm) {
+    const float ci = dot(n, wi), co = dot(n, wo);
+    if (!(ci > 0.0f) || !(co > 0.0f)) return;
+    gm[0] += gf.x * INV_PI_F; gm[1] += gf.y * INV_PI_F; gm[2] += gf.z * INV_PI_F;
+    const float a = alpha_eff(m.a);
+    const V3 hv = wi + wo;
+    const float hl = len(hv);
+    const V3 h = hv * (1.0f / hl);
+    const float ch = dot(n, h);
+    if (!(ch > 0.0f)) return;
+    const float D = beckmann_D(ch, a);
+    const float li = smith_lambda(ci, a), lo = smith_lambda(co, a);
+    const float G = 1.0f / (1.0f + li + lo);
+    const float K = D * G / (4.0f * ci * co);
+    gm[3] += gf.x * K; gm[4] += gf.y * K; gm[5] += gf.z * K;
+    const float glnK = dot(gf, m.ks) * K;       // gradient w.r.t. ln K
+    const float c2 = ch * ch;
+    const float dlnD_dch = 2.0f / (c2 * ch * a * a) - 4.0f / ch;
+    const float dlnD_da = 2.0f * (1.0f - c2) / (c2 * a * a * a) - 2.0f / a;
+    float dlia, dloa;
+    const float dli = dlambda_dc(ci, a, dlia), dlo = dlambda_dc(co, a, dloa);
+    if (m.a > ALPHA_MIN) gm[6] += glnK * (dlnD_da - G * (dlia + dloa));
+    const float gci = glnK * (-G * dli - 1.0f / ci);
+    const float gco = glnK * (-G * dlo - 1.0f / co);
+    const float gch = glnK * dlnD_dch;
+    gn = gn + wi * gci + wo * gco + h * gch;
+    // through h = normalize(wi + wo) (wo is fixed)
+    const V3 gh = n * gch;
+    const V3 ghv = (gh - h * dot(h, gh)) * (1.0f / hl);
+    gwi = gwi + n * gci + ghv;
+}
+
+// ---------------------------------------------------------------------------
+// environment map: equirectangular, +y up, row 0 at theta = 0
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int cdf_find(const double* C, int n, double u) {
+    // largest i in [0, n-1] with C[i] <= u (C[0] == 0 <= u)
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (C[mid] <= u) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int env_texel_of(const DevScene& S, V3 d) {
+    const float y = fminf(1.0f, fmaxf(-1.0f, d.y));
+    const float th = acosf(y);
+    float ph = atan2f(d.x, d.z);
+    if (ph < 0.0f) ph += 2.0f * PI_F;
+    const int r = min((int)(th * (1.0f / PI_F) * S.he), S.he - 1);
+    const int c = min((int)(ph * (0.5f / PI_F) * S.we), S.we - 1);
+    return r * S.we + c;
+}
+__device__ __forceinline__ V3 env_rgb(const DevScene& S, int t) { return ld3(S.env + 3 * (size_t)t); }
+
+__device__ __forceinline__ int env_sample(const DevScene& S, float4 u, V3& dir, float& pdf) {
+    const int r = cdf_find(S.marg, S.he, (double)u.x);
+    const int c = cdf_find(S.cond + (size_t)r * (S.we + 1), S.we, (double)u.y);
+    const float phi = 2.0f * PI_F * ((float)c + u.z) / (float)S.we;
+    const float ct = S.rowcos[r], cb = S.rowcos[r + 1];
+    const float cth = ct - u.w * (ct - cb);
+    const float sth = sqrtf(fmaxf(0.0f, 1.0f - cth * cth));
+    float sp, cp;
+    sincosf(phi, &sp, &cp);
+    dir = V3{sth * sp, cth, sth * cp};
+    const int t = r * S.we + c;
+    pdf = S.texpdf[t];
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// camera (precomputed basis; r and u already scaled by tan(fov/2) and aspect)
+// ---------------------------------------------------------------------------
+struct DevCam {
+    float eye[3], f[3], rs[3], us[3];
+    double deye[3], df[3], dr[3], du[3], dth, daspect;
+    int W, H, scene, pad;
+    long long qoff;      // processing-order path offset
+    long long pixoff;    // canonical pixel offset
+    long long eoff;      // primary edge sample offset
+    long long ne;        // primary edge samples of this view
+};
+
+__device__ __forceinline__ V3 cam_dir(const DevCam& c, float sx, float sy) {
+    const float nx = 2.0f * sx / (float)c.W - 1.0f, ny = 1.0f - 2.0f * sy / (float)c.H;
+    const V3 d = ld3(c.f) + ld3(c.rs) * nx + ld3(c.us) * ny;
+    return normalize(d);
+}
+
+// ---------------------------------------------------------------------------
+// the path estimator (forward radiance only): used for the edge side paths and
+// the single-kernel forward.  first_escape_full: a first-segment miss returns
+// the environment radiance (secondary side rays) instead of black (camera).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void push_face(Hash& h, int f) { h.push(f < 0 ? 0xFFFFFFFFu : (uint32_t)f); }
+
+__device__ V3 trace_estimator(const DevScene& S, V3 o, V3 d, int exclude, int nvert, bool first_escape_full,
+                              const Ctr& ctr, const Key& key, Hash& hash, TravStack& st) {
+    V3 L{0.f, 0.f, 0.f}, beta{1.f, 1.f, 1.f};
+    float p_prev = 0.0f;
+    for (int k = 1; k <= nvert + 1; ++k) {
+        float t;
+        const int f = trace_closest(S, o, d, TMIN, exclude, t, st);
+        push_face(hash, f);
+        if (f < 0) {
+            if (S.has_env && (k > 1 || first_escape_full)) {
+                const int tex = env_texel_of(S, d);
+                hash.push((uint32_t)tex);
+                const V3 Le = env_rgb(S, tex);
+                float w = 1.0f;
+                if (k > 1) { const float pe = S.texpdf[tex]; w = p_prev / (p_prev + pe); }
+                L = L + mul(beta, Le) * w;
+            }
+            break;
+        }
+        if (k == nvert + 1) break;
+        const V3 x = o + d * t;
+        V3 n = xyz(S.fnorm[f]);
+        const V3 wo = -d;
+        if (dot(n, wo) < 0.0f) n = -n;
+        const Mat m = load_mat(S.mat + 7 * (size_t)f);
+        for (int l = 0; l < S.nl; ++l) {
+            const float* lt = S.lights + 6 * l;
+            const V3 dl = ld3(lt) - x;
+            const float r2 = dot(dl, dl);
+            uint32_t code = 0;
+            if (r2 > 0.0f) {
+                const float r = sqrtf(r2);
+                const V3 wl = dl * (1.0f / r);
+                const float c = dot(n, wl);
+                if (c > 0.0f) {
+                    const bool occ = trace_any(S, x, wl, TMIN, r * (1.0f - SHADOW_SHRINK), f, st);
+                    code = occ ? 1u : 2u;
+                    if (!occ) L = L + mul(beta, mul(ld3(lt + 3), brdf_eval(wl, wo, n, m))) * (c / r2);
+                }
+            }
+            hash.push(code);
+        }
+        if (S.has_env) {
+            const float4 u = draw4(ctr, k, 1, key);
+            V3 we; float pe;
+            const int tex = env_sample(S, u, we, pe);
+            hash.push((uint32_t)tex);
+            const float c = dot(n, we);
+            uint32_t code = 0;
+            if (c > 0.0f && pe > 0.0f) {
+                const bool occ = trace_any(S, x, we, TMIN, __int_as_float(0x7f800000), f, st);
+                code = occ ? 1u : 2u;
+                if (!occ) {
+                    const V3 fv = brdf_eval(we, wo, n, m);
+                    const float den = pe + bsdf_pdf(we, wo, n, m.a);
+                    L = L + mul(beta, mul(env_rgb(S, tex), fv)) * (c / den);
+                }
+            }
+            hash.push(code);
+        }
+        if (!(k < nvert || S.has_env)) break;
+        const float4 u = draw4(ctr, k, 2, key);
+        V3 wi;
+        const int lobe = bsdf_sample(u, wo, n, m.a, wi);
+        const float ci = dot(n, wi);
+        const float pb = bsdf_pdf(wi, wo, n, m.a);
+        hash.push((uint32_t)lobe);
+        if (!(ci > 0.0f) || !(pb > 0.0f)) { hash.push(0u); break; }
+        hash.push(1u);
+        beta = mul(beta, brdf_eval(wi, wo, n, m)) * (ci / pb);
+        p_prev = pb;
+        o = x; d = wi; exclude = f;
+    }
+    return L;
+}
+
+// processing order of path samples inside one view: sample-major, then 8x8
+// pixel tiles (when the view is a multiple of 8 in both axes), then row-major
+__device__ __forceinline__ void decode_path(const DevCam& c, long long local, int spp, int& x, int& y, int& j) {
+    const long long hw = (long long)c.W * c.H;
+    j = (int)(local / hw);
+    const int p = (int)(local - (long long)j * hw);
+    if ((c.W & 7) == 0 && (c.H & 7) == 0) {
+        const int tile = p >> 6, within = p & 63, tw = c.W >> 3;
+        x = (tile % tw) * 8 + (within & 7);
+        y = (tile / tw) * 8 + (within >> 3);
+    } else {
+        x = p % c.W;
+        y = p / c.W;
+    }
+    (void)spp;
+}
+
+__device__ __forceinline__ int find_view(const long long* off, int ncam, long long q) {
+    // largest v with off[v] <= q
+    int lo = 0, hi = ncam - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= q) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------
+// prefix sums in double inside one block of 1024 threads (contiguous chunks per
+// thread, then a serial scan of the 1024 partial sums): out[0] = 0,
+// out[i+1] = out[i] + w[i], then optionally normalised by the total.
+// ---------------------------------------------------------------------------
+__device__ inline void block_scan_normalise(const double* w, int n, double* out, double* total_out) {
+    __shared__ double part[1024];
+    __shared__ double total_s;
+    const int t = threadIdx.x;
+    const int per = (n + 1023) / 1024;
+    const int b = t * per, e = min(n, b + per);
+    double s = 0.0;
+    for (int i = b; i < e; ++i) s += w[i];
+    part[t] = s;
+    __syncthreads();
+    if (t == 0) {
+        double acc = 0.0;
+        for (int i = 0; i < 1024; ++i) { const double v = part[i]; part[i] = acc; acc += v; }
+        total_s = acc;
+        *total_out = acc;
+    }
+    __syncthreads();
+    const double tot = total_s;
+    double acc = part[t];
+    if (t == 0) out[0] = 0.0;
+    for (int i = b; i < e; ++i) {
+        acc += w[i];
+        out[i + 1] = tot > 0.0 ? acc / tot : 0.0;
+    }
+}
+
+
+} // namespace st

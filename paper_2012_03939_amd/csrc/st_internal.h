@@ -1,0 +1,131 @@
+// Internal declarations shared by the HIP translation units of the library.
+#pragma once
+
+#include "st_device.h"
+
+namespace st {
+
+// every device allocation of one scene (library-owned)
+struct SceneDev {
+    int nv = 0, nf = 0, nl = 0, he = 0, we = 0, ne = 0;
+    uint32_t scene_id = 0;
+    bool has_env = false;
+    float* V = nullptr;
+    int* F = nullptr;
+    float* mat = nullptr;
+    float* lights = nullptr;
+    float* env = nullptr;
+    // geometry build
+    float4 *fnorm = nullptr, *bmin = nullptr, *bmax = nullptr, *cen = nullptr;
+    float* bounds = nullptr;                 // lo[3], hi[3], scale[3]
+    uint32_t* mkeys[2] = {nullptr, nullptr};
+    uint32_t* mvals[2] = {nullptr, nullptr};
+    uint32_t* rs_hist = nullptr;
+    uint64_t* keys64 = nullptr;
+    int* child = nullptr;                    // [2*(nf-1)]
+    int* parent = nullptr;                   // [2*nf-1]
+    float* aabb = nullptr;                   // [(2*nf-1)*6]
+    int* refit_cnt = nullptr;
+    float4* nodes = nullptr;                 // [(nf-1)*4]
+    float4* tri = nullptr;                   // [nf*3]
+    // edges (topology fixed at creation)
+    int4* edges = nullptr;
+    double* edge_w = nullptr;
+    double* ecdf = nullptr;
+    double* etotal_d = nullptr;
+    float* etotal_f = nullptr;
+    // environment map
+    double* row_dom = nullptr;               // [he] row solid angles
+    float* rowcos = nullptr;                 // [he+1]
+    double* cond = nullptr;
+    double* marg = nullptr;
+    double* env_rows = nullptr;
+    double* env_total = nullptr;
+    float* texpdf = nullptr;
+    uint32_t* err = nullptr;                 // device error word
+    DevScene* dscene = nullptr;              // device copy of the kernel view
+    DevScene hscene;                         // host copy of the kernel view
+};
+
+// per-render workspace (grow-only)
+struct Workspace {
+    size_t bytes = 0;
+    void* base = nullptr;
+};
+
+// queue and path-state arrays of one wavefront chunk (SoA)
+struct Queues {
+    float* ray[2][9];        // ox oy oz dx dy dz | slot excl (int bits) | pprev
+    uint32_t* pq;            // path: processing index q
+    uint32_t* pc0;           // path: Philox c0 (pixel index)
+    uint32_t* pc1;           // path: Philox c1 (view << 16 | sample)
+    float* pbeta[3];
+    uint32_t* phash;
+    float* ht;               // hit t
+    int* hf;                 // hit face
+    float* sx[3];            // shade record: hit point
+    int* sface;              // shade record: face, -1 when no vertex
+    uint32_t* sinfo;         // shade record: bit0 sampled, bit1 lobe, bit2 continued
+    int* stex;               // shade record: env texel sampled
+    float* sh[7];            // shadow entries [entry][i]: dir xyz, tmax, contrib rgb
+    int* cnt;                // ray counts per bounce
+    uint32_t* spill;         // traversal stack spill
+    float* L;                // per path sample radiance [total, 3] (processing order)
+    int cap;                 // chunk capacity in paths
+    int nent;                // shadow entries per shading point (nl + env)
+};
+
+struct FwdParams {
+    const DevScene* scenes;
+    const DevCam* cams;
+    const long long* qoff;   // [ncam+1]
+    int ncam, spp, B;
+    uint32_t seed;
+    uint32_t* dbg_hash;      // canonical order, optional
+    uint32_t* err;
+};
+
+void launch_scene_geometry(SceneDev& s, hipStream_t st);
+void launch_env_build(SceneDev& s, hipStream_t st);
+
+void launch_forward_wavefront(const FwdParams& p, Queues& q, long long total, int has_env_any, int nent,
+                              hipStream_t st);
+void launch_forward_mega(const FwdParams& p, float* L, long long total, uint32_t* spill, int grid, hipStream_t st);
+void launch_film(const DevCam* cams, const long long* pixoff, int ncam, int spp, const float* L,
+                 long long npix, float* out, hipStream_t st);
+void launch_sample_radiance(const FwdParams& p, const float* L, long long total, float* out, hipStream_t st);
+
+struct BwdParams {
+    const DevScene* scenes;
+    const DevCam* cams;
+    const long long* qoff;   // [ncam+1] path offsets (processing order)
+    const long long* eoff;   // [ncam+1] primary edge sample offsets
+    int ncam, spp, B;
+    uint32_t seed;
+    uint32_t flags;
+    const float* d_image;
+    const uint8_t* path_mask;
+    const uint8_t* edge_mask;
+    float* dV;
+    float* dmat;
+    uint32_t* dbg_hash;
+    uint32_t* dbg_edge_hash;
+    uint32_t* err;
+    uint32_t* spill;
+    double* pcdf;            // per-view primary edge CDF [ncam, ne+1]
+    double* pw;              // per-view primary edge weights [ncam, ne]
+    double* ptotal;          // [ncam]
+    int ne;
+};
+
+void launch_backward(const BwdParams& p, long long total_paths, long long total_edges, int grid, hipStream_t st);
+void launch_fill_f32(float* p, long long n, float v, hipStream_t st);
+void launch_fill_u32(uint32_t* p, long long n, uint32_t v, hipStream_t st);
+void launch_trace_debug(const DevScene* s, const float* o, const float* d, int n, float tmin, int brute,
+                        int* out_face, float* out_t, uint32_t* spill, uint32_t* err, hipStream_t st);
+
+constexpr int TRACE_BLOCK = 256;
+// largest grid of the traversal kernels; the spill stack has one column per thread of it
+constexpr unsigned TRACE_GRID = 4096;
+
+} // namespace st

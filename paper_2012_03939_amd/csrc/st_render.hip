@@ -1,0 +1,410 @@
+// Forward rendering R(x, m, c_i) (Shape from Tracing, Sec. 3.2) as a wavefront
+// path tracer: per bounce a closest-hit kernel over a compacted ray queue, a
+// shading kernel (next-event estimation set-up, BRDF sampling, wave-ballot
+// compaction of the surviving paths) and a per-path shadow kernel that traces
+// the point-light and environment shadow rays and adds their contributions in a
+// fixed order.  Queues are structure-of-arrays in HBM; per-sample radiance is
+// kept for a final film pass that averages the samples of each pixel.
+#include "st_internal.h"
+
+namespace st {
+
+__device__ __forceinline__ TravStack make_stack(uint32_t* lds, uint32_t* spill, uint32_t* err) {
+    TravStack s;
+    s.lds = lds;
+    s.spill = spill;
+    s.bs = blockDim.x;
+    s.tid = threadIdx.x;
+    s.gstride = gridDim.x * blockDim.x;
+    s.gid = blockIdx.x * blockDim.x + threadIdx.x;
+    s.err = err;
+    return s;
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt64() {
+    const uint32_t lane = __lane_id();
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// canonical path index of a (view, pixel, sample)
+__device__ __forceinline__ long long canon(const DevCam& c, int x, int y, int j, int spp) {
+    return (c.pixoff + (long long)y * c.W + x) * spp + j;
+}
+
+// ---------------------------------------------------------------------------
+__global__ void k_camera(FwdParams p, Queues q, long long q0, int n) {
+    const int stride = gridDim.x * blockDim.x;
+    if (blockIdx.x == 0 && threadIdx.x < 16) q.cnt[threadIdx.x] = threadIdx.x == 1 ? n : 0;
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += stride) {
+        const long long qq = q0 + s;
+        const int v = find_view(p.qoff, p.ncam, qq);
+        const DevCam& c = p.cams[v];
+        const DevScene& S = p.scenes[c.scene];
+        int x, y, j;
+        decode_path(c, qq - c.qoff, p.spp, x, y, j);
+        const Ctr ctr{(uint32_t)(y * c.W + x), ((uint32_t)v << 16) | (uint32_t)j, 0u, 0u};
+        const float4 u = draw4(ctr, 0, 0, Key{p.seed, S.scene_id});
+        const V3 d = cam_dir(c, (float)x + u.x, (float)y + u.y);
+        float* const* r = q.ray[1];
+        r[0][s] = c.eye[0]; r[1][s] = c.eye[1]; r[2][s] = c.eye[2];
+        r[3][s] = d.x; r[4][s] = d.y; r[5][s] = d.z;
+        ((int*)r[6])[s] = s;
+        ((int*)r[7])[s] = -1;
+        r[8][s] = 0.0f;
+        q.pq[s] = (uint32_t)qq;
+        q.pc0[s] = ctr.c0;
+        q.pc1[s] = ctr.c1;
+        q.pbeta[0][s] = 1.0f; q.pbeta[1][s] = 1.0f; q.pbeta[2][s] = 1.0f;
+        q.phash[s] = FNV_INIT;
+        q.L[3 * (size_t)qq] = 0.0f; q.L[3 * (size_t)qq + 1] = 0.0f; q.L[3 * (size_t)qq + 2] = 0.0f;
+    }
+}
+
+// closest hit for every queued ray of bounce k (queue k & 1)
+__global__ void __launch_bounds__(TRACE_BLOCK) k_extend(FwdParams p, Queues q, int k) {
+    __shared__ uint32_t lds[LDS_STACK * TRACE_BLOCK];
+    TravStack st = make_stack(lds, q.spill, p.err);
+    const int n = q.cnt[k];
+    float* const* r = q.ray[k & 1];
+    const int stride = gridDim.x * blockDim.x;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const int slot = ((const int*)r[6])[i];
+        const uint32_t v = q.pc1[slot] >> 16;
+        const DevScene& S = p.scenes[p.cams[v].scene];
+        const V3 o{r[0][i], r[1][i], r[2][i]}, d{r[3][i], r[4][i], r[5][i]};
+        float t;
+        const int f = trace_closest(S, o, d, TMIN, ((const int*)r[7])[i], t, st);
+        q.ht[i] = t;
+        q.hf[i] = f;
+    }
+}
+
+// shading of bounce k: escapes, next-event set-up and BRDF continuation
+__global__ void k_shade(FwdParams p, Queues q, int k) {
+    const int n = q.cnt[k];
+    float* const* r = q.ray[k & 1];
+    float* const* rn = q.ray[(k + 1) & 1];
+    const int stride = gridDim.x * blockDim.x;
+    const int nent = q.nent;
+    // every lane of a wave runs the same number of iterations so that the
+    // compaction ballot below sees whole waves
+    const int base0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63);
+    for (int wb = base0; wb < n; wb += stride) {
+        const int i = wb + (threadIdx.x & 63);
+        const bool active = i < n;
+        bool emit = false;
+        V3 x{0.f, 0.f, 0.f}, wi{0.f, 0.f, 0.f};
+        float pb = 0.0f;
+        int f = -1, slot = 0;
+        if (active) {
+            slot = ((const int*)r[6])[i];
+            const uint32_t c1 = q.pc1[slot];
+            const uint32_t v = c1 >> 16;
+            const DevScene& S = p.scenes[p.cams[v].scene];
+            const Key key{p.seed, S.scene_id};
+            const Ctr ctr{q.pc0[slot], c1, 0u, 0u};
+            Hash h{q.phash[slot], true};
+            V3 beta{q.pbeta[0][slot], q.pbeta[1][slot], q.pbeta[2][slot]};
+            const uint32_t qq = q.pq[slot];
+            f = q.hf[i];
+            push_face(h, f);
+            q.sface[i] = -1;
+            const V3 d{r[3][i], r[4][i], r[5][i]};
+            if (f < 0) {
+                if (S.has_env && k > 1) {
+                    const int tex = env_texel_of(S, d);
+                    h.push((uint32_t)tex);
+                    const float pp = r[8][i];
+                    const float w = pp / (pp + S.texpdf[tex]);
+                    const V3 c = mul(beta, env_rgb(S, tex)) * w;
+                    float* L = q.L + 3 * (size_t)qq;
+                    L[0] += c.x; L[1] += c.y; L[2] += c.z;
+                }
+            } else if (k <= p.B) {
+                const V3 o{r[0][i], r[1][i], r[2][i]};
+                x = o + d * q.ht[i];
+                V3 n = xyz(S.fnorm[f]);
+                const V3 wo = -d;
+                if (dot(n, wo) < 0.0f) n = -n;
+                const Mat m = load_mat(S.mat + 7 * (size_t)f);
+                for (int l = 0; l < S.nl; ++l) {
+                    const float* lt = S.lights + 6 * l;
+                    const V3 dl = ld3(lt) - x;
+                    const float r2 = dot(dl, dl);
+                    float tmax = -1.0f;
+                    V3 wl{0.f, 0.f, 0.f}, ct{0.f, 0.f, 0.f};
+                    if (r2 > 0.0f) {
+                        const float rr = sqrtf(r2);
+                        wl = dl * (1.0f / rr);
+                        const float c = dot(n, wl);
+                        if (c > 0.0f) {
+                            tmax = rr * (1.0f - SHADOW_SHRINK);
+                            ct = mul(beta, mul(ld3(lt + 3), brdf_eval(wl, wo, n, m))) * (c / r2);
+                        }
+                    }
+                    const size_t e = (size_t)l * q.cap + i;
+                    q.sh[0][e] = wl.x; q.sh[1][e] = wl.y; q.sh[2][e] = wl.z; q.sh[3][e] = tmax;
+                    q.sh[4][e] = ct.x; q.sh[5][e] = ct.y; q.sh[6][e] = ct.z;
+                }
+                int tex = 0;
+                if (S.has_env) {
+                    const float4 u = draw4(ctr, k, 1, key);
+                    V3 we; float pe;
+                    tex = env_sample(S, u, we, pe);
+                    const float c = dot(n, we);
+                    float tmax = -1.0f;
+                    V3 ct{0.f, 0.f, 0.f};
+                    if (c > 0.0f && pe > 0.0f) {
+                        tmax = __int_as_float(0x7f800000);
+                        const float den = pe + bsdf_pdf(we, wo, n, m.a);
+                        ct = mul(beta, mul(env_rgb(S, tex), brdf_eval(we, wo, n, m))) * (c / den);
+                    }
+                    const size_t e = (size_t)S.nl * q.cap + i;
+                    q.sh[0][e] = we.x; q.sh[1][e] = we.y; q.sh[2][e] = we.z; q.sh[3][e] = tmax;
+                    q.sh[4][e] = ct.x; q.sh[5][e] = ct.y; q.sh[6][e] = ct.z;
+                }
+                uint32_t info = 0;
+                if (k < p.B || S.has_env) {
+                    const float4 u = draw4(ctr, k, 2, key);
+                    const int lobe = bsdf_sample(u, wo, n, m.a, wi);
+                    const float ci = dot(n, wi);
+                    pb = bsdf_pdf(wi, wo, n, m.a);
+                    info = 1u | ((uint32_t)lobe << 1);
+                    if (ci > 0.0f && pb > 0.0f) {
+                        info |= 4u;
+                        emit = true;
+                        beta = mul(beta, brdf_eval(wi, wo, n, m)) * (ci / pb);
+                        q.pbeta[0][slot] = beta.x; q.pbeta[1][slot] = beta.y; q.pbeta[2][slot] = beta.z;
+                    }
+                }
+                q.sface[i] = f;
+                q.sinfo[i] = info;
+                q.stex[i] = tex;
+                q.sx[0][i] = x.x; q.sx[1][i] = x.y; q.sx[2][i] = x.z;
+            }
+            q.phash[slot] = h.h;
+        }
+        (void)nent;
+        // wave-level compaction of the continuing paths into the next queue
+        const uint64_t mask = __ballot(emit);
+        if (mask) {
+            const int leader = __ffsll((long long)mask) - 1;
+            int basei = 0;
+            if ((int)__lane_id() == leader) basei = atomicAdd(&q.cnt[k + 1], __popcll(mask));
+            basei = __shfl(basei, leader);
+            if (emit) {
+                const int o = basei + __popcll(mask & lanemask_lt64());
+                rn[0][o] = x.x; rn[1][o] = x.y; rn[2][o] = x.z;
+                rn[3][o] = wi.x; rn[4][o] = wi.y; rn[5][o] = wi.z;
+                ((int*)rn[6])[o] = slot;
+                ((int*)rn[7])[o] = f;
+                rn[8][o] = pb;
+            }
+        }
+    }
+}
+
+// shadow rays of bounce k, one thread per shading point, fixed order
+__global__ void __launch_bounds__(TRACE_BLOCK) k_shadow(FwdParams p, Queues q, int k) {
+    __shared__ uint32_t lds[LDS_STACK * TRACE_BLOCK];
+    TravStack st = make_stack(lds, q.spill, p.err);
+    const int n = q.cnt[k];
+    float* const* r = q.ray[k & 1];
+    const int stride = gridDim.x * blockDim.x;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const int f = q.sface[i];
+        if (f < 0) continue;
+        const int slot = ((const int*)r[6])[i];
+        const uint32_t v = q.pc1[slot] >> 16;
+        const DevScene& S = p.scenes[p.cams[v].scene];
+        const V3 x{q.sx[0][i], q.sx[1][i], q.sx[2][i]};
+        Hash h{q.phash[slot], true};
+        V3 acc{0.f, 0.f, 0.f};
+        const int nent = S.nl + (S.has_env ? 1 : 0);
+        for (int l = 0; l < nent; ++l) {
+            const size_t e = (size_t)l * q.cap + i;
+            const float tmax = q.sh[3][e];
+            uint32_t code = 0;
+            if (l == S.nl) h.push((uint32_t)q.stex[i]);
+            if (tmax >= 0.0f) {
+                const V3 dir{q.sh[0][e], q.sh[1][e], q.sh[2][e]};
+                const bool occ = trace_any(S, x, dir, TMIN, tmax, f, st);
+                code = occ ? 1u : 2u;
+                if (!occ) acc = acc + V3{q.sh[4][e], q.sh[5][e], q.sh[6][e]};
+            }
+            h.push(code);
+        }
+        const uint32_t info = q.sinfo[i];
+        if (info & 1u) {
+            h.push((info >> 1) & 1u);
+            h.push((info >> 2) & 1u);
+        }
+        q.phash[slot] = h.h;
+        float* L = q.L + 3 * (size_t)q.pq[slot];
+        L[0] += acc.x; L[1] += acc.y; L[2] += acc.z;
+    }
+}
+
+__global__ void k_chunk_hash(FwdParams p, Queues q, int n) {
+    const int stride = gridDim.x * blockDim.x;
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += stride) {
+        const long long qq = q.pq[s];
+        const int v = (int)(q.pc1[s] >> 16), j = (int)(q.pc1[s] & 0xFFFFu);
+        const DevCam& c = p.cams[v];
+        const int x = (int)(q.pc0[s] % (uint32_t)c.W), y = (int)(q.pc0[s] / (uint32_t)c.W);
+        p.dbg_hash[canon(c, x, y, j, p.spp)] = q.phash[s];
+        (void)qq;
+    }
+}
+
+// single-kernel forward (one thread per path sample); same estimator
+__global__ void __launch_bounds__(TRACE_BLOCK) k_forward_mega(FwdParams p, float* L, long long total,
+                                                              uint32_t* spill) {
+    __shared__ uint32_t lds[LDS_STACK * TRACE_BLOCK];
+    TravStack st = make_stack(lds, spill, p.err);
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long qq = blockIdx.x * (long long)blockDim.x + threadIdx.x; qq < total; qq += stride) {
+        const int v = find_view(p.qoff, p.ncam, qq);
+        const DevCam& c = p.cams[v];
+        const DevScene& S = p.scenes[c.scene];
+        int x, y, j;
+        decode_path(c, qq - c.qoff, p.spp, x, y, j);
+        const Ctr ctr{(uint32_t)(y * c.W + x), ((uint32_t)v << 16) | (uint32_t)j, 0u, 0u};
+        const Key key{p.seed, S.scene_id};
+        const float4 u = draw4(ctr, 0, 0, key);
+        const V3 d = cam_dir(c, (float)x + u.x, (float)y + u.y);
+        Hash h{FNV_INIT, true};
+        const V3 r = trace_estimator(S, ld3(c.eye), d, -1, p.B, false, ctr, key, h, st);
+        L[3 * qq] = r.x; L[3 * qq + 1] = r.y; L[3 * qq + 2] = r.z;
+        if (p.dbg_hash) p.dbg_hash[canon(c, x, y, j, p.spp)] = h.h;
+    }
+}
+
+// film: average the spp samples of each pixel in sample order
+__global__ void k_film(const DevCam* __restrict__ cams, const long long* __restrict__ pixoff, int ncam, int spp,
+                       const float* __restrict__ L, long long npix, float* out) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < npix; g += stride) {
+        const int v = find_view(pixoff, ncam, g);
+        const DevCam& c = cams[v];
+        const int p = (int)(g - c.pixoff);
+        const int x = p % c.W, y = p / c.W;
+        int pt;
+        if ((c.W & 7) == 0 && (c.H & 7) == 0) pt = (((y >> 3) * (c.W >> 3) + (x >> 3)) << 6) | ((y & 7) << 3) | (x & 7);
+        else pt = p;
+        const long long hw = (long long)c.W * c.H;
+        float a = 0.f, b = 0.f, cc = 0.f;
+        for (int j = 0; j < spp; ++j) {
+            const long long qq = c.qoff + (long long)j * hw + pt;
+            a += L[3 * qq]; b += L[3 * qq + 1]; cc += L[3 * qq + 2];
+        }
+        const float inv = 1.0f / (float)spp;
+        out[3 * g] = a * inv; out[3 * g + 1] = b * inv; out[3 * g + 2] = cc * inv;
+    }
+}
+
+// per-sample radiance in canonical order (debug output)
+__global__ void k_sample_radiance(FwdParams p, const float* __restrict__ L, long long total, float* out) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long qq = blockIdx.x * (long long)blockDim.x + threadIdx.x; qq < total; qq += stride) {
+        const int v = find_view(p.qoff, p.ncam, qq);
+        const DevCam& c = p.cams[v];
+        int x, y, j;
+        decode_path(c, qq - c.qoff, p.spp, x, y, j);
+        const long long g = canon(c, x, y, j, p.spp);
+        out[3 * g] = L[3 * qq]; out[3 * g + 1] = L[3 * qq + 1]; out[3 * g + 2] = L[3 * qq + 2];
+    }
+}
+
+__global__ void k_fill_f32(float* p, long long n, float v) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+__global__ void k_fill_u32(uint32_t* p, long long n, uint32_t v) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+// closest hit of caller-given rays (BVH, or brute force over all faces)
+__global__ void __launch_bounds__(TRACE_BLOCK) k_trace_debug(const DevScene* sc, const float* o, const float* d,
+                                                             int n, float tmin, int brute, int* of, float* ot,
+                                                             uint32_t* spill, uint32_t* err) {
+    __shared__ uint32_t lds[LDS_STACK * TRACE_BLOCK];
+    const DevScene& S = *sc;
+    TravStack st = make_stack(lds, spill, err);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const V3 oo = ld3(o + 3 * i), dd = ld3(d + 3 * i);
+    float tb = __int_as_float(0x7f800000);
+    int fb = -1;
+    if (brute) {
+        for (int l = 0; l < S.nf; ++l) {
+            float t; int f;
+            if (tri_test(S.tri, (uint32_t)l, oo, dd, tmin, __int_as_float(0x7f800000), t, f))
+                if (t < tb || (t == tb && f < fb)) { tb = t; fb = f; }
+        }
+    } else {
+        fb = trace_closest(S, oo, dd, tmin, -1, tb, st);
+    }
+    of[i] = fb;
+    ot[i] = tb;
+}
+
+// ---------------------------------------------------------------------------
+static inline unsigned grid_for(long long n, int bs, unsigned cap) {
+    long long g = (n + bs - 1) / bs;
+    if (g < 1) g = 1;
+    return (unsigned)(g < (long long)cap ? g : cap);
+}
+
+
+void launch_forward_wavefront(const FwdParams& p, Queues& q, long long total, int has_env_any, int nent,
+                              hipStream_t st) {
+    q.nent = nent;
+    for (long long q0 = 0; q0 < total; q0 += q.cap) {
+        const int n = (int)((total - q0) < q.cap ? (total - q0) : q.cap);
+        const unsigned g = grid_for(n, TRACE_BLOCK, TRACE_GRID);
+        hipLaunchKernelGGL(k_camera, dim3(grid_for(n, 256, 1u << 20)), dim3(256), 0, st, p, q, q0, n);
+        const int last = p.B + (has_env_any ? 1 : 0);
+        for (int k = 1; k <= last; ++k) {
+            hipLaunchKernelGGL(k_extend, dim3(g), dim3(TRACE_BLOCK), 0, st, p, q, k);
+            hipLaunchKernelGGL(k_shade, dim3(grid_for(n, 256, TRACE_GRID)), dim3(256), 0, st, p, q, k);
+            if (k <= p.B) hipLaunchKernelGGL(k_shadow, dim3(g), dim3(TRACE_BLOCK), 0, st, p, q, k);
+        }
+        if (p.dbg_hash)
+            hipLaunchKernelGGL(k_chunk_hash, dim3(grid_for(n, 256, 1u << 20)), dim3(256), 0, st, p, q, n);
+    }
+}
+
+void launch_forward_mega(const FwdParams& p, float* L, long long total, uint32_t* spill, int grid,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(k_forward_mega, dim3(grid_for(total, TRACE_BLOCK, grid)), dim3(TRACE_BLOCK), 0, st, p, L,
+                       total, spill);
+}
+
+void launch_film(const DevCam* cams, const long long* pixoff, int ncam, int spp, const float* L, long long npix,
+                 float* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_film, dim3(grid_for(npix, 256, 1u << 16)), dim3(256), 0, st, cams, pixoff, ncam, spp, L,
+                       npix, out);
+}
+
+void launch_sample_radiance(const FwdParams& p, const float* L, long long total, float* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_sample_radiance, dim3(grid_for(total, 256, 1u << 16)), dim3(256), 0, st, p, L, total,
+                       out);
+}
+
+void launch_fill_f32(float* ptr, long long n, float v, hipStream_t st) {
+    if (n > 0) hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(n, 256, 1u << 16)), dim3(256), 0, st, ptr, n, v);
+}
+void launch_fill_u32(uint32_t* ptr, long long n, uint32_t v, hipStream_t st) {
+    if (n > 0) hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256, 1u << 16)), dim3(256), 0, st, ptr, n, v);
+}
+
+void launch_trace_debug(const DevScene* s, const float* o, const float* d, int n, float tmin, int brute,
+                        int* out_face, float* out_t, uint32_t* spill, uint32_t* err, hipStream_t st) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_trace_debug, dim3((n + TRACE_BLOCK - 1) / TRACE_BLOCK), dim3(TRACE_BLOCK), 0, st, s, o,
+                           d, n, tmin, brute, out_face, out_t, spill, err);
+}
+
+} // namespace st
