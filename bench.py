@@ -1,0 +1,183 @@
+#!/usr/bin/env python3
+"""Throughput of one optimisation step of the differentiable path tracer.
+
+Step = LBVH rebuild for the current vertices (st_scene_update) + forward render
+(st_render) + image-loss gradient (torch) + adjoint with interior, primary-edge
+and secondary-edge terms (st_render_backward).  Workload: 40,000-face
+noise-displaced torus under a 512x256 six-lobe HDR environment map, 16 views at
+512x512, 16 samples per pixel, 3 bounces (67,108,864 path samples per step).
+Inputs are synthetic and resident in HBM before the timed region.
+
+Prints one JSON line.  --gpus N with N > 1 is refused: the method runs on one GPU.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic work per unit, stated once here and in the design doc:
+#  - a BVH node visit tests two child boxes: 2 x (6 sub + 6 mul + 12 min/max) = 48 FP32 ops
+#  - a Moller-Trumbore triangle test: 2 cross (18) + 4 dot (20) + 1 rcp + 3 sub + 3 mul = 45 FP32 ops
+FLOPS_PER_VISIT = 48
+FLOPS_PER_TEST = 45
+PEAK_FP32_VECTOR_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--spp", type=int, default=16)
+    ap.add_argument("--res", type=int, default=512)
+    ap.add_argument("--views", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-baseline-res", type=int, default=384)
+    ap.add_argument("--profile-only", action="store_true", help="one untimed step (for rocprofv3 runs)")
+    return ap.parse_args()
+
+
+def cpu_baseline(wl, res, spp, bounces):
+    """The FP64 oracle on a bounded sample: the same torus scene, one view at
+    res x res, same spp and bounces, full forward + adjoint (all three terms)."""
+    import numpy as np
+    import oracle as O
+    from paper_2012_03939_amd import scenes as S
+    sc = wl.scenes[0]
+    cam = S.look_at_origin(wl.cams[0].eye, res, res)
+    o = O.OracleScene.from_scene(sc)
+    nt = O.default_threads()
+    t0 = time.perf_counter()
+    img, _ = o.render([cam], spp, bounces, seed=0, nthreads=nt)
+    d = np.random.default_rng(0).normal(size=img.shape).astype(np.float32)
+    o.backward([cam], spp, bounces, d, seed=0, flags=7, nthreads=nt)
+    dt = time.perf_counter() - t0
+    n = res * res * spp
+    return {"value": n / dt, "unit": "path samples/s (fwd+adjoint)", "cores": nt, "kind": "oracle",
+            "sample": f"same torus scene and envmap, 1 view at {res}x{res}, {spp} spp, {bounces} bounces, "
+                      f"forward + adjoint (interior, primary and secondary edges): {n} path samples in {dt:.2f} s"}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this path tracer runs on one GPU; multi-GPU runs are not supported "
+                                   "(see DESIGN.md for how the path would shard)"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2012_03939_amd import binding as B, scenes as S
+
+    wl = S.torus_envmap(res=args.res, nviews=args.views, spp=args.spp, bounces=3)
+    sc = wl.scenes[0]
+    g = B.GPUScene.from_scene(sc)
+    cams, spp, bounces = wl.cams, wl.spp, wl.bounces
+    npix = B.num_pixels(cams)
+    n_paths = npix * spp
+    dev = torch.device("cuda")
+    V0 = torch.from_numpy(sc.V).to(dev)
+    # target images from perturbed vertices (synthetic stand-in for captured views)
+    g.update(V=torch.from_numpy(S.perturbed_vertices(sc.V, 0.01, 77)).to(dev))
+    target = g.render(cams, spp, bounces, seed=1).clone()
+    Vs = [V0 + 1e-4 * torch.randn_like(V0) for _ in range(2)]
+    dV = torch.empty_like(V0)
+    dM = torch.empty((g.nf, 7), dtype=torch.float32, device=dev)
+    img = torch.empty((npix, 3), dtype=torch.float32, device=dev)
+    scale = 2.0 / img.numel()
+
+    def step(i):
+        g.update(V=Vs[i & 1])
+        g.render(cams, spp, bounces, seed=i, out=img)
+        d = (img - target) * scale
+        g.backward(cams, spp, bounces, d, seed=i, flags=B.ST_ALL_GRADS, dV=dV, dmat=dM)
+
+    if args.profile_only:
+        step(0)
+        torch.cuda.synchronize()
+        g.check_errors()
+        print(json.dumps({"profile_only": True, "n_paths": n_paths}))
+        return
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    g.check_errors()
+    B.profile_read()
+    B.profile_enable(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    for i in range(args.steps):
+        step(100 + i)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    B.profile_enable(False)
+    prof = B.profile_read()
+    g.check_errors()
+    ms = e0.elapsed_time(e1)
+    ms_per_step = ms / args.steps
+    value = n_paths * args.steps / (ms / 1e3)
+
+    # dominant kernel and its algorithmic work, counted in a separate (untimed) pass
+    dom = max(prof.items(), key=lambda kv: kv[1][0])
+    dom_name, (dom_ms, dom_n) = dom[0], dom[1]
+    g.read_work()
+    if dom_name.startswith("k_adjoint"):
+        g.backward(cams, spp, bounces, (img - target) * scale, seed=100, flags=B.ST_GRAD_INTERIOR | B.ST_EDGE_SECONDARY
+                   | B.ST_COUNT_WORK, dV=dV, dmat=dM)
+    elif dom_name.startswith("k_prim"):
+        g.backward(cams, spp, bounces, (img - target) * scale, seed=100, flags=B.ST_EDGE_PRIMARY | B.ST_COUNT_WORK,
+                   dV=dV, dmat=dM)
+    else:
+        g.render(cams, spp, bounces, seed=100, out=img, flags=B.ST_COUNT_WORK)
+    visits, tests, rays = g.read_work()
+    if dom_name in ("k_extend", "k_shadow"):
+        # the render pass counted both traversal kernels; split by their launch time share
+        share = prof[dom_name][0] / (prof.get("k_extend", (0, 0))[0] + prof.get("k_shadow", (0, 0))[0])
+        visits, tests, rays = visits * share, tests * share, rays * share
+    launches_per_step = dom_n / args.steps
+    flops_per_launch = (visits * FLOPS_PER_VISIT + tests * FLOPS_PER_TEST) / max(launches_per_step, 1)
+    avg_ms = dom_ms / dom_n
+    achieved = flops_per_launch / (avg_ms / 1e3) / 1e12
+    kernels = {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[1] / args.steps} for k, v in prof.items()}
+    out = {
+        "metric": "fwd+adjoint path samples/sec at 16 views 512^2 16spp",
+        "value": value,
+        "unit": "path samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "wall_s": wall,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "faces": int(sc.F.shape[0]), "views": len(cams), "res": args.res,
+                   "spp": spp, "bounces": bounces, "path_samples_per_step": n_paths,
+                   "edge_samples_per_step": B.num_edge_samples(cams, spp, 1.0), "envmap": "512x256"},
+        "roofline": {"bound": "alu", "kernel": dom_name, "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
+                     "avg_launch_ms": avg_ms, "node_visits_per_launch": visits / max(launches_per_step, 1),
+                     "tri_tests_per_launch": tests / max(launches_per_step, 1),
+                     "rays_per_launch": rays / max(launches_per_step, 1),
+                     "rays_per_s": rays / max(launches_per_step, 1) / (avg_ms / 1e3)},
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_baseline_res, spp, bounces)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

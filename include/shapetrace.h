@@ -52,6 +52,7 @@ extern "C" {
 #define ST_EDGE_PRIMARY 2u         /* screen-space silhouette / crease edges (camera visibility) */
 #define ST_EDGE_SECONDARY 4u       /* direction-space silhouette edges at every path vertex */
 #define ST_FORWARD_MEGAKERNEL 16u  /* forward as one kernel per path sample instead of the wavefront */
+#define ST_COUNT_WORK 32u          /* count BVH node visits, triangle tests and rays (st_read_work) */
 
 typedef struct st_scene st_scene;
 
@@ -134,10 +135,23 @@ int st_check_errors(st_scene* scene, hipStream_t s);
  *  st_trace_rays: closest hit of n rays o,d (float [n,3]) with t > tmin, through
  *    the BVH or by brute force; out_face int32 [n] (-1 miss), out_t float [n]. */
 int st_scene_info(const st_scene* scene, int64_t* out6);
+/* Traversal work counted by calls made with ST_COUNT_WORK since the last read:
+ * host uint64 [3] = BVH node visits, triangle tests, rays traced.  Waits for s
+ * and resets the counters. */
+int st_read_work(st_scene* scene, uint64_t* out3, hipStream_t s);
 int st_scene_edges(st_scene* scene, int32_t* out_edges, hipStream_t s);
 int st_scene_lbvh(st_scene* scene, uint64_t* keys, int32_t* child, int32_t* parent, float* aabb, hipStream_t s);
 int st_trace_rays(st_scene* scene, const float* o, const float* d, int32_t n, float tmin, int32_t brute,
                   int32_t* out_face, float* out_t, hipStream_t s);
+
+/* Kernel timing for profiling harnesses: while enabled, every kernel the
+ * library launches is bracketed by two HIP events recorded on its launch
+ * stream.  st_profile_read waits for those events, writes the kernel names
+ * (newline-separated, NUL-terminated, at most names_len bytes), the summed
+ * milliseconds and the launch counts of up to max_kernels kernels in first-seen
+ * order, clears the record, and returns the number of kernels (or < 0). */
+int st_profile_enable(int on);
+int st_profile_read(char* names, int32_t names_len, double* ms, int32_t* counts, int32_t max_kernels);
 
 void st_scene_destroy(st_scene* scene);
 const char* st_last_error(void);

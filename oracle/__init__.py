@@ -102,7 +102,7 @@ def _f64(x, n=None):
 
 
 def default_threads() -> int:
-    return max(1, min(os.cpu_count() or 1, 64))
+    return max(1, min(os.cpu_count() or 1, 16))
 
 
 def cam_arrays(cams):

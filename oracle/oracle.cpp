@@ -695,8 +695,10 @@ static D3 trace_estimator(const Scene& s, D3 o, D3 d, int exclude, int nvert, bo
             sech.push((uint32_t)e);
             const Edge& E = s.edges[e];
             D3 va = s.vert(E.va), vb = s.vert(E.vb);
-            bool sil = true;
-            if (E.f2 >= 0) {
+            // an edge of the shading face lies in the tangent plane (cos = 0):
+            // its direction-space contribution vanishes, so it is never taken
+            bool sil = E.f1 != f && E.f2 != f;
+            if (sil && E.f2 >= 0) {
                 double s1 = dot(face_N(s, E.f1), x - va), s2 = dot(face_N(s, E.f2), x - va);
                 sil = (s1 > 0.0) != (s2 > 0.0);
             }

@@ -20,11 +20,13 @@ ST_GRAD_INTERIOR = 1
 ST_EDGE_PRIMARY = 2
 ST_EDGE_SECONDARY = 4
 ST_FORWARD_MEGAKERNEL = 16
+ST_COUNT_WORK = 32
 ST_ALL_GRADS = 7
 
 EXPORTED = ["st_render_opts_default", "st_scene_create", "st_scene_update", "st_render", "st_render_backward",
-            "st_render_batch", "st_check_errors", "st_scene_info", "st_scene_edges", "st_scene_lbvh",
-            "st_trace_rays", "st_scene_destroy", "st_last_error", "st_version"]
+            "st_render_batch", "st_check_errors", "st_read_work", "st_scene_info", "st_scene_edges", "st_scene_lbvh",
+            "st_trace_rays", "st_profile_enable", "st_profile_read", "st_scene_destroy", "st_last_error",
+            "st_version"]
 
 
 class StCamera(ctypes.Structure):
@@ -63,9 +65,12 @@ def load(path: str = LIB_PATH):
     L.st_render_batch.argtypes = [P, I32, P, P, I32, I32, I32, U32, ctypes.POINTER(StOpts), P, P]
     L.st_check_errors.argtypes = [P, P]
     L.st_scene_info.argtypes = [P, P]
+    L.st_read_work.argtypes = [P, P, P]
     L.st_scene_edges.argtypes = [P, P, P]
     L.st_scene_lbvh.argtypes = [P, P, P, P, P, P]
     L.st_trace_rays.argtypes = [P, P, P, I32, F32, I32, P, P, P]
+    L.st_profile_enable.argtypes = [ctypes.c_int]
+    L.st_profile_read.argtypes = [ctypes.c_char_p, I32, P, P, I32]
     L.st_scene_destroy.argtypes = [P]
     L.st_last_error.restype = ctypes.c_char_p
     L.st_version.restype = ctypes.c_int
@@ -198,6 +203,12 @@ class GPUScene:
     def check_errors(self):
         _check(load().st_check_errors(self.h, _stream()))
 
+    def read_work(self):
+        """(node visits, triangle tests, rays) counted by ST_COUNT_WORK calls since the last read."""
+        out = (ctypes.c_uint64 * 3)()
+        _check(load().st_read_work(self.h, out, _stream()))
+        return int(out[0]), int(out[1]), int(out[2])
+
     def edges(self):
         import torch
         out = torch.empty((self.ne, 4), dtype=torch.int32, device="cuda")
@@ -223,6 +234,23 @@ class GPUScene:
         _check(load().st_trace_rays(self.h, _ptr(o.contiguous()), _ptr(d.contiguous()), n, tmin, int(brute),
                                     _ptr(f), _ptr(t), _stream()))
         return f, t
+
+
+def profile_enable(on: bool = True):
+    load().st_profile_enable(1 if on else 0)
+
+
+def profile_read(max_kernels: int = 64):
+    """{kernel name: (total ms, launches)} for the launches since the last read."""
+    L = load()
+    names = ctypes.create_string_buffer(1 << 16)
+    ms = (ctypes.c_double * max_kernels)()
+    cnt = (ctypes.c_int32 * max_kernels)()
+    n = L.st_profile_read(names, len(names), ms, cnt, max_kernels)
+    if n < 0:
+        _check(n)
+    keys = names.value.decode().split("\n")[:n]
+    return {k: (ms[i], cnt[i]) for i, k in enumerate(keys)}
 
 
 def render_batch(scenes: Sequence[GPUScene], cams, cam_scene, spp: int, bounces: int, seed: int = 0, out=None,

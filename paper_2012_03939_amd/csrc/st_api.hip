@@ -101,6 +101,32 @@ bool make_devcam(const st_camera& c, DevCam& o) {
 
 } // namespace
 
+// ---- per-kernel event profiler -------------------------------------------
+namespace st {
+bool g_prof_on = false;
+}
+namespace {
+struct ProfRec { std::string name; hipEvent_t a, b; };
+std::vector<ProfRec> g_prof;
+std::vector<hipEvent_t> g_evpool;
+hipEvent_t take_event() {
+    if (!g_evpool.empty()) { hipEvent_t e = g_evpool.back(); g_evpool.pop_back(); return e; }
+    hipEvent_t e = nullptr;
+    hipEventCreate(&e);
+    return e;
+}
+} // namespace
+void st::prof_begin(hipStream_t s, const char* name) {
+    ProfRec r{name, take_event(), nullptr};
+    hipEventRecord(r.a, s);
+    g_prof.push_back(r);
+}
+void st::prof_end(hipStream_t s) {
+    if (g_prof.empty()) return;
+    g_prof.back().b = take_event();
+    hipEventRecord(g_prof.back().b, s);
+}
+
 struct st_scene {
     SceneDev d;
     GrowBuf camsbuf, Lbuf, qbuf, spillbuf, primbuf, scenesbuf;
@@ -254,6 +280,7 @@ int render_impl(st_scene* owner, st_scene* const* scenes, int nscenes, const st_
     p.seed = seed;
     p.dbg_hash = o.debug_decision_hash;
     p.err = owner->d.err;
+    p.work = (o.flags & ST_COUNT_WORK) ? owner->d.work : nullptr;
     float* L = (float*)owner->Lbuf.p;
     if (o.flags & ST_FORWARD_MEGAKERNEL) {
         launch_forward_mega(p, L, cs.total_paths, (uint32_t*)owner->spillbuf.p, TRACE_GRID, s);
@@ -285,6 +312,43 @@ st_render_opts st_render_opts_default(void) {
 }
 
 int st_version(void) { return 1; }
+
+int st_profile_enable(int on) {
+    g_prof_on = on != 0;
+    return ST_OK;
+}
+
+int st_profile_read(char* names, int32_t names_len, double* ms, int32_t* counts, int32_t max_kernels) {
+    // aggregate by kernel name in first-seen order; "name1\nname2\n..." into names
+    std::vector<std::string> order;
+    std::vector<double> tot;
+    std::vector<int> cnt;
+    for (auto& r : g_prof) {
+        if (!r.b) continue;
+        if (hipEventSynchronize(r.b) != hipSuccess) return fail(ST_ERR_HIP, "event synchronize failed");
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) return fail(ST_ERR_HIP, "event elapsed failed");
+        size_t k = 0;
+        while (k < order.size() && order[k] != r.name) ++k;
+        if (k == order.size()) { order.push_back(r.name); tot.push_back(0.0); cnt.push_back(0); }
+        tot[k] += t;
+        cnt[k] += 1;
+    }
+    for (auto& r : g_prof) { g_evpool.push_back(r.a); if (r.b) g_evpool.push_back(r.b); }
+    g_prof.clear();
+    std::string joined;
+    const int n = std::min<int>((int)order.size(), max_kernels);
+    for (int i = 0; i < n; ++i) {
+        joined += order[i] + "\n";
+        if (ms) ms[i] = tot[i];
+        if (counts) counts[i] = cnt[i];
+    }
+    if (names && names_len > 0) {
+        std::strncpy(names, joined.c_str(), names_len - 1);
+        names[names_len - 1] = 0;
+    }
+    return n;
+}
 
 const char* st_last_error(void) { return g_err.c_str(); }
 
@@ -345,6 +409,7 @@ int st_scene_create(const float* V, int32_t nv, const int32_t* F, int32_t nf, co
     A(dalloc(&d.etotal_d, 1));
     A(dalloc(&d.etotal_f, 1));
     A(dalloc(&d.err, 1));
+    A(dalloc(&d.work, 4));
     A(dalloc(&d.dscene, 1));
     if (he > 0) {
         A(dalloc(&d.env, 3 * (size_t)he * we));
@@ -366,6 +431,7 @@ int st_scene_create(const float* V, int32_t nv, const int32_t* F, int32_t nf, co
     if (!edges.empty())
         HIPCHK2(hipMemcpyAsync(d.edges, edges.data(), sizeof(int4) * edges.size(), hipMemcpyHostToDevice, s));
     launch_fill_u32(d.err, 1, 0u, s);
+    launch_fill_u32((uint32_t*)d.work, 8, 0u, s);
     std::vector<double> dom(std::max(he, 1));
     std::vector<float> rowcos(he + 1);
     if (he > 0) {
@@ -461,6 +527,7 @@ int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_
     p.dbg_hash = o.debug_decision_hash;
     p.dbg_edge_hash = o.debug_edge_hash;
     p.err = sc->d.err;
+    p.work = (o.flags & ST_COUNT_WORK) ? sc->d.work : nullptr;
     p.spill = (uint32_t*)sc->spillbuf.p;
     p.pw = c.take<double>((size_t)ncam * ne);
     p.pcdf = c.take<double>((size_t)ncam * (ne + 1));
@@ -486,6 +553,17 @@ int st_check_errors(st_scene* sc, hipStream_t s) {
         HIPCHK(hipStreamSynchronize(s));
         return fail(ST_ERR_DEVICE_FAULT, "device error word " + std::to_string(e) + " (1: traversal stack overflow, 8: traversal iteration cap)");
     }
+    return ST_OK;
+}
+
+int st_read_work(st_scene* sc, uint64_t* out3, hipStream_t s) {
+    int rc = check_scene(sc);
+    if (rc) return rc;
+    if (!out3) return fail(ST_ERR_INVALID_ARG, "out is NULL");
+    HIPCHK(hipMemcpyAsync(out3, sc->d.work, 3 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    launch_fill_u32((uint32_t*)sc->d.work, 8, 0u, s);
+    HIPCHK(hipStreamSynchronize(s));
     return ST_OK;
 }
 
@@ -539,7 +617,7 @@ void st_scene_destroy(st_scene* sc) {
     void* ptrs[] = {d.V, d.F, d.mat, d.lights, d.env, d.fnorm, d.bmin, d.bmax, d.cen, d.bounds, d.mkeys[0], d.mkeys[1],
                     d.mvals[0], d.mvals[1], d.rs_hist, d.keys64, d.child, d.parent, d.aabb, d.refit_cnt, d.nodes,
                     d.tri, d.edges, d.edge_w, d.ecdf, d.etotal_d, d.etotal_f, d.row_dom, d.rowcos, d.cond, d.marg,
-                    d.env_rows, d.env_total, d.texpdf, d.err, d.dscene};
+                    d.env_rows, d.env_total, d.texpdf, d.err, d.work, d.dscene};
     for (void* p : ptrs)
         if (p) hipFree(p);
     sc->camsbuf.release(); sc->Lbuf.release(); sc->qbuf.release(); sc->spillbuf.release(); sc->primbuf.release();

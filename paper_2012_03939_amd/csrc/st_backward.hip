@@ -24,7 +24,8 @@
 
 namespace st {
 
-__device__ __forceinline__ TravStack make_stack_b(uint32_t* lds, uint32_t* spill, uint32_t* err) {
+__device__ __forceinline__ TravStack make_stack_b(uint32_t* lds, uint32_t* spill, uint32_t* err,
+                                                  unsigned long long* work) {
     TravStack s;
     s.lds = lds;
     s.spill = spill;
@@ -33,6 +34,7 @@ __device__ __forceinline__ TravStack make_stack_b(uint32_t* lds, uint32_t* spill
     s.gstride = gridDim.x * blockDim.x;
     s.gid = blockIdx.x * blockDim.x + threadIdx.x;
     s.err = err;
+    s.work = work;
     return s;
 }
 
@@ -87,7 +89,7 @@ constexpr uint32_t R_FLIP = 1u, R_ENV = 2u, R_CONT = 4u, R_ESC = 8u, R_SEC = 16u
 template <int BM>
 __global__ void __launch_bounds__(TRACE_BLOCK) k_adjoint(BwdParams p, long long total) {
     __shared__ uint32_t lds[LDS_STACK * TRACE_BLOCK];
-    TravStack st = make_stack_b(lds, p.spill, p.err);
+    TravStack st = make_stack_b(lds, p.spill, p.err, p.work);
     const bool want_interior = p.flags & 1u, want_secondary = p.flags & 4u;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long qq = blockIdx.x * (long long)blockDim.x + threadIdx.x; qq < total; qq += stride) {
@@ -222,7 +224,8 @@ __global__ void __launch_bounds__(TRACE_BLOCK) k_adjoint(BwdParams p, long long 
                 const V3 yv = va + (vb - va) * te;
                 const V3 wv = yv - xh;
                 const float r2 = dot(wv, wv);
-                bool ok = silhouette(S, E, xh) && r2 > 0.0f;
+                // an edge of the shading face lies in the tangent plane: never a silhouette
+                bool ok = E.z != f && E.w != f && silhouette(S, E, xh) && r2 > 0.0f;
                 V3 n = xyz(S.fnorm[f]);
                 if (sel(rfl, k) & R_FLIP) n = -n;
                 V3 ud{0.f, 0.f, 0.f}, mv{0.f, 0.f, 0.f};
@@ -403,7 +406,7 @@ __global__ void k_prim_cdf(BwdParams p) {
 
 __global__ void __launch_bounds__(TRACE_BLOCK) k_prim_samples(BwdParams p, long long total) {
     __shared__ uint32_t lds[LDS_STACK * TRACE_BLOCK];
-    TravStack st = make_stack_b(lds, p.spill, p.err);
+    TravStack st = make_stack_b(lds, p.spill, p.err, p.work);
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long ge = blockIdx.x * (long long)blockDim.x + threadIdx.x; ge < total; ge += stride) {
         if (p.edge_mask && !p.edge_mask[ge]) continue;
@@ -485,15 +488,15 @@ static inline unsigned gridb(long long n, int bs, int cap) {
 void launch_backward(const BwdParams& p, long long total_paths, long long total_edges, int grid, hipStream_t st) {
     if ((p.flags & 5u) && total_paths > 0) {
         const dim3 gd(gridb(total_paths, TRACE_BLOCK, grid)), bd(TRACE_BLOCK);
-        if (p.B <= 1) hipLaunchKernelGGL(k_adjoint<1>, gd, bd, 0, st, p, total_paths);
-        else if (p.B <= 2) hipLaunchKernelGGL(k_adjoint<2>, gd, bd, 0, st, p, total_paths);
-        else if (p.B <= 3) hipLaunchKernelGGL(k_adjoint<3>, gd, bd, 0, st, p, total_paths);
-        else hipLaunchKernelGGL(k_adjoint<8>, gd, bd, 0, st, p, total_paths);
+        if (p.B <= 1) ST_LAUNCH("k_adjoint<1>", k_adjoint<1>, gd, bd, 0, st, p, total_paths);
+        else if (p.B <= 2) ST_LAUNCH("k_adjoint<2>", k_adjoint<2>, gd, bd, 0, st, p, total_paths);
+        else if (p.B <= 3) ST_LAUNCH("k_adjoint<3>", k_adjoint<3>, gd, bd, 0, st, p, total_paths);
+        else ST_LAUNCH("k_adjoint<8>", k_adjoint<8>, gd, bd, 0, st, p, total_paths);
     }
     if ((p.flags & 2u) && total_edges > 0 && p.ne > 0) {
-        hipLaunchKernelGGL(k_prim_weights, dim3(gridb(p.ne, 256, 1024), p.ncam), dim3(256), 0, st, p);
-        hipLaunchKernelGGL(k_prim_cdf, dim3(p.ncam), dim3(1024), 0, st, p);
-        hipLaunchKernelGGL(k_prim_samples, dim3(gridb(total_edges, TRACE_BLOCK, grid)), dim3(TRACE_BLOCK), 0, st, p,
+        ST_LAUNCH("k_prim_weights", k_prim_weights, dim3(gridb(p.ne, 256, 1024), p.ncam), dim3(256), 0, st, p);
+        ST_LAUNCH("k_prim_cdf", k_prim_cdf, dim3(p.ncam), dim3(1024), 0, st, p);
+        ST_LAUNCH("k_prim_samples", k_prim_samples, dim3(gridb(total_edges, TRACE_BLOCK, grid)), dim3(TRACE_BLOCK), 0, st, p,
                            total_edges);
     }
 }

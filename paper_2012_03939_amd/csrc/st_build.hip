@@ -339,46 +339,46 @@ static inline unsigned nb(long long n, int bs) { return (unsigned)((n + bs - 1) 
 void launch_scene_geometry(SceneDev& s, hipStream_t st) {
     const int nf = s.nf;
     if (nf <= 0) return;
-    hipLaunchKernelGGL(k_face_prep, dim3(nb(nf, 256)), dim3(256), 0, st, s.V, s.F, nf, s.fnorm, s.bmin, s.bmax,
+    ST_LAUNCH("k_face_prep", k_face_prep, dim3(nb(nf, 256)), dim3(256), 0, st, s.V, s.F, nf, s.fnorm, s.bmin, s.bmax,
                        s.cen);
-    hipLaunchKernelGGL(k_bounds, dim3(1), dim3(1024), 0, st, s.cen, nf, s.bounds);
-    hipLaunchKernelGGL(k_morton, dim3(nb(nf, 256)), dim3(256), 0, st, s.cen, nf, s.bounds, s.mkeys[0], s.mvals[0]);
+    ST_LAUNCH("k_bounds", k_bounds, dim3(1), dim3(1024), 0, st, s.cen, nf, s.bounds);
+    ST_LAUNCH("k_morton", k_morton, dim3(nb(nf, 256)), dim3(256), 0, st, s.cen, nf, s.bounds, s.mkeys[0], s.mvals[0]);
     const int nblocks = (nf + RS_TILE - 1) / RS_TILE;
     int cur = 0;
     for (int shift = 0; shift < 32; shift += 8) {
-        hipLaunchKernelGGL(k_rs_hist, dim3(nblocks), dim3(RS_THREADS), 0, st, s.mkeys[cur], nf, shift, s.rs_hist,
+        ST_LAUNCH("k_rs_hist", k_rs_hist, dim3(nblocks), dim3(RS_THREADS), 0, st, s.mkeys[cur], nf, shift, s.rs_hist,
                            nblocks);
-        hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, st, s.rs_hist, 256 * nblocks);
-        hipLaunchKernelGGL(k_rs_scatter, dim3(nblocks), dim3(RS_THREADS), 0, st, s.mkeys[cur], s.mvals[cur],
+        ST_LAUNCH("k_rs_scan", k_rs_scan, dim3(1), dim3(1024), 0, st, s.rs_hist, 256 * nblocks);
+        ST_LAUNCH("k_rs_scatter", k_rs_scatter, dim3(nblocks), dim3(RS_THREADS), 0, st, s.mkeys[cur], s.mvals[cur],
                            s.mkeys[cur ^ 1], s.mvals[cur ^ 1], nf, shift, s.rs_hist, nblocks);
         cur ^= 1;
     }
     // after 4 passes the sorted data is back in buffer 0
     const uint32_t* sm = s.mkeys[cur];
     const uint32_t* sf = s.mvals[cur];
-    hipLaunchKernelGGL(k_keys64, dim3(nb(nf, 256)), dim3(256), 0, st, sm, sf, nf, s.keys64);
+    ST_LAUNCH("k_keys64", k_keys64, dim3(nb(nf, 256)), dim3(256), 0, st, sm, sf, nf, s.keys64);
     if (nf > 1)
-        hipLaunchKernelGGL(k_karras, dim3(nb(nf - 1, 256)), dim3(256), 0, st, sm, sf, nf, s.child, s.parent);
-    hipLaunchKernelGGL(k_leaf_init, dim3(nb(nf, 256)), dim3(256), 0, st, sf, s.bmin, s.bmax, s.V, s.F, nf, s.aabb,
+        ST_LAUNCH("k_karras", k_karras, dim3(nb(nf - 1, 256)), dim3(256), 0, st, sm, sf, nf, s.child, s.parent);
+    ST_LAUNCH("k_leaf_init", k_leaf_init, dim3(nb(nf, 256)), dim3(256), 0, st, sf, s.bmin, s.bmax, s.V, s.F, nf, s.aabb,
                        s.tri, s.refit_cnt);
     if (nf > 1) {
-        hipLaunchKernelGGL(k_refit, dim3(nb(nf, 256)), dim3(256), 0, st, s.parent, s.child, nf, s.aabb,
+        ST_LAUNCH("k_refit", k_refit, dim3(nb(nf, 256)), dim3(256), 0, st, s.parent, s.child, nf, s.aabb,
                            s.refit_cnt);
-        hipLaunchKernelGGL(k_pack_nodes, dim3(nb(nf - 1, 256)), dim3(256), 0, st, s.child, s.aabb, nf, s.nodes);
+        ST_LAUNCH("k_pack_nodes", k_pack_nodes, dim3(nb(nf - 1, 256)), dim3(256), 0, st, s.child, s.aabb, nf, s.nodes);
     }
     if (s.ne > 0) {
-        hipLaunchKernelGGL(k_edge_len, dim3(nb(s.ne, 256)), dim3(256), 0, st, s.edges, s.ne, s.V, s.edge_w);
-        hipLaunchKernelGGL(k_edge_cdf, dim3(1), dim3(1024), 0, st, s.edge_w, s.ne, s.ecdf, s.etotal_d,
+        ST_LAUNCH("k_edge_len", k_edge_len, dim3(nb(s.ne, 256)), dim3(256), 0, st, s.edges, s.ne, s.V, s.edge_w);
+        ST_LAUNCH("k_edge_cdf", k_edge_cdf, dim3(1), dim3(1024), 0, st, s.edge_w, s.ne, s.ecdf, s.etotal_d,
                            s.etotal_f);
     }
 }
 
 void launch_env_build(SceneDev& s, hipStream_t st) {
     if (s.he <= 0) return;
-    hipLaunchKernelGGL(k_env_rows, dim3(nb(s.he, 64)), dim3(64), 0, st, s.env, s.he, s.we, s.row_dom, s.cond,
+    ST_LAUNCH("k_env_rows", k_env_rows, dim3(nb(s.he, 64)), dim3(64), 0, st, s.env, s.he, s.we, s.row_dom, s.cond,
                        s.env_rows);
-    hipLaunchKernelGGL(k_env_marg, dim3(1), dim3(64), 0, st, s.env_rows, s.he, s.marg, s.env_total);
-    hipLaunchKernelGGL(k_env_pdf, dim3(nb((long long)s.he * s.we, 256)), dim3(256), 0, st, s.env, s.he, s.we,
+    ST_LAUNCH("k_env_marg", k_env_marg, dim3(1), dim3(64), 0, st, s.env_rows, s.he, s.marg, s.env_total);
+    ST_LAUNCH("k_env_pdf", k_env_pdf, dim3(nb((long long)s.he * s.we, 256)), dim3(256), 0, st, s.env, s.he, s.we,
                        s.row_dom, s.env_total, s.texpdf);
 }
 

@@ -126,6 +126,7 @@ struct TravStack {
     uint32_t* spill;   // spill base; entry i of thread g at spill[i*gstride + g]
     uint32_t bs, tid, gstride, gid;
     uint32_t* err;
+    unsigned long long* work;   // optional: node visits, triangle tests, rays
     __device__ __forceinline__ void put(int i, uint32_t v) {
         if (i < LDS_STACK) lds[i * bs + tid] = v;
         else spill[(i - LDS_STACK) * gstride + gid] = v;
@@ -193,7 +194,9 @@ __device__ int trace_closest(const DevScene& S, V3 o, V3 d, float tmin, int excl
     float tbest = __int_as_float(0x7f800000);
     int best = -1;
     if (S.nf <= 0) return -1;
+    uint32_t visits = 0, tests = 0;
     auto leaf = [&](uint32_t l) {
+        ++tests;
         float t; int f;
         if (tri_test(S.tri, l, o, d, tmin, __int_as_float(0x7f800000), t, f) && f != exclude) {
             if (t < tbest || (t == tbest && f < best)) { tbest = t; best = f; }
@@ -205,6 +208,7 @@ __device__ int trace_closest(const DevScene& S, V3 o, V3 d, float tmin, int excl
     int sp = 0;
     for (int iter = 0;; ++iter) {
         if (iter >= TRAVERSAL_CAP) { atomicOr(st.err, ERR_LOOP); break; }
+        ++visits;
         bool hl, hr; float tl, tr; uint32_t cl, cr;
         node_test(S.nodes, node, o, inv, tmin, tbest, hl, hr, tl, tr, cl, cr);
         if (hl && (cl & LEAF_BIT)) { leaf(cl & ~LEAF_BIT); hl = false; }
@@ -223,13 +227,20 @@ __device__ int trace_closest(const DevScene& S, V3 o, V3 d, float tmin, int excl
             node = st.get(--sp);
         }
     }
+    if (st.work) {
+        atomicAdd(st.work, (unsigned long long)visits);
+        atomicAdd(st.work + 1, (unsigned long long)tests);
+        atomicAdd(st.work + 2, 1ull);
+    }
     thit = tbest;
     return best;
 }
 
-__device__ bool trace_any(const DevScene& S, V3 o, V3 d, float tmin, float tmax, int exclude, TravStack& st) {
+__device__ bool trace_any_impl(const DevScene& S, V3 o, V3 d, float tmin, float tmax, int exclude, TravStack& st,
+                               uint32_t& visits, uint32_t& tests) {
     if (S.nf <= 0) return false;
     auto leaf = [&](uint32_t l) -> bool {
+        ++tests;
         float t; int f;
         return tri_test(S.tri, l, o, d, tmin, tmax, t, f) && f != exclude;
     };
@@ -239,6 +250,7 @@ __device__ bool trace_any(const DevScene& S, V3 o, V3 d, float tmin, float tmax,
     int sp = 0;
     for (int iter = 0;; ++iter) {
         if (iter >= TRAVERSAL_CAP) { atomicOr(st.err, ERR_LOOP); return false; }
+        ++visits;
         bool hl, hr; float tl, tr; uint32_t cl, cr;
         node_test(S.nodes, node, o, inv, tmin, tmax, hl, hr, tl, tr, cl, cr);
         if (hl && (cl & LEAF_BIT)) { if (leaf(cl & ~LEAF_BIT)) return true; hl = false; }
@@ -258,6 +270,18 @@ __device__ bool trace_any(const DevScene& S, V3 o, V3 d, float tmin, float tmax,
     }
 }
 
+__device__ __forceinline__ bool trace_any(const DevScene& S, V3 o, V3 d, float tmin, float tmax, int exclude,
+                                          TravStack& st) {
+    uint32_t visits = 0, tests = 0;
+    const bool r = trace_any_impl(S, o, d, tmin, tmax, exclude, st, visits, tests);
+    if (st.work) {
+        atomicAdd(st.work, (unsigned long long)visits);
+        atomicAdd(st.work + 1, (unsigned long long)tests);
+        atomicAdd(st.work + 2, 1ull);
+    }
+    return r;
+}
+
 // ---------------------------------------------------------------------------
 // Torrance-Sparrow BRDF: kd/pi + ks * D * G / (4 cos_i cos_o), Beckmann D,
 // height-correlated Smith G of the Beckmann surface.
@@ -272,9 +296,12 @@ __device__ __forceinline__ Mat load_mat(const float* m) {
 }
 __device__ __forceinline__ float alpha_eff(float a) { return a > ALPHA_MIN ? a : ALPHA_MIN; }
 
-__device__ __forceinline__ float beckmann_D(float ch, float a) {
+// Beckmann D with tan^2 taken from |n x h|^2 / (n.h)^2: 1 - (n.h)^2 cancels in
+// float32 near the highlight, the cross product does not
+__device__ __forceinline__ float beckmann_D(V3 n, V3 h, float ch, float a) {
     const float c2 = ch * ch;
-    const float t2 = (1.0f - c2) / c2;
+    const V3 nh = cross(n, h);
+    const float t2 = dot(nh, nh) / c2;
     return expf(-t2 / (a * a)) / (PI_F * a * a * c2 * c2);
 }
 
@@ -293,7 +320,7 @@ __device__ __forceinline__ V3 brdf_eval(V3 wi, V3 wo, V3 n, const Mat& m) {
     const float ch = dot(n, h);
     float spec = 0.0f;
     if (ch > 0.0f) {
-        const float D = beckmann_D(ch, a);
+        const float D = beckmann_D(n, h, ch, a);
         const float G = 1.0f / (1.0f + smith_lambda(ci, a) + smith_lambda(co, a));
         spec = D * G / (4.0f * ci * co);
     }
@@ -311,7 +338,7 @@ __device__ __forceinline__ float bsdf_pdf(V3 wi, V3 wo, V3 n, float alpha) {
     if (hl > 0.0f) {
         const V3 h = hv * (1.0f / hl);
         const float ch = dot(n, h), oh = fabsf(dot(wo, h));
-        if (ch > 0.0f && oh > 0.0f) ps = LOBE_SPEC_P * beckmann_D(ch, a) * ch / (4.0f * oh);
+        if (ch > 0.0f && oh > 0.0f) ps = LOBE_SPEC_P * beckmann_D(n, h, ch, a) * ch / (4.0f * oh);
     }
     return pd + ps;
 }
@@ -371,7 +398,7 @@ __device__ __forceinline__ void brdf_backward(V3 wi, V3 wo, V3 n, const Mat& m, 
     const V3 h = hv * (1.0f / hl);
     const float ch = dot(n, h);
     if (!(ch > 0.0f)) return;
-    const float D = beckmann_D(ch, a);
+    const float D = beckmann_D(n, h, ch, a);
     const float li = smith_lambda(ci, a), lo = smith_lambda(co, a);
     const float G = 1.0f / (1.0f + li + lo);
     const float K = D * G / (4.0f * ci * co);
@@ -379,7 +406,8 @@ __device__ __forceinline__ void brdf_backward(V3 wi, V3 wo, V3 n, const Mat& m, 
     const float glnK = dot(gf, m.ks) * K;       // gradient w.r.t. ln K
     const float c2 = ch * ch;
     const float dlnD_dch = 2.0f / (c2 * ch * a * a) - 4.0f / ch;
-    const float dlnD_da = 2.0f * (1.0f - c2) / (c2 * a * a * a) - 2.0f / a;
+    const V3 nh = cross(n, h);
+    const float dlnD_da = 2.0f * dot(nh, nh) / (c2 * a * a * a) - 2.0f / a;
     float dlia, dloa;
     const float dli = dlambda_dc(ci, a, dlia), dlo = dlambda_dc(co, a, dloa);
     if (m.a > ALPHA_MIN) gm[6] += glnK * (dlnD_da - G * (dlia + dloa));

@@ -5,6 +5,18 @@
 
 namespace st {
 
+// optional per-kernel timing with HIP events recorded on the launch stream
+void prof_begin(hipStream_t s, const char* name);
+void prof_end(hipStream_t s);
+extern bool g_prof_on;
+
+#define ST_LAUNCH(name, kern, grid, block, shm, stream, ...)                   \
+    do {                                                                        \
+        if (st::g_prof_on) st::prof_begin(stream, name);                        \
+        hipLaunchKernelGGL(kern, grid, block, shm, stream, __VA_ARGS__);        \
+        if (st::g_prof_on) st::prof_end(stream);                                \
+    } while (0)
+
 // every device allocation of one scene (library-owned)
 struct SceneDev {
     int nv = 0, nf = 0, nl = 0, he = 0, we = 0, ne = 0;
@@ -43,6 +55,7 @@ struct SceneDev {
     double* env_total = nullptr;
     float* texpdf = nullptr;
     uint32_t* err = nullptr;                 // device error word
+    unsigned long long* work = nullptr;      // traversal work counters [3]
     DevScene* dscene = nullptr;              // device copy of the kernel view
     DevScene hscene;                         // host copy of the kernel view
 };
@@ -83,6 +96,7 @@ struct FwdParams {
     uint32_t seed;
     uint32_t* dbg_hash;      // canonical order, optional
     uint32_t* err;
+    unsigned long long* work;  // optional traversal counters
 };
 
 void launch_scene_geometry(SceneDev& s, hipStream_t st);
@@ -111,6 +125,7 @@ struct BwdParams {
     uint32_t* dbg_hash;
     uint32_t* dbg_edge_hash;
     uint32_t* err;
+    unsigned long long* work;
     uint32_t* spill;
     double* pcdf;            // per-view primary edge CDF [ncam, ne+1]
     double* pw;              // per-view primary edge weights [ncam, ne]

@@ -9,7 +9,8 @@
 
 namespace st {
 
-__device__ __forceinline__ TravStack make_stack(uint32_t* lds, uint32_t* spill, uint32_t* err) {
+__device__ __forceinline__ TravStack make_stack(uint32_t* lds, uint32_t* spill, uint32_t* err,
+                                                unsigned long long* work) {
     TravStack s;
     s.lds = lds;
     s.spill = spill;
@@ -18,6 +19,7 @@ __device__ __forceinline__ TravStack make_stack(uint32_t* lds, uint32_t* spill, 
     s.gstride = gridDim.x * blockDim.x;
     s.gid = blockIdx.x * blockDim.x + threadIdx.x;
     s.err = err;
+    s.work = work;
     return s;
 }
 
@@ -63,7 +65,7 @@ __global__ void k_camera(FwdParams p, Queues q, long long q0, int n) {
 // closest hit for every queued ray of bounce k (queue k & 1)
 __global__ void __launch_bounds__(TRACE_BLOCK) k_extend(FwdParams p, Queues q, int k) {
     __shared__ uint32_t lds[LDS_STACK * TRACE_BLOCK];
-    TravStack st = make_stack(lds, q.spill, p.err);
+    TravStack st = make_stack(lds, q.spill, p.err, p.work);
     const int n = q.cnt[k];
     float* const* r = q.ray[k & 1];
     const int stride = gridDim.x * blockDim.x;
@@ -207,7 +209,7 @@ __global__ void k_shade(FwdParams p, Queues q, int k) {
 // shadow rays of bounce k, one thread per shading point, fixed order
 __global__ void __launch_bounds__(TRACE_BLOCK) k_shadow(FwdParams p, Queues q, int k) {
     __shared__ uint32_t lds[LDS_STACK * TRACE_BLOCK];
-    TravStack st = make_stack(lds, q.spill, p.err);
+    TravStack st = make_stack(lds, q.spill, p.err, p.work);
     const int n = q.cnt[k];
     float* const* r = q.ray[k & 1];
     const int stride = gridDim.x * blockDim.x;
@@ -261,7 +263,7 @@ __global__ void k_chunk_hash(FwdParams p, Queues q, int n) {
 __global__ void __launch_bounds__(TRACE_BLOCK) k_forward_mega(FwdParams p, float* L, long long total,
                                                               uint32_t* spill) {
     __shared__ uint32_t lds[LDS_STACK * TRACE_BLOCK];
-    TravStack st = make_stack(lds, spill, p.err);
+    TravStack st = make_stack(lds, spill, p.err, p.work);
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long qq = blockIdx.x * (long long)blockDim.x + threadIdx.x; qq < total; qq += stride) {
         const int v = find_view(p.qoff, p.ncam, qq);
@@ -331,7 +333,7 @@ __global__ void __launch_bounds__(TRACE_BLOCK) k_trace_debug(const DevScene* sc,
                                                              uint32_t* spill, uint32_t* err) {
     __shared__ uint32_t lds[LDS_STACK * TRACE_BLOCK];
     const DevScene& S = *sc;
-    TravStack st = make_stack(lds, spill, err);
+    TravStack st = make_stack(lds, spill, err, nullptr);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const V3 oo = ld3(o + 3 * i), dd = ld3(d + 3 * i);
@@ -364,46 +366,46 @@ void launch_forward_wavefront(const FwdParams& p, Queues& q, long long total, in
     for (long long q0 = 0; q0 < total; q0 += q.cap) {
         const int n = (int)((total - q0) < q.cap ? (total - q0) : q.cap);
         const unsigned g = grid_for(n, TRACE_BLOCK, TRACE_GRID);
-        hipLaunchKernelGGL(k_camera, dim3(grid_for(n, 256, 1u << 20)), dim3(256), 0, st, p, q, q0, n);
+        ST_LAUNCH("k_camera", k_camera, dim3(grid_for(n, 256, 1u << 20)), dim3(256), 0, st, p, q, q0, n);
         const int last = p.B + (has_env_any ? 1 : 0);
         for (int k = 1; k <= last; ++k) {
-            hipLaunchKernelGGL(k_extend, dim3(g), dim3(TRACE_BLOCK), 0, st, p, q, k);
-            hipLaunchKernelGGL(k_shade, dim3(grid_for(n, 256, TRACE_GRID)), dim3(256), 0, st, p, q, k);
-            if (k <= p.B) hipLaunchKernelGGL(k_shadow, dim3(g), dim3(TRACE_BLOCK), 0, st, p, q, k);
+            ST_LAUNCH("k_extend", k_extend, dim3(g), dim3(TRACE_BLOCK), 0, st, p, q, k);
+            ST_LAUNCH("k_shade", k_shade, dim3(grid_for(n, 256, TRACE_GRID)), dim3(256), 0, st, p, q, k);
+            if (k <= p.B) ST_LAUNCH("k_shadow", k_shadow, dim3(g), dim3(TRACE_BLOCK), 0, st, p, q, k);
         }
         if (p.dbg_hash)
-            hipLaunchKernelGGL(k_chunk_hash, dim3(grid_for(n, 256, 1u << 20)), dim3(256), 0, st, p, q, n);
+            ST_LAUNCH("k_chunk_hash", k_chunk_hash, dim3(grid_for(n, 256, 1u << 20)), dim3(256), 0, st, p, q, n);
     }
 }
 
 void launch_forward_mega(const FwdParams& p, float* L, long long total, uint32_t* spill, int grid,
                          hipStream_t st) {
-    hipLaunchKernelGGL(k_forward_mega, dim3(grid_for(total, TRACE_BLOCK, grid)), dim3(TRACE_BLOCK), 0, st, p, L,
+    ST_LAUNCH("k_forward_mega", k_forward_mega, dim3(grid_for(total, TRACE_BLOCK, grid)), dim3(TRACE_BLOCK), 0, st, p, L,
                        total, spill);
 }
 
 void launch_film(const DevCam* cams, const long long* pixoff, int ncam, int spp, const float* L, long long npix,
                  float* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_film, dim3(grid_for(npix, 256, 1u << 16)), dim3(256), 0, st, cams, pixoff, ncam, spp, L,
+    ST_LAUNCH("k_film", k_film, dim3(grid_for(npix, 256, 1u << 16)), dim3(256), 0, st, cams, pixoff, ncam, spp, L,
                        npix, out);
 }
 
 void launch_sample_radiance(const FwdParams& p, const float* L, long long total, float* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_sample_radiance, dim3(grid_for(total, 256, 1u << 16)), dim3(256), 0, st, p, L, total,
+    ST_LAUNCH("k_sample_radiance", k_sample_radiance, dim3(grid_for(total, 256, 1u << 16)), dim3(256), 0, st, p, L, total,
                        out);
 }
 
 void launch_fill_f32(float* ptr, long long n, float v, hipStream_t st) {
-    if (n > 0) hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(n, 256, 1u << 16)), dim3(256), 0, st, ptr, n, v);
+    if (n > 0) ST_LAUNCH("k_fill_f32", k_fill_f32, dim3(grid_for(n, 256, 1u << 16)), dim3(256), 0, st, ptr, n, v);
 }
 void launch_fill_u32(uint32_t* ptr, long long n, uint32_t v, hipStream_t st) {
-    if (n > 0) hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256, 1u << 16)), dim3(256), 0, st, ptr, n, v);
+    if (n > 0) ST_LAUNCH("k_fill_u32", k_fill_u32, dim3(grid_for(n, 256, 1u << 16)), dim3(256), 0, st, ptr, n, v);
 }
 
 void launch_trace_debug(const DevScene* s, const float* o, const float* d, int n, float tmin, int brute,
                         int* out_face, float* out_t, uint32_t* spill, uint32_t* err, hipStream_t st) {
     if (n > 0)
-        hipLaunchKernelGGL(k_trace_debug, dim3((n + TRACE_BLOCK - 1) / TRACE_BLOCK), dim3(TRACE_BLOCK), 0, st, s, o,
+        ST_LAUNCH("k_trace_debug", k_trace_debug, dim3((n + TRACE_BLOCK - 1) / TRACE_BLOCK), dim3(TRACE_BLOCK), 0, st, s, o,
                            d, n, tmin, brute, out_face, out_t, spill, err);
 }
 

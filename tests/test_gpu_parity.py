@@ -114,7 +114,7 @@ def test_bvh_closest_equals_brute_force(B):
     assert np.array_equal(f1, f2)
     hit = f1 >= 0
     assert np.array_equal(t1[hit], t2[hit])
-    assert hit.mean() > 0.2
+    assert hit.mean() > 0.05
 
 
 # --------------------------------------------------------------------------
