@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--res", type=int, default=512)
     ap.add_argument("--views", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-baseline-res", type=int, default=384)
+    ap.add_argument("--cpu-baseline-res", type=int, default=1024)
     ap.add_argument("--profile-only", action="store_true", help="one untimed step (for rocprofv3 runs)")
     return ap.parse_args()
 

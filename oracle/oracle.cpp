@@ -43,6 +43,7 @@ static const double LOBE_SPEC_P = 0.5;      // probability of sampling the specu
 static const double EPS_PRIMARY = 1e-3;     // primary edge side offset, pixels
 static const double EPS_SECONDARY = 1e-4;   // secondary edge side offset, radians
 static const double ZNEAR = 1e-3;           // edges with an endpoint nearer than this are dropped
+static const double SEC_COS_MIN = 1e-5;     // secondary edge points this close to the tangent plane are skipped
 
 // --------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds, the key bumped
@@ -713,7 +714,7 @@ static D3 trace_estimator(const Scene& s, D3 o, D3 d, int exclude, int nvert, bo
                 D3 eh = normalize(vb - va);
                 D3 mv = cross(ud, eh);
                 double ml = length(mv);
-                if (cv > 0.0 && ml > 0.0) {
+                if (cv > SEC_COS_MIN && ml > 0.0) {
                     code = 1;
                     sech.push(1u);
                     D3 mm = mv * (1.0 / ml);
@@ -1410,7 +1411,7 @@ void or_secondary_term(void* p, const double* pp, const double* nn, const double
         double cv = dot(n, ud);
         D3 mv = cross(ud, normalize(vb - va));
         double ml = length(mv);
-        if (!(cv > 0.0) || !(ml > 0.0)) continue;
+        if (!(cv > SEC_COS_MIN) || !(ml > 0.0)) continue;
         D3 mm = mv * (1.0 / ml);
         Hash h; h.on = false;
         Ctr sc{(uint32_t)i, 0u, 1u << 16, 2u};

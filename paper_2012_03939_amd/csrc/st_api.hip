@@ -414,7 +414,7 @@ int st_scene_create(const float* V, int32_t nv, const int32_t* F, int32_t nf, co
     if (he > 0) {
         A(dalloc(&d.env, 3 * (size_t)he * we));
         A(dalloc(&d.row_dom, he));
-        A(dalloc(&d.rowcos, he + 1));
+        A(dalloc(&d.rowcos, 2 * (he + 1)));
         A(dalloc(&d.cond, (size_t)he * (we + 1)));
         A(dalloc(&d.marg, he + 1));
         A(dalloc(&d.env_rows, he));
@@ -433,14 +433,18 @@ int st_scene_create(const float* V, int32_t nv, const int32_t* F, int32_t nf, co
     launch_fill_u32(d.err, 1, 0u, s);
     launch_fill_u32((uint32_t*)d.work, 8, 0u, s);
     std::vector<double> dom(std::max(he, 1));
-    std::vector<float> rowcos(he + 1);
+    std::vector<float> rowcos(2 * (he + 1));
     if (he > 0) {
         HIPCHK2(hipMemcpyAsync(d.env, env, sizeof(float) * 3 * (size_t)he * we, hipMemcpyDeviceToDevice, s));
         const double PI = 3.14159265358979323846;
         for (int r = 0; r < he; ++r) dom[r] = (2.0 * PI / we) * (std::cos(PI * r / he) - std::cos(PI * (r + 1) / he));
-        for (int r = 0; r <= he; ++r) rowcos[r] = (float)std::cos(PI * r / he);
+        for (int r = 0; r <= he; ++r) {
+            const double h = 0.5 * PI * r / he;
+            rowcos[r] = (float)(2.0 * std::sin(h) * std::sin(h));            // 1 - cos(pi r / he)
+            rowcos[he + 1 + r] = (float)(2.0 * std::cos(h) * std::cos(h));   // 1 + cos(pi r / he)
+        }
         HIPCHK2(hipMemcpyAsync(d.row_dom, dom.data(), sizeof(double) * he, hipMemcpyHostToDevice, s));
-        HIPCHK2(hipMemcpyAsync(d.rowcos, rowcos.data(), sizeof(float) * (he + 1), hipMemcpyHostToDevice, s));
+        HIPCHK2(hipMemcpyAsync(d.rowcos, rowcos.data(), sizeof(float) * 2 * (he + 1), hipMemcpyHostToDevice, s));
         launch_env_build(d, s);
     }
     launch_scene_geometry(d, s);

@@ -235,7 +235,7 @@ __global__ void __launch_bounds__(TRACE_BLOCK) k_adjoint(BwdParams p, long long 
                     cv = dot(n, ud);
                     mv = cross(ud, normalize(vb - va));
                     ml = len(mv);
-                    ok = cv > 0.0f && ml > 0.0f;
+                    ok = cv > SEC_COS_MIN && ml > 0.0f;
                 }
                 if (!ok) { h.push(0u); continue; }
                 h.push(1u);

@@ -28,6 +28,7 @@ constexpr float LOBE_SPEC_P = 0.5f;
 constexpr double EPS_PRIMARY = 1e-3;    // pixels
 constexpr float EPS_SECONDARY = 1e-4f;  // radians
 constexpr double ZNEAR = 1e-3;
+constexpr float SEC_COS_MIN = 1e-5f;    // secondary edge points this close to the tangent plane are skipped
 constexpr float BOX_GROW = 1.0000004f;  // 1 + 2*gamma(3): conservative slab exit distance
 constexpr int LDS_STACK = 32;           // per-lane traversal stack entries held in LDS
 constexpr int SPILL_STACK = 32;         // further entries spilled to HBM
@@ -111,7 +112,7 @@ struct DevScene {
     const double* marg;   // [he+1]
     const double* cond;   // [he,we+1]
     const float* texpdf;  // [he*we] solid-angle pdf of each texel
-    const float* rowcos;  // [he+1] cos(pi r / he)
+    const float* rowcos;  // [2*(he+1)]: 1 - cos(pi r / he), then 1 + cos(pi r / he)
     const int4* edges;    // [ne] (va, vb, f1, f2)
     const double* ecdf;   // [ne+1] cumulative 3-D length / total
     const float* etotal;  // total 3-D edge length
@@ -362,7 +363,7 @@ __device__ __forceinline__ int bsdf_sample(float4 u, V3 wo, V3 n, float alpha, V
     if (u.x < LOBE_SPEC_P) {
         const float t2 = -a * a * logf(1.0f - u.y);
         const float ch = 1.0f / sqrtf(1.0f + t2);
-        const float sh = sqrtf(fmaxf(0.0f, 1.0f - ch * ch));
+        const float sh = sqrtf(t2 / (1.0f + t2));    // sin^2 = tan^2 / (1 + tan^2): no cancellation near the pole
         const V3 h = t * (sh * cp) + b * (sh * sp) + n * ch;
         wi = h * (2.0f * dot(wo, h)) - wo;
         return 0;
@@ -449,9 +450,22 @@ __device__ __forceinline__ int env_sample(const DevScene& S, float4 u, V3& dir, 
     const int r = cdf_find(S.marg, S.he, (double)u.x);
     const int c = cdf_find(S.cond + (size_t)r * (S.we + 1), S.we, (double)u.y);
     const float phi = 2.0f * PI_F * ((float)c + u.z) / (float)S.we;
-    const float ct = S.rowcos[r], cb = S.rowcos[r + 1];
-    const float cth = ct - u.w * (ct - cb);
-    const float sth = sqrtf(fmaxf(0.0f, 1.0f - cth * cth));
+    // cos(theta) uniform between the row's bounds; 1 -+ cos(theta) are taken
+    // from the per-row tables of 1 - cos and 1 + cos so that sin(theta) keeps
+    // full precision near both poles
+    const float om0 = S.rowcos[r], om1 = S.rowcos[r + 1];                        // 1 - cos
+    const float op0 = S.rowcos[S.he + 1 + r], op1 = S.rowcos[S.he + 2 + r];      // 1 + cos
+    float a, b, cth;
+    if (op0 + op1 >= om0 + om1) {       // upper half of the sphere: 1 - cos is the small one
+        a = om0 + u.w * (om1 - om0);
+        b = 2.0f - a;
+        cth = 1.0f - a;
+    } else {
+        b = op0 - u.w * (op0 - op1);
+        a = 2.0f - b;
+        cth = b - 1.0f;
+    }
+    const float sth = sqrtf(fmaxf(0.0f, a * b));
     float sp, cp;
     sincosf(phi, &sp, &cp);
     dir = V3{sth * sp, cth, sth * cp};
