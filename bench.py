@@ -127,23 +127,16 @@ def main():
     ms_per_step = ms / args.steps
     value = n_paths * args.steps / (ms / 1e3)
 
-    # dominant kernel and its algorithmic work, counted in a separate (untimed) pass
-    dom = max(prof.items(), key=lambda kv: kv[1][0])
-    dom_name, (dom_ms, dom_n) = dom[0], dom[1]
+    # dominant kernel and its algorithmic work, counted on device in one extra (untimed) step
+    dom_name, (dom_ms, dom_n) = max(prof.items(), key=lambda kv: kv[1][0])
     g.read_work()
-    if dom_name.startswith("k_adjoint"):
-        g.backward(cams, spp, bounces, (img - target) * scale, seed=100, flags=B.ST_GRAD_INTERIOR | B.ST_EDGE_SECONDARY
-                   | B.ST_COUNT_WORK, dV=dV, dmat=dM)
-    elif dom_name.startswith("k_prim"):
-        g.backward(cams, spp, bounces, (img - target) * scale, seed=100, flags=B.ST_EDGE_PRIMARY | B.ST_COUNT_WORK,
-                   dV=dV, dmat=dM)
-    else:
-        g.render(cams, spp, bounces, seed=100, out=img, flags=B.ST_COUNT_WORK)
-    visits, tests, rays = g.read_work()
-    if dom_name in ("k_extend", "k_shadow"):
-        # the render pass counted both traversal kernels; split by their launch time share
-        share = prof[dom_name][0] / (prof.get("k_extend", (0, 0))[0] + prof.get("k_shadow", (0, 0))[0])
-        visits, tests, rays = visits * share, tests * share, rays * share
+    g.update(V=Vs[0])
+    g.render(cams, spp, bounces, seed=100, out=img, flags=B.ST_COUNT_WORK)
+    g.backward(cams, spp, bounces, (img - target) * scale, seed=100, flags=B.ST_ALL_GRADS | B.ST_COUNT_WORK,
+               dV=dV, dmat=dM)
+    work = g.read_work()
+    wkey = dom_name.split("<")[0]
+    visits, tests, rays = work.get(wkey, (0, 0, 0))
     launches_per_step = dom_n / args.steps
     flops_per_launch = (visits * FLOPS_PER_VISIT + tests * FLOPS_PER_TEST) / max(launches_per_step, 1)
     avg_ms = dom_ms / dom_n

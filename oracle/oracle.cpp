@@ -1015,8 +1015,13 @@ static void primary_edge_sample(const Scene& s, const Cam& c, const EdgeView& ev
     double nx = -dy / l, ny = dx / l;
     D3 dm = cam_dir(c, xs - EPS_PRIMARY * nx, ys - EPS_PRIMARY * ny);
     D3 dp = cam_dir(c, xs + EPS_PRIMARY * nx, ys + EPS_PRIMARY * ny);
-    D3 Lm = trace_estimator(s, c.eye, dm, -1, bounces, false, ctr, key, h, nullptr, nullptr);
-    D3 Lp = trace_estimator(s, c.eye, dp, -1, bounces, false, ctr, key, h, nullptr, nullptr);
+    // each side path hashes its own decisions; the sample hash takes both results
+    Hash hm, hp;
+    hm.on = hp.on = h.on;
+    D3 Lm = trace_estimator(s, c.eye, dm, -1, bounces, false, ctr, key, hm, nullptr, nullptr);
+    D3 Lp = trace_estimator(s, c.eye, dp, -1, bounces, false, ctr, key, hp, nullptr, nullptr);
+    h.push(hm.h);
+    h.push(hp.h);
     double cc = 0.0;
     for (int ch = 0; ch < 3; ++ch) cc += (double)dimg[ch] * (Lm[ch] - Lp[ch]);
     cc *= ev.total / (double)ne;

@@ -14,7 +14,8 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libshapetrace.so")
+# SHAPETRACE_LIB selects another build of the same library (tuning variants)
+LIB_PATH = os.environ.get("SHAPETRACE_LIB", os.path.join(_HERE, "libshapetrace.so"))
 
 ST_GRAD_INTERIOR = 1
 ST_EDGE_PRIMARY = 2
@@ -203,11 +204,13 @@ class GPUScene:
     def check_errors(self):
         _check(load().st_check_errors(self.h, _stream()))
 
+    WORK_KERNELS = ("k_extend", "k_shadow", "k_adjoint", "k_forward_mega")
+
     def read_work(self):
-        """(node visits, triangle tests, rays) counted by ST_COUNT_WORK calls since the last read."""
-        out = (ctypes.c_uint64 * 3)()
+        """{kernel: (node visits, triangle tests, rays)} counted by ST_COUNT_WORK calls since the last read."""
+        out = (ctypes.c_uint64 * 12)()
         _check(load().st_read_work(self.h, out, _stream()))
-        return int(out[0]), int(out[1]), int(out[2])
+        return {k: (int(out[3 * i]), int(out[3 * i + 1]), int(out[3 * i + 2])) for i, k in enumerate(self.WORK_KERNELS)}
 
     def edges(self):
         import torch

@@ -129,7 +129,7 @@ void st::prof_end(hipStream_t s) {
 
 struct st_scene {
     SceneDev d;
-    GrowBuf camsbuf, Lbuf, qbuf, spillbuf, primbuf, scenesbuf;
+    GrowBuf camsbuf, Lbuf, qbuf, spillbuf, primbuf, scenesbuf, sidebuf, sidehash;
     void* pinned = nullptr;
     size_t pinned_cap = 0;
     hipEvent_t staged = nullptr;
@@ -217,7 +217,7 @@ int ensure_spill(st_scene* sc) {
 int make_queues(st_scene* sc, int cap, int nent, float* L, Queues& q) {
     const size_t per = 256;
     size_t bytes = 0;
-    bytes += (size_t)cap * 4 * (2 * 9 + 3 + 3 + 1 + 2 + 3 + 3 + 7 * std::max(nent, 1)) + 40 * per + 64 * 4;
+    bytes += (size_t)cap * 4 * (2 * 9 + 4 + 3 + 1 + 2 + 3 + 3 + 7 * std::max(nent, 1)) + 40 * per + 64 * 4;
     int rc = sc->qbuf.ensure(bytes);
     if (rc) return rc;
     Carver c{(char*)sc->qbuf.p};
@@ -226,6 +226,7 @@ int make_queues(st_scene* sc, int cap, int nent, float* L, Queues& q) {
     q.pq = c.take<uint32_t>(cap);
     q.pc0 = c.take<uint32_t>(cap);
     q.pc1 = c.take<uint32_t>(cap);
+    q.pdom = c.take<uint32_t>(cap);
     for (int i = 0; i < 3; ++i) q.pbeta[i] = c.take<float>(cap);
     q.phash = c.take<uint32_t>(cap);
     q.ht = c.take<float>(cap);
@@ -281,6 +282,7 @@ int render_impl(st_scene* owner, st_scene* const* scenes, int nscenes, const st_
     p.dbg_hash = o.debug_decision_hash;
     p.err = owner->d.err;
     p.work = (o.flags & ST_COUNT_WORK) ? owner->d.work : nullptr;
+    p.hash_by_q = nullptr;
     float* L = (float*)owner->Lbuf.p;
     if (o.flags & ST_FORWARD_MEGAKERNEL) {
         launch_forward_mega(p, L, cs.total_paths, (uint32_t*)owner->spillbuf.p, TRACE_GRID, s);
@@ -409,7 +411,7 @@ int st_scene_create(const float* V, int32_t nv, const int32_t* F, int32_t nf, co
     A(dalloc(&d.etotal_d, 1));
     A(dalloc(&d.etotal_f, 1));
     A(dalloc(&d.err, 1));
-    A(dalloc(&d.work, 4));
+    A(dalloc(&d.work, 3 * WORK_SLOTS));
     A(dalloc(&d.dscene, 1));
     if (he > 0) {
         A(dalloc(&d.env, 3 * (size_t)he * we));
@@ -431,7 +433,7 @@ int st_scene_create(const float* V, int32_t nv, const int32_t* F, int32_t nf, co
     if (!edges.empty())
         HIPCHK2(hipMemcpyAsync(d.edges, edges.data(), sizeof(int4) * edges.size(), hipMemcpyHostToDevice, s));
     launch_fill_u32(d.err, 1, 0u, s);
-    launch_fill_u32((uint32_t*)d.work, 8, 0u, s);
+    launch_fill_u32((uint32_t*)d.work, 6 * WORK_SLOTS, 0u, s);
     std::vector<double> dom(std::max(he, 1));
     std::vector<float> rowcos(2 * (he + 1));
     if (he > 0) {
@@ -542,6 +544,38 @@ int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_
     if (o.debug_decision_hash) launch_fill_u32(o.debug_decision_hash, cs.total_paths, 0u, s);
     if (o.debug_edge_hash) launch_fill_u32(o.debug_edge_hash, cs.total_edges, 0u, s);
     launch_backward(p, cs.total_paths, cs.total_edges, TRACE_GRID, s);
+    if ((p.flags & ST_EDGE_PRIMARY) && cs.total_edges > 0 && ne > 0) {
+        // side paths of the primary edge samples run through the wavefront kernels
+        if (2 * cs.total_edges >= (1ll << 32)) return fail(ST_ERR_INVALID_ARG, "too many primary edge samples");
+        rc = sc->sidebuf.ensure((size_t)cs.total_edges * 6 * sizeof(float));
+        if (rc) return rc;
+        uint32_t* hside = nullptr;
+        if (o.debug_edge_hash) {
+            rc = sc->sidehash.ensure((size_t)cs.total_edges * 2 * sizeof(uint32_t));
+            if (rc) return rc;
+            hside = (uint32_t*)sc->sidehash.p;
+        }
+        long long cap = o.queue_capacity > 0 ? o.queue_capacity : (1ll << 22);
+        cap = std::min<long long>(cap, std::max<long long>(2 * cs.total_edges, 2));
+        cap = std::min<long long>(cap, 1ll << 28) & ~1ll;
+        const int nent = sc->d.nl + (sc->d.has_env ? 1 : 0);
+        Queues q;
+        rc = make_queues(sc, (int)cap, nent, (float*)sc->sidebuf.p, q);
+        if (rc) return rc;
+        FwdParams fp;
+        fp.scenes = sc->d.dscene;
+        fp.cams = cs.cams;
+        fp.qoff = cs.qoff;
+        fp.ncam = ncam;
+        fp.spp = spp;
+        fp.B = bounces;
+        fp.seed = seed;
+        fp.dbg_hash = nullptr;
+        fp.err = sc->d.err;
+        fp.work = p.work;
+        fp.hash_by_q = hside;
+        launch_primary_edges(p, fp, q, (float*)sc->sidebuf.p, hside, cs.total_edges, sc->d.has_env ? 1 : 0, s);
+    }
     HIPCHK(hipGetLastError());
     return ST_OK;
 }
@@ -564,9 +598,9 @@ int st_read_work(st_scene* sc, uint64_t* out3, hipStream_t s) {
     int rc = check_scene(sc);
     if (rc) return rc;
     if (!out3) return fail(ST_ERR_INVALID_ARG, "out is NULL");
-    HIPCHK(hipMemcpyAsync(out3, sc->d.work, 3 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(out3, sc->d.work, 3 * WORK_SLOTS * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    launch_fill_u32((uint32_t*)sc->d.work, 8, 0u, s);
+    launch_fill_u32((uint32_t*)sc->d.work, 6 * WORK_SLOTS, 0u, s);
     HIPCHK(hipStreamSynchronize(s));
     return ST_OK;
 }
@@ -625,6 +659,7 @@ void st_scene_destroy(st_scene* sc) {
     for (void* p : ptrs)
         if (p) hipFree(p);
     sc->camsbuf.release(); sc->Lbuf.release(); sc->qbuf.release(); sc->spillbuf.release(); sc->primbuf.release();
+    sc->sidebuf.release(); sc->sidehash.release();
     sc->scenesbuf.release();
     if (sc->pinned) hipHostFree(sc->pinned);
     if (sc->staged) hipEventDestroy(sc->staged);

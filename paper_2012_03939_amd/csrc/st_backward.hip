@@ -89,7 +89,7 @@ constexpr uint32_t R_FLIP = 1u, R_ENV = 2u, R_CONT = 4u, R_ESC = 8u, R_SEC = 16u
 template <int BM>
 __global__ void __launch_bounds__(TRACE_BLOCK) k_adjoint(BwdParams p, long long total) {
     __shared__ uint32_t lds[LDS_STACK * TRACE_BLOCK];
-    TravStack st = make_stack_b(lds, p.spill, p.err, p.work);
+    TravStack st = make_stack_b(lds, p.spill, p.err, p.work ? p.work + 3 * WORK_ADJOINT : nullptr);
     const bool want_interior = p.flags & 1u, want_secondary = p.flags & 4u;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long qq = blockIdx.x * (long long)blockDim.x + threadIdx.x; qq < total; qq += stride) {
@@ -404,61 +404,131 @@ __global__ void k_prim_cdf(BwdParams p) {
     block_scan_normalise(p.pw + (size_t)v * p.ne, S.ne, p.pcdf + (size_t)v * (p.ne + 1), p.ptotal + v);
 }
 
-__global__ void __launch_bounds__(TRACE_BLOCK) k_prim_samples(BwdParams p, long long total) {
-    __shared__ uint32_t lds[LDS_STACK * TRACE_BLOCK];
-    TravStack st = make_stack_b(lds, p.spill, p.err, p.work);
+// ---------------------------------------------------------------------------
+// primary edges through the wavefront: set-up of one edge sample, emission of
+// its two side camera rays, and the gradient once their radiance is known
+// ---------------------------------------------------------------------------
+struct EdgeSample {
+    int v, e, px, py;
+    long long si;
+    double t, xs, ys, nx, ny;
+    bool inside;
+};
+
+// false when the sample is masked or its view has no candidate edge
+__device__ __forceinline__ bool edge_setup(const BwdParams& p, long long ge, EdgeSample& es) {
+    if (p.edge_mask && !p.edge_mask[ge]) return false;
+    es.v = find_view(p.eoff, p.ncam, ge);
+    const DevCam& c = p.cams[es.v];
+    const DevScene& S = p.scenes[c.scene];
+    if (!(p.ptotal[es.v] > 0.0)) return false;
+    es.si = ge - c.eoff;
+    const Ctr ctr{(uint32_t)es.si, (uint32_t)es.v << 16, 0u, 1u};
+    const float4 u = draw4(ctr, 0, 3, Key{p.seed, S.scene_id});
+    es.e = cdf_find(p.pcdf + (size_t)es.v * (p.ne + 1), S.ne, (double)u.x);
+    es.t = u.y;
+    const int4 E = S.edges[es.e];
+    double ax, ay, az, bx, by, bz;
+    project_d(c, S.V[3 * E.x], S.V[3 * E.x + 1], S.V[3 * E.x + 2], ax, ay, az);
+    project_d(c, S.V[3 * E.y], S.V[3 * E.y + 1], S.V[3 * E.y + 2], bx, by, bz);
+    es.xs = (1.0 - es.t) * ax + es.t * bx;
+    es.ys = (1.0 - es.t) * ay + es.t * by;
+    es.px = (int)floor(es.xs);
+    es.py = (int)floor(es.ys);
+    es.inside = es.xs >= 0.0 && es.ys >= 0.0 && es.px < c.W && es.py < c.H;
+    const double dx = bx - ax, dy = by - ay;
+    const double l = sqrt(dx * dx + dy * dy);
+    es.nx = -dy / l;
+    es.ny = dx / l;
+    return true;
+}
+
+__device__ __forceinline__ V3 side_dir(const DevCam& c, const EdgeSample& es, int side) {
+    const double sgn = side == 0 ? -1.0 : 1.0;
+    const double sx = es.xs + sgn * EPS_PRIMARY * es.nx, sy = es.ys + sgn * EPS_PRIMARY * es.ny;
+    const double ndx = 2.0 * sx / c.W - 1.0, ndy = 1.0 - 2.0 * sy / c.H;
+    const double kx = ndx * c.dth * c.daspect, ky = ndy * c.dth;
+    const double ddx = c.df[0] + c.dr[0] * kx + c.du[0] * ky;
+    const double ddy = c.df[1] + c.dr[1] * kx + c.du[1] * ky;
+    const double ddz = c.df[2] + c.dr[2] * kx + c.du[2] * ky;
+    const double il = 1.0 / sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
+    return V3{(float)(ddx * il), (float)(ddy * il), (float)(ddz * il)};
+}
+
+__global__ void k_edge_camera(BwdParams p, Queues q, long long e0, int n) {
+    const int stride = gridDim.x * blockDim.x;
+    float* const* r = q.ray[1];
+    const int base0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63);
+    for (int wb = base0; wb < n; wb += stride) {
+        const int i = wb + (threadIdx.x & 63);
+        const long long ge = e0 + i;
+        EdgeSample es;
+        bool active = false;
+        if (i < n && edge_setup(p, ge, es) && es.inside) {
+            const DevCam& c = p.cams[es.v];
+            const float* di = p.d_image + 3 * (c.pixoff + (long long)es.py * c.W + es.px);
+            active = !(di[0] == 0.0f && di[1] == 0.0f && di[2] == 0.0f);
+        }
+        const uint64_t mask = __ballot(active);
+        if (!mask) continue;
+        const int leader = __ffsll((long long)mask) - 1;
+        int basei = 0;
+        if ((int)__lane_id() == leader) basei = atomicAdd(&q.cnt[1], 2 * __popcll(mask));
+        basei = __shfl(basei, leader);
+        if (!active) continue;
+        const DevCam& c = p.cams[es.v];
+        const int o0 = basei + 2 * __popcll(mask & lanemask_lt64());
+        for (int side = 0; side < 2; ++side) {
+            const int s = o0 + side;
+            const V3 d = side_dir(c, es, side);
+            r[0][s] = c.eye[0]; r[1][s] = c.eye[1]; r[2][s] = c.eye[2];
+            r[3][s] = d.x; r[4][s] = d.y; r[5][s] = d.z;
+            ((int*)r[6])[s] = s;
+            ((int*)r[7])[s] = -1;
+            r[8][s] = 0.0f;
+            const uint32_t lq = (uint32_t)(2 * ge + side);
+            q.pq[s] = lq;
+            q.pc0[s] = (uint32_t)es.si;
+            q.pc1[s] = (uint32_t)es.v << 16;
+            q.pdom[s] = 1u;
+            q.pbeta[0][s] = 1.0f; q.pbeta[1][s] = 1.0f; q.pbeta[2][s] = 1.0f;
+            q.phash[s] = FNV_INIT;
+            q.L[3 * (size_t)lq] = 0.0f; q.L[3 * (size_t)lq + 1] = 0.0f; q.L[3 * (size_t)lq + 2] = 0.0f;
+        }
+    }
+}
+
+__global__ void k_edge_grad(BwdParams p, const float* __restrict__ Ls, const uint32_t* __restrict__ hs,
+                            long long total) {
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long ge = blockIdx.x * (long long)blockDim.x + threadIdx.x; ge < total; ge += stride) {
-        if (p.edge_mask && !p.edge_mask[ge]) continue;
-        const int v = find_view(p.eoff, p.ncam, ge);
-        const DevCam& c = p.cams[v];
+        EdgeSample es;
+        if (!edge_setup(p, ge, es)) continue;
+        const DevCam& c = p.cams[es.v];
         const DevScene& S = p.scenes[c.scene];
-        const double tot = p.ptotal[v];
-        if (!(tot > 0.0)) continue;
-        const long long si = ge - c.eoff;
-        const Key key{p.seed, S.scene_id};
-        const Ctr ctr{(uint32_t)si, (uint32_t)v << 16, 0u, 1u};
-        const float4 u = draw4(ctr, 0, 3, key);
-        const int e = cdf_find(p.pcdf + (size_t)v * (p.ne + 1), S.ne, (double)u.x);
-        const double t = u.y;
-        const int4 E = S.edges[e];
-        double ax, ay, az, bx, by, bz;
-        project_d(c, S.V[3 * E.x], S.V[3 * E.x + 1], S.V[3 * E.x + 2], ax, ay, az);
-        project_d(c, S.V[3 * E.y], S.V[3 * E.y + 1], S.V[3 * E.y + 2], bx, by, bz);
-        const double xs = (1.0 - t) * ax + t * bx, ys = (1.0 - t) * ay + t * by;
-        const int px = (int)floor(xs), py = (int)floor(ys);
-        const bool inside = xs >= 0.0 && ys >= 0.0 && px < c.W && py < c.H;
-        const float* di = inside ? p.d_image + 3 * (c.pixoff + (long long)py * c.W + px) : nullptr;
-        if (inside && di[0] == 0.0f && di[1] == 0.0f && di[2] == 0.0f) continue;
         Hash h{FNV_INIT, p.dbg_edge_hash != nullptr};
-        h.push((uint32_t)e);
-        if (!inside) {
+        if (!es.inside) {
+            h.push((uint32_t)es.e);
             h.push(0u);
             if (p.dbg_edge_hash) p.dbg_edge_hash[ge] = h.h;
             continue;
         }
+        const float* di = p.d_image + 3 * (c.pixoff + (long long)es.py * c.W + es.px);
+        if (di[0] == 0.0f && di[1] == 0.0f && di[2] == 0.0f) continue;
+        h.push((uint32_t)es.e);
         h.push(1u);
-        const double dx = bx - ax, dy = by - ay;
-        const double l = sqrt(dx * dx + dy * dy);
-        const double nx = -dy / l, ny = dx / l;
-        V3 Ls[2];
-        for (int side = 0; side < 2; ++side) {
-            const double sgn = side == 0 ? -1.0 : 1.0;
-            const double sx = xs + sgn * EPS_PRIMARY * nx, sy = ys + sgn * EPS_PRIMARY * ny;
-            const double ndx = 2.0 * sx / c.W - 1.0, ndy = 1.0 - 2.0 * sy / c.H;
-            const double kx = ndx * c.dth * c.daspect, ky = ndy * c.dth;
-            double ddx = c.df[0] + c.dr[0] * kx + c.du[0] * ky;
-            double ddy = c.df[1] + c.dr[1] * kx + c.du[1] * ky;
-            double ddz = c.df[2] + c.dr[2] * kx + c.du[2] * ky;
-            const double il = 1.0 / sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
-            const V3 dir{(float)(ddx * il), (float)(ddy * il), (float)(ddz * il)};
-            Ls[side] = trace_estimator(S, ld3(c.eye), dir, -1, p.B, false, ctr, key, h, st);
+        if (p.dbg_edge_hash) {
+            h.push(hs[2 * ge]);
+            h.push(hs[2 * ge + 1]);
+            p.dbg_edge_hash[ge] = h.h;
         }
-        const double cc = ((double)di[0] * (Ls[0].x - Ls[1].x) + (double)di[1] * (Ls[0].y - Ls[1].y) +
-                           (double)di[2] * (Ls[0].z - Ls[1].z)) * (tot / (double)c.ne);
+        const float* lm = Ls + 6 * ge;
+        const double cc = ((double)di[0] * ((double)lm[0] - lm[3]) + (double)di[1] * ((double)lm[1] - lm[4]) +
+                           (double)di[2] * ((double)lm[2] - lm[5])) * (p.ptotal[es.v] / (double)c.ne);
+        const int4 E = S.edges[es.e];
         for (int end = 0; end < 2; ++end) {
             const int vid = end == 0 ? E.x : E.y;
-            const double wgt = end == 0 ? (1.0 - t) : t;
+            const double wgt = end == 0 ? (1.0 - es.t) : es.t;
             const double qx = (double)S.V[3 * vid] - c.deye[0], qy = (double)S.V[3 * vid + 1] - c.deye[1],
                          qz = (double)S.V[3 * vid + 2] - c.deye[2];
             const double z = qx * c.df[0] + qy * c.df[1] + qz * c.df[2];
@@ -470,11 +540,10 @@ __global__ void __launch_bounds__(TRACE_BLOCK) k_prim_samples(BwdParams p, long 
             for (int k3 = 0; k3 < 3; ++k3) {
                 const double dsx = kx * (c.dr[k3] * z - aa * c.df[k3]);
                 const double dsy = ky * (c.du[k3] * z - bb * c.df[k3]);
-                gv[k3] = cc * wgt * (dsx * nx + dsy * ny);
+                gv[k3] = cc * wgt * (dsx * es.nx + dsy * es.ny);
             }
             atomic_add3(p.dV + 3 * (size_t)vid, V3{(float)gv[0], (float)gv[1], (float)gv[2]});
         }
-        if (p.dbg_edge_hash) p.dbg_edge_hash[ge] = h.h;
     }
 }
 
@@ -485,6 +554,23 @@ static inline unsigned gridb(long long n, int bs, int cap) {
     return (unsigned)(g < cap ? g : cap);
 }
 
+void launch_primary_edges(const BwdParams& p, const FwdParams& fp, Queues& q, float* Lside, uint32_t* hside,
+                          long long total_edges, int has_env_any, hipStream_t st) {
+    if (total_edges <= 0 || p.ne <= 0) return;
+    ST_LAUNCH("k_prim_weights", k_prim_weights, dim3(gridb(p.ne, 256, 1024), p.ncam), dim3(256), 0, st, p);
+    ST_LAUNCH("k_prim_cdf", k_prim_cdf, dim3(p.ncam), dim3(1024), 0, st, p);
+    const long long per = q.cap / 2;
+    for (long long e0 = 0; e0 < total_edges; e0 += per) {
+        const int n = (int)((total_edges - e0) < per ? (total_edges - e0) : per);
+        launch_fill_u32((uint32_t*)q.cnt, 16, 0u, st);
+        ST_LAUNCH("k_edge_camera", k_edge_camera, dim3(gridb(n, 256, 1 << 20)), dim3(256), 0, st, p, q, e0, n);
+        launch_wavefront_bounces(fp, q, 2 * n, has_env_any, st);
+        if (hside) launch_chunk_hash_by_q(fp, q, 2 * n, st);
+    }
+    ST_LAUNCH("k_edge_grad", k_edge_grad, dim3(gridb(total_edges, 256, 1 << 16)), dim3(256), 0, st, p, Lside, hside,
+              total_edges);
+}
+
 void launch_backward(const BwdParams& p, long long total_paths, long long total_edges, int grid, hipStream_t st) {
     if ((p.flags & 5u) && total_paths > 0) {
         const dim3 gd(gridb(total_paths, TRACE_BLOCK, grid)), bd(TRACE_BLOCK);
@@ -493,12 +579,7 @@ void launch_backward(const BwdParams& p, long long total_paths, long long total_
         else if (p.B <= 3) ST_LAUNCH("k_adjoint<3>", k_adjoint<3>, gd, bd, 0, st, p, total_paths);
         else ST_LAUNCH("k_adjoint<8>", k_adjoint<8>, gd, bd, 0, st, p, total_paths);
     }
-    if ((p.flags & 2u) && total_edges > 0 && p.ne > 0) {
-        ST_LAUNCH("k_prim_weights", k_prim_weights, dim3(gridb(p.ne, 256, 1024), p.ncam), dim3(256), 0, st, p);
-        ST_LAUNCH("k_prim_cdf", k_prim_cdf, dim3(p.ncam), dim3(1024), 0, st, p);
-        ST_LAUNCH("k_prim_samples", k_prim_samples, dim3(gridb(total_edges, TRACE_BLOCK, grid)), dim3(TRACE_BLOCK), 0, st, p,
-                           total_edges);
-    }
+
 }
 
 } // namespace st

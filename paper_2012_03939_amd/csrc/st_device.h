@@ -30,10 +30,15 @@ constexpr float EPS_SECONDARY = 1e-4f;  // radians
 constexpr double ZNEAR = 1e-3;
 constexpr float SEC_COS_MIN = 1e-5f;    // secondary edge points this close to the tangent plane are skipped
 constexpr float BOX_GROW = 1.0000004f;  // 1 + 2*gamma(3): conservative slab exit distance
-constexpr int LDS_STACK = 32;           // per-lane traversal stack entries held in LDS
-constexpr int SPILL_STACK = 32;         // further entries spilled to HBM
+#ifndef ST_LDS_STACK
+#define ST_LDS_STACK 16
+#endif
+constexpr int LDS_STACK = ST_LDS_STACK; // per-lane traversal stack entries held in LDS
+constexpr int SPILL_STACK = 64 - LDS_STACK;  // further entries spilled to HBM (64 in all)
 constexpr uint32_t LEAF_BIT = 0x80000000u;
 constexpr int MAX_LIGHTS = 16;
+// slots of the traversal work counters (node visits, triangle tests, rays each)
+constexpr int WORK_EXTEND = 0, WORK_SHADOW = 1, WORK_ADJOINT = 2, WORK_MEGA = 3, WORK_SLOTS = 4;
 
 // error word bits (device -> host)
 constexpr uint32_t ERR_STACK = 1u;
@@ -574,6 +579,11 @@ __device__ V3 trace_estimator(const DevScene& S, V3 o, V3 d, int exclude, int nv
         o = x; d = wi; exclude = f;
     }
     return L;
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt64() {
+    const uint32_t lane = __lane_id();
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
 // processing order of path samples inside one view: sample-major, then 8x8

@@ -72,6 +72,7 @@ struct Queues {
     uint32_t* pq;            // path: processing index q
     uint32_t* pc0;           // path: Philox c0 (pixel index)
     uint32_t* pc1;           // path: Philox c1 (view << 16 | sample)
+    uint32_t* pdom;          // path: Philox c3 (stream domain)
     float* pbeta[3];
     uint32_t* phash;
     float* ht;               // hit t
@@ -97,6 +98,7 @@ struct FwdParams {
     uint32_t* dbg_hash;      // canonical order, optional
     uint32_t* err;
     unsigned long long* work;  // optional traversal counters
+    uint32_t* hash_by_q;     // optional: final path hash stored at the path's radiance index
 };
 
 void launch_scene_geometry(SceneDev& s, hipStream_t st);
@@ -104,6 +106,8 @@ void launch_env_build(SceneDev& s, hipStream_t st);
 
 void launch_forward_wavefront(const FwdParams& p, Queues& q, long long total, int has_env_any, int nent,
                               hipStream_t st);
+void launch_wavefront_bounces(const FwdParams& p, Queues& q, int n, int has_env_any, hipStream_t st);
+void launch_chunk_hash_by_q(const FwdParams& p, Queues& q, int n, hipStream_t st);
 void launch_forward_mega(const FwdParams& p, float* L, long long total, uint32_t* spill, int grid, hipStream_t st);
 void launch_film(const DevCam* cams, const long long* pixoff, int ncam, int spp, const float* L,
                  long long npix, float* out, hipStream_t st);
@@ -134,6 +138,9 @@ struct BwdParams {
 };
 
 void launch_backward(const BwdParams& p, long long total_paths, long long total_edges, int grid, hipStream_t st);
+// primary edges with their side paths traced by the wavefront kernels
+void launch_primary_edges(const BwdParams& p, const FwdParams& fp, Queues& q, float* Lside, uint32_t* hside,
+                          long long total_edges, int has_env_any, hipStream_t st);
 void launch_fill_f32(float* p, long long n, float v, hipStream_t st);
 void launch_fill_u32(uint32_t* p, long long n, uint32_t v, hipStream_t st);
 void launch_trace_debug(const DevScene* s, const float* o, const float* d, int n, float tmin, int brute,

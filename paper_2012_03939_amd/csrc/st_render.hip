@@ -23,10 +23,6 @@ __device__ __forceinline__ TravStack make_stack(uint32_t* lds, uint32_t* spill, 
     return s;
 }
 
-__device__ __forceinline__ uint64_t lanemask_lt64() {
-    const uint32_t lane = __lane_id();
-    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
-}
 
 // canonical path index of a (view, pixel, sample)
 __device__ __forceinline__ long long canon(const DevCam& c, int x, int y, int j, int spp) {
@@ -56,6 +52,7 @@ __global__ void k_camera(FwdParams p, Queues q, long long q0, int n) {
         q.pq[s] = (uint32_t)qq;
         q.pc0[s] = ctr.c0;
         q.pc1[s] = ctr.c1;
+        q.pdom[s] = 0u;
         q.pbeta[0][s] = 1.0f; q.pbeta[1][s] = 1.0f; q.pbeta[2][s] = 1.0f;
         q.phash[s] = FNV_INIT;
         q.L[3 * (size_t)qq] = 0.0f; q.L[3 * (size_t)qq + 1] = 0.0f; q.L[3 * (size_t)qq + 2] = 0.0f;
@@ -65,7 +62,7 @@ __global__ void k_camera(FwdParams p, Queues q, long long q0, int n) {
 // closest hit for every queued ray of bounce k (queue k & 1)
 __global__ void __launch_bounds__(TRACE_BLOCK) k_extend(FwdParams p, Queues q, int k) {
     __shared__ uint32_t lds[LDS_STACK * TRACE_BLOCK];
-    TravStack st = make_stack(lds, q.spill, p.err, p.work);
+    TravStack st = make_stack(lds, q.spill, p.err, p.work ? p.work + 3 * WORK_EXTEND : nullptr);
     const int n = q.cnt[k];
     float* const* r = q.ray[k & 1];
     const int stride = gridDim.x * blockDim.x;
@@ -104,7 +101,7 @@ __global__ void k_shade(FwdParams p, Queues q, int k) {
             const uint32_t v = c1 >> 16;
             const DevScene& S = p.scenes[p.cams[v].scene];
             const Key key{p.seed, S.scene_id};
-            const Ctr ctr{q.pc0[slot], c1, 0u, 0u};
+            const Ctr ctr{q.pc0[slot], c1, 0u, q.pdom[slot]};
             Hash h{q.phash[slot], true};
             V3 beta{q.pbeta[0][slot], q.pbeta[1][slot], q.pbeta[2][slot]};
             const uint32_t qq = q.pq[slot];
@@ -209,7 +206,7 @@ __global__ void k_shade(FwdParams p, Queues q, int k) {
 // shadow rays of bounce k, one thread per shading point, fixed order
 __global__ void __launch_bounds__(TRACE_BLOCK) k_shadow(FwdParams p, Queues q, int k) {
     __shared__ uint32_t lds[LDS_STACK * TRACE_BLOCK];
-    TravStack st = make_stack(lds, q.spill, p.err, p.work);
+    TravStack st = make_stack(lds, q.spill, p.err, p.work ? p.work + 3 * WORK_SHADOW : nullptr);
     const int n = q.cnt[k];
     float* const* r = q.ray[k & 1];
     const int stride = gridDim.x * blockDim.x;
@@ -247,6 +244,12 @@ __global__ void __launch_bounds__(TRACE_BLOCK) k_shadow(FwdParams p, Queues q, i
     }
 }
 
+__global__ void k_chunk_hash_q(FwdParams p, Queues q) {
+    const int n = q.cnt[1];
+    const int stride = gridDim.x * blockDim.x;
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += stride) p.hash_by_q[q.pq[s]] = q.phash[s];
+}
+
 __global__ void k_chunk_hash(FwdParams p, Queues q, int n) {
     const int stride = gridDim.x * blockDim.x;
     for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += stride) {
@@ -263,7 +266,7 @@ __global__ void k_chunk_hash(FwdParams p, Queues q, int n) {
 __global__ void __launch_bounds__(TRACE_BLOCK) k_forward_mega(FwdParams p, float* L, long long total,
                                                               uint32_t* spill) {
     __shared__ uint32_t lds[LDS_STACK * TRACE_BLOCK];
-    TravStack st = make_stack(lds, spill, p.err, p.work);
+    TravStack st = make_stack(lds, spill, p.err, p.work ? p.work + 3 * WORK_MEGA : nullptr);
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long qq = blockIdx.x * (long long)blockDim.x + threadIdx.x; qq < total; qq += stride) {
         const int v = find_view(p.qoff, p.ncam, qq);
@@ -367,15 +370,27 @@ void launch_forward_wavefront(const FwdParams& p, Queues& q, long long total, in
         const int n = (int)((total - q0) < q.cap ? (total - q0) : q.cap);
         const unsigned g = grid_for(n, TRACE_BLOCK, TRACE_GRID);
         ST_LAUNCH("k_camera", k_camera, dim3(grid_for(n, 256, 1u << 20)), dim3(256), 0, st, p, q, q0, n);
-        const int last = p.B + (has_env_any ? 1 : 0);
-        for (int k = 1; k <= last; ++k) {
-            ST_LAUNCH("k_extend", k_extend, dim3(g), dim3(TRACE_BLOCK), 0, st, p, q, k);
-            ST_LAUNCH("k_shade", k_shade, dim3(grid_for(n, 256, TRACE_GRID)), dim3(256), 0, st, p, q, k);
-            if (k <= p.B) ST_LAUNCH("k_shadow", k_shadow, dim3(g), dim3(TRACE_BLOCK), 0, st, p, q, k);
-        }
+        (void)g;
+        launch_wavefront_bounces(p, q, n, has_env_any, st);
         if (p.dbg_hash)
             ST_LAUNCH("k_chunk_hash", k_chunk_hash, dim3(grid_for(n, 256, 1u << 20)), dim3(256), 0, st, p, q, n);
     }
+}
+
+// extension / shading / shadow kernels of every bounce for a chunk whose first
+// ray queue (queue 1) and count cnt[1] have been filled; n bounds the count
+void launch_wavefront_bounces(const FwdParams& p, Queues& q, int n, int has_env_any, hipStream_t st) {
+    const unsigned g = grid_for(n, TRACE_BLOCK, TRACE_GRID);
+    const int last = p.B + (has_env_any ? 1 : 0);
+    for (int k = 1; k <= last; ++k) {
+        ST_LAUNCH("k_extend", k_extend, dim3(g), dim3(TRACE_BLOCK), 0, st, p, q, k);
+        ST_LAUNCH("k_shade", k_shade, dim3(grid_for(n, 256, TRACE_GRID)), dim3(256), 0, st, p, q, k);
+        if (k <= p.B) ST_LAUNCH("k_shadow", k_shadow, dim3(g), dim3(TRACE_BLOCK), 0, st, p, q, k);
+    }
+}
+
+void launch_chunk_hash_by_q(const FwdParams& p, Queues& q, int n, hipStream_t st) {
+    ST_LAUNCH("k_chunk_hash_q", k_chunk_hash_q, dim3(grid_for(n, 256, 1u << 20)), dim3(256), 0, st, p, q);
 }
 
 void launch_forward_mega(const FwdParams& p, float* L, long long total, uint32_t* spill, int grid,
