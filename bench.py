@@ -21,9 +21,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Algorithmic work per unit, stated once here and in the design doc:
-#  - a BVH node visit tests two child boxes: 2 x (6 sub + 6 mul + 12 min/max) = 48 FP32 ops
+#  - a visit of a 4-wide BVH node tests four child boxes: 4 x (6 sub + 6 mul + 12 min/max) = 96 FP32 ops
 #  - a Moller-Trumbore triangle test: 2 cross (18) + 4 dot (20) + 1 rcp + 3 sub + 3 mul = 45 FP32 ops
-FLOPS_PER_VISIT = 48
+FLOPS_PER_VISIT = 96
 FLOPS_PER_TEST = 45
 PEAK_FP32_VECTOR_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0

@@ -403,7 +403,9 @@ int st_scene_create(const float* V, int32_t nv, const int32_t* F, int32_t nf, co
     A(dalloc(&d.parent, 2 * (size_t)nf));
     A(dalloc(&d.aabb, 6 * (size_t)(2 * nf)));
     A(dalloc(&d.refit_cnt, (size_t)nf));
-    A(dalloc(&d.nodes, 4 * (size_t)std::max(nf - 1, 1)));
+    A(dalloc(&d.nodes4, 8 * (size_t)std::max(nf - 1, 1)));
+    A(dalloc(&d.flag4, (size_t)std::max(nf - 1, 1)));
+    A(dalloc(&d.id4, (size_t)std::max(nf - 1, 1)));
     A(dalloc(&d.tri, 3 * (size_t)nf));
     A(dalloc(&d.edges, edges.size()));
     A(dalloc(&d.edge_w, edges.size()));
@@ -456,7 +458,7 @@ int st_scene_create(const float* V, int32_t nv, const int32_t* F, int32_t nf, co
     HIPCHK2(hipStreamSynchronize(s));
     d.has_env = he > 0 && etot > 0.0;
     DevScene& h = d.hscene;
-    h.V = d.V; h.F = d.F; h.mat = d.mat; h.lights = d.lights; h.fnorm = d.fnorm; h.tri = d.tri; h.nodes = d.nodes;
+    h.V = d.V; h.F = d.F; h.mat = d.mat; h.lights = d.lights; h.fnorm = d.fnorm; h.tri = d.tri; h.nodes4 = d.nodes4;
     h.env = d.env; h.marg = d.marg; h.cond = d.cond; h.texpdf = d.texpdf; h.rowcos = d.rowcos;
     h.edges = d.edges; h.ecdf = d.ecdf; h.etotal = d.etotal_f;
     h.nv = nv; h.nf = nf; h.nl = nl; h.he = he; h.we = we; h.ne = d.ne; h.has_env = d.has_env ? 1 : 0;
@@ -653,7 +655,7 @@ void st_scene_destroy(st_scene* sc) {
     hipDeviceSynchronize();
     SceneDev& d = sc->d;
     void* ptrs[] = {d.V, d.F, d.mat, d.lights, d.env, d.fnorm, d.bmin, d.bmax, d.cen, d.bounds, d.mkeys[0], d.mkeys[1],
-                    d.mvals[0], d.mvals[1], d.rs_hist, d.keys64, d.child, d.parent, d.aabb, d.refit_cnt, d.nodes,
+                    d.mvals[0], d.mvals[1], d.rs_hist, d.keys64, d.child, d.parent, d.aabb, d.refit_cnt, d.nodes4, d.flag4, d.id4,
                     d.tri, d.edges, d.edge_w, d.ecdf, d.etotal_d, d.etotal_f, d.row_dom, d.rowcos, d.cond, d.marg,
                     d.env_rows, d.env_total, d.texpdf, d.err, d.work, d.dscene};
     for (void* p : ptrs)

@@ -256,18 +256,56 @@ __global__ void k_refit(const int* __restrict__ parent, const int* __restrict__ 
     }
 }
 
-__global__ void k_pack_nodes(const int* __restrict__ child, const float* __restrict__ aabb, int n, float4* nodes) {
+// depth of every internal node of the binary tree, and the flag "starts a
+// 4-wide node" (even depth)
+__global__ void k_depth(const int* __restrict__ parent, int n, int* flag) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n - 1) return;
-    const int c0 = child[2 * i], c1 = child[2 * i + 1];
-    const size_t i0 = (c0 & (int)LEAF_BIT) ? (size_t)(n - 1) + (c0 & 0x7FFFFFFF) : (size_t)c0;
-    const size_t i1 = (c1 & (int)LEAF_BIT) ? (size_t)(n - 1) + (c1 & 0x7FFFFFFF) : (size_t)c1;
-    const float* L = aabb + 6 * i0;
-    const float* R = aabb + 6 * i1;
-    nodes[4 * i] = make_float4(L[0], L[1], L[2], R[0]);
-    nodes[4 * i + 1] = make_float4(L[3], L[4], L[5], R[1]);
-    nodes[4 * i + 2] = make_float4(R[3], R[4], R[5], R[2]);
-    nodes[4 * i + 3] = make_float4(__int_as_float(c0), __int_as_float(c1), 0.f, 0.f);
+    int d = 0, x = i;
+    for (int guard = 0; guard < 128 && parent[x] >= 0; ++guard) { x = parent[x]; ++d; }
+    flag[i] = (d & 1) ? 0 : 1;
+}
+
+// 4-wide node of an even-depth binary node: its children, with every internal
+// child replaced by that child's own two children (8 float4: min x, max x,
+// min y, max y, min z, max z of the 4 slots, child codes, pad)
+__global__ void k_pack4(const int* __restrict__ child, const float* __restrict__ aabb, const int* __restrict__ flag,
+                        const uint32_t* __restrict__ id4, int n, float4* nodes4) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n - 1 || !flag[i]) return;
+    int codes[4];
+    size_t box[4];
+    int m = 0;
+    for (int a = 0; a < 2; ++a) {
+        const int c = child[2 * i + a];
+        if (c & (int)LEAF_BIT) {
+            codes[m] = c;
+            box[m++] = (size_t)(n - 1) + (c & 0x7FFFFFFF);
+        } else {
+            for (int b = 0; b < 2; ++b) {
+                const int g = child[2 * c + b];
+                if (g & (int)LEAF_BIT) { codes[m] = g; box[m++] = (size_t)(n - 1) + (g & 0x7FFFFFFF); }
+                else { codes[m] = (int)id4[g]; box[m++] = (size_t)g; }
+            }
+        }
+    }
+    float v[6][4];
+    int cc[4];
+    for (int s = 0; s < 4; ++s) {
+        if (s < m) {
+            const float* bb = aabb + 6 * box[s];
+            v[0][s] = bb[0]; v[1][s] = bb[3]; v[2][s] = bb[1]; v[3][s] = bb[4]; v[4][s] = bb[2]; v[5][s] = bb[5];
+            cc[s] = codes[s];
+        } else {
+            v[0][s] = v[2][s] = v[4][s] = __int_as_float(0x7f800000);
+            v[1][s] = v[3][s] = v[5][s] = -__int_as_float(0x7f800000);
+            cc[s] = -1;
+        }
+    }
+    float4* o = nodes4 + 8 * (size_t)id4[i];
+    for (int k = 0; k < 6; ++k) o[k] = make_float4(v[k][0], v[k][1], v[k][2], v[k][3]);
+    o[6] = make_float4(__int_as_float(cc[0]), __int_as_float(cc[1]), __int_as_float(cc[2]), __int_as_float(cc[3]));
+    o[7] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
 __global__ void k_keys64(const uint32_t* __restrict__ m, const uint32_t* __restrict__ fa, int n, uint64_t* out) {
@@ -364,7 +402,11 @@ void launch_scene_geometry(SceneDev& s, hipStream_t st) {
     if (nf > 1) {
         ST_LAUNCH("k_refit", k_refit, dim3(nb(nf, 256)), dim3(256), 0, st, s.parent, s.child, nf, s.aabb,
                            s.refit_cnt);
-        ST_LAUNCH("k_pack_nodes", k_pack_nodes, dim3(nb(nf - 1, 256)), dim3(256), 0, st, s.child, s.aabb, nf, s.nodes);
+        ST_LAUNCH("k_depth", k_depth, dim3(nb(nf - 1, 256)), dim3(256), 0, st, s.parent, nf, s.flag4);
+        hipMemcpyAsync(s.id4, s.flag4, sizeof(int) * (nf - 1), hipMemcpyDeviceToDevice, st);
+        ST_LAUNCH("k_rs_scan", k_rs_scan, dim3(1), dim3(1024), 0, st, s.id4, nf - 1);
+        ST_LAUNCH("k_pack4", k_pack4, dim3(nb(nf - 1, 256)), dim3(256), 0, st, s.child, s.aabb, s.flag4, s.id4, nf,
+                  s.nodes4);
     }
     if (s.ne > 0) {
         ST_LAUNCH("k_edge_len", k_edge_len, dim3(nb(s.ne, 256)), dim3(256), 0, st, s.edges, s.ne, s.V, s.edge_w);

@@ -112,7 +112,7 @@ struct DevScene {
     const float* lights;  // [nl,6]
     const float4* fnorm;  // [nf] unit geometric normal
     const float4* tri;    // [nf*3] leaf-ordered (v0, face bits) (e1) (e2)
-    const float4* nodes;  // [(nf-1)*4] two child boxes + child codes
+    const float4* nodes4; // 4-wide nodes, 8 float4 each: SoA child boxes + child codes
     const float* env;     // [he,we,3]
     const double* marg;   // [he+1]
     const double* cond;   // [he,we+1]
@@ -167,44 +167,45 @@ __device__ __forceinline__ V3 safe_inv(V3 d) {
     return V3{f(d.x), f(d.y), f(d.z)};
 }
 
-// slab test of both children of one node; returns entry distances
-__device__ __forceinline__ void node_test(const float4* nodes, uint32_t node, V3 o, V3 inv, float tmin, float tmax,
-                                          bool& hl, bool& hr, float& tl, float& tr, uint32_t& cl, uint32_t& cr) {
-    const float4 n0 = nodes[4 * node], n1 = nodes[4 * node + 1], n2 = nodes[4 * node + 2],
-                 n3 = nodes[4 * node + 3];
-    // left box (n0.xyz, n1.xyz), right box (n0.w, n1.w, n2.w) - (n2.xyz)
-    {
-        float ax = (n0.x - o.x) * inv.x, bx = (n1.x - o.x) * inv.x;
-        float ay = (n0.y - o.y) * inv.y, by = (n1.y - o.y) * inv.y;
-        float az = (n0.z - o.z) * inv.z, bz = (n1.z - o.z) * inv.z;
-        float t0 = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), tmin));
-        float t1 = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), tmax)) * BOX_GROW;
-        hl = t0 <= t1;
-        tl = t0;
+// slab test of the 4 child boxes of a 4-wide node; entry distance per slot,
+// +inf for a miss or an empty slot
+__device__ __forceinline__ void node4_test(const float4* nodes4, uint32_t node, V3 o, V3 inv, float tmin, float tmax,
+                                           float t[4], uint32_t c[4]) {
+    const float4* n = nodes4 + 8 * (size_t)node;
+    const float4 x0 = n[0], x1 = n[1], y0 = n[2], y1 = n[3], z0 = n[4], z1 = n[5], cc = n[6];
+    const float lx[4] = {x0.x, x0.y, x0.z, x0.w}, hx[4] = {x1.x, x1.y, x1.z, x1.w};
+    const float ly[4] = {y0.x, y0.y, y0.z, y0.w}, hy[4] = {y1.x, y1.y, y1.z, y1.w};
+    const float lz[4] = {z0.x, z0.y, z0.z, z0.w}, hz[4] = {z1.x, z1.y, z1.z, z1.w};
+    c[0] = __float_as_uint(cc.x); c[1] = __float_as_uint(cc.y); c[2] = __float_as_uint(cc.z); c[3] = __float_as_uint(cc.w);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const float ax = (lx[s] - o.x) * inv.x, bx = (hx[s] - o.x) * inv.x;
+        const float ay = (ly[s] - o.y) * inv.y, by = (hy[s] - o.y) * inv.y;
+        const float az = (lz[s] - o.z) * inv.z, bz = (hz[s] - o.z) * inv.z;
+        const float t0 = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), tmin));
+        const float t1 = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), tmax)) * BOX_GROW;
+        t[s] = (t0 <= t1 && c[s] != 0xFFFFFFFFu) ? t0 : __int_as_float(0x7f800000);
     }
-    {
-        float ax = (n0.w - o.x) * inv.x, bx = (n2.x - o.x) * inv.x;
-        float ay = (n1.w - o.y) * inv.y, by = (n2.y - o.y) * inv.y;
-        float az = (n2.w - o.z) * inv.z, bz = (n2.z - o.z) * inv.z;
-        float t0 = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), tmin));
-        float t1 = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), tmax)) * BOX_GROW;
-        hr = t0 <= t1;
-        tr = t0;
+}
+
+__device__ __forceinline__ void cswap(float& ta, uint32_t& ca, float& tb, uint32_t& cb) {
+    if (tb < ta) {
+        const float t = ta; ta = tb; tb = t;
+        const uint32_t c = ca; ca = cb; cb = c;
     }
-    cl = __float_as_uint(n3.x);
-    cr = __float_as_uint(n3.y);
 }
 
 // closest hit with t in (tmin, inf) excluding one face; ties go to the smaller face id
 __device__ int trace_closest(const DevScene& S, V3 o, V3 d, float tmin, int exclude, float& thit, TravStack& st) {
-    float tbest = __int_as_float(0x7f800000);
+    const float INF = __int_as_float(0x7f800000);
+    float tbest = INF;
     int best = -1;
     if (S.nf <= 0) return -1;
     uint32_t visits = 0, tests = 0;
     auto leaf = [&](uint32_t l) {
         ++tests;
         float t; int f;
-        if (tri_test(S.tri, l, o, d, tmin, __int_as_float(0x7f800000), t, f) && f != exclude) {
+        if (tri_test(S.tri, l, o, d, tmin, INF, t, f) && f != exclude) {
             if (t < tbest || (t == tbest && f < best)) { tbest = t; best = f; }
         }
     };
@@ -215,19 +216,30 @@ __device__ int trace_closest(const DevScene& S, V3 o, V3 d, float tmin, int excl
     for (int iter = 0;; ++iter) {
         if (iter >= TRAVERSAL_CAP) { atomicOr(st.err, ERR_LOOP); break; }
         ++visits;
-        bool hl, hr; float tl, tr; uint32_t cl, cr;
-        node_test(S.nodes, node, o, inv, tmin, tbest, hl, hr, tl, tr, cl, cr);
-        if (hl && (cl & LEAF_BIT)) { leaf(cl & ~LEAF_BIT); hl = false; }
-        if (hr && (cr & LEAF_BIT)) { leaf(cr & ~LEAF_BIT); hr = false; }
-        if (hl && hr) {
-            uint32_t nearc = tl <= tr ? cl : cr, farc = tl <= tr ? cr : cl;
-            if (sp >= LDS_STACK + SPILL_STACK) { atomicOr(st.err, ERR_STACK); break; }
-            st.put(sp++, farc);
-            node = nearc;
-        } else if (hl) {
-            node = cl;
-        } else if (hr) {
-            node = cr;
+        float t[4];
+        uint32_t c[4];
+        node4_test(S.nodes4, node, o, inv, tmin, tbest, t, c);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+            if (t[s] < INF && (c[s] & LEAF_BIT)) { leaf(c[s] & ~LEAF_BIT); t[s] = INF; }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+            if (t[s] > tbest) t[s] = INF;
+        // nearest first: sort the 4 (distance, code) pairs
+        cswap(t[0], c[0], t[1], c[1]); cswap(t[2], c[2], t[3], c[3]);
+        cswap(t[0], c[0], t[2], c[2]); cswap(t[1], c[1], t[3], c[3]);
+        cswap(t[1], c[1], t[2], c[2]);
+        if (t[0] < INF) {
+            bool overflow = false;
+#pragma unroll
+            for (int s = 3; s >= 1; --s) {
+                if (t[s] < INF) {
+                    if (sp >= LDS_STACK + SPILL_STACK) overflow = true;
+                    else st.put(sp++, c[s]);
+                }
+            }
+            if (overflow) { atomicOr(st.err, ERR_STACK); break; }
+            node = c[0];
         } else {
             if (sp == 0) break;
             node = st.get(--sp);
@@ -244,6 +256,7 @@ __device__ int trace_closest(const DevScene& S, V3 o, V3 d, float tmin, int excl
 
 __device__ bool trace_any_impl(const DevScene& S, V3 o, V3 d, float tmin, float tmax, int exclude, TravStack& st,
                                uint32_t& visits, uint32_t& tests) {
+    const float INF = __int_as_float(0x7f800000);
     if (S.nf <= 0) return false;
     auto leaf = [&](uint32_t l) -> bool {
         ++tests;
@@ -257,18 +270,28 @@ __device__ bool trace_any_impl(const DevScene& S, V3 o, V3 d, float tmin, float 
     for (int iter = 0;; ++iter) {
         if (iter >= TRAVERSAL_CAP) { atomicOr(st.err, ERR_LOOP); return false; }
         ++visits;
-        bool hl, hr; float tl, tr; uint32_t cl, cr;
-        node_test(S.nodes, node, o, inv, tmin, tmax, hl, hr, tl, tr, cl, cr);
-        if (hl && (cl & LEAF_BIT)) { if (leaf(cl & ~LEAF_BIT)) return true; hl = false; }
-        if (hr && (cr & LEAF_BIT)) { if (leaf(cr & ~LEAF_BIT)) return true; hr = false; }
-        if (hl && hr) {
-            if (sp >= LDS_STACK + SPILL_STACK) { atomicOr(st.err, ERR_STACK); return false; }
-            st.put(sp++, tl <= tr ? cr : cl);
-            node = tl <= tr ? cl : cr;
-        } else if (hl) {
-            node = cl;
-        } else if (hr) {
-            node = cr;
+        float t[4];
+        uint32_t c[4];
+        node4_test(S.nodes4, node, o, inv, tmin, tmax, t, c);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+            if (t[s] < INF && (c[s] & LEAF_BIT)) {
+                if (leaf(c[s] & ~LEAF_BIT)) return true;
+                t[s] = INF;
+            }
+        int next = -1;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            if (t[s] < INF) {
+                if (next < 0) next = s;
+                else {
+                    if (sp >= LDS_STACK + SPILL_STACK) { atomicOr(st.err, ERR_STACK); return false; }
+                    st.put(sp++, c[s]);
+                }
+            }
+        }
+        if (next >= 0) {
+            node = next == 0 ? c[0] : (next == 1 ? c[1] : (next == 2 ? c[2] : c[3]));
         } else {
             if (sp == 0) return false;
             node = st.get(--sp);

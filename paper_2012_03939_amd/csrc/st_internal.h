@@ -38,7 +38,9 @@ struct SceneDev {
     int* parent = nullptr;                   // [2*nf-1]
     float* aabb = nullptr;                   // [(2*nf-1)*6]
     int* refit_cnt = nullptr;
-    float4* nodes = nullptr;                 // [(nf-1)*4]
+    float4* nodes4 = nullptr;                // [(nf-1)*8] 4-wide nodes (at most nf-1 of them)
+    int* flag4 = nullptr;                    // [nf-1] even-depth flag of the binary nodes
+    uint32_t* id4 = nullptr;                 // [nf-1] 4-wide node index of each even-depth node
     float4* tri = nullptr;                   // [nf*3]
     // edges (topology fixed at creation)
     int4* edges = nullptr;
