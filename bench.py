@@ -29,6 +29,33 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 
 
+def kernel_source_hash() -> str:
+    """Hash of the HIP sources; counter summaries are valid only for the sources they were taken on."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2012_03939_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by their plain-copy factors), or None when
+    the kernel sources changed after the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "pmc_traversal_kernels_torus40k_16x512sq_16spp.json")
+    try:
+        with open(path) as fh:
+            pm = json.load(fh)
+    except OSError:
+        return None
+    if pm.get("source_hash") != kernel_source_hash():
+        return None
+    k = pm["kernels"].get(kernel.split("<")[0])
+    return None if k is None else k["hbm_bytes_per_dispatch"]
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -38,6 +65,7 @@ def parse():
     ap.add_argument("--res", type=int, default=512)
     ap.add_argument("--views", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--cpu-baseline-res", type=int, default=1024)
     ap.add_argument("--profile-only", action="store_true", help="one untimed step (for rocprofv3 runs)")
     return ap.parse_args()
@@ -62,6 +90,39 @@ def cpu_baseline(wl, res, spp, bounces):
     return {"value": n / dt, "unit": "path samples/s (fwd+adjoint)", "cores": nt, "kind": "oracle",
             "sample": f"same torus scene and envmap, 1 view at {res}x{res}, {spp} spp, {bounces} bounces, "
                       f"forward + adjoint (interior, primary and secondary edges): {n} path samples in {dt:.2f} s"}
+
+
+def batched_vs_per_view(B, S, torch, reps=3):
+    """Forward render of 4 scenes (2,000 / 8,000 / 20,480 / 60,500 faces) with 24 views
+    of uneven resolution, 16 spp, 2 bounces: one batched pass against one call per view."""
+    wl = S.batched_uneven()
+    gs = [B.GPUScene.from_scene(s) for s in wl.scenes]
+    npix = B.num_pixels(wl.cams)
+    out = torch.empty((npix, 3), dtype=torch.float32, device="cuda")
+    outs = [torch.empty((c.width * c.height, 3), dtype=torch.float32, device="cuda") for c in wl.cams]
+
+    def batched():
+        B.render_batch(gs, wl.cams, wl.cam_scene, wl.spp, wl.bounces, seed=0, out=out)
+
+    def per_view():
+        for i, c in enumerate(wl.cams):
+            gs[wl.cam_scene[i]].render([c], wl.spp, wl.bounces, seed=0, out=outs[i])
+
+    res = {}
+    for name, fn in (("batched", batched), ("per_view", per_view)):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        res[name + "_ms"] = e0.elapsed_time(e1) / reps
+    res["speedup"] = res["per_view_ms"] / res["batched_ms"]
+    res["path_samples"] = npix * wl.spp
+    res["workload"] = wl.name
+    return res
 
 
 def main():
@@ -160,13 +221,16 @@ def main():
                    "spp": spp, "bounces": bounces, "path_samples_per_step": n_paths,
                    "edge_samples_per_step": B.num_edge_samples(cams, spp, 1.0), "envmap": "512x256"},
         "roofline": {"bound": "alu", "kernel": dom_name, "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": measured_traffic(dom_name),
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-scaled)",
                      "avg_launch_ms": avg_ms, "node_visits_per_launch": visits / max(launches_per_step, 1),
                      "tri_tests_per_launch": tests / max(launches_per_step, 1),
                      "rays_per_launch": rays / max(launches_per_step, 1),
                      "rays_per_s": rays / max(launches_per_step, 1) / (avg_ms / 1e3)},
         "kernels": kernels,
     }
+    if not args.no_batched:
+        out["batched"] = batched_vs_per_view(B, S, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_baseline_res, spp, bounces)
     print(json.dumps(out))

@@ -122,6 +122,19 @@ int st_render_batch(st_scene* const* scenes, int32_t nscenes, const st_camera* c
                     int32_t ncam, int32_t spp, int32_t bounces, uint32_t seed, const st_render_opts* opts,
                     float* out, hipStream_t s);
 
+/* Autotuner: times st_render of this exact workload (same arguments as
+ * st_render_batch; cam_scene may be NULL for one scene) over wavefront chunk
+ * sizes {2^20..2^24} x traversal grids {1024, 2048, 4096} blocks and keeps the
+ * fastest on every scene in the list; later renders and backward passes of
+ * those scenes use it unless opts->queue_capacity is set.  cache_path (may be
+ * NULL): JSON-lines file keyed by device and workload signature; a matching
+ * line is used without timing, a new result is appended.  Synchronises s and
+ * allocates a temporary image.  The chosen values are returned through the two
+ * optional host pointers. */
+int st_autotune(st_scene* const* scenes, int32_t nscenes, const st_camera* cams, const int32_t* cam_scene,
+                int32_t ncam, int32_t spp, int32_t bounces, const char* cache_path, int64_t* out_queue_capacity,
+                int32_t* out_trace_grid, hipStream_t s);
+
 /* Wait for stream s and report device-side faults recorded by earlier calls on
  * this scene (traversal stack overflow): ST_ERR_DEVICE_FAULT, and clears them. */
 int st_check_errors(st_scene* scene, hipStream_t s);

@@ -25,7 +25,7 @@ ST_COUNT_WORK = 32
 ST_ALL_GRADS = 7
 
 EXPORTED = ["st_render_opts_default", "st_scene_create", "st_scene_update", "st_render", "st_render_backward",
-            "st_render_batch", "st_check_errors", "st_read_work", "st_scene_info", "st_scene_edges", "st_scene_lbvh",
+            "st_render_batch", "st_autotune", "st_check_errors", "st_read_work", "st_scene_info", "st_scene_edges", "st_scene_lbvh",
             "st_trace_rays", "st_profile_enable", "st_profile_read", "st_scene_destroy", "st_last_error",
             "st_version"]
 
@@ -65,6 +65,7 @@ def load(path: str = LIB_PATH):
     L.st_render_backward.argtypes = [P, P, I32, I32, I32, U32, ctypes.POINTER(StOpts), P, P, P, P]
     L.st_render_batch.argtypes = [P, I32, P, P, I32, I32, I32, U32, ctypes.POINTER(StOpts), P, P]
     L.st_check_errors.argtypes = [P, P]
+    L.st_autotune.argtypes = [P, I32, P, P, I32, I32, I32, ctypes.c_char_p, P, P, P]
     L.st_scene_info.argtypes = [P, P]
     L.st_read_work.argtypes = [P, P, P]
     L.st_scene_edges.argtypes = [P, P, P]
@@ -237,6 +238,18 @@ class GPUScene:
         _check(load().st_trace_rays(self.h, _ptr(o.contiguous()), _ptr(d.contiguous()), n, tmin, int(brute),
                                     _ptr(f), _ptr(t), _stream()))
         return f, t
+
+
+def autotune(scenes: Sequence["GPUScene"], cams, spp: int, bounces: int, cam_scene=None, cache_path=None):
+    """Pick the wavefront chunk size and traversal grid for this workload (see st_autotune)."""
+    arr = (ctypes.c_void_p * len(scenes))(*[s.h.value for s in scenes])
+    cs = None if cam_scene is None else (ctypes.c_int32 * len(cams))(*[int(x) for x in cam_scene])
+    cap = ctypes.c_int64(0)
+    grid = ctypes.c_int32(0)
+    _check(load().st_autotune(arr, len(scenes), make_cameras(cams), cs, len(cams), spp, bounces,
+                              None if cache_path is None else cache_path.encode(), ctypes.byref(cap),
+                              ctypes.byref(grid), _stream()))
+    return int(cap.value), int(grid.value)
 
 
 def profile_enable(on: bool = True):

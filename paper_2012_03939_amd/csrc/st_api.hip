@@ -6,6 +6,8 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -27,11 +29,18 @@ int fail(int code, const std::string& msg) {
         if (e_ != hipSuccess) return fail(ST_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+// set while the current call's stream is being captured into a graph: no
+// allocation may happen then
+thread_local bool g_capturing = false;
+
 struct GrowBuf {
     void* p = nullptr;
     size_t cap = 0;
     int ensure(size_t bytes) {
         if (bytes <= cap && p) return ST_OK;
+        if (g_capturing)
+            return fail(ST_ERR_INVALID_ARG, "workspace would grow during graph capture: make one uncaptured call "
+                                            "with the same shapes first");
         if (p) { hipFree(p); p = nullptr; cap = 0; }
         const size_t want = std::max<size_t>(bytes + bytes / 8, 256);
         if (hipMalloc(&p, want) != hipSuccess) { p = nullptr; return fail(ST_ERR_OOM, "device allocation failed"); }
@@ -95,7 +104,7 @@ bool make_devcam(const st_camera& c, DevCam& o) {
     o.W = c.width;
     o.H = c.height;
     o.scene = 0;
-    o.pad = 0;
+    o.rngview = 0;
     return true;
 }
 
@@ -134,6 +143,9 @@ struct st_scene {
     size_t pinned_cap = 0;
     hipEvent_t staged = nullptr;
     bool staged_valid = false;
+    std::vector<void*> graph_pinned;   // staging buffers referenced by captured graphs
+    long long tuned_cap = 0;           // autotuned wavefront chunk size (0: none)
+    int tuned_grid = 0;                // autotuned traversal grid (0: none)
 };
 
 namespace {
@@ -143,22 +155,24 @@ int check_scene(const st_scene* s) {
     return ST_OK;
 }
 
-// stage camera records and offset tables into device memory on stream s
+// stage camera records, offset tables and the scene table into device memory on stream s
 struct CamSetup {
     DevCam* cams = nullptr;
     long long* qoff = nullptr;
     long long* pixoff = nullptr;
     long long* eoff = nullptr;
+    DevScene* scenes = nullptr;
     long long total_paths = 0, total_pix = 0, total_edges = 0;
 };
 
-int setup_cams(st_scene* owner, const st_camera* cams, const int32_t* cam_scene, int32_t ncam, int32_t spp,
-               double ratio, int nscenes, hipStream_t s, CamSetup& out) {
+int setup_cams(st_scene* owner, st_scene* const* scenes, int nscenes, const st_camera* cams,
+               const int32_t* cam_scene, int32_t ncam, int32_t spp, double ratio, hipStream_t s, CamSetup& out) {
     if (!cams) return fail(ST_ERR_INVALID_ARG, "cams is NULL");
     if (ncam < 1 || ncam > 65535) return fail(ST_ERR_INVALID_ARG, "ncam must be in [1, 65535]");
     if (spp < 1 || spp > 65535) return fail(ST_ERR_INVALID_ARG, "spp must be in [1, 65535]");
     std::vector<DevCam> dc(ncam);
     std::vector<long long> qoff(ncam + 1), pix(ncam + 1), eoff(ncam + 1);
+    std::vector<int> per_scene(nscenes, 0);
     long long q = 0, p = 0, e = 0;
     for (int i = 0; i < ncam; ++i) {
         if (!make_devcam(cams[i], dc[i])) return fail(ST_ERR_INVALID_ARG, "invalid camera " + std::to_string(i));
@@ -166,6 +180,7 @@ int setup_cams(st_scene* owner, const st_camera* cams, const int32_t* cam_scene,
         if (hw >= (1ll << 31)) return fail(ST_ERR_INVALID_ARG, "image too large");
         dc[i].scene = cam_scene ? cam_scene[i] : 0;
         if (dc[i].scene < 0 || dc[i].scene >= nscenes) return fail(ST_ERR_INVALID_ARG, "cam_scene out of range");
+        dc[i].rngview = per_scene[dc[i].scene]++;
         const long long ne = (long long)std::llround(ratio * (double)cams[i].width * (double)cams[i].height * (double)spp);
         dc[i].qoff = q; dc[i].pixoff = p; dc[i].eoff = e; dc[i].ne = ne;
         qoff[i] = q; pix[i] = p; eoff[i] = e;
@@ -174,36 +189,49 @@ int setup_cams(st_scene* owner, const st_camera* cams, const int32_t* cam_scene,
     qoff[ncam] = q; pix[ncam] = p; eoff[ncam] = e;
     if (q >= (1ll << 31)) return fail(ST_ERR_INVALID_ARG, "more than 2^31 path samples in one call");
     if (e >= (1ll << 40)) return fail(ST_ERR_INVALID_ARG, "too many edge samples");
-    const size_t bytes = 256 + sizeof(DevCam) * ncam + 3 * 256 + 3 * sizeof(long long) * (ncam + 1);
+    const size_t bytes = 5 * 256 + sizeof(DevCam) * ncam + 3 * sizeof(long long) * (ncam + 1) +
+                         sizeof(DevScene) * nscenes;
+    hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
+    HIPCHK(hipStreamIsCapturing(s, &cst));
+    const bool capturing = cst != hipStreamCaptureStatusNone;
+    g_capturing = capturing;
     int rc = owner->camsbuf.ensure(bytes);
     if (rc) return rc;
-    if (owner->pinned_cap < bytes) {
+    void* staging = nullptr;
+    if (capturing) {
+        // a captured copy reads its source at every replay: give it a buffer of its own
+        HIPCHK(hipHostMalloc(&staging, bytes, hipHostMallocDefault));
+        owner->graph_pinned.push_back(staging);
+    } else {
         if (owner->staged_valid) HIPCHK(hipEventSynchronize(owner->staged));
-        if (owner->pinned) hipHostFree(owner->pinned);
-        owner->pinned = nullptr;
-        HIPCHK(hipHostMalloc(&owner->pinned, bytes, hipHostMallocDefault));
-        owner->pinned_cap = bytes;
-    } else if (owner->staged_valid) {
-        HIPCHK(hipEventSynchronize(owner->staged));
+        if (owner->pinned_cap < bytes) {
+            if (owner->pinned) hipHostFree(owner->pinned);
+            owner->pinned = nullptr;
+            owner->pinned_cap = 0;
+            HIPCHK(hipHostMalloc(&owner->pinned, bytes, hipHostMallocDefault));
+            owner->pinned_cap = bytes;
+        }
+        staging = owner->pinned;
     }
-    Carver hc{(char*)owner->pinned};
+    Carver hc{(char*)staging};
     Carver dcv{(char*)owner->camsbuf.p};
-    DevCam* hcam = hc.take<DevCam>(ncam);
-    long long* hq = hc.take<long long>(ncam + 1);
-    long long* hp = hc.take<long long>(ncam + 1);
-    long long* he = hc.take<long long>(ncam + 1);
-    std::memcpy(hcam, dc.data(), sizeof(DevCam) * ncam);
-    std::memcpy(hq, qoff.data(), sizeof(long long) * (ncam + 1));
-    std::memcpy(hp, pix.data(), sizeof(long long) * (ncam + 1));
-    std::memcpy(he, eoff.data(), sizeof(long long) * (ncam + 1));
+    std::memcpy(hc.take<DevCam>(ncam), dc.data(), sizeof(DevCam) * ncam);
+    std::memcpy(hc.take<long long>(ncam + 1), qoff.data(), sizeof(long long) * (ncam + 1));
+    std::memcpy(hc.take<long long>(ncam + 1), pix.data(), sizeof(long long) * (ncam + 1));
+    std::memcpy(hc.take<long long>(ncam + 1), eoff.data(), sizeof(long long) * (ncam + 1));
+    DevScene* hs = hc.take<DevScene>(nscenes);
+    for (int i = 0; i < nscenes; ++i) hs[i] = scenes[i]->d.hscene;
     out.cams = dcv.take<DevCam>(ncam);
     out.qoff = dcv.take<long long>(ncam + 1);
     out.pixoff = dcv.take<long long>(ncam + 1);
     out.eoff = dcv.take<long long>(ncam + 1);
-    HIPCHK(hipMemcpyAsync(owner->camsbuf.p, owner->pinned, hc.off, hipMemcpyHostToDevice, s));
-    if (!owner->staged) HIPCHK(hipEventCreateWithFlags(&owner->staged, hipEventDisableTiming));
-    HIPCHK(hipEventRecord(owner->staged, s));
-    owner->staged_valid = true;
+    out.scenes = dcv.take<DevScene>(nscenes);
+    HIPCHK(hipMemcpyAsync(owner->camsbuf.p, staging, hc.off, hipMemcpyHostToDevice, s));
+    if (!capturing) {
+        if (!owner->staged) HIPCHK(hipEventCreateWithFlags(&owner->staged, hipEventDisableTiming));
+        HIPCHK(hipEventRecord(owner->staged, s));
+        owner->staged_valid = true;
+    }
     out.total_paths = q;
     out.total_pix = p;
     out.total_edges = e;
@@ -217,7 +245,7 @@ int ensure_spill(st_scene* sc) {
 int make_queues(st_scene* sc, int cap, int nent, float* L, Queues& q) {
     const size_t per = 256;
     size_t bytes = 0;
-    bytes += (size_t)cap * 4 * (2 * 9 + 4 + 3 + 1 + 2 + 3 + 3 + 7 * std::max(nent, 1)) + 40 * per + 64 * 4;
+    bytes += (size_t)cap * 4 * (2 * 9 + 5 + 3 + 1 + 2 + 3 + 3 + 7 * std::max(nent, 1)) + 40 * per + 64 * 4;
     int rc = sc->qbuf.ensure(bytes);
     if (rc) return rc;
     Carver c{(char*)sc->qbuf.p};
@@ -227,6 +255,7 @@ int make_queues(st_scene* sc, int cap, int nent, float* L, Queues& q) {
     q.pc0 = c.take<uint32_t>(cap);
     q.pc1 = c.take<uint32_t>(cap);
     q.pdom = c.take<uint32_t>(cap);
+    q.pview = c.take<uint32_t>(cap);
     for (int i = 0; i < 3; ++i) q.pbeta[i] = c.take<float>(cap);
     q.phash = c.take<uint32_t>(cap);
     q.ht = c.take<float>(cap);
@@ -251,21 +280,13 @@ int render_impl(st_scene* owner, st_scene* const* scenes, int nscenes, const st_
     if (bounces < 1 || bounces > 8) return fail(ST_ERR_INVALID_ARG, "bounces must be in [1, 8]");
     st_render_opts o = opts ? *opts : st_render_opts_default();
     CamSetup cs;
-    int rc = setup_cams(owner, cams, cam_scene, ncam, spp, 0.0, nscenes, s, cs);
+    int rc = setup_cams(owner, scenes, nscenes, cams, cam_scene, ncam, spp, 0.0, s, cs);
     if (rc) return rc;
-    const DevScene* dscenes = owner->d.dscene;
+    const DevScene* dscenes = cs.scenes;
     int nent = 0, has_env_any = 0;
     for (int i = 0; i < nscenes; ++i) {
         nent = std::max(nent, scenes[i]->d.nl + (scenes[i]->d.has_env ? 1 : 0));
         has_env_any |= scenes[i]->d.has_env ? 1 : 0;
-    }
-    if (nscenes > 1) {
-        rc = owner->scenesbuf.ensure(sizeof(DevScene) * nscenes);
-        if (rc) return rc;
-        std::vector<DevScene> hs(nscenes);
-        for (int i = 0; i < nscenes; ++i) hs[i] = scenes[i]->d.hscene;
-        HIPCHK(hipMemcpyAsync(owner->scenesbuf.p, hs.data(), sizeof(DevScene) * nscenes, hipMemcpyHostToDevice, s));
-        dscenes = (const DevScene*)owner->scenesbuf.p;
     }
     rc = owner->Lbuf.ensure((size_t)cs.total_paths * 3 * sizeof(float));
     if (rc) return rc;
@@ -287,12 +308,13 @@ int render_impl(st_scene* owner, st_scene* const* scenes, int nscenes, const st_
     if (o.flags & ST_FORWARD_MEGAKERNEL) {
         launch_forward_mega(p, L, cs.total_paths, (uint32_t*)owner->spillbuf.p, TRACE_GRID, s);
     } else {
-        long long cap = o.queue_capacity > 0 ? o.queue_capacity : (1ll << 22);
+        long long cap = o.queue_capacity > 0 ? o.queue_capacity : (owner->tuned_cap > 0 ? owner->tuned_cap : (1ll << 22));
         cap = std::min<long long>(cap, std::max<long long>(cs.total_paths, 1));
         cap = std::min<long long>(cap, 1ll << 28);
         Queues q;
         rc = make_queues(owner, (int)cap, nent, L, q);
         if (rc) return rc;
+        q.grid = owner->tuned_grid;
         launch_forward_wavefront(p, q, cs.total_paths, has_env_any, nent, s);
     }
     launch_film(cs.cams, cs.pixoff, ncam, spp, L, cs.total_pix, out, s);
@@ -508,7 +530,8 @@ int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_
     st_render_opts o = opts ? *opts : st_render_opts_default();
     if (!(o.edge_spp_ratio >= 0.0f) || o.edge_spp_ratio > 64.0f) return fail(ST_ERR_INVALID_ARG, "edge_spp_ratio must be in [0, 64]");
     CamSetup cs;
-    rc = setup_cams(sc, cams, nullptr, ncam, spp, (double)o.edge_spp_ratio, 1, s, cs);
+    st_scene* list[1] = {sc};
+    rc = setup_cams(sc, list, 1, cams, nullptr, ncam, spp, (double)o.edge_spp_ratio, s, cs);
     if (rc) return rc;
     rc = ensure_spill(sc);
     if (rc) return rc;
@@ -518,7 +541,7 @@ int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_
     if (rc) return rc;
     Carver c{(char*)sc->primbuf.p};
     BwdParams p;
-    p.scenes = sc->d.dscene;
+    p.scenes = cs.scenes;
     p.cams = cs.cams;
     p.qoff = cs.qoff;
     p.eoff = cs.eoff;
@@ -557,15 +580,16 @@ int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_
             if (rc) return rc;
             hside = (uint32_t*)sc->sidehash.p;
         }
-        long long cap = o.queue_capacity > 0 ? o.queue_capacity : (1ll << 22);
+        long long cap = o.queue_capacity > 0 ? o.queue_capacity : (sc->tuned_cap > 0 ? sc->tuned_cap : (1ll << 22));
         cap = std::min<long long>(cap, std::max<long long>(2 * cs.total_edges, 2));
         cap = std::min<long long>(cap, 1ll << 28) & ~1ll;
         const int nent = sc->d.nl + (sc->d.has_env ? 1 : 0);
         Queues q;
         rc = make_queues(sc, (int)cap, nent, (float*)sc->sidebuf.p, q);
         if (rc) return rc;
+        q.grid = sc->tuned_grid;
         FwdParams fp;
-        fp.scenes = sc->d.dscene;
+        fp.scenes = cs.scenes;
         fp.cams = cs.cams;
         fp.qoff = cs.qoff;
         fp.ncam = ncam;
@@ -579,6 +603,93 @@ int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_
         launch_primary_edges(p, fp, q, (float*)sc->sidebuf.p, hside, cs.total_edges, sc->d.has_env ? 1 : 0, s);
     }
     HIPCHK(hipGetLastError());
+    return ST_OK;
+}
+
+int st_autotune(st_scene* const* scenes, int32_t nscenes, const st_camera* cams, const int32_t* cam_scene,
+                int32_t ncam, int32_t spp, int32_t bounces, const char* cache_path, int64_t* out_queue_capacity,
+                int32_t* out_trace_grid, hipStream_t s) {
+    if (!scenes || nscenes < 1) return fail(ST_ERR_INVALID_ARG, "need at least one scene");
+    for (int i = 0; i < nscenes; ++i)
+        if (!scenes[i]) return fail(ST_ERR_INVALID_ARG, "scene is NULL");
+    if (nscenes > 1 && !cam_scene) return fail(ST_ERR_INVALID_ARG, "cam_scene is NULL");
+    if (!cams || ncam < 1 || spp < 1 || bounces < 1 || bounces > 8) return fail(ST_ERR_INVALID_ARG, "bad workload");
+    // workload signature
+    long long paths = 0, pix = 0, faces = 0;
+    int env = 0, lights = 0;
+    for (int i = 0; i < ncam; ++i) { pix += (long long)cams[i].width * cams[i].height; }
+    paths = pix * spp;
+    for (int i = 0; i < nscenes; ++i) { faces += scenes[i]->d.nf; env += scenes[i]->d.has_env; lights += scenes[i]->d.nl; }
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, dev));
+    char sig[256];
+    std::snprintf(sig, sizeof(sig), "scenes=%d faces=%lld views=%d paths=%lld bounces=%d env=%d lights=%d", nscenes,
+                  faces, ncam, paths, bounces, env, lights);
+    std::string device = std::string(prop.gcnArchName) + " cu=" + std::to_string(prop.multiProcessorCount);
+    long long best_cap = 0;
+    int best_grid = 0;
+    if (cache_path) {
+        if (FILE* f = std::fopen(cache_path, "r")) {
+            char line[1024];
+            while (std::fgets(line, sizeof(line), f)) {
+                std::string l(line);
+                if (l.find("\"device\": \"" + device + "\"") == std::string::npos) continue;
+                if (l.find("\"key\": \"" + std::string(sig) + "\"") == std::string::npos) continue;
+                const size_t a0 = l.find("\"queue_capacity\": "), a1 = l.find("\"trace_grid\": ");
+                if (a0 == std::string::npos || a1 == std::string::npos) continue;
+                best_cap = std::atoll(l.c_str() + a0 + 18);
+                best_grid = std::atoi(l.c_str() + a1 + 14);
+            }
+            std::fclose(f);
+        }
+    }
+    if (best_cap <= 0) {
+        float* out = nullptr;
+        if (hipMalloc((void**)&out, sizeof(float) * 3 * (size_t)pix) != hipSuccess) return fail(ST_ERR_OOM, "autotune buffer");
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        const long long caps[] = {1ll << 24, 1ll << 23, 1ll << 22, 1ll << 21, 1ll << 20};
+        const int grids[] = {4096, 2048, 1024};
+        float best_ms = 1e30f;
+        st_render_opts o = st_render_opts_default();
+        int rc = ST_OK;
+        for (long long cap : caps) {
+            if (cap > 2 * std::max(paths, 1ll) && cap != (1ll << 20)) continue;
+            for (int grid : grids) {
+                for (int i = 0; i < nscenes; ++i) { scenes[i]->tuned_cap = cap; scenes[i]->tuned_grid = grid; }
+                float ms = 1e30f;
+                for (int rep = 0; rep < 3 && rc == ST_OK; ++rep) {
+                    HIPCHK(hipEventRecord(e0, s));
+                    rc = render_impl(scenes[0], scenes, nscenes, cams, cam_scene, ncam, spp, bounces, 0, &o, out, s);
+                    HIPCHK(hipEventRecord(e1, s));
+                    HIPCHK(hipEventSynchronize(e1));
+                    float t = 0.f;
+                    HIPCHK(hipEventElapsedTime(&t, e0, e1));
+                    if (rep > 0) ms = std::min(ms, t);     // the first run may allocate
+                }
+                if (rc) break;
+                if (ms < best_ms) { best_ms = ms; best_cap = cap; best_grid = grid; }
+            }
+            if (rc) break;
+        }
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        hipFree(out);
+        if (rc) return rc;
+        if (cache_path) {
+            if (FILE* f = std::fopen(cache_path, "a")) {
+                std::fprintf(f, "{\"device\": \"%s\", \"key\": \"%s\", \"queue_capacity\": %lld, \"trace_grid\": %d, \"ms\": %.4f}\n",
+                             device.c_str(), sig, best_cap, best_grid, best_ms);
+                std::fclose(f);
+            }
+        }
+    }
+    for (int i = 0; i < nscenes; ++i) { scenes[i]->tuned_cap = best_cap; scenes[i]->tuned_grid = best_grid; }
+    if (out_queue_capacity) *out_queue_capacity = best_cap;
+    if (out_trace_grid) *out_trace_grid = best_grid;
     return ST_OK;
 }
 
@@ -664,6 +775,7 @@ void st_scene_destroy(st_scene* sc) {
     sc->sidebuf.release(); sc->sidehash.release();
     sc->scenesbuf.release();
     if (sc->pinned) hipHostFree(sc->pinned);
+    for (void* g : sc->graph_pinned) hipHostFree(g);
     if (sc->staged) hipEventDestroy(sc->staged);
     delete sc;
 }

@@ -104,7 +104,7 @@ __global__ void __launch_bounds__(TRACE_BLOCK) k_adjoint(BwdParams p, long long 
         if (di[0] == 0.0f && di[1] == 0.0f && di[2] == 0.0f) continue;
         const V3 w = V3{di[0], di[1], di[2]} * (1.0f / (float)p.spp);
         const Key key{p.seed, S.scene_id};
-        const Ctr ctr{(uint32_t)(y * c.W + x), ((uint32_t)vw << 16) | (uint32_t)j, 0u, 0u};
+        const Ctr ctr{(uint32_t)(y * c.W + x), ((uint32_t)c.rngview << 16) | (uint32_t)j, 0u, 0u};
         const float4 u0 = draw4(ctr, 0, 0, key);
         const V3 d0 = cam_dir(c, (float)x + u0.x, (float)y + u0.y);
         Hash h{FNV_INIT, p.dbg_hash != nullptr};
@@ -423,7 +423,7 @@ __device__ __forceinline__ bool edge_setup(const BwdParams& p, long long ge, Edg
     const DevScene& S = p.scenes[c.scene];
     if (!(p.ptotal[es.v] > 0.0)) return false;
     es.si = ge - c.eoff;
-    const Ctr ctr{(uint32_t)es.si, (uint32_t)es.v << 16, 0u, 1u};
+    const Ctr ctr{(uint32_t)es.si, (uint32_t)c.rngview << 16, 0u, 1u};
     const float4 u = draw4(ctr, 0, 3, Key{p.seed, S.scene_id});
     es.e = cdf_find(p.pcdf + (size_t)es.v * (p.ne + 1), S.ne, (double)u.x);
     es.t = u.y;
@@ -489,7 +489,8 @@ __global__ void k_edge_camera(BwdParams p, Queues q, long long e0, int n) {
             const uint32_t lq = (uint32_t)(2 * ge + side);
             q.pq[s] = lq;
             q.pc0[s] = (uint32_t)es.si;
-            q.pc1[s] = (uint32_t)es.v << 16;
+            q.pc1[s] = (uint32_t)c.rngview << 16;
+            q.pview[s] = (uint32_t)es.v;
             q.pdom[s] = 1u;
             q.pbeta[0][s] = 1.0f; q.pbeta[1][s] = 1.0f; q.pbeta[2][s] = 1.0f;
             q.phash[s] = FNV_INIT;

@@ -508,7 +508,8 @@ __device__ __forceinline__ int env_sample(const DevScene& S, float4 u, V3& dir, 
 struct DevCam {
     float eye[3], f[3], rs[3], us[3];
     double deye[3], df[3], dr[3], du[3], dth, daspect;
-    int W, H, scene, pad;
+    int W, H, scene;
+    int rngview;         // view field of the random-stream counters: index among this scene's cameras
     long long qoff;      // processing-order path offset
     long long pixoff;    // canonical pixel offset
     long long eoff;      // primary edge sample offset

@@ -75,6 +75,7 @@ struct Queues {
     uint32_t* pc0;           // path: Philox c0 (pixel index)
     uint32_t* pc1;           // path: Philox c1 (view << 16 | sample)
     uint32_t* pdom;          // path: Philox c3 (stream domain)
+    uint32_t* pview;         // path: index of its camera in the call
     float* pbeta[3];
     uint32_t* phash;
     float* ht;               // hit t
@@ -88,6 +89,7 @@ struct Queues {
     uint32_t* spill;         // traversal stack spill
     float* L;                // per path sample radiance [total, 3] (processing order)
     int cap;                 // chunk capacity in paths
+    int grid;                // blocks of the traversal kernels (<= TRACE_GRID)
     int nent;                // shadow entries per shading point (nl + env)
 };
 

@@ -40,7 +40,7 @@ __global__ void k_camera(FwdParams p, Queues q, long long q0, int n) {
         const DevScene& S = p.scenes[c.scene];
         int x, y, j;
         decode_path(c, qq - c.qoff, p.spp, x, y, j);
-        const Ctr ctr{(uint32_t)(y * c.W + x), ((uint32_t)v << 16) | (uint32_t)j, 0u, 0u};
+        const Ctr ctr{(uint32_t)(y * c.W + x), ((uint32_t)c.rngview << 16) | (uint32_t)j, 0u, 0u};
         const float4 u = draw4(ctr, 0, 0, Key{p.seed, S.scene_id});
         const V3 d = cam_dir(c, (float)x + u.x, (float)y + u.y);
         float* const* r = q.ray[1];
@@ -53,6 +53,7 @@ __global__ void k_camera(FwdParams p, Queues q, long long q0, int n) {
         q.pc0[s] = ctr.c0;
         q.pc1[s] = ctr.c1;
         q.pdom[s] = 0u;
+        q.pview[s] = (uint32_t)v;
         q.pbeta[0][s] = 1.0f; q.pbeta[1][s] = 1.0f; q.pbeta[2][s] = 1.0f;
         q.phash[s] = FNV_INIT;
         q.L[3 * (size_t)qq] = 0.0f; q.L[3 * (size_t)qq + 1] = 0.0f; q.L[3 * (size_t)qq + 2] = 0.0f;
@@ -68,7 +69,7 @@ __global__ void __launch_bounds__(TRACE_BLOCK) k_extend(FwdParams p, Queues q, i
     const int stride = gridDim.x * blockDim.x;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const int slot = ((const int*)r[6])[i];
-        const uint32_t v = q.pc1[slot] >> 16;
+        const uint32_t v = q.pview[slot];
         const DevScene& S = p.scenes[p.cams[v].scene];
         const V3 o{r[0][i], r[1][i], r[2][i]}, d{r[3][i], r[4][i], r[5][i]};
         float t;
@@ -98,7 +99,7 @@ __global__ void k_shade(FwdParams p, Queues q, int k) {
         if (active) {
             slot = ((const int*)r[6])[i];
             const uint32_t c1 = q.pc1[slot];
-            const uint32_t v = c1 >> 16;
+            const uint32_t v = q.pview[slot];
             const DevScene& S = p.scenes[p.cams[v].scene];
             const Key key{p.seed, S.scene_id};
             const Ctr ctr{q.pc0[slot], c1, 0u, q.pdom[slot]};
@@ -214,7 +215,7 @@ __global__ void __launch_bounds__(TRACE_BLOCK) k_shadow(FwdParams p, Queues q, i
         const int f = q.sface[i];
         if (f < 0) continue;
         const int slot = ((const int*)r[6])[i];
-        const uint32_t v = q.pc1[slot] >> 16;
+        const uint32_t v = q.pview[slot];
         const DevScene& S = p.scenes[p.cams[v].scene];
         const V3 x{q.sx[0][i], q.sx[1][i], q.sx[2][i]};
         Hash h{q.phash[slot], true};
@@ -254,7 +255,7 @@ __global__ void k_chunk_hash(FwdParams p, Queues q, int n) {
     const int stride = gridDim.x * blockDim.x;
     for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += stride) {
         const long long qq = q.pq[s];
-        const int v = (int)(q.pc1[s] >> 16), j = (int)(q.pc1[s] & 0xFFFFu);
+        const int v = (int)q.pview[s], j = (int)(q.pc1[s] & 0xFFFFu);
         const DevCam& c = p.cams[v];
         const int x = (int)(q.pc0[s] % (uint32_t)c.W), y = (int)(q.pc0[s] / (uint32_t)c.W);
         p.dbg_hash[canon(c, x, y, j, p.spp)] = q.phash[s];
@@ -274,7 +275,7 @@ __global__ void __launch_bounds__(TRACE_BLOCK) k_forward_mega(FwdParams p, float
         const DevScene& S = p.scenes[c.scene];
         int x, y, j;
         decode_path(c, qq - c.qoff, p.spp, x, y, j);
-        const Ctr ctr{(uint32_t)(y * c.W + x), ((uint32_t)v << 16) | (uint32_t)j, 0u, 0u};
+        const Ctr ctr{(uint32_t)(y * c.W + x), ((uint32_t)c.rngview << 16) | (uint32_t)j, 0u, 0u};
         const Key key{p.seed, S.scene_id};
         const float4 u = draw4(ctr, 0, 0, key);
         const V3 d = cam_dir(c, (float)x + u.x, (float)y + u.y);
@@ -368,9 +369,7 @@ void launch_forward_wavefront(const FwdParams& p, Queues& q, long long total, in
     q.nent = nent;
     for (long long q0 = 0; q0 < total; q0 += q.cap) {
         const int n = (int)((total - q0) < q.cap ? (total - q0) : q.cap);
-        const unsigned g = grid_for(n, TRACE_BLOCK, TRACE_GRID);
         ST_LAUNCH("k_camera", k_camera, dim3(grid_for(n, 256, 1u << 20)), dim3(256), 0, st, p, q, q0, n);
-        (void)g;
         launch_wavefront_bounces(p, q, n, has_env_any, st);
         if (p.dbg_hash)
             ST_LAUNCH("k_chunk_hash", k_chunk_hash, dim3(grid_for(n, 256, 1u << 20)), dim3(256), 0, st, p, q, n);
@@ -380,11 +379,12 @@ void launch_forward_wavefront(const FwdParams& p, Queues& q, long long total, in
 // extension / shading / shadow kernels of every bounce for a chunk whose first
 // ray queue (queue 1) and count cnt[1] have been filled; n bounds the count
 void launch_wavefront_bounces(const FwdParams& p, Queues& q, int n, int has_env_any, hipStream_t st) {
-    const unsigned g = grid_for(n, TRACE_BLOCK, TRACE_GRID);
+    const unsigned gmax = (q.grid > 0 && (unsigned)q.grid < TRACE_GRID) ? (unsigned)q.grid : TRACE_GRID;
+    const unsigned g = grid_for(n, TRACE_BLOCK, gmax);
     const int last = p.B + (has_env_any ? 1 : 0);
     for (int k = 1; k <= last; ++k) {
         ST_LAUNCH("k_extend", k_extend, dim3(g), dim3(TRACE_BLOCK), 0, st, p, q, k);
-        ST_LAUNCH("k_shade", k_shade, dim3(grid_for(n, 256, TRACE_GRID)), dim3(256), 0, st, p, q, k);
+        ST_LAUNCH("k_shade", k_shade, dim3(grid_for(n, 256, gmax)), dim3(256), 0, st, p, q, k);
         if (k <= p.B) ST_LAUNCH("k_shadow", k_shadow, dim3(g), dim3(TRACE_BLOCK), 0, st, p, q, k);
     }
 }
