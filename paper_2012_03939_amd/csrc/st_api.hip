@@ -138,12 +138,11 @@ void st::prof_end(hipStream_t s) {
 
 struct st_scene {
     SceneDev d;
-    GrowBuf camsbuf, Lbuf, qbuf, spillbuf, primbuf, scenesbuf, sidebuf, sidehash;
-    void* pinned = nullptr;
-    size_t pinned_cap = 0;
-    hipEvent_t staged = nullptr;
-    bool staged_valid = false;
-    std::vector<void*> graph_pinned;   // staging buffers referenced by captured graphs
+    GrowBuf Lbuf, qbuf, spillbuf, primbuf, sidebuf, sidehash;
+    // immutable device tables of camera records, offsets and scene views, keyed
+    // by content: written once by an uncaptured call, then reused (also by graphs)
+    struct CamTable { uint64_t hash; std::vector<char> host; void* dev; void* pinned; };
+    std::vector<CamTable> tables;
     long long tuned_cap = 0;           // autotuned wavefront chunk size (0: none)
     int tuned_grid = 0;                // autotuned traversal grid (0: none)
 };
@@ -189,49 +188,52 @@ int setup_cams(st_scene* owner, st_scene* const* scenes, int nscenes, const st_c
     qoff[ncam] = q; pix[ncam] = p; eoff[ncam] = e;
     if (q >= (1ll << 31)) return fail(ST_ERR_INVALID_ARG, "more than 2^31 path samples in one call");
     if (e >= (1ll << 40)) return fail(ST_ERR_INVALID_ARG, "too many edge samples");
-    const size_t bytes = 5 * 256 + sizeof(DevCam) * ncam + 3 * sizeof(long long) * (ncam + 1) +
-                         sizeof(DevScene) * nscenes;
     hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
     HIPCHK(hipStreamIsCapturing(s, &cst));
     const bool capturing = cst != hipStreamCaptureStatusNone;
     g_capturing = capturing;
-    int rc = owner->camsbuf.ensure(bytes);
-    if (rc) return rc;
-    void* staging = nullptr;
-    if (capturing) {
-        // a captured copy reads its source at every replay: give it a buffer of its own
-        HIPCHK(hipHostMalloc(&staging, bytes, hipHostMallocDefault));
-        owner->graph_pinned.push_back(staging);
-    } else {
-        if (owner->staged_valid) HIPCHK(hipEventSynchronize(owner->staged));
-        if (owner->pinned_cap < bytes) {
-            if (owner->pinned) hipHostFree(owner->pinned);
-            owner->pinned = nullptr;
-            owner->pinned_cap = 0;
-            HIPCHK(hipHostMalloc(&owner->pinned, bytes, hipHostMallocDefault));
-            owner->pinned_cap = bytes;
-        }
-        staging = owner->pinned;
-    }
-    Carver hc{(char*)staging};
-    Carver dcv{(char*)owner->camsbuf.p};
-    std::memcpy(hc.take<DevCam>(ncam), dc.data(), sizeof(DevCam) * ncam);
-    std::memcpy(hc.take<long long>(ncam + 1), qoff.data(), sizeof(long long) * (ncam + 1));
-    std::memcpy(hc.take<long long>(ncam + 1), pix.data(), sizeof(long long) * (ncam + 1));
-    std::memcpy(hc.take<long long>(ncam + 1), eoff.data(), sizeof(long long) * (ncam + 1));
-    DevScene* hs = hc.take<DevScene>(nscenes);
+    // serialise the table on the host, then find or create its device copy
+    std::vector<char> host;
+    Carver hc{nullptr};
+    auto put = [&](const void* src, size_t n) {
+        const size_t off = hc.off = (hc.off + 255) & ~(size_t)255;
+        hc.off += n;
+        host.resize(hc.off);
+        std::memcpy(host.data() + off, src, n);
+        return off;
+    };
+    std::vector<DevScene> hs(nscenes);
     for (int i = 0; i < nscenes; ++i) hs[i] = scenes[i]->d.hscene;
-    out.cams = dcv.take<DevCam>(ncam);
-    out.qoff = dcv.take<long long>(ncam + 1);
-    out.pixoff = dcv.take<long long>(ncam + 1);
-    out.eoff = dcv.take<long long>(ncam + 1);
-    out.scenes = dcv.take<DevScene>(nscenes);
-    HIPCHK(hipMemcpyAsync(owner->camsbuf.p, staging, hc.off, hipMemcpyHostToDevice, s));
-    if (!capturing) {
-        if (!owner->staged) HIPCHK(hipEventCreateWithFlags(&owner->staged, hipEventDisableTiming));
-        HIPCHK(hipEventRecord(owner->staged, s));
-        owner->staged_valid = true;
+    const size_t o_cam = put(dc.data(), sizeof(DevCam) * ncam);
+    const size_t o_q = put(qoff.data(), sizeof(long long) * (ncam + 1));
+    const size_t o_p = put(pix.data(), sizeof(long long) * (ncam + 1));
+    const size_t o_e = put(eoff.data(), sizeof(long long) * (ncam + 1));
+    const size_t o_s = put(hs.data(), sizeof(DevScene) * nscenes);
+    uint64_t hv = 1469598103934665603ull;      // FNV-1a 64 of the serialised table
+    for (char ch : host) { hv ^= (unsigned char)ch; hv *= 1099511628211ull; }
+    char* dev = nullptr;
+    for (auto& t : owner->tables)
+        if (t.hash == hv && t.host == host) { dev = (char*)t.dev; break; }
+    if (!dev) {
+        if (capturing)
+            return fail(ST_ERR_INVALID_ARG, "cameras not staged: make one uncaptured call with the same cameras, "
+                                            "spp and edge ratio before capturing");
+        st_scene::CamTable t{hv, host, nullptr, nullptr};
+        if (hipMalloc(&t.dev, host.size()) != hipSuccess) return fail(ST_ERR_OOM, "camera table allocation failed");
+        if (hipHostMalloc(&t.pinned, host.size(), hipHostMallocDefault) != hipSuccess) {
+            hipFree(t.dev);
+            return fail(ST_ERR_OOM, "camera staging allocation failed");
+        }
+        std::memcpy(t.pinned, host.data(), host.size());
+        HIPCHK(hipMemcpyAsync(t.dev, t.pinned, host.size(), hipMemcpyHostToDevice, s));
+        owner->tables.push_back(std::move(t));
+        dev = (char*)owner->tables.back().dev;
     }
+    out.cams = (DevCam*)(dev + o_cam);
+    out.qoff = (long long*)(dev + o_q);
+    out.pixoff = (long long*)(dev + o_p);
+    out.eoff = (long long*)(dev + o_e);
+    out.scenes = (DevScene*)(dev + o_s);
     out.total_paths = q;
     out.total_pix = p;
     out.total_edges = e;
@@ -771,12 +773,12 @@ void st_scene_destroy(st_scene* sc) {
                     d.env_rows, d.env_total, d.texpdf, d.err, d.work, d.dscene};
     for (void* p : ptrs)
         if (p) hipFree(p);
-    sc->camsbuf.release(); sc->Lbuf.release(); sc->qbuf.release(); sc->spillbuf.release(); sc->primbuf.release();
+    sc->Lbuf.release(); sc->qbuf.release(); sc->spillbuf.release(); sc->primbuf.release();
     sc->sidebuf.release(); sc->sidehash.release();
-    sc->scenesbuf.release();
-    if (sc->pinned) hipHostFree(sc->pinned);
-    for (void* g : sc->graph_pinned) hipHostFree(g);
-    if (sc->staged) hipEventDestroy(sc->staged);
+    for (auto& t : sc->tables) {
+        if (t.dev) hipFree(t.dev);
+        if (t.pinned) hipHostFree(t.pinned);
+    }
     delete sc;
 }
 
