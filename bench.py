@@ -66,6 +66,7 @@ def parse():
     ap.add_argument("--views", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--opt-steps", type=int, default=200, help="optimisation-loop steps (0 skips)")
     ap.add_argument("--cpu-baseline-res", type=int, default=1024)
     ap.add_argument("--profile-only", action="store_true", help="one untimed step (for rocprofv3 runs)")
     return ap.parse_args()
@@ -204,7 +205,7 @@ def main():
     achieved = flops_per_launch / (avg_ms / 1e3) / 1e12
     kernels = {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[1] / args.steps} for k, v in prof.items()}
     out = {
-        "metric": "fwd+adjoint path samples/sec at 16 views 512^2 16spp",
+        "metric": "fwd+adjoint path samples/sec at 16 views 512^2 16spp; sec per optimisation step",
         "value": value,
         "unit": "path samples/s",
         "n_gpus": 1,
@@ -231,6 +232,10 @@ def main():
     }
     if not args.no_batched:
         out["batched"] = batched_vs_per_view(B, S, torch)
+    if args.opt_steps > 0:
+        # second half of the metric: seconds per optimisation step (Adam through torch.autograd)
+        from paper_2012_03939_amd.optimise import run as optimise
+        out["optimisation"] = optimise(steps=args.opt_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_baseline_res, spp, bounces)
     print(json.dumps(out))

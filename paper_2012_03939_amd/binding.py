@@ -154,6 +154,7 @@ class GPUScene:
                                  _ptr(ev), he, we, scene_id, _stream(), ctypes.byref(h)))
         self.h = h
         self.scene_id = scene_id
+        self.version = 0          # bumped by every update()
         info = (ctypes.c_int64 * 6)()
         _check(L.st_scene_info(self.h, info))
         self.ne = int(info[2])
@@ -175,6 +176,7 @@ class GPUScene:
 
     def update(self, V=None, mat=None):
         _check(load().st_scene_update(self.h, _ptr(V), _ptr(mat), _stream()))
+        self.version += 1
 
     def render(self, cams, spp: int, bounces: int, seed: int = 0, out=None, flags: int = 0, queue_capacity: int = 0,
                debug_hash=None, debug_radiance=None):
