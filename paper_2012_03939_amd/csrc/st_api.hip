@@ -246,31 +246,26 @@ int ensure_spill(st_scene* sc) {
 
 int make_queues(st_scene* sc, int cap, int nent, float* L, Queues& q) {
     const size_t per = 256;
-    size_t bytes = 0;
-    bytes += (size_t)cap * 4 * (2 * 9 + 5 + 3 + 1 + 2 + 3 + 3 + 7 * std::max(nent, 1)) + 40 * per + 64 * 4;
+    const size_t words = 2 * QNCOL + 2 + 3 + 4 + 7 * (size_t)std::max(nent, 1);
+    const size_t bytes = (size_t)cap * 4 * words + (words + 8) * per + 64 * 4;
     int rc = sc->qbuf.ensure(bytes);
     if (rc) return rc;
     Carver c{(char*)sc->qbuf.p};
     for (int b = 0; b < 2; ++b)
-        for (int i = 0; i < 9; ++i) q.ray[b][i] = c.take<float>(cap);
-    q.pq = c.take<uint32_t>(cap);
-    q.pc0 = c.take<uint32_t>(cap);
-    q.pc1 = c.take<uint32_t>(cap);
-    q.pdom = c.take<uint32_t>(cap);
-    q.pview = c.take<uint32_t>(cap);
-    for (int i = 0; i < 3; ++i) q.pbeta[i] = c.take<float>(cap);
-    q.phash = c.take<uint32_t>(cap);
+        for (int i = 0; i < QNCOL; ++i) q.ray[b][i] = c.take<float>(cap);
     q.ht = c.take<float>(cap);
     q.hf = c.take<int>(cap);
     for (int i = 0; i < 3; ++i) q.sx[i] = c.take<float>(cap);
     q.sface = c.take<int>(cap);
     q.sinfo = c.take<uint32_t>(cap);
     q.stex = c.take<int>(cap);
+    q.snext = c.take<int>(cap);
     for (int i = 0; i < 7; ++i) q.sh[i] = c.take<float>((size_t)cap * std::max(nent, 1));
     q.cnt = c.take<int>(64);
     q.spill = (uint32_t*)sc->spillbuf.p;
     q.L = L;
     q.cap = cap;
+    q.grid = 0;
     q.nent = nent;
     return ST_OK;
 }
@@ -433,6 +428,7 @@ int st_scene_create(const float* V, int32_t nv, const int32_t* F, int32_t nf, co
     A(dalloc(&d.tri, 3 * (size_t)nf));
     A(dalloc(&d.edges, edges.size()));
     A(dalloc(&d.edge_w, edges.size()));
+    A(dalloc(&d.eguide, (size_t)1 << guide_log2((int)edges.size())));
     A(dalloc(&d.ecdf, edges.size() + 1));
     A(dalloc(&d.etotal_d, 1));
     A(dalloc(&d.etotal_f, 1));
@@ -448,6 +444,8 @@ int st_scene_create(const float* V, int32_t nv, const int32_t* F, int32_t nf, co
         A(dalloc(&d.env_rows, he));
         A(dalloc(&d.env_total, 1));
         A(dalloc(&d.texpdf, (size_t)he * we));
+        A(dalloc(&d.mguide, (size_t)1 << guide_log2(he)));
+        A(dalloc(&d.cguide, (size_t)he << guide_log2(we)));
     }
     if (rc) { st_scene_destroy(sc); return rc; }
     auto cleanup_fail = [&](int code, const std::string& m) { st_scene_destroy(sc); return fail(code, m); };
@@ -485,6 +483,8 @@ int st_scene_create(const float* V, int32_t nv, const int32_t* F, int32_t nf, co
     h.V = d.V; h.F = d.F; h.mat = d.mat; h.lights = d.lights; h.fnorm = d.fnorm; h.tri = d.tri; h.nodes4 = d.nodes4;
     h.env = d.env; h.marg = d.marg; h.cond = d.cond; h.texpdf = d.texpdf; h.rowcos = d.rowcos;
     h.edges = d.edges; h.ecdf = d.ecdf; h.etotal = d.etotal_f;
+    h.eguide = d.eguide; h.mguide = d.mguide; h.cguide = d.cguide;
+    h.eglog = guide_log2(d.ne); h.mglog = guide_log2(he); h.cglog = guide_log2(we);
     h.nv = nv; h.nf = nf; h.nl = nl; h.he = he; h.we = we; h.ne = d.ne; h.has_env = d.has_env ? 1 : 0;
     h.scene_id = scene_id;
     HIPCHK2(hipMemcpyAsync(d.dscene, &h, sizeof(DevScene), hipMemcpyHostToDevice, s));
@@ -538,7 +538,9 @@ int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_
     rc = ensure_spill(sc);
     if (rc) return rc;
     const int ne = sc->d.ne;
-    const size_t pbytes = sizeof(double) * ((size_t)ncam * ne + (size_t)ncam * (ne + 1) + ncam) + 3 * 256;
+    const int pglog = guide_log2(ne);
+    const size_t pbytes = sizeof(double) * ((size_t)ncam * ne + (size_t)ncam * (ne + 1) + ncam) +
+                          sizeof(int) * ((size_t)ncam << pglog) + sizeof(double) * 2 * (size_t)ncam * ne + 5 * 256;
     rc = sc->primbuf.ensure(pbytes);
     if (rc) return rc;
     Carver c{(char*)sc->primbuf.p};
@@ -565,6 +567,9 @@ int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_
     p.pw = c.take<double>((size_t)ncam * ne);
     p.pcdf = c.take<double>((size_t)ncam * (ne + 1));
     p.ptotal = c.take<double>(ncam);
+    p.pguide = c.take<int>((size_t)ncam << pglog);
+    p.pglog = pglog;
+    p.pacc = c.take<double>(2 * (size_t)ncam * ne);
     p.ne = ne;
     launch_fill_f32(out_dV, 3ll * sc->d.nv, 0.0f, s);
     launch_fill_f32(out_dmat, 7ll * sc->d.nf, 0.0f, s);
@@ -769,7 +774,7 @@ void st_scene_destroy(st_scene* sc) {
     SceneDev& d = sc->d;
     void* ptrs[] = {d.V, d.F, d.mat, d.lights, d.env, d.fnorm, d.bmin, d.bmax, d.cen, d.bounds, d.mkeys[0], d.mkeys[1],
                     d.mvals[0], d.mvals[1], d.rs_hist, d.keys64, d.child, d.parent, d.aabb, d.refit_cnt, d.nodes4, d.flag4, d.id4,
-                    d.tri, d.edges, d.edge_w, d.ecdf, d.etotal_d, d.etotal_f, d.row_dom, d.rowcos, d.cond, d.marg,
+                    d.tri, d.edges, d.edge_w, d.eguide, d.mguide, d.cguide, d.ecdf, d.etotal_d, d.etotal_f, d.row_dom, d.rowcos, d.cond, d.marg,
                     d.env_rows, d.env_total, d.texpdf, d.err, d.work, d.dscene};
     for (void* p : ptrs)
         if (p) hipFree(p);

@@ -184,7 +184,7 @@ __global__ void __launch_bounds__(TRACE_BLOCK) k_adjoint(BwdParams p, long long 
                 const bool continues = (k < p.B) || S.has_env;
                 if (want_secondary && continues && S.ne > 0 && *S.etotal > 0.0f) {
                     const float4 u = draw4(ctr, k, 3, key);
-                    put(rse, k - 1, cdf_find(S.ecdf, S.ne, (double)u.x));
+                    put(rse, k - 1, cdf_guided(S.ecdf, S.ne, S.eguide, S.eglog, (double)u.x));
                     put(rte, k - 1, u.y);
                 }
                 put(rf, k - 1, f);
@@ -425,7 +425,8 @@ __device__ __forceinline__ bool edge_setup(const BwdParams& p, long long ge, Edg
     es.si = ge - c.eoff;
     const Ctr ctr{(uint32_t)es.si, (uint32_t)c.rngview << 16, 0u, 1u};
     const float4 u = draw4(ctr, 0, 3, Key{p.seed, S.scene_id});
-    es.e = cdf_find(p.pcdf + (size_t)es.v * (p.ne + 1), S.ne, (double)u.x);
+    es.e = cdf_guided(p.pcdf + (size_t)es.v * (p.ne + 1), S.ne, p.pguide + ((size_t)es.v << p.pglog), p.pglog,
+                      (double)u.x);
     es.t = u.y;
     const int4 E = S.edges[es.e];
     double ax, ay, az, bx, by, bz;
@@ -481,19 +482,17 @@ __global__ void k_edge_camera(BwdParams p, Queues q, long long e0, int n) {
         for (int side = 0; side < 2; ++side) {
             const int s = o0 + side;
             const V3 d = side_dir(c, es, side);
-            r[0][s] = c.eye[0]; r[1][s] = c.eye[1]; r[2][s] = c.eye[2];
-            r[3][s] = d.x; r[4][s] = d.y; r[5][s] = d.z;
-            ((int*)r[6])[s] = s;
-            ((int*)r[7])[s] = -1;
-            r[8][s] = 0.0f;
+            r[QOX][s] = c.eye[0]; r[QOY][s] = c.eye[1]; r[QOZ][s] = c.eye[2];
+            r[QDX][s] = d.x; r[QDY][s] = d.y; r[QDZ][s] = d.z;
+            qu(r, QEXCL, s) = 0xFFFFFFFFu;
+            r[QPPREV][s] = 0.0f;
             const uint32_t lq = (uint32_t)(2 * ge + side);
-            q.pq[s] = lq;
-            q.pc0[s] = (uint32_t)es.si;
-            q.pc1[s] = (uint32_t)c.rngview << 16;
-            q.pview[s] = (uint32_t)es.v;
-            q.pdom[s] = 1u;
-            q.pbeta[0][s] = 1.0f; q.pbeta[1][s] = 1.0f; q.pbeta[2][s] = 1.0f;
-            q.phash[s] = FNV_INIT;
+            qu(r, QQ, s) = lq;
+            qu(r, QC0, s) = (uint32_t)es.si;
+            qu(r, QC1, s) = (uint32_t)c.rngview << 16;
+            qu(r, QVD, s) = (uint32_t)es.v | (1u << 16);
+            r[QBR][s] = 1.0f; r[QBG][s] = 1.0f; r[QBB][s] = 1.0f;
+            qu(r, QHASH, s) = FNV_INIT;
             q.L[3 * (size_t)lq] = 0.0f; q.L[3 * (size_t)lq + 1] = 0.0f; q.L[3 * (size_t)lq + 2] = 0.0f;
         }
     }
@@ -526,10 +525,35 @@ __global__ void k_edge_grad(BwdParams p, const float* __restrict__ Ls, const uin
         const float* lm = Ls + 6 * ge;
         const double cc = ((double)di[0] * ((double)lm[0] - lm[3]) + (double)di[1] * ((double)lm[1] - lm[4]) +
                            (double)di[2] * ((double)lm[2] - lm[5])) * (p.ptotal[es.v] / (double)c.ne);
-        const int4 E = S.edges[es.e];
+        // the screen-space Jacobian and the edge normal depend on (view, edge) only:
+        // sum the two endpoint weights here, apply them once in k_edge_finish
+        double* acc = p.pacc + 2 * ((size_t)es.v * p.ne + es.e);
+        atomicAdd(acc, cc * (1.0 - es.t));
+        atomicAdd(acc + 1, cc * es.t);
+    }
+}
+
+// d(x_s, y_s)/d(vertex) of the perspective projection, contracted with the
+// screen-space edge normal and the accumulated endpoint weights of (view, edge)
+__global__ void k_edge_finish(BwdParams p) {
+#pragma clang fp contract(off)
+    const int v = blockIdx.y;
+    const DevCam& c = p.cams[v];
+    const DevScene& S = p.scenes[c.scene];
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < S.ne; e += gridDim.x * blockDim.x) {
+        const double* acc = p.pacc + 2 * ((size_t)v * p.ne + e);
+        const double w0 = acc[0], w1 = acc[1];
+        if (w0 == 0.0 && w1 == 0.0) continue;
+        const int4 E = S.edges[e];
+        double ax, ay, az, bx, by, bz;
+        project_d(c, S.V[3 * E.x], S.V[3 * E.x + 1], S.V[3 * E.x + 2], ax, ay, az);
+        project_d(c, S.V[3 * E.y], S.V[3 * E.y + 1], S.V[3 * E.y + 2], bx, by, bz);
+        const double dx = bx - ax, dy = by - ay;
+        const double l = sqrt(dx * dx + dy * dy);
+        const double nx = -dy / l, ny = dx / l;
         for (int end = 0; end < 2; ++end) {
             const int vid = end == 0 ? E.x : E.y;
-            const double wgt = end == 0 ? (1.0 - es.t) : es.t;
+            const double wgt = end == 0 ? w0 : w1;
             const double qx = (double)S.V[3 * vid] - c.deye[0], qy = (double)S.V[3 * vid + 1] - c.deye[1],
                          qz = (double)S.V[3 * vid + 2] - c.deye[2];
             const double z = qx * c.df[0] + qy * c.df[1] + qz * c.df[2];
@@ -541,7 +565,7 @@ __global__ void k_edge_grad(BwdParams p, const float* __restrict__ Ls, const uin
             for (int k3 = 0; k3 < 3; ++k3) {
                 const double dsx = kx * (c.dr[k3] * z - aa * c.df[k3]);
                 const double dsy = ky * (c.du[k3] * z - bb * c.df[k3]);
-                gv[k3] = cc * wgt * (dsx * es.nx + dsy * es.ny);
+                gv[k3] = wgt * (dsx * nx + dsy * ny);
             }
             atomic_add3(p.dV + 3 * (size_t)vid, V3{(float)gv[0], (float)gv[1], (float)gv[2]});
         }
@@ -560,16 +584,18 @@ void launch_primary_edges(const BwdParams& p, const FwdParams& fp, Queues& q, fl
     if (total_edges <= 0 || p.ne <= 0) return;
     ST_LAUNCH("k_prim_weights", k_prim_weights, dim3(gridb(p.ne, 256, 1024), p.ncam), dim3(256), 0, st, p);
     ST_LAUNCH("k_prim_cdf", k_prim_cdf, dim3(p.ncam), dim3(1024), 0, st, p);
+    launch_guide(p.pcdf, p.ne, (size_t)(p.ne + 1), p.ncam, p.pguide, p.pglog, st);
     const long long per = q.cap / 2;
     for (long long e0 = 0; e0 < total_edges; e0 += per) {
         const int n = (int)((total_edges - e0) < per ? (total_edges - e0) : per);
         launch_fill_u32((uint32_t*)q.cnt, 16, 0u, st);
         ST_LAUNCH("k_edge_camera", k_edge_camera, dim3(gridb(n, 256, 1 << 20)), dim3(256), 0, st, p, q, e0, n);
         launch_wavefront_bounces(fp, q, 2 * n, has_env_any, st);
-        if (hside) launch_chunk_hash_by_q(fp, q, 2 * n, st);
     }
+    launch_fill_u32((uint32_t*)p.pacc, 4ll * p.ncam * p.ne, 0u, st);      // +0.0 doubles
     ST_LAUNCH("k_edge_grad", k_edge_grad, dim3(gridb(total_edges, 256, 1 << 16)), dim3(256), 0, st, p, Lside, hside,
               total_edges);
+    ST_LAUNCH("k_edge_finish", k_edge_finish, dim3(gridb(p.ne, 256, 1024), p.ncam), dim3(256), 0, st, p);
 }
 
 void launch_backward(const BwdParams& p, long long total_paths, long long total_edges, int grid, hipStream_t st) {

@@ -369,6 +369,29 @@ __global__ void k_env_pdf(const float* __restrict__ env, int he, int we, const d
     texpdf[i] = tot > 0.0 ? (float)((m * dom[r]) / tot / dom[r]) : 0.0f;
 }
 
+// guide tables: for CDF row y (blockIdx.y), guide[g] = largest i in [0, n-1]
+// with C[i] <= g / 2^glog (C[0] == 0)
+__global__ void k_guide(const double* __restrict__ C, int n, size_t cstride, int* guide, int glog) {
+    const int G = 1 << glog;
+    const double* Cr = C + cstride * blockIdx.y;
+    int* gr = guide + ((size_t)blockIdx.y << glog);
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < G; g += gridDim.x * blockDim.x)
+        gr[g] = cdf_find(Cr, n, (double)g / (double)G);
+}
+
+void launch_guide(const double* C, int n, size_t cstride, int rows, int* guide, int glog, hipStream_t st) {
+    if (n <= 0 || rows <= 0) return;
+    const int G = 1 << glog;
+    ST_LAUNCH("k_guide", k_guide, dim3((G + 255) / 256 < 1024 ? (G + 255) / 256 : 1024, rows), dim3(256), 0, st, C, n,
+              cstride, guide, glog);
+}
+
+int guide_log2(int n) {
+    int l = 0;
+    while ((1 << l) < n && l < 24) ++l;
+    return l;
+}
+
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
@@ -412,6 +435,7 @@ void launch_scene_geometry(SceneDev& s, hipStream_t st) {
         ST_LAUNCH("k_edge_len", k_edge_len, dim3(nb(s.ne, 256)), dim3(256), 0, st, s.edges, s.ne, s.V, s.edge_w);
         ST_LAUNCH("k_edge_cdf", k_edge_cdf, dim3(1), dim3(1024), 0, st, s.edge_w, s.ne, s.ecdf, s.etotal_d,
                            s.etotal_f);
+        launch_guide(s.ecdf, s.ne, 0, 1, s.eguide, guide_log2(s.ne), st);
     }
 }
 
@@ -420,6 +444,8 @@ void launch_env_build(SceneDev& s, hipStream_t st) {
     ST_LAUNCH("k_env_rows", k_env_rows, dim3(nb(s.he, 64)), dim3(64), 0, st, s.env, s.he, s.we, s.row_dom, s.cond,
                        s.env_rows);
     ST_LAUNCH("k_env_marg", k_env_marg, dim3(1), dim3(64), 0, st, s.env_rows, s.he, s.marg, s.env_total);
+    launch_guide(s.marg, s.he, 0, 1, s.mguide, guide_log2(s.he), st);
+    launch_guide(s.cond, s.we, (size_t)(s.we + 1), s.he, s.cguide, guide_log2(s.we), st);
     ST_LAUNCH("k_env_pdf", k_env_pdf, dim3(nb((long long)s.he * s.we, 256)), dim3(256), 0, st, s.env, s.he, s.we,
                        s.row_dom, s.env_total, s.texpdf);
 }

@@ -121,6 +121,10 @@ struct DevScene {
     const int4* edges;    // [ne] (va, vb, f1, f2)
     const double* ecdf;   // [ne+1] cumulative 3-D length / total
     const float* etotal;  // total 3-D edge length
+    const int* eguide;    // guide table of ecdf, 2^eglog entries
+    const int* mguide;    // guide table of the env marginal CDF, 2^mglog entries
+    const int* cguide;    // guide tables of the env conditional CDFs, 2^cglog entries per row
+    int eglog, mglog, cglog;
     int nv, nf, nl, he, we, ne, has_env;
     uint32_t scene_id;
 };
@@ -188,6 +192,11 @@ __device__ __forceinline__ void node4_test(const float4* nodes4, uint32_t node, 
     }
 }
 
+// c[s] for a lane-varying s without indexing a register array
+__device__ __forceinline__ uint32_t slot_code(const uint32_t c[4], int s) {
+    return s == 0 ? c[0] : (s == 1 ? c[1] : (s == 2 ? c[2] : c[3]));
+}
+
 __device__ __forceinline__ void cswap(float& ta, uint32_t& ca, float& tb, uint32_t& cb) {
     if (tb < ta) {
         const float t = ta; ta = tb; tb = t;
@@ -219,9 +228,17 @@ __device__ int trace_closest(const DevScene& S, V3 o, V3 d, float tmin, int excl
         float t[4];
         uint32_t c[4];
         node4_test(S.nodes4, node, o, inv, tmin, tbest, t, c);
+        // hit leaf slots, tested in slot order at one site (a wave runs the
+        // largest per-lane count of leaf tests, not one block per slot)
+        uint32_t lm = 0;
 #pragma unroll
         for (int s = 0; s < 4; ++s)
-            if (t[s] < INF && (c[s] & LEAF_BIT)) { leaf(c[s] & ~LEAF_BIT); t[s] = INF; }
+            if (t[s] < INF && (c[s] & LEAF_BIT)) { lm |= 1u << s; t[s] = INF; }
+        while (lm) {
+            const int s = __builtin_ctz(lm);
+            lm &= lm - 1;
+            leaf(slot_code(c, s) & ~LEAF_BIT);
+        }
 #pragma unroll
         for (int s = 0; s < 4; ++s)
             if (t[s] > tbest) t[s] = INF;
@@ -273,12 +290,15 @@ __device__ bool trace_any_impl(const DevScene& S, V3 o, V3 d, float tmin, float 
         float t[4];
         uint32_t c[4];
         node4_test(S.nodes4, node, o, inv, tmin, tmax, t, c);
+        uint32_t lm = 0;
 #pragma unroll
         for (int s = 0; s < 4; ++s)
-            if (t[s] < INF && (c[s] & LEAF_BIT)) {
-                if (leaf(c[s] & ~LEAF_BIT)) return true;
-                t[s] = INF;
-            }
+            if (t[s] < INF && (c[s] & LEAF_BIT)) { lm |= 1u << s; t[s] = INF; }
+        while (lm) {
+            const int s = __builtin_ctz(lm);
+            lm &= lm - 1;
+            if (leaf(slot_code(c, s) & ~LEAF_BIT)) return true;
+        }
         int next = -1;
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -291,7 +311,7 @@ __device__ bool trace_any_impl(const DevScene& S, V3 o, V3 d, float tmin, float 
             }
         }
         if (next >= 0) {
-            node = next == 0 ? c[0] : (next == 1 ? c[1] : (next == 2 ? c[2] : c[3]));
+            node = slot_code(c, next);
         } else {
             if (sp == 0) return false;
             node = st.get(--sp);
@@ -453,6 +473,23 @@ __device__ __forceinline__ void brdf_backward(V3 wi, V3 wo, V3 n, const Mat& m, 
 // ---------------------------------------------------------------------------
 // environment map: equirectangular, +y up, row 0 at theta = 0
 // ---------------------------------------------------------------------------
+// guide table of a CDF (cut-point method): guide[g] = largest i in [0, n-1] with
+// C[i] <= g / G, G = 2^glog.  With g = floor(u G) the answer of cdf_find lies in
+// [guide[g], guide[g + 1]], so a search of that (usually one- or two-entry)
+// range returns exactly the index of the plain search.
+__device__ __forceinline__ int cdf_guided(const double* C, int n, const int* guide, int glog, double u) {
+    const int G = 1 << glog;
+    int g = (int)(u * (double)G);
+    g = g < G - 1 ? g : G - 1;
+    int lo = guide[g];
+    int hi = g + 1 < G ? guide[g + 1] : n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (C[mid] <= u) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 __device__ __forceinline__ int cdf_find(const double* C, int n, double u) {
     // largest i in [0, n-1] with C[i] <= u (C[0] == 0 <= u)
     int lo = 0, hi = n - 1;
@@ -475,8 +512,9 @@ __device__ __forceinline__ int env_texel_of(const DevScene& S, V3 d) {
 __device__ __forceinline__ V3 env_rgb(const DevScene& S, int t) { return ld3(S.env + 3 * (size_t)t); }
 
 __device__ __forceinline__ int env_sample(const DevScene& S, float4 u, V3& dir, float& pdf) {
-    const int r = cdf_find(S.marg, S.he, (double)u.x);
-    const int c = cdf_find(S.cond + (size_t)r * (S.we + 1), S.we, (double)u.y);
+    const int r = cdf_guided(S.marg, S.he, S.mguide, S.mglog, (double)u.x);
+    const int c = cdf_guided(S.cond + (size_t)r * (S.we + 1), S.we, S.cguide + ((size_t)r << S.cglog), S.cglog,
+                             (double)u.y);
     const float phi = 2.0f * PI_F * ((float)c + u.z) / (float)S.we;
     // cos(theta) uniform between the row's bounds; 1 -+ cos(theta) are taken
     // from the per-row tables of 1 - cos and 1 + cos so that sin(theta) keeps

@@ -45,6 +45,9 @@ struct SceneDev {
     // edges (topology fixed at creation)
     int4* edges = nullptr;
     double* edge_w = nullptr;
+    int* eguide = nullptr;                   // guide table of ecdf
+    int* mguide = nullptr;                   // guide table of the env marginal CDF
+    int* cguide = nullptr;                   // guide tables of the env conditional CDFs
     double* ecdf = nullptr;
     double* etotal_d = nullptr;
     float* etotal_f = nullptr;
@@ -68,22 +71,31 @@ struct Workspace {
     void* base = nullptr;
 };
 
+// columns of a ray queue (SoA, one float-sized word each): the ray and the state
+// of the path it continues, copied along on compaction so that every kernel
+// reads its queue entries coalesced
+enum QCol {
+    QOX, QOY, QOZ, QDX, QDY, QDZ,   // ray origin, direction
+    QEXCL,                          // face the ray leaves (int), -1 for camera rays
+    QPPREV,                         // BRDF pdf of the sampled direction (MIS at escape)
+    QQ,                             // index of the path's radiance slot
+    QC0, QC1,                       // Philox counter words c0, c1 of the path
+    QVD,                            // camera index | stream domain << 16
+    QBR, QBG, QBB,                  // throughput
+    QHASH,                          // decision hash (debug outputs only)
+    QNCOL
+};
+
 // queue and path-state arrays of one wavefront chunk (SoA)
 struct Queues {
-    float* ray[2][9];        // ox oy oz dx dy dz | slot excl (int bits) | pprev
-    uint32_t* pq;            // path: processing index q
-    uint32_t* pc0;           // path: Philox c0 (pixel index)
-    uint32_t* pc1;           // path: Philox c1 (view << 16 | sample)
-    uint32_t* pdom;          // path: Philox c3 (stream domain)
-    uint32_t* pview;         // path: index of its camera in the call
-    float* pbeta[3];
-    uint32_t* phash;
+    float* ray[2][QNCOL];    // queue of bounce k is ray[k & 1]
     float* ht;               // hit t
     int* hf;                 // hit face
     float* sx[3];            // shade record: hit point
     int* sface;              // shade record: face, -1 when no vertex
     uint32_t* sinfo;         // shade record: bit0 sampled, bit1 lobe, bit2 continued
     int* stex;               // shade record: env texel sampled
+    int* snext;              // shade record: index of the continuation in the next queue, -1 if none
     float* sh[7];            // shadow entries [entry][i]: dir xyz, tmax, contrib rgb
     int* cnt;                // ray counts per bounce
     uint32_t* spill;         // traversal stack spill
@@ -92,6 +104,8 @@ struct Queues {
     int grid;                // blocks of the traversal kernels (<= TRACE_GRID)
     int nent;                // shadow entries per shading point (nl + env)
 };
+
+__device__ __forceinline__ uint32_t& qu(float* const* cols, int c, int i) { return ((uint32_t*)cols[c])[i]; }
 
 struct FwdParams {
     const DevScene* scenes;
@@ -106,12 +120,13 @@ struct FwdParams {
 };
 
 void launch_scene_geometry(SceneDev& s, hipStream_t st);
+void launch_guide(const double* C, int n, size_t cstride, int rows, int* guide, int glog, hipStream_t st);
+int guide_log2(int n);
 void launch_env_build(SceneDev& s, hipStream_t st);
 
 void launch_forward_wavefront(const FwdParams& p, Queues& q, long long total, int has_env_any, int nent,
                               hipStream_t st);
 void launch_wavefront_bounces(const FwdParams& p, Queues& q, int n, int has_env_any, hipStream_t st);
-void launch_chunk_hash_by_q(const FwdParams& p, Queues& q, int n, hipStream_t st);
 void launch_forward_mega(const FwdParams& p, float* L, long long total, uint32_t* spill, int grid, hipStream_t st);
 void launch_film(const DevCam* cams, const long long* pixoff, int ncam, int spp, const float* L,
                  long long npix, float* out, hipStream_t st);
@@ -138,6 +153,9 @@ struct BwdParams {
     double* pcdf;            // per-view primary edge CDF [ncam, ne+1]
     double* pw;              // per-view primary edge weights [ncam, ne]
     double* ptotal;          // [ncam]
+    int* pguide;             // per-view guide tables of pcdf [ncam, 2^pglog]
+    int pglog;
+    double* pacc;            // per (view, edge): sums of c (1-t) and c t over its primary edge samples [ncam, ne, 2]
     int ne;
 };
 

@@ -29,10 +29,21 @@ __device__ __forceinline__ long long canon(const DevCam& c, int x, int y, int j,
     return (c.pixoff + (long long)y * c.W + x) * spp + j;
 }
 
+// final decision hash of a path: canonical debug slot, or the path's radiance slot
+__device__ __forceinline__ void final_hash(const FwdParams& p, float* const* r, int i, uint32_t h) {
+    if (p.hash_by_q) {
+        p.hash_by_q[qu(r, QQ, i)] = h;
+    } else if (p.dbg_hash) {
+        const DevCam& c = p.cams[qu(r, QVD, i) & 0xFFFFu];
+        p.dbg_hash[(c.pixoff + (long long)qu(r, QC0, i)) * p.spp + (qu(r, QC1, i) & 0xFFFFu)] = h;
+    }
+}
+
 // ---------------------------------------------------------------------------
 __global__ void k_camera(FwdParams p, Queues q, long long q0, int n) {
     const int stride = gridDim.x * blockDim.x;
     if (blockIdx.x == 0 && threadIdx.x < 16) q.cnt[threadIdx.x] = threadIdx.x == 1 ? n : 0;
+    float* const* r = q.ray[1];
     for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += stride) {
         const long long qq = q0 + s;
         const int v = find_view(p.qoff, p.ncam, qq);
@@ -43,19 +54,16 @@ __global__ void k_camera(FwdParams p, Queues q, long long q0, int n) {
         const Ctr ctr{(uint32_t)(y * c.W + x), ((uint32_t)c.rngview << 16) | (uint32_t)j, 0u, 0u};
         const float4 u = draw4(ctr, 0, 0, Key{p.seed, S.scene_id});
         const V3 d = cam_dir(c, (float)x + u.x, (float)y + u.y);
-        float* const* r = q.ray[1];
-        r[0][s] = c.eye[0]; r[1][s] = c.eye[1]; r[2][s] = c.eye[2];
-        r[3][s] = d.x; r[4][s] = d.y; r[5][s] = d.z;
-        ((int*)r[6])[s] = s;
-        ((int*)r[7])[s] = -1;
-        r[8][s] = 0.0f;
-        q.pq[s] = (uint32_t)qq;
-        q.pc0[s] = ctr.c0;
-        q.pc1[s] = ctr.c1;
-        q.pdom[s] = 0u;
-        q.pview[s] = (uint32_t)v;
-        q.pbeta[0][s] = 1.0f; q.pbeta[1][s] = 1.0f; q.pbeta[2][s] = 1.0f;
-        q.phash[s] = FNV_INIT;
+        r[QOX][s] = c.eye[0]; r[QOY][s] = c.eye[1]; r[QOZ][s] = c.eye[2];
+        r[QDX][s] = d.x; r[QDY][s] = d.y; r[QDZ][s] = d.z;
+        qu(r, QEXCL, s) = 0xFFFFFFFFu;
+        r[QPPREV][s] = 0.0f;
+        qu(r, QQ, s) = (uint32_t)qq;
+        qu(r, QC0, s) = ctr.c0;
+        qu(r, QC1, s) = ctr.c1;
+        qu(r, QVD, s) = (uint32_t)v;
+        r[QBR][s] = 1.0f; r[QBG][s] = 1.0f; r[QBB][s] = 1.0f;
+        qu(r, QHASH, s) = FNV_INIT;
         q.L[3 * (size_t)qq] = 0.0f; q.L[3 * (size_t)qq + 1] = 0.0f; q.L[3 * (size_t)qq + 2] = 0.0f;
     }
 }
@@ -68,12 +76,10 @@ __global__ void __launch_bounds__(TRACE_BLOCK) k_extend(FwdParams p, Queues q, i
     float* const* r = q.ray[k & 1];
     const int stride = gridDim.x * blockDim.x;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const int slot = ((const int*)r[6])[i];
-        const uint32_t v = q.pview[slot];
-        const DevScene& S = p.scenes[p.cams[v].scene];
-        const V3 o{r[0][i], r[1][i], r[2][i]}, d{r[3][i], r[4][i], r[5][i]};
+        const DevScene& S = p.scenes[p.cams[qu(r, QVD, i) & 0xFFFFu].scene];
+        const V3 o{r[QOX][i], r[QOY][i], r[QOZ][i]}, d{r[QDX][i], r[QDY][i], r[QDZ][i]};
         float t;
-        const int f = trace_closest(S, o, d, TMIN, ((const int*)r[7])[i], t, st);
+        const int f = trace_closest(S, o, d, TMIN, (int)qu(r, QEXCL, i), t, st);
         q.ht[i] = t;
         q.hf[i] = f;
     }
@@ -85,7 +91,7 @@ __global__ void k_shade(FwdParams p, Queues q, int k) {
     float* const* r = q.ray[k & 1];
     float* const* rn = q.ray[(k + 1) & 1];
     const int stride = gridDim.x * blockDim.x;
-    const int nent = q.nent;
+    const bool hashing = p.dbg_hash || p.hash_by_q;
     // every lane of a wave runs the same number of iterations so that the
     // compaction ballot below sees whole waves
     const int base0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63);
@@ -93,35 +99,36 @@ __global__ void k_shade(FwdParams p, Queues q, int k) {
         const int i = wb + (threadIdx.x & 63);
         const bool active = i < n;
         bool emit = false;
-        V3 x{0.f, 0.f, 0.f}, wi{0.f, 0.f, 0.f};
+        V3 x{0.f, 0.f, 0.f}, wi{0.f, 0.f, 0.f}, beta{0.f, 0.f, 0.f};
         float pb = 0.0f;
-        int f = -1, slot = 0;
+        int f = -1;
+        uint32_t hv = 0;
         if (active) {
-            slot = ((const int*)r[6])[i];
-            const uint32_t c1 = q.pc1[slot];
-            const uint32_t v = q.pview[slot];
-            const DevScene& S = p.scenes[p.cams[v].scene];
+            const uint32_t c0 = qu(r, QC0, i), c1 = qu(r, QC1, i), vd = qu(r, QVD, i);
+            const DevScene& S = p.scenes[p.cams[vd & 0xFFFFu].scene];
             const Key key{p.seed, S.scene_id};
-            const Ctr ctr{q.pc0[slot], c1, 0u, q.pdom[slot]};
-            Hash h{q.phash[slot], true};
-            V3 beta{q.pbeta[0][slot], q.pbeta[1][slot], q.pbeta[2][slot]};
-            const uint32_t qq = q.pq[slot];
+            const Ctr ctr{c0, c1, 0u, vd >> 16};
+            Hash h{hashing ? qu(r, QHASH, i) : 0u, hashing};
+            beta = V3{r[QBR][i], r[QBG][i], r[QBB][i]};
             f = q.hf[i];
             push_face(h, f);
             q.sface[i] = -1;
-            const V3 d{r[3][i], r[4][i], r[5][i]};
+            const V3 d{r[QDX][i], r[QDY][i], r[QDZ][i]};
             if (f < 0) {
                 if (S.has_env && k > 1) {
                     const int tex = env_texel_of(S, d);
                     h.push((uint32_t)tex);
-                    const float pp = r[8][i];
+                    const float pp = r[QPPREV][i];
                     const float w = pp / (pp + S.texpdf[tex]);
                     const V3 c = mul(beta, env_rgb(S, tex)) * w;
-                    float* L = q.L + 3 * (size_t)qq;
+                    float* L = q.L + 3 * (size_t)qu(r, QQ, i);
                     L[0] += c.x; L[1] += c.y; L[2] += c.z;
                 }
-            } else if (k <= p.B) {
-                const V3 o{r[0][i], r[1][i], r[2][i]};
+                if (hashing) final_hash(p, r, i, h.h);
+            } else if (k > p.B) {
+                if (hashing) final_hash(p, r, i, h.h);
+            } else {
+                const V3 o{r[QOX][i], r[QOY][i], r[QOZ][i]};
                 x = o + d * q.ht[i];
                 V3 n = xyz(S.fnorm[f]);
                 const V3 wo = -d;
@@ -174,17 +181,16 @@ __global__ void k_shade(FwdParams p, Queues q, int k) {
                         info |= 4u;
                         emit = true;
                         beta = mul(beta, brdf_eval(wi, wo, n, m)) * (ci / pb);
-                        q.pbeta[0][slot] = beta.x; q.pbeta[1][slot] = beta.y; q.pbeta[2][slot] = beta.z;
                     }
                 }
                 q.sface[i] = f;
                 q.sinfo[i] = info;
                 q.stex[i] = tex;
                 q.sx[0][i] = x.x; q.sx[1][i] = x.y; q.sx[2][i] = x.z;
+                q.snext[i] = -1;
             }
-            q.phash[slot] = h.h;
+            hv = h.h;
         }
-        (void)nent;
         // wave-level compaction of the continuing paths into the next queue
         const uint64_t mask = __ballot(emit);
         if (mask) {
@@ -194,13 +200,20 @@ __global__ void k_shade(FwdParams p, Queues q, int k) {
             basei = __shfl(basei, leader);
             if (emit) {
                 const int o = basei + __popcll(mask & lanemask_lt64());
-                rn[0][o] = x.x; rn[1][o] = x.y; rn[2][o] = x.z;
-                rn[3][o] = wi.x; rn[4][o] = wi.y; rn[5][o] = wi.z;
-                ((int*)rn[6])[o] = slot;
-                ((int*)rn[7])[o] = f;
-                rn[8][o] = pb;
+                rn[QOX][o] = x.x; rn[QOY][o] = x.y; rn[QOZ][o] = x.z;
+                rn[QDX][o] = wi.x; rn[QDY][o] = wi.y; rn[QDZ][o] = wi.z;
+                qu(rn, QEXCL, o) = (uint32_t)f;
+                rn[QPPREV][o] = pb;
+                qu(rn, QQ, o) = qu(r, QQ, i);
+                qu(rn, QC0, o) = qu(r, QC0, i);
+                qu(rn, QC1, o) = qu(r, QC1, i);
+                qu(rn, QVD, o) = qu(r, QVD, i);
+                rn[QBR][o] = beta.x; rn[QBG][o] = beta.y; rn[QBB][o] = beta.z;
+                if (hashing) qu(rn, QHASH, o) = hv;
+                q.snext[i] = o;
             }
         }
+        if (active && hashing) qu(r, QHASH, i) = hv;
     }
 }
 
@@ -210,15 +223,15 @@ __global__ void __launch_bounds__(TRACE_BLOCK) k_shadow(FwdParams p, Queues q, i
     TravStack st = make_stack(lds, q.spill, p.err, p.work ? p.work + 3 * WORK_SHADOW : nullptr);
     const int n = q.cnt[k];
     float* const* r = q.ray[k & 1];
+    float* const* rn = q.ray[(k + 1) & 1];
     const int stride = gridDim.x * blockDim.x;
+    const bool hashing = p.dbg_hash || p.hash_by_q;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const int f = q.sface[i];
         if (f < 0) continue;
-        const int slot = ((const int*)r[6])[i];
-        const uint32_t v = q.pview[slot];
-        const DevScene& S = p.scenes[p.cams[v].scene];
+        const DevScene& S = p.scenes[p.cams[qu(r, QVD, i) & 0xFFFFu].scene];
         const V3 x{q.sx[0][i], q.sx[1][i], q.sx[2][i]};
-        Hash h{q.phash[slot], true};
+        Hash h{hashing ? qu(r, QHASH, i) : 0u, hashing};
         V3 acc{0.f, 0.f, 0.f};
         const int nent = S.nl + (S.has_env ? 1 : 0);
         for (int l = 0; l < nent; ++l) {
@@ -239,27 +252,13 @@ __global__ void __launch_bounds__(TRACE_BLOCK) k_shadow(FwdParams p, Queues q, i
             h.push((info >> 1) & 1u);
             h.push((info >> 2) & 1u);
         }
-        q.phash[slot] = h.h;
-        float* L = q.L + 3 * (size_t)q.pq[slot];
+        float* L = q.L + 3 * (size_t)qu(r, QQ, i);
         L[0] += acc.x; L[1] += acc.y; L[2] += acc.z;
-    }
-}
-
-__global__ void k_chunk_hash_q(FwdParams p, Queues q) {
-    const int n = q.cnt[1];
-    const int stride = gridDim.x * blockDim.x;
-    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += stride) p.hash_by_q[q.pq[s]] = q.phash[s];
-}
-
-__global__ void k_chunk_hash(FwdParams p, Queues q, int n) {
-    const int stride = gridDim.x * blockDim.x;
-    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += stride) {
-        const long long qq = q.pq[s];
-        const int v = (int)q.pview[s], j = (int)(q.pc1[s] & 0xFFFFu);
-        const DevCam& c = p.cams[v];
-        const int x = (int)(q.pc0[s] % (uint32_t)c.W), y = (int)(q.pc0[s] / (uint32_t)c.W);
-        p.dbg_hash[canon(c, x, y, j, p.spp)] = q.phash[s];
-        (void)qq;
+        if (hashing) {
+            const int o = q.snext[i];
+            if (o >= 0) qu(rn, QHASH, o) = h.h;
+            else final_hash(p, r, i, h.h);
+        }
     }
 }
 
@@ -371,8 +370,6 @@ void launch_forward_wavefront(const FwdParams& p, Queues& q, long long total, in
         const int n = (int)((total - q0) < q.cap ? (total - q0) : q.cap);
         ST_LAUNCH("k_camera", k_camera, dim3(grid_for(n, 256, 1u << 20)), dim3(256), 0, st, p, q, q0, n);
         launch_wavefront_bounces(p, q, n, has_env_any, st);
-        if (p.dbg_hash)
-            ST_LAUNCH("k_chunk_hash", k_chunk_hash, dim3(grid_for(n, 256, 1u << 20)), dim3(256), 0, st, p, q, n);
     }
 }
 
@@ -387,10 +384,6 @@ void launch_wavefront_bounces(const FwdParams& p, Queues& q, int n, int has_env_
         ST_LAUNCH("k_shade", k_shade, dim3(grid_for(n, 256, gmax)), dim3(256), 0, st, p, q, k);
         if (k <= p.B) ST_LAUNCH("k_shadow", k_shadow, dim3(g), dim3(TRACE_BLOCK), 0, st, p, q, k);
     }
-}
-
-void launch_chunk_hash_by_q(const FwdParams& p, Queues& q, int n, hipStream_t st) {
-    ST_LAUNCH("k_chunk_hash_q", k_chunk_hash_q, dim3(grid_for(n, 256, 1u << 20)), dim3(256), 0, st, p, q);
 }
 
 void launch_forward_mega(const FwdParams& p, float* L, long long total, uint32_t* spill, int grid,
