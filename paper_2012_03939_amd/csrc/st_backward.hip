@@ -24,19 +24,6 @@
 
 namespace st {
 
-__device__ __forceinline__ TravStack make_stack_b(uint32_t* lds, uint32_t* spill, uint32_t* err,
-                                                  unsigned long long* work) {
-    TravStack s;
-    s.lds = lds;
-    s.spill = spill;
-    s.bs = blockDim.x;
-    s.tid = threadIdx.x;
-    s.gstride = gridDim.x * blockDim.x;
-    s.gid = blockIdx.x * blockDim.x + threadIdx.x;
-    s.err = err;
-    s.work = work;
-    return s;
-}
 
 template <class T, int N> __device__ __forceinline__ T sel(const T (&a)[N], int k) {
     T r = a[0];
@@ -89,7 +76,7 @@ constexpr uint32_t R_FLIP = 1u, R_ENV = 2u, R_CONT = 4u, R_ESC = 8u, R_SEC = 16u
 template <int BM>
 __global__ void __launch_bounds__(TRACE_BLOCK) k_adjoint(BwdParams p, long long total) {
     __shared__ uint32_t lds[LDS_STACK * TRACE_BLOCK];
-    TravStack st = make_stack_b(lds, p.spill, p.err, p.work ? p.work + 3 * WORK_ADJOINT : nullptr);
+    TravStack st = make_trav_stack(lds, p.spill, p.err, p.work ? p.work + 3 * WORK_ADJOINT : nullptr);
     const bool want_interior = p.flags & 1u, want_secondary = p.flags & 4u;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long qq = blockIdx.x * (long long)blockDim.x + threadIdx.x; qq < total; qq += stride) {

@@ -131,9 +131,16 @@ struct DevScene {
 
 // per-lane traversal stack: LDS_STACK entries in LDS (lane-interleaved), the
 // rest in a per-thread HBM spill region
+// address-space-qualified views: loads through them compile to global_load /
+// ds_read instead of generic flat accesses
+typedef float vf4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const vf4 gfloat4;
+typedef __attribute__((address_space(1))) uint32_t gu32;
+typedef __attribute__((address_space(3))) uint32_t lu32;
+
 struct TravStack {
-    uint32_t* lds;     // base of this block's LDS stack area; entry i of lane t at lds[i*bs + t]
-    uint32_t* spill;   // spill base; entry i of thread g at spill[i*gstride + g]
+    lu32* lds;         // base of this block's LDS stack area; entry i of lane t at lds[i*bs + t]
+    gu32* spill;       // spill base; entry i of thread g at spill[i*gstride + g]
     uint32_t bs, tid, gstride, gid;
     uint32_t* err;
     unsigned long long* work;   // optional: node visits, triangle tests, rays
@@ -142,20 +149,45 @@ struct TravStack {
         else spill[(i - LDS_STACK) * gstride + gid] = v;
     }
     __device__ __forceinline__ uint32_t get(int i) const {
-        return i < LDS_STACK ? lds[i * bs + tid] : spill[(i - LDS_STACK) * gstride + gid];
+        if (i < LDS_STACK) return lds[i * bs + tid];
+        return spill[(i - LDS_STACK) * gstride + gid];
     }
 };
 
+__device__ __forceinline__ TravStack make_trav_stack(uint32_t* lds, uint32_t* spill, uint32_t* err,
+                                                     unsigned long long* work) {
+    TravStack s;
+    s.lds = (lu32*)lds;
+    s.spill = (gu32*)spill;
+    s.bs = blockDim.x;
+    s.tid = threadIdx.x;
+    s.gstride = gridDim.x * blockDim.x;
+    s.gid = blockIdx.x * blockDim.x + threadIdx.x;
+    s.err = err;
+    s.work = work;
+    return s;
+}
+
+// the geometry one traversal reads, held in registers for the whole traversal
+struct TraceGeo {
+    const gfloat4* nodes4;
+    const gfloat4* tri;
+    int nf;
+};
+__device__ __forceinline__ TraceGeo trace_geo(const DevScene& S) {
+    return TraceGeo{(const gfloat4*)S.nodes4, (const gfloat4*)S.tri, S.nf};
+}
+
 // Moller-Trumbore, two-sided, on the leaf-ordered triangle record
-__device__ __forceinline__ bool tri_test(const float4* tri, uint32_t leaf, V3 o, V3 d, float tmin, float tmax,
+__device__ __forceinline__ bool tri_test(const gfloat4* tri, uint32_t leaf, V3 o, V3 d, float tmin, float tmax,
                                          float& t, int& face) {
-    const float4 a = tri[3 * leaf], b = tri[3 * leaf + 1], c = tri[3 * leaf + 2];
-    const V3 e1 = xyz(b), e2 = xyz(c);
+    const vf4 a = tri[3 * leaf], b = tri[3 * leaf + 1], c = tri[3 * leaf + 2];
+    const V3 e1 = V3{b.x, b.y, b.z}, e2 = V3{c.x, c.y, c.z};
     const V3 p = cross(d, e2);
     const float det = dot(e1, p);
     if (det == 0.0f) return false;
     const float inv = 1.0f / det;
-    const V3 s = o - xyz(a);
+    const V3 s = o - V3{a.x, a.y, a.z};
     const float b1 = dot(s, p) * inv;
     if (b1 < 0.0f || b1 > 1.0f) return false;
     const V3 q = cross(s, e1);
@@ -173,10 +205,10 @@ __device__ __forceinline__ V3 safe_inv(V3 d) {
 
 // slab test of the 4 child boxes of a 4-wide node; entry distance per slot,
 // +inf for a miss or an empty slot
-__device__ __forceinline__ void node4_test(const float4* nodes4, uint32_t node, V3 o, V3 inv, float tmin, float tmax,
+__device__ __forceinline__ void node4_test(const gfloat4* nodes4, uint32_t node, V3 o, V3 inv, float tmin, float tmax,
                                            float t[4], uint32_t c[4]) {
-    const float4* n = nodes4 + 8 * (size_t)node;
-    const float4 x0 = n[0], x1 = n[1], y0 = n[2], y1 = n[3], z0 = n[4], z1 = n[5], cc = n[6];
+    const gfloat4* n = nodes4 + 8 * (size_t)node;
+    const vf4 x0 = n[0], x1 = n[1], y0 = n[2], y1 = n[3], z0 = n[4], z1 = n[5], cc = n[6];
     const float lx[4] = {x0.x, x0.y, x0.z, x0.w}, hx[4] = {x1.x, x1.y, x1.z, x1.w};
     const float ly[4] = {y0.x, y0.y, y0.z, y0.w}, hy[4] = {y1.x, y1.y, y1.z, y1.w};
     const float lz[4] = {z0.x, z0.y, z0.z, z0.w}, hz[4] = {z1.x, z1.y, z1.z, z1.w};
@@ -209,16 +241,17 @@ __device__ int trace_closest(const DevScene& S, V3 o, V3 d, float tmin, int excl
     const float INF = __int_as_float(0x7f800000);
     float tbest = INF;
     int best = -1;
-    if (S.nf <= 0) return -1;
+    const TraceGeo G = trace_geo(S);
+    if (G.nf <= 0) return -1;
     uint32_t visits = 0, tests = 0;
     auto leaf = [&](uint32_t l) {
         ++tests;
         float t; int f;
-        if (tri_test(S.tri, l, o, d, tmin, INF, t, f) && f != exclude) {
+        if (tri_test(G.tri, l, o, d, tmin, INF, t, f) && f != exclude) {
             if (t < tbest || (t == tbest && f < best)) { tbest = t; best = f; }
         }
     };
-    if (S.nf == 1) { leaf(0); thit = tbest; return best; }
+    if (G.nf == 1) { leaf(0); thit = tbest; return best; }
     const V3 inv = safe_inv(d);
     uint32_t node = 0;
     int sp = 0;
@@ -227,7 +260,7 @@ __device__ int trace_closest(const DevScene& S, V3 o, V3 d, float tmin, int excl
         ++visits;
         float t[4];
         uint32_t c[4];
-        node4_test(S.nodes4, node, o, inv, tmin, tbest, t, c);
+        node4_test(G.nodes4, node, o, inv, tmin, tbest, t, c);
         // hit leaf slots, tested in slot order at one site (a wave runs the
         // largest per-lane count of leaf tests, not one block per slot)
         uint32_t lm = 0;
@@ -274,13 +307,14 @@ __device__ int trace_closest(const DevScene& S, V3 o, V3 d, float tmin, int excl
 __device__ bool trace_any_impl(const DevScene& S, V3 o, V3 d, float tmin, float tmax, int exclude, TravStack& st,
                                uint32_t& visits, uint32_t& tests) {
     const float INF = __int_as_float(0x7f800000);
-    if (S.nf <= 0) return false;
+    const TraceGeo G = trace_geo(S);
+    if (G.nf <= 0) return false;
     auto leaf = [&](uint32_t l) -> bool {
         ++tests;
         float t; int f;
-        return tri_test(S.tri, l, o, d, tmin, tmax, t, f) && f != exclude;
+        return tri_test(G.tri, l, o, d, tmin, tmax, t, f) && f != exclude;
     };
-    if (S.nf == 1) return leaf(0);
+    if (G.nf == 1) return leaf(0);
     const V3 inv = safe_inv(d);
     uint32_t node = 0;
     int sp = 0;
@@ -289,7 +323,7 @@ __device__ bool trace_any_impl(const DevScene& S, V3 o, V3 d, float tmin, float 
         ++visits;
         float t[4];
         uint32_t c[4];
-        node4_test(S.nodes4, node, o, inv, tmin, tmax, t, c);
+        node4_test(G.nodes4, node, o, inv, tmin, tmax, t, c);
         uint32_t lm = 0;
 #pragma unroll
         for (int s = 0; s < 4; ++s)

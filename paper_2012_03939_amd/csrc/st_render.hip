@@ -9,19 +9,6 @@
 
 namespace st {
 
-__device__ __forceinline__ TravStack make_stack(uint32_t* lds, uint32_t* spill, uint32_t* err,
-                                                unsigned long long* work) {
-    TravStack s;
-    s.lds = lds;
-    s.spill = spill;
-    s.bs = blockDim.x;
-    s.tid = threadIdx.x;
-    s.gstride = gridDim.x * blockDim.x;
-    s.gid = blockIdx.x * blockDim.x + threadIdx.x;
-    s.err = err;
-    s.work = work;
-    return s;
-}
 
 
 // canonical path index of a (view, pixel, sample)
@@ -71,7 +58,7 @@ __global__ void k_camera(FwdParams p, Queues q, long long q0, int n) {
 // closest hit for every queued ray of bounce k (queue k & 1)
 __global__ void __launch_bounds__(TRACE_BLOCK) k_extend(FwdParams p, Queues q, int k) {
     __shared__ uint32_t lds[LDS_STACK * TRACE_BLOCK];
-    TravStack st = make_stack(lds, q.spill, p.err, p.work ? p.work + 3 * WORK_EXTEND : nullptr);
+    TravStack st = make_trav_stack(lds, q.spill, p.err, p.work ? p.work + 3 * WORK_EXTEND : nullptr);
     const int n = q.cnt[k];
     float* const* r = q.ray[k & 1];
     const int stride = gridDim.x * blockDim.x;
@@ -220,7 +207,7 @@ __global__ void k_shade(FwdParams p, Queues q, int k) {
 // shadow rays of bounce k, one thread per shading point, fixed order
 __global__ void __launch_bounds__(TRACE_BLOCK) k_shadow(FwdParams p, Queues q, int k) {
     __shared__ uint32_t lds[LDS_STACK * TRACE_BLOCK];
-    TravStack st = make_stack(lds, q.spill, p.err, p.work ? p.work + 3 * WORK_SHADOW : nullptr);
+    TravStack st = make_trav_stack(lds, q.spill, p.err, p.work ? p.work + 3 * WORK_SHADOW : nullptr);
     const int n = q.cnt[k];
     float* const* r = q.ray[k & 1];
     float* const* rn = q.ray[(k + 1) & 1];
@@ -266,7 +253,7 @@ __global__ void __launch_bounds__(TRACE_BLOCK) k_shadow(FwdParams p, Queues q, i
 __global__ void __launch_bounds__(TRACE_BLOCK) k_forward_mega(FwdParams p, float* L, long long total,
                                                               uint32_t* spill) {
     __shared__ uint32_t lds[LDS_STACK * TRACE_BLOCK];
-    TravStack st = make_stack(lds, spill, p.err, p.work ? p.work + 3 * WORK_MEGA : nullptr);
+    TravStack st = make_trav_stack(lds, spill, p.err, p.work ? p.work + 3 * WORK_MEGA : nullptr);
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long qq = blockIdx.x * (long long)blockDim.x + threadIdx.x; qq < total; qq += stride) {
         const int v = find_view(p.qoff, p.ncam, qq);
@@ -336,7 +323,7 @@ __global__ void __launch_bounds__(TRACE_BLOCK) k_trace_debug(const DevScene* sc,
                                                              uint32_t* spill, uint32_t* err) {
     __shared__ uint32_t lds[LDS_STACK * TRACE_BLOCK];
     const DevScene& S = *sc;
-    TravStack st = make_stack(lds, spill, err, nullptr);
+    TravStack st = make_trav_stack(lds, spill, err, nullptr);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const V3 oo = ld3(o + 3 * i), dd = ld3(d + 3 * i);
@@ -345,7 +332,7 @@ __global__ void __launch_bounds__(TRACE_BLOCK) k_trace_debug(const DevScene* sc,
     if (brute) {
         for (int l = 0; l < S.nf; ++l) {
             float t; int f;
-            if (tri_test(S.tri, (uint32_t)l, oo, dd, tmin, __int_as_float(0x7f800000), t, f))
+            if (tri_test((const gfloat4*)S.tri, (uint32_t)l, oo, dd, tmin, __int_as_float(0x7f800000), t, f))
                 if (t < tb || (t == tb && f < fb)) { tb = t; fb = f; }
         }
     } else {
