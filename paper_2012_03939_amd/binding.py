@@ -211,7 +211,7 @@ class GPUScene:
 
     def read_work(self):
         """{kernel: (node visits, triangle tests, rays)} counted by ST_COUNT_WORK calls since the last read."""
-        out = (ctypes.c_uint64 * 12)()
+        out = (ctypes.c_uint64 * (3 * len(self.WORK_KERNELS)))()
         _check(load().st_read_work(self.h, out, _stream()))
         return {k: (int(out[3 * i]), int(out[3 * i + 1]), int(out[3 * i + 2])) for i, k in enumerate(self.WORK_KERNELS)}
 

@@ -245,9 +245,12 @@ int ensure_spill(st_scene* sc) {
 }
 
 int make_queues(st_scene* sc, int cap, int nent, float* L, Queues& q) {
+    // shadow entries are numbered l * n + i in a 32-bit index
+    cap = (int)std::min<long long>(cap, (0x7FFFFFFFll / std::max(nent, 1)) & ~1ll);
     const size_t per = 256;
     const size_t words = 2 * QNCOL + 2 + 3 + 4 + 7 * (size_t)std::max(nent, 1);
-    const size_t bytes = (size_t)cap * 4 * words + (words + 8) * per + 64 * 4;
+    const size_t bytes = (size_t)cap * 4 * words + (size_t)cap * std::max(nent, 1) + (words + 10) * per + 64 * 4 +
+                         FETCH_INTS * sizeof(int);
     int rc = sc->qbuf.ensure(bytes);
     if (rc) return rc;
     Carver c{(char*)sc->qbuf.p};
@@ -261,7 +264,9 @@ int make_queues(st_scene* sc, int cap, int nent, float* L, Queues& q) {
     q.stex = c.take<int>(cap);
     q.snext = c.take<int>(cap);
     for (int i = 0; i < 7; ++i) q.sh[i] = c.take<float>((size_t)cap * std::max(nent, 1));
+    q.socc = c.take<uint8_t>((size_t)cap * std::max(nent, 1));
     q.cnt = c.take<int>(64);
+    q.fetch = c.take<int>(FETCH_INTS);
     q.spill = (uint32_t*)sc->spillbuf.p;
     q.L = L;
     q.cap = cap;

@@ -575,7 +575,8 @@ void launch_primary_edges(const BwdParams& p, const FwdParams& fp, Queues& q, fl
     const long long per = q.cap / 2;
     for (long long e0 = 0; e0 < total_edges; e0 += per) {
         const int n = (int)((total_edges - e0) < per ? (total_edges - e0) : per);
-        launch_fill_u32((uint32_t*)q.cnt, 16, 0u, st);
+        launch_fill_u32((uint32_t*)q.cnt, 64, 0u, st);
+        launch_fill_u32((uint32_t*)q.fetch, FETCH_INTS, 0u, st);
         ST_LAUNCH("k_edge_camera", k_edge_camera, dim3(gridb(n, 256, 1 << 20)), dim3(256), 0, st, p, q, e0, n);
         launch_wavefront_bounces(fp, q, 2 * n, has_env_any, st);
     }

@@ -224,9 +224,37 @@ __device__ __forceinline__ void node4_test(const gfloat4* nodes4, uint32_t node,
     }
 }
 
-// c[s] for a lane-varying s without indexing a register array
-__device__ __forceinline__ uint32_t slot_code(const uint32_t c[4], int s) {
-    return s == 0 ? c[0] : (s == 1 ? c[1] : (s == 2 ? c[2] : c[3]));
+// leaf children of a visited node in slot order, kept in four registers: no
+// lane-varying index into a register array (which the compiler would move to
+// LDS), and one triangle-test site for all of them
+struct LeafList {
+    uint32_t l0 = 0, l1 = 0, l2 = 0, l3 = 0;
+    int n = 0;
+    __device__ __forceinline__ void add(uint32_t v) {
+        l0 = n == 0 ? v : l0;
+        l1 = n == 1 ? v : l1;
+        l2 = n == 2 ? v : l2;
+        l3 = n == 3 ? v : l3;
+        ++n;
+    }
+    __device__ __forceinline__ uint32_t pop() {
+        const uint32_t v = l0;
+        l0 = l1; l1 = l2; l2 = l3;
+        --n;
+        return v;
+    }
+};
+
+// moves the hit leaf children out of (t, c): their distance becomes +inf
+__device__ __forceinline__ LeafList take_leaves(float t[4], const uint32_t c[4]) {
+    LeafList L;
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+        if (t[s] < __int_as_float(0x7f800000) && (c[s] & LEAF_BIT)) {
+            L.add(c[s] & ~LEAF_BIT);
+            t[s] = __int_as_float(0x7f800000);
+        }
+    return L;
 }
 
 __device__ __forceinline__ void cswap(float& ta, uint32_t& ca, float& tb, uint32_t& cb) {
@@ -263,15 +291,8 @@ __device__ int trace_closest(const DevScene& S, V3 o, V3 d, float tmin, int excl
         node4_test(G.nodes4, node, o, inv, tmin, tbest, t, c);
         // hit leaf slots, tested in slot order at one site (a wave runs the
         // largest per-lane count of leaf tests, not one block per slot)
-        uint32_t lm = 0;
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-            if (t[s] < INF && (c[s] & LEAF_BIT)) { lm |= 1u << s; t[s] = INF; }
-        while (lm) {
-            const int s = __builtin_ctz(lm);
-            lm &= lm - 1;
-            leaf(slot_code(c, s) & ~LEAF_BIT);
-        }
+        LeafList lv = take_leaves(t, c);
+        while (lv.n > 0) leaf(lv.pop());
 #pragma unroll
         for (int s = 0; s < 4; ++s)
             if (t[s] > tbest) t[s] = INF;
@@ -324,28 +345,23 @@ __device__ bool trace_any_impl(const DevScene& S, V3 o, V3 d, float tmin, float 
         float t[4];
         uint32_t c[4];
         node4_test(G.nodes4, node, o, inv, tmin, tmax, t, c);
-        uint32_t lm = 0;
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-            if (t[s] < INF && (c[s] & LEAF_BIT)) { lm |= 1u << s; t[s] = INF; }
-        while (lm) {
-            const int s = __builtin_ctz(lm);
-            lm &= lm - 1;
-            if (leaf(slot_code(c, s) & ~LEAF_BIT)) return true;
-        }
-        int next = -1;
+        LeafList lv = take_leaves(t, c);
+        while (lv.n > 0)
+            if (leaf(lv.pop())) return true;
+        bool have = false;
+        uint32_t next = 0;
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             if (t[s] < INF) {
-                if (next < 0) next = s;
+                if (!have) { next = c[s]; have = true; }
                 else {
                     if (sp >= LDS_STACK + SPILL_STACK) { atomicOr(st.err, ERR_STACK); return false; }
                     st.put(sp++, c[s]);
                 }
             }
         }
-        if (next >= 0) {
-            node = slot_code(c, next);
+        if (have) {
+            node = next;
         } else {
             if (sp == 0) return false;
             node = st.get(--sp);
@@ -740,5 +756,151 @@ __device__ inline void block_scan_normalise(const double* w, int n, double* out,
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// persistent any-hit traversal of a queue of shadow rays with dynamic fetch:
+// a wave refills its idle lanes whenever at least FETCH_MIN of them are idle,
+// so a lane whose ray finished early takes the next ray instead of waiting for
+// the slowest lane of its wave.  Each ray's outcome is that of trace_any.
+// ---------------------------------------------------------------------------
+#ifndef ST_FETCH_MIN
+#define ST_FETCH_MIN 16
+#endif
+#ifndef ST_FETCH_CHUNK
+#define ST_FETCH_CHUNK 128
+#endif
+#ifndef ST_FETCH_NC
+#define ST_FETCH_NC 8
+#endif
+constexpr int FETCH_MIN = ST_FETCH_MIN;      // idle lanes that trigger a refill
+constexpr int FETCH_CHUNK = ST_FETCH_CHUNK;  // rays a wave takes from a counter at a time
+constexpr int FETCH_NC = ST_FETCH_NC;        // counters, each owning a contiguous segment of the queue
+constexpr int FETCH_SLOT_INTS = FETCH_NC * 32;   // one 128-byte line per counter
+
+struct RayJob {
+    V3 o, d;
+    float tmax;   // the ray is tested on (TMIN, tmax)
+    int excl;     // face excluded from the test (the ray's origin face), -1 for none
+    TraceGeo G;
+};
+
+// fetch(i, job) loads ray i and returns true, or stores ray i's outcome itself
+// and returns false when it needs no traversal; finish(i, occluded) stores it
+template <class Fetch, class Finish>
+__device__ __forceinline__ void trace_any_queue(int* counters, int n, TravStack& st, Fetch fetch, Finish finish) {
+    const float INF = __int_as_float(0x7f800000);
+    // a finished ray's outcome is stored when its lane is refilled (or at the
+    // end), so that no store is in flight while the traversal waits on loads
+    bool live = false, pend = false, occ = false, drained = n <= 0;
+    int idx = 0, sp = 0, iters = 0;
+    uint32_t node = 0;
+    RayJob J;
+    V3 inv{0.f, 0.f, 0.f};
+    uint32_t visits = 0, tests = 0, rays = 0;
+    // wave-uniform pool [cur, end) of rays taken from the counters; counter c
+    // hands out chunks of segment [c seg, (c + 1) seg), starting at this
+    // block's own counter and moving on to the others once it is used up
+    int cur = 0, end = 0, tried = 0;
+    const int seg = (int)(((long long)n + FETCH_NC - 1) / FETCH_NC);
+    const int home = (int)(blockIdx.x % FETCH_NC);
+    for (;;) {
+        const uint64_t idle = __ballot(!live);
+        const int nidle = __popcll(idle);
+        if ((cur < end || !drained) && (nidle >= FETCH_MIN || nidle == (int)__builtin_amdgcn_wavefrontsize())) {
+            const int leader = __ffsll((long long)idle) - 1;
+            while (cur >= end && !drained) {
+                const int c = (home + tried) % FETCH_NC;
+                int b = 0;
+                if ((int)__lane_id() == leader) b = atomicAdd(counters + 32 * c, FETCH_CHUNK);
+                b = __builtin_amdgcn_readlane(b, leader);   // wave-uniform from here on
+                const int s0 = c * seg, s1 = (int)min((long long)s0 + seg, (long long)n);
+                if (b < s1 - s0) {
+                    cur = s0 + b;
+                    end = (int)min((long long)cur + FETCH_CHUNK, (long long)s1);
+                } else if (++tried >= FETCH_NC) {
+                    drained = true;
+                }
+            }
+            if (pend) {
+                finish(idx, occ);
+                pend = false;
+            }
+            const int take = min(nidle, end - cur);
+            if (!live && take > 0) {
+                const int rank = __popcll(idle & lanemask_lt64());
+                if (rank < take) {
+                    idx = cur + rank;
+                    if (fetch(idx, J)) {
+                        if (J.G.nf <= 0) {
+                            finish(idx, false);
+                        } else if (J.G.nf == 1) {
+                            float t; int f;
+                            finish(idx, tri_test(J.G.tri, 0, J.o, J.d, TMIN, J.tmax, t, f) && f != J.excl);
+                        } else {
+                            live = true;
+                            ++rays;
+                            inv = safe_inv(J.d);
+                            node = 0; sp = 0; iters = 0; occ = false;
+                        }
+                    }
+                }
+            }
+            if (take > 0) cur += take;
+        }
+        if (nidle == (int)__builtin_amdgcn_wavefrontsize() && drained && cur >= end) break;
+        if (!live) continue;
+        bool done = false;
+        if (iters >= TRAVERSAL_CAP) {
+            atomicOr(st.err, ERR_LOOP);
+            done = true;
+        } else {
+            ++iters;
+            ++visits;
+            float t[4];
+            uint32_t c[4];
+            node4_test(J.G.nodes4, node, J.o, inv, TMIN, J.tmax, t, c);
+            LeafList lv = take_leaves(t, c);
+            while (lv.n > 0) {
+                ++tests;
+                float th; int fh;
+                if (tri_test(J.G.tri, lv.pop(), J.o, J.d, TMIN, J.tmax, th, fh) && fh != J.excl) { occ = true; break; }
+            }
+            if (occ) {
+                done = true;
+            } else {
+                bool have = false, overflow = false;
+                uint32_t next = 0;
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    if (t[s] < INF) {
+                        if (!have) { next = c[s]; have = true; }
+                        else if (sp >= LDS_STACK + SPILL_STACK) overflow = true;
+                        else st.put(sp++, c[s]);
+                    }
+                }
+                if (overflow) {
+                    atomicOr(st.err, ERR_STACK);
+                    done = true;
+                } else if (have) {
+                    node = next;
+                } else if (sp == 0) {
+                    done = true;
+                } else {
+                    node = st.get(--sp);
+                }
+            }
+        }
+        if (done) {
+            live = false;
+            pend = true;
+        }
+    }
+    if (pend) finish(idx, occ);
+    if (st.work && rays) {
+        atomicAdd(st.work, (unsigned long long)visits);
+        atomicAdd(st.work + 1, (unsigned long long)tests);
+        atomicAdd(st.work + 2, (unsigned long long)rays);
+    }
+}
 
 } // namespace st

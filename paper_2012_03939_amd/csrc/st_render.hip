@@ -29,7 +29,8 @@ __device__ __forceinline__ void final_hash(const FwdParams& p, float* const* r, 
 // ---------------------------------------------------------------------------
 __global__ void k_camera(FwdParams p, Queues q, long long q0, int n) {
     const int stride = gridDim.x * blockDim.x;
-    if (blockIdx.x == 0 && threadIdx.x < 16) q.cnt[threadIdx.x] = threadIdx.x == 1 ? n : 0;
+    if (blockIdx.x == 0 && threadIdx.x < 64) q.cnt[threadIdx.x] = threadIdx.x == 1 ? n : 0;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < FETCH_INTS; j += stride) q.fetch[j] = 0;
     float* const* r = q.ray[1];
     for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += stride) {
         const long long qq = q0 + s;
@@ -55,7 +56,10 @@ __global__ void k_camera(FwdParams p, Queues q, long long q0, int n) {
     }
 }
 
-// closest hit for every queued ray of bounce k (queue k & 1)
+// closest hit for every queued ray of bounce k (queue k & 1).  The 64 rays of
+// a wave are 64 consecutive queue entries (an 8x8 pixel tile for camera rays)
+// and are traced in lockstep: measured faster here than refilling idle lanes
+// (trace_any_queue), which pays off for the shadow rays only.
 __global__ void __launch_bounds__(TRACE_BLOCK) k_extend(FwdParams p, Queues q, int k) {
     __shared__ uint32_t lds[LDS_STACK * TRACE_BLOCK];
     TravStack st = make_trav_stack(lds, q.spill, p.err, p.work ? p.work + 3 * WORK_EXTEND : nullptr);
@@ -204,10 +208,41 @@ __global__ void k_shade(FwdParams p, Queues q, int k) {
     }
 }
 
-// shadow rays of bounce k, one thread per shading point, fixed order
+// shadow rays of bounce k: entry l of shading point i is item l * n + i;
+// persistent waves take items from the fetch counters of slot k and store one
+// outcome code per entry (0 no ray, 1 occluded, 2 unoccluded)
 __global__ void __launch_bounds__(TRACE_BLOCK) k_shadow(FwdParams p, Queues q, int k) {
     __shared__ uint32_t lds[LDS_STACK * TRACE_BLOCK];
     TravStack st = make_trav_stack(lds, q.spill, p.err, p.work ? p.work + 3 * WORK_SHADOW : nullptr);
+    const int n = q.cnt[k];
+    float* const* r = q.ray[k & 1];
+    const long long items = (long long)n * q.nent;
+    trace_any_queue(
+        q.fetch + FETCH_SLOT_INTS * k, (int)items, st,
+        [&](int w, RayJob& J) {
+            const int l = w / n, i = w - l * n;
+            const size_t e = (size_t)l * q.cap + i;
+            const int f = q.sface[i];
+            if (f < 0) return false;
+            const DevScene& S = p.scenes[p.cams[qu(r, QVD, i) & 0xFFFFu].scene];
+            if (l >= S.nl + (S.has_env ? 1 : 0)) return false;      // entry unused in this scene
+            const float tmax = q.sh[3][e];
+            if (!(tmax >= 0.0f)) { q.socc[e] = 0; return false; }
+            J.o = V3{q.sx[0][i], q.sx[1][i], q.sx[2][i]};
+            J.d = V3{q.sh[0][e], q.sh[1][e], q.sh[2][e]};
+            J.tmax = tmax;
+            J.excl = f;
+            J.G = trace_geo(S);
+            return true;
+        },
+        [&](int w, bool occ) {
+            const int l = w / n, i = w - l * n;
+            q.socc[(size_t)l * q.cap + i] = occ ? 1 : 2;
+        });
+}
+
+// shadow contributions of bounce k added per shading point in entry order
+__global__ void k_shadow_sum(FwdParams p, Queues q, int k) {
     const int n = q.cnt[k];
     float* const* r = q.ray[k & 1];
     float* const* rn = q.ray[(k + 1) & 1];
@@ -217,21 +252,14 @@ __global__ void __launch_bounds__(TRACE_BLOCK) k_shadow(FwdParams p, Queues q, i
         const int f = q.sface[i];
         if (f < 0) continue;
         const DevScene& S = p.scenes[p.cams[qu(r, QVD, i) & 0xFFFFu].scene];
-        const V3 x{q.sx[0][i], q.sx[1][i], q.sx[2][i]};
         Hash h{hashing ? qu(r, QHASH, i) : 0u, hashing};
         V3 acc{0.f, 0.f, 0.f};
         const int nent = S.nl + (S.has_env ? 1 : 0);
         for (int l = 0; l < nent; ++l) {
             const size_t e = (size_t)l * q.cap + i;
-            const float tmax = q.sh[3][e];
-            uint32_t code = 0;
             if (l == S.nl) h.push((uint32_t)q.stex[i]);
-            if (tmax >= 0.0f) {
-                const V3 dir{q.sh[0][e], q.sh[1][e], q.sh[2][e]};
-                const bool occ = trace_any(S, x, dir, TMIN, tmax, f, st);
-                code = occ ? 1u : 2u;
-                if (!occ) acc = acc + V3{q.sh[4][e], q.sh[5][e], q.sh[6][e]};
-            }
+            const uint32_t code = q.socc[e];
+            if (code == 2u) acc = acc + V3{q.sh[4][e], q.sh[5][e], q.sh[6][e]};
             h.push(code);
         }
         const uint32_t info = q.sinfo[i];
@@ -369,7 +397,10 @@ void launch_wavefront_bounces(const FwdParams& p, Queues& q, int n, int has_env_
     for (int k = 1; k <= last; ++k) {
         ST_LAUNCH("k_extend", k_extend, dim3(g), dim3(TRACE_BLOCK), 0, st, p, q, k);
         ST_LAUNCH("k_shade", k_shade, dim3(grid_for(n, 256, gmax)), dim3(256), 0, st, p, q, k);
-        if (k <= p.B) ST_LAUNCH("k_shadow", k_shadow, dim3(g), dim3(TRACE_BLOCK), 0, st, p, q, k);
+        if (k <= p.B) {
+            ST_LAUNCH("k_shadow", k_shadow, dim3(g), dim3(TRACE_BLOCK), 0, st, p, q, k);
+            ST_LAUNCH("k_shadow_sum", k_shadow_sum, dim3(grid_for(n, 256, gmax)), dim3(256), 0, st, p, q, k);
+        }
     }
 }
 
