@@ -443,12 +443,14 @@ __device__ __forceinline__ V3 side_dir(const DevCam& c, const EdgeSample& es, in
     return V3{(float)(ddx * il), (float)(ddy * il), (float)(ddz * il)};
 }
 
-__global__ void k_edge_camera(BwdParams p, Queues q, long long e0, int n) {
+constexpr int EDGE_CAM_BLOCK = 1024;   // threads of a k_edge_camera block (one queue reservation each)
+
+__global__ void __launch_bounds__(EDGE_CAM_BLOCK) k_edge_camera(BwdParams p, Queues q, long long e0, int n) {
+    __shared__ int resv[EDGE_CAM_BLOCK / 64 + 1];
     const int stride = gridDim.x * blockDim.x;
     float* const* r = q.ray[1];
-    const int base0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63);
-    for (int wb = base0; wb < n; wb += stride) {
-        const int i = wb + (threadIdx.x & 63);
+    for (int b0 = blockIdx.x * blockDim.x; b0 < n; b0 += stride) {
+        const int i = b0 + (int)threadIdx.x;
         const long long ge = e0 + i;
         EdgeSample es;
         bool active = false;
@@ -457,15 +459,9 @@ __global__ void k_edge_camera(BwdParams p, Queues q, long long e0, int n) {
             const float* di = p.d_image + 3 * (c.pixoff + (long long)es.py * c.W + es.px);
             active = !(di[0] == 0.0f && di[1] == 0.0f && di[2] == 0.0f);
         }
-        const uint64_t mask = __ballot(active);
-        if (!mask) continue;
-        const int leader = __ffsll((long long)mask) - 1;
-        int basei = 0;
-        if ((int)__lane_id() == leader) basei = atomicAdd(&q.cnt[1], 2 * __popcll(mask));
-        basei = __shfl(basei, leader);
+        const int o0 = block_reserve<EDGE_CAM_BLOCK, 2>(active, &q.cnt[1], resv);
         if (!active) continue;
         const DevCam& c = p.cams[es.v];
-        const int o0 = basei + 2 * __popcll(mask & lanemask_lt64());
         for (int side = 0; side < 2; ++side) {
             const int s = o0 + side;
             const V3 d = side_dir(c, es, side);
@@ -577,7 +573,8 @@ void launch_primary_edges(const BwdParams& p, const FwdParams& fp, Queues& q, fl
         const int n = (int)((total_edges - e0) < per ? (total_edges - e0) : per);
         launch_fill_u32((uint32_t*)q.cnt, 64, 0u, st);
         launch_fill_u32((uint32_t*)q.fetch, FETCH_INTS, 0u, st);
-        ST_LAUNCH("k_edge_camera", k_edge_camera, dim3(gridb(n, 256, 1 << 20)), dim3(256), 0, st, p, q, e0, n);
+        ST_LAUNCH("k_edge_camera", k_edge_camera, dim3(gridb(n, EDGE_CAM_BLOCK, 1 << 20)), dim3(EDGE_CAM_BLOCK), 0, st,
+                  p, q, e0, n);
         launch_wavefront_bounces(fp, q, 2 * n, has_env_any, st);
     }
     launch_fill_u32((uint32_t*)p.pacc, 4ll * p.ncam * p.ne, 0u, st);      // +0.0 doubles

@@ -758,6 +758,35 @@ __device__ inline void block_scan_normalise(const double* w, int n, double* out,
 
 
 // ---------------------------------------------------------------------------
+// queue reservation with one atomic per block.  Atomics on one address are
+// serialised by the memory system (about 11 ns apiece on this part), so one
+// reservation per wave caps a compaction kernel at roughly 90 M waves/s;
+// reserving per block of BS threads divides that cost by BS / 64.  Every thread
+// of the block calls it (it synchronises the block); lanes with emit get M
+// consecutive slots, the others -1.  lds holds BS / 64 + 1 ints.
+// ---------------------------------------------------------------------------
+template <int BS, int M>
+__device__ __forceinline__ int block_reserve(bool emit, int* counter, int* lds) {
+    const uint64_t mask = __ballot(emit);
+    const int w = (int)(threadIdx.x >> 6);
+    if (__lane_id() == 0) lds[w] = M * __popcll(mask);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int j = 0; j < BS / 64; ++j) {
+            const int c = lds[j];
+            lds[j] = acc;
+            acc += c;
+        }
+        lds[BS / 64] = acc > 0 ? atomicAdd(counter, acc) : 0;
+    }
+    __syncthreads();
+    const int o = lds[BS / 64] + lds[w] + M * __popcll(mask & lanemask_lt64());
+    __syncthreads();
+    return emit ? o : -1;
+}
+
+// ---------------------------------------------------------------------------
 // persistent any-hit traversal of a queue of shadow rays with dynamic fetch:
 // a wave refills its idle lanes whenever at least FETCH_MIN of them are idle,
 // so a lane whose ray finished early takes the next ray instead of waiting for

@@ -9,6 +9,20 @@
 
 namespace st {
 
+// occupancy targets (waves per SIMD) the compiler fits the register budget to
+#ifndef ST_SHADE_WAVES
+#define ST_SHADE_WAVES 4
+#endif
+#ifndef ST_TRACE_WAVES
+#define ST_TRACE_WAVES 6
+#endif
+#define SHADE_OCC __attribute__((amdgpu_waves_per_eu(ST_SHADE_WAVES)))
+#ifndef ST_SHADE_BLOCK
+#define ST_SHADE_BLOCK 512
+#endif
+constexpr int SHADE_BLOCK = ST_SHADE_BLOCK;   // threads of a k_shade block (one queue reservation each)
+#define TRACE_OCC __attribute__((amdgpu_waves_per_eu(ST_TRACE_WAVES)))
+
 
 
 // canonical path index of a (view, pixel, sample)
@@ -60,7 +74,7 @@ __global__ void k_camera(FwdParams p, Queues q, long long q0, int n) {
 // a wave are 64 consecutive queue entries (an 8x8 pixel tile for camera rays)
 // and are traced in lockstep: measured faster here than refilling idle lanes
 // (trace_any_queue), which pays off for the shadow rays only.
-__global__ void __launch_bounds__(TRACE_BLOCK) k_extend(FwdParams p, Queues q, int k) {
+__global__ void __launch_bounds__(TRACE_BLOCK) TRACE_OCC k_extend(FwdParams p, Queues q, int k) {
     __shared__ uint32_t lds[LDS_STACK * TRACE_BLOCK];
     TravStack st = make_trav_stack(lds, q.spill, p.err, p.work ? p.work + 3 * WORK_EXTEND : nullptr);
     const int n = q.cnt[k];
@@ -77,17 +91,17 @@ __global__ void __launch_bounds__(TRACE_BLOCK) k_extend(FwdParams p, Queues q, i
 }
 
 // shading of bounce k: escapes, next-event set-up and BRDF continuation
-__global__ void k_shade(FwdParams p, Queues q, int k) {
+__global__ void __launch_bounds__(SHADE_BLOCK) SHADE_OCC k_shade(FwdParams p, Queues q, int k) {
+    __shared__ int resv[SHADE_BLOCK / 64 + 1];
     const int n = q.cnt[k];
     float* const* r = q.ray[k & 1];
     float* const* rn = q.ray[(k + 1) & 1];
     const int stride = gridDim.x * blockDim.x;
     const bool hashing = p.dbg_hash || p.hash_by_q;
-    // every lane of a wave runs the same number of iterations so that the
-    // compaction ballot below sees whole waves
-    const int base0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63);
-    for (int wb = base0; wb < n; wb += stride) {
-        const int i = wb + (threadIdx.x & 63);
+    // every thread of a block runs the same number of iterations: the
+    // compaction below reserves queue slots per block
+    for (int b0 = blockIdx.x * blockDim.x; b0 < n; b0 += stride) {
+        const int i = b0 + (int)threadIdx.x;
         const bool active = i < n;
         bool emit = false;
         V3 x{0.f, 0.f, 0.f}, wi{0.f, 0.f, 0.f}, beta{0.f, 0.f, 0.f};
@@ -182,15 +196,10 @@ __global__ void k_shade(FwdParams p, Queues q, int k) {
             }
             hv = h.h;
         }
-        // wave-level compaction of the continuing paths into the next queue
-        const uint64_t mask = __ballot(emit);
-        if (mask) {
-            const int leader = __ffsll((long long)mask) - 1;
-            int basei = 0;
-            if ((int)__lane_id() == leader) basei = atomicAdd(&q.cnt[k + 1], __popcll(mask));
-            basei = __shfl(basei, leader);
+        // compaction of the continuing paths into the next queue
+        const int o = block_reserve<SHADE_BLOCK, 1>(emit, &q.cnt[k + 1], resv);
+        {
             if (emit) {
-                const int o = basei + __popcll(mask & lanemask_lt64());
                 rn[QOX][o] = x.x; rn[QOY][o] = x.y; rn[QOZ][o] = x.z;
                 rn[QDX][o] = wi.x; rn[QDY][o] = wi.y; rn[QDZ][o] = wi.z;
                 qu(rn, QEXCL, o) = (uint32_t)f;
@@ -211,7 +220,7 @@ __global__ void k_shade(FwdParams p, Queues q, int k) {
 // shadow rays of bounce k: entry l of shading point i is item l * n + i;
 // persistent waves take items from the fetch counters of slot k and store one
 // outcome code per entry (0 no ray, 1 occluded, 2 unoccluded)
-__global__ void __launch_bounds__(TRACE_BLOCK) k_shadow(FwdParams p, Queues q, int k) {
+__global__ void __launch_bounds__(TRACE_BLOCK) TRACE_OCC k_shadow(FwdParams p, Queues q, int k) {
     __shared__ uint32_t lds[LDS_STACK * TRACE_BLOCK];
     TravStack st = make_trav_stack(lds, q.spill, p.err, p.work ? p.work + 3 * WORK_SHADOW : nullptr);
     const int n = q.cnt[k];
@@ -396,7 +405,7 @@ void launch_wavefront_bounces(const FwdParams& p, Queues& q, int n, int has_env_
     const int last = p.B + (has_env_any ? 1 : 0);
     for (int k = 1; k <= last; ++k) {
         ST_LAUNCH("k_extend", k_extend, dim3(g), dim3(TRACE_BLOCK), 0, st, p, q, k);
-        ST_LAUNCH("k_shade", k_shade, dim3(grid_for(n, 256, gmax)), dim3(256), 0, st, p, q, k);
+        ST_LAUNCH("k_shade", k_shade, dim3(grid_for(n, SHADE_BLOCK, gmax)), dim3(SHADE_BLOCK), 0, st, p, q, k);
         if (k <= p.B) {
             ST_LAUNCH("k_shadow", k_shadow, dim3(g), dim3(TRACE_BLOCK), 0, st, p, q, k);
             ST_LAUNCH("k_shadow_sum", k_shadow_sum, dim3(grid_for(n, 256, gmax)), dim3(256), 0, st, p, q, k);
