@@ -395,6 +395,15 @@ int st_scene_create(const float* V, int32_t nv, const int32_t* F, int32_t nf, co
     HIPCHK(hipStreamSynchronize(s));
     for (int32_t v : Fh)
         if (v < 0 || v >= nv) return fail(ST_ERR_INVALID_ARG, "face index out of range");
+    // vertex -> (face, corner) incidence in CSR form, for the gather of per-face gradients
+    std::vector<int32_t> vf_off((size_t)nv + 1, 0), vf_idx(3 * (size_t)nf);
+    for (int32_t v : Fh) ++vf_off[(size_t)v + 1];
+    for (int v = 0; v < nv; ++v) vf_off[(size_t)v + 1] += vf_off[v];
+    {
+        std::vector<int32_t> fill(vf_off.begin(), vf_off.end() - 1);
+        for (int f = 0; f < nf; ++f)
+            for (int k = 0; k < 3; ++k) vf_idx[fill[Fh[3 * f + k]]++] = 3 * f + k;
+    }
     std::vector<std::array<int, 3>> hes;
     hes.reserve(3 * (size_t)nf);
     for (int f = 0; f < nf; ++f)
@@ -431,6 +440,9 @@ int st_scene_create(const float* V, int32_t nv, const int32_t* F, int32_t nf, co
     A(dalloc(&d.flag4, (size_t)std::max(nf - 1, 1)));
     A(dalloc(&d.id4, (size_t)std::max(nf - 1, 1)));
     A(dalloc(&d.tri, 3 * (size_t)nf));
+    A(dalloc(&d.vf_off, (size_t)nv + 1));
+    A(dalloc(&d.vf_idx, 3 * (size_t)nf));
+    A(dalloc(&d.facc, (size_t)FACC * nf));
     A(dalloc(&d.edges, edges.size()));
     A(dalloc(&d.edge_w, edges.size()));
     A(dalloc(&d.eguide, (size_t)1 << guide_log2((int)edges.size())));
@@ -461,6 +473,8 @@ int st_scene_create(const float* V, int32_t nv, const int32_t* F, int32_t nf, co
     if (nl > 0) HIPCHK2(hipMemcpyAsync(d.lights, lights, sizeof(float) * 6 * nl, hipMemcpyDeviceToDevice, s));
     if (!edges.empty())
         HIPCHK2(hipMemcpyAsync(d.edges, edges.data(), sizeof(int4) * edges.size(), hipMemcpyHostToDevice, s));
+    HIPCHK2(hipMemcpyAsync(d.vf_off, vf_off.data(), sizeof(int32_t) * vf_off.size(), hipMemcpyHostToDevice, s));
+    HIPCHK2(hipMemcpyAsync(d.vf_idx, vf_idx.data(), sizeof(int32_t) * vf_idx.size(), hipMemcpyHostToDevice, s));
     launch_fill_u32(d.err, 1, 0u, s);
     launch_fill_u32((uint32_t*)d.work, 6 * WORK_SLOTS, 0u, s);
     std::vector<double> dom(std::max(he, 1));
@@ -575,12 +589,15 @@ int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_
     p.pguide = c.take<int>((size_t)ncam << pglog);
     p.pglog = pglog;
     p.pacc = c.take<double>(2 * (size_t)ncam * ne);
+    p.facc = sc->d.facc;
+    p.vf_off = sc->d.vf_off;
+    p.vf_idx = sc->d.vf_idx;
     p.ne = ne;
     launch_fill_f32(out_dV, 3ll * sc->d.nv, 0.0f, s);
     launch_fill_f32(out_dmat, 7ll * sc->d.nf, 0.0f, s);
     if (o.debug_decision_hash) launch_fill_u32(o.debug_decision_hash, cs.total_paths, 0u, s);
     if (o.debug_edge_hash) launch_fill_u32(o.debug_edge_hash, cs.total_edges, 0u, s);
-    launch_backward(p, cs.total_paths, cs.total_edges, TRACE_GRID, s);
+    launch_backward(p, sc->d.nv, sc->d.nf, cs.total_paths, cs.total_edges, TRACE_GRID, s);
     if ((p.flags & ST_EDGE_PRIMARY) && cs.total_edges > 0 && ne > 0) {
         // side paths of the primary edge samples run through the wavefront kernels
         if (2 * cs.total_edges >= (1ll << 32)) return fail(ST_ERR_INVALID_ARG, "too many primary edge samples");
@@ -780,7 +797,7 @@ void st_scene_destroy(st_scene* sc) {
     void* ptrs[] = {d.V, d.F, d.mat, d.lights, d.env, d.fnorm, d.bmin, d.bmax, d.cen, d.bounds, d.mkeys[0], d.mkeys[1],
                     d.mvals[0], d.mvals[1], d.rs_hist, d.keys64, d.child, d.parent, d.aabb, d.refit_cnt, d.nodes4, d.flag4, d.id4,
                     d.tri, d.edges, d.edge_w, d.eguide, d.mguide, d.cguide, d.ecdf, d.etotal_d, d.etotal_f, d.row_dom, d.rowcos, d.cond, d.marg,
-                    d.env_rows, d.env_total, d.texpdf, d.err, d.work, d.dscene};
+                    d.env_rows, d.env_total, d.texpdf, d.err, d.work, d.dscene, d.vf_off, d.vf_idx, d.facc};
     for (void* p : ptrs)
         if (p) hipFree(p);
     sc->Lbuf.release(); sc->qbuf.release(); sc->spillbuf.release(); sc->primbuf.release();

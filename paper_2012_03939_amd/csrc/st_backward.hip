@@ -73,9 +73,56 @@ __device__ __forceinline__ bool silhouette(const DevScene& S, int4 E, V3 x) {
 
 constexpr uint32_t R_FLIP = 1u, R_ENV = 2u, R_CONT = 4u, R_ESC = 8u, R_SEC = 16u;
 
+#ifndef ST_FACE_REDUCE
+#define ST_FACE_REDUCE 1
+#endif
+constexpr bool FACE_REDUCE = ST_FACE_REDUCE != 0;   // wave-level reduction of the primary-vertex gradients
+
+// Adds vals to the accumulators of face f with one set of atomics per (face,
+// wave): lanes of the wave with the same face are summed first (peeling one
+// face per round; partner lanes add into the leader's LDS row).  Primary hits
+// of a wave are the 64 pixels of a tile, so few faces cover most lanes.
+// Lanes with !has contribute nothing.  red: this wave's FACC floats of LDS.
+__device__ __forceinline__ void face_reduce_add(bool has, int f, const float (&vals)[FACC], float* acc, int nf,
+                                                float* red) {
+    bool pending = has;
+    for (;;) {
+        const uint64_t m = __ballot(pending);
+        if (!m) break;
+        const int leader = __ffsll((long long)m) - 1;
+        const int lf = __builtin_amdgcn_readlane(f, leader);
+        const bool mine = pending && f == lf;
+        const bool lead = (int)__lane_id() == leader;
+        const uint64_t grp = __ballot(mine);
+        float* dst = acc + lf;
+        if (grp == (1ull << leader)) {
+            if (lead)
+#pragma unroll
+                for (int j = 0; j < FACC; ++j) atomicAdd(dst + (size_t)j * nf, vals[j]);
+        } else {
+            if (lead)
+#pragma unroll
+                for (int j = 0; j < FACC; ++j) red[j] = vals[j];
+            if (mine && !lead)
+#pragma unroll
+                for (int j = 0; j < FACC; ++j) atomicAdd(red + j, vals[j]);
+            if (lead)
+#pragma unroll
+                for (int j = 0; j < FACC; ++j) atomicAdd(dst + (size_t)j * nf, red[j]);
+        }
+        pending = pending && !mine;
+    }
+}
+
+#ifndef ST_ADJ_WAVES
+#define ST_ADJ_WAVES 4
+#endif
 template <int BM>
-__global__ void __launch_bounds__(TRACE_BLOCK) k_adjoint(BwdParams p, long long total) {
+__global__ void __launch_bounds__(TRACE_BLOCK) __attribute__((amdgpu_waves_per_eu(ST_ADJ_WAVES)))
+k_adjoint(BwdParams p, long long total) {
     __shared__ uint32_t lds[LDS_STACK * TRACE_BLOCK];
+    __shared__ float red_s[TRACE_BLOCK / 64][FACC];
+    float* const red = red_s[threadIdx.x >> 6];
     TravStack st = make_trav_stack(lds, p.spill, p.err, p.work ? p.work + 3 * WORK_ADJOINT : nullptr);
     const bool want_interior = p.flags & 1u, want_secondary = p.flags & 4u;
     const long long stride = (long long)gridDim.x * blockDim.x;
@@ -246,94 +293,103 @@ __global__ void __launch_bounds__(TRACE_BLOCK) k_adjoint(BwdParams p, long long 
         }
 
         // ---- reverse sweep ------------------------------------------------
+        // every lane runs BM rounds so that the primary vertices (k = 0) of
+        // the wave are accumulated together
         {
             V3 Snext{0.f, 0.f, 0.f}, gxnext{0.f, 0.f, 0.f};
-            for (int k = nvtx - 1; k >= 0; --k) {
-                const int f = sel(rf, k);
-                const uint32_t fl = sel(rfl, k);
-                const V3 xh = sel(rx, k);
-                const V3 dir = k == 0 ? d0 : sel(rwi, k - 1);
-                const V3 wo = -dir;
-                const int i0 = S.F[3 * f], i1 = S.F[3 * f + 1], i2 = S.F[3 * f + 2];
-                const V3 v0 = ld3(S.V + 3 * i0), v1 = ld3(S.V + 3 * i1), v2 = ld3(S.V + 3 * i2);
-                const V3 e1 = v1 - v0, e2 = v2 - v0;
-                const V3 N = cross(e1, e2);
-                const float Nl = len(N);
-                const V3 nu = N * (1.0f / Nl);
-                const float sg = (fl & R_FLIP) ? -1.0f : 1.0f;
-                const V3 n = nu * sg;
-                const Mat m = load_mat(S.mat + 7 * (size_t)f);
-                const V3 a = want_interior ? mul(w, sel(rbeta, k)) : V3{0.f, 0.f, 0.f};
-                V3 C{0.f, 0.f, 0.f}, gn{0.f, 0.f, 0.f}, gx = gxnext, gdummy{0.f, 0.f, 0.f};
-                float gm[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-                for (int l = 0; l < S.nl; ++l) {
-                    if (!((fl >> (8 + l)) & 1u)) continue;
-                    const float* lt = S.lights + 6 * l;
-                    const V3 I = ld3(lt + 3);
-                    const V3 dl = ld3(lt) - xh;
-                    const float r2 = dot(dl, dl);
-                    const float rr = sqrtf(r2);
-                    const V3 wl = dl * (1.0f / rr);
-                    const float cl = dot(n, wl);
-                    const V3 fv = brdf_eval(wl, wo, n, m);
-                    const V3 If = mul(I, fv);
-                    C = C + If * (cl / r2);
-                    const V3 aI = mul(a, I);
-                    const float gcl = dot(aI, fv) / r2;
-                    const float gr2 = -dot(aI, fv) * cl / (r2 * r2);
-                    V3 gwl{0.f, 0.f, 0.f};
-                    brdf_backward(wl, wo, n, m, aI * (cl / r2), gn, gwl, gm);
-                    gn = gn + wl * gcl;
-                    gwl = gwl + n * gcl;
-                    const V3 gd = (gwl - wl * dot(wl, gwl)) * (1.0f / rr) + dl * (2.0f * gr2);
-                    gx = gx - gd;
+            for (int k = BM - 1; k >= 0; --k) {
+                float vals[FACC];
+                const bool has = k < nvtx;
+                const int f = has ? sel(rf, k) : -1;
+                if (has) {
+                    const uint32_t fl = sel(rfl, k);
+                    const V3 xh = sel(rx, k);
+                    const V3 dir = k == 0 ? d0 : sel(rwi, k - 1);
+                    const V3 wo = -dir;
+                    const int i0 = S.F[3 * f], i1 = S.F[3 * f + 1], i2 = S.F[3 * f + 2];
+                    const V3 v0 = ld3(S.V + 3 * i0), v1 = ld3(S.V + 3 * i1), v2 = ld3(S.V + 3 * i2);
+                    const V3 e1 = v1 - v0, e2 = v2 - v0;
+                    const V3 N = cross(e1, e2);
+                    const float Nl = len(N);
+                    const V3 nu = N * (1.0f / Nl);
+                    const float sg = (fl & R_FLIP) ? -1.0f : 1.0f;
+                    const V3 n = nu * sg;
+                    const Mat m = load_mat(S.mat + 7 * (size_t)f);
+                    const V3 a = want_interior ? mul(w, sel(rbeta, k)) : V3{0.f, 0.f, 0.f};
+                    V3 C{0.f, 0.f, 0.f}, gn{0.f, 0.f, 0.f}, gx = gxnext, gdummy{0.f, 0.f, 0.f};
+                    float gm[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                    for (int l = 0; l < S.nl; ++l) {
+                        if (!((fl >> (8 + l)) & 1u)) continue;
+                        const float* lt = S.lights + 6 * l;
+                        const V3 I = ld3(lt + 3);
+                        const V3 dl = ld3(lt) - xh;
+                        const float r2 = dot(dl, dl);
+                        const float rr = sqrtf(r2);
+                        const V3 wl = dl * (1.0f / rr);
+                        const float cl = dot(n, wl);
+                        const V3 fv = brdf_eval(wl, wo, n, m);
+                        const V3 If = mul(I, fv);
+                        C = C + If * (cl / r2);
+                        const V3 aI = mul(a, I);
+                        const float gcl = dot(aI, fv) / r2;
+                        const float gr2 = -dot(aI, fv) * cl / (r2 * r2);
+                        V3 gwl{0.f, 0.f, 0.f};
+                        brdf_backward(wl, wo, n, m, aI * (cl / r2), gn, gwl, gm);
+                        gn = gn + wl * gcl;
+                        gwl = gwl + n * gcl;
+                        const V3 gd = (gwl - wl * dot(wl, gwl)) * (1.0f / rr) + dl * (2.0f * gr2);
+                        gx = gx - gd;
+                    }
+                    if (fl & R_ENV) {
+                        const V3 we = sel(rwe, k);
+                        const float den = sel(rden, k);
+                        const V3 Le = env_rgb(S, sel(rtex, k));
+                        const float ce = dot(n, we);
+                        const V3 fv = brdf_eval(we, wo, n, m);
+                        C = C + mul(Le, fv) * (ce / den);
+                        const V3 aL = mul(a, Le);
+                        brdf_backward(we, wo, n, m, aL * (ce / den), gn, gdummy, gm);
+                        gn = gn + we * (dot(aL, fv) / den);
+                    }
+                    V3 Sk = C;
+                    if (fl & R_CONT) {
+                        const V3 wi = sel(rwi, k);
+                        const float pb = sel(rpb, k);
+                        const V3 S1 = (fl & R_ESC) ? sel(resc, k) : Snext;
+                        const float ci = dot(n, wi);
+                        const V3 fv = brdf_eval(wi, wo, n, m);
+                        const V3 uu = mul(a, S1);
+                        brdf_backward(wi, wo, n, m, uu * (ci / pb), gn, gdummy, gm);
+                        gn = gn + wi * (dot(uu, fv) / pb);
+                        Sk = Sk + mul(fv, S1) * (ci / pb);
+                    }
+                    if (fl & R_SEC) gx = gx - sel(rsecm, k) * sel(rsecc, k);
+                    // normal n = sg * N / |N|
+                    const V3 gnu = gn * sg;
+                    V3 gN = (gnu - nu * dot(nu, gnu)) * (1.0f / Nl);
+                    // hit point x = o + t dir, t = ((v0 - o) . N) / (dir . N)
+                    const float dN = dot(dir, N);
+                    const float gt = dot(gx, dir) / dN;
+                    const V3 go = gx - N * gt;
+                    V3 gv0 = N * gt;
+                    gN = gN + (v0 - xh) * gt;
+                    const V3 ge1 = cross(e2, gN), ge2 = cross(gN, e1);
+                    gv0 = gv0 - ge1 - ge2;
+                    vals[0] = gv0.x; vals[1] = gv0.y; vals[2] = gv0.z;
+                    vals[3] = ge1.x; vals[4] = ge1.y; vals[5] = ge1.z;
+                    vals[6] = ge2.x; vals[7] = ge2.y; vals[8] = ge2.z;
+    #pragma unroll
+                    for (int i = 0; i < 7; ++i) vals[9 + i] = want_interior ? gm[i] : 0.0f;
+                    Snext = Sk;
+                    gxnext = go;
                 }
-                if (fl & R_ENV) {
-                    const V3 we = sel(rwe, k);
-                    const float den = sel(rden, k);
-                    const V3 Le = env_rgb(S, sel(rtex, k));
-                    const float ce = dot(n, we);
-                    const V3 fv = brdf_eval(we, wo, n, m);
-                    C = C + mul(Le, fv) * (ce / den);
-                    const V3 aL = mul(a, Le);
-                    brdf_backward(we, wo, n, m, aL * (ce / den), gn, gdummy, gm);
-                    gn = gn + we * (dot(aL, fv) / den);
+                if (k == 0 && FACE_REDUCE) {
+                    face_reduce_add(has, f, vals, p.facc, S.nf, red);
+                } else if (has) {
+                    float* dst = p.facc + f;
+#pragma unroll
+                    for (int j = 0; j < FACC; ++j) atomicAdd(dst + (size_t)j * S.nf, vals[j]);
                 }
-                V3 Sk = C;
-                if (fl & R_CONT) {
-                    const V3 wi = sel(rwi, k);
-                    const float pb = sel(rpb, k);
-                    const V3 S1 = (fl & R_ESC) ? sel(resc, k) : Snext;
-                    const float ci = dot(n, wi);
-                    const V3 fv = brdf_eval(wi, wo, n, m);
-                    const V3 uu = mul(a, S1);
-                    brdf_backward(wi, wo, n, m, uu * (ci / pb), gn, gdummy, gm);
-                    gn = gn + wi * (dot(uu, fv) / pb);
-                    Sk = Sk + mul(fv, S1) * (ci / pb);
-                }
-                if (fl & R_SEC) gx = gx - sel(rsecm, k) * sel(rsecc, k);
-                // normal n = sg * N / |N|
-                const V3 gnu = gn * sg;
-                V3 gN = (gnu - nu * dot(nu, gnu)) * (1.0f / Nl);
-                // hit point x = o + t dir, t = ((v0 - o) . N) / (dir . N)
-                const float dN = dot(dir, N);
-                const float gt = dot(gx, dir) / dN;
-                const V3 go = gx - N * gt;
-                V3 gv0 = N * gt;
-                gN = gN + (v0 - xh) * gt;
-                const V3 ge1 = cross(e2, gN), ge2 = cross(gN, e1);
-                gv0 = gv0 - ge1 - ge2;
-                if (want_interior || want_secondary) {
-                    atomic_add3(p.dV + 3 * (size_t)i0, gv0);
-                    atomic_add3(p.dV + 3 * (size_t)i1, ge1);
-                    atomic_add3(p.dV + 3 * (size_t)i2, ge2);
-                }
-                if (want_interior) {
-                    float* dm = p.dmat + 7 * (size_t)f;
-                    for (int i = 0; i < 7; ++i) atomicAdd(dm + i, gm[i]);
-                }
-                Snext = Sk;
-                gxnext = go;
             }
         }
         if (p.dbg_hash) p.dbg_hash[g] = h.h;
@@ -555,6 +611,27 @@ __global__ void k_edge_finish(BwdParams p) {
     }
 }
 
+// per-face accumulators (slot-major: slot j of face f at j nf + f) to dV
+// (vertex gather over the incidence CSR, fixed order) and dmat
+__global__ void k_face_gather(BwdParams p) {
+    const DevScene& S = p.scenes[0];
+    const int stride = gridDim.x * blockDim.x;
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < S.nv; v += stride) {
+        float sx = 0.f, sy = 0.f, sz = 0.f;
+        for (int j = p.vf_off[v]; j < p.vf_off[v + 1]; ++j) {
+            const int e = p.vf_idx[j];
+            const float* a = p.facc + (size_t)(3 * (e % 3)) * S.nf + e / 3;
+            sx += a[0]; sy += a[S.nf]; sz += a[2 * (size_t)S.nf];
+        }
+        p.dV[3 * (size_t)v] += sx;
+        p.dV[3 * (size_t)v + 1] += sy;
+        p.dV[3 * (size_t)v + 2] += sz;
+    }
+    for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < S.nf; f += stride)
+#pragma unroll
+        for (int i = 0; i < 7; ++i) p.dmat[7 * (size_t)f + i] = p.facc[(size_t)(9 + i) * S.nf + f];
+}
+
 // ---------------------------------------------------------------------------
 static inline unsigned gridb(long long n, int bs, int cap) {
     long long g = (n + bs - 1) / bs;
@@ -583,13 +660,16 @@ void launch_primary_edges(const BwdParams& p, const FwdParams& fp, Queues& q, fl
     ST_LAUNCH("k_edge_finish", k_edge_finish, dim3(gridb(p.ne, 256, 1024), p.ncam), dim3(256), 0, st, p);
 }
 
-void launch_backward(const BwdParams& p, long long total_paths, long long total_edges, int grid, hipStream_t st) {
+void launch_backward(const BwdParams& p, int nv, int nf, long long total_paths, long long total_edges, int grid,
+                     hipStream_t st) {
     if ((p.flags & 5u) && total_paths > 0) {
+        launch_fill_u32((uint32_t*)p.facc, (long long)FACC * nf, 0u, st);
         const dim3 gd(gridb(total_paths, TRACE_BLOCK, grid)), bd(TRACE_BLOCK);
         if (p.B <= 1) ST_LAUNCH("k_adjoint<1>", k_adjoint<1>, gd, bd, 0, st, p, total_paths);
         else if (p.B <= 2) ST_LAUNCH("k_adjoint<2>", k_adjoint<2>, gd, bd, 0, st, p, total_paths);
         else if (p.B <= 3) ST_LAUNCH("k_adjoint<3>", k_adjoint<3>, gd, bd, 0, st, p, total_paths);
         else ST_LAUNCH("k_adjoint<8>", k_adjoint<8>, gd, bd, 0, st, p, total_paths);
+        ST_LAUNCH("k_face_gather", k_face_gather, dim3(gridb(std::max(nv, nf), 256, 4096)), dim3(256), 0, st, p);
     }
 
 }

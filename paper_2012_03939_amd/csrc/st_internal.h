@@ -18,12 +18,17 @@ extern bool g_prof_on;
     } while (0)
 
 // every device allocation of one scene (library-owned)
+constexpr int FACC = 16;   // per-face gradient slots: 3 corners x xyz, then the 7 material parameters
+
 struct SceneDev {
     int nv = 0, nf = 0, nl = 0, he = 0, we = 0, ne = 0;
     uint32_t scene_id = 0;
     bool has_env = false;
     float* V = nullptr;
     int* F = nullptr;
+    int* vf_off = nullptr;                   // vertex -> (face, corner) CSR offsets [nv+1]
+    int* vf_idx = nullptr;                   // entries 3 f + corner [3 nf]
+    float* facc = nullptr;                   // per-face gradient accumulators [FACC, nf]
     float* mat = nullptr;
     float* lights = nullptr;
     float* env = nullptr;
@@ -161,9 +166,13 @@ struct BwdParams {
     int pglog;
     double* pacc;            // per (view, edge): sums of c (1-t) and c t over its primary edge samples [ncam, ne, 2]
     int ne;
+    float* facc;             // per-face accumulators [FACC, nf]: d/d(v0, v1, v2) then d/d(material)
+    const int* vf_off;       // vertex -> (face, corner) CSR of the scene
+    const int* vf_idx;
 };
 
-void launch_backward(const BwdParams& p, long long total_paths, long long total_edges, int grid, hipStream_t st);
+void launch_backward(const BwdParams& p, int nv, int nf, long long total_paths, long long total_edges, int grid,
+                     hipStream_t st);
 // primary edges with their side paths traced by the wavefront kernels
 void launch_primary_edges(const BwdParams& p, const FwdParams& fp, Queues& q, float* Lside, uint32_t* hside,
                           long long total_edges, int has_env_any, hipStream_t st);
