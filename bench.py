@@ -29,21 +29,11 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 
 
-def kernel_source_hash() -> str:
-    """Hash of the HIP sources; counter summaries are valid only for the sources they were taken on."""
-    import glob
-    import hashlib
-    h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2012_03939_amd", "csrc", "*"))):
-        with open(f, "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def measured_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
     (FETCH_SIZE and WRITE_SIZE scaled by their plain-copy factors), or None when
     the kernel sources changed after the counters were taken."""
+    from paper_2012_03939_amd.profiling import kernel_source_hash
     path = os.path.join(ROOT, "profiles", "pmc_traversal_kernels_torus40k_16x512sq_16spp.json")
     try:
         with open(path) as fh:
@@ -52,7 +42,7 @@ def measured_traffic(kernel: str):
         return None
     if pm.get("source_hash") != kernel_source_hash():
         return None
-    k = pm["kernels"].get(kernel.split("<")[0])
+    k = pm["kernels"].get(kernel) or pm["kernels"].get(kernel.split("<")[0])
     return None if k is None else k["hbm_bytes_per_dispatch"]
 
 

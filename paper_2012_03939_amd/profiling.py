@@ -1,0 +1,167 @@
+"""rocprofv3 helpers: the plain-copy reference for the HBM byte counters and the
+summaries kept under profiles/.
+
+    python -m paper_2012_03939_amd.profiling copyref
+        a plain 512 MiB device-to-device copy (three times), the reference that
+        scales FETCH_SIZE / WRITE_SIZE to bytes
+    python -m paper_2012_03939_amd.profiling pmc --fetch D1 --write D2 --copy-fetch D3 --copy-write D4
+                                            [--sq D5] --out FILE.json --command "..."
+        per-kernel counter summary (KiB per dispatch, copy-scaled HBM bytes per dispatch)
+    python -m paper_2012_03939_amd.profiling trace --stats run_kernel_stats.csv --out FILE.md --title "..."
+                                              --command "..."
+        kernel-time table of a --kernel-trace --stats run
+
+Counter summaries carry the hash of the HIP sources they were taken on; bench.py
+reports the measured traffic only while that hash matches.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+COPY_BYTES = 512 << 20          # bytes read and written by one copy of the reference
+
+
+def kernel_source_hash() -> str:
+    """Hash of the HIP sources (csrc/*): counter summaries are valid only for these."""
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def copy_reference(reps: int = 3):
+    import torch
+    a = torch.ones(COPY_BYTES // 4, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"copied {COPY_BYTES} bytes x{reps}", flush=True)
+
+
+def _short(name: str) -> str:
+    n = name.split("(")[0]
+    if n.startswith("void "):
+        n = n[5:]
+    return n[4:] if n.startswith("st::") else n
+
+
+def read_counters(d: str):
+    """{kernel: {counter: [value per dispatch]}} and {kernel: [duration ns per dispatch]}."""
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no counter_collection.csv under {d}")
+    vals = collections.defaultdict(lambda: collections.defaultdict(dict))
+    dur = collections.defaultdict(dict)
+    for fn in files:
+        with open(fn) as fh:
+            for row in csv.DictReader(fh):
+                k = _short(row["Kernel_Name"])
+                disp = row["Dispatch_Id"]
+                c = row["Counter_Name"]
+                vals[k][c][disp] = vals[k][c].get(disp, 0.0) + float(row["Counter_Value"])
+                dur[k][disp] = int(row["End_Timestamp"]) - int(row["Start_Timestamp"])
+    out = {k: {c: list(v.values()) for c, v in cs.items()} for k, cs in vals.items()}
+    return out, {k: list(v.values()) for k, v in dur.items()}
+
+
+def _copy_factor(d: str, counter: str) -> float:
+    vals, _ = read_counters(d)
+    per = [v for k, cs in vals.items() if "copyBuffer" in k or "copy" in k.lower() for v in cs.get(counter, [])]
+    if not per:
+        raise ValueError(f"no copy dispatch with {counter} in {d}")
+    kib = max(per)              # the 512 MiB copy is the largest copy dispatch
+    return COPY_BYTES / (kib * 1024.0)
+
+
+def pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, sq_dir=None, command="") -> dict:
+    ff = _copy_factor(copy_fetch_dir, "FETCH_SIZE")
+    wf = _copy_factor(copy_write_dir, "WRITE_SIZE")
+    fv, fdur = read_counters(fetch_dir)
+    wv, _ = read_counters(write_dir)
+    sv = read_counters(sq_dir)[0] if sq_dir else {}
+    kernels = {}
+    for k in sorted(fv):
+        f = fv[k].get("FETCH_SIZE")
+        w = wv.get(k, {}).get("WRITE_SIZE")
+        if not f or not w:
+            continue
+        n = len(f)
+        e = {"dispatches": n,
+             "fetch_kib_per_dispatch": sum(f) / n,
+             "write_kib_per_dispatch": sum(w) / len(w),
+             "mean_dispatch_ms_under_counters": sum(fdur[k]) / len(fdur[k]) / 1e6}
+        e["hbm_bytes_per_dispatch"] = (e["fetch_kib_per_dispatch"] * ff + e["write_kib_per_dispatch"] * wf) * 1024.0
+        for c in ("TCC_HIT_sum", "TCC_MISS_sum"):
+            if c in wv.get(k, {}):
+                e[c.lower() + "_per_dispatch"] = sum(wv[k][c]) / len(wv[k][c])
+        if "tcc_hit_sum_per_dispatch" in e and "tcc_miss_sum_per_dispatch" in e:
+            t = e["tcc_hit_sum_per_dispatch"] + e["tcc_miss_sum_per_dispatch"]
+            e["l2_hit_rate"] = e["tcc_hit_sum_per_dispatch"] / t if t else None
+        for c, v in sv.get(k, {}).items():
+            e[c.lower() + "_per_dispatch"] = sum(v) / len(v)
+        kernels[k] = e
+    return {"command": command, "source_hash": kernel_source_hash(), "fetch_size_factor": ff,
+            "write_size_factor": wf, "copy_reference_bytes": COPY_BYTES, "kernels": kernels}
+
+
+def trace_table(stats_csv: str, top: int = 24):
+    rows = []
+    with open(stats_csv) as fh:
+        for r in csv.DictReader(fh):
+            rows.append((_short(r["Name"]), int(r["Calls"]), float(r["TotalDurationNs"]) / 1e6,
+                         float(r["AverageNs"]) / 1e3, float(r["Percentage"])))
+    rows.sort(key=lambda r: -r[2])
+    lines = ["| kernel | calls | total ms | avg us | % |", "|---|---|---|---|---|"]
+    for name, calls, tot, avg, pct in rows[:top]:
+        lines.append(f"| {name} | {calls} | {tot:.2f} | {avg:.1f} | {pct:.2f} |")
+    return "\n".join(lines)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    sub.add_parser("copyref")
+    p = sub.add_parser("pmc")
+    for a in ("--fetch", "--write", "--copy-fetch", "--copy-write", "--out"):
+        p.add_argument(a, required=True)
+    p.add_argument("--sq")
+    p.add_argument("--command", default="")
+    t = sub.add_parser("trace")
+    t.add_argument("--stats", required=True)
+    t.add_argument("--out", required=True)
+    t.add_argument("--title", default="Kernel times")
+    t.add_argument("--command", default="")
+    t.add_argument("--notes", default="")
+    a = ap.parse_args(argv)
+    if a.cmd == "copyref":
+        copy_reference()
+    elif a.cmd == "pmc":
+        s = pmc_summary(a.fetch, a.write, a.copy_fetch, a.copy_write, a.sq, a.command)
+        with open(a.out, "w") as fh:
+            json.dump(s, fh, indent=1)
+        print(f"wrote {a.out}: {', '.join(s['kernels'])}")
+    else:
+        body = [f"# {a.title}", ""]
+        if a.notes:
+            body += [a.notes, ""]
+        body += ["Command (from the repository root on the GPU box):", "", "```", a.command, "```", "",
+                 trace_table(a.stats), ""]
+        with open(a.out, "w") as fh:
+            fh.write("\n".join(body))
+        print(f"wrote {a.out}")
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
