@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--opt-steps", type=int, default=200, help="optimisation-loop steps (0 skips)")
     ap.add_argument("--cpu-baseline-res", type=int, default=1024)
     ap.add_argument("--profile-only", action="store_true", help="one untimed step (for rocprofv3 runs)")
+    ap.add_argument("--copy-reference", action="store_true",
+                    help="only a plain 512 MiB device copy: the reference that scales the HBM byte counters")
     return ap.parse_args()
 
 
@@ -123,6 +125,10 @@ def main():
         print(json.dumps({"error": "this path tracer runs on one GPU; multi-GPU runs are not supported "
                                    "(see DESIGN.md for how the path would shard)"}))
         sys.exit(2)
+    if args.copy_reference:
+        from paper_2012_03939_amd.profiling import copy_reference
+        copy_reference()
+        return
     import numpy as np
     import torch
     from paper_2012_03939_amd import binding as B, scenes as S
@@ -137,7 +143,9 @@ def main():
     V0 = torch.from_numpy(sc.V).to(dev)
     # target images from perturbed vertices (synthetic stand-in for captured views)
     g.update(V=torch.from_numpy(S.perturbed_vertices(sc.V, 0.01, 77)).to(dev))
-    target = g.render(cams, spp, bounces, seed=1).clone()
+    # (a profiling run renders the target with the single-kernel forward, so that its
+    # trace holds the wavefront kernels of exactly one step)
+    target = g.render(cams, spp, bounces, seed=1, flags=B.ST_FORWARD_MEGAKERNEL if args.profile_only else 0).clone()
     Vs = [V0 + 1e-4 * torch.randn_like(V0) for _ in range(2)]
     dV = torch.empty_like(V0)
     dM = torch.empty((g.nf, 7), dtype=torch.float32, device=dev)
