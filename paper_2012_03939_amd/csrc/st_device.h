@@ -787,10 +787,10 @@ __device__ __forceinline__ int block_reserve(bool emit, int* counter, int* lds) 
 }
 
 // ---------------------------------------------------------------------------
-// persistent any-hit traversal of a queue of shadow rays with dynamic fetch:
-// a wave refills its idle lanes whenever at least FETCH_MIN of them are idle,
-// so a lane whose ray finished early takes the next ray instead of waiting for
-// the slowest lane of its wave.  Each ray's outcome is that of trace_any.
+// persistent traversal of a ray queue with dynamic fetch: a wave refills its
+// idle lanes whenever at least FETCH_MIN of them are idle, so a lane whose ray
+// finished early takes the next ray instead of waiting for the slowest lane of
+// its wave.  Each ray's outcome is that of trace_any (ANY) or trace_closest.
 // ---------------------------------------------------------------------------
 #ifndef ST_FETCH_MIN
 #define ST_FETCH_MIN 16
@@ -808,20 +808,23 @@ constexpr int FETCH_SLOT_INTS = FETCH_NC * 32;   // one 128-byte line per counte
 
 struct RayJob {
     V3 o, d;
-    float tmax;   // the ray is tested on (TMIN, tmax)
+    float tmax;   // any-hit: the ray is tested on (TMIN, tmax); closest hit: +inf
     int excl;     // face excluded from the test (the ray's origin face), -1 for none
     TraceGeo G;
 };
 
 // fetch(i, job) loads ray i and returns true, or stores ray i's outcome itself
-// and returns false when it needs no traversal; finish(i, occluded) stores it
-template <class Fetch, class Finish>
-__device__ __forceinline__ void trace_any_queue(int* counters, int n, TravStack& st, Fetch fetch, Finish finish) {
+// and returns false when it needs no traversal.  finish(i, face, t) stores the
+// outcome: for ANY face is 1 when occluded and 0 otherwise; for the closest
+// hit face is -1 and t = +inf on a miss.
+template <bool ANY, class Fetch, class Finish>
+__device__ __forceinline__ void trace_queue(int* counters, int n, TravStack& st, Fetch fetch, Finish finish) {
     const float INF = __int_as_float(0x7f800000);
     // a finished ray's outcome is stored when its lane is refilled (or at the
     // end), so that no store is in flight while the traversal waits on loads
-    bool live = false, pend = false, occ = false, drained = n <= 0;
-    int idx = 0, sp = 0, iters = 0;
+    bool live = false, pend = false, drained = n <= 0;
+    int idx = 0, sp = 0, iters = 0, best = -1;
+    float tbest = INF;
     uint32_t node = 0;
     RayJob J;
     V3 inv{0.f, 0.f, 0.f};
@@ -851,7 +854,7 @@ __device__ __forceinline__ void trace_any_queue(int* counters, int n, TravStack&
                 }
             }
             if (pend) {
-                finish(idx, occ);
+                finish(idx, best, tbest);
                 pend = false;
             }
             const int take = min(nidle, end - cur);
@@ -861,15 +864,17 @@ __device__ __forceinline__ void trace_any_queue(int* counters, int n, TravStack&
                     idx = cur + rank;
                     if (fetch(idx, J)) {
                         if (J.G.nf <= 0) {
-                            finish(idx, false);
+                            finish(idx, ANY ? 0 : -1, INF);
                         } else if (J.G.nf == 1) {
                             float t; int f;
-                            finish(idx, tri_test(J.G.tri, 0, J.o, J.d, TMIN, J.tmax, t, f) && f != J.excl);
+                            const bool h = tri_test(J.G.tri, 0, J.o, J.d, TMIN, J.tmax, t, f) && f != J.excl;
+                            if (ANY) finish(idx, h ? 1 : 0, INF);
+                            else finish(idx, h ? f : -1, h ? t : INF);
                         } else {
                             live = true;
                             ++rays;
                             inv = safe_inv(J.d);
-                            node = 0; sp = 0; iters = 0; occ = false;
+                            node = 0; sp = 0; iters = 0; best = ANY ? 0 : -1; tbest = INF;
                         }
                     }
                 }
@@ -887,24 +892,48 @@ __device__ __forceinline__ void trace_any_queue(int* counters, int n, TravStack&
             ++visits;
             float t[4];
             uint32_t c[4];
-            node4_test(J.G.nodes4, node, J.o, inv, TMIN, J.tmax, t, c);
+            node4_test(J.G.nodes4, node, J.o, inv, TMIN, ANY ? J.tmax : tbest, t, c);
             LeafList lv = take_leaves(t, c);
             while (lv.n > 0) {
                 ++tests;
                 float th; int fh;
-                if (tri_test(J.G.tri, lv.pop(), J.o, J.d, TMIN, J.tmax, th, fh) && fh != J.excl) { occ = true; break; }
+                if (tri_test(J.G.tri, lv.pop(), J.o, J.d, TMIN, J.tmax, th, fh) && fh != J.excl) {
+                    if (ANY) { best = 1; break; }
+                    if (th < tbest || (th == tbest && fh < best)) { tbest = th; best = fh; }
+                }
             }
-            if (occ) {
+            if (ANY && best) {
                 done = true;
             } else {
                 bool have = false, overflow = false;
                 uint32_t next = 0;
+                if (ANY) {
 #pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    if (t[s] < INF) {
-                        if (!have) { next = c[s]; have = true; }
-                        else if (sp >= LDS_STACK + SPILL_STACK) overflow = true;
-                        else st.put(sp++, c[s]);
+                    for (int s = 0; s < 4; ++s) {
+                        if (t[s] < INF) {
+                            if (!have) { next = c[s]; have = true; }
+                            else if (sp >= LDS_STACK + SPILL_STACK) overflow = true;
+                            else st.put(sp++, c[s]);
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int s = 0; s < 4; ++s)
+                        if (t[s] > tbest) t[s] = INF;
+                    // nearest first: continue with the nearest child, stack the others farthest-first
+                    cswap(t[0], c[0], t[1], c[1]); cswap(t[2], c[2], t[3], c[3]);
+                    cswap(t[0], c[0], t[2], c[2]); cswap(t[1], c[1], t[3], c[3]);
+                    cswap(t[1], c[1], t[2], c[2]);
+                    if (t[0] < INF) {
+                        next = c[0];
+                        have = true;
+#pragma unroll
+                        for (int s = 3; s >= 1; --s) {
+                            if (t[s] < INF) {
+                                if (sp >= LDS_STACK + SPILL_STACK) overflow = true;
+                                else st.put(sp++, c[s]);
+                            }
+                        }
                     }
                 }
                 if (overflow) {
@@ -924,7 +953,7 @@ __device__ __forceinline__ void trace_any_queue(int* counters, int n, TravStack&
             pend = true;
         }
     }
-    if (pend) finish(idx, occ);
+    if (pend) finish(idx, best, tbest);
     if (st.work && rays) {
         atomicAdd(st.work, (unsigned long long)visits);
         atomicAdd(st.work + 1, (unsigned long long)tests);

@@ -92,7 +92,7 @@ enum QCol {
 };
 
 // queue and path-state arrays of one wavefront chunk (SoA)
-constexpr int FETCH_INTS = 16 * FETCH_SLOT_INTS;   // slots for bounces 0..15
+constexpr int FETCH_INTS = 32 * FETCH_SLOT_INTS;   // slots k (shadow) and 16 + k (extension), k < 16
 
 struct Queues {
     float* ray[2][QNCOL];    // queue of bounce k is ray[k & 1]
@@ -106,7 +106,7 @@ struct Queues {
     float* sh[7];            // shadow entries [entry][i]: dir xyz, tmax, contrib rgb
     uint8_t* socc;           // shadow entry outcome [entry][i]: 0 no ray, 1 occluded, 2 unoccluded
     int* cnt;                // ray counts per bounce
-    int* fetch;              // fetch counters of the shadow traversal of bounce k: slot k, FETCH_SLOT_INTS each
+    int* fetch;              // fetch counters: slot k (shadow rays of bounce k), 16 + k (extension rays)
     uint32_t* spill;         // traversal stack spill
     float* L;                // per path sample radiance [total, 3] (processing order)
     int cap;                 // chunk capacity in paths

@@ -14,7 +14,7 @@ namespace st {
 #define ST_SHADE_WAVES 4
 #endif
 #ifndef ST_TRACE_WAVES
-#define ST_TRACE_WAVES 6
+#define ST_TRACE_WAVES 7
 #endif
 #define SHADE_OCC __attribute__((amdgpu_waves_per_eu(ST_SHADE_WAVES)))
 #ifndef ST_SHADE_BLOCK
@@ -70,15 +70,35 @@ __global__ void k_camera(FwdParams p, Queues q, long long q0, int n) {
     }
 }
 
-// closest hit for every queued ray of bounce k (queue k & 1).  The 64 rays of
-// a wave are 64 consecutive queue entries (an 8x8 pixel tile for camera rays)
-// and are traced in lockstep: measured faster here than refilling idle lanes
-// (trace_any_queue), which pays off for the shadow rays only.
+// closest hit for every queued ray of bounce k (queue k & 1)
+#ifndef ST_EXTEND_QUEUE
+#define ST_EXTEND_QUEUE 0
+#endif
 __global__ void __launch_bounds__(TRACE_BLOCK) TRACE_OCC k_extend(FwdParams p, Queues q, int k) {
     __shared__ uint32_t lds[LDS_STACK * TRACE_BLOCK];
     TravStack st = make_trav_stack(lds, q.spill, p.err, p.work ? p.work + 3 * WORK_EXTEND : nullptr);
     const int n = q.cnt[k];
     float* const* r = q.ray[k & 1];
+    if (ST_EXTEND_QUEUE) {
+        // persistent waves refilled from the fetch counters of slot 16 + k
+        trace_queue<false>(
+            q.fetch + FETCH_SLOT_INTS * (16 + k), n, st,
+            [&](int i, RayJob& J) {
+                const DevScene& S = p.scenes[p.cams[qu(r, QVD, i) & 0xFFFFu].scene];
+                J.o = V3{r[QOX][i], r[QOY][i], r[QOZ][i]};
+                J.d = V3{r[QDX][i], r[QDY][i], r[QDZ][i]};
+                J.tmax = __int_as_float(0x7f800000);
+                J.excl = (int)qu(r, QEXCL, i);
+                J.G = trace_geo(S);
+                return true;
+            },
+            [&](int i, int f, float t) {
+                q.ht[i] = t;
+                q.hf[i] = f;
+            });
+        return;
+    }
+    // 64 consecutive queue entries per wave, traced in lockstep
     const int stride = gridDim.x * blockDim.x;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const DevScene& S = p.scenes[p.cams[qu(r, QVD, i) & 0xFFFFu].scene];
@@ -226,7 +246,7 @@ __global__ void __launch_bounds__(TRACE_BLOCK) TRACE_OCC k_shadow(FwdParams p, Q
     const int n = q.cnt[k];
     float* const* r = q.ray[k & 1];
     const long long items = (long long)n * q.nent;
-    trace_any_queue(
+    trace_queue<true>(
         q.fetch + FETCH_SLOT_INTS * k, (int)items, st,
         [&](int w, RayJob& J) {
             const int l = w / n, i = w - l * n;
@@ -244,7 +264,7 @@ __global__ void __launch_bounds__(TRACE_BLOCK) TRACE_OCC k_shadow(FwdParams p, Q
             J.G = trace_geo(S);
             return true;
         },
-        [&](int w, bool occ) {
+        [&](int w, int occ, float) {
             const int l = w / n, i = w - l * n;
             q.socc[(size_t)l * q.cap + i] = occ ? 1 : 2;
         });
