@@ -88,6 +88,12 @@ def lib():
         L.or_sample_grad.restype = ctypes.c_double
         L.or_secondary_term.argtypes = [P, P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_longlong,
                                         ctypes.c_uint, P]
+        L.or_scene_set_texels.argtypes = [P, ctypes.c_int, P]
+        L.or_scene_set_texels.restype = ctypes.c_longlong
+        L.or_texel_index.argtypes = [ctypes.c_int, ctypes.c_longlong, ctypes.c_double, ctypes.c_double]
+        L.or_texel_index.restype = ctypes.c_longlong
+        L.or_texel_of.argtypes = [P, ctypes.c_int, P]
+        L.or_texel_of.restype = ctypes.c_longlong
         _lib = L
     return _lib
 
@@ -126,6 +132,22 @@ class OracleScene:
         if not self.h:
             raise ValueError("oracle scene creation failed")
         self.nv, self.nf = self.V.shape[0], self.F.shape[0]
+        self.tex_res, self.ntex = 0, self.nf
+
+    def set_mesh_colors(self, r, texels):
+        """Materials as mesh colours of resolution r: texels [nf (r+1)(r+2)/2, 7] (Sec. 3.3)."""
+        t = np.ascontiguousarray(texels, np.float32)
+        n = self.nf * (r + 1) * (r + 2) // 2
+        if t.shape != (n, 7):
+            raise ValueError(f"texels must be [{n}, 7] at r = {r}")
+        self.mat = t
+        got = lib().or_scene_set_texels(self.h, int(r), _p(self.mat))
+        if got != n:
+            raise ValueError("oracle rejected the mesh-colour resolution")
+        self.tex_res, self.ntex = int(r), n
+
+    def texel_of(self, face, x):
+        return int(lib().or_texel_of(self.h, int(face), _p(_f64(x))))
 
     @classmethod
     def from_scene(cls, sc):
@@ -198,7 +220,7 @@ class OracleScene:
         d = np.ascontiguousarray(d_image, np.float32).reshape(npix, 3)
         ne = int(sum(round(edge_ratio * int(w) * int(h) * spp) for w, h in res))
         dV = np.zeros((self.nv, 3))
-        dM = np.zeros((self.nf, 7))
+        dM = np.zeros((self.ntex, 7))
         ph = np.zeros(npix * spp, np.uint32)
         eh = np.zeros(max(ne, 1), np.uint32)
         pm = None if path_mask is None else np.ascontiguousarray(path_mask, np.uint8)
@@ -214,7 +236,7 @@ class OracleScene:
         rows, res = cam_arrays(cams)
         rgb = np.zeros(3)
         dV = np.zeros((self.nv, 3))
-        dM = np.zeros((self.nf, 7))
+        dM = np.zeros((self.ntex, 7))
         loss = lib().or_sample_grad(self.h, _p(rows), _p(res), len(cams), spp, bounces, seed, flags, view, px, py,
                                     j, _p(_f64(w)), _p(rgb), _p(dV), _p(dM))
         return loss, rgb, dV, dM
@@ -232,6 +254,11 @@ class OracleScene:
 
 
 # ---- stateless pieces ----------------------------------------------------
+
+def texel_index(r, t, alpha, beta):
+    """Mesh-colour texel of barycentric (alpha, beta) in triangle t at resolution r (Sec. 3.3)."""
+    return int(lib().or_texel_index(int(r), int(t), float(alpha), float(beta)))
+
 
 def philox4x32(ctr, key):
     c = np.ascontiguousarray(ctr, np.uint32)

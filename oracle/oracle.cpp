@@ -165,6 +165,7 @@ struct BVHNode { double lo[3], hi[3]; int left, right, first, count; };
 
 struct Scene {
     int nv = 0, nf = 0, nl = 0, he = 0, we = 0;
+    int tex_res = 0;               // mesh-colours resolution r; mat holds nf (r+1)(r+2)/2 texels
     uint32_t id = 0;
     std::vector<double> V, mat, lights, env;
     std::vector<int> F;
@@ -180,10 +181,43 @@ struct Scene {
     D3 vert(int i) const { return D3(V[3 * i], V[3 * i + 1], V[3 * i + 2]); }
 };
 
+// Mesh colours (Sec. 3.3 "Representation"): the texel of the point with
+// barycentric coordinates (alpha, beta) in triangle t at resolution r is
+// entry t (r+1)(r+2)/2 + i (2r - i + 3)/2 + j of the texel array, with
+// (i, j) = floor(r (alpha, beta)); alpha weighs the triangle's second vertex and
+// beta its third.  Points on the boundary of the barycentric domain are
+// clamped into it (0 <= i <= r, 0 <= j <= r - i).
+static long long texel_index(int r, long long t, double alpha, double beta) {
+    long long i = (long long)std::floor(r * alpha), j = (long long)std::floor(r * beta);
+    if (!(alpha == alpha) || !(beta == beta)) i = j = 0;
+    i = std::min<long long>(std::max<long long>(i, 0), r);
+    j = std::min<long long>(std::max<long long>(j, 0), r - i);
+    return (t * (r + 1) * (r + 2) + i * (2 * r - i + 3)) / 2 + j;
+}
+
+// Barycentric coordinates (alpha of v1, beta of v2) of point x in the plane of face f.
+static void barycentric(const Scene& s, int f, const D3& x, double& alpha, double& beta);
+
+// Texel (material row) of the point x on face f.
+static long long texel_of(const Scene& s, int f, const D3& x) {
+    if (s.tex_res == 0) return f;
+    double a, b;
+    barycentric(s, f, x, a, b);
+    return texel_index(s.tex_res, f, a, b);
+}
+
 // Unnormalised face normal (v1-v0)x(v2-v0), evaluated in a fixed operation order.
 static D3 face_N(const Scene& s, int f) {
     D3 a = s.vert(s.F[3 * f]), b = s.vert(s.F[3 * f + 1]), c = s.vert(s.F[3 * f + 2]);
     return cross(b - a, c - a);
+}
+
+static void barycentric(const Scene& s, int f, const D3& x, double& alpha, double& beta) {
+    D3 v0 = s.vert(s.F[3 * f]), e1 = s.vert(s.F[3 * f + 1]) - v0, e2 = s.vert(s.F[3 * f + 2]) - v0;
+    D3 N = cross(e1, e2), q = x - v0;
+    double nn = dot(N, N);
+    alpha = dot(cross(q, e2), N) / nn;
+    beta = dot(cross(e1, q), N) / nn;
 }
 
 // Edge list in canonical order: (va < vb) ascending, f1 the smaller face id.
@@ -565,6 +599,7 @@ static const int MAXL = 16;
 
 struct VRec {
     int face = -1, flip = 0;
+    long long tex = -1;           // material texel of the vertex
     D3 wo;
     int lcode[MAXL];
     int ecode = 0; D3 we, Le; double eden = 0.0;
@@ -638,8 +673,10 @@ static D3 trace_estimator(const Scene& s, D3 o, D3 d, int exclude, int nvert, bo
         D3 wo = -d;
         int flip = dot(n, wo) < 0.0;
         if (flip) n = -n;
-        const double* m = &s.mat[7 * f];
-        if (vr) { vr->face = f; vr->flip = flip; vr->wo = wo; rec->nv = k; }
+        const long long tx = texel_of(s, f, x);
+        if (s.tex_res > 0) hash.push((uint32_t)tx);
+        const double* m = &s.mat[7 * tx];
+        if (vr) { vr->face = f; vr->flip = flip; vr->wo = wo; vr->tex = tx; rec->nv = k; }
         // next-event estimation: every point light (Sec. 3.1 point-light input)
         for (int l = 0; l < s.nl; ++l) {
             const double* lt = &s.lights[6 * l];
@@ -782,14 +819,15 @@ template <class T> static T seeded(double v, int slot) { (void)slot; return T(v)
 template <> Dual<48> seeded<Dual<48>>(double v, int slot) { Dual<48> r(v); if (slot >= 0) r.d[slot] = 1.0; return r; }
 template <> Dual<128> seeded<Dual<128>>(double v, int slot) { Dual<128> r(v); if (slot >= 0) r.d[slot] = 1.0; return r; }
 
-struct PView {                 // local parameters of one path: its faces and their vertices
+struct PView {                 // local parameters of one path: its vertices' texels and face vertices
     const Scene* s = nullptr;
     int nvs = 0, vids[3 * MAXV];
-    int nfs = 0, fids[MAXV];
+    int nts = 0;
+    long long tids[MAXV];
     int vslot(int v) const { for (int i = 0; i < nvs; ++i) if (vids[i] == v) return i; return -1; }
-    int fslot(int f) const { for (int i = 0; i < nfs; ++i) if (fids[i] == f) return i; return -1; }
-    void add_face(int f) {
-        if (fslot(f) < 0) fids[nfs++] = f;
+    int tslot(long long t) const { for (int i = 0; i < nts; ++i) if (tids[i] == t) return i; return -1; }
+    void add_vertex(int f, long long tex) {
+        if (tslot(tex) < 0) tids[nts++] = tex;
         for (int k = 0; k < 3; ++k) { int v = s->F[3 * f + k]; if (vslot(v) < 0) vids[nvs++] = v; }
     }
 };
@@ -804,11 +842,11 @@ template <class T> static V3<T> pvert(const PView& P, int v, const Perturb& pt) 
     return V3<T>(seeded<T>(p.x, 3 * sl), seeded<T>(p.y, 3 * sl + 1), seeded<T>(p.z, 3 * sl + 2));
 }
 
-template <class T> static void pmat(const PView& P, int f, const Perturb& pt, T out[7]) {
-    int sl = DT<T>::N ? P.fslot(f) : -1;
+template <class T> static void pmat(const PView& P, long long tex, const Perturb& pt, T out[7]) {
+    int sl = DT<T>::N ? P.tslot(tex) : -1;
     for (int c = 0; c < 7; ++c) {
-        double v = P.s->mat[7 * f + c];
-        if (pt.kind == 1 && pt.index == 7 * f + c) v += pt.delta;
+        double v = P.s->mat[7 * tex + c];
+        if (pt.kind == 1 && pt.index == 7 * tex + c) v += pt.delta;
         out[c] = sl < 0 ? T(v) : seeded<T>(v, DT<T>::FB + 7 * sl + c);
     }
 }
@@ -830,7 +868,7 @@ static T replay(const Scene& s, const PRec& R, const double w[3], bool interior,
         if (vr.flip) n = -n;
         V3<T> wo = lift<T>(vr.wo);
         T m[7];
-        pmat<T>(P, f, pt, m);
+        pmat<T>(P, vr.tex, pt, m);
         V3<T> C;
         for (int l = 0; l < s.nl; ++l) {
             if (vr.lcode[l] != 2) continue;
@@ -873,14 +911,14 @@ static T replay(const Scene& s, const PRec& R, const double w[3], bool interior,
 template <class T> static void scatter(const PView& P, const T& loss, Grad& g) {
     for (int i = 0; i < P.nvs; ++i)
         for (int c = 0; c < 3; ++c) g.dV[3 * P.vids[i] + c] += loss.d[3 * i + c];
-    for (int i = 0; i < P.nfs; ++i)
-        for (int c = 0; c < 7; ++c) g.dM[7 * P.fids[i] + c] += loss.d[DT<T>::FB + 7 * i + c];
+    for (int i = 0; i < P.nts; ++i)
+        for (int c = 0; c < 7; ++c) g.dM[7 * P.tids[i] + c] += loss.d[DT<T>::FB + 7 * i + c];
 }
 
 static void path_gradient(const Scene& s, const PRec& R, const double w[3], bool interior, bool secondary,
                           int bounces, Grad& g) {
     PView P; P.s = &s;
-    for (int k = 0; k < R.nv; ++k) P.add_face(R.v[k].face);
+    for (int k = 0; k < R.nv; ++k) P.add_vertex(R.v[k].face, R.v[k].tex);
     if (bounces <= 3) {
         Perturb none;
         Dual<48> l = replay<Dual<48>>(s, R, w, interior, secondary, P, none);
@@ -1166,6 +1204,21 @@ void* or_scene_create(const float* V, int nv, const int* F, int nf, const float*
 
 void or_scene_destroy(void* p) { delete (Scene*)p; }
 
+// Switch the scene's materials to mesh colours of resolution r: texels holds
+// nf (r+1)(r+2)/2 rows of 7 (r = 0: one row per face).  Returns the row count.
+long long or_scene_set_texels(void* p, int r, const float* texels) {
+    Scene* s = (Scene*)p;
+    if (r < 0 || r > 64) return -1;
+    s->tex_res = r;
+    const size_t n = 7 * (size_t)s->nf * (size_t)((r + 1) * (r + 2) / 2);
+    s->mat.assign(texels, texels + n);
+    return (long long)(n / 7);
+}
+
+long long or_texel_index(int r, long long t, double alpha, double beta) { return texel_index(r, t, alpha, beta); }
+
+long long or_texel_of(void* p, int f, const double* x) { return texel_of(*(Scene*)p, f, D3(x[0], x[1], x[2])); }
+
 int or_num_edges(void* p) { return (int)((Scene*)p)->edges.size(); }
 
 void or_edges(void* p, int* out) {
@@ -1292,7 +1345,7 @@ int or_backward(void* p, const double* cams, const int* res, int ncam, int spp, 
     Key key{seed, s->id};
     int nt = std::max(1, nthreads);
     std::vector<Grad> G(nt);
-    for (auto& g : G) { g.dV.assign(3 * (size_t)s->nv, 0.0); g.dM.assign(7 * (size_t)s->nf, 0.0); }
+    for (auto& g : G) { g.dV.assign(3 * (size_t)s->nv, 0.0); g.dM.assign(s->mat.size(), 0.0); }
     const bool interior = flags & 1, primary = flags & 2, secondary = flags & 4;
     const int64_t npath = vw.pixoff[ncam] * spp;
     if (path_hash) std::memset(path_hash, 0, sizeof(unsigned) * npath);
@@ -1332,7 +1385,7 @@ int or_backward(void* p, const double* cams, const int* res, int ncam, int spp, 
         }
     }
     for (size_t i = 0; i < 3 * (size_t)s->nv; ++i) { double a = 0; for (auto& g : G) a += g.dV[i]; dV[i] = a; }
-    for (size_t i = 0; i < 7 * (size_t)s->nf; ++i) { double a = 0; for (auto& g : G) a += g.dM[i]; dmat[i] = a; }
+    for (size_t i = 0; i < s->mat.size(); ++i) { double a = 0; for (auto& g : G) a += g.dM[i]; dmat[i] = a; }
     return 0;
 }
 
@@ -1348,11 +1401,11 @@ double or_sample_frozen(void* p, const double* cams, const int* res, int ncam, i
     Key key{seed, s->id};
     Hash h;
     PRec rec;
-    Grad dummy; dummy.dV.assign(3 * (size_t)s->nv, 0.0); dummy.dM.assign(7 * (size_t)s->nf, 0.0);
+    Grad dummy; dummy.dV.assign(3 * (size_t)s->nv, 0.0); dummy.dM.assign(s->mat.size(), 0.0);
     SecCtx sc{{w[0], w[1], w[2]}, &dummy};
     pixel_sample(*s, vw.cams[view], view, px, py, j, spp, bounces, key, h, &rec, (flags & 4) ? &sc : nullptr);
     PView P; P.s = s;
-    for (int k = 0; k < rec.nv; ++k) P.add_face(rec.v[k].face);
+    for (int k = 0; k < rec.nv; ++k) P.add_vertex(rec.v[k].face, rec.v[k].tex);
     Perturb pt; pt.kind = kind; pt.index = index; pt.delta = delta;
     return replay<double>(*s, rec, w, (flags & 1) != 0, (flags & 4) != 0, P, pt);
 }
@@ -1367,7 +1420,7 @@ double or_sample_grad(void* p, const double* cams, const int* res, int ncam, int
     Key key{seed, s->id};
     Hash h;
     PRec rec;
-    Grad g; g.dV.assign(3 * (size_t)s->nv, 0.0); g.dM.assign(7 * (size_t)s->nf, 0.0);
+    Grad g; g.dV.assign(3 * (size_t)s->nv, 0.0); g.dM.assign(s->mat.size(), 0.0);
     // flag 8: leave out the direct edge-endpoint terms (only the replay derivative)
     SecCtx sc{{w[0], w[1], w[2]}, (flags & 8) ? nullptr : &g};
     D3 L = pixel_sample(*s, vw.cams[view], view, px, py, j, spp, bounces, key, h, &rec,
@@ -1375,9 +1428,9 @@ double or_sample_grad(void* p, const double* cams, const int* res, int ncam, int
     rgb[0] = L.x; rgb[1] = L.y; rgb[2] = L.z;
     path_gradient(*s, rec, w, (flags & 1) != 0, (flags & 4) != 0, bounces, g);
     for (size_t i = 0; i < 3 * (size_t)s->nv; ++i) dV[i] = g.dV[i];
-    for (size_t i = 0; i < 7 * (size_t)s->nf; ++i) dmat[i] = g.dM[i];
+    for (size_t i = 0; i < s->mat.size(); ++i) dmat[i] = g.dM[i];
     PView P; P.s = s;
-    for (int k = 0; k < rec.nv; ++k) P.add_face(rec.v[k].face);
+    for (int k = 0; k < rec.nv; ++k) P.add_vertex(rec.v[k].face, rec.v[k].tex);
     Perturb none;
     return replay<double>(*s, rec, w, true, false, P, none);
 }
@@ -1390,10 +1443,10 @@ double or_sample_grad(void* p, const double* cams, const int* res, int ncam, int
 void or_secondary_term(void* p, const double* pp, const double* nn, const double* wo, int face, int budget,
                        long long nsamples, unsigned seed, double* dV) {
     Scene* s = (Scene*)p;
-    Grad g; g.dV.assign(3 * (size_t)s->nv, 0.0); g.dM.assign(7 * (size_t)s->nf, 0.0);
+    Grad g; g.dV.assign(3 * (size_t)s->nv, 0.0); g.dM.assign(s->mat.size(), 0.0);
     Key key{seed, s->id};
     D3 x(pp[0], pp[1], pp[2]), n(nn[0], nn[1], nn[2]), o(wo[0], wo[1], wo[2]);
-    const double* m = &s->mat[7 * face];
+    const double* m = &s->mat[7 * texel_of(*s, face, x)];
     for (long long i = 0; i < nsamples; ++i) {
         Ctr ctr{(uint32_t)i, 0u, 0u, 3u};
         double u[4];

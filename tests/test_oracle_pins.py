@@ -598,3 +598,125 @@ def test_lbvh_reference_definition(k):
     for i in range(n):
         f = int(keys[i] & np.uint64(0xFFFFFFFF))
         assert np.array_equal(aabb[n - 1 + i, :3], mn[f]) and np.array_equal(aabb[n - 1 + i, 3:], mx[f])
+
+
+# --------------------------------------------------------------------------
+# mesh colours (Sec. 3.3 "Representation")
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("r", [0, 1, 2, 3, 5, 8])
+def test_mesh_color_layout_is_a_bijection_per_triangle(r):
+    """The cells {(i, j): 0 <= i <= r, 0 <= j <= r - i} of every triangle map one to
+    one onto that triangle's block of (r+1)(r+2)/2 texels, blocks in triangle
+    order; r = 0 is one texel per triangle."""
+    T = (r + 1) * (r + 2) // 2
+    for t in (0, 1, 7, 1000):
+        seen = set()
+        for i in range(r + 1):
+            for j in range(r - i + 1):
+                # a point strictly inside cell (i, j) of the barycentric grid
+                a, b = ((i + 0.25) / r, (j + 0.25) / r) if r else (0.25, 0.25)
+                k = O.texel_index(r, t, a, b)
+                assert t * T <= k < (t + 1) * T
+                seen.add(k)
+        assert len(seen) == T
+    # the corners and the far edge of the domain stay inside the block
+    for a, b in [(0, 0), (1, 0), (0, 1), (0.5, 0.5), (-1e-9, 0.3), (0.7, 0.3 + 1e-9)]:
+        assert 5 * T <= O.texel_index(r, 5, a, b) < 6 * T
+
+
+def _bary_numpy(p, v0, v1, v2):
+    """(alpha, beta) with p = v0 + alpha (v1 - v0) + beta (v2 - v0), by least squares."""
+    A = np.stack([v1 - v0, v2 - v0], 1)
+    sol, *_ = np.linalg.lstsq(A, p - v0, rcond=None)
+    return sol
+
+
+def test_mesh_colors_lambertian_plane_point_light():
+    """Per-sample radiance of a two-triangle plane textured with mesh colours at
+    r = 4 (a different albedo per texel): kd of the hit point's texel / pi * I cos / r^2."""
+    V = np.array([[-1.2, -1.2, 0], [1.2, -1.2, 0], [1.2, 1.2, 0], [-1.2, 1.2, 0]], np.float32)
+    F = np.array([[0, 1, 2], [0, 2, 3]], np.int32)
+    r = 4
+    T = (r + 1) * (r + 2) // 2
+    rng = np.random.default_rng(12)
+    tex = np.zeros((2 * T, 7), np.float32)
+    tex[:, :3] = rng.uniform(0.1, 0.9, (2 * T, 3))
+    tex[:, 6] = 0.3
+    light = np.array([[0.5, 0.3, 2.0, 10.0, 8.0, 6.0]], np.float32)
+    sc = O.OracleScene(V, F, tex[:2], light, None, scene_id=3)
+    sc.set_mesh_colors(r, tex)
+    cam = S.Camera((0.0, 0.0, 3.0), (0, 0, 0), (0, 1, 0), 45.0, 16, 12)
+    seed, spp = 9, 2
+    rgb, _ = sc.render_samples([cam], spp, 1, seed)
+    pl, I = light[0, :3].astype(float), light[0, 3:].astype(float)
+    Vd = V.astype(float)
+    worst, used = 0.0, set()
+    for y in range(12):
+        for x in range(16):
+            for j in range(spp):
+                u = draw4(y * 16 + x, j, 0, 0, seed, 3)
+                o, d = _pinhole(cam, x + u[0], y + u[1])
+                p = o + (-o[2] / d[2]) * d
+                if max(abs(p[0]), abs(p[1])) > 1.2 - 1e-6:       # off the plane (or on its rim)
+                    if max(abs(p[0]), abs(p[1])) > 1.2 + 1e-6:
+                        assert not rgb[y * 16 + x, j].any()
+                    continue
+                # face of the quad containing p (diagonal v0-v2: x >= y is face 0)
+                f = 0 if p[0] >= p[1] else 1
+                a, b = _bary_numpy(p, *Vd[F[f]])
+                k = O.texel_index(r, f, a, b)
+                used.add(k)
+                wl = pl - p
+                r2 = wl @ wl
+                expect = tex[k, :3].astype(float) / np.pi * I * (wl[2] / math.sqrt(r2)) / r2
+                worst = max(worst, np.abs(rgb[y * 16 + x, j] - expect).max() / expect.max())
+    assert worst < 1e-12
+    assert len(used) > 15         # the view covers most of the 30 texels
+
+
+def _textured_test_scene(r, constant_per_face):
+    rng = np.random.default_rng(44)
+    V, F = S.noise_sphere(4, 0.2, noise_seed=5)
+    floor = np.array([[-3, -1.2, -3], [3, -1.2, -3], [3, -1.2, 3], [-3, -1.2, 3]], np.float32)
+    nv = V.shape[0]
+    Vf = np.concatenate([V, floor]).astype(np.float32)
+    Ff = np.concatenate([F, [[nv, nv + 2, nv + 1], [nv, nv + 3, nv + 2]]]).astype(np.int32)
+    mat = S.random_materials(Ff.shape[0], rng)
+    T = (r + 1) * (r + 2) // 2
+    tex = np.repeat(mat, T, axis=0) if constant_per_face else S.random_materials(Ff.shape[0] * T, rng)
+    env = S.gaussian_lobe_envmap(rng, 32, 16)
+    lights = np.array([[1.0, 2.0, 1.5, 6, 6, 6]], np.float32)
+    return Vf, Ff, mat, tex, lights, env
+
+
+def test_mesh_colors_constant_per_face_equal_per_face_materials():
+    """Texels equal within every triangle render exactly like per-face materials,
+    and the texel gradients of a triangle sum to its per-face gradient (all terms)."""
+    r = 3
+    Vf, Ff, mat, tex, lights, env = _textured_test_scene(r, True)
+    cams = [S.look_at_origin((0.3, 0.9, 3.0), 12, 10)]
+    a = O.OracleScene(Vf, Ff, mat, lights, env)
+    b = O.OracleScene(Vf, Ff, mat, lights, env)
+    b.set_mesh_colors(r, tex)
+    ia, _ = a.render(cams, 4, 2, seed=5)
+    ib, _ = b.render(cams, 4, 2, seed=5)
+    assert np.array_equal(ia, ib)
+    d = np.random.default_rng(3).normal(size=ia.shape).astype(np.float32)
+    dVa, dMa, _, _ = a.backward(cams, 4, 2, d, seed=5, flags=7)
+    dVb, dMb, _, _ = b.backward(cams, 4, 2, d, seed=5, flags=7)
+    T = (r + 1) * (r + 2) // 2
+    assert np.allclose(dVa, dVb, rtol=1e-12, atol=1e-15)
+    assert np.allclose(dMb.reshape(-1, T, 7).sum(1), dMa, rtol=1e-10, atol=1e-14)
+    assert np.abs(dMa).max() > 0
+
+
+def test_fd_frozen_mesh_colors():
+    """Dual-number derivative with respect to texels and vertices ≡ central
+    differences of the frozen path, textured scene at r = 2, envmap + point light."""
+    Vf, Ff, mat, tex, lights, env = _textured_test_scene(2, False)
+    sc = O.OracleScene(Vf, Ff, mat, lights, env)
+    sc.set_mesh_colors(2, tex)
+    cams = [S.look_at_origin((0.3, 0.9, 3.0), 16, 16)]
+    samples = [(0, x, y, j) for (x, y) in [(8, 8), (5, 9), (10, 4), (3, 13)] for j in range(2)]
+    assert _fd_check(sc, cams, 2, 3, samples, flags=1) > 50
