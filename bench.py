@@ -56,6 +56,7 @@ def parse():
     ap.add_argument("--views", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--mesh-colors-res", type=int, default=4, help="mesh-colour step at this resolution (0 skips)")
     ap.add_argument("--opt-steps", type=int, default=200, help="optimisation-loop steps (0 skips)")
     ap.add_argument("--cpu-baseline-res", type=int, default=1024)
     ap.add_argument("--profile-only", action="store_true", help="one untimed step (for rocprofv3 runs)")
@@ -83,6 +84,42 @@ def cpu_baseline(wl, res, spp, bounces):
     return {"value": n / dt, "unit": "path samples/s (fwd+adjoint)", "cores": nt, "kind": "oracle",
             "sample": f"same torus scene and envmap, 1 view at {res}x{res}, {spp} spp, {bounces} bounces, "
                       f"forward + adjoint (interior, primary and secondary edges): {n} path samples in {dt:.2f} s"}
+
+
+def mesh_colors_step(B, S, torch, wl, r, steps=3):
+    """The same optimisation step (update + render + adjoint, all terms) with the
+    materials as mesh colours of resolution r (Sec. 3.3): 40,000 (r+1)(r+2)/2 texels."""
+    import numpy as np
+    sc = wl.scenes[0]
+    g = B.GPUScene.from_scene(sc)
+    tex = torch.from_numpy(S.mesh_color_texels(sc.mat, r, np.random.default_rng(8))).cuda()
+    g.set_mesh_colors(r, tex)
+    npix = B.num_pixels(wl.cams)
+    img = torch.empty((npix, 3), dtype=torch.float32, device="cuda")
+    dV = torch.empty((g.nv, 3), dtype=torch.float32, device="cuda")
+    dM = torch.empty((g.ntex, 7), dtype=torch.float32, device="cuda")
+    V0 = torch.from_numpy(sc.V).cuda()
+    target = g.render(wl.cams, wl.spp, wl.bounces, seed=1).clone()
+
+    def step(i):
+        g.update(V=V0)
+        g.render(wl.cams, wl.spp, wl.bounces, seed=i, out=img)
+        g.backward(wl.cams, wl.spp, wl.bounces, (img - target) * (2.0 / img.numel()), seed=i,
+                   flags=B.ST_ALL_GRADS, dV=dV, dmat=dM)
+
+    step(0)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(steps):
+        step(10 + i)
+    e1.record()
+    torch.cuda.synchronize()
+    g.check_errors()
+    ms = e0.elapsed_time(e1) / steps
+    n = npix * wl.spp
+    return {"tex_res": r, "texels": g.ntex, "ms_per_step": ms, "value": n / (ms / 1e3), "unit": "path samples/s",
+            "steps": steps}
 
 
 def batched_vs_per_view(B, S, torch, reps=3):
@@ -228,6 +265,8 @@ def main():
                      "rays_per_s": rays / max(launches_per_step, 1) / (avg_ms / 1e3)},
         "kernels": kernels,
     }
+    if args.mesh_colors_res > 0:
+        out["mesh_colors"] = mesh_colors_step(B, S, torch, wl, args.mesh_colors_res)
     if not args.no_batched:
         out["batched"] = batched_vs_per_view(B, S, torch)
     if args.opt_steps > 0:

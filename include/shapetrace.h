@@ -94,9 +94,27 @@ int st_scene_create(const float* V, int32_t nv, const int32_t* F, int32_t nf, co
                     const float* lights, int32_t nl, const float* envmap, int32_t he, int32_t we,
                     uint32_t scene_id, hipStream_t s, st_scene** out);
 
-/* Replace vertex positions (float [nv,3]) and/or materials (float [nf,7]); either
- * may be NULL.  Rebuilds the LBVH and edge CDF on the stream; allocates nothing. */
+/* Replace vertex positions (float [nv,3]) and/or materials (float [ntex,7], the
+ * current material rows: one per face, or the mesh-colour texels); either may be
+ * NULL.  Rebuilds the LBVH and edge CDF on the stream; allocates nothing. */
 int st_scene_update(st_scene* scene, const float* V, const float* face_materials, hipStream_t s);
+
+/* Switch the scene's materials to mesh colours (Sec. 3.3 "Representation") of
+ * resolution r in [0, 64]: texels is a device float [ntex, 7] with
+ * ntex = nf (r+1)(r+2)/2, same 7 parameters as per-face materials.  The point
+ * with barycentric coordinates (alpha, beta) of face t (alpha weighs the face's
+ * second vertex, beta its third) is shaded with texel
+ * t (r+1)(r+2)/2 + i (2r - i + 3)/2 + j, (i, j) = floor(r (alpha, beta)) clamped
+ * to 0 <= i <= r, 0 <= j <= r - i.  r = 0 is one texel per face (the
+ * representation st_scene_create sets up).  Afterwards st_scene_update takes
+ * [ntex,7] materials and st_render_backward writes d/d(texels) [ntex,7] (texel
+ * lookup is piecewise constant, so texels receive the material gradient of the
+ * points they shade; texel boundaries inside a face carry no edge term).
+ * Allocates (not capturable) and synchronises s; ST_ERR_INVALID_ARG when
+ * 7 ntex >= 2^31. */
+int st_scene_set_mesh_colors(st_scene* scene, int32_t r, const float* texels, hipStream_t s);
+/* Current mesh-colour resolution and number of material rows (either may be NULL). */
+int st_scene_mesh_colors_info(const st_scene* scene, int32_t* r, int64_t* ntex);
 
 /* Forward render (Sec. 3.2, R(x, c_i)).  cams: host array of ncam cameras.
  * out: device float [sum_i width_i*height_i, 3], views concatenated, each row-major;
@@ -111,7 +129,8 @@ int st_render(st_scene* scene, const st_camera* cams, int32_t ncam, int32_t spp,
  * whose image gradient it receives; it replays every path from its random
  * counters and keeps no state from st_render.
  *   d_image: device float, same layout as st_render's out.
- *   out_dV: device float [nv,3]; out_dmat: device float [nf,7]; both overwritten. */
+ *   out_dV: device float [nv,3]; out_dmat: device float [ntex,7] (ntex = nf unless the scene uses
+ *   mesh colours, st_scene_set_mesh_colors); both overwritten. */
 int st_render_backward(st_scene* scene, const st_camera* cams, int32_t ncam, int32_t spp, int32_t bounces,
                        uint32_t seed, const st_render_opts* opts, const float* d_image, float* out_dV,
                        float* out_dmat, hipStream_t s);

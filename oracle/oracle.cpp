@@ -188,8 +188,10 @@ struct Scene {
 // beta its third.  Points on the boundary of the barycentric domain are
 // clamped into it (0 <= i <= r, 0 <= j <= r - i).
 static long long texel_index(int r, long long t, double alpha, double beta) {
+    if (!(alpha == alpha) || !(beta == beta)) alpha = beta = 0.0;
+    alpha = std::min(std::max(alpha, -1.0), 2.0);
+    beta = std::min(std::max(beta, -1.0), 2.0);
     long long i = (long long)std::floor(r * alpha), j = (long long)std::floor(r * beta);
-    if (!(alpha == alpha) || !(beta == beta)) i = j = 0;
     i = std::min<long long>(std::max<long long>(i, 0), r);
     j = std::min<long long>(std::max<long long>(j, 0), r - i);
     return (t * (r + 1) * (r + 2) + i * (2 * r - i + 3)) / 2 + j;

@@ -24,7 +24,8 @@ ST_FORWARD_MEGAKERNEL = 16
 ST_COUNT_WORK = 32
 ST_ALL_GRADS = 7
 
-EXPORTED = ["st_render_opts_default", "st_scene_create", "st_scene_update", "st_render", "st_render_backward",
+EXPORTED = ["st_render_opts_default", "st_scene_create", "st_scene_update", "st_scene_set_mesh_colors",
+            "st_scene_mesh_colors_info", "st_render", "st_render_backward",
             "st_render_batch", "st_autotune", "st_check_errors", "st_read_work", "st_scene_info", "st_scene_edges", "st_scene_lbvh",
             "st_trace_rays", "st_profile_enable", "st_profile_read", "st_scene_destroy", "st_last_error",
             "st_version"]
@@ -61,6 +62,8 @@ def load(path: str = LIB_PATH):
     L.st_render_opts_default.restype = StOpts
     L.st_scene_create.argtypes = [P, I32, P, I32, P, P, I32, P, I32, I32, U32, P, ctypes.POINTER(P)]
     L.st_scene_update.argtypes = [P, P, P, P]
+    L.st_scene_set_mesh_colors.argtypes = [P, I32, P, P]
+    L.st_scene_mesh_colors_info.argtypes = [P, P, P]
     L.st_render.argtypes = [P, P, I32, I32, I32, U32, ctypes.POINTER(StOpts), P, P]
     L.st_render_backward.argtypes = [P, P, I32, I32, I32, U32, ctypes.POINTER(StOpts), P, P, P, P]
     L.st_render_batch.argtypes = [P, I32, P, P, I32, I32, I32, U32, ctypes.POINTER(StOpts), P, P]
@@ -158,6 +161,20 @@ class GPUScene:
         info = (ctypes.c_int64 * 6)()
         _check(L.st_scene_info(self.h, info))
         self.ne = int(info[2])
+        self.tex_res, self.ntex = 0, self.nf
+
+    def set_mesh_colors(self, r: int, texels):
+        """Materials as mesh colours of resolution r: texels [nf (r+1)(r+2)/2, 7] (Sec. 3.3)."""
+        import torch
+        n = self.nf * (r + 1) * (r + 2) // 2
+        t = torch.as_tensor(texels, dtype=torch.float32, device="cuda").contiguous()
+        if tuple(t.shape) != (n, 7):
+            raise ValueError(f"texels must be [{n}, 7] at r = {r}")
+        _check(load().st_scene_set_mesh_colors(self.h, int(r), _ptr(t), _stream()))
+        self.mat = t
+        rr, nt = ctypes.c_int32(), ctypes.c_int64()
+        _check(load().st_scene_mesh_colors_info(self.h, ctypes.byref(rr), ctypes.byref(nt)))
+        self.tex_res, self.ntex = int(rr.value), int(nt.value)
 
     @classmethod
     def from_scene(cls, sc):
@@ -196,7 +213,7 @@ class GPUScene:
         if dV is None:
             dV = torch.empty((self.nv, 3), dtype=torch.float32, device="cuda")
         if dmat is None:
-            dmat = torch.empty((self.nf, 7), dtype=torch.float32, device="cuda")
+            dmat = torch.empty((self.ntex, 7), dtype=torch.float32, device="cuda")
         o = make_opts(flags=flags, edge_ratio=edge_ratio, dbg_hash=debug_hash, dbg_edge_hash=debug_edge_hash,
                       path_mask=path_mask, edge_mask=edge_mask)
         d = d_image.contiguous()

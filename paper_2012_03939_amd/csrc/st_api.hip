@@ -423,6 +423,7 @@ int st_scene_create(const float* V, int32_t nv, const int32_t* F, int32_t nf, co
     st_scene* sc = new st_scene();
     SceneDev& d = sc->d;
     d.nv = nv; d.nf = nf; d.nl = nl; d.he = he; d.we = we; d.ne = (int)edges.size(); d.scene_id = scene_id;
+    d.tex_res = 0; d.ntex = nf;
     int rc = ST_OK;
     auto A = [&](int r) { if (r && !rc) rc = r; };
     A(dalloc(&d.V, 3 * (size_t)nv)); A(dalloc(&d.F, 3 * (size_t)nf)); A(dalloc(&d.mat, 7 * (size_t)nf));
@@ -442,7 +443,8 @@ int st_scene_create(const float* V, int32_t nv, const int32_t* F, int32_t nf, co
     A(dalloc(&d.tri, 3 * (size_t)nf));
     A(dalloc(&d.vf_off, (size_t)nv + 1));
     A(dalloc(&d.vf_idx, 3 * (size_t)nf));
-    A(dalloc(&d.facc, (size_t)FACC * nf));
+    A(dalloc(&d.facc, 9 * (size_t)nf));
+    A(dalloc(&d.macc, 7 * (size_t)nf));
     A(dalloc(&d.edges, edges.size()));
     A(dalloc(&d.edge_w, edges.size()));
     A(dalloc(&d.eguide, (size_t)1 << guide_log2((int)edges.size())));
@@ -505,6 +507,7 @@ int st_scene_create(const float* V, int32_t nv, const int32_t* F, int32_t nf, co
     h.eguide = d.eguide; h.mguide = d.mguide; h.cguide = d.cguide;
     h.eglog = guide_log2(d.ne); h.mglog = guide_log2(he); h.cglog = guide_log2(we);
     h.nv = nv; h.nf = nf; h.nl = nl; h.he = he; h.we = we; h.ne = d.ne; h.has_env = d.has_env ? 1 : 0;
+    h.tex_res = 0;
     h.scene_id = scene_id;
     HIPCHK2(hipMemcpyAsync(d.dscene, &h, sizeof(DevScene), hipMemcpyHostToDevice, s));
     HIPCHK2(hipStreamSynchronize(s));
@@ -517,9 +520,47 @@ int st_scene_update(st_scene* sc, const float* V, const float* mat, hipStream_t 
     int rc = check_scene(sc);
     if (rc) return rc;
     if (V) HIPCHK(hipMemcpyAsync(sc->d.V, V, sizeof(float) * 3 * sc->d.nv, hipMemcpyDeviceToDevice, s));
-    if (mat) HIPCHK(hipMemcpyAsync(sc->d.mat, mat, sizeof(float) * 7 * sc->d.nf, hipMemcpyDeviceToDevice, s));
+    if (mat) HIPCHK(hipMemcpyAsync(sc->d.mat, mat, sizeof(float) * 7 * (size_t)sc->d.ntex, hipMemcpyDeviceToDevice, s));
     if (V) launch_scene_geometry(sc->d, s);
     HIPCHK(hipGetLastError());
+    return ST_OK;
+}
+
+int st_scene_set_mesh_colors(st_scene* sc, int32_t r, const float* texels, hipStream_t s) {
+    int rc = check_scene(sc);
+    if (rc) return rc;
+    if (r < 0 || r > 64) return fail(ST_ERR_INVALID_ARG, "mesh-colour resolution must be in [0, 64]");
+    if (!texels) return fail(ST_ERR_INVALID_ARG, "texels is NULL");
+    SceneDev& d = sc->d;
+    const long long ntex = (long long)d.nf * ((r + 1) * (r + 2) / 2);
+    if (7 * ntex >= (1ll << 31)) return fail(ST_ERR_INVALID_ARG, "too many texels (7 nf (r+1)(r+2)/2 must be < 2^31)");
+    HIPCHK(hipStreamSynchronize(s));
+    float *mat = nullptr, *macc = nullptr;
+    if (dalloc(&mat, 7 * (size_t)ntex) || dalloc(&macc, 7 * (size_t)ntex)) {
+        if (mat) hipFree(mat);
+        if (macc) hipFree(macc);
+        return fail(ST_ERR_OOM, "texel arrays");
+    }
+    HIPCHK(hipMemcpyAsync(mat, texels, sizeof(float) * 7 * (size_t)ntex, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    hipFree(d.mat);
+    hipFree(d.macc);
+    d.mat = mat;
+    d.macc = macc;
+    d.tex_res = r;
+    d.ntex = (int)ntex;
+    d.hscene.mat = mat;
+    d.hscene.tex_res = r;
+    HIPCHK(hipMemcpyAsync(d.dscene, &d.hscene, sizeof(DevScene), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return ST_OK;
+}
+
+int st_scene_mesh_colors_info(const st_scene* sc, int32_t* r, int64_t* ntex) {
+    int rc = check_scene(sc);
+    if (rc) return rc;
+    if (r) *r = sc->d.tex_res;
+    if (ntex) *ntex = sc->d.ntex;
     return ST_OK;
 }
 
@@ -590,11 +631,13 @@ int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_
     p.pglog = pglog;
     p.pacc = c.take<double>(2 * (size_t)ncam * ne);
     p.facc = sc->d.facc;
+    p.macc = sc->d.macc;
+    p.ntex = sc->d.ntex;
     p.vf_off = sc->d.vf_off;
     p.vf_idx = sc->d.vf_idx;
     p.ne = ne;
     launch_fill_f32(out_dV, 3ll * sc->d.nv, 0.0f, s);
-    launch_fill_f32(out_dmat, 7ll * sc->d.nf, 0.0f, s);
+    launch_fill_f32(out_dmat, 7ll * sc->d.ntex, 0.0f, s);
     if (o.debug_decision_hash) launch_fill_u32(o.debug_decision_hash, cs.total_paths, 0u, s);
     if (o.debug_edge_hash) launch_fill_u32(o.debug_edge_hash, cs.total_edges, 0u, s);
     launch_backward(p, sc->d.nv, sc->d.nf, cs.total_paths, cs.total_edges, TRACE_GRID, s);
@@ -797,7 +840,7 @@ void st_scene_destroy(st_scene* sc) {
     void* ptrs[] = {d.V, d.F, d.mat, d.lights, d.env, d.fnorm, d.bmin, d.bmax, d.cen, d.bounds, d.mkeys[0], d.mkeys[1],
                     d.mvals[0], d.mvals[1], d.rs_hist, d.keys64, d.child, d.parent, d.aabb, d.refit_cnt, d.nodes4, d.flag4, d.id4,
                     d.tri, d.edges, d.edge_w, d.eguide, d.mguide, d.cguide, d.ecdf, d.etotal_d, d.etotal_f, d.row_dom, d.rowcos, d.cond, d.marg,
-                    d.env_rows, d.env_total, d.texpdf, d.err, d.work, d.dscene, d.vf_off, d.vf_idx, d.facc};
+                    d.env_rows, d.env_total, d.texpdf, d.err, d.work, d.dscene, d.vf_off, d.vf_idx, d.facc, d.macc};
     for (void* p : ptrs)
         if (p) hipFree(p);
     sc->Lbuf.release(); sc->qbuf.release(); sc->spillbuf.release(); sc->primbuf.release();

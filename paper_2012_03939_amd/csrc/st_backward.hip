@@ -78,42 +78,46 @@ constexpr uint32_t R_FLIP = 1u, R_ENV = 2u, R_CONT = 4u, R_ESC = 8u, R_SEC = 16u
 #endif
 constexpr bool FACE_REDUCE = ST_FACE_REDUCE != 0;   // wave-level reduction of the primary-vertex gradients
 
-// Adds vals to the accumulators of face f with one set of atomics per (face,
-// wave): lanes of the wave with the same face are summed first (peeling one
-// face per round; partner lanes add into the leader's LDS row).  Primary hits
-// of a wave are the 64 pixels of a tile, so few faces cover most lanes.
-// Lanes with !has contribute nothing.  red: this wave's FACC floats of LDS.
-__device__ __forceinline__ void face_reduce_add(bool has, int f, const float (&vals)[FACC], float* acc, int nf,
-                                                float* red) {
+// Adds vals to the accumulators of face f (slots 0..8: the three corners) and
+// of its texel tx (slots 9..15: the material) with one set of atomics per
+// (texel, wave): lanes of the wave with the same texel (hence the same face)
+// are summed first, peeling one texel per round; partner lanes add into the
+// leader's LDS row.  Primary hits of a wave are the 64 pixels of a tile, so few
+// texels cover most lanes.  Lanes with !has contribute nothing.
+// red: this wave's FACC floats of LDS.  Accumulators are slot-major.
+__device__ __forceinline__ void face_reduce_add(bool has, int f, int tx, const float (&vals)[FACC], float* facc,
+                                                int nf, float* macc, int ntex, float* red) {
     bool pending = has;
     for (;;) {
         const uint64_t m = __ballot(pending);
         if (!m) break;
         const int leader = __ffsll((long long)m) - 1;
+        const int lt = __builtin_amdgcn_readlane(tx, leader);
         const int lf = __builtin_amdgcn_readlane(f, leader);
-        const bool mine = pending && f == lf;
+        const bool mine = pending && tx == lt;
         const bool lead = (int)__lane_id() == leader;
         const uint64_t grp = __ballot(mine);
-        float* dst = acc + lf;
-        if (grp == (1ull << leader)) {
-            if (lead)
-#pragma unroll
-                for (int j = 0; j < FACC; ++j) atomicAdd(dst + (size_t)j * nf, vals[j]);
-        } else {
+        if (grp != (1ull << leader)) {
             if (lead)
 #pragma unroll
                 for (int j = 0; j < FACC; ++j) red[j] = vals[j];
             if (mine && !lead)
 #pragma unroll
                 for (int j = 0; j < FACC; ++j) atomicAdd(red + j, vals[j]);
-            if (lead)
+        }
+        if (lead) {
+            const bool single = grp == (1ull << leader);
 #pragma unroll
-                for (int j = 0; j < FACC; ++j) atomicAdd(dst + (size_t)j * nf, red[j]);
+            for (int j = 0; j < 9; ++j) atomicAdd(facc + (size_t)j * nf + lf, single ? vals[j] : red[j]);
+#pragma unroll
+            for (int j = 0; j < 7; ++j) atomicAdd(macc + (size_t)j * ntex + lt, single ? vals[9 + j] : red[9 + j]);
         }
         pending = pending && !mine;
     }
 }
 
+// occupancy target of the adjoint (waves per SIMD): the register budget the
+// compiler fits it to (4: measured fastest among 3 to 8)
 #ifndef ST_ADJ_WAVES
 #define ST_ADJ_WAVES 4
 #endif
@@ -179,7 +183,9 @@ k_adjoint(BwdParams p, long long total) {
                 const V3 wo = -d;
                 uint32_t fl = 0;
                 if (dot(n, wo) < 0.0f) { n = -n; fl |= R_FLIP; }
-                const Mat m = load_mat(S.mat + 7 * (size_t)f);
+                const int tx = texel_of(S, f, xh);
+                if (S.tex_res) h.push((uint32_t)tx);
+                const Mat m = load_mat(S.mat + 7 * (size_t)tx);
                 for (int l = 0; l < S.nl; ++l) {
                     const float* lt = S.lights + 6 * l;
                     const V3 dl = ld3(lt) - xh;
@@ -281,7 +287,7 @@ k_adjoint(BwdParams p, long long total) {
                     Ls[side] = trace_estimator(S, xh, dir, f, p.B - (k + 1), true, sc, key, h, st);
                 }
                 const V3 dirk = k == 0 ? d0 : sel(rwi, k - 1);
-                const Mat m = load_mat(S.mat + 7 * (size_t)f);
+                const Mat m = load_mat(S.mat + 7 * (size_t)texel_of(S, f, xh));
                 const V3 fv = brdf_eval(ud, -dirk, n, m);
                 const float cc = dot(mul(w, mul(sel(rbeta, k), fv)), Ls[0] - Ls[1]) * cv * (*S.etotal / r2);
                 put(rsecc, k, cc);
@@ -301,6 +307,7 @@ k_adjoint(BwdParams p, long long total) {
                 float vals[FACC];
                 const bool has = k < nvtx;
                 const int f = has ? sel(rf, k) : -1;
+                const int tx = has ? texel_of(S, f, sel(rx, k)) : -1;
                 if (has) {
                     const uint32_t fl = sel(rfl, k);
                     const V3 xh = sel(rx, k);
@@ -314,7 +321,7 @@ k_adjoint(BwdParams p, long long total) {
                     const V3 nu = N * (1.0f / Nl);
                     const float sg = (fl & R_FLIP) ? -1.0f : 1.0f;
                     const V3 n = nu * sg;
-                    const Mat m = load_mat(S.mat + 7 * (size_t)f);
+                    const Mat m = load_mat(S.mat + 7 * (size_t)tx);
                     const V3 a = want_interior ? mul(w, sel(rbeta, k)) : V3{0.f, 0.f, 0.f};
                     V3 C{0.f, 0.f, 0.f}, gn{0.f, 0.f, 0.f}, gx = gxnext, gdummy{0.f, 0.f, 0.f};
                     float gm[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -384,11 +391,12 @@ k_adjoint(BwdParams p, long long total) {
                     gxnext = go;
                 }
                 if (k == 0 && FACE_REDUCE) {
-                    face_reduce_add(has, f, vals, p.facc, S.nf, red);
+                    face_reduce_add(has, f, tx, vals, p.facc, S.nf, p.macc, p.ntex, red);
                 } else if (has) {
-                    float* dst = p.facc + f;
 #pragma unroll
-                    for (int j = 0; j < FACC; ++j) atomicAdd(dst + (size_t)j * S.nf, vals[j]);
+                    for (int j = 0; j < 9; ++j) atomicAdd(p.facc + (size_t)j * S.nf + f, vals[j]);
+#pragma unroll
+                    for (int j = 0; j < 7; ++j) atomicAdd(p.macc + (size_t)j * p.ntex + tx, vals[9 + j]);
                 }
             }
         }
@@ -611,8 +619,9 @@ __global__ void k_edge_finish(BwdParams p) {
     }
 }
 
-// per-face accumulators (slot-major: slot j of face f at j nf + f) to dV
-// (vertex gather over the incidence CSR, fixed order) and dmat
+// per-face corner accumulators (slot-major: slot j of face f at j nf + f) to
+// dV (vertex gather over the incidence CSR, fixed order); per-texel material
+// accumulators (slot j of texel t at j ntex + t) to dmat [ntex, 7]
 __global__ void k_face_gather(BwdParams p) {
     const DevScene& S = p.scenes[0];
     const int stride = gridDim.x * blockDim.x;
@@ -627,9 +636,9 @@ __global__ void k_face_gather(BwdParams p) {
         p.dV[3 * (size_t)v + 1] += sy;
         p.dV[3 * (size_t)v + 2] += sz;
     }
-    for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < S.nf; f += stride)
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < p.ntex; t += stride)
 #pragma unroll
-        for (int i = 0; i < 7; ++i) p.dmat[7 * (size_t)f + i] = p.facc[(size_t)(9 + i) * S.nf + f];
+        for (int i = 0; i < 7; ++i) p.dmat[7 * (size_t)t + i] = p.macc[(size_t)i * p.ntex + t];
 }
 
 // ---------------------------------------------------------------------------
@@ -663,13 +672,15 @@ void launch_primary_edges(const BwdParams& p, const FwdParams& fp, Queues& q, fl
 void launch_backward(const BwdParams& p, int nv, int nf, long long total_paths, long long total_edges, int grid,
                      hipStream_t st) {
     if ((p.flags & 5u) && total_paths > 0) {
-        launch_fill_u32((uint32_t*)p.facc, (long long)FACC * nf, 0u, st);
+        launch_fill_u32((uint32_t*)p.facc, 9ll * nf, 0u, st);
+        launch_fill_u32((uint32_t*)p.macc, 7ll * p.ntex, 0u, st);
         const dim3 gd(gridb(total_paths, TRACE_BLOCK, grid)), bd(TRACE_BLOCK);
         if (p.B <= 1) ST_LAUNCH("k_adjoint<1>", k_adjoint<1>, gd, bd, 0, st, p, total_paths);
         else if (p.B <= 2) ST_LAUNCH("k_adjoint<2>", k_adjoint<2>, gd, bd, 0, st, p, total_paths);
         else if (p.B <= 3) ST_LAUNCH("k_adjoint<3>", k_adjoint<3>, gd, bd, 0, st, p, total_paths);
         else ST_LAUNCH("k_adjoint<8>", k_adjoint<8>, gd, bd, 0, st, p, total_paths);
-        ST_LAUNCH("k_face_gather", k_face_gather, dim3(gridb(std::max(nv, nf), 256, 4096)), dim3(256), 0, st, p);
+        ST_LAUNCH("k_face_gather", k_face_gather, dim3(gridb(std::max<long long>(nv, p.ntex), 256, 4096)), dim3(256), 0,
+                  st, p);
     }
 
 }

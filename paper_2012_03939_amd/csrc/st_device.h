@@ -126,6 +126,7 @@ struct DevScene {
     const int* cguide;    // guide tables of the env conditional CDFs, 2^cglog entries per row
     int eglog, mglog, cglog;
     int nv, nf, nl, he, we, ne, has_env;
+    int tex_res;          // mesh-colours resolution r: mat has nf (r+1)(r+2)/2 rows
     uint32_t scene_id;
 };
 
@@ -395,6 +396,27 @@ __device__ __forceinline__ Mat load_mat(const float* m) {
 }
 __device__ __forceinline__ float alpha_eff(float a) { return a > ALPHA_MIN ? a : ALPHA_MIN; }
 
+// Material row of the point x on face f.  Mesh colours (Sec. 3.3
+// "Representation"): at resolution r the point with barycentric coordinates
+// (alpha of the second vertex, beta of the third) uses texel
+// f (r+1)(r+2)/2 + i (2r - i + 3)/2 + j, (i, j) = floor(r (alpha, beta)),
+// clamped to 0 <= i <= r, 0 <= j <= r - i; r = 0 is one row per face.
+__device__ __forceinline__ int texel_of(const DevScene& S, int f, V3 x) {
+    const int r = S.tex_res;
+    if (r == 0) return f;
+    const V3 v0 = ld3(S.V + 3 * S.F[3 * f]), v1 = ld3(S.V + 3 * S.F[3 * f + 1]), v2 = ld3(S.V + 3 * S.F[3 * f + 2]);
+    const V3 e1 = v1 - v0, e2 = v2 - v0, q = x - v0;
+    const V3 N = cross(e1, e2);
+    const float nn = dot(N, N);
+    float a = dot(cross(q, e2), N) / nn, b = dot(cross(e1, q), N) / nn;
+    a = fminf(fmaxf(a, -1.0f), 2.0f);   // also maps NaN to -1
+    b = fminf(fmaxf(b, -1.0f), 2.0f);
+    int i = (int)floorf((float)r * a), j = (int)floorf((float)r * b);
+    i = min(max(i, 0), r);
+    j = min(max(j, 0), r - i);
+    return (f * (r + 1) * (r + 2) + i * (2 * r - i + 3)) / 2 + j;
+}
+
 // Beckmann D with tan^2 taken from |n x h|^2 / (n.h)^2: 1 - (n.h)^2 cancels in
 // float32 near the highlight, the cross product does not
 __device__ __forceinline__ float beckmann_D(V3 n, V3 h, float ch, float a) {
@@ -641,7 +663,9 @@ __device__ V3 trace_estimator(const DevScene& S, V3 o, V3 d, int exclude, int nv
         V3 n = xyz(S.fnorm[f]);
         const V3 wo = -d;
         if (dot(n, wo) < 0.0f) n = -n;
-        const Mat m = load_mat(S.mat + 7 * (size_t)f);
+        const int tx = texel_of(S, f, x);
+        if (S.tex_res) hash.push((uint32_t)tx);
+        const Mat m = load_mat(S.mat + 7 * (size_t)tx);
         for (int l = 0; l < S.nl; ++l) {
             const float* lt = S.lights + 6 * l;
             const V3 dl = ld3(lt) - x;

@@ -18,7 +18,7 @@ extern bool g_prof_on;
     } while (0)
 
 // every device allocation of one scene (library-owned)
-constexpr int FACC = 16;   // per-face gradient slots: 3 corners x xyz, then the 7 material parameters
+constexpr int FACC = 16;   // gradient slots of one vertex: 3 corners x xyz, then the 7 material parameters
 
 struct SceneDev {
     int nv = 0, nf = 0, nl = 0, he = 0, we = 0, ne = 0;
@@ -28,7 +28,10 @@ struct SceneDev {
     int* F = nullptr;
     int* vf_off = nullptr;                   // vertex -> (face, corner) CSR offsets [nv+1]
     int* vf_idx = nullptr;                   // entries 3 f + corner [3 nf]
-    float* facc = nullptr;                   // per-face gradient accumulators [FACC, nf]
+    float* facc = nullptr;                   // per-face corner gradient accumulators [9, nf]
+    float* macc = nullptr;                   // per-texel material gradient accumulators [7, ntex]
+    int tex_res = 0;                         // mesh-colours resolution r
+    int ntex = 0;                            // material rows: nf (r+1)(r+2)/2
     float* mat = nullptr;
     float* lights = nullptr;
     float* env = nullptr;
@@ -166,7 +169,9 @@ struct BwdParams {
     int pglog;
     double* pacc;            // per (view, edge): sums of c (1-t) and c t over its primary edge samples [ncam, ne, 2]
     int ne;
-    float* facc;             // per-face accumulators [FACC, nf]: d/d(v0, v1, v2) then d/d(material)
+    float* facc;             // per-face corner accumulators [9, nf]: d/d(v0, v1, v2)
+    float* macc;             // per-texel material accumulators [7, ntex]
+    int ntex;
     const int* vf_off;       // vertex -> (face, corner) CSR of the scene
     const int* vf_idx;
 };

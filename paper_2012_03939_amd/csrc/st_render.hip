@@ -158,7 +158,9 @@ __global__ void __launch_bounds__(SHADE_BLOCK) SHADE_OCC k_shade(FwdParams p, Qu
                 V3 n = xyz(S.fnorm[f]);
                 const V3 wo = -d;
                 if (dot(n, wo) < 0.0f) n = -n;
-                const Mat m = load_mat(S.mat + 7 * (size_t)f);
+                const int tx = texel_of(S, f, x);
+                if (S.tex_res) h.push((uint32_t)tx);
+                const Mat m = load_mat(S.mat + 7 * (size_t)tx);
                 for (int l = 0; l < S.nl; ++l) {
                     const float* lt = S.lights + 6 * l;
                     const V3 dl = ld3(lt) - x;

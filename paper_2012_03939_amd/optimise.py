@@ -8,6 +8,12 @@ sphere with random per-face materials under an HDR environment map; the start is
 a 5,120-face sphere with a uniform grey material.  Adam (lr 1e-3 vertices, 1e-2
 materials), uniform-Laplacian smoothness weighted 0.1, 8 spp, 2 bounces.
 
+With tex_res = r > 0 the materials are mesh colours of resolution r (Sec. 3.3
+"Representation"), started from the grey material in every texel, and
+spec_var_w > 0 adds the Sec. 3.3 specular variance penalty
+spec_var_w * Var(m_s): the variance over texels of each specular channel,
+summed over the three channels.
+
     python -m paper_2012_03939_amd.optimise --steps 200
 """
 from __future__ import annotations
@@ -25,7 +31,8 @@ from .autograd import render, uniform_laplacian, vertex_neighbours
 
 
 def run(steps: int = 200, nviews: int = 32, res: int = 256, spp: int = 8, bounces: int = 2, target_spp: int = 64,
-        lr_v: float = 1e-3, lr_m: float = 1e-2, lap_w: float = 0.1, log_every: int = 0) -> dict:
+        lr_v: float = 1e-3, lr_m: float = 1e-2, lap_w: float = 0.1, log_every: int = 0, tex_res: int = 0,
+        spec_var_w: float = 0.0) -> dict:
     dev = torch.device("cuda")
     target_sc, start_sc, cams = S.optimisation_problem(nviews, res)
     gt = B.GPUScene.from_scene(target_sc)
@@ -33,7 +40,11 @@ def run(steps: int = 200, nviews: int = 32, res: int = 256, spp: int = 8, bounce
     gt.close()
     g = B.GPUScene.from_scene(start_sc)
     V = torch.tensor(start_sc.V, device=dev, requires_grad=True)
-    M = torch.tensor(start_sc.mat, device=dev, requires_grad=True)
+    mat0 = start_sc.mat
+    if tex_res > 0:
+        mat0 = np.repeat(start_sc.mat, (tex_res + 1) * (tex_res + 2) // 2, axis=0)
+        g.set_mesh_colors(tex_res, torch.from_numpy(mat0).to(dev))
+    M = torch.tensor(mat0, device=dev, requires_grad=True)
     F = torch.from_numpy(start_sc.F).to(dev)
     src, dst = vertex_neighbours(F, V.shape[0])
     opt = torch.optim.Adam([{"params": [V], "lr": lr_v}, {"params": [M], "lr": lr_m}])
@@ -45,6 +56,8 @@ def run(steps: int = 200, nviews: int = 32, res: int = 256, spp: int = 8, bounce
         img = render(V, M, g, cams, spp, bounces, seed=it)
         img_l2 = ((img - T) ** 2).mean()
         loss = img_l2 + lap_w * uniform_laplacian(V, src, dst)
+        if spec_var_w > 0.0:
+            loss = loss + spec_var_w * M[:, 3:6].var(dim=0, unbiased=False).sum()
         loss.backward()
         opt.step()
         with torch.no_grad():
@@ -59,12 +72,15 @@ def run(steps: int = 200, nviews: int = 32, res: int = 256, spp: int = 8, bounce
     warm = times[2:] if len(times) > 4 else times
     return {"steps": steps, "s_per_step": float(np.median(warm)), "image_l2_first": l2[0], "image_l2_last": l2[-1],
             "path_samples_per_step": B.num_pixels(cams) * spp, "views": nviews, "res": res, "spp": spp,
-            "bounces": bounces, "faces": int(start_sc.F.shape[0]), "target_faces": int(target_sc.F.shape[0])}
+            "bounces": bounces, "faces": int(start_sc.F.shape[0]), "target_faces": int(target_sc.F.shape[0]),
+            "tex_res": tex_res, "material_rows": int(M.shape[0])}
 
 
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--log-every", type=int, default=20)
+    ap.add_argument("--tex-res", type=int, default=0)
+    ap.add_argument("--spec-var", type=float, default=0.0)
     a = ap.parse_args()
-    print(json.dumps(run(a.steps, log_every=a.log_every)))
+    print(json.dumps(run(a.steps, log_every=a.log_every, tex_res=a.tex_res, spec_var_w=a.spec_var)))

@@ -202,6 +202,17 @@ def random_materials(nf: int, rng: np.random.Generator) -> np.ndarray:
     return np.concatenate([kd, ks, al], axis=1).astype(np.float32)
 
 
+def mesh_color_texels(face_mat: np.ndarray, r: int, rng: np.random.Generator) -> np.ndarray:
+    """Mesh-colour texels at resolution r ([nf (r+1)(r+2)/2, 7], triangle blocks in
+    face order): each texel is its face's material with kd and ks scaled by
+    U[0.6, 1.4] per channel (clipped to [0, 1]) and roughness by U[0.7, 1.3]."""
+    T = (r + 1) * (r + 2) // 2
+    tex = np.repeat(np.asarray(face_mat, np.float64), T, axis=0)
+    tex[:, :6] = np.clip(tex[:, :6] * rng.uniform(0.6, 1.4, (tex.shape[0], 6)), 0.0, 1.0)
+    tex[:, 6] = tex[:, 6] * rng.uniform(0.7, 1.3, tex.shape[0])
+    return tex.astype(np.float32)
+
+
 def uniform_materials(nf: int, kd=0.5, ks=0.04, rough=0.3) -> np.ndarray:
     m = np.empty((nf, 7), np.float32)
     m[:, 0:3] = kd
