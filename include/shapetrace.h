@@ -113,6 +113,16 @@ int st_scene_update(st_scene* scene, const float* V, const float* face_materials
  * Allocates (not capturable) and synchronises s; ST_ERR_INVALID_ARG when
  * 7 ntex >= 2^31. */
 int st_scene_set_mesh_colors(st_scene* scene, int32_t r, const float* texels, hipStream_t s);
+/* 1 -> 4 subdivision of the scene's current mesh (Sec. 3.2 "Subdivision": every
+ * edge split at its midpoint), for a coarse-to-fine schedule; the caller creates
+ * a new scene from the result (topology changes need st_scene_create).
+ *   out_V: device float [nv + ne, 3] = the vertices, then the midpoint
+ *   (va + vb) / 2 of every edge in st_scene_edges order;
+ *   out_F: device int32 [4 nf, 3]: face f becomes (v0, m01, m20), (v1, m12, m01),
+ *   (v2, m20, m12), (m01, m12, m20) at rows 4f .. 4f+3, with mij the midpoint of
+ *   edge (vi, vj) (orientation kept; a degenerate edge's midpoint is its vertex).
+ * ne is entry 2 of st_scene_info (nv, nf, ne, nl, he, we).  Allocates nothing. */
+int st_scene_subdivide(const st_scene* scene, float* out_V, int32_t* out_F, hipStream_t s);
 /* Current mesh-colour resolution and number of material rows (either may be NULL). */
 int st_scene_mesh_colors_info(const st_scene* scene, int32_t* r, int64_t* ntex);
 

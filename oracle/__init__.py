@@ -255,6 +255,28 @@ class OracleScene:
 
 # ---- stateless pieces ----------------------------------------------------
 
+def subdivide(V, F):
+    """1 -> 4 subdivision by edge midpoints (Sec. 3.2 "Subdivision"), straight from
+    the definition: new vertex (va + vb) / 2 per undirected edge, numbered after
+    the old vertices in ascending (min, max) vertex order; face (v0, v1, v2) ->
+    (v0, m01, m20), (v1, m12, m01), (v2, m20, m12), (m01, m12, m20)."""
+    V = np.asarray(V, np.float32)
+    F = np.asarray(F, np.int64)
+    nv = V.shape[0]
+    keys = sorted({(min(a, b), max(a, b)) for f in F for a, b in ((f[0], f[1]), (f[1], f[2]), (f[2], f[0])) if a != b})
+    mid = {k: nv + i for i, k in enumerate(keys)}
+    newV = [V] + [((V[a] + V[b]) * np.float32(0.5))[None, :] for a, b in keys]
+
+    def m(a, b):
+        return a if a == b else mid[(min(a, b), max(a, b))]
+
+    out = []
+    for v0, v1, v2 in F:
+        m01, m12, m20 = m(v0, v1), m(v1, v2), m(v2, v0)
+        out += [(v0, m01, m20), (v1, m12, m01), (v2, m20, m12), (m01, m12, m20)]
+    return np.concatenate(newV).astype(np.float32), np.asarray(out, np.int32)
+
+
 def texel_index(r, t, alpha, beta):
     """Mesh-colour texel of barycentric (alpha, beta) in triangle t at resolution r (Sec. 3.3)."""
     return int(lib().or_texel_index(int(r), int(t), float(alpha), float(beta)))

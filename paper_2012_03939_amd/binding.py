@@ -25,7 +25,7 @@ ST_COUNT_WORK = 32
 ST_ALL_GRADS = 7
 
 EXPORTED = ["st_render_opts_default", "st_scene_create", "st_scene_update", "st_scene_set_mesh_colors",
-            "st_scene_mesh_colors_info", "st_render", "st_render_backward",
+            "st_scene_mesh_colors_info", "st_scene_subdivide", "st_render", "st_render_backward",
             "st_render_batch", "st_autotune", "st_check_errors", "st_read_work", "st_scene_info", "st_scene_edges", "st_scene_lbvh",
             "st_trace_rays", "st_profile_enable", "st_profile_read", "st_scene_destroy", "st_last_error",
             "st_version"]
@@ -64,6 +64,7 @@ def load(path: str = LIB_PATH):
     L.st_scene_update.argtypes = [P, P, P, P]
     L.st_scene_set_mesh_colors.argtypes = [P, I32, P, P]
     L.st_scene_mesh_colors_info.argtypes = [P, P, P]
+    L.st_scene_subdivide.argtypes = [P, P, P, P]
     L.st_render.argtypes = [P, P, I32, I32, I32, U32, ctypes.POINTER(StOpts), P, P]
     L.st_render_backward.argtypes = [P, P, I32, I32, I32, U32, ctypes.POINTER(StOpts), P, P, P, P]
     L.st_render_batch.argtypes = [P, I32, P, P, I32, I32, I32, U32, ctypes.POINTER(StOpts), P, P]
@@ -162,6 +163,14 @@ class GPUScene:
         _check(L.st_scene_info(self.h, info))
         self.ne = int(info[2])
         self.tex_res, self.ntex = 0, self.nf
+
+    def subdivide(self):
+        """1 -> 4 midpoint subdivision of the current mesh: (V [nv+ne,3], F [4nf,3]) device tensors."""
+        import torch
+        V = torch.empty((self.nv + self.ne, 3), dtype=torch.float32, device="cuda")
+        F = torch.empty((4 * self.nf, 3), dtype=torch.int32, device="cuda")
+        _check(load().st_scene_subdivide(self.h, _ptr(V), _ptr(F), _stream()))
+        return V, F
 
     def set_mesh_colors(self, r: int, texels):
         """Materials as mesh colours of resolution r: texels [nf (r+1)(r+2)/2, 7] (Sec. 3.3)."""

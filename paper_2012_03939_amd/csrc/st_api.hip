@@ -404,19 +404,25 @@ int st_scene_create(const float* V, int32_t nv, const int32_t* F, int32_t nf, co
         for (int f = 0; f < nf; ++f)
             for (int k = 0; k < 3; ++k) vf_idx[fill[Fh[3 * f + k]]++] = 3 * f + k;
     }
-    std::vector<std::array<int, 3>> hes;
+    // half-edges (min vertex, max vertex, face, corner) sorted: equal edges are
+    // adjacent; fe[3 f + k] = edge of face f from corner k to corner k+1
+    std::vector<std::array<int, 4>> hes;
     hes.reserve(3 * (size_t)nf);
     for (int f = 0; f < nf; ++f)
         for (int k = 0; k < 3; ++k) {
             const int a = Fh[3 * f + k], b = Fh[3 * f + (k + 1) % 3];
-            hes.push_back({std::min(a, b), std::max(a, b), f});
+            hes.push_back({std::min(a, b), std::max(a, b), f, k});
         }
     std::sort(hes.begin(), hes.end());
     std::vector<int4> edges;
+    std::vector<int32_t> fe(3 * (size_t)nf, -1);
     for (size_t i = 0; i < hes.size();) {
         size_t j = i;
         while (j < hes.size() && hes[j][0] == hes[i][0] && hes[j][1] == hes[i][1]) ++j;
-        if (hes[i][0] != hes[i][1]) edges.push_back(make_int4(hes[i][0], hes[i][1], hes[i][2], j - i >= 2 ? hes[i + 1][2] : -1));
+        if (hes[i][0] != hes[i][1]) {
+            for (size_t m = i; m < j; ++m) fe[3 * (size_t)hes[m][2] + hes[m][3]] = (int32_t)edges.size();
+            edges.push_back(make_int4(hes[i][0], hes[i][1], hes[i][2], j - i >= 2 ? hes[i + 1][2] : -1));
+        }
         i = j;
     }
 
@@ -442,6 +448,7 @@ int st_scene_create(const float* V, int32_t nv, const int32_t* F, int32_t nf, co
     A(dalloc(&d.id4, (size_t)std::max(nf - 1, 1)));
     A(dalloc(&d.tri, 3 * (size_t)nf));
     A(dalloc(&d.vf_off, (size_t)nv + 1));
+    A(dalloc(&d.fe, 3 * (size_t)nf));
     A(dalloc(&d.vf_idx, 3 * (size_t)nf));
     A(dalloc(&d.facc, 9 * (size_t)nf));
     A(dalloc(&d.macc, 7 * (size_t)nf));
@@ -476,6 +483,7 @@ int st_scene_create(const float* V, int32_t nv, const int32_t* F, int32_t nf, co
     if (!edges.empty())
         HIPCHK2(hipMemcpyAsync(d.edges, edges.data(), sizeof(int4) * edges.size(), hipMemcpyHostToDevice, s));
     HIPCHK2(hipMemcpyAsync(d.vf_off, vf_off.data(), sizeof(int32_t) * vf_off.size(), hipMemcpyHostToDevice, s));
+    HIPCHK2(hipMemcpyAsync(d.fe, fe.data(), sizeof(int32_t) * fe.size(), hipMemcpyHostToDevice, s));
     HIPCHK2(hipMemcpyAsync(d.vf_idx, vf_idx.data(), sizeof(int32_t) * vf_idx.size(), hipMemcpyHostToDevice, s));
     launch_fill_u32(d.err, 1, 0u, s);
     launch_fill_u32((uint32_t*)d.work, 6 * WORK_SLOTS, 0u, s);
@@ -522,6 +530,15 @@ int st_scene_update(st_scene* sc, const float* V, const float* mat, hipStream_t 
     if (V) HIPCHK(hipMemcpyAsync(sc->d.V, V, sizeof(float) * 3 * sc->d.nv, hipMemcpyDeviceToDevice, s));
     if (mat) HIPCHK(hipMemcpyAsync(sc->d.mat, mat, sizeof(float) * 7 * (size_t)sc->d.ntex, hipMemcpyDeviceToDevice, s));
     if (V) launch_scene_geometry(sc->d, s);
+    HIPCHK(hipGetLastError());
+    return ST_OK;
+}
+
+int st_scene_subdivide(const st_scene* sc, float* out_V, int32_t* out_F, hipStream_t s) {
+    int rc = check_scene(sc);
+    if (rc) return rc;
+    if (!out_V || !out_F) return fail(ST_ERR_INVALID_ARG, "out_V and out_F must be non-NULL");
+    launch_subdivide(sc->d, out_V, out_F, s);
     HIPCHK(hipGetLastError());
     return ST_OK;
 }
@@ -840,7 +857,7 @@ void st_scene_destroy(st_scene* sc) {
     void* ptrs[] = {d.V, d.F, d.mat, d.lights, d.env, d.fnorm, d.bmin, d.bmax, d.cen, d.bounds, d.mkeys[0], d.mkeys[1],
                     d.mvals[0], d.mvals[1], d.rs_hist, d.keys64, d.child, d.parent, d.aabb, d.refit_cnt, d.nodes4, d.flag4, d.id4,
                     d.tri, d.edges, d.edge_w, d.eguide, d.mguide, d.cguide, d.ecdf, d.etotal_d, d.etotal_f, d.row_dom, d.rowcos, d.cond, d.marg,
-                    d.env_rows, d.env_total, d.texpdf, d.err, d.work, d.dscene, d.vf_off, d.vf_idx, d.facc, d.macc};
+                    d.env_rows, d.env_total, d.texpdf, d.err, d.work, d.dscene, d.vf_off, d.vf_idx, d.facc, d.macc, d.fe};
     for (void* p : ptrs)
         if (p) hipFree(p);
     sc->Lbuf.release(); sc->qbuf.release(); sc->spillbuf.release(); sc->primbuf.release();

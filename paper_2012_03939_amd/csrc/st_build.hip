@@ -392,10 +392,44 @@ int guide_log2(int n) {
     return l;
 }
 
+// 1 -> 4 subdivision (Sec. 3.2 "Subdivision": every edge split at its
+// midpoint): vertices [V; midpoint of edge e at nv + e], face f ->
+// (v0, m01, m20), (v1, m12, m01), (v2, m20, m12), (m01, m12, m20) at 4f.. 4f+3,
+// which keeps every face's orientation
+__global__ void k_subdivide(const float* __restrict__ V, const int* __restrict__ F, const int* __restrict__ fe,
+                            const int4* __restrict__ edges, int nv, int nf, int ne, float* outV, int* outF) {
+    const int stride = gridDim.x * blockDim.x;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 3 * nv; i += stride) outV[i] = V[i];
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += stride) {
+        const int4 E = edges[e];
+        for (int c = 0; c < 3; ++c) outV[3 * (size_t)(nv + e) + c] = (V[3 * E.x + c] + V[3 * E.y + c]) * 0.5f;
+    }
+    for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < nf; f += stride) {
+        const int v0 = F[3 * f], v1 = F[3 * f + 1], v2 = F[3 * f + 2];
+        // a degenerate edge (both ends one vertex) has that vertex as its midpoint
+        const int m01 = fe[3 * f] >= 0 ? nv + fe[3 * f] : v0;
+        const int m12 = fe[3 * f + 1] >= 0 ? nv + fe[3 * f + 1] : v1;
+        const int m20 = fe[3 * f + 2] >= 0 ? nv + fe[3 * f + 2] : v2;
+        int* o = outF + 12 * (size_t)f;
+        o[0] = v0;  o[1] = m01; o[2] = m20;
+        o[3] = v1;  o[4] = m12; o[5] = m01;
+        o[6] = v2;  o[7] = m20; o[8] = m12;
+        o[9] = m01; o[10] = m12; o[11] = m20;
+    }
+}
+
+
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
 static inline unsigned nb(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+void launch_subdivide(const SceneDev& s, float* out_V, int32_t* out_F, hipStream_t st) {
+    const long long n = std::max<long long>(std::max<long long>(3ll * s.nv, s.ne), s.nf);
+    ST_LAUNCH("k_subdivide", k_subdivide, dim3(nb(n, 256) < 4096 ? nb(n, 256) : 4096), dim3(256), 0, st, s.V, s.F,
+              s.fe, s.edges, s.nv, s.nf, s.ne, out_V, out_F);
+}
+
 
 void launch_scene_geometry(SceneDev& s, hipStream_t st) {
     const int nf = s.nf;

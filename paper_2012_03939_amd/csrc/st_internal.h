@@ -27,6 +27,7 @@ struct SceneDev {
     float* V = nullptr;
     int* F = nullptr;
     int* vf_off = nullptr;                   // vertex -> (face, corner) CSR offsets [nv+1]
+    int* fe = nullptr;                       // edge of face f from corner k to k+1 [3 nf] (-1: degenerate)
     int* vf_idx = nullptr;                   // entries 3 f + corner [3 nf]
     float* facc = nullptr;                   // per-face corner gradient accumulators [9, nf]
     float* macc = nullptr;                   // per-texel material gradient accumulators [7, ntex]
@@ -132,6 +133,7 @@ struct FwdParams {
 };
 
 void launch_scene_geometry(SceneDev& s, hipStream_t st);
+void launch_subdivide(const SceneDev& s, float* out_V, int32_t* out_F, hipStream_t st);
 void launch_guide(const double* C, int n, size_t cstride, int rows, int* guide, int glog, hipStream_t st);
 int guide_log2(int n);
 void launch_env_build(SceneDev& s, hipStream_t st);

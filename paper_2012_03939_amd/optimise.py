@@ -12,7 +12,11 @@ With tex_res = r > 0 the materials are mesh colours of resolution r (Sec. 3.3
 "Representation"), started from the grey material in every texel, and
 spec_var_w > 0 adds the Sec. 3.3 specular variance penalty
 spec_var_w * Var(m_s): the variance over texels of each specular channel,
-summed over the three channels.
+summed over the three channels.  With subdivisions = s > 0 the schedule is
+coarse to fine (Sec. 3.2 "Subdivision"): the start mesh is the k = 4 sphere
+(320 faces), every `steps` iterations the current mesh is subdivided 1 -> 4 on
+the GPU (st_scene_subdivide) into a new scene, and the materials restart from
+the neutral grey (Sec. 3.3: re-optimised after every topology change), s times.
 
     python -m paper_2012_03939_amd.optimise --steps 200
 """
@@ -32,48 +36,63 @@ from .autograd import render, uniform_laplacian, vertex_neighbours
 
 def run(steps: int = 200, nviews: int = 32, res: int = 256, spp: int = 8, bounces: int = 2, target_spp: int = 64,
         lr_v: float = 1e-3, lr_m: float = 1e-2, lap_w: float = 0.1, log_every: int = 0, tex_res: int = 0,
-        spec_var_w: float = 0.0) -> dict:
+        spec_var_w: float = 0.0, subdivisions: int = 0) -> dict:
     dev = torch.device("cuda")
     target_sc, start_sc, cams = S.optimisation_problem(nviews, res)
     gt = B.GPUScene.from_scene(target_sc)
     T = gt.render(cams, target_spp, bounces, seed=12345).clone()
     gt.close()
-    g = B.GPUScene.from_scene(start_sc)
-    V = torch.tensor(start_sc.V, device=dev, requires_grad=True)
-    mat0 = start_sc.mat
-    if tex_res > 0:
-        mat0 = np.repeat(start_sc.mat, (tex_res + 1) * (tex_res + 2) // 2, axis=0)
-        g.set_mesh_colors(tex_res, torch.from_numpy(mat0).to(dev))
-    M = torch.tensor(mat0, device=dev, requires_grad=True)
-    F = torch.from_numpy(start_sc.F).to(dev)
-    src, dst = vertex_neighbours(F, V.shape[0])
-    opt = torch.optim.Adam([{"params": [V], "lr": lr_v}, {"params": [M], "lr": lr_m}])
-    times, l2 = [], []
-    for it in range(steps):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        opt.zero_grad(set_to_none=True)
-        img = render(V, M, g, cams, spp, bounces, seed=it)
-        img_l2 = ((img - T) ** 2).mean()
-        loss = img_l2 + lap_w * uniform_laplacian(V, src, dst)
-        if spec_var_w > 0.0:
-            loss = loss + spec_var_w * M[:, 3:6].var(dim=0, unbiased=False).sum()
-        loss.backward()
-        opt.step()
-        with torch.no_grad():
-            M[:, :6].clamp_(0.0, 1.0)
-            M[:, 6].clamp_(0.01, 1.0)
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
-        l2.append(float(img_l2.detach()))
-        if log_every and it % log_every == 0:
-            print(json.dumps({"step": it, "image_l2": l2[-1], "s": times[-1]}), flush=True)
+    if subdivisions > 0:
+        Vs, Fs = S.geodesic_sphere(4)
+        start_sc = S.Scene(Vs.astype(np.float32), Fs, S.uniform_materials(Fs.shape[0]), start_sc.lights, start_sc.env,
+                           start_sc.scene_id)
+    times, l2, faces = [], [], []
+    for level in range(subdivisions + 1):
+        if level > 0:
+            with torch.no_grad():
+                g.update(V=V.detach().contiguous())
+                Vn, Fn = g.subdivide()
+            grey = S.uniform_materials(int(Fn.shape[0]))
+            start_sc = S.Scene(Vn.cpu().numpy(), Fn.cpu().numpy(), grey, start_sc.lights, start_sc.env,
+                               start_sc.scene_id)
+            g.close()
+        g = B.GPUScene.from_scene(start_sc)
+        V = torch.tensor(start_sc.V, device=dev, requires_grad=True)
+        mat0 = start_sc.mat
+        if tex_res > 0:
+            mat0 = np.repeat(start_sc.mat, (tex_res + 1) * (tex_res + 2) // 2, axis=0)
+            g.set_mesh_colors(tex_res, torch.from_numpy(mat0).to(dev))
+        M = torch.tensor(mat0, device=dev, requires_grad=True)
+        F = torch.from_numpy(start_sc.F).to(dev)
+        src, dst = vertex_neighbours(F, V.shape[0])
+        opt = torch.optim.Adam([{"params": [V], "lr": lr_v}, {"params": [M], "lr": lr_m}])
+        faces.append(int(F.shape[0]))
+        for it in range(steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            opt.zero_grad(set_to_none=True)
+            img = render(V, M, g, cams, spp, bounces, seed=level * steps + it)
+            img_l2 = ((img - T) ** 2).mean()
+            loss = img_l2 + lap_w * uniform_laplacian(V, src, dst)
+            if spec_var_w > 0.0:
+                loss = loss + spec_var_w * M[:, 3:6].var(dim=0, unbiased=False).sum()
+            loss.backward()
+            opt.step()
+            with torch.no_grad():
+                M[:, :6].clamp_(0.0, 1.0)
+                M[:, 6].clamp_(0.01, 1.0)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            l2.append(float(img_l2.detach()))
+            if log_every and it % log_every == 0:
+                print(json.dumps({"level": level, "step": it, "image_l2": l2[-1], "s": times[-1]}), flush=True)
     g.check_errors()
     warm = times[2:] if len(times) > 4 else times
-    return {"steps": steps, "s_per_step": float(np.median(warm)), "image_l2_first": l2[0], "image_l2_last": l2[-1],
+    return {"steps": steps * (subdivisions + 1), "s_per_step": float(np.median(warm)), "image_l2_first": l2[0],
+            "image_l2_last": l2[-1], "faces_per_level": faces,
             "path_samples_per_step": B.num_pixels(cams) * spp, "views": nviews, "res": res, "spp": spp,
-            "bounces": bounces, "faces": int(start_sc.F.shape[0]), "target_faces": int(target_sc.F.shape[0]),
-            "tex_res": tex_res, "material_rows": int(M.shape[0])}
+            "bounces": bounces, "target_faces": int(target_sc.F.shape[0]),
+            "tex_res": tex_res, "material_rows": int(M.shape[0]), "faces": faces[-1]}
 
 
 if __name__ == "__main__":
@@ -82,5 +101,7 @@ if __name__ == "__main__":
     ap.add_argument("--log-every", type=int, default=20)
     ap.add_argument("--tex-res", type=int, default=0)
     ap.add_argument("--spec-var", type=float, default=0.0)
+    ap.add_argument("--subdivisions", type=int, default=0)
     a = ap.parse_args()
-    print(json.dumps(run(a.steps, log_every=a.log_every, tex_res=a.tex_res, spec_var_w=a.spec_var)))
+    print(json.dumps(run(a.steps, log_every=a.log_every, tex_res=a.tex_res, spec_var_w=a.spec_var,
+                         subdivisions=a.subdivisions)))

@@ -720,3 +720,40 @@ def test_fd_frozen_mesh_colors():
     cams = [S.look_at_origin((0.3, 0.9, 3.0), 16, 16)]
     samples = [(0, x, y, j) for (x, y) in [(8, 8), (5, 9), (10, 4), (3, 13)] for j in range(2)]
     assert _fd_check(sc, cams, 2, 3, samples, flags=1) > 50
+
+
+# --------------------------------------------------------------------------
+# 1 -> 4 subdivision (Sec. 3.2 "Subdivision")
+# --------------------------------------------------------------------------
+
+def test_subdivide_single_triangle_by_hand():
+    V = np.array([[0, 0, 0], [2, 0, 0], [0, 4, 0]], np.float32)
+    F = np.array([[0, 1, 2]], np.int32)
+    V2, F2 = O.subdivide(V, F)
+    # edges in (min, max) order: (0,1) -> 3, (0,2) -> 4, (1,2) -> 5
+    assert np.array_equal(V2, np.array([[0, 0, 0], [2, 0, 0], [0, 4, 0], [1, 0, 0], [0, 2, 0], [1, 2, 0]], np.float32))
+    assert np.array_equal(F2, np.array([[0, 3, 4], [1, 5, 3], [2, 4, 5], [3, 5, 4]], np.int32))
+
+
+@pytest.mark.parametrize("k", [1, 3])
+def test_subdivide_invariants_closed_mesh(k):
+    V, F = S.noise_sphere(k, 0.2, noise_seed=3)
+    V = V.astype(np.float32)
+    V2, F2 = O.subdivide(V, F)
+    ne = 30 * k * k
+    assert V2.shape == (V.shape[0] + ne, 3) and F2.shape == (4 * F.shape[0], 3)
+    # Euler characteristic of a sphere, and every edge shared by exactly two faces
+    e2 = {}
+    for f in F2:
+        for a, b in ((f[0], f[1]), (f[1], f[2]), (f[2], f[0])):
+            e2[(min(a, b), max(a, b))] = e2.get((min(a, b), max(a, b)), 0) + 1
+    assert V2.shape[0] - len(e2) + F2.shape[0] == 2
+    assert set(e2.values()) == {2}
+    # the four children tile the parent: areas add up and normals keep their direction
+    def area_normal(VV, FF):
+        n = np.cross(VV[FF[:, 1]] - VV[FF[:, 0]], VV[FF[:, 2]] - VV[FF[:, 0]]).astype(np.float64)
+        return n
+    npar = area_normal(V.astype(np.float64), F)
+    nch = area_normal(V2.astype(np.float64), F2).reshape(-1, 4, 3)
+    assert np.allclose(nch.sum(1), npar, rtol=1e-5, atol=1e-7)
+    assert (np.einsum("fcj,fj->fc", nch, npar) > 0).all()
