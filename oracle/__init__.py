@@ -219,6 +219,8 @@ class OracleScene:
         npix = int((res[:, 0].astype(np.int64) * res[:, 1]).sum())
         d = np.ascontiguousarray(d_image, np.float32).reshape(npix, 3)
         ne = int(sum(round(edge_ratio * int(w) * int(h) * spp) for w, h in res))
+        if flags & 8:           # point-light shadow boundary samples follow the primary edge samples
+            ne *= 1 + self.lights.shape[0]
         dV = np.zeros((self.nv, 3))
         dM = np.zeros((self.ntex, 7))
         ph = np.zeros(npix * spp, np.uint32)

@@ -1079,6 +1079,144 @@ static void primary_edge_sample(const Scene& s, const Cam& c, const EdgeView& ev
 }
 
 // --------------------------------------------------------------------------
+// point-light shadow boundaries seen directly by the camera (the image-space
+// edge term of a shadow; the shadow of an occluder edge e under light l is the
+// central projection of e from the light onto the receiving surface).
+//
+// Candidate edges for light l: boundary edges and edges whose two faces lie on
+// opposite sides of the light position (fp64 test, fixed operation order).  An
+// edge is chosen with probability proportional to its 3-D length, a point
+// y = va + t (vb - va) on it with t uniform; the light ray through y continues
+// to the receiver point z (first hit from y, the edge's faces excluded).  When
+// z is seen by the camera, its screen point s = pi(z) lies on the image curve of
+// the shadow boundary; with tau = ds/dt and n the screen normal perp(tau)/|tau|,
+// the receiver points under s -/+ 1e-3 px n take the light's visibility V-, V+,
+// and the sample adds d_image(pixel of s) . (V- - V+) L_l(z) (n . ds/dtheta)
+// |tau| W_l / (|vb - va| N_s) to dLoss/dtheta, where L_l(z) is the unshadowed
+// radiance of light l reflected at z toward the camera, W_l the total candidate
+// length and N_s the number of samples of the (view, light) pair.  theta moves
+// the edge's endpoints and the receiver face's vertices; the light is fixed.
+// --------------------------------------------------------------------------
+struct LightEdges {
+    std::vector<double> cdf;
+    double total = 0.0;
+};
+
+static LightEdges light_cdf(const Scene& s, int l) {
+    LightEdges le;
+    const size_t ne = s.edges.size();
+    const double* lt = &s.lights[6 * l];
+    D3 pl(lt[0], lt[1], lt[2]);
+    std::vector<double> cum(ne + 1, 0.0);
+    double acc = 0.0;
+    for (size_t e = 0; e < ne; ++e) {
+        const Edge& E = s.edges[e];
+        D3 va = s.vert(E.va), vb = s.vert(E.vb);
+        bool cand = E.f2 < 0;
+        if (!cand) {
+            double s1 = dot(face_N(s, E.f1), pl - va), s2 = dot(face_N(s, E.f2), pl - va);
+            cand = (s1 > 0.0) != (s2 > 0.0);
+        }
+        acc += cand ? length(vb - va) : 0.0;
+        cum[e + 1] = acc;
+    }
+    le.total = acc;
+    le.cdf.assign(ne + 1, 0.0);
+    for (size_t e = 0; e <= ne; ++e) le.cdf[e] = acc > 0 ? cum[e] / acc : 0.0;
+    return le;
+}
+
+static void shadow_edge_sample(const Scene& s, const Cam& c, const LightEdges& le, int view, int l, int64_t si,
+                               int64_t ns, const Key& key, const float* d_img_view, Hash& h, Grad& g) {
+    if (!(le.total > 0.0)) return;
+    double u[4];
+    Ctr ctr{(uint32_t)si, ((uint32_t)view << 16) | (uint32_t)l, 0u, 3u};
+    draw4(ctr, 0, 3, key.k0, key.k1, u);
+    const int e = cdf_find(le.cdf.data(), (int)s.edges.size(), u[0]);
+    const double t = u[1];
+    h.push((uint32_t)e);
+    const Edge& E = s.edges[e];
+    const double* lt = &s.lights[6 * l];
+    const D3 pl(lt[0], lt[1], lt[2]), I(lt[3], lt[4], lt[5]);
+    const D3 va = s.vert(E.va), vb = s.vert(E.vb);
+    const D3 y = va + (vb - va) * t;
+    const D3 w = normalize(y - pl);
+    double tr;
+    const int fr = closest_hit(s, y, w, TMIN, E.f1, tr);
+    push_face(h, fr);
+    if (fr < 0 || fr == E.f2) return;
+    const D3 z = y + w * tr;
+    double tc;
+    const int fc = closest_hit(s, c.eye, normalize(z - c.eye), TMIN, -1, tc);
+    const bool vis = fc == fr;
+    h.push(vis ? 2u : 1u);
+    if (!vis) return;
+    // the receiver point and its screen point as functions of (t, va, vb, r0, r1, r2)
+    typedef Dual<48> T;
+    const int rv[3] = {s.F[3 * fr], s.F[3 * fr + 1], s.F[3 * fr + 2]};
+    V3<T> A(seeded<T>(va.x, 1), seeded<T>(va.y, 2), seeded<T>(va.z, 3));
+    V3<T> Bv(seeded<T>(vb.x, 4), seeded<T>(vb.y, 5), seeded<T>(vb.z, 6));
+    V3<T> R[3];
+    for (int k = 0; k < 3; ++k) {
+        D3 p = s.vert(rv[k]);
+        R[k] = V3<T>(seeded<T>(p.x, 7 + 3 * k), seeded<T>(p.y, 8 + 3 * k), seeded<T>(p.z, 9 + 3 * k));
+    }
+    T tt = seeded<T>(t, 0);
+    V3<T> yy = A + (Bv - A) * tt;
+    V3<T> P = lift<T>(pl);
+    V3<T> Nr = cross(R[1] - R[0], R[2] - R[0]);
+    T lam = dot(Nr, R[0] - P) / dot(Nr, yy - P);
+    V3<T> zz = P + (yy - P) * lam;
+    T sx, sy, sz;
+    project<T>(c, zz, sx, sy, sz);
+    const double xs = sx.v, ys = sy.v;
+    const int px = (int)std::floor(xs), py = (int)std::floor(ys);
+    const bool inside = sz.v > ZNEAR && xs >= 0.0 && ys >= 0.0 && px < c.W && py < c.H;
+    h.push(inside ? 1u : 0u);
+    if (!inside) return;
+    const float* dimg = d_img_view + 3 * ((int64_t)py * c.W + px);
+    if (dimg[0] == 0.0f && dimg[1] == 0.0f && dimg[2] == 0.0f) return;
+    const double tx = sx.d[0], ty = sy.d[0];
+    const double tl = std::sqrt(tx * tx + ty * ty);
+    if (!(tl > 0.0)) return;
+    const double nx = -ty / tl, ny = tx / tl;
+    // light visibility on both sides, at the receiver plane under the side points
+    const D3 r0 = s.vert(rv[0]);
+    const D3 Nd = face_N(s, fr);
+    int vsd[2];
+    for (int side = 0; side < 2; ++side) {
+        const double sg = side == 0 ? -1.0 : 1.0;
+        const D3 dd = cam_dir(c, xs + sg * EPS_PRIMARY * nx, ys + sg * EPS_PRIMARY * ny);
+        const D3 zs = c.eye + dd * (dot(Nd, r0 - c.eye) / dot(Nd, dd));
+        const D3 wl = pl - zs;
+        const double r = length(wl);
+        vsd[side] = any_hit(s, zs, wl * (1.0 / r), TMIN, r * (1.0 - SHADOW_SHRINK), fr) ? 0 : 1;
+        h.push((uint32_t)vsd[side]);
+    }
+    if (vsd[0] == vsd[1]) return;
+    // unshadowed radiance of light l at z toward the camera
+    const D3 wo = normalize(c.eye - z);
+    D3 n = normalize(Nd);
+    if (dot(n, wo) < 0.0) n = -n;
+    const D3 dl = pl - z;
+    const double r2 = dot(dl, dl);
+    const D3 wl = dl * (1.0 / std::sqrt(r2));
+    const double cl = dot(n, wl);
+    if (!(cl > 0.0)) return;
+    const double* m = &s.mat[7 * texel_of(s, fr, z)];
+    const D3 fv = brdf(wl, wo, n, m);
+    double cc = 0.0;
+    for (int ch = 0; ch < 3; ++ch) cc += (double)dimg[ch] * (vsd[0] - vsd[1]) * fv[ch] * I[ch] * cl / r2;
+    cc *= tl * le.total / (length(vb - va) * (double)ns);
+    auto vn = [&](int slot) { return nx * sx.d[slot] + ny * sy.d[slot]; };
+    for (int k = 0; k < 3; ++k) {
+        g.dV[3 * E.va + k] += cc * vn(1 + k);
+        g.dV[3 * E.vb + k] += cc * vn(4 + k);
+        for (int q = 0; q < 3; ++q) g.dV[3 * rv[q] + k] += cc * vn(7 + 3 * q + k);
+    }
+}
+
+// --------------------------------------------------------------------------
 // LBVH reference (integer Morton codes, bit-exact spec shared with the GPU):
 // float32 centroids and scale, 10 bits per axis (x highest), key = morton<<32 |
 // face, ascending sort, Karras 2012 hierarchy, min/max refit.
@@ -1348,7 +1486,7 @@ int or_backward(void* p, const double* cams, const int* res, int ncam, int spp, 
     int nt = std::max(1, nthreads);
     std::vector<Grad> G(nt);
     for (auto& g : G) { g.dV.assign(3 * (size_t)s->nv, 0.0); g.dM.assign(s->mat.size(), 0.0); }
-    const bool interior = flags & 1, primary = flags & 2, secondary = flags & 4;
+    const bool interior = flags & 1, primary = flags & 2, secondary = flags & 4, shadow = flags & 8;
     const int64_t npath = vw.pixoff[ncam] * spp;
     if (path_hash) std::memset(path_hash, 0, sizeof(unsigned) * npath);
     if (interior || secondary) {
@@ -1370,7 +1508,8 @@ int or_backward(void* p, const double* cams, const int* res, int ncam, int spp, 
             if (path_hash) path_hash[idx] = h.h;
         });
     }
-    if (edge_hash) std::memset(edge_hash, 0, sizeof(unsigned) * vw.eoff[ncam]);
+    const int64_t n_edge_all = vw.eoff[ncam] * (1 + ((flags & 8) ? (int64_t)s->nl : 0));
+    if (edge_hash) std::memset(edge_hash, 0, sizeof(unsigned) * n_edge_all);
     if (primary) {
         for (int v = 0; v < ncam; ++v) {
             const Cam& c = vw.cams[v];
@@ -1384,6 +1523,26 @@ int or_backward(void* p, const double* cams, const int* res, int ncam, int spp, 
                 primary_edge_sample(*s, c, ev, v, si, vw.ne[v], spp, bounces, key, dv, h, G[tid], comp);
                 if (edge_hash && comp) edge_hash[gi] = h.h;
             });
+        }
+    }
+    if (shadow && s->nl > 0) {
+        // point-light shadow boundaries: samples of (view v, light l) follow the
+        // primary edge samples, at nl eoff[v] + l N_e(v) + i
+        const int64_t ep = vw.eoff[ncam];
+        for (int l = 0; l < s->nl; ++l) {
+            LightEdges le = light_cdf(*s, l);
+            for (int v = 0; v < ncam; ++v) {
+                const Cam& c = vw.cams[v];
+                const float* dv = d_image + 3 * vw.pixoff[v];
+                const int64_t base = ep + (int64_t)s->nl * vw.eoff[v] + (int64_t)l * vw.ne[v];
+                parallel_for(vw.ne[v], nt, [&](int64_t si, int tid) {
+                    const int64_t gi = base + si;
+                    if (edge_mask && !edge_mask[gi]) return;
+                    Hash h;
+                    shadow_edge_sample(*s, c, le, v, l, si, vw.ne[v], key, dv, h, G[tid]);
+                    if (edge_hash) edge_hash[gi] = h.h;
+                });
+            }
         }
     }
     for (size_t i = 0; i < 3 * (size_t)s->nv; ++i) { double a = 0; for (auto& g : G) a += g.dV[i]; dV[i] = a; }

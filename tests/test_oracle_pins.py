@@ -757,3 +757,92 @@ def test_subdivide_invariants_closed_mesh(k):
     nch = area_normal(V2.astype(np.float64), F2).reshape(-1, 4, 3)
     assert np.allclose(nch.sum(1), npar, rtol=1e-5, atol=1e-7)
     assert (np.einsum("fcj,fj->fc", nch, npar) > 0).all()
+
+
+# --------------------------------------------------------------------------
+# point-light shadow boundaries (row NEXT-1)
+# --------------------------------------------------------------------------
+
+def _gauss_legendre(n):
+    x, w = np.polynomial.legendre.leggauss(n)
+    return 0.5 * (x + 1.0), 0.5 * w
+
+
+def test_shadow_edges_closed_form_polygon():
+    """A Lambertian floor z = 0 seen straight down, lit by one point light and
+    shadowed by a triangle that the camera does not see.  The image is zero
+    inside the shadow polygon (the central projection of the triangle from the
+    light) and L(x) = kd/pi I cos/r^2 outside, so d(sum of pixels)/d(occluder
+    vertex) = - boundary integral of L times the polygon's outward normal
+    velocity, evaluated here by Gauss-Legendre quadrature along the three edges
+    of the projected polygon.  The shadow-edge estimator must match it."""
+    floor = np.array([[-3, -3, 0], [3, -3, 0], [3, 3, 0], [-3, 3, 0]], np.float32)
+    occ = np.array([[-1.2, -0.2, 1.0], [-0.8, -0.3, 1.05], [-1.0, 0.3, 0.95]], np.float32)
+    V = np.concatenate([floor, occ])
+    F = np.array([[0, 1, 2], [0, 2, 3], [4, 5, 6]], np.int32)
+    kd = 0.6
+    mat = np.zeros((3, 7), np.float32)
+    mat[:, :3] = kd
+    mat[:, 6] = 0.5
+    light = np.array([[-2.2, 0.0, 3.0, 10.0, 10.0, 10.0]], np.float32)
+    W = H = 64
+    cam = S.Camera((0.0, 0.0, 2.5), (0, 0, 0), (0, 1, 0), 45.0, W, H)
+    sc = O.OracleScene(V, F, mat, light, None)
+    d_img = np.ones((W * H, 3), np.float32)
+    dV, _, _, eh = sc.backward([cam], 1, 1, d_img, seed=3, flags=8, edge_ratio=50.0)
+    assert (eh[W * H * 50:] != 0).all()          # every shadow sample hashes its decisions
+    est = dV[4:7]
+
+    pl, I = light[0, :3].astype(float), float(light[0, 3])
+    Vd = V.astype(float)
+
+    def screen(X):                       # the camera's projection (pinhole looking down -z, up +y)
+        e = np.array([0.0, 0.0, 2.5])
+        f, r, u = np.array([0, 0, -1.0]), np.array([1.0, 0, 0]), np.array([0, 1.0, 0])
+        th = math.tan(math.radians(22.5))
+        p = X - e
+        z = p @ f
+        return np.array([(p @ r / (z * th) + 1.0) * 0.5 * W, (1.0 - p @ u / (z * th)) * 0.5 * H])
+
+    def unscreen(s):                     # floor point under screen point s
+        th = math.tan(math.radians(22.5))
+        a = (2.0 * s[0] / W - 1.0) * th * 2.5
+        b = (1.0 - 2.0 * s[1] / H) * th * 2.5
+        return np.array([a, b, 0.0])
+
+    def L(x):
+        dl = pl - x
+        r2 = dl @ dl
+        return kd / math.pi * I * (dl[2] / math.sqrt(r2)) / r2
+
+    def Q(v):                            # shadow of occluder vertex v on the floor
+        lam = pl[2] / (pl[2] - v[2])
+        return pl + lam * (v - pl)
+
+    q = np.array([screen(Q(v)) for v in Vd[4:7]])
+    area2 = (q[1, 0] - q[0, 0]) * (q[2, 1] - q[0, 1]) - (q[2, 0] - q[0, 0]) * (q[1, 1] - q[0, 1])
+    uq, wq = _gauss_legendre(64)
+    expect = np.zeros((3, 3))
+    h = 1e-6
+    for i in range(3):
+        for k in range(3):
+            vp, vm = Vd[4 + i].copy(), Vd[4 + i].copy()
+            vp[k] += h
+            vm[k] -= h
+            qdot = (screen(Q(vp)) - screen(Q(vm))) / (2 * h)     # velocity of polygon vertex i
+            tot = 0.0
+            for a in range(3):
+                b2 = (a + 1) % 3
+                if i not in (a, b2):
+                    continue
+                d = q[b2] - q[a]
+                ln = math.hypot(*d)
+                nout = np.array([d[1], -d[0]]) / ln * (1.0 if area2 > 0 else -1.0)
+                for uu, ww in zip(uq, wq):
+                    s = q[a] + uu * d
+                    wgt = (1.0 - uu) if i == a else uu
+                    tot += ww * ln * L(unscreen(s)) * wgt * (qdot @ nout)
+            expect[i, k] = -3.0 * tot         # three colour channels, d_image = 1 each
+    scale = np.abs(expect).max()
+    assert scale > 0
+    assert np.abs(est - expect).max() < 0.03 * scale, (est, expect)
