@@ -51,6 +51,7 @@ extern "C" {
 #define ST_GRAD_INTERIOR 1u        /* derivative of the estimator at fixed sampled directions */
 #define ST_EDGE_PRIMARY 2u         /* screen-space silhouette / crease edges (camera visibility) */
 #define ST_EDGE_SECONDARY 4u       /* direction-space silhouette edges at every path vertex */
+#define ST_EDGE_SHADOW 8u          /* point-light shadow boundaries seen by the camera (image-space term) */
 #define ST_FORWARD_MEGAKERNEL 16u  /* forward as one kernel per path sample instead of the wavefront */
 #define ST_COUNT_WORK 32u          /* count BVH node visits, triangle tests and rays (st_read_work) */
 
@@ -66,18 +67,23 @@ typedef struct {
 
 typedef struct {
     uint32_t flags;                  /* ST_GRAD_* | ST_EDGE_* | ST_FORWARD_MEGAKERNEL */
-    float edge_spp_ratio;            /* primary edge samples per (pixel x spp) of each view */
+    float edge_spp_ratio;            /* primary edge samples per (pixel x spp) of each view; with
+                                        ST_EDGE_SHADOW as many shadow-edge samples per (view, light) */
     int64_t queue_capacity;          /* wavefront chunk size in path samples (0: library default) */
     uint32_t* debug_decision_hash;   /* device, optional: one FNV-1a hash of the discrete decisions per
                                         path sample, index ((pixel offset of view + y*W + x) * spp + j) */
-    uint32_t* debug_edge_hash;       /* device, optional (backward): one hash per primary edge sample */
+    uint32_t* debug_edge_hash;       /* device, optional (backward): one hash per primary edge sample,
+                                        then (ST_EDGE_SHADOW) one per shadow-edge sample, sample i of
+                                        (view v, light l) at N_e + nl eoff_v + l N_e(v) + i, N_e the
+                                        primary total, eoff_v the primary offset of view v */
     float* debug_sample_radiance;    /* device, optional (forward): per path sample rgb, same index */
     const uint8_t* path_mask;        /* device, optional (backward): 0 skips a path sample */
-    const uint8_t* edge_mask;        /* device, optional (backward): 0 skips a primary edge sample */
+    const uint8_t* edge_mask;        /* device, optional (backward): 0 skips an edge sample (same index) */
 } st_render_opts;
 
-/* Default options: all three gradient terms, one primary edge sample per
- * pixel sample, default queue capacity, no debug outputs. */
+/* Default options: interior, primary and secondary edge terms and the
+ * point-light shadow boundaries, one edge sample per pixel sample, default
+ * queue capacity, no debug outputs. */
 st_render_opts st_render_opts_default(void);
 
 /* Create a scene (Sec. 3.2 triangle mesh x with faces; Sec. 3.3 per-face

@@ -20,9 +20,10 @@ LIB_PATH = os.environ.get("SHAPETRACE_LIB", os.path.join(_HERE, "libshapetrace.s
 ST_GRAD_INTERIOR = 1
 ST_EDGE_PRIMARY = 2
 ST_EDGE_SECONDARY = 4
+ST_EDGE_SHADOW = 8
 ST_FORWARD_MEGAKERNEL = 16
 ST_COUNT_WORK = 32
-ST_ALL_GRADS = 7
+ST_ALL_GRADS = 15
 
 EXPORTED = ["st_render_opts_default", "st_scene_create", "st_scene_update", "st_scene_set_mesh_colors",
             "st_scene_mesh_colors_info", "st_scene_subdivide", "st_render", "st_render_backward",
@@ -119,8 +120,11 @@ def num_pixels(cams) -> int:
     return int(sum(int(c.width) * int(c.height) for c in cams))
 
 
-def num_edge_samples(cams, spp: int, ratio: float) -> int:
-    return int(sum(round(ratio * int(c.width) * int(c.height) * spp) for c in cams))
+def num_edge_samples(cams, spp: int, ratio: float, n_shadow_lights: int = 0) -> int:
+    """Primary edge samples, followed by n_shadow_lights x as many point-light
+    shadow-edge samples (ST_EDGE_SHADOW with the scene's light count)."""
+    n = int(sum(round(ratio * int(c.width) * int(c.height) * spp) for c in cams))
+    return n * (1 + int(n_shadow_lights))
 
 
 def make_opts(flags=ST_ALL_GRADS, edge_ratio=1.0, queue_capacity=0, dbg_hash=None, dbg_edge_hash=None,

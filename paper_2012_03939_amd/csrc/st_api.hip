@@ -332,7 +332,7 @@ extern "C" {
 st_render_opts st_render_opts_default(void) {
     st_render_opts o;
     std::memset(&o, 0, sizeof(o));
-    o.flags = ST_GRAD_INTERIOR | ST_EDGE_PRIMARY | ST_EDGE_SECONDARY;
+    o.flags = ST_GRAD_INTERIOR | ST_EDGE_PRIMARY | ST_EDGE_SECONDARY | ST_EDGE_SHADOW;
     o.edge_spp_ratio = 1.0f;
     return o;
 }
@@ -616,8 +616,11 @@ int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_
     if (rc) return rc;
     const int ne = sc->d.ne;
     const int pglog = guide_log2(ne);
+    const int nls = (o.flags & ST_EDGE_SHADOW) ? sc->d.nl : 0;     // lights with shadow-edge tables
     const size_t pbytes = sizeof(double) * ((size_t)ncam * ne + (size_t)ncam * (ne + 1) + ncam) +
-                          sizeof(int) * ((size_t)ncam << pglog) + sizeof(double) * 2 * (size_t)ncam * ne + 5 * 256;
+                          sizeof(int) * ((size_t)ncam << pglog) + sizeof(double) * 2 * (size_t)ncam * ne +
+                          sizeof(double) * ((size_t)nls * ne + (size_t)nls * (ne + 1) + nls) +
+                          sizeof(int) * ((size_t)nls << pglog) + 9 * 256;
     rc = sc->primbuf.ensure(pbytes);
     if (rc) return rc;
     Carver c{(char*)sc->primbuf.p};
@@ -630,7 +633,7 @@ int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_
     p.spp = spp;
     p.B = bounces;
     p.seed = seed;
-    p.flags = o.flags & 7u;
+    p.flags = o.flags & 15u;
     p.d_image = d_image;
     p.path_mask = o.path_mask;
     p.edge_mask = o.edge_mask;
@@ -647,6 +650,10 @@ int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_
     p.pguide = c.take<int>((size_t)ncam << pglog);
     p.pglog = pglog;
     p.pacc = c.take<double>(2 * (size_t)ncam * ne);
+    p.lw = c.take<double>((size_t)nls * ne);
+    p.lcdf = c.take<double>((size_t)nls * (ne + 1));
+    p.ltotal = c.take<double>(nls);
+    p.lguide = c.take<int>((size_t)nls << pglog);
     p.facc = sc->d.facc;
     p.macc = sc->d.macc;
     p.ntex = sc->d.ntex;
@@ -656,7 +663,7 @@ int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_
     launch_fill_f32(out_dV, 3ll * sc->d.nv, 0.0f, s);
     launch_fill_f32(out_dmat, 7ll * sc->d.ntex, 0.0f, s);
     if (o.debug_decision_hash) launch_fill_u32(o.debug_decision_hash, cs.total_paths, 0u, s);
-    if (o.debug_edge_hash) launch_fill_u32(o.debug_edge_hash, cs.total_edges, 0u, s);
+    if (o.debug_edge_hash) launch_fill_u32(o.debug_edge_hash, cs.total_edges * (1 + nls), 0u, s);
     launch_backward(p, sc->d.nv, sc->d.nf, cs.total_paths, cs.total_edges, TRACE_GRID, s);
     if ((p.flags & ST_EDGE_PRIMARY) && cs.total_edges > 0 && ne > 0) {
         // side paths of the primary edge samples run through the wavefront kernels
@@ -691,6 +698,7 @@ int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_
         fp.hash_by_q = hside;
         launch_primary_edges(p, fp, q, (float*)sc->sidebuf.p, hside, cs.total_edges, sc->d.has_env ? 1 : 0, s);
     }
+    if (nls > 0) launch_shadow_edges(p, cs.total_edges, nls, s);
     HIPCHK(hipGetLastError());
     return ST_OK;
 }

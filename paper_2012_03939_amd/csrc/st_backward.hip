@@ -642,6 +642,204 @@ __global__ void k_face_gather(BwdParams p) {
 }
 
 // ---------------------------------------------------------------------------
+// point-light shadow boundaries seen by the camera.  For light l an edge is a
+// candidate when it is a boundary edge or its faces lie on opposite sides of the
+// light (the fp64 side test of the secondary edges, at the light position);
+// edges are drawn by 3-D length, t uniform.  The light ray through the edge
+// point y continues to the receiver point z; if the camera sees z, the screen
+// point s = pi(z) lies on the image of the shadow boundary.  With tau = ds/dt
+// and n = perp(tau)/|tau| the receiver points under s -/+ 1e-3 px n take the
+// light's visibility V-, V+, and the sample adds
+// d_image(s) . (V- - V+) L_l(z) (n . ds/dtheta) |tau| W_l / (|vb - va| N_s)
+// for theta = the edge's endpoints and the receiver face's vertices.
+// ---------------------------------------------------------------------------
+__global__ void k_light_weights(BwdParams p) {
+#pragma clang fp contract(off)
+    const int l = blockIdx.y;
+    const DevScene& S = p.scenes[0];
+    const V3 pl = ld3(S.lights + 6 * l);
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < S.ne; e += gridDim.x * blockDim.x) {
+        const int4 E = S.edges[e];
+        double w = 0.0;
+        if (silhouette(S, E, pl)) {
+            const double dx = (double)S.V[3 * E.y] - (double)S.V[3 * E.x];
+            const double dy = (double)S.V[3 * E.y + 1] - (double)S.V[3 * E.x + 1];
+            const double dz = (double)S.V[3 * E.y + 2] - (double)S.V[3 * E.x + 2];
+            w = sqrt(dx * dx + dy * dy + dz * dz);
+        }
+        p.lw[(size_t)l * p.ne + e] = w;
+    }
+}
+
+__global__ void k_light_cdf(BwdParams p) {
+    const int l = blockIdx.x;
+    block_scan_normalise(p.lw + (size_t)l * p.ne, p.ne, p.lcdf + (size_t)l * (p.ne + 1), p.ltotal + l);
+}
+
+// screen point of z and its Jacobian rows (d sx/dz, d sy/dz) for camera c
+__device__ __forceinline__ void project_jac(const DevCam& c, const double z[3], double& sx, double& sy, double& depth,
+                                            double jx[3], double jy[3]) {
+#pragma clang fp contract(off)
+    const double q[3] = {z[0] - c.deye[0], z[1] - c.deye[1], z[2] - c.deye[2]};
+    depth = q[0] * c.df[0] + q[1] * c.df[1] + q[2] * c.df[2];
+    const double a = q[0] * c.dr[0] + q[1] * c.dr[1] + q[2] * c.dr[2];
+    const double b = q[0] * c.du[0] + q[1] * c.du[1] + q[2] * c.du[2];
+    sx = (a / (depth * (c.dth * c.daspect)) + 1.0) * (0.5 * c.W);
+    sy = (1.0 - b / (depth * c.dth)) * (0.5 * c.H);
+    const double kx = (0.5 * c.W) / (c.dth * c.daspect) / (depth * depth);
+    const double ky = -(0.5 * c.H) / c.dth / (depth * depth);
+    for (int k = 0; k < 3; ++k) {
+        jx[k] = kx * (c.dr[k] * depth - a * c.df[k]);
+        jy[k] = ky * (c.du[k] * depth - b * c.df[k]);
+    }
+}
+
+__device__ void shadow_edge_one(const BwdParams& p, const DevScene& S, const DevCam& c, int v, int l, long long si,
+                                long long nsv, Hash& h, TravStack& st) {
+#pragma clang fp contract(off)
+    if (!(p.ltotal[l] > 0.0)) return;
+    const Ctr ctr{(uint32_t)si, ((uint32_t)c.rngview << 16) | (uint32_t)l, 0u, 3u};
+    const float4 u = draw4(ctr, 0, 3, Key{p.seed, S.scene_id});
+    const int e = cdf_guided(p.lcdf + (size_t)l * (p.ne + 1), S.ne, p.lguide + ((size_t)l << p.pglog), p.pglog,
+                             (double)u.x);
+    const float t = u.y;
+    h.push((uint32_t)e);
+    const int4 E = S.edges[e];
+    const float* lt = S.lights + 6 * l;
+    const V3 pl = ld3(lt), va = ld3(S.V + 3 * E.x), vb = ld3(S.V + 3 * E.y);
+    const V3 y = va + (vb - va) * t;
+    const V3 w = normalize(y - pl);
+    float tr;
+    const int fr = trace_closest(S, y, w, TMIN, E.z, tr, st);
+    h.push(fr < 0 ? 0xFFFFFFFFu : (uint32_t)fr);
+    if (fr < 0 || fr == E.w) return;
+    const V3 zt = y + w * tr;
+    const V3 eye = ld3(c.eye);
+    float tc;
+    const int fc = trace_closest(S, eye, normalize(zt - eye), TMIN, -1, tc, st);
+    const bool vis = fc == fr;
+    h.push(vis ? 2u : 1u);
+    if (!vis) return;
+    // receiver point on the plane of fr along the light ray through y (fp64)
+    double Nr[3], r0[3];
+    face_N_d(S, fr, Nr, r0);
+    const double yd[3] = {(double)y.x, (double)y.y, (double)y.z}, pd[3] = {(double)pl.x, (double)pl.y, (double)pl.z};
+    const double D[3] = {yd[0] - pd[0], yd[1] - pd[1], yd[2] - pd[2]};
+    const double Bd = Nr[0] * D[0] + Nr[1] * D[1] + Nr[2] * D[2];
+    const double A = Nr[0] * (r0[0] - pd[0]) + Nr[1] * (r0[1] - pd[1]) + Nr[2] * (r0[2] - pd[2]);
+    const double lam = A / Bd;
+    const double z[3] = {pd[0] + D[0] * lam, pd[1] + D[1] * lam, pd[2] + D[2] * lam};
+    double xs, ys, depth, jx[3], jy[3];
+    project_jac(c, z, xs, ys, depth, jx, jy);
+    const int px = (int)floor(xs), py = (int)floor(ys);
+    const bool inside = depth > ZNEAR && xs >= 0.0 && ys >= 0.0 && px < c.W && py < c.H;
+    h.push(inside ? 1u : 0u);
+    if (!inside) return;
+    const float* di = p.d_image + 3 * (c.pixoff + (long long)py * c.W + px);
+    if (di[0] == 0.0f && di[1] == 0.0f && di[2] == 0.0f) return;
+    // tau = ds/dt = J (dz/dy)(vb - va), dz/dy d = lam (d - D (Nr . d) / Bd)
+    const double ed[3] = {(double)vb.x - (double)va.x, (double)vb.y - (double)va.y, (double)vb.z - (double)va.z};
+    const double ne_ = (Nr[0] * ed[0] + Nr[1] * ed[1] + Nr[2] * ed[2]) / Bd;
+    double dz[3];
+    for (int k = 0; k < 3; ++k) dz[k] = lam * (ed[k] - D[k] * ne_);
+    const double tx = jx[0] * dz[0] + jx[1] * dz[1] + jx[2] * dz[2];
+    const double ty = jy[0] * dz[0] + jy[1] * dz[1] + jy[2] * dz[2];
+    const double tl = sqrt(tx * tx + ty * ty);
+    if (!(tl > 0.0)) return;
+    const double nx = -ty / tl, ny = tx / tl;
+    // light visibility on both sides, at the receiver plane under the side points
+    int vsd[2];
+    for (int side = 0; side < 2; ++side) {
+        const double sg = side == 0 ? -1.0 : 1.0;
+        const double sxp = xs + sg * EPS_PRIMARY * nx, syp = ys + sg * EPS_PRIMARY * ny;
+        const double ndx = 2.0 * sxp / c.W - 1.0, ndy = 1.0 - 2.0 * syp / c.H;
+        const double kx = ndx * c.dth * c.daspect, ky = ndy * c.dth;
+        double dd[3];
+        for (int k = 0; k < 3; ++k) dd[k] = c.df[k] + c.dr[k] * kx + c.du[k] * ky;
+        const double il = 1.0 / sqrt(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]);
+        for (int k = 0; k < 3; ++k) dd[k] *= il;
+        const double tp = (Nr[0] * (r0[0] - c.deye[0]) + Nr[1] * (r0[1] - c.deye[1]) + Nr[2] * (r0[2] - c.deye[2])) /
+                          (Nr[0] * dd[0] + Nr[1] * dd[1] + Nr[2] * dd[2]);
+        const double zs[3] = {c.deye[0] + dd[0] * tp, c.deye[1] + dd[1] * tp, c.deye[2] + dd[2] * tp};
+        const double wl[3] = {pd[0] - zs[0], pd[1] - zs[1], pd[2] - zs[2]};
+        const double r = sqrt(wl[0] * wl[0] + wl[1] * wl[1] + wl[2] * wl[2]);
+        const V3 zf{(float)zs[0], (float)zs[1], (float)zs[2]};
+        const V3 wf{(float)(wl[0] / r), (float)(wl[1] / r), (float)(wl[2] / r)};
+        vsd[side] = trace_any(S, zf, wf, TMIN, (float)(r * (1.0 - (double)SHADOW_SHRINK)), fr, st) ? 0 : 1;
+        h.push((uint32_t)vsd[side]);
+    }
+    if (vsd[0] == vsd[1]) return;
+    // unshadowed radiance of the light at z toward the camera
+    const V3 zf{(float)z[0], (float)z[1], (float)z[2]};
+    const V3 wo = normalize(eye - zt);
+    V3 n = normalize(V3{(float)Nr[0], (float)Nr[1], (float)Nr[2]});
+    if (dot(n, wo) < 0.0f) n = -n;
+    const V3 dl = pl - zt;
+    const float r2 = dot(dl, dl);
+    const V3 wl = dl * (1.0f / sqrtf(r2));
+    const float cl = dot(n, wl);
+    if (!(cl > 0.0f)) return;
+    const Mat m = load_mat(S.mat + 7 * (size_t)texel_of(S, fr, zf));
+    const V3 fv = brdf_eval(wl, wo, n, m);
+    const V3 I = ld3(lt + 3);
+    const double dv = (double)(vsd[0] - vsd[1]);
+    double cc = ((double)di[0] * fv.x * I.x + (double)di[1] * fv.y * I.y + (double)di[2] * fv.z * I.z) * dv *
+                (double)cl / (double)r2;
+    cc *= tl * p.ltotal[l] / (p.lw[(size_t)l * p.ne + e] * (double)nsv);
+    // reverse: g_z = J^T (cc n), then z = pl + lam (y - pl), lam = (Nr . (r0 - pl)) / (Nr . (y - pl))
+    double gz[3];
+    for (int k = 0; k < 3; ++k) gz[k] = cc * (nx * jx[k] + ny * jy[k]);
+    const double glam = gz[0] * D[0] + gz[1] * D[1] + gz[2] * D[2];
+    double gy[3], gN[3], gr0[3];
+    for (int k = 0; k < 3; ++k) {
+        gy[k] = lam * gz[k] - glam * lam * Nr[k] / Bd;
+        gN[k] = glam * ((r0[k] - pd[k]) * Bd - A * D[k]) / (Bd * Bd);
+        gr0[k] = glam * Nr[k] / Bd;
+    }
+    // N = e1 x e2 with e1 = r1 - r0, e2 = r2 - r0
+    const int i0 = S.F[3 * fr], i1 = S.F[3 * fr + 1], i2 = S.F[3 * fr + 2];
+    const double e1[3] = {(double)S.V[3 * i1] - r0[0], (double)S.V[3 * i1 + 1] - r0[1], (double)S.V[3 * i1 + 2] - r0[2]};
+    const double e2[3] = {(double)S.V[3 * i2] - r0[0], (double)S.V[3 * i2 + 1] - r0[1], (double)S.V[3 * i2 + 2] - r0[2]};
+    const double ge1[3] = {e2[1] * gN[2] - e2[2] * gN[1], e2[2] * gN[0] - e2[0] * gN[2], e2[0] * gN[1] - e2[1] * gN[0]};
+    const double ge2[3] = {gN[1] * e1[2] - gN[2] * e1[1], gN[2] * e1[0] - gN[0] * e1[2], gN[0] * e1[1] - gN[1] * e1[0]};
+    const float tt = t;
+    atomic_add3(p.dV + 3 * (size_t)E.x, V3{(float)(gy[0] * (1.0 - tt)), (float)(gy[1] * (1.0 - tt)),
+                                           (float)(gy[2] * (1.0 - tt))});
+    atomic_add3(p.dV + 3 * (size_t)E.y, V3{(float)(gy[0] * tt), (float)(gy[1] * tt), (float)(gy[2] * tt)});
+    atomic_add3(p.dV + 3 * (size_t)i0, V3{(float)(gr0[0] - ge1[0] - ge2[0]), (float)(gr0[1] - ge1[1] - ge2[1]),
+                                          (float)(gr0[2] - ge1[2] - ge2[2])});
+    atomic_add3(p.dV + 3 * (size_t)i1, V3{(float)ge1[0], (float)ge1[1], (float)ge1[2]});
+    atomic_add3(p.dV + 3 * (size_t)i2, V3{(float)ge2[0], (float)ge2[1], (float)ge2[2]});
+}
+
+// one thread per shadow-edge sample; sample gs of (view v, light l, index i) is
+// nl eoff[v] + l N_e(v) + i, and its hash / mask slot follows the primary edge samples
+__global__ void __launch_bounds__(TRACE_BLOCK) k_shadow_edges(BwdParams p, long long total_edges, long long nsh) {
+    __shared__ uint32_t lds[LDS_STACK * TRACE_BLOCK];
+    TravStack st = make_trav_stack(lds, p.spill, p.err, nullptr);
+    const DevScene& S = p.scenes[0];
+    const long long nl = S.nl;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long gs = blockIdx.x * (long long)blockDim.x + threadIdx.x; gs < nsh; gs += stride) {
+        int lo = 0, hi = p.ncam - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (nl * p.eoff[mid] <= gs) lo = mid; else hi = mid - 1;
+        }
+        const DevCam& c = p.cams[lo];
+        const long long nsv = p.eoff[lo + 1] - p.eoff[lo];
+        const long long rem = gs - nl * p.eoff[lo];
+        const int l = (int)(rem / nsv);
+        const long long si = rem - (long long)l * nsv;
+        if (p.edge_mask && !p.edge_mask[total_edges + gs]) continue;
+        Hash h{FNV_INIT, p.dbg_edge_hash != nullptr};
+        shadow_edge_one(p, S, c, lo, l, si, nsv, h, st);
+        if (p.dbg_edge_hash) p.dbg_edge_hash[total_edges + gs] = h.h;
+    }
+}
+
+
+// ---------------------------------------------------------------------------
 static inline unsigned gridb(long long n, int bs, int cap) {
     long long g = (n + bs - 1) / bs;
     if (g < 1) g = 1;
@@ -683,6 +881,16 @@ void launch_backward(const BwdParams& p, int nv, int nf, long long total_paths, 
                   st, p);
     }
 
+}
+
+void launch_shadow_edges(const BwdParams& p, long long total_edges, int nl, hipStream_t st) {
+    if (total_edges <= 0 || p.ne <= 0 || nl <= 0) return;
+    ST_LAUNCH("k_light_weights", k_light_weights, dim3(gridb(p.ne, 256, 1024), nl), dim3(256), 0, st, p);
+    ST_LAUNCH("k_light_cdf", k_light_cdf, dim3(nl), dim3(1024), 0, st, p);
+    launch_guide(p.lcdf, p.ne, (size_t)(p.ne + 1), nl, p.lguide, p.pglog, st);
+    const long long nsh = total_edges * nl;
+    ST_LAUNCH("k_shadow_edges", k_shadow_edges, dim3(gridb(nsh, TRACE_BLOCK, TRACE_GRID)), dim3(TRACE_BLOCK), 0, st, p,
+              total_edges, nsh);
 }
 
 } // namespace st

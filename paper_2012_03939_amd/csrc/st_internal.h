@@ -171,6 +171,10 @@ struct BwdParams {
     int pglog;
     double* pacc;            // per (view, edge): sums of c (1-t) and c t over its primary edge samples [ncam, ne, 2]
     int ne;
+    double* lw;              // per-light shadow-edge weights [nl, ne]
+    double* lcdf;            // per-light shadow-edge CDF [nl, ne+1]
+    double* ltotal;          // [nl]
+    int* lguide;             // per-light guide tables [nl, 2^pglog]
     float* facc;             // per-face corner accumulators [9, nf]: d/d(v0, v1, v2)
     float* macc;             // per-texel material accumulators [7, ntex]
     int ntex;
@@ -181,6 +185,8 @@ struct BwdParams {
 void launch_backward(const BwdParams& p, int nv, int nf, long long total_paths, long long total_edges, int grid,
                      hipStream_t st);
 // primary edges with their side paths traced by the wavefront kernels
+// point-light shadow boundaries (ST_EDGE_SHADOW); total_edges = primary edge samples
+void launch_shadow_edges(const BwdParams& p, long long total_edges, int nl, hipStream_t st);
 void launch_primary_edges(const BwdParams& p, const FwdParams& fp, Queues& q, float* Lside, uint32_t* hside,
                           long long total_edges, int has_env_any, hipStream_t st);
 void launch_fill_f32(float* p, long long n, float v, hipStream_t st);

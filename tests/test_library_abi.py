@@ -31,7 +31,7 @@ def test_host_side_validation_without_gpu():
     L = B.load()
     assert L.st_version() == 1
     o = L.st_render_opts_default()
-    assert o.flags == 7 and abs(o.edge_spp_ratio - 1.0) < 1e-7 and o.queue_capacity == 0
+    assert o.flags == 15 and abs(o.edge_spp_ratio - 1.0) < 1e-7 and o.queue_capacity == 0
     out = ctypes.c_void_p()
     rc = L.st_scene_create(None, 0, None, 0, None, None, 0, None, 0, 0, 0, None, ctypes.byref(out))
     assert rc == -1 and b"non-NULL" in L.st_last_error()
