@@ -54,6 +54,8 @@ extern "C" {
 #define ST_EDGE_SHADOW 8u          /* point-light shadow boundaries seen by the camera (image-space term) */
 #define ST_FORWARD_MEGAKERNEL 16u  /* forward as one kernel per path sample instead of the wavefront */
 #define ST_COUNT_WORK 32u          /* count BVH node visits, triangle tests and rays (st_read_work) */
+#define ST_EDGE_SECONDARY_INTERIOR 64u  /* secondary edges: also creases and material boundaries seen from
+                                           a path vertex, not only silhouettes (2 side paths per sample) */
 
 typedef struct st_scene st_scene;
 

@@ -618,6 +618,8 @@ struct Grad {           // double accumulators for dV [nv*3] and dmat [nf*7]
 struct SecCtx {         // secondary-edge state of a main path (backward only)
     double w[3];        // loss weight per channel for this sample
     Grad* g;
+    bool interior = false;  // also take edges that are not silhouettes from the shading point
+                            // (creases and material boundaries seen in direction space)
 };
 
 struct Key { uint32_t k0, k1; };
@@ -738,7 +740,7 @@ static D3 trace_estimator(const Scene& s, D3 o, D3 d, int exclude, int nvert, bo
             // an edge of the shading face lies in the tangent plane (cos = 0):
             // its direction-space contribution vanishes, so it is never taken
             bool sil = E.f1 != f && E.f2 != f;
-            if (sil && E.f2 >= 0) {
+            if (sil && E.f2 >= 0 && !sec->interior) {
                 double s1 = dot(face_N(s, E.f1), x - va), s2 = dot(face_N(s, E.f2), x - va);
                 sil = (s1 > 0.0) != (s2 > 0.0);
             }
@@ -1501,7 +1503,7 @@ int or_backward(void* p, const double* cams, const int* res, int ncam, int spp, 
             double w[3] = {di[0] / (double)spp, di[1] / (double)spp, di[2] / (double)spp};
             Hash h;
             PRec rec;
-            SecCtx sc{{w[0], w[1], w[2]}, &G[tid]};
+            SecCtx sc{{w[0], w[1], w[2]}, &G[tid], (flags & 64) != 0};
             pixel_sample(*s, c, view, (int)(local % c.W), (int)(local / c.W), j, spp, bounces, key, h, &rec,
                          secondary ? &sc : nullptr);
             path_gradient(*s, rec, w, interior, secondary, bounces, G[tid]);
@@ -1563,7 +1565,7 @@ double or_sample_frozen(void* p, const double* cams, const int* res, int ncam, i
     Hash h;
     PRec rec;
     Grad dummy; dummy.dV.assign(3 * (size_t)s->nv, 0.0); dummy.dM.assign(s->mat.size(), 0.0);
-    SecCtx sc{{w[0], w[1], w[2]}, &dummy};
+    SecCtx sc{{w[0], w[1], w[2]}, &dummy, (flags & 64) != 0};
     pixel_sample(*s, vw.cams[view], view, px, py, j, spp, bounces, key, h, &rec, (flags & 4) ? &sc : nullptr);
     PView P; P.s = s;
     for (int k = 0; k < rec.nv; ++k) P.add_vertex(rec.v[k].face, rec.v[k].tex);
@@ -1583,7 +1585,7 @@ double or_sample_grad(void* p, const double* cams, const int* res, int ncam, int
     PRec rec;
     Grad g; g.dV.assign(3 * (size_t)s->nv, 0.0); g.dM.assign(s->mat.size(), 0.0);
     // flag 8: leave out the direct edge-endpoint terms (only the replay derivative)
-    SecCtx sc{{w[0], w[1], w[2]}, (flags & 8) ? nullptr : &g};
+    SecCtx sc{{w[0], w[1], w[2]}, (flags & 8) ? nullptr : &g, (flags & 64) != 0};
     D3 L = pixel_sample(*s, vw.cams[view], view, px, py, j, spp, bounces, key, h, &rec,
                         (flags & 4) ? &sc : nullptr);
     rgb[0] = L.x; rgb[1] = L.y; rgb[2] = L.z;

@@ -21,6 +21,7 @@ ST_GRAD_INTERIOR = 1
 ST_EDGE_PRIMARY = 2
 ST_EDGE_SECONDARY = 4
 ST_EDGE_SHADOW = 8
+ST_EDGE_SECONDARY_INTERIOR = 64
 ST_FORWARD_MEGAKERNEL = 16
 ST_COUNT_WORK = 32
 ST_ALL_GRADS = 15

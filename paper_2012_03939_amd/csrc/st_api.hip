@@ -633,7 +633,7 @@ int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_
     p.spp = spp;
     p.B = bounces;
     p.seed = seed;
-    p.flags = o.flags & 15u;
+    p.flags = o.flags & (15u | ST_EDGE_SECONDARY_INTERIOR);
     p.d_image = d_image;
     p.path_mask = o.path_mask;
     p.edge_mask = o.edge_mask;

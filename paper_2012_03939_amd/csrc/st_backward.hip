@@ -129,6 +129,7 @@ k_adjoint(BwdParams p, long long total) {
     float* const red = red_s[threadIdx.x >> 6];
     TravStack st = make_trav_stack(lds, p.spill, p.err, p.work ? p.work + 3 * WORK_ADJOINT : nullptr);
     const bool want_interior = p.flags & 1u, want_secondary = p.flags & 4u;
+    const bool sec_interior = p.flags & ST_EDGE_SECONDARY_INTERIOR;   // creases / material edges too
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long qq = blockIdx.x * (long long)blockDim.x + threadIdx.x; qq < total; qq += stride) {
         const int vw = find_view(p.qoff, p.ncam, qq);
@@ -265,7 +266,7 @@ k_adjoint(BwdParams p, long long total) {
                 const V3 wv = yv - xh;
                 const float r2 = dot(wv, wv);
                 // an edge of the shading face lies in the tangent plane: never a silhouette
-                bool ok = E.z != f && E.w != f && silhouette(S, E, xh) && r2 > 0.0f;
+                bool ok = E.z != f && E.w != f && (sec_interior || silhouette(S, E, xh)) && r2 > 0.0f;
                 V3 n = xyz(S.fnorm[f]);
                 if (sel(rfl, k) & R_FLIP) n = -n;
                 V3 ud{0.f, 0.f, 0.f}, mv{0.f, 0.f, 0.f};

@@ -2,6 +2,7 @@
 #pragma once
 
 #include "st_device.h"
+#include "../../include/shapetrace.h"
 
 namespace st {
 
