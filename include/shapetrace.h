@@ -134,6 +134,26 @@ int st_scene_subdivide(const st_scene* scene, float* out_V, int32_t* out_F, hipS
 /* Current mesh-colour resolution and number of material rows (either may be NULL). */
 int st_scene_mesh_colors_info(const st_scene* scene, int32_t* r, int64_t* ntex);
 
+/* How environment light samples pick their texel (Sec. 3.2: the map is sampled
+ * in proportion to its texels' power).  Both give the same distribution, the
+ * texel probability P_t = mean(rgb_t) * solid angle_t / sum over texels, and the
+ * same pdf; only the draw differs:
+ *   ST_ENV_SAMPLER_CDF (default): marginal row CDF on u0, then the row's
+ *   conditional CDF on u1 (guided binary searches in fp64);
+ *   ST_ENV_SAMPLER_ALIAS: Walker's alias method with Vose's construction, built
+ *   on the host in fp64 from the P_t above: bin k = floor(u0 n) (n = he we),
+ *   texel k if u1 < prob_k, else alias_k.  One 16-byte load per sample.
+ * The position inside the texel uses u2, u3 in both.  The first ALIAS request
+ * copies the map to the host, builds the table and allocates 16 n bytes (not
+ * capturable); synchronises s.  ST_ERR_INVALID_ARG for an unknown method or a
+ * scene without an environment map. */
+#define ST_ENV_SAMPLER_CDF 0
+#define ST_ENV_SAMPLER_ALIAS 1
+int st_scene_set_env_sampler(st_scene* scene, int32_t method, hipStream_t s);
+/* The alias table (host arrays of he*we entries: double prob, int32 alias), for
+ * inspection; ST_ERR_INVALID_ARG before the table is built. */
+int st_scene_env_alias_table(const st_scene* scene, double* prob, int32_t* alias);
+
 /* Forward render (Sec. 3.2, R(x, c_i)).  cams: host array of ncam cameras.
  * out: device float [sum_i width_i*height_i, 3], views concatenated, each row-major;
  * every pixel is the mean of spp path samples with a one-pixel box filter.

@@ -94,6 +94,8 @@ def lib():
         L.or_texel_index.restype = ctypes.c_longlong
         L.or_texel_of.argtypes = [P, ctypes.c_int, P]
         L.or_texel_of.restype = ctypes.c_longlong
+        L.or_scene_set_env_alias.argtypes = [P, ctypes.c_int]
+        L.or_env_alias_table.argtypes = [P, P, P]
         _lib = L
     return _lib
 
@@ -145,6 +147,17 @@ class OracleScene:
         if got != n:
             raise ValueError("oracle rejected the mesh-colour resolution")
         self.tex_res, self.ntex = int(r), n
+
+    def set_env_alias(self, on=True):
+        """Choose environment texels through the alias table (on) or the CDFs."""
+        if lib().or_scene_set_env_alias(self.h, int(bool(on))) != 0:
+            raise ValueError("scene has no environment map")
+
+    def env_alias_table(self):
+        n = self.env.shape[0] * self.env.shape[1]
+        prob, alias = np.zeros(n), np.zeros(n, np.int32)
+        lib().or_env_alias_table(self.h, _p(prob), _p(alias))
+        return prob, alias
 
     def texel_of(self, face, x):
         return int(lib().or_texel_of(self.h, int(face), _p(_f64(x))))

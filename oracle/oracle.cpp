@@ -175,6 +175,9 @@ struct Scene {
     bool has_env = false;
     std::vector<double> marg, cond, texp;   // env CDFs and texel probabilities
     double env_total = 0.0;
+    bool env_alias = false;                 // texel chosen through the alias table instead of the CDFs
+    std::vector<double> aprob;              // Walker/Vose alias table over the texels
+    std::vector<int> alias;
     std::vector<BVHNode> nodes;
     std::vector<int> perm;
 
@@ -319,9 +322,45 @@ static double env_pdf_texel(const Scene& s, int texel) {
     return s.texp[texel] / row_solid_angle(s, r);
 }
 
+// Alias table of the texel probabilities (Walker 1977, Vose 1991): bin k keeps
+// probability aprob[k] for texel k and gives the rest to texel alias[k].  Built
+// with two stacks in index order, taking from their tops, in fp64.
+static void build_alias(Scene& s) {
+    const int n = s.he * s.we;
+    s.aprob.assign(n, 1.0);
+    s.alias.resize(n);
+    std::vector<double> q(n);
+    std::vector<int> small, large;
+    for (int i = 0; i < n; ++i) {
+        s.alias[i] = i;
+        q[i] = s.texp[i] * n;
+        if (q[i] < 1.0) small.push_back(i); else large.push_back(i);
+    }
+    while (!small.empty() && !large.empty()) {
+        const int a = small.back(), l = large.back();
+        small.pop_back();
+        large.pop_back();
+        s.aprob[a] = q[a];
+        s.alias[a] = l;
+        q[l] = (q[l] + q[a]) - 1.0;
+        if (q[l] < 1.0) small.push_back(l); else large.push_back(l);
+    }
+}
+
 static int env_sample(const Scene& s, const double u[4], D3& dir, double& pdf) {
-    int r = cdf_find(s.marg.data(), s.he, u[0]);
-    int c = cdf_find(&s.cond[(size_t)r * (s.we + 1)], s.we, u[1]);
+    int r, c;
+    if (s.env_alias) {
+        // bin by u0, texel of the bin or its alias by u1
+        const int n = s.he * s.we;
+        int k = (int)(u[0] * n);
+        if (k > n - 1) k = n - 1;
+        const int texel = u[1] < s.aprob[k] ? k : s.alias[k];
+        r = texel / s.we;
+        c = texel % s.we;
+    } else {
+        r = cdf_find(s.marg.data(), s.he, u[0]);
+        c = cdf_find(&s.cond[(size_t)r * (s.we + 1)], s.we, u[1]);
+    }
     double phi = 2.0 * PI * (c + u[2]) / s.we;
     double ct = std::cos(PI * r / s.he), cb = std::cos(PI * (r + 1) / s.he);
     double cth = ct - u[3] * (ct - cb);
@@ -1358,6 +1397,21 @@ long long or_scene_set_texels(void* p, int r, const float* texels) {
 }
 
 long long or_texel_index(int r, long long t, double alpha, double beta) { return texel_index(r, t, alpha, beta); }
+
+// Environment texels chosen through the alias table (on) or the CDFs (off, the default).
+int or_scene_set_env_alias(void* p, int on) {
+    Scene* s = (Scene*)p;
+    if (!s->has_env) return -1;
+    s->env_alias = on != 0;
+    if (s->env_alias && s->aprob.empty()) build_alias(*s);
+    return 0;
+}
+
+void or_env_alias_table(void* p, double* prob, int* alias) {
+    Scene* s = (Scene*)p;
+    if (s->aprob.empty()) build_alias(*s);
+    for (size_t i = 0; i < s->aprob.size(); ++i) { prob[i] = s->aprob[i]; alias[i] = s->alias[i]; }
+}
 
 long long or_texel_of(void* p, int f, const double* x) { return texel_of(*(Scene*)p, f, D3(x[0], x[1], x[2])); }
 

@@ -25,9 +25,11 @@ ST_EDGE_SECONDARY_INTERIOR = 64
 ST_FORWARD_MEGAKERNEL = 16
 ST_COUNT_WORK = 32
 ST_ALL_GRADS = 15
+ST_ENV_SAMPLER_CDF = 0
+ST_ENV_SAMPLER_ALIAS = 1
 
 EXPORTED = ["st_render_opts_default", "st_scene_create", "st_scene_update", "st_scene_set_mesh_colors",
-            "st_scene_mesh_colors_info", "st_scene_subdivide", "st_render", "st_render_backward",
+            "st_scene_mesh_colors_info", "st_scene_subdivide", "st_scene_set_env_sampler", "st_scene_env_alias_table", "st_render", "st_render_backward",
             "st_render_batch", "st_autotune", "st_check_errors", "st_read_work", "st_scene_info", "st_scene_edges", "st_scene_lbvh",
             "st_trace_rays", "st_profile_enable", "st_profile_read", "st_scene_destroy", "st_last_error",
             "st_version"]
@@ -67,6 +69,8 @@ def load(path: str = LIB_PATH):
     L.st_scene_set_mesh_colors.argtypes = [P, I32, P, P]
     L.st_scene_mesh_colors_info.argtypes = [P, P, P]
     L.st_scene_subdivide.argtypes = [P, P, P, P]
+    L.st_scene_set_env_sampler.argtypes = [P, I32, P]
+    L.st_scene_env_alias_table.argtypes = [P, P, P]
     L.st_render.argtypes = [P, P, I32, I32, I32, U32, ctypes.POINTER(StOpts), P, P]
     L.st_render_backward.argtypes = [P, P, I32, I32, I32, U32, ctypes.POINTER(StOpts), P, P, P, P]
     L.st_render_batch.argtypes = [P, I32, P, P, I32, I32, I32, U32, ctypes.POINTER(StOpts), P, P]
@@ -167,6 +171,7 @@ class GPUScene:
         info = (ctypes.c_int64 * 6)()
         _check(L.st_scene_info(self.h, info))
         self.ne = int(info[2])
+        self.he, self.we = int(info[4]), int(info[5])
         self.tex_res, self.ntex = 0, self.nf
 
     def subdivide(self):
@@ -189,6 +194,17 @@ class GPUScene:
         rr, nt = ctypes.c_int32(), ctypes.c_int64()
         _check(load().st_scene_mesh_colors_info(self.h, ctypes.byref(rr), ctypes.byref(nt)))
         self.tex_res, self.ntex = int(rr.value), int(nt.value)
+
+    def set_env_sampler(self, method: int):
+        """ST_ENV_SAMPLER_CDF (default) or ST_ENV_SAMPLER_ALIAS for environment texels."""
+        _check(load().st_scene_set_env_sampler(self.h, int(method), _stream()))
+
+    def env_alias_table(self):
+        """(prob float64 [he*we], alias int32 [he*we]) of the built alias table."""
+        n = self.he * self.we
+        prob, alias = np.zeros(n), np.zeros(n, np.int32)
+        _check(load().st_scene_env_alias_table(self.h, prob.ctypes.data, alias.ctypes.data))
+        return prob, alias
 
     @classmethod
     def from_scene(cls, sc):

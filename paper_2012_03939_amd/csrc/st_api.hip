@@ -516,6 +516,8 @@ int st_scene_create(const float* V, int32_t nv, const int32_t* F, int32_t nf, co
     h.eglog = guide_log2(d.ne); h.mglog = guide_log2(he); h.cglog = guide_log2(we);
     h.nv = nv; h.nf = nf; h.nl = nl; h.he = he; h.we = we; h.ne = d.ne; h.has_env = d.has_env ? 1 : 0;
     h.tex_res = 0;
+    h.ealias = nullptr;
+    h.env_alias = 0;
     h.scene_id = scene_id;
     HIPCHK2(hipMemcpyAsync(d.dscene, &h, sizeof(DevScene), hipMemcpyHostToDevice, s));
     HIPCHK2(hipStreamSynchronize(s));
@@ -570,6 +572,89 @@ int st_scene_set_mesh_colors(st_scene* sc, int32_t r, const float* texels, hipSt
     d.hscene.tex_res = r;
     HIPCHK(hipMemcpyAsync(d.dscene, &d.hscene, sizeof(DevScene), hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
+    return ST_OK;
+}
+
+// Texel probabilities of the environment map, as the CDFs and the pdf use them:
+// mean of the three channels times the texel's solid angle, over the total;
+// rows and the total summed in index order.  Then Vose's construction of the
+// alias table: bins below their share on one stack, the rest on another, in
+// index order; each step takes the top of both.
+static void build_env_alias(const std::vector<float>& env, int he, int we, std::vector<EnvAlias>& out) {
+    const double PI = 3.14159265358979323846;
+    const size_t n = (size_t)he * we;
+    std::vector<double> w(n), rows(he);
+    for (int r = 0; r < he; ++r) {
+        const double dom = (2.0 * PI / we) * (std::cos(PI * r / he) - std::cos(PI * (r + 1) / he));
+        double rs = 0.0;
+        for (int c = 0; c < we; ++c) {
+            const float* t = &env[3 * ((size_t)r * we + c)];
+            const double m = ((double)t[0] + (double)t[1] + (double)t[2]) / 3.0;
+            w[(size_t)r * we + c] = m * dom;
+            rs += m * dom;
+        }
+        rows[r] = rs;
+    }
+    double tot = 0.0;
+    for (int r = 0; r < he; ++r) tot += rows[r];
+    out.assign(n, EnvAlias{1.0, 0, 0});
+    std::vector<double> share(n);
+    std::vector<int> lo, hi;
+    lo.reserve(n);
+    hi.reserve(n);
+    for (size_t i = 0; i < n; ++i) {
+        out[i].alias = (int)i;
+        share[i] = (w[i] / tot) * (double)n;
+        (share[i] < 1.0 ? lo : hi).push_back((int)i);
+    }
+    while (!lo.empty() && !hi.empty()) {
+        const int a = lo.back(), b = hi.back();
+        lo.pop_back();
+        hi.pop_back();
+        out[a].prob = share[a];
+        out[a].alias = b;
+        share[b] = (share[b] + share[a]) - 1.0;
+        (share[b] < 1.0 ? lo : hi).push_back(b);
+    }
+}
+
+int st_scene_set_env_sampler(st_scene* sc, int32_t method, hipStream_t s) {
+    int rc = check_scene(sc);
+    if (rc) return rc;
+    SceneDev& d = sc->d;
+    if (method != ST_ENV_SAMPLER_CDF && method != ST_ENV_SAMPLER_ALIAS)
+        return fail(ST_ERR_INVALID_ARG, "unknown environment sampler");
+    if (!d.has_env) return fail(ST_ERR_INVALID_ARG, "scene has no environment map");
+    HIPCHK(hipStreamSynchronize(s));
+    if (method == ST_ENV_SAMPLER_ALIAS && !d.ealias) {
+        const size_t n = (size_t)d.he * d.we;
+        std::vector<float> env(3 * n);
+        HIPCHK(hipMemcpyAsync(env.data(), d.env, sizeof(float) * 3 * n, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        std::vector<EnvAlias> tab;
+        build_env_alias(env, d.he, d.we, tab);
+        if (dalloc(&d.ealias, n)) return fail(ST_ERR_OOM, "environment alias table");
+        HIPCHK(hipMemcpyAsync(d.ealias, tab.data(), sizeof(EnvAlias) * n, hipMemcpyHostToDevice, s));
+    }
+    d.hscene.ealias = d.ealias;
+    d.hscene.env_alias = method == ST_ENV_SAMPLER_ALIAS ? 1 : 0;
+    HIPCHK(hipMemcpyAsync(d.dscene, &d.hscene, sizeof(DevScene), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return ST_OK;
+}
+
+int st_scene_env_alias_table(const st_scene* sc, double* prob, int32_t* alias) {
+    int rc = check_scene(sc);
+    if (rc) return rc;
+    const SceneDev& d = sc->d;
+    if (!d.ealias) return fail(ST_ERR_INVALID_ARG, "no alias table (st_scene_set_env_sampler with ST_ENV_SAMPLER_ALIAS first)");
+    const size_t n = (size_t)d.he * d.we;
+    std::vector<EnvAlias> tab(n);
+    HIPCHK(hipMemcpy(tab.data(), d.ealias, sizeof(EnvAlias) * n, hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < n; ++i) {
+        if (prob) prob[i] = tab[i].prob;
+        if (alias) alias[i] = tab[i].alias;
+    }
     return ST_OK;
 }
 
@@ -865,7 +950,8 @@ void st_scene_destroy(st_scene* sc) {
     void* ptrs[] = {d.V, d.F, d.mat, d.lights, d.env, d.fnorm, d.bmin, d.bmax, d.cen, d.bounds, d.mkeys[0], d.mkeys[1],
                     d.mvals[0], d.mvals[1], d.rs_hist, d.keys64, d.child, d.parent, d.aabb, d.refit_cnt, d.nodes4, d.flag4, d.id4,
                     d.tri, d.edges, d.edge_w, d.eguide, d.mguide, d.cguide, d.ecdf, d.etotal_d, d.etotal_f, d.row_dom, d.rowcos, d.cond, d.marg,
-                    d.env_rows, d.env_total, d.texpdf, d.err, d.work, d.dscene, d.vf_off, d.vf_idx, d.facc, d.macc, d.fe};
+                    d.env_rows, d.env_total, d.texpdf, d.err, d.work, d.dscene, d.vf_off, d.vf_idx, d.facc, d.macc, d.fe,
+                    d.ealias};
     for (void* p : ptrs)
         if (p) hipFree(p);
     sc->Lbuf.release(); sc->qbuf.release(); sc->spillbuf.release(); sc->primbuf.release();

@@ -105,6 +105,14 @@ constexpr uint32_t FNV_INIT = 0x811C9DC5u;
 // ---------------------------------------------------------------------------
 // scene as the kernels see it
 // ---------------------------------------------------------------------------
+// one bin of the environment alias table: texel k of bin k is kept when the
+// second uniform is below prob, otherwise the bin's alias texel is taken
+struct __align__(16) EnvAlias {
+    double prob;
+    int alias;
+    int pad;
+};
+
 struct DevScene {
     const float* V;       // [nv,3]
     const int* F;         // [nf,3]
@@ -124,6 +132,8 @@ struct DevScene {
     const int* eguide;    // guide table of ecdf, 2^eglog entries
     const int* mguide;    // guide table of the env marginal CDF, 2^mglog entries
     const int* cguide;    // guide tables of the env conditional CDFs, 2^cglog entries per row
+    const EnvAlias* ealias; // [he*we] alias table of the texel probabilities, used when env_alias
+    int env_alias;
     int eglog, mglog, cglog;
     int nv, nf, nl, he, we, ne, has_env;
     int tex_res;          // mesh-colours resolution r: mat has nf (r+1)(r+2)/2 rows
@@ -584,9 +594,20 @@ __device__ __forceinline__ int env_texel_of(const DevScene& S, V3 d) {
 __device__ __forceinline__ V3 env_rgb(const DevScene& S, int t) { return ld3(S.env + 3 * (size_t)t); }
 
 __device__ __forceinline__ int env_sample(const DevScene& S, float4 u, V3& dir, float& pdf) {
-    const int r = cdf_guided(S.marg, S.he, S.mguide, S.mglog, (double)u.x);
-    const int c = cdf_guided(S.cond + (size_t)r * (S.we + 1), S.we, S.cguide + ((size_t)r << S.cglog), S.cglog,
-                             (double)u.y);
+    int r, c;
+    if (S.env_alias) {
+        // bin from the first uniform, the bin's texel or its alias from the second
+        const int n = S.he * S.we;
+        const int k = min((int)((double)u.x * (double)n), n - 1);
+        const EnvAlias e = S.ealias[k];
+        const int t = (double)u.y < e.prob ? k : e.alias;
+        r = t / S.we;
+        c = t - r * S.we;
+    } else {
+        r = cdf_guided(S.marg, S.he, S.mguide, S.mglog, (double)u.x);
+        c = cdf_guided(S.cond + (size_t)r * (S.we + 1), S.we, S.cguide + ((size_t)r << S.cglog), S.cglog,
+                       (double)u.y);
+    }
     const float phi = 2.0f * PI_F * ((float)c + u.z) / (float)S.we;
     // cos(theta) uniform between the row's bounds; 1 -+ cos(theta) are taken
     // from the per-row tables of 1 - cos and 1 + cos so that sin(theta) keeps

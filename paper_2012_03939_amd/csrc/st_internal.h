@@ -69,6 +69,7 @@ struct SceneDev {
     double* env_rows = nullptr;
     double* env_total = nullptr;
     float* texpdf = nullptr;
+    EnvAlias* ealias = nullptr;              // [he*we], built on the first request for alias sampling
     uint32_t* err = nullptr;                 // device error word
     unsigned long long* work = nullptr;      // traversal work counters [3]
     DevScene* dscene = nullptr;              // device copy of the kernel view

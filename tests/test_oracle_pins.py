@@ -236,6 +236,77 @@ def test_env_sample_direction_inside_texel():
     assert misses <= 3    # only exact texel borders may round across
 
 
+def _texel_probs(env):
+    """Texel probabilities written out from their definition (power x solid angle)."""
+    he, we = env.shape[:2]
+    w = env.astype(np.float64).mean(axis=2)
+    dom = np.array([(2 * np.pi / we) * (math.cos(np.pi * r / he) - math.cos(np.pi * (r + 1) / he)) for r in range(he)])
+    P = (w * dom[:, None]).ravel()
+    return P / P.sum(), dom
+
+
+def test_env_alias_table_reproduces_texel_probabilities():
+    """Walker's alias table: bin k keeps prob_k of its 1/n for texel k and hands
+    1 - prob_k to alias_k, so summing the pieces over all bins must give back
+    every texel's probability; a dropped leftover or a wrong stack update fails."""
+    rng = np.random.default_rng(11)
+    for he, we in [(16, 32), (7, 5), (1, 1), (64, 128)]:
+        env = S.gaussian_lobe_envmap(rng, we, he) if he > 1 else np.full((1, 1, 3), 2.0, np.float32)
+        sc = _tiny_scene(env)
+        prob, alias = sc.env_alias_table()
+        n = he * we
+        P, _ = _texel_probs(env)
+        assert ((prob >= 0) & (prob <= 1)).all() and ((alias >= 0) & (alias < n)).all()
+        back = prob.copy()
+        np.add.at(back, alias, 1.0 - prob)
+        back -= np.where(alias == np.arange(n), 1.0 - prob, 0.0)    # a bin aliased to itself gives nothing away
+        assert np.abs(back / n - P).max() < 1e-12 * max(P.max(), 1.0 / n)
+        # a bin below its share is never the alias of another bin unless it was topped up first
+        assert (prob[alias == np.arange(n)] == 1.0).all()
+
+
+def test_env_alias_sampling_histogram_and_pdf():
+    """With the alias table on, the texel histogram matches the texel
+    probabilities, the pdf is the same, and directions stay inside their texel."""
+    from scipy import stats
+    rng = np.random.default_rng(4)
+    env = S.gaussian_lobe_envmap(rng, 32, 16)
+    sc = _tiny_scene(env)
+    sc.set_env_alias(True)
+    he, we = env.shape[:2]
+    P, dom = _texel_probs(env)
+    N = 50000
+    counts = np.zeros(he * we)
+    misses = 0
+    for u in rng.random((N, 4)):
+        t, d, pdf = sc.env_sample(u)
+        counts[t] += 1
+        assert abs(pdf - P[t] / dom[t // we]) <= 1e-9 * pdf
+        misses += sc.env_texel(d) != t
+    assert misses <= 20
+    keep = P * N > 20
+    exp = P[keep] * N
+    obs = counts[keep]
+    exp *= obs.sum() / exp.sum()
+    assert stats.chisquare(obs, exp).pvalue > 1e-4
+
+
+def test_env_alias_exhaustive_two_by_two():
+    """2 x 2 map: the probability of each texel over an exact grid of (u0, u1)
+    equals its texel probability up to the grid step."""
+    env = np.array([[[1, 1, 1], [3, 3, 3]], [[0.5, 0.5, 0.5], [6, 6, 6]]], np.float32)
+    sc = _tiny_scene(env)
+    sc.set_env_alias(True)
+    P, _ = _texel_probs(env)
+    G = 400
+    hits = np.zeros(4)
+    for i in range(G):
+        for j in range(G):
+            t, _, _ = sc.env_sample([(i + 0.5) / G, (j + 0.5) / G, 0.5, 0.5])
+            hits[t] += 1
+    assert np.abs(hits / G ** 2 - P).max() <= 2.0 / G
+
+
 # --------------------------------------------------------------------------
 # intersection and acceleration structure
 # --------------------------------------------------------------------------
