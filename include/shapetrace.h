@@ -199,9 +199,15 @@ int st_check_errors(st_scene* scene, hipStream_t s);
 /* Introspection for tests (device outputs, caller-allocated):
  *  st_scene_info: host int64 [6] = nv, nf, number of edges, nl, he, we.
  *  st_scene_edges: int32 [ne,4] = (va < vb, f1, f2 or -1), canonical order.
- *  st_scene_lbvh: keys uint64 [nf] (morton << 32 | face, ascending), child int32
- *    [nf-1,2] (bit 31 marks a leaf index), parent int32 [2nf-1] (internal nodes,
- *    then leaves; -1 at the root), aabb float [2nf-1,6] (min xyz, max xyz).
+ *  st_scene_lbvh: keys uint64 [nf] (morton << 32 | face, ascending; 10 bits per
+ *    axis over cubic cells, 1024 along the longest extent of the face-centre
+ *    box), child int32 [nf-1,2] (bit 31 marks a leaf index), parent int32
+ *    [2nf-1] (internal nodes, then leaves; -1 at the root), aabb float [2nf-1,6]
+ *    (min xyz, max xyz).  The tree is the Karras radix tree over the keys after
+ *    two bottom-up passes of treelet restructuring (7-entry treelets re-arranged
+ *    to their least SAH cost, triangle cost = box area, internal node cost =
+ *    1.2 x box area + children); leaves and the root box are those of the radix
+ *    tree.  Deterministic: a function of the mesh alone.
  *  st_trace_rays: closest hit of n rays o,d (float [n,3]) with t > tmin, through
  *    the BVH or by brute force; out_face int32 [n] (-1 miss), out_t float [n]. */
 int st_scene_info(const st_scene* scene, int64_t* out6);

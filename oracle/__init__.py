@@ -74,6 +74,7 @@ def lib():
         L.or_camera_ray.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, P, P]
         L.or_project.argtypes = [P, ctypes.c_int, ctypes.c_int, P, P]
         L.or_lbvh.argtypes = [P, ctypes.c_int, P, ctypes.c_int, P, P, P, P]
+        L.or_bvh_treelets.argtypes = [P, ctypes.c_int, P, ctypes.c_int, ctypes.c_int, P, P, P, P]
         L.or_render.argtypes = [P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint, P,
                                 ctypes.c_longlong, P, P, ctypes.c_int]
         L.or_backward.argtypes = [P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint,
@@ -343,7 +344,12 @@ def project(cam, v):
     return out
 
 
-def lbvh(V, F):
+TREELET_ROUNDS = 2      # restructuring passes the GPU builder applies to the Karras tree
+
+
+def lbvh(V, F, treelet_rounds=0):
+    """Karras tree over the sorted Morton keys (treelet_rounds=0), or that tree
+    after bottom-up treelet restructuring passes."""
     V = np.ascontiguousarray(V, np.float32)
     F = np.ascontiguousarray(F, np.int32)
     n = F.shape[0]
@@ -351,5 +357,9 @@ def lbvh(V, F):
     child = np.zeros((max(n - 1, 0), 2), np.int32)
     parent = np.zeros(2 * n - 1, np.int32)
     aabb = np.zeros((2 * n - 1, 6), np.float32)
-    lib().or_lbvh(_p(V), V.shape[0], _p(F), n, _p(keys), _p(child), _p(parent), _p(aabb))
+    if treelet_rounds:
+        lib().or_bvh_treelets(_p(V), V.shape[0], _p(F), n, int(treelet_rounds), _p(keys), _p(child), _p(parent),
+                              _p(aabb))
+    else:
+        lib().or_lbvh(_p(V), V.shape[0], _p(F), n, _p(keys), _p(child), _p(parent), _p(aabb))
     return keys, child, parent, aabb

@@ -1285,8 +1285,12 @@ static void lbvh_reference(const float* V, int nv, const int* F, int nf, uint64_
             ce[3 * f + k] = cc;
             lo[k] = std::min(lo[k], cc); hi[k] = std::max(hi[k], cc);
         }
+    // one scale for all three axes (cells are cubes): 1024 cells along the
+    // longest extent of the centroid box
+    double ext = 0.0;
+    for (int k = 0; k < 3; ++k) ext = std::max(ext, (double)hi[k] - (double)lo[k]);
     float sc[3];
-    for (int k = 0; k < 3; ++k) sc[k] = hi[k] > lo[k] ? (float)(1024.0 / ((double)hi[k] - (double)lo[k])) : 0.0f;
+    for (int k = 0; k < 3; ++k) sc[k] = ext > 0.0 ? (float)(1024.0 / ext) : 0.0f;
     std::vector<uint64_t> kv(nf);
     for (int f = 0; f < nf; ++f) {
         uint32_t q[3];
@@ -1355,6 +1359,166 @@ static void lbvh_reference(const float* V, int nv, const int* F, int nf, uint64_
             b[k] = std::min(cb[0][k], cb[1][k]);
             b[3 + k] = std::max(cb[0][3 + k], cb[1][3 + k]);
         }
+    }
+}
+
+// --------------------------------------------------------------------------
+// Treelet restructuring of the binary tree (Karras and Aila, HPG 2013: small
+// treelets re-arranged into their SAH-optimal topology, bottom-up).  Stated
+// here as a definition, in float32 like the tree's boxes, so that every
+// comparison is taken in the same precision as on the GPU:
+//  - SAH cost of a subtree: a triangle leaf costs the area of its box; an
+//    internal node costs C_INNER * area(box) + cost(left) + cost(right);
+//    area(b) = 2 ((dx dy + dy dz) + dz dx).
+//  - Every internal node r is visited after both of its subtrees (post-order).
+//    A node with fewer than TREELET_LEAVES triangles below it is left as it is
+//    (its cost: C_INNER * area(box) + (cost(child0) + cost(child1))).
+//    Otherwise its treelet: the list starts as (child0, child1); while the list has fewer
+//    than TREELET_LEAVES entries and holds an internal node, the internal entry
+//    of largest box area (first in list order on ties) is removed and its two
+//    children appended.  The removed nodes, r first, are the treelet's
+//    internal nodes.
+//  - Over the k list entries (bit j of a subset = entry j), opt({j}) = cost of
+//    entry j and, for |S| >= 2, opt(S) = C_INNER * area(union of S) +
+//    min over P (opt(P) + opt(S \ P)), P = lowest bit of S plus a proper subset
+//    `sub` of the rest, sub taken in the order (rest-1)&rest, (sub-1)&rest, ..., 0;
+//    the first strict minimum wins.
+//  - Rebuild: the internal subsets of the optimal tree in preorder (a stack:
+//    pop S, record it, push S\P if internal, then P if internal) take the ids
+//    r, then the other treelet internal nodes in ascending id order; node S
+//    gets children (P, S \ P), box = union of its entries, cost = opt(S).
+// Rounds repeat the whole bottom-up pass.
+// --------------------------------------------------------------------------
+static const float C_INNER = 1.2f;
+static const int TREELET_LEAVES = 7;
+
+static inline float box_area(const float* b) {
+    float dx = b[3] - b[0], dy = b[4] - b[1], dz = b[5] - b[2];
+    return 2.0f * ((dx * dy + dy * dz) + dz * dx);
+}
+
+struct TreeRef {
+    int n;
+    int* child;
+    int* parent;
+    float* aabb;
+    std::vector<float> cost;      // per internal node
+    std::vector<int> leaves;      // triangles below each internal node
+    static const int LEAF = (int)0x80000000;
+    float* box(int code) { return aabb + 6 * ((code & LEAF) ? (size_t)(n - 1) + (code & 0x7FFFFFFF) : (size_t)code); }
+    int pidx(int code) const { return (code & LEAF) ? (n - 1) + (code & 0x7FFFFFFF) : code; }
+    float code_cost(int code) { return (code & LEAF) ? box_area(box(code)) : cost[code]; }
+    int code_leaves(int code) const { return (code & LEAF) ? 1 : leaves[code]; }
+};
+
+static void treelet_node(TreeRef& T, int r) {
+    const int LEAF = TreeRef::LEAF;
+    const int c0 = T.child[2 * r], c1 = T.child[2 * r + 1];
+    T.leaves[r] = T.code_leaves(c0) + T.code_leaves(c1);
+    if (T.leaves[r] < TREELET_LEAVES) {
+        T.cost[r] = C_INNER * box_area(T.box(r)) + (T.code_cost(c0) + T.code_cost(c1));
+        return;
+    }
+    std::vector<int> ent = {c0, c1};
+    std::vector<int> inner = {r};
+    while ((int)ent.size() < TREELET_LEAVES) {
+        int bi = -1;
+        float ba = -1.0f;
+        for (int i = 0; i < (int)ent.size(); ++i)
+            if (!(ent[i] & LEAF)) {
+                float a = box_area(T.box(ent[i]));
+                if (a > ba) { ba = a; bi = i; }
+            }
+        if (bi < 0) break;
+        int c = ent[bi];
+        inner.push_back(c);
+        ent.erase(ent.begin() + bi);
+        ent.push_back(T.child[2 * c]);
+        ent.push_back(T.child[2 * c + 1]);
+    }
+    const int k = (int)ent.size(), full = (1 << k) - 1;
+    std::vector<float> opt(1 << k), area(1 << k);
+    std::vector<int> part(1 << k, 0);
+    for (int S = 1; S <= full; ++S) {
+        float u[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+        for (int j = 0; j < k; ++j)
+            if (S >> j & 1) {
+                const float* bb = T.box(ent[j]);
+                for (int q = 0; q < 3; ++q) { u[q] = std::min(u[q], bb[q]); u[3 + q] = std::max(u[3 + q], bb[3 + q]); }
+            }
+        area[S] = box_area(u);
+    }
+    for (int j = 0; j < k; ++j) opt[1 << j] = T.code_cost(ent[j]);
+    for (int size = 2; size <= k; ++size)
+        for (int S = 1; S <= full; ++S) {
+            if (__builtin_popcount(S) != size) continue;
+            const int lb = S & -S, rest = S ^ lb;
+            float best = INFINITY;
+            int bp = 0;
+            int sub = (rest - 1) & rest;
+            for (;;) {
+                const int P = lb | sub;
+                const float c = opt[P] + opt[S ^ P];
+                if (c < best) { best = c; bp = P; }
+                if (sub == 0) break;
+                sub = (sub - 1) & rest;
+            }
+            opt[S] = C_INNER * area[S] + best;
+            part[S] = bp;
+        }
+    // preorder of the optimal tree's internal subsets
+    std::vector<int> pre, st = {full};
+    while (!st.empty()) {
+        int S = st.back();
+        st.pop_back();
+        pre.push_back(S);
+        const int P = part[S], Q = S ^ P;
+        if (__builtin_popcount(Q) > 1) st.push_back(Q);
+        if (__builtin_popcount(P) > 1) st.push_back(P);
+    }
+    std::vector<int> ids(inner.begin() + 1, inner.end());
+    std::sort(ids.begin(), ids.end());
+    ids.insert(ids.begin(), r);
+    auto code_of = [&](int X) -> int {
+        if (__builtin_popcount(X) == 1) return ent[__builtin_ctz(X)];
+        for (size_t i = 0; i < pre.size(); ++i) if (pre[i] == X) return ids[i];
+        return -1;
+    };
+    for (size_t i = 0; i < pre.size(); ++i) {
+        const int S = pre[i], id = ids[i], P = part[S], Q = S ^ P;
+        const int a = code_of(P), c = code_of(Q);
+        T.child[2 * id] = a;
+        T.child[2 * id + 1] = c;
+        T.parent[T.pidx(a)] = id;
+        T.parent[T.pidx(c)] = id;
+        T.cost[id] = opt[S];
+        int cnt = 0;
+        for (int j = 0; j < k; ++j) if (S >> j & 1) cnt += T.code_leaves(ent[j]);
+        T.leaves[id] = cnt;
+    }
+    // boxes bottom-up over the rebuilt nodes (reverse preorder)
+    for (size_t i = pre.size(); i-- > 0;) {
+        const int id = ids[i];
+        float* b = T.box(id);
+        const float* b0 = T.box(T.child[2 * id]);
+        const float* b1 = T.box(T.child[2 * id + 1]);
+        for (int q = 0; q < 3; ++q) { b[q] = std::min(b0[q], b1[q]); b[3 + q] = std::max(b0[3 + q], b1[3 + q]); }
+    }
+}
+
+static void treelet_rounds(int n, int* child, int* parent, float* aabb, int rounds) {
+    if (n < 2) return;
+    TreeRef T{n, child, parent, aabb, std::vector<float>(n - 1, 0.0f), std::vector<int>(n - 1, 0)};
+    for (int rd = 0; rd < rounds; ++rd) {
+        // post-order of the current tree
+        std::vector<int> order, st{0};
+        while (!st.empty()) {
+            int i = st.back();
+            st.pop_back();
+            order.push_back(i);
+            for (int c = 0; c < 2; ++c) if (!(child[2 * i + c] & TreeRef::LEAF)) st.push_back(child[2 * i + c]);
+        }
+        for (auto it = order.rbegin(); it != order.rend(); ++it) treelet_node(T, *it);
     }
 }
 
@@ -1496,6 +1660,13 @@ void or_project(const double* cam, int W, int H, const double* v, double* out) {
 void or_lbvh(const float* V, int nv, const int* F, int nf, unsigned long long* keys, int* child, int* parent,
              float* aabb) {
     lbvh_reference(V, nv, F, nf, (uint64_t*)keys, child, parent, aabb);
+}
+
+// The Karras tree after `rounds` bottom-up treelet-restructuring passes.
+void or_bvh_treelets(const float* V, int nv, const int* F, int nf, int rounds, unsigned long long* keys, int* child,
+                     int* parent, float* aabb) {
+    lbvh_reference(V, nv, F, nf, (uint64_t*)keys, child, parent, aabb);
+    treelet_rounds(nf, child, parent, aabb, rounds);
 }
 
 // Forward render.  pix: npix pairs (view, y*W+x), or NULL for every pixel of

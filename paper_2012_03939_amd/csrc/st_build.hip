@@ -53,13 +53,16 @@ __global__ void k_bounds(const float4* __restrict__ cen, int nf, float* out /* l
             }
         __syncthreads();
     }
-    if (t == 0)
+    if (t == 0) {
+        // one scale for all axes (cubic cells): 1024 cells along the longest extent
+        double ext = 0.0;
+        for (int k = 0; k < 3; ++k) ext = fmax(ext, (double)smax[k][0] - (double)smin[k][0]);
         for (int k = 0; k < 3; ++k) {
-            const float l = smin[k][0], h = smax[k][0];
-            out[k] = l;
-            out[3 + k] = h;
-            out[6 + k] = h > l ? (float)(1024.0 / ((double)h - (double)l)) : 0.0f;
+            out[k] = smin[k][0];
+            out[3 + k] = smax[k][0];
+            out[6 + k] = ext > 0.0 ? (float)(1024.0 / ext) : 0.0f;
         }
+    }
 }
 
 __device__ __forceinline__ uint32_t spread10(uint32_t v) {
@@ -256,13 +259,277 @@ __global__ void k_refit(const int* __restrict__ parent, const int* __restrict__ 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Treelet restructuring of the Karras tree (Karras and Aila, HPG 2013), one
+// bottom-up pass per launch.  Every internal node r with at least TL_LEAVES
+// triangles below it, once both of its subtrees are final (second arrival at
+// r's counter, as in the refit), becomes the root of a treelet of TL_LEAVES
+// entries (smaller nodes only get their triangle count and SAH cost, each by
+// the lane that reached it): starting from r's two children, the
+// internal entry with the largest box area (first in list order on ties) is
+// replaced by its two children, appended at the end of the list.  The entries
+// are re-arranged into the binary tree of least SAH cost (a triangle leaf costs
+// its box area, an internal node C_INNER * area + the costs of its children),
+// found by dynamic programming over the 2^k - 1 subsets of entries; the
+// treelet's internal nodes are reused (r stays the root, the others in
+// ascending id order along the preorder of the new tree).  All comparisons are
+// in float32 with contraction off, in a fixed order, so the tree is a function
+// of the mesh alone, not of the wave schedule.
+//
+// One wave owns a treelet at a time: lane 0 forms it and writes the rebuilt
+// nodes, the 64 lanes share the subset DP (subsets L and L + 64 per lane, one
+// subset size per step).  Every access to tree data that another wave may
+// write during the pass is an agent-scope atomic (coherent across the XCDs'
+// L2s without flushing them), so the hand-off at a node's counter needs only
+// the wave's own outstanding stores drained before the increment
+// (handoff_release), not an L2 write-back and invalidate per level.
+// ---------------------------------------------------------------------------
+constexpr int TL_LEAVES = 7;
+constexpr float TL_C_INNER = 1.2f;
+constexpr int TL_BLOCK = 256;
+constexpr int TL_WAVES = TL_BLOCK / 64;
+constexpr int TL_GUARD = 1 << 16;
+
+__device__ __forceinline__ int ald_i(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void ast_i(int* p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void ast_f(float* p, float v) {
+    __hip_atomic_store((uint32_t*)p, __float_as_uint(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float tl_area(const float* b) {
+#pragma clang fp contract(off)
+    const float dx = b[3] - b[0], dy = b[4] - b[1], dz = b[5] - b[2];
+    return 2.0f * ((dx * dy + dy * dz) + dz * dx);
+}
+__device__ __forceinline__ void handoff_release() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);     // no compiler motion across this point
+    __builtin_amdgcn_s_waitcnt(0);               // every store of this wave has completed
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+struct TreeletLds {
+    float opt[128];
+    int part[128];
+    int ent[TL_LEAVES + 1];
+    int ids[TL_LEAVES];
+    float box[TL_LEAVES + 1][6];
+    float cost[TL_LEAVES + 1];
+    int leaves[TL_LEAVES + 1];
+    int k;
+};
+
+__device__ void treelet_restructure(int r, int lane, TreeletLds& T, int* child, int* parent, float* aabb,
+                                    float* tcost, int* tleaves, int n) {
+#pragma clang fp contract(off)
+    auto bidx = [n](int code) -> size_t {
+        return (code & (int)LEAF_BIT) ? (size_t)(n - 1) + (code & 0x7FFFFFFF) : (size_t)code;
+    };
+    wave_sync_lds();
+    if (lane == 0) {
+        int ent[TL_LEAVES + 1], ids[TL_LEAVES];
+        float box[TL_LEAVES + 1][6], area[TL_LEAVES + 1];
+        int k = 2, ni = 1;
+        ids[0] = r;
+        for (int a = 0; a < 2; ++a) {
+            ent[a] = ald_i(child + 2 * r + a);
+            for (int q = 0; q < 6; ++q) box[a][q] = aload(aabb + 6 * bidx(ent[a]) + q);
+            area[a] = tl_area(box[a]);
+        }
+        while (k < TL_LEAVES) {
+            int bi = -1;
+            float ba = -1.0f;
+            for (int i = 0; i < k; ++i)
+                if (!(ent[i] & (int)LEAF_BIT) && area[i] > ba) { ba = area[i]; bi = i; }
+            if (bi < 0) break;
+            const int c = ent[bi];
+            ids[ni++] = c;
+            for (int i = bi; i + 1 < k; ++i) {
+                ent[i] = ent[i + 1];
+                area[i] = area[i + 1];
+                for (int q = 0; q < 6; ++q) box[i][q] = box[i + 1][q];
+            }
+            k -= 1;
+            for (int a = 0; a < 2; ++a, ++k) {
+                ent[k] = ald_i(child + 2 * c + a);
+                for (int q = 0; q < 6; ++q) box[k][q] = aload(aabb + 6 * bidx(ent[k]) + q);
+                area[k] = tl_area(box[k]);
+            }
+        }
+        T.k = k;
+        for (int i = 0; i < k; ++i) {
+            T.ent[i] = ent[i];
+            for (int q = 0; q < 6; ++q) T.box[i][q] = box[i][q];
+            T.cost[i] = (ent[i] & (int)LEAF_BIT) ? area[i] : aload(tcost + ent[i]);
+            T.leaves[i] = (ent[i] & (int)LEAF_BIT) ? 1 : ald_i(tleaves + ent[i]);
+        }
+        // the internal nodes other than r in ascending id order (insertion sort)
+        for (int i = 2; i < ni; ++i) {
+            const int v = ids[i];
+            int j = i - 1;
+            while (j >= 1 && ids[j] > v) { ids[j + 1] = ids[j]; --j; }
+            ids[j + 1] = v;
+        }
+        for (int i = 0; i < ni; ++i) T.ids[i] = ids[i];
+    }
+    wave_sync_lds();
+    const int k = T.k, full = (1 << k) - 1;
+    // union-box areas of this lane's subsets, singletons' costs
+    float sarea[2];
+    int sset[2];
+    for (int h = 0; h < 2; ++h) {
+        const int S = lane + 64 * h;
+        sset[h] = (S >= 1 && S <= full) ? S : 0;
+        float u[6] = {__int_as_float(0x7f800000), __int_as_float(0x7f800000), __int_as_float(0x7f800000),
+                      -__int_as_float(0x7f800000), -__int_as_float(0x7f800000), -__int_as_float(0x7f800000)};
+        for (int j = 0; j < k; ++j)
+            if (sset[h] >> j & 1)
+                for (int q = 0; q < 3; ++q) {
+                    u[q] = fminf(u[q], T.box[j][q]);
+                    u[3 + q] = fmaxf(u[3 + q], T.box[j][3 + q]);
+                }
+        sarea[h] = sset[h] ? tl_area(u) : 0.0f;
+        if (sset[h] && __popc(sset[h]) == 1) T.opt[sset[h]] = T.cost[__ffs(sset[h]) - 1];
+    }
+    wave_sync_lds();
+    for (int size = 2; size <= k; ++size) {
+        for (int h = 0; h < 2; ++h) {
+            const int S = sset[h];
+            if (!S || __popc(S) != size) continue;
+            const int lb = S & -S, rest = S ^ lb;
+            float best = __int_as_float(0x7f800000);
+            int bp = 0;
+            int sub = (rest - 1) & rest;
+            for (;;) {
+                const int P = lb | sub;
+                const float c = T.opt[P] + T.opt[S ^ P];
+                if (c < best) { best = c; bp = P; }
+                if (sub == 0) break;
+                sub = (sub - 1) & rest;
+            }
+            T.opt[S] = TL_C_INNER * sarea[h] + best;
+            T.part[S] = bp;
+        }
+        wave_sync_lds();
+    }
+    if (lane == 0) {
+        // preorder of the optimal tree's internal subsets
+        int pre[TL_LEAVES], st[TL_LEAVES + 1];
+        int np = 0, sp = 0;
+        st[sp++] = full;
+        while (sp > 0) {
+            const int S = st[--sp];
+            pre[np++] = S;
+            const int P = T.part[S], Q = S ^ P;
+            if (__popc(Q) > 1) st[sp++] = Q;
+            if (__popc(P) > 1) st[sp++] = P;
+        }
+        auto code_of = [&](int X) -> int {
+            if (__popc(X) == 1) return T.ent[__ffs(X) - 1];
+            for (int i = 0; i < np; ++i)
+                if (pre[i] == X) return T.ids[i];
+            return -1;
+        };
+        for (int i = 0; i < np; ++i) {
+            const int S = pre[i], id = T.ids[i], P = T.part[S], Q = S ^ P;
+            const int a = code_of(P), c = code_of(Q);
+            ast_i(child + 2 * id, a);
+            ast_i(child + 2 * id + 1, c);
+            ast_i(parent + bidx(a), id);
+            ast_i(parent + bidx(c), id);
+            ast_f(tcost + id, T.opt[S]);
+            int cnt = 0;
+            for (int j = 0; j < k; ++j)
+                if (S >> j & 1) cnt += T.leaves[j];
+            ast_i(tleaves + id, cnt);
+            float u[6] = {__int_as_float(0x7f800000), __int_as_float(0x7f800000), __int_as_float(0x7f800000),
+                          -__int_as_float(0x7f800000), -__int_as_float(0x7f800000), -__int_as_float(0x7f800000)};
+            for (int j = 0; j < k; ++j)
+                if (S >> j & 1)
+                    for (int q = 0; q < 3; ++q) {
+                        u[q] = fminf(u[q], T.box[j][q]);
+                        u[3 + q] = fmaxf(u[3 + q], T.box[j][3 + q]);
+                    }
+            for (int q = 0; q < 6; ++q) ast_f(aabb + 6 * (size_t)id + q, u[q]);
+        }
+    }
+}
+
+// triangle count and SAH cost of a code (leaf: 1 and its box area)
+__device__ __forceinline__ void code_stats(int code, const float* aabb, const float* tcost, const int* tleaves, int n,
+                                           int& leaves, float& cost) {
+    if (code & (int)LEAF_BIT) {
+        float b[6];
+        for (int q = 0; q < 6; ++q) b[q] = aload(aabb + 6 * ((size_t)(n - 1) + (code & 0x7FFFFFFF)) + q);
+        leaves = 1;
+        cost = tl_area(b);
+    } else {
+        leaves = ald_i(tleaves + code);
+        cost = aload(tcost + code);
+    }
+}
+
+__global__ __launch_bounds__(TL_BLOCK) void k_treelet(int* child, int* parent, float* aabb, float* tcost,
+                                                      int* tleaves, int* cnt, int n, uint32_t* err) {
+#pragma clang fp contract(off)
+    __shared__ TreeletLds lds[TL_WAVES];
+    const int lane = threadIdx.x & 63;
+    TreeletLds& T = lds[threadIdx.x >> 6];
+    const int leaf = blockIdx.x * blockDim.x + threadIdx.x;
+    bool active = leaf < n;
+    int node = active ? parent[(n - 1) + leaf] : -1;
+    if (node < 0) active = false;
+    int guard = 0;
+    for (; guard < TL_GUARD; ++guard) {
+        bool own = false, big = false;
+        if (active) {
+            handoff_release();
+            if (atomicAdd(&cnt[node], 1) == 0) active = false;    // the other subtree is not done yet
+            else own = true;
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        }
+        if (own) {
+            int l0, l1;
+            float k0, k1;
+            code_stats(ald_i(child + 2 * node), aabb, tcost, tleaves, n, l0, k0);
+            code_stats(ald_i(child + 2 * node + 1), aabb, tcost, tleaves, n, l1, k1);
+            big = l0 + l1 >= TL_LEAVES;
+            if (!big) {
+                float b[6];
+                for (int q = 0; q < 6; ++q) b[q] = aload(aabb + 6 * (size_t)node + q);
+                ast_i(tleaves + node, l0 + l1);
+                ast_f(tcost + node, TL_C_INNER * tl_area(b) + (k0 + k1));
+            }
+        }
+        uint64_t m = __ballot(big);
+        while (m) {
+            const int src = __ffsll((unsigned long long)m) - 1;
+            m &= m - 1;
+            treelet_restructure(__builtin_amdgcn_readlane(node, src), lane, T, child, parent, aabb, tcost, tleaves, n);
+        }
+        if (own) {
+            const int p = ald_i(parent + node);
+            if (p < 0) active = false;
+            else node = p;
+        }
+        if (__ballot(active) == 0) break;
+    }
+    if (guard == TL_GUARD && active) atomicOr(err, ERR_LOOP);
+}
+
 // depth of every internal node of the binary tree, and the flag "starts a
 // 4-wide node" (even depth)
 __global__ void k_depth(const int* __restrict__ parent, int n, int* flag) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n - 1) return;
     int d = 0, x = i;
-    for (int guard = 0; guard < 128 && parent[x] >= 0; ++guard) { x = parent[x]; ++d; }
+    for (int guard = 0; guard < TL_GUARD && parent[x] >= 0; ++guard) { x = parent[x]; ++d; }
     flag[i] = (d & 1) ? 0 : 1;
 }
 
@@ -459,6 +726,11 @@ void launch_scene_geometry(SceneDev& s, hipStream_t st) {
     if (nf > 1) {
         ST_LAUNCH("k_refit", k_refit, dim3(nb(nf, 256)), dim3(256), 0, st, s.parent, s.child, nf, s.aabb,
                            s.refit_cnt);
+        for (int rd = 0; rd < TREELET_ROUNDS; ++rd) {
+            launch_fill_u32((uint32_t*)s.refit_cnt, nf - 1, 0u, st);
+            ST_LAUNCH("k_treelet", k_treelet, dim3(nb(nf, TL_BLOCK)), dim3(TL_BLOCK), 0, st, s.child, s.parent, s.aabb,
+                      s.tcost, s.tleaves, s.refit_cnt, nf, s.err);
+        }
         ST_LAUNCH("k_depth", k_depth, dim3(nb(nf - 1, 256)), dim3(256), 0, st, s.parent, nf, s.flag4);
         hipMemcpyAsync(s.id4, s.flag4, sizeof(int) * (nf - 1), hipMemcpyDeviceToDevice, st);
         ST_LAUNCH("k_rs_scan", k_rs_scan, dim3(1), dim3(1024), 0, st, s.id4, nf - 1);

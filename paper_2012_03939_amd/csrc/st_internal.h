@@ -19,6 +19,7 @@ extern bool g_prof_on;
     } while (0)
 
 // every device allocation of one scene (library-owned)
+constexpr int TREELET_ROUNDS = 2;   // bottom-up treelet-restructuring passes over the Karras tree
 constexpr int FACC = 16;   // gradient slots of one vertex: 3 corners x xyz, then the 7 material parameters
 
 struct SceneDev {
@@ -48,6 +49,8 @@ struct SceneDev {
     int* parent = nullptr;                   // [2*nf-1]
     float* aabb = nullptr;                   // [(2*nf-1)*6]
     int* refit_cnt = nullptr;
+    float* tcost = nullptr;                  // [nf-1] SAH cost of every internal node's subtree
+    int* tleaves = nullptr;                  // [nf-1] triangles below every internal node
     float4* nodes4 = nullptr;                // [(nf-1)*8] 4-wide nodes (at most nf-1 of them)
     int* flag4 = nullptr;                    // [nf-1] even-depth flag of the binary nodes
     uint32_t* id4 = nullptr;                 // [nf-1] 4-wide node index of each even-depth node

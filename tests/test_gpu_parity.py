@@ -63,7 +63,7 @@ def test_lbvh_bit_exact(B, k):
     g = B.GPUScene.from_scene(sc)
     keys, child, parent, aabb = g.lbvh()
     torch.cuda.synchronize()
-    rk, rc, rp, ra = O.lbvh(sc.V, sc.F)
+    rk, rc, rp, ra = O.lbvh(sc.V, sc.F, treelet_rounds=O.TREELET_ROUNDS)
     assert np.array_equal(keys.cpu().numpy().view(np.uint64), rk)
     assert np.array_equal(child.cpu().numpy(), rc)
     assert np.array_equal(parent.cpu().numpy(), rp)
@@ -79,7 +79,7 @@ def test_lbvh_torus_and_rebuild(B):
     g.update(V=torch.from_numpy(V2).cuda())
     keys, child, parent, aabb = g.lbvh()
     torch.cuda.synchronize()
-    rk, rc, rp, ra = O.lbvh(V2, sc.F)
+    rk, rc, rp, ra = O.lbvh(V2, sc.F, treelet_rounds=O.TREELET_ROUNDS)
     assert np.array_equal(keys.cpu().numpy().view(np.uint64), rk)
     assert np.array_equal(child.cpu().numpy(), rc)
     assert np.array_equal(parent.cpu().numpy(), rp)

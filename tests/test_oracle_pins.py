@@ -629,8 +629,8 @@ def test_lbvh_reference_definition(k):
     mn, mx = tri.min(axis=1), tri.max(axis=1)
     c = ((mn + mx) * np.float32(0.5)).astype(np.float32)
     lo, hi = c.min(axis=0), c.max(axis=0)
-    s = np.array([np.float32(1024.0 / (float(h) - float(l))) if h > l else np.float32(0) for l, h in zip(lo, hi)],
-                 np.float32)
+    ext = max(float(h) - float(l) for l, h in zip(lo, hi))      # cubic cells: one scale for all axes
+    s = np.full(3, np.float32(1024.0 / ext) if ext > 0 else np.float32(0), np.float32)
     q = np.clip(np.floor((c - lo).astype(np.float32) * s).astype(np.int64), 0, 1023)
     mort = np.array([(_spread(a) << 2) | (_spread(b) << 1) | _spread(cc) for a, b, cc in q], np.uint64)
     ref = np.sort((mort << np.uint64(32)) | np.arange(n, dtype=np.uint64))
@@ -917,3 +917,111 @@ def test_shadow_edges_closed_form_polygon():
     scale = np.abs(expect).max()
     assert scale > 0
     assert np.abs(est - expect).max() < 0.03 * scale, (est, expect)
+
+
+# --------------------------------------------------------------------------
+# treelet restructuring of the Karras tree
+# --------------------------------------------------------------------------
+
+C_INNER = 1.2
+
+
+def _area(b):
+    d = np.maximum(np.asarray(b[3:], np.float64) - np.asarray(b[:3], np.float64), 0.0)
+    return 2.0 * (d[0] * d[1] + d[1] * d[2] + d[2] * d[0])
+
+
+def _tree_check(child, parent, aabb, n):
+    """Every leaf reached once from the root, parent links consistent, every box
+    the exact union of its children's; returns the SAH cost in float64."""
+    LEAF = 0x80000000
+    seen = np.zeros(n, int)
+    cost = 0.0
+    stack = [0]
+    assert parent[0] == -1
+    while stack:
+        i = stack.pop()
+        cost += C_INNER * _area(aabb[i])
+        boxes = []
+        for c in child[i]:
+            c = int(c) & 0xFFFFFFFF
+            if c & LEAF:
+                j = c & 0x7FFFFFFF
+                seen[j] += 1
+                assert parent[n - 1 + j] == i
+                boxes.append(aabb[n - 1 + j])
+                cost += _area(aabb[n - 1 + j])
+            else:
+                assert parent[c] == i
+                boxes.append(aabb[c])
+                stack.append(c)
+        assert np.array_equal(aabb[i][:3], np.minimum(boxes[0][:3], boxes[1][:3]))
+        assert np.array_equal(aabb[i][3:], np.maximum(boxes[0][3:], boxes[1][3:]))
+    assert (seen == 1).all()
+    return cost
+
+
+@pytest.mark.parametrize("which", ["sphere80", "sphere720", "torus_small"])
+def test_treelets_valid_and_lower_sah(which):
+    if which == "torus_small":
+        V, F = S.noise_torus(40, 20, 0.1, noise_seed=13)
+    else:
+        V, F = S.noise_sphere(2 if which == "sphere80" else 6, 0.1, noise_seed=1)
+    V = V.astype(np.float32)
+    n = F.shape[0]
+    k0, c0, p0, a0 = O.lbvh(V, F)
+    costs = [_tree_check(c0, p0, a0, n)]
+    for rounds in (1, 2, 3):
+        k, c, p, a = O.lbvh(V, F, treelet_rounds=rounds)
+        assert np.array_equal(k, k0)                       # leaves (sorted keys) and their boxes are untouched
+        assert np.array_equal(a[n - 1:], a0[n - 1:]) and np.array_equal(a[0], a0[0])
+        costs.append(_tree_check(c, p, a, n))
+    assert costs[1] < costs[0] and costs[2] <= costs[1] * (1 + 1e-6) and costs[3] <= costs[2] * (1 + 1e-6)
+    assert costs[2] < 0.99 * costs[0]
+
+
+def _all_trees(items):
+    """Every full binary tree over the labelled leaves (nested pairs)."""
+    if len(items) == 1:
+        yield items[0]
+        return
+    first, rest = items[0], items[1:]
+    m = len(rest)
+    for mask in range(1 << m):
+        if mask == (1 << m) - 1:
+            continue
+        left = [first] + [rest[i] for i in range(m) if mask >> i & 1]
+        right = [rest[i] for i in range(m) if not mask >> i & 1]
+        for a in _all_trees(left):
+            for b in _all_trees(right):
+                yield (a, b)
+
+
+def _tree_cost(t, boxes):
+    if not isinstance(t, tuple):
+        return _area(boxes[t]), boxes[t]
+    ca, ba = _tree_cost(t[0], boxes)
+    cb, bb = _tree_cost(t[1], boxes)
+    u = np.concatenate([np.minimum(ba[:3], bb[:3]), np.maximum(ba[3:], bb[3:])])
+    return C_INNER * _area(u) + ca + cb, u
+
+
+@pytest.mark.parametrize("n", [3, 6, 7])
+def test_treelets_reach_brute_force_optimum_on_small_trees(n):
+    """With exactly 7 triangles the root's treelet holds every leaf, so the
+    restructured tree must cost what the best of all (2n-3)!! = 10395 binary
+    trees costs; below 7 triangles no node qualifies and the tree is the radix tree."""
+    rng = np.random.default_rng(20 + n)
+    for trial in range(4 if n == 7 else 2):
+        V = rng.uniform(-1, 1, size=(3 * n, 3)).astype(np.float32) * np.array([1.0, 0.2, 1.0], np.float32)
+        V[3:] += rng.uniform(-0.5, 0.5, size=(1, 3)).astype(np.float32)
+        F = np.arange(3 * n, dtype=np.int32).reshape(n, 3)
+        k, c, p, a = O.lbvh(V, F, treelet_rounds=1)
+        if n < 7:
+            k0, c0, p0, a0 = O.lbvh(V, F)
+            assert np.array_equal(c, c0) and np.array_equal(p, p0) and np.array_equal(a, a0)
+            continue
+        got = _tree_check(c, p, a, n)
+        boxes = [a[n - 1 + i].astype(np.float64) for i in range(n)]
+        best = min(_tree_cost(t, boxes)[0] for t in _all_trees(list(range(n))))
+        assert abs(got - best) <= 1e-5 * best, (trial, got, best)
