@@ -11,17 +11,21 @@ namespace st {
 
 // occupancy targets (waves per SIMD) the compiler fits the register budget to
 #ifndef ST_SHADE_WAVES
-#define ST_SHADE_WAVES 4
+#define ST_SHADE_WAVES 6
 #endif
-#ifndef ST_TRACE_WAVES
-#define ST_TRACE_WAVES 7
+#ifndef ST_EXTEND_WAVES
+#define ST_EXTEND_WAVES 8
+#endif
+#ifndef ST_SHADOW_WAVES
+#define ST_SHADOW_WAVES 7
 #endif
 #define SHADE_OCC __attribute__((amdgpu_waves_per_eu(ST_SHADE_WAVES)))
 #ifndef ST_SHADE_BLOCK
 #define ST_SHADE_BLOCK 512
 #endif
 constexpr int SHADE_BLOCK = ST_SHADE_BLOCK;   // threads of a k_shade block (one queue reservation each)
-#define TRACE_OCC __attribute__((amdgpu_waves_per_eu(ST_TRACE_WAVES)))
+#define EXTEND_OCC __attribute__((amdgpu_waves_per_eu(ST_EXTEND_WAVES)))
+#define SHADOW_OCC __attribute__((amdgpu_waves_per_eu(ST_SHADOW_WAVES)))
 
 
 
@@ -74,7 +78,7 @@ __global__ void k_camera(FwdParams p, Queues q, long long q0, int n) {
 #ifndef ST_EXTEND_QUEUE
 #define ST_EXTEND_QUEUE 0
 #endif
-__global__ void __launch_bounds__(TRACE_BLOCK) TRACE_OCC k_extend(FwdParams p, Queues q, int k) {
+__global__ void __launch_bounds__(TRACE_BLOCK) EXTEND_OCC k_extend(FwdParams p, Queues q, int k) {
     __shared__ uint32_t lds[LDS_STACK * TRACE_BLOCK];
     TravStack st = make_trav_stack(lds, q.spill, p.err, p.work ? p.work + 3 * WORK_EXTEND : nullptr);
     const int n = q.cnt[k];
@@ -242,7 +246,7 @@ __global__ void __launch_bounds__(SHADE_BLOCK) SHADE_OCC k_shade(FwdParams p, Qu
 // shadow rays of bounce k: entry l of shading point i is item l * n + i;
 // persistent waves take items from the fetch counters of slot k and store one
 // outcome code per entry (0 no ray, 1 occluded, 2 unoccluded)
-__global__ void __launch_bounds__(TRACE_BLOCK) TRACE_OCC k_shadow(FwdParams p, Queues q, int k) {
+__global__ void __launch_bounds__(TRACE_BLOCK) SHADOW_OCC k_shadow(FwdParams p, Queues q, int k) {
     __shared__ uint32_t lds[LDS_STACK * TRACE_BLOCK];
     TravStack st = make_trav_stack(lds, q.spill, p.err, p.work ? p.work + 3 * WORK_SHADOW : nullptr);
     const int n = q.cnt[k];
