@@ -5,7 +5,7 @@ summaries kept under profiles/.
         a plain 512 MiB device-to-device copy (three times), the reference that
         scales FETCH_SIZE / WRITE_SIZE to bytes
     python -m paper_2012_03939_amd.profiling pmc --fetch D1 --write D2 --copy-fetch D3 --copy-write D4
-                                            [--sq D5] --out FILE.json --command "..."
+                                            [--sq D5 ...] --out FILE.json --command "..."
         per-kernel counter summary (KiB per dispatch, copy-scaled HBM bytes per dispatch)
     python -m paper_2012_03939_amd.profiling trace --stats run_kernel_stats.csv --out FILE.md --title "..."
                                               --command "..."
@@ -84,12 +84,15 @@ def _copy_factor(d: str, counter: str) -> float:
     return COPY_BYTES / (kib * 1024.0)
 
 
-def pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, sq_dir=None, command="") -> dict:
+def pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, sq_dirs=(), command="") -> dict:
     ff = _copy_factor(copy_fetch_dir, "FETCH_SIZE")
     wf = _copy_factor(copy_write_dir, "WRITE_SIZE")
     fv, fdur = read_counters(fetch_dir)
     wv, _ = read_counters(write_dir)
-    sv = read_counters(sq_dir)[0] if sq_dir else {}
+    sv = collections.defaultdict(dict)
+    for d in sq_dirs or ():
+        for k, cs in read_counters(d)[0].items():
+            sv[k].update(cs)
     kernels = {}
     for k in sorted(fv):
         f = fv[k].get("FETCH_SIZE")
@@ -110,6 +113,10 @@ def pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, sq_dir=Non
             e["l2_hit_rate"] = e["tcc_hit_sum_per_dispatch"] / t if t else None
         for c, v in sv.get(k, {}).items():
             e[c.lower() + "_per_dispatch"] = sum(v) / len(v)
+        if e.get("sq_thread_cycles_valu_per_dispatch") and e.get("sq_active_inst_valu_per_dispatch"):
+            # active lanes per VALU instruction cycle, over the 64 of a wave
+            e["valu_lane_utilisation"] = (e["sq_thread_cycles_valu_per_dispatch"]
+                                          / e["sq_active_inst_valu_per_dispatch"] / 64.0)
         kernels[k] = e
     return {"command": command, "source_hash": kernel_source_hash(), "fetch_size_factor": ff,
             "write_size_factor": wf, "copy_reference_bytes": COPY_BYTES, "kernels": kernels}
@@ -135,7 +142,7 @@ def main(argv=None):
     p = sub.add_parser("pmc")
     for a in ("--fetch", "--write", "--copy-fetch", "--copy-write", "--out"):
         p.add_argument(a, required=True)
-    p.add_argument("--sq")
+    p.add_argument("--sq", action="append", default=[], help="counter directory of an SQ pass (repeatable)")
     p.add_argument("--command", default="")
     t = sub.add_parser("trace")
     t.add_argument("--stats", required=True)
