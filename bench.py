@@ -242,6 +242,13 @@ def main():
     avg_ms = dom_ms / dom_n
     achieved = flops_per_launch / (avg_ms / 1e3) / 1e12
     kernels = {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[1] / args.steps} for k, v in prof.items()}
+    # rays, node visits and triangle tests of every traversal kernel in one step
+    traversal = {}
+    for k, (kv, kt, kr) in work.items():
+        kms = sum(v["ms_per_step"] for n, v in kernels.items() if n.split("<")[0] == k)
+        if kr:
+            traversal[k] = {"rays_per_step": kr, "node_visits_per_ray": kv / kr, "tri_tests_per_ray": kt / kr,
+                            "ms_per_step": kms, "rays_per_s": kr / (kms / 1e3) if kms else None}
     out = {
         "metric": "fwd+adjoint path samples/sec at 16 views 512^2 16spp; sec per optimisation step",
         "value": value,
@@ -268,6 +275,7 @@ def main():
                      "rays_per_launch": rays / max(launches_per_step, 1),
                      "rays_per_s": rays / max(launches_per_step, 1) / (avg_ms / 1e3)},
         "kernels": kernels,
+        "traversal": traversal,
     }
     if args.mesh_colors_res > 0:
         out["mesh_colors"] = mesh_colors_step(B, S, torch, wl, args.mesh_colors_res)

@@ -56,6 +56,8 @@ extern "C" {
 #define ST_COUNT_WORK 32u          /* count BVH node visits, triangle tests and rays (st_read_work) */
 #define ST_EDGE_SECONDARY_INTERIOR 64u  /* secondary edges: also creases and material boundaries seen from
                                            a path vertex, not only silhouettes (2 side paths per sample) */
+#define ST_BACKWARD_RETRACE 128u   /* backward: trace every main-path ray again even when hit records of
+                                      the matching forward pass are held (see st_render_backward) */
 
 typedef struct st_scene st_scene;
 
@@ -165,7 +167,16 @@ int st_render(st_scene* scene, const st_camera* cams, int32_t ncam, int32_t spp,
 /* Adjoint of st_render (Sec. 3.2 gradients w.r.t. geometry; Sec. 3.3 materials).
  * Must be called with the same (cams, spp, bounces, seed) as the forward pass
  * whose image gradient it receives; it replays every path from its random
- * counters and keeps no state from st_render.
+ * counters.  Hit records: a single-scene wavefront st_render keeps, per path
+ * sample, the face hit at every bounce and the occlusion of every shadow ray
+ * (4 (2 bounces + 1) bytes per path sample, scene-owned, at most 16 GiB; scenes
+ * with more than 30 point lights keep none).  When the backward's (cams, spp,
+ * bounces, seed) equal those of the last such render and the scene has not
+ * changed since (st_scene_update, st_scene_set_mesh_colors,
+ * st_scene_set_env_sampler), the replay takes hits and occlusions from the
+ * records (the hit distance from the recorded face's plane) instead of tracing
+ * the main path again; ST_BACKWARD_RETRACE in opts->flags disables this.  The
+ * result is the same estimator either way.
  *   d_image: device float, same layout as st_render's out.
  *   out_dV: device float [nv,3]; out_dmat: device float [ntex,7] (ntex = nf unless the scene uses
  *   mesh colours, st_scene_set_mesh_colors); both overwritten. */

@@ -25,6 +25,7 @@ ST_EDGE_SECONDARY_INTERIOR = 64
 ST_FORWARD_MEGAKERNEL = 16
 ST_COUNT_WORK = 32
 ST_ALL_GRADS = 15
+ST_BACKWARD_RETRACE = 128
 ST_ENV_SAMPLER_CDF = 0
 ST_ENV_SAMPLER_ALIAS = 1
 

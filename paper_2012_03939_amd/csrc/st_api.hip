@@ -145,6 +145,11 @@ struct st_scene {
     std::vector<CamTable> tables;
     long long tuned_cap = 0;           // autotuned wavefront chunk size (0: none)
     int tuned_grid = 0;                // autotuned traversal grid (0: none)
+    // hit records of the last single-scene wavefront render, for its backward
+    GrowBuf recbuf;
+    uint64_t version = 0;              // bumped by every change of geometry, materials or sampler
+    bool rec_valid = false;
+    uint64_t rec_key = 0;
 };
 
 namespace {
@@ -240,6 +245,21 @@ int setup_cams(st_scene* owner, st_scene* const* scenes, int nscenes, const st_c
     return ST_OK;
 }
 
+// identity of a forward pass's main paths: cameras, spp, bounces, seed and the scene state
+uint64_t record_key(const st_scene* sc, const st_camera* cams, int ncam, int spp, int bounces, uint32_t seed) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&h](const void* src, size_t n) {
+        const unsigned char* b = (const unsigned char*)src;
+        for (size_t i = 0; i < n; ++i) { h ^= b[i]; h *= 1099511628211ull; }
+    };
+    mix(cams, sizeof(st_camera) * (size_t)ncam);
+    const long long w[5] = {ncam, spp, bounces, (long long)seed, (long long)sc->version};
+    mix(w, sizeof(w));
+    return h;
+}
+
+constexpr size_t REC_MAX_BYTES = 16ull << 30;
+
 int ensure_spill(st_scene* sc) {
     return sc->spillbuf.ensure((size_t)SPILL_STACK * TRACE_GRID * TRACE_BLOCK * sizeof(uint32_t));
 }
@@ -306,6 +326,21 @@ int render_impl(st_scene* owner, st_scene* const* scenes, int nscenes, const st_
     p.err = owner->d.err;
     p.work = (o.flags & ST_COUNT_WORK) ? owner->d.work : nullptr;
     p.hash_by_q = nullptr;
+    p.rec_face = nullptr;
+    p.rec_occ = nullptr;
+    p.rec_n = 0;
+    // hit records for the backward of a single-scene wavefront render
+    const size_t rec_bytes = (size_t)(2 * bounces + 1) * (size_t)cs.total_paths * sizeof(int);
+    const bool want_rec = nscenes == 1 && !(o.flags & ST_FORWARD_MEGAKERNEL) && scenes[0]->d.nl <= 30 &&
+                          rec_bytes <= REC_MAX_BYTES;
+    if (nscenes == 1) owner->rec_valid = false;
+    if (want_rec && !(g_capturing && owner->recbuf.cap < rec_bytes) && owner->recbuf.ensure(rec_bytes) == ST_OK) {
+        p.rec_face = (int*)owner->recbuf.p;
+        p.rec_occ = (uint32_t*)(p.rec_face + (size_t)(bounces + 1) * cs.total_paths);
+        p.rec_n = cs.total_paths;
+        owner->rec_valid = true;
+        owner->rec_key = record_key(owner, cams, ncam, spp, bounces, seed);
+    }
     float* L = (float*)owner->Lbuf.p;
     if (o.flags & ST_FORWARD_MEGAKERNEL) {
         launch_forward_mega(p, L, cs.total_paths, (uint32_t*)owner->spillbuf.p, TRACE_GRID, s);
@@ -534,6 +569,7 @@ int st_scene_update(st_scene* sc, const float* V, const float* mat, hipStream_t 
     if (V) HIPCHK(hipMemcpyAsync(sc->d.V, V, sizeof(float) * 3 * sc->d.nv, hipMemcpyDeviceToDevice, s));
     if (mat) HIPCHK(hipMemcpyAsync(sc->d.mat, mat, sizeof(float) * 7 * (size_t)sc->d.ntex, hipMemcpyDeviceToDevice, s));
     if (V) launch_scene_geometry(sc->d, s);
+    if (V || mat) { ++sc->version; sc->rec_valid = false; }
     HIPCHK(hipGetLastError());
     return ST_OK;
 }
@@ -572,6 +608,8 @@ int st_scene_set_mesh_colors(st_scene* sc, int32_t r, const float* texels, hipSt
     d.ntex = (int)ntex;
     d.hscene.mat = mat;
     d.hscene.tex_res = r;
+    ++sc->version;
+    sc->rec_valid = false;
     HIPCHK(hipMemcpyAsync(d.dscene, &d.hscene, sizeof(DevScene), hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
     return ST_OK;
@@ -640,6 +678,8 @@ int st_scene_set_env_sampler(st_scene* sc, int32_t method, hipStream_t s) {
     }
     d.hscene.ealias = d.ealias;
     d.hscene.env_alias = method == ST_ENV_SAMPLER_ALIAS ? 1 : 0;
+    ++sc->version;
+    sc->rec_valid = false;
     HIPCHK(hipMemcpyAsync(d.dscene, &d.hscene, sizeof(DevScene), hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
     return ST_OK;
@@ -747,6 +787,11 @@ int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_
     p.vf_off = sc->d.vf_off;
     p.vf_idx = sc->d.vf_idx;
     p.ne = ne;
+    const bool use_rec = sc->rec_valid && !(o.flags & ST_BACKWARD_RETRACE) &&
+                         sc->rec_key == record_key(sc, cams, ncam, spp, bounces, seed);
+    p.rec_face = use_rec ? (const int*)sc->recbuf.p : nullptr;
+    p.rec_occ = use_rec ? (const uint32_t*)((const int*)sc->recbuf.p + (size_t)(bounces + 1) * cs.total_paths) : nullptr;
+    p.rec_n = use_rec ? cs.total_paths : 0;
     launch_fill_f32(out_dV, 3ll * sc->d.nv, 0.0f, s);
     launch_fill_f32(out_dmat, 7ll * sc->d.ntex, 0.0f, s);
     if (o.debug_decision_hash) launch_fill_u32(o.debug_decision_hash, cs.total_paths, 0u, s);
@@ -783,6 +828,9 @@ int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_
         fp.err = sc->d.err;
         fp.work = p.work;
         fp.hash_by_q = hside;
+        fp.rec_face = nullptr;
+        fp.rec_occ = nullptr;
+        fp.rec_n = 0;
         launch_primary_edges(p, fp, q, (float*)sc->sidebuf.p, hside, cs.total_edges, sc->d.has_env ? 1 : 0, s);
     }
     if (nls > 0) launch_shadow_edges(p, cs.total_edges, nls, s);
@@ -956,7 +1004,7 @@ void st_scene_destroy(st_scene* sc) {
                     d.ealias};
     for (void* p : ptrs)
         if (p) hipFree(p);
-    sc->Lbuf.release(); sc->qbuf.release(); sc->spillbuf.release(); sc->primbuf.release();
+    sc->Lbuf.release(); sc->qbuf.release(); sc->spillbuf.release(); sc->primbuf.release(); sc->recbuf.release();
     sc->sidebuf.release(); sc->sidehash.release();
     for (auto& t : sc->tables) {
         if (t.dev) hipFree(t.dev);

@@ -166,7 +166,14 @@ k_adjoint(BwdParams p, long long total) {
             float pprev = 0.0f;
             for (int k = 1; k <= p.B + 1; ++k) {
                 float t;
-                const int f = trace_closest(S, o, d, TMIN, excl, t, st);
+                const size_t ri = (size_t)(k - 1) * p.rec_n + qq;
+                int f;
+                if (p.rec_face) {
+                    f = p.rec_face[ri];
+                    t = f >= 0 ? face_hit_t(S, f, o, d) : __int_as_float(0x7f800000);
+                } else {
+                    f = trace_closest(S, o, d, TMIN, excl, t, st);
+                }
                 push_face(h, f);
                 if (f < 0) {
                     if (S.has_env && k > 1) {
@@ -187,6 +194,7 @@ k_adjoint(BwdParams p, long long total) {
                 const int tx = texel_of(S, f, xh);
                 if (S.tex_res) h.push((uint32_t)tx);
                 const Mat m = load_mat(S.mat + 7 * (size_t)tx);
+                const uint32_t rocc = p.rec_occ ? p.rec_occ[ri] : 0u;
                 for (int l = 0; l < S.nl; ++l) {
                     const float* lt = S.lights + 6 * l;
                     const V3 dl = ld3(lt) - xh;
@@ -196,7 +204,8 @@ k_adjoint(BwdParams p, long long total) {
                         const float rr = sqrtf(r2);
                         const V3 wl = dl * (1.0f / rr);
                         if (dot(n, wl) > 0.0f) {
-                            const bool occ = trace_any(S, xh, wl, TMIN, rr * (1.0f - SHADOW_SHRINK), f, st);
+                            const bool occ = p.rec_occ ? ((rocc >> l) & 1u) != 0u
+                                                       : trace_any(S, xh, wl, TMIN, rr * (1.0f - SHADOW_SHRINK), f, st);
                             code = occ ? 1u : 2u;
                             if (!occ) fl |= 1u << (8 + l);
                         }
@@ -211,7 +220,8 @@ k_adjoint(BwdParams p, long long total) {
                     const float ce = dot(n, we);
                     uint32_t code = 0;
                     if (ce > 0.0f && pe > 0.0f) {
-                        const bool occ = trace_any(S, xh, we, TMIN, __int_as_float(0x7f800000), f, st);
+                        const bool occ = p.rec_occ ? ((rocc >> S.nl) & 1u) != 0u
+                                                   : trace_any(S, xh, we, TMIN, __int_as_float(0x7f800000), f, st);
                         code = occ ? 1u : 2u;
                         if (!occ) {
                             fl |= R_ENV;

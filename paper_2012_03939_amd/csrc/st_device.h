@@ -209,6 +209,17 @@ __device__ __forceinline__ bool tri_test(const gfloat4* tri, uint32_t leaf, V3 o
     return t > tmin && t < tmax;
 }
 
+// distance along o + t d to the plane of face f, with the arithmetic of the
+// triangle test (the hit distance of a recorded hit)
+__device__ __forceinline__ float face_hit_t(const DevScene& S, int f, V3 o, V3 d) {
+    const V3 a = ld3(S.V + 3 * (size_t)S.F[3 * f]);
+    const V3 e1 = ld3(S.V + 3 * (size_t)S.F[3 * f + 1]) - a, e2 = ld3(S.V + 3 * (size_t)S.F[3 * f + 2]) - a;
+    const V3 p = cross(d, e2);
+    const float inv = 1.0f / dot(e1, p);
+    const V3 q = cross(o - a, e1);
+    return dot(e2, q) * inv;
+}
+
 __device__ __forceinline__ V3 safe_inv(V3 d) {
     auto f = [](float v) { return 1.0f / (fabsf(v) > 1e-30f ? v : copysignf(1e-30f, v)); };
     return V3{f(d.x), f(d.y), f(d.z)};

@@ -135,6 +135,9 @@ struct FwdParams {
     uint32_t* err;
     unsigned long long* work;  // optional traversal counters
     uint32_t* hash_by_q;     // optional: final path hash stored at the path's radiance index
+    int* rec_face;           // optional hit records of the main paths: face of bounce k at [(k-1) rec_n + path]
+    uint32_t* rec_occ;       // occluded shadow entries (bit l) of bounce k at [(k-1) rec_n + path]
+    long long rec_n;
 };
 
 void launch_scene_geometry(SceneDev& s, hipStream_t st);
@@ -185,6 +188,9 @@ struct BwdParams {
     int ntex;
     const int* vf_off;       // vertex -> (face, corner) CSR of the scene
     const int* vf_idx;
+    const int* rec_face;     // hit records of the matching forward pass, or null (trace again)
+    const uint32_t* rec_occ;
+    long long rec_n;
 };
 
 void launch_backward(const BwdParams& p, int nv, int nf, long long total_paths, long long total_edges, int grid,

@@ -141,6 +141,7 @@ __global__ void __launch_bounds__(SHADE_BLOCK) SHADE_OCC k_shade(FwdParams p, Qu
             beta = V3{r[QBR][i], r[QBG][i], r[QBB][i]};
             f = q.hf[i];
             push_face(h, f);
+            if (p.rec_face && (vd >> 16) == 0u) p.rec_face[(size_t)(k - 1) * p.rec_n + qu(r, QQ, i)] = f;
             q.sface[i] = -1;
             const V3 d{r[QDX][i], r[QDY][i], r[QDZ][i]};
             if (f < 0) {
@@ -290,13 +291,16 @@ __global__ void k_shadow_sum(FwdParams p, Queues q, int k) {
         Hash h{hashing ? qu(r, QHASH, i) : 0u, hashing};
         V3 acc{0.f, 0.f, 0.f};
         const int nent = S.nl + (S.has_env ? 1 : 0);
+        uint32_t occ = 0;
         for (int l = 0; l < nent; ++l) {
             const size_t e = (size_t)l * q.cap + i;
             if (l == S.nl) h.push((uint32_t)q.stex[i]);
             const uint32_t code = q.socc[e];
             if (code == 2u) acc = acc + V3{q.sh[4][e], q.sh[5][e], q.sh[6][e]};
+            if (code == 1u) occ |= 1u << l;
             h.push(code);
         }
+        if (p.rec_occ && (qu(r, QVD, i) >> 16) == 0u) p.rec_occ[(size_t)(k - 1) * p.rec_n + qu(r, QQ, i)] = occ;
         const uint32_t info = q.sinfo[i];
         if (info & 1u) {
             h.push((info >> 1) & 1u);
