@@ -1076,7 +1076,8 @@ static void primary_edge_sample(const Scene& s, const Cam& c, const EdgeView& ev
     double u[4];
     Ctr ctr{(uint32_t)si, (uint32_t)view << 16, 0u, 1u};
     draw4(ctr, 0, 3, key.k0, key.k1, u);
-    int e = cdf_find(ev.cdf.data(), (int)s.edges.size(), u[0]);
+    // stratified over the view's ne samples: sample si takes the CDF at (si + u0) / ne
+    int e = cdf_find(ev.cdf.data(), (int)s.edges.size(), ((double)si + u[0]) / (double)ne);
     double t = u[1];
     const Edge& E = s.edges[e];
     double ax, ay, az, bx, by, bz;
@@ -1173,7 +1174,8 @@ static void shadow_edge_sample(const Scene& s, const Cam& c, const LightEdges& l
     double u[4];
     Ctr ctr{(uint32_t)si, ((uint32_t)view << 16) | (uint32_t)l, 0u, 3u};
     draw4(ctr, 0, 3, key.k0, key.k1, u);
-    const int e = cdf_find(le.cdf.data(), (int)s.edges.size(), u[0]);
+    // stratified over the ns samples of the (view, light) pair
+    const int e = cdf_find(le.cdf.data(), (int)s.edges.size(), ((double)si + u[0]) / (double)ns);
     const double t = u[1];
     h.push((uint32_t)e);
     const Edge& E = s.edges[e];

@@ -487,8 +487,10 @@ __device__ __forceinline__ bool edge_setup(const BwdParams& p, long long ge, Edg
     es.si = ge - c.eoff;
     const Ctr ctr{(uint32_t)es.si, (uint32_t)c.rngview << 16, 0u, 1u};
     const float4 u = draw4(ctr, 0, 3, Key{p.seed, S.scene_id});
+    // stratified over the view's ne samples: sample si takes the CDF at (si + u0) / ne, so
+    // consecutive samples walk along the CDF (coherent side rays and accumulators)
     es.e = cdf_guided(p.pcdf + (size_t)es.v * (p.ne + 1), S.ne, p.pguide + ((size_t)es.v << p.pglog), p.pglog,
-                      (double)u.x);
+                      ((double)es.si + (double)u.x) / (double)c.ne);
     es.t = u.y;
     const int4 E = S.edges[es.e];
     double ax, ay, az, bx, by, bz;
@@ -556,38 +558,73 @@ __global__ void __launch_bounds__(EDGE_CAM_BLOCK) k_edge_camera(BwdParams p, Que
     }
 }
 
+// sum of v over the lanes of the wave whose flag is set (every lane takes part)
+__device__ __forceinline__ double wave_sum_masked(bool in, double v) {
+    double s = in ? v : 0.0;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    return s;
+}
+
 __global__ void k_edge_grad(BwdParams p, const float* __restrict__ Ls, const uint32_t* __restrict__ hs,
                             long long total) {
     const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long ge = blockIdx.x * (long long)blockDim.x + threadIdx.x; ge < total; ge += stride) {
+    const int lane = (int)(threadIdx.x & 63u);
+    // whole waves iterate together: the reduction below needs every lane
+    for (long long w0 = blockIdx.x * (long long)blockDim.x + (threadIdx.x & ~63u); w0 < total; w0 += stride) {
+        const long long ge = w0 + lane;
         EdgeSample es;
-        if (!edge_setup(p, ge, es)) continue;
-        const DevCam& c = p.cams[es.v];
-        const DevScene& S = p.scenes[c.scene];
-        Hash h{FNV_INIT, p.dbg_edge_hash != nullptr};
-        if (!es.inside) {
-            h.push((uint32_t)es.e);
-            h.push(0u);
-            if (p.dbg_edge_hash) p.dbg_edge_hash[ge] = h.h;
-            continue;
+        bool has = false;
+        double a0 = 0.0, a1 = 0.0;
+        long long key = -1;
+        if (ge < total && edge_setup(p, ge, es)) {
+            const DevCam& c = p.cams[es.v];
+            Hash h{FNV_INIT, p.dbg_edge_hash != nullptr};
+            if (!es.inside) {
+                h.push((uint32_t)es.e);
+                h.push(0u);
+                if (p.dbg_edge_hash) p.dbg_edge_hash[ge] = h.h;
+            } else {
+                const float* di = p.d_image + 3 * (c.pixoff + (long long)es.py * c.W + es.px);
+                if (!(di[0] == 0.0f && di[1] == 0.0f && di[2] == 0.0f)) {
+                    h.push((uint32_t)es.e);
+                    h.push(1u);
+                    if (p.dbg_edge_hash) {
+                        h.push(hs[2 * ge]);
+                        h.push(hs[2 * ge + 1]);
+                        p.dbg_edge_hash[ge] = h.h;
+                    }
+                    const float* lm = Ls + 6 * ge;
+                    const double cc = ((double)di[0] * ((double)lm[0] - lm[3]) +
+                                       (double)di[1] * ((double)lm[1] - lm[4]) +
+                                       (double)di[2] * ((double)lm[2] - lm[5])) * (p.ptotal[es.v] / (double)c.ne);
+                    a0 = cc * (1.0 - es.t);
+                    a1 = cc * es.t;
+                    key = (long long)es.v * p.ne + es.e;
+                    has = true;
+                }
+            }
         }
-        const float* di = p.d_image + 3 * (c.pixoff + (long long)es.py * c.W + es.px);
-        if (di[0] == 0.0f && di[1] == 0.0f && di[2] == 0.0f) continue;
-        h.push((uint32_t)es.e);
-        h.push(1u);
-        if (p.dbg_edge_hash) {
-            h.push(hs[2 * ge]);
-            h.push(hs[2 * ge + 1]);
-            p.dbg_edge_hash[ge] = h.h;
-        }
-        const float* lm = Ls + 6 * ge;
-        const double cc = ((double)di[0] * ((double)lm[0] - lm[3]) + (double)di[1] * ((double)lm[1] - lm[4]) +
-                           (double)di[2] * ((double)lm[2] - lm[5])) * (p.ptotal[es.v] / (double)c.ne);
         // the screen-space Jacobian and the edge normal depend on (view, edge) only:
-        // sum the two endpoint weights here, apply them once in k_edge_finish
-        double* acc = p.pacc + 2 * ((size_t)es.v * p.ne + es.e);
-        atomicAdd(acc, cc * (1.0 - es.t));
-        atomicAdd(acc + 1, cc * es.t);
+        // the two endpoint weights are summed per (view, edge) here and applied once in
+        // k_edge_finish; lanes of a wave that share a (view, edge) (consecutive
+        // stratified samples mostly do) are summed first, one atomic pair per group
+        bool pending = has;
+        for (;;) {
+            const uint64_t m = __ballot(pending);
+            if (!m) break;
+            const int leader = __ffsll((long long)m) - 1;
+            const long long lk = ((long long)__builtin_amdgcn_readlane((int)(key >> 32), leader) << 32) |
+                                 (unsigned int)__builtin_amdgcn_readlane((int)(key & 0xFFFFFFFFll), leader);
+            const bool mine = pending && key == lk;
+            const double s0 = wave_sum_masked(mine, a0), s1 = wave_sum_masked(mine, a1);
+            if (lane == leader) {
+                double* acc = p.pacc + 2 * (size_t)lk;
+                atomicAdd(acc, s0);
+                atomicAdd(acc + 1, s1);
+            }
+            pending = pending && !mine;
+        }
     }
 }
 
@@ -711,8 +748,9 @@ __device__ void shadow_edge_one(const BwdParams& p, const DevScene& S, const Dev
     if (!(p.ltotal[l] > 0.0)) return;
     const Ctr ctr{(uint32_t)si, ((uint32_t)c.rngview << 16) | (uint32_t)l, 0u, 3u};
     const float4 u = draw4(ctr, 0, 3, Key{p.seed, S.scene_id});
+    // stratified over the nsv samples of the (view, light) pair
     const int e = cdf_guided(p.lcdf + (size_t)l * (p.ne + 1), S.ne, p.lguide + ((size_t)l << p.pglog), p.pglog,
-                             (double)u.x);
+                             ((double)si + (double)u.x) / (double)nsv);
     const float t = u.y;
     h.push((uint32_t)e);
     const int4 E = S.edges[e];

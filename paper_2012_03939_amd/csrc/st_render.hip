@@ -17,7 +17,7 @@ namespace st {
 #define ST_EXTEND_WAVES 8
 #endif
 #ifndef ST_SHADOW_WAVES
-#define ST_SHADOW_WAVES 7
+#define ST_SHADOW_WAVES 8
 #endif
 #define SHADE_OCC __attribute__((amdgpu_waves_per_eu(ST_SHADE_WAVES)))
 #ifndef ST_SHADE_BLOCK
@@ -244,8 +244,7 @@ __global__ void __launch_bounds__(SHADE_BLOCK) SHADE_OCC k_shade(FwdParams p, Qu
     }
 }
 
-// shadow rays of bounce k: entry l of shading point i is item l * n + i;
-// persistent waves take items from the fetch counters of slot k and store one
+// shadow rays of bounce k: entry l of shading point i is item l * n + i; one
 // outcome code per entry (0 no ray, 1 occluded, 2 unoccluded)
 __global__ void __launch_bounds__(TRACE_BLOCK) SHADOW_OCC k_shadow(FwdParams p, Queues q, int k) {
     __shared__ uint32_t lds[LDS_STACK * TRACE_BLOCK];
@@ -253,28 +252,20 @@ __global__ void __launch_bounds__(TRACE_BLOCK) SHADOW_OCC k_shadow(FwdParams p, 
     const int n = q.cnt[k];
     float* const* r = q.ray[k & 1];
     const long long items = (long long)n * q.nent;
-    trace_queue<true>(
-        q.fetch + FETCH_SLOT_INTS * k, (int)items, st,
-        [&](int w, RayJob& J) {
-            const int l = w / n, i = w - l * n;
-            const size_t e = (size_t)l * q.cap + i;
-            const int f = q.sface[i];
-            if (f < 0) return false;
-            const DevScene& S = p.scenes[p.cams[qu(r, QVD, i) & 0xFFFFu].scene];
-            if (l >= S.nl + (S.has_env ? 1 : 0)) return false;      // entry unused in this scene
-            const float tmax = q.sh[3][e];
-            if (!(tmax >= 0.0f)) { q.socc[e] = 0; return false; }
-            J.o = V3{q.sx[0][i], q.sx[1][i], q.sx[2][i]};
-            J.d = V3{q.sh[0][e], q.sh[1][e], q.sh[2][e]};
-            J.tmax = tmax;
-            J.excl = f;
-            J.G = trace_geo(S);
-            return true;
-        },
-        [&](int w, int occ, float) {
-            const int l = w / n, i = w - l * n;
-            q.socc[(size_t)l * q.cap + i] = occ ? 1 : 2;
-        });
+    // 64 consecutive entries per wave (one light, consecutive shading points), in lockstep
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long w = blockIdx.x * (long long)blockDim.x + threadIdx.x; w < items; w += stride) {
+        const int l = (int)(w / n), i = (int)(w - (long long)l * n);
+        const size_t e = (size_t)l * q.cap + i;
+        const int f = q.sface[i];
+        if (f < 0) continue;
+        const DevScene& S = p.scenes[p.cams[qu(r, QVD, i) & 0xFFFFu].scene];
+        if (l >= S.nl + (S.has_env ? 1 : 0)) continue;      // entry unused in this scene
+        const float tmax = q.sh[3][e];
+        if (!(tmax >= 0.0f)) { q.socc[e] = 0; continue; }
+        const V3 o{q.sx[0][i], q.sx[1][i], q.sx[2][i]}, dd{q.sh[0][e], q.sh[1][e], q.sh[2][e]};
+        q.socc[e] = trace_any(S, o, dd, TMIN, tmax, f, st) ? 1 : 2;
+    }
 }
 
 // shadow contributions of bounce k added per shading point in entry order
