@@ -138,7 +138,7 @@ void st::prof_end(hipStream_t s) {
 
 struct st_scene {
     SceneDev d;
-    GrowBuf Lbuf, qbuf, spillbuf, primbuf, sidebuf, sidehash;
+    GrowBuf Lbuf, qbuf, spillbuf, primbuf, sidebuf, sidehash, secbuf;
     // immutable device tables of camera records, offsets and scene views, keyed
     // by content: written once by an uncaptured call, then reused (also by graphs)
     struct CamTable { uint64_t hash; std::vector<char> host; void* dev; void* pinned; };
@@ -792,6 +792,16 @@ int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_
     p.rec_face = use_rec ? (const int*)sc->recbuf.p : nullptr;
     p.rec_occ = use_rec ? (const uint32_t*)((const int*)sc->recbuf.p + (size_t)(bounces + 1) * cs.total_paths) : nullptr;
     p.rec_n = use_rec ? cs.total_paths : 0;
+    // secondary edges deferred to a job pass (not when decision hashes are asked for:
+    // those follow the inline order)
+    p.sec_mask = nullptr;
+    p.sec_jobs = nullptr;
+    p.sec_njobs = nullptr;
+    if ((p.flags & ST_EDGE_SECONDARY) && !o.debug_decision_hash && cs.total_paths > 0 && sc->d.ne > 0) {
+        rc = sc->secbuf.ensure(sec_workspace_bytes(cs.total_paths, bounces));
+        if (rc) return rc;
+        carve_sec_workspace(p, sc->secbuf.p, cs.total_paths);
+    }
     launch_fill_f32(out_dV, 3ll * sc->d.nv, 0.0f, s);
     launch_fill_f32(out_dmat, 7ll * sc->d.ntex, 0.0f, s);
     if (o.debug_decision_hash) launch_fill_u32(o.debug_decision_hash, cs.total_paths, 0u, s);
@@ -1005,7 +1015,7 @@ void st_scene_destroy(st_scene* sc) {
     for (void* p : ptrs)
         if (p) hipFree(p);
     sc->Lbuf.release(); sc->qbuf.release(); sc->spillbuf.release(); sc->primbuf.release(); sc->recbuf.release();
-    sc->sidebuf.release(); sc->sidehash.release();
+    sc->sidebuf.release(); sc->sidehash.release(); sc->secbuf.release();
     for (auto& t : sc->tables) {
         if (t.dev) hipFree(t.dev);
         if (t.pinned) hipHostFree(t.pinned);

@@ -121,17 +121,33 @@ __device__ __forceinline__ void face_reduce_add(bool has, int f, int tx, const f
 #ifndef ST_ADJ_WAVES
 #define ST_ADJ_WAVES 4
 #endif
-template <int BM>
+// JOBS = false: one thread per path sample (qq < total).  With p.sec_mask set,
+// an accepted secondary edge sample only marks bit k of the path's mask; its
+// side paths, its direct term and its pseudo term (propagated back along the
+// path) are left to the JOBS = true pass, one thread per marked (path, vertex),
+// which replays the path with the interior term off and processes that vertex
+// alone.  Accepted samples are rare, so inline they would hold whole waves for
+// one lane's side paths; as jobs they fill the lanes.
+template <int BM, bool JOBS>
 __global__ void __launch_bounds__(TRACE_BLOCK) __attribute__((amdgpu_waves_per_eu(ST_ADJ_WAVES)))
 k_adjoint(BwdParams p, long long total) {
     __shared__ uint32_t lds[LDS_STACK * TRACE_BLOCK];
     __shared__ float red_s[TRACE_BLOCK / 64][FACC];
     float* const red = red_s[threadIdx.x >> 6];
     TravStack st = make_trav_stack(lds, p.spill, p.err, p.work ? p.work + 3 * WORK_ADJOINT : nullptr);
-    const bool want_interior = p.flags & 1u, want_secondary = p.flags & 4u;
+    const bool want_interior = !JOBS && (p.flags & 1u), want_secondary = p.flags & 4u;
     const bool sec_interior = p.flags & ST_EDGE_SECONDARY_INTERIOR;   // creases / material edges too
+    const bool defer = !JOBS && p.sec_mask != nullptr;
     const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long qq = blockIdx.x * (long long)blockDim.x + threadIdx.x; qq < total; qq += stride) {
+    const long long count = JOBS ? (long long)*p.sec_njobs : total;
+    for (long long it = blockIdx.x * (long long)blockDim.x + threadIdx.x; it < count; it += stride) {
+        int ksel = -1;
+        long long qq = it;
+        if (JOBS) {
+            const int2 jb = p.sec_jobs[it];
+            qq = jb.x;
+            ksel = jb.y;
+        }
         const int vw = find_view(p.qoff, p.ncam, qq);
         const DevCam& c = p.cams[vw];
         const DevScene& S = p.scenes[c.scene];
@@ -263,9 +279,10 @@ k_adjoint(BwdParams p, long long total) {
 
         // ---- secondary edge samples (side paths in their own stream) --------
         if (want_secondary) {
+            uint32_t accepted = 0;
             for (int k = 0; k < nvtx; ++k) {
                 const int e = sel(rse, k);
-                if (e < 0) continue;
+                if (e < 0 || (JOBS && k != ksel)) continue;
                 h.push((uint32_t)e);
                 const int f = sel(rf, k);
                 const V3 xh = sel(rx, k);
@@ -290,6 +307,7 @@ k_adjoint(BwdParams p, long long total) {
                 }
                 if (!ok) { h.push(0u); continue; }
                 h.push(1u);
+                if (defer) { accepted |= 1u << k; continue; }
                 const V3 mm = mv * (1.0f / ml);
                 const Ctr sc{ctr.c0, ctr.c1, (uint32_t)(k + 1) << 16, 2u};
                 V3 Ls[2];
@@ -307,6 +325,7 @@ k_adjoint(BwdParams p, long long total) {
                 atomic_add3(p.dV + 3 * (size_t)E.x, mv * (cc * (1.0f - te)));
                 atomic_add3(p.dV + 3 * (size_t)E.y, mv * (cc * te));
             }
+            if (defer && accepted) p.sec_mask[qq] = (uint8_t)accepted;
         }
 
         // ---- reverse sweep ------------------------------------------------
@@ -916,16 +935,60 @@ void launch_primary_edges(const BwdParams& p, const FwdParams& fp, Queues& q, fl
     ST_LAUNCH("k_edge_finish", k_edge_finish, dim3(gridb(p.ne, 256, 1024), p.ncam), dim3(256), 0, st, p);
 }
 
+// (path, vertex) jobs of the marked secondary edge samples, in blocks of 256
+// paths with one counter reservation per block and bit
+__global__ void __launch_bounds__(256) k_sec_jobs(const uint8_t* __restrict__ mask, long long total, int B,
+                                                 int2* jobs, int* njobs) {
+    __shared__ int resv[256 / 64 + 1];
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long b0 = (long long)blockIdx.x * blockDim.x; b0 < total; b0 += stride) {
+        const long long i = b0 + threadIdx.x;
+        const uint32_t m = i < total ? mask[i] : 0u;
+        for (int k = 0; k < B; ++k) {
+            const bool emit = (m >> k) & 1u;
+            const int o = block_reserve<256, 1>(emit, njobs, resv);
+            if (emit) jobs[o] = make_int2((int)i, k);
+        }
+    }
+}
+
+size_t sec_workspace_bytes(long long total_paths, int B) {
+    return 256 + (((size_t)total_paths + 255) & ~(size_t)255) + sizeof(int2) * (size_t)total_paths * B + 256;
+}
+
+void carve_sec_workspace(BwdParams& p, void* base, long long total_paths) {
+    char* c = (char*)base;
+    p.sec_njobs = (int*)c;
+    p.sec_mask = (uint8_t*)(c + 256);
+    p.sec_jobs = (int2*)(c + 256 + (((size_t)total_paths + 255) & ~(size_t)255));
+}
+
+template <int BM>
+static void launch_adjoint(const BwdParams& p, long long total_paths, int grid, const char* name,
+                           const char* name_jobs, hipStream_t st) {
+    const dim3 gd(gridb(total_paths, TRACE_BLOCK, grid)), bd(TRACE_BLOCK);
+    if (p.sec_mask) {
+        launch_fill_u32((uint32_t*)p.sec_njobs, 1, 0u, st);
+        launch_fill_u32((uint32_t*)p.sec_mask, (total_paths + 3) / 4, 0u, st);
+    }
+    ST_LAUNCH(name, (k_adjoint<BM, false>), gd, bd, 0, st, p, total_paths);
+    if (p.sec_mask) {
+        ST_LAUNCH("k_sec_jobs", k_sec_jobs, dim3(gridb(total_paths, 256, 1 << 14)), dim3(256), 0, st, p.sec_mask,
+                  total_paths, p.B, p.sec_jobs, p.sec_njobs);
+        // the job count stays on the device: a fixed grid strides over it
+        ST_LAUNCH(name_jobs, (k_adjoint<BM, true>), dim3(1024), bd, 0, st, p, 0ll);
+    }
+}
+
 void launch_backward(const BwdParams& p, int nv, int nf, long long total_paths, long long total_edges, int grid,
                      hipStream_t st) {
     if ((p.flags & 5u) && total_paths > 0) {
         launch_fill_u32((uint32_t*)p.facc, 9ll * nf, 0u, st);
         launch_fill_u32((uint32_t*)p.macc, 7ll * p.ntex, 0u, st);
-        const dim3 gd(gridb(total_paths, TRACE_BLOCK, grid)), bd(TRACE_BLOCK);
-        if (p.B <= 1) ST_LAUNCH("k_adjoint<1>", k_adjoint<1>, gd, bd, 0, st, p, total_paths);
-        else if (p.B <= 2) ST_LAUNCH("k_adjoint<2>", k_adjoint<2>, gd, bd, 0, st, p, total_paths);
-        else if (p.B <= 3) ST_LAUNCH("k_adjoint<3>", k_adjoint<3>, gd, bd, 0, st, p, total_paths);
-        else ST_LAUNCH("k_adjoint<8>", k_adjoint<8>, gd, bd, 0, st, p, total_paths);
+        if (p.B <= 1) launch_adjoint<1>(p, total_paths, grid, "k_adjoint<1>", "k_adjoint_sec<1>", st);
+        else if (p.B <= 2) launch_adjoint<2>(p, total_paths, grid, "k_adjoint<2>", "k_adjoint_sec<2>", st);
+        else if (p.B <= 3) launch_adjoint<3>(p, total_paths, grid, "k_adjoint<3>", "k_adjoint_sec<3>", st);
+        else launch_adjoint<8>(p, total_paths, grid, "k_adjoint<8>", "k_adjoint_sec<8>", st);
         ST_LAUNCH("k_face_gather", k_face_gather, dim3(gridb(std::max<long long>(nv, p.ntex), 256, 4096)), dim3(256), 0,
                   st, p);
     }

@@ -191,10 +191,18 @@ struct BwdParams {
     const int* rec_face;     // hit records of the matching forward pass, or null (trace again)
     const uint32_t* rec_occ;
     long long rec_n;
+    // deferred secondary edges (null: traced inline): accepted vertices per path
+    // (bit k), then the compacted (path, vertex) jobs and their count
+    uint8_t* sec_mask;
+    int2* sec_jobs;
+    int* sec_njobs;
 };
 
 void launch_backward(const BwdParams& p, int nv, int nf, long long total_paths, long long total_edges, int grid,
                      hipStream_t st);
+// bytes of the deferred secondary-edge workspace for total_paths paths of B bounces
+size_t sec_workspace_bytes(long long total_paths, int B);
+void carve_sec_workspace(BwdParams& p, void* base, long long total_paths);
 // primary edges with their side paths traced by the wavefront kernels
 // point-light shadow boundaries (ST_EDGE_SHADOW); total_edges = primary edge samples
 void launch_shadow_edges(const BwdParams& p, long long total_edges, int nl, hipStream_t st);
