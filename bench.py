@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--cpu-baseline-res", type=int, default=1024)
     ap.add_argument("--env-sampler", choices=["cdf", "alias"], default="cdf",
                     help="environment texel draw: row/column CDFs or the alias table (same distribution)")
+    ap.add_argument("--bsdf-sampler", choices=["halfvector", "vndf"], default="halfvector",
+                    help="specular half-vectors from D cos(theta_h) or from the visible normals")
     ap.add_argument("--profile-only", action="store_true", help="one untimed step (for rocprofv3 runs)")
     ap.add_argument("--copy-reference", action="store_true",
                     help="only a plain 512 MiB device copy: the reference that scales the HBM byte counters")
@@ -176,6 +178,7 @@ def main():
     sc = wl.scenes[0]
     g = B.GPUScene.from_scene(sc)
     g.set_env_sampler(B.ST_ENV_SAMPLER_ALIAS if args.env_sampler == "alias" else B.ST_ENV_SAMPLER_CDF)
+    g.set_bsdf_sampler(B.ST_BSDF_SAMPLER_VNDF if args.bsdf_sampler == "vndf" else B.ST_BSDF_SAMPLER_HALFVECTOR)
     cams, spp, bounces = wl.cams, wl.spp, wl.bounces
     npix = B.num_pixels(cams)
     n_paths = npix * spp
@@ -266,7 +269,7 @@ def main():
         "config": {"workload": wl.name, "faces": int(sc.F.shape[0]), "views": len(cams), "res": args.res,
                    "spp": spp, "bounces": bounces, "path_samples_per_step": n_paths,
                    "edge_samples_per_step": B.num_edge_samples(cams, spp, 1.0, int(sc.lights.shape[0])),
-                   "envmap": "512x256", "env_sampler": args.env_sampler},
+                   "envmap": "512x256", "env_sampler": args.env_sampler, "bsdf_sampler": args.bsdf_sampler},
         "roofline": {"bound": "alu", "kernel": dom_name, "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": measured_traffic(dom_name),
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-scaled)",

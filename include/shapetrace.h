@@ -156,6 +156,19 @@ int st_scene_set_env_sampler(st_scene* scene, int32_t method, hipStream_t s);
  * inspection; ST_ERR_INVALID_ARG before the table is built. */
 int st_scene_env_alias_table(const st_scene* scene, double* prob, int32_t* alias);
 
+/* How the specular lobe of the BRDF mixture (Sec. 3.3 Torrance-Sparrow; lobe
+ * chosen with probability 1/2) draws its half-vector h:
+ *   ST_BSDF_SAMPLER_HALFVECTOR (default): h ~ D(h) cos(theta_h);
+ *   ST_BSDF_SAMPLER_VNDF: h ~ the normals visible from wo, G1(wo) max(0, wo.h)
+ *   D(h) / cos(theta_o) (Heitz and d'Eon 2014, Beckmann: stretched slopes, the
+ *   in-plane slope by bracketed Newton on its CDF, the other by erfinv).
+ * Both are unbiased with their own pdf (used for the path weight and the MIS
+ * weights); VNDF never samples back-facing microfacets.  Changes the scene's
+ * state (hit records of earlier renders are dropped); synchronises s. */
+#define ST_BSDF_SAMPLER_HALFVECTOR 0
+#define ST_BSDF_SAMPLER_VNDF 1
+int st_scene_set_bsdf_sampler(st_scene* scene, int32_t method, hipStream_t s);
+
 /* Forward render (Sec. 3.2, R(x, c_i)).  cams: host array of ncam cameras.
  * out: device float [sum_i width_i*height_i, 3], views concatenated, each row-major;
  * every pixel is the mean of spp path samples with a one-pixel box filter.

@@ -58,9 +58,12 @@ def lib():
         L.or_edge_total.restype = ctypes.c_double
         L.or_philox.argtypes = [P, P, P]
         L.or_brdf.argtypes = [P, P, P, P, P]
-        L.or_bsdf_pdf.argtypes = [P, P, P, ctypes.c_double]
+        L.or_bsdf_pdf.argtypes = [P, P, P, ctypes.c_double, ctypes.c_int]
         L.or_bsdf_pdf.restype = ctypes.c_double
-        L.or_bsdf_sample.argtypes = [P, P, P, ctypes.c_double, P]
+        L.or_bsdf_sample.argtypes = [P, P, P, ctypes.c_double, ctypes.c_int, P]
+        L.or_scene_set_vndf.argtypes = [P, ctypes.c_int]
+        L.or_erfinv.argtypes = [ctypes.c_double]
+        L.or_erfinv.restype = ctypes.c_double
         L.or_beckmann_D.argtypes = [ctypes.c_double, ctypes.c_double]
         L.or_beckmann_D.restype = ctypes.c_double
         L.or_smith_lambda.argtypes = [ctypes.c_double, ctypes.c_double]
@@ -148,6 +151,10 @@ class OracleScene:
         if got != n:
             raise ValueError("oracle rejected the mesh-colour resolution")
         self.tex_res, self.ntex = int(r), n
+
+    def set_vndf(self, on=True):
+        """Sample the specular lobe from the visible normals (on) or from D cos(theta_h)."""
+        lib().or_scene_set_vndf(self.h, int(bool(on)))
 
     def set_env_alias(self, on=True):
         """Choose environment texels through the alias table (on) or the CDFs."""
@@ -312,14 +319,18 @@ def brdf(wi, wo, n, m):
     return out
 
 
-def bsdf_pdf(wi, wo, n, alpha):
-    return lib().or_bsdf_pdf(_p(_f64(wi)), _p(_f64(wo)), _p(_f64(n)), alpha)
+def bsdf_pdf(wi, wo, n, alpha, vndf=False):
+    return lib().or_bsdf_pdf(_p(_f64(wi)), _p(_f64(wo)), _p(_f64(n)), alpha, int(bool(vndf)))
 
 
-def bsdf_sample(u, wo, n, alpha):
+def bsdf_sample(u, wo, n, alpha, vndf=False):
     wi = np.zeros(3)
-    lobe = lib().or_bsdf_sample(_p(_f64(u)), _p(_f64(wo)), _p(_f64(n)), alpha, _p(wi))
+    lobe = lib().or_bsdf_sample(_p(_f64(u)), _p(_f64(wo)), _p(_f64(n)), alpha, int(bool(vndf)), _p(wi))
     return lobe, wi
+
+
+def erfinv(y):
+    return lib().or_erfinv(float(y))
 
 
 def beckmann_D(ch, a):

@@ -176,6 +176,7 @@ struct Scene {
     std::vector<double> marg, cond, texp;   // env CDFs and texel probabilities
     double env_total = 0.0;
     bool env_alias = false;                 // texel chosen through the alias table instead of the CDFs
+    bool vndf = false;                      // specular lobe sampled from the visible normals
     std::vector<double> aprob;              // Walker/Vose alias table over the texels
     std::vector<int> alias;
     std::vector<BVHNode> nodes;
@@ -586,8 +587,11 @@ static V3<T> brdf(const V3<T>& wi, const V3<T>& wo, const V3<T>& n, const T* m) 
     return V3<T>(m[0] * (1.0 / PI) + m[3] * spec, m[1] * (1.0 / PI) + m[4] * spec, m[2] * (1.0 / PI) + m[5] * spec);
 }
 
-// pdf of the one-sample mixture: 1/2 cosine-weighted + 1/2 Beckmann-D cos(theta_h) half-vectors
-static double bsdf_pdf(const D3& wi, const D3& wo, const D3& n, double alpha) {
+// pdf of the one-sample mixture: 1/2 cosine-weighted + 1/2 specular.  The
+// specular half-vectors follow D(h) cos(theta_h) (classical), or with vndf the
+// distribution of normals visible from wo, G1(wo) max(0, wo.h) D(h) / cos(theta_o)
+// (Heitz and d'Eon 2014); either is turned into a pdf of wi by 1 / (4 |wo.h|).
+static double bsdf_pdf(const D3& wi, const D3& wo, const D3& n, double alpha, bool vndf) {
     double ci = dot(n, wi);
     if (!(ci > 0.0)) return 0.0;
     double a = std::max(alpha, ALPHA_MIN);
@@ -597,10 +601,79 @@ static double bsdf_pdf(const D3& wi, const D3& wo, const D3& n, double alpha) {
     double ps = 0.0;
     if (hl > 0.0) {
         D3 h = hv * (1.0 / hl);
-        double ch = dot(n, h), oh = std::fabs(dot(wo, h));
-        if (ch > 0.0 && oh > 0.0) ps = LOBE_SPEC_P * beckmann_D(ch, a) * ch / (4.0 * oh);
+        double ch = dot(n, h), oh = dot(wo, h);
+        if (!vndf) {
+            oh = std::fabs(oh);
+            if (ch > 0.0 && oh > 0.0) ps = LOBE_SPEC_P * beckmann_D(ch, a) * ch / (4.0 * oh);
+        } else {
+            double co = dot(n, wo);
+            if (ch > 0.0 && oh > 0.0 && co > 0.0) {
+                double g1 = 1.0 / (1.0 + smith_lambda(co, a));
+                ps = LOBE_SPEC_P * g1 * beckmann_D(ch, a) / (4.0 * co);
+            }
+        }
     }
     return pd + ps;
+}
+
+// inverse error function: Winitzki's closed-form approximation (S. Winitzki,
+// "A handy approximation for the error function and its inverse", 2008, a = 0.147)
+// refined by Newton steps on erf in double precision
+static double erfinv_d(double y) {
+    const double a = 0.147;
+    const double l = std::log((1.0 - y) * (1.0 + y));
+    const double t = 2.0 / (PI * a) + 0.5 * l;
+    double x = std::copysign(std::sqrt(std::sqrt(t * t - l / a) - t), y);
+    for (int it = 0; it < 8; ++it) {
+        // erf(x) - y, taken through erfc near |y| = 1 where erf(x) and y cancel
+        const double r = y > 0.5 ? (1.0 - y) - std::erfc(x) : y < -0.5 ? std::erfc(-x) - (1.0 + y) : std::erf(x) - y;
+        const double d = r / (2.0 / std::sqrt(PI) * std::exp(-x * x));
+        x -= d;
+        if (std::fabs(d) < 1e-16 * std::max(1.0, std::fabs(x))) break;
+    }
+    return x;
+}
+
+// Visible-normal sampling of the Beckmann lobe (Heitz and d'Eon 2014): stretch
+// wo by alpha; for the standard surface seen at cot(theta') = c, the slope along
+// the incident plane has density ~ (c - x) exp(-x^2) on x < c, whose integral
+// F(x) = c sqrt(pi)/2 erfc(-x) + exp(-x^2) / 2 is inverted at u1 F(c); the
+// other slope is erfinv(2 u2 - 1); rotate back, unstretch, normal from slopes.
+static const double VNDF_COT_MAX = 1e4;         // cot(theta') at (near) normal incidence
+static const double VNDF_Y_MAX = 1.0 - 1.0 / 8388608.0;   // |2 u2 - 1| kept below 1 (u2 = 0)
+
+static double vndf_F(double x, double c) {
+    return c * (0.5 * std::sqrt(PI)) * std::erfc(-x) + 0.5 * std::exp(-x * x);
+}
+// F(c) - F(x), without the cancellation of the difference near x = c
+static double vndf_G(double x, double c) {
+    return c * (0.5 * std::sqrt(PI)) * (std::erfc(x) - std::erfc(c)) + 0.5 * (std::exp(-c * c) - std::exp(-x * x));
+}
+
+static D3 vndf_normal(const D3& wo_l, double a, double u1, double u2) {
+    D3 ws = normalize(D3(a * wo_l.x, a * wo_l.y, wo_l.z));
+    double st = std::sqrt(ws.x * ws.x + ws.y * ws.y);
+    double cphi = st > 0.0 ? ws.x / st : 1.0, sphi = st > 0.0 ? ws.y / st : 0.0;
+    double c = st > 0.0 ? std::min(ws.z / st, VNDF_COT_MAX) : VNDF_COT_MAX;
+    // bracketed Newton over (-8, c): F(x) = u1 F(c) on the lower half of u1,
+    // F(c) - F(x) = (1 - u1) F(c) on the upper half
+    const bool upper = u1 > 0.5;
+    const double target = (upper ? 1.0 - u1 : u1) * vndf_F(c, c);
+    // (the root lies below 8: F(8) equals F(c) to far below double rounding)
+    double lo = -8.0, hi = std::min(c, 8.0), x = std::min(0.0, 0.5 * c);
+    for (int it = 0; it < 100; ++it) {
+        double g = upper ? target - vndf_G(x, c) : vndf_F(x, c) - target;    // increasing in x
+        if (g > 0.0) hi = x; else lo = x;
+        double dg = (c - x) * std::exp(-x * x);
+        double xn = dg > 0.0 ? x - g / dg : 0.5 * (lo + hi);
+        if (!(xn >= lo && xn <= hi)) xn = 0.5 * (lo + hi);
+        if (std::fabs(xn - x) < 1e-15 * std::max(1.0, std::fabs(x))) { x = xn; break; }
+        x = xn;
+    }
+    double yv = std::max(-VNDF_Y_MAX, std::min(VNDF_Y_MAX, 2.0 * u2 - 1.0));
+    double y = erfinv_d(yv);
+    double sx = (cphi * x - sphi * y) * a, sy = (sphi * x + cphi * y) * a;
+    return normalize(D3(-sx, -sy, 1.0));
 }
 
 // orthonormal basis around n (Duff et al. 2017, JCGT 6(1), branchless construction)
@@ -613,11 +686,17 @@ static void onb(const D3& n, D3& t, D3& b) {
 }
 
 // returns lobe (0 specular, 1 diffuse) and the sampled world direction
-static int bsdf_sample(const double u[4], const D3& wo, const D3& n, double alpha, D3& wi) {
+static int bsdf_sample(const double u[4], const D3& wo, const D3& n, double alpha, bool vndf, D3& wi) {
     D3 t, b;
     onb(n, t, b);
     double a = std::max(alpha, ALPHA_MIN);
     double phi = 2.0 * PI * u[2];
+    if (u[0] < LOBE_SPEC_P && vndf) {
+        D3 hl = vndf_normal(D3(dot(wo, t), dot(wo, b), dot(wo, n)), a, u[1], u[2]);
+        D3 h = t * hl.x + b * hl.y + n * hl.z;
+        wi = h * (2.0 * dot(wo, h)) - wo;
+        return 0;
+    }
     if (u[0] < LOBE_SPEC_P) {
         double t2 = -a * a * std::log(1.0 - u[1]);
         double ch = 1.0 / std::sqrt(1.0 + t2);
@@ -756,7 +835,7 @@ static D3 trace_estimator(const Scene& s, D3 o, D3 d, int exclude, int nvert, bo
                 code = occ ? 1 : 2;
                 if (!occ) {
                     D3 fv = brdf(we, wo, n, m);
-                    double pb = bsdf_pdf(we, wo, n, m[6]);
+                    double pb = bsdf_pdf(we, wo, n, m[6], s.vndf);
                     double den = pe + pb;
                     D3 Le = env_rgb(s, tex);
                     L = L + D3(beta.x * Le.x * fv.x, beta.y * Le.y * fv.y, beta.z * Le.z * fv.z) * (c / den);
@@ -823,9 +902,9 @@ static D3 trace_estimator(const Scene& s, D3 o, D3 d, int exclude, int nvert, bo
         double u[4];
         draw4(ctr, k, 2, key.k0, key.k1, u);
         D3 wi;
-        int lobe = bsdf_sample(u, wo, n, m[6], wi);
+        int lobe = bsdf_sample(u, wo, n, m[6], s.vndf, wi);
         double ci = dot(n, wi);
-        double pb = bsdf_pdf(wi, wo, n, m[6]);
+        double pb = bsdf_pdf(wi, wo, n, m[6], s.vndf);
         hash.push((uint32_t)lobe);
         if (!(ci > 0.0) || !(pb > 0.0)) { hash.push(0u); break; }
         hash.push(1u);
@@ -1564,6 +1643,14 @@ long long or_scene_set_texels(void* p, int r, const float* texels) {
 
 long long or_texel_index(int r, long long t, double alpha, double beta) { return texel_index(r, t, alpha, beta); }
 
+// Specular lobe sampled from the visible normals (on) or from D cos(theta_h) (off, the default).
+int or_scene_set_vndf(void* p, int on) {
+    ((Scene*)p)->vndf = on != 0;
+    return 0;
+}
+
+double or_erfinv(double y) { return erfinv_d(y); }
+
 // Environment texels chosen through the alias table (on) or the CDFs (off, the default).
 int or_scene_set_env_alias(void* p, int on) {
     Scene* s = (Scene*)p;
@@ -1603,13 +1690,13 @@ void or_brdf(const double* wi, const double* wo, const double* n, const double* 
     out[0] = r.x; out[1] = r.y; out[2] = r.z;
 }
 
-double or_bsdf_pdf(const double* wi, const double* wo, const double* n, double alpha) {
-    return bsdf_pdf(D3(wi[0], wi[1], wi[2]), D3(wo[0], wo[1], wo[2]), D3(n[0], n[1], n[2]), alpha);
+double or_bsdf_pdf(const double* wi, const double* wo, const double* n, double alpha, int vndf) {
+    return bsdf_pdf(D3(wi[0], wi[1], wi[2]), D3(wo[0], wo[1], wo[2]), D3(n[0], n[1], n[2]), alpha, vndf != 0);
 }
 
-int or_bsdf_sample(const double* u, const double* wo, const double* n, double alpha, double* wi) {
+int or_bsdf_sample(const double* u, const double* wo, const double* n, double alpha, int vndf, double* wi) {
     D3 w;
-    int lobe = bsdf_sample(u, D3(wo[0], wo[1], wo[2]), D3(n[0], n[1], n[2]), alpha, w);
+    int lobe = bsdf_sample(u, D3(wo[0], wo[1], wo[2]), D3(n[0], n[1], n[2]), alpha, vndf != 0, w);
     wi[0] = w.x; wi[1] = w.y; wi[2] = w.z;
     return lobe;
 }

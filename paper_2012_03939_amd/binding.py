@@ -28,9 +28,11 @@ ST_ALL_GRADS = 15
 ST_BACKWARD_RETRACE = 128
 ST_ENV_SAMPLER_CDF = 0
 ST_ENV_SAMPLER_ALIAS = 1
+ST_BSDF_SAMPLER_HALFVECTOR = 0
+ST_BSDF_SAMPLER_VNDF = 1
 
 EXPORTED = ["st_render_opts_default", "st_scene_create", "st_scene_update", "st_scene_set_mesh_colors",
-            "st_scene_mesh_colors_info", "st_scene_subdivide", "st_scene_set_env_sampler", "st_scene_env_alias_table", "st_render", "st_render_backward",
+            "st_scene_mesh_colors_info", "st_scene_subdivide", "st_scene_set_env_sampler", "st_scene_env_alias_table", "st_scene_set_bsdf_sampler", "st_render", "st_render_backward",
             "st_render_batch", "st_autotune", "st_check_errors", "st_read_work", "st_scene_info", "st_scene_edges", "st_scene_lbvh",
             "st_trace_rays", "st_profile_enable", "st_profile_read", "st_scene_destroy", "st_last_error",
             "st_version"]
@@ -71,6 +73,7 @@ def load(path: str = LIB_PATH):
     L.st_scene_mesh_colors_info.argtypes = [P, P, P]
     L.st_scene_subdivide.argtypes = [P, P, P, P]
     L.st_scene_set_env_sampler.argtypes = [P, I32, P]
+    L.st_scene_set_bsdf_sampler.argtypes = [P, I32, P]
     L.st_scene_env_alias_table.argtypes = [P, P, P]
     L.st_render.argtypes = [P, P, I32, I32, I32, U32, ctypes.POINTER(StOpts), P, P]
     L.st_render_backward.argtypes = [P, P, I32, I32, I32, U32, ctypes.POINTER(StOpts), P, P, P, P]
@@ -199,6 +202,10 @@ class GPUScene:
     def set_env_sampler(self, method: int):
         """ST_ENV_SAMPLER_CDF (default) or ST_ENV_SAMPLER_ALIAS for environment texels."""
         _check(load().st_scene_set_env_sampler(self.h, int(method), _stream()))
+
+    def set_bsdf_sampler(self, method: int):
+        """ST_BSDF_SAMPLER_HALFVECTOR (default) or ST_BSDF_SAMPLER_VNDF for the specular lobe."""
+        _check(load().st_scene_set_bsdf_sampler(self.h, int(method), _stream()))
 
     def env_alias_table(self):
         """(prob float64 [he*we], alias int32 [he*we]) of the built alias table."""

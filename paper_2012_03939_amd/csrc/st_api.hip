@@ -555,6 +555,7 @@ int st_scene_create(const float* V, int32_t nv, const int32_t* F, int32_t nf, co
     h.tex_res = 0;
     h.ealias = nullptr;
     h.env_alias = 0;
+    h.vndf = 0;
     h.scene_id = scene_id;
     HIPCHK2(hipMemcpyAsync(d.dscene, &h, sizeof(DevScene), hipMemcpyHostToDevice, s));
     HIPCHK2(hipStreamSynchronize(s));
@@ -678,6 +679,20 @@ int st_scene_set_env_sampler(st_scene* sc, int32_t method, hipStream_t s) {
     }
     d.hscene.ealias = d.ealias;
     d.hscene.env_alias = method == ST_ENV_SAMPLER_ALIAS ? 1 : 0;
+    ++sc->version;
+    sc->rec_valid = false;
+    HIPCHK(hipMemcpyAsync(d.dscene, &d.hscene, sizeof(DevScene), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return ST_OK;
+}
+
+int st_scene_set_bsdf_sampler(st_scene* sc, int32_t method, hipStream_t s) {
+    int rc = check_scene(sc);
+    if (rc) return rc;
+    if (method != ST_BSDF_SAMPLER_HALFVECTOR && method != ST_BSDF_SAMPLER_VNDF)
+        return fail(ST_ERR_INVALID_ARG, "unknown BRDF sampler");
+    SceneDev& d = sc->d;
+    d.hscene.vndf = method == ST_BSDF_SAMPLER_VNDF ? 1 : 0;
     ++sc->version;
     sc->rec_valid = false;
     HIPCHK(hipMemcpyAsync(d.dscene, &d.hscene, sizeof(DevScene), hipMemcpyHostToDevice, s));

@@ -242,7 +242,7 @@ k_adjoint(BwdParams p, long long total) {
                         if (!occ) {
                             fl |= R_ENV;
                             put(rwe, k - 1, we);
-                            put(rden, k - 1, pe + bsdf_pdf(we, wo, n, m.a));
+                            put(rden, k - 1, pe + bsdf_pdf(we, wo, n, m.a, S.vndf));
                             put(rtex, k - 1, tex);
                         }
                     }
@@ -261,9 +261,9 @@ k_adjoint(BwdParams p, long long total) {
                 if (!continues) { put(rfl, k - 1, fl); break; }
                 const float4 u = draw4(ctr, k, 2, key);
                 V3 wi;
-                const int lobe = bsdf_sample(u, wo, n, m.a, wi);
+                const int lobe = bsdf_sample(u, wo, n, m.a, S.vndf, wi);
                 const float ci = dot(n, wi);
-                const float pb = bsdf_pdf(wi, wo, n, m.a);
+                const float pb = bsdf_pdf(wi, wo, n, m.a, S.vndf);
                 h.push((uint32_t)lobe);
                 if (!(ci > 0.0f) || !(pb > 0.0f)) { h.push(0u); put(rfl, k - 1, fl); break; }
                 h.push(1u);

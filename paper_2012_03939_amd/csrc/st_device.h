@@ -134,6 +134,7 @@ struct DevScene {
     const int* cguide;    // guide tables of the env conditional CDFs, 2^cglog entries per row
     const EnvAlias* ealias; // [he*we] alias table of the texel probabilities, used when env_alias
     int env_alias;
+    int vndf;             // specular lobe sampled from the visible normals
     int eglog, mglog, cglog;
     int nv, nf, nl, he, we, ne, has_env;
     int tex_res;          // mesh-colours resolution r: mat has nf (r+1)(r+2)/2 rows
@@ -469,7 +470,11 @@ __device__ __forceinline__ V3 brdf_eval(V3 wi, V3 wo, V3 n, const Mat& m) {
     return m.kd * INV_PI_F + m.ks * spec;
 }
 
-__device__ __forceinline__ float bsdf_pdf(V3 wi, V3 wo, V3 n, float alpha) {
+// pdf of the one-sample mixture: 1/2 cosine-weighted + 1/2 specular, whose
+// half-vectors follow D(h) cos(theta_h), or with vndf the normals visible from
+// wo, G1(wo) max(0, wo.h) D(h) / cos(theta_o) (Heitz and d'Eon 2014); either
+// becomes a pdf of wi through 1 / (4 |wo.h|)
+__device__ __forceinline__ float bsdf_pdf(V3 wi, V3 wo, V3 n, float alpha, bool vndf) {
     const float ci = dot(n, wi);
     if (!(ci > 0.0f)) return 0.0f;
     const float a = alpha_eff(alpha);
@@ -479,10 +484,52 @@ __device__ __forceinline__ float bsdf_pdf(V3 wi, V3 wo, V3 n, float alpha) {
     float ps = 0.0f;
     if (hl > 0.0f) {
         const V3 h = hv * (1.0f / hl);
-        const float ch = dot(n, h), oh = fabsf(dot(wo, h));
-        if (ch > 0.0f && oh > 0.0f) ps = LOBE_SPEC_P * beckmann_D(n, h, ch, a) * ch / (4.0f * oh);
+        const float ch = dot(n, h);
+        if (!vndf) {
+            const float oh = fabsf(dot(wo, h));
+            if (ch > 0.0f && oh > 0.0f) ps = LOBE_SPEC_P * beckmann_D(n, h, ch, a) * ch / (4.0f * oh);
+        } else {
+            const float oh = dot(wo, h), co = dot(n, wo);
+            if (ch > 0.0f && oh > 0.0f && co > 0.0f) {
+                const float g1 = 1.0f / (1.0f + smith_lambda(co, a));
+                ps = LOBE_SPEC_P * g1 * beckmann_D(n, h, ch, a) / (4.0f * co);
+            }
+        }
     }
     return pd + ps;
+}
+
+// Visible-normal sample of the Beckmann lobe in the local frame (z = normal):
+// stretch wo by alpha; for the standard surface seen at cot(theta') = c the
+// slope along the incident plane has density ~ (c - x) exp(-x^2) on x < c with
+// integral F(x) = c sqrt(pi)/2 erfc(-x) + exp(-x^2)/2, inverted by bracketed
+// Newton steps (from below on the lower half of u1, through F(c) - F(x) on the
+// upper half); the other slope is erfinv(2 u2 - 1); rotate, unstretch.
+constexpr float VNDF_COT_MAX = 1e4f;
+constexpr float VNDF_Y_MAX = 1.0f - 1.0f / 8388608.0f;
+constexpr float HALF_SQRT_PI_F = 0.886226925452758013649f;
+__device__ __forceinline__ V3 vndf_normal(V3 wl, float a, float u1, float u2) {
+    const V3 ws = normalize(V3{a * wl.x, a * wl.y, wl.z});
+    const float st = sqrtf(ws.x * ws.x + ws.y * ws.y);
+    const float cphi = st > 0.0f ? ws.x / st : 1.0f, sphi = st > 0.0f ? ws.y / st : 0.0f;
+    const float c = st > 0.0f ? fminf(ws.z / st, VNDF_COT_MAX) : VNDF_COT_MAX;
+    const bool upper = u1 > 0.5f;
+    const float Fc = c * HALF_SQRT_PI_F * erfcf(-c) + 0.5f * expf(-c * c);
+    const float target = (upper ? 1.0f - u1 : u1) * Fc;
+    float lo = -8.0f, hi = fminf(c, 8.0f), x = fminf(0.0f, 0.5f * c);   // the root lies below 8
+    for (int it = 0; it < 24; ++it) {
+        const float ex = expf(-x * x);
+        const float g = upper ? target - (c * HALF_SQRT_PI_F * (erfcf(x) - erfcf(c)) + 0.5f * (expf(-c * c) - ex))
+                              : (c * HALF_SQRT_PI_F * erfcf(-x) + 0.5f * ex) - target;
+        if (g > 0.0f) hi = x; else lo = x;
+        const float dg = (c - x) * ex;
+        float xn = dg > 0.0f ? x - g / dg : 0.5f * (lo + hi);
+        if (!(xn >= lo && xn <= hi)) xn = 0.5f * (lo + hi);    // a converged step stays put
+        x = xn;
+    }
+    const float y = erfinvf(fmaxf(-VNDF_Y_MAX, fminf(VNDF_Y_MAX, 2.0f * u2 - 1.0f)));
+    const float sx = (cphi * x - sphi * y) * a, sy = (sphi * x + cphi * y) * a;
+    return normalize(V3{-sx, -sy, 1.0f});
 }
 
 // orthonormal basis around n (Duff et al. 2017, branchless)
@@ -494,10 +541,16 @@ __device__ __forceinline__ void onb(V3 n, V3& t, V3& b) {
     b = V3{bb, sg + n.y * n.y * a, -n.y};
 }
 
-__device__ __forceinline__ int bsdf_sample(float4 u, V3 wo, V3 n, float alpha, V3& wi) {
+__device__ __forceinline__ int bsdf_sample(float4 u, V3 wo, V3 n, float alpha, bool vndf, V3& wi) {
     V3 t, b;
     onb(n, t, b);
     const float a = alpha_eff(alpha);
+    if (u.x < LOBE_SPEC_P && vndf) {
+        const V3 hl = vndf_normal(V3{dot(wo, t), dot(wo, b), dot(wo, n)}, a, u.y, u.z);
+        const V3 h = t * hl.x + b * hl.y + n * hl.z;
+        wi = h * (2.0f * dot(wo, h)) - wo;
+        return 0;
+    }
     const float phi = 2.0f * PI_F * u.z;
     float sp, cp;
     sincosf(phi, &sp, &cp);
@@ -727,7 +780,7 @@ __device__ V3 trace_estimator(const DevScene& S, V3 o, V3 d, int exclude, int nv
                 code = occ ? 1u : 2u;
                 if (!occ) {
                     const V3 fv = brdf_eval(we, wo, n, m);
-                    const float den = pe + bsdf_pdf(we, wo, n, m.a);
+                    const float den = pe + bsdf_pdf(we, wo, n, m.a, S.vndf);
                     L = L + mul(beta, mul(env_rgb(S, tex), fv)) * (c / den);
                 }
             }
@@ -736,9 +789,9 @@ __device__ V3 trace_estimator(const DevScene& S, V3 o, V3 d, int exclude, int nv
         if (!(k < nvert || S.has_env)) break;
         const float4 u = draw4(ctr, k, 2, key);
         V3 wi;
-        const int lobe = bsdf_sample(u, wo, n, m.a, wi);
+        const int lobe = bsdf_sample(u, wo, n, m.a, S.vndf, wi);
         const float ci = dot(n, wi);
-        const float pb = bsdf_pdf(wi, wo, n, m.a);
+        const float pb = bsdf_pdf(wi, wo, n, m.a, S.vndf);
         hash.push((uint32_t)lobe);
         if (!(ci > 0.0f) || !(pb > 0.0f)) { hash.push(0u); break; }
         hash.push(1u);

@@ -195,7 +195,7 @@ __global__ void __launch_bounds__(SHADE_BLOCK) SHADE_OCC k_shade(FwdParams p, Qu
                     V3 ct{0.f, 0.f, 0.f};
                     if (c > 0.0f && pe > 0.0f) {
                         tmax = __int_as_float(0x7f800000);
-                        const float den = pe + bsdf_pdf(we, wo, n, m.a);
+                        const float den = pe + bsdf_pdf(we, wo, n, m.a, S.vndf);
                         ct = mul(beta, mul(env_rgb(S, tex), brdf_eval(we, wo, n, m))) * (c / den);
                     }
                     const size_t e = (size_t)S.nl * q.cap + i;
@@ -205,9 +205,9 @@ __global__ void __launch_bounds__(SHADE_BLOCK) SHADE_OCC k_shade(FwdParams p, Qu
                 uint32_t info = 0;
                 if (k < p.B || S.has_env) {
                     const float4 u = draw4(ctr, k, 2, key);
-                    const int lobe = bsdf_sample(u, wo, n, m.a, wi);
+                    const int lobe = bsdf_sample(u, wo, n, m.a, S.vndf, wi);
                     const float ci = dot(n, wi);
-                    pb = bsdf_pdf(wi, wo, n, m.a);
+                    pb = bsdf_pdf(wi, wo, n, m.a, S.vndf);
                     info = 1u | ((uint32_t)lobe << 1);
                     if (ci > 0.0f && pb > 0.0f) {
                         info |= 4u;

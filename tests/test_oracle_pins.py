@@ -125,8 +125,11 @@ def test_specular_energy_bounded(alpha):
         assert 0.5 < tot <= 1.0 + 1e-3
 
 
-@pytest.mark.parametrize("alpha,to", [(0.08, 0.4), (0.3, 1.0), (0.6, 0.2)])
-def test_bsdf_sampling_matches_pdf(alpha, to):
+@pytest.mark.parametrize("vndf", [False, True])
+@pytest.mark.parametrize("alpha,to", [(0.08, 0.4), (0.3, 1.0), (0.6, 0.2), (0.5, 1.45)])
+def test_bsdf_sampling_matches_pdf(alpha, to, vndf):
+    """Sampled directions against the mixture pdf (chi^2 over cos(theta) x phi bins,
+    the mass below the surface as one more bin), classical and visible-normal."""
     from scipy import stats
     rng = np.random.default_rng(9)
     n = np.array([0.0, 0.0, 1.0])
@@ -137,7 +140,7 @@ def test_bsdf_sampling_matches_pdf(alpha, to):
     below = 0
     us = rng.random((N, 4))
     for u in us:
-        _, wi = O.bsdf_sample(u, wo, n, alpha)
+        _, wi = O.bsdf_sample(u, wo, n, alpha, vndf)
         if wi[2] <= 0:
             below += 1
             continue
@@ -156,7 +159,7 @@ def test_bsdf_sampling_matches_pdf(alpha, to):
                 for b in range(sub):
                     p = (ip + (b + 0.5) / sub) / nb_p * 2 * np.pi
                     wi = np.array([s * math.cos(p), s * math.sin(p), c])
-                    acc += O.bsdf_pdf(wi, wo, n, alpha)
+                    acc += O.bsdf_pdf(wi, wo, n, alpha, vndf)
             exp_mass[ic, ip] = acc / sub ** 2 * (1.0 / nb_c) * (2 * np.pi / nb_p)
     upper = exp_mass.sum()
     assert upper <= 1.0 + 1e-3
@@ -1025,3 +1028,40 @@ def test_treelets_reach_brute_force_optimum_on_small_trees(n):
         boxes = [a[n - 1 + i].astype(np.float64) for i in range(n)]
         best = min(_tree_cost(t, boxes)[0] for t in _all_trees(list(range(n))))
         assert abs(got - best) <= 1e-5 * best, (trial, got, best)
+
+
+# --------------------------------------------------------------------------
+# visible-normal sampling of the specular lobe
+# --------------------------------------------------------------------------
+
+def test_erfinv_against_scipy():
+    from scipy.special import erfinv
+    for y in [-0.9999998, -0.999, -0.7, -0.1, 0.0, 1e-9, 0.3, 0.5, 0.95, 0.9999998]:
+        assert abs(O.erfinv(y) - erfinv(y)) <= 1e-13 * max(1.0, abs(erfinv(y)))
+
+
+@pytest.mark.parametrize("alpha", [0.05, 0.3, 0.8])
+def test_vndf_pdf_at_normal_incidence_is_the_classical_pdf(alpha):
+    """Seen along the normal every microfacet is visible (G1 = 1, wo.h = n.h), so
+    the visible-normal pdf equals the D cos(theta_h) / (4 wo.h) one."""
+    rng = np.random.default_rng(3)
+    n = np.array([0.0, 0.0, 1.0])
+    for _ in range(200):
+        wi = rng.normal(size=3)
+        wi[2] = abs(wi[2])
+        wi /= np.linalg.norm(wi)
+        a, b = O.bsdf_pdf(wi, n, n, alpha, True), O.bsdf_pdf(wi, n, n, alpha, False)
+        assert abs(a - b) <= 1e-12 * max(a, 1e-300)
+
+
+def test_vndf_samples_only_visible_normals():
+    """Every sampled half-vector faces wo (wo.h > 0), at grazing angles too."""
+    rng = np.random.default_rng(5)
+    n = np.array([0.0, 0.0, 1.0])
+    for to in (0.1, 1.2, 1.55):
+        wo = np.array([math.sin(to), 0.0, math.cos(to)])
+        for u in rng.random((3000, 4)):
+            u[0] = 0.1                                   # specular lobe
+            _, wi = O.bsdf_sample(u, wo, n, 0.4, True)
+            h = wi + wo
+            assert np.dot(wo, h / np.linalg.norm(h)) > 0.0
