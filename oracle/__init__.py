@@ -62,6 +62,8 @@ def lib():
         L.or_bsdf_pdf.restype = ctypes.c_double
         L.or_bsdf_sample.argtypes = [P, P, P, ctypes.c_double, ctypes.c_int, P]
         L.or_scene_set_vndf.argtypes = [P, ctypes.c_int]
+        L.or_edge_tree.argtypes = [P, P, P, P, P, P]
+        L.or_edge_tree_sample.argtypes = [P, P, P, ctypes.c_longlong, ctypes.c_uint, P]
         L.or_erfinv.argtypes = [ctypes.c_double]
         L.or_erfinv.restype = ctypes.c_double
         L.or_beckmann_D.argtypes = [ctypes.c_double, ctypes.c_double]
@@ -91,7 +93,7 @@ def lib():
                                      P, P, P, P]
         L.or_sample_grad.restype = ctypes.c_double
         L.or_secondary_term.argtypes = [P, P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_longlong,
-                                        ctypes.c_uint, P]
+                                        ctypes.c_uint, ctypes.c_int, P]
         L.or_scene_set_texels.argtypes = [P, ctypes.c_int, P]
         L.or_scene_set_texels.restype = ctypes.c_longlong
         L.or_texel_index.argtypes = [ctypes.c_int, ctypes.c_longlong, ctypes.c_double, ctypes.c_double]
@@ -269,11 +271,27 @@ class OracleScene:
         return lib().or_sample_frozen(self.h, _p(rows), _p(res), len(cams), spp, bounces, seed, flags, view, px,
                                       py, j, _p(_f64(w)), kind, index, delta)
 
-    def secondary_term(self, p, n, wo, face, budget, nsamples, seed=0):
+    def secondary_term(self, p, n, wo, face, budget, nsamples, seed=0, hierarchy=False):
         dV = np.zeros((self.nv, 3))
         lib().or_secondary_term(self.h, _p(_f64(p)), _p(_f64(n)), _p(_f64(wo)), face, budget, nsamples, seed,
-                                _p(dV))
+                                int(bool(hierarchy)), _p(dV))
         return dV
+
+    def edge_tree(self):
+        """(keys, child, parent, box, len) of the secondary-edge importance tree."""
+        n = len(self.edges())
+        keys = np.zeros(n, np.uint64)
+        child = np.zeros((max(n - 1, 0), 2), np.int32)
+        parent = np.zeros(2 * n - 1, np.int32)
+        box = np.zeros((2 * n - 1, 6), np.float32)
+        ln = np.zeros(2 * n - 1, np.float32)
+        lib().or_edge_tree(self.h, _p(keys), _p(child), _p(parent), _p(box), _p(ln))
+        return keys, child, parent, box, ln
+
+    def edge_tree_sample(self, x, n, i, seed=0):
+        pe = ctypes.c_float()
+        e = lib().or_edge_tree_sample(self.h, _p(_f64(x)), _p(_f64(n)), int(i), seed, ctypes.byref(pe))
+        return e, float(pe.value)
 
 
 # ---- stateless pieces ----------------------------------------------------

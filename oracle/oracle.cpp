@@ -163,6 +163,13 @@ struct Edge { int va, vb, f1, f2; };
 
 struct BVHNode { double lo[3], hi[3]; int left, right, first, count; };
 
+struct EdgeTree {
+    int n = 0;                      // edges (leaves)
+    std::vector<uint64_t> keys;     // sorted morton << 32 | edge
+    std::vector<int> child, parent;
+    std::vector<float> box, len;    // per node (internal nodes, then leaves)
+};
+
 struct Scene {
     int nv = 0, nf = 0, nl = 0, he = 0, we = 0;
     int tex_res = 0;               // mesh-colours resolution r; mat holds nf (r+1)(r+2)/2 texels
@@ -177,6 +184,7 @@ struct Scene {
     double env_total = 0.0;
     bool env_alias = false;                 // texel chosen through the alias table instead of the CDFs
     bool vndf = false;                      // specular lobe sampled from the visible normals
+    EdgeTree etree;                         // secondary-edge importance hierarchy
     std::vector<double> aprob;              // Walker/Vose alias table over the texels
     std::vector<int> alias;
     std::vector<BVHNode> nodes;
@@ -738,9 +746,13 @@ struct SecCtx {         // secondary-edge state of a main path (backward only)
     Grad* g;
     bool interior = false;  // also take edges that are not silhouettes from the shading point
                             // (creases and material boundaries seen in direction space)
+    bool hier = false;      // edges drawn by the importance hierarchy instead of the length CDF
 };
 
 struct Key { uint32_t k0, k1; };
+
+static int edge_tree_sample(const Scene& s, const D3& x, const D3& nn, const Ctr& ctr, int k, const Key& key,
+                            float& pe);
 
 static void push_face(Hash& h, int f) { h.push(f < 0 ? 0xFFFFFFFFu : (uint32_t)f); }
 
@@ -850,8 +862,21 @@ static D3 trace_estimator(const Scene& s, D3 o, D3 d, int exclude, int nvert, bo
         if (sec && continues && !s.edges.empty() && s.elen_total > 0.0) {
             double u[4];
             draw4(ctr, k, 3, key.k0, key.k1, u);
-            int e = cdf_find(s.ecdf.data(), (int)s.edges.size(), u[0]);
+            int e;
+            double wsel;            // 1 / (probability density of the edge point per unit length)
+            if (sec->hier) {
+                float pe;
+                e = edge_tree_sample(s, x, n, ctr, k, key, pe);
+                if (e >= 0) {
+                    const Edge& Es = s.edges[e];
+                    wsel = length(s.vert(Es.vb) - s.vert(Es.va)) / (double)pe;
+                }
+            } else {
+                e = cdf_find(s.ecdf.data(), (int)s.edges.size(), u[0]);
+                wsel = s.elen_total;
+            }
             double te = u[1];
+            if (e < 0) { sech.push(0xFFFFFFFFu); sech.push(0u); goto no_secondary; }
             sech.push((uint32_t)e);
             const Edge& E = s.edges[e];
             D3 va = s.vert(E.va), vb = s.vert(E.vb);
@@ -885,7 +910,7 @@ static D3 trace_estimator(const Scene& s, D3 o, D3 d, int exclude, int nvert, bo
                     double cc = 0.0;
                     for (int ch = 0; ch < 3; ++ch)
                         cc += sec->w[ch] * beta[ch] * fv[ch] * cv * (Lm[ch] - Lp[ch]);
-                    cc *= s.elen_total / r2;
+                    cc *= wsel / r2;
                     if (sec->g) {
                         for (int k3 = 0; k3 < 3; ++k3) {
                             sec->g->dV[3 * E.va + k3] += cc * (1.0 - te) * mv[k3];
@@ -897,6 +922,7 @@ static D3 trace_estimator(const Scene& s, D3 o, D3 d, int exclude, int nvert, bo
             }
             if (code == 0) sech.push(0u);
         }
+    no_secondary:
         // continuation by sampling the BRDF mixture
         if (!continues) break;
         double u[4];
@@ -1351,17 +1377,16 @@ static inline uint32_t spread10(uint32_t v) {
 
 static inline int clz64(uint64_t x) { return x ? __builtin_clzll(x) : 64; }
 
-static void lbvh_reference(const float* V, int nv, const int* F, int nf, uint64_t* keys, int* child,
-                           int* parent, float* aabb) {
-    (void)nv;
-    std::vector<float> mn(3 * nf), mx(3 * nf), ce(3 * nf);
+// Radix tree (Karras 2012) over n primitive boxes mn/mx (float [n,3]):
+// centres (mn + mx) / 2, 30-bit Morton codes over cubic cells, keys
+// morton << 32 | primitive, sorted; children, parents and refitted boxes.
+static void radix_tree_of_boxes(const std::vector<float>& mn, const std::vector<float>& mx, int nf, uint64_t* keys,
+                                int* child, int* parent, float* aabb) {
+    std::vector<float> ce(3 * (size_t)nf);
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int f = 0; f < nf; ++f)
         for (int k = 0; k < 3; ++k) {
-            float a = V[3 * F[3 * f] + k], b = V[3 * F[3 * f + 1] + k], c = V[3 * F[3 * f + 2] + k];
-            float m0 = std::min(a, std::min(b, c)), m1 = std::max(a, std::max(b, c));
-            mn[3 * f + k] = m0; mx[3 * f + k] = m1;
-            volatile float sum = m0 + m1;
+            volatile float sum = mn[3 * f + k] + mx[3 * f + k];
             float cc = sum * 0.5f;
             ce[3 * f + k] = cc;
             lo[k] = std::min(lo[k], cc); hi[k] = std::max(hi[k], cc);
@@ -1441,6 +1466,111 @@ static void lbvh_reference(const float* V, int nv, const int* F, int nf, uint64_
             b[3 + k] = std::max(cb[0][3 + k], cb[1][3 + k]);
         }
     }
+}
+
+static void lbvh_reference(const float* V, int nv, const int* F, int nf, uint64_t* keys, int* child,
+                           int* parent, float* aabb) {
+    (void)nv;
+    std::vector<float> mn(3 * (size_t)nf), mx(3 * (size_t)nf);
+    for (int f = 0; f < nf; ++f)
+        for (int k = 0; k < 3; ++k) {
+            float a = V[3 * F[3 * f] + k], b = V[3 * F[3 * f + 1] + k], c = V[3 * F[3 * f + 2] + k];
+            mn[3 * f + k] = std::min(a, std::min(b, c));
+            mx[3 * f + k] = std::max(a, std::max(b, c));
+        }
+    radix_tree_of_boxes(mn, mx, nf, keys, child, parent, aabb);
+}
+
+// Edge tree of the secondary-edge importance hierarchy: the radix tree over the
+// edges' boxes, every node carrying the float sum of the lengths below it
+// (a leaf: its edge's length rounded to float; a node: left + right).
+static void build_edge_tree(Scene& s) {
+    EdgeTree& T = s.etree;
+    const int n = (int)s.edges.size();
+    T.n = n;
+    T.keys.assign(n, 0);
+    T.child.assign(2 * (size_t)std::max(n - 1, 0), 0);
+    T.parent.assign(2 * (size_t)n - (n > 0 ? 1 : 0), -1);
+    T.box.assign(6 * T.parent.size(), 0.0f);
+    T.len.assign(T.parent.size(), 0.0f);
+    if (n == 0) return;
+    std::vector<float> mn(3 * (size_t)n), mx(3 * (size_t)n);
+    for (int e = 0; e < n; ++e)
+        for (int k = 0; k < 3; ++k) {
+            const float a = (float)s.V[3 * s.edges[e].va + k], c = (float)s.V[3 * s.edges[e].vb + k];
+            mn[3 * e + k] = std::min(a, c);
+            mx[3 * e + k] = std::max(a, c);
+        }
+    radix_tree_of_boxes(mn, mx, n, T.keys.data(), T.child.data(), T.parent.data(), T.box.data());
+    for (int i = 0; i < n; ++i) {
+        const Edge& E = s.edges[(int)(T.keys[i] & 0xFFFFFFFFu)];
+        double d2 = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            const double d = (double)(float)s.V[3 * E.vb + k] - (double)(float)s.V[3 * E.va + k];
+            d2 += d * d;
+        }
+        T.len[(n - 1) + i] = (float)std::sqrt(d2);
+    }
+    if (n < 2) return;
+    const int LEAF = (int)0x80000000;
+    std::vector<int> order, st{0};
+    while (!st.empty()) {
+        int i = st.back(); st.pop_back(); order.push_back(i);
+        for (int c = 0; c < 2; ++c) if (!(T.child[2 * i + c] & LEAF)) st.push_back(T.child[2 * i + c]);
+    }
+    for (auto it = order.rbegin(); it != order.rend(); ++it) {
+        const int i = *it;
+        float l[2];
+        for (int c = 0; c < 2; ++c) {
+            const int ch = T.child[2 * i + c];
+            l[c] = T.len[(ch & LEAF) ? (n - 1) + (ch & 0x7FFFFFFF) : ch];
+        }
+        T.len[i] = l[0] + l[1];
+    }
+}
+
+// Importance of a tree node seen from the shading point p with normal nrm
+// (float, contraction off, this operation order on both implementations):
+// zero when the node's box lies wholly behind the tangent plane of p (such
+// edges contribute nothing), otherwise the node's length over the squared
+// distance to the box centre plus the squared half diagonal.
+static float edge_node_weight(const EdgeTree& T, int code, const float p[3], const float nrm[3]) {
+    const int idx = (code & (int)0x80000000) ? (T.n - 1) + (code & 0x7FFFFFFF) : code;
+    const float* bx = &T.box[6 * (size_t)idx];
+    const float dx = (bx[0] + bx[3]) * 0.5f - p[0], dy = (bx[1] + bx[4]) * 0.5f - p[1], dz = (bx[2] + bx[5]) * 0.5f - p[2];
+    const float ex = bx[3] - bx[0], ey = bx[4] - bx[1], ez = bx[5] - bx[2];
+    const float reach = (dx * nrm[0] + dy * nrm[1] + dz * nrm[2]) +
+                        0.5f * ((std::fabs(nrm[0]) * ex + std::fabs(nrm[1]) * ey) + std::fabs(nrm[2]) * ez);
+    if (!(reach > 0.0f)) return 0.0f;
+    return T.len[idx] / ((dx * dx + dy * dy + dz * dz) + 0.25f * ((ex * ex + ey * ey) + ez * ez));
+}
+
+// Stochastic descent of the edge tree: at every node the child is taken with
+// probability proportional to its weight, by a fresh uniform per level (level l
+// uses component l % 4 of the draw of block 4 + l / 4 at vertex k).  Returns the
+// edge (canonical index) and its probability pe, or -1 when every weight is zero.
+static int edge_tree_sample(const Scene& s, const D3& x, const D3& nn, const Ctr& ctr, int k, const Key& key,
+                            float& pe) {
+    const EdgeTree& T = s.etree;
+    pe = 1.0f;
+    if (T.n <= 0) return -1;
+    const float p[3] = {(float)x.x, (float)x.y, (float)x.z}, nrm[3] = {(float)nn.x, (float)nn.y, (float)nn.z};
+    const int LEAF = (int)0x80000000;
+    int code = T.n == 1 ? LEAF : 0;
+    double u[4] = {0, 0, 0, 0};
+    for (int level = 0; !(code & LEAF); ++level) {
+        if (level >= 128) return -1;
+        if ((level & 3) == 0) draw4(ctr, k, 4 + (level >> 2), key.k0, key.k1, u);
+        const int c0 = T.child[2 * code], c1 = T.child[2 * code + 1];
+        const float w0 = edge_node_weight(T, c0, p, nrm), w1 = edge_node_weight(T, c1, p, nrm);
+        const float tot = w0 + w1;
+        if (!(tot > 0.0f)) return -1;
+        const float p0 = w0 / tot;
+        if ((float)u[level & 3] < p0) { code = c0; pe *= p0; }
+        else { code = c1; pe *= w1 / tot; }
+    }
+    if (T.n == 1 && !(edge_node_weight(T, LEAF, p, nrm) > 0.0f)) return -1;
+    return (int)(T.keys[code & 0x7FFFFFFF] & 0xFFFFFFFFu);
 }
 
 // --------------------------------------------------------------------------
@@ -1623,6 +1753,7 @@ void* or_scene_create(const float* V, int nv, const int* F, int nf, const float*
     if (nl > 0) s->lights.assign(lights, lights + 6 * (size_t)nl);
     if (env && he > 0 && we > 0) { s->he = he; s->we = we; s->env.assign(env, env + 3 * (size_t)he * we); }
     build_edges(*s);
+    build_edge_tree(*s);
     build_env(*s);
     build_bvh(*s);
     return s;
@@ -1642,6 +1773,26 @@ long long or_scene_set_texels(void* p, int r, const float* texels) {
 }
 
 long long or_texel_index(int r, long long t, double alpha, double beta) { return texel_index(r, t, alpha, beta); }
+
+// The secondary-edge importance tree: keys [n], child [n-1,2], parent [2n-1],
+// box [2n-1,6], len [2n-1] (the layout of or_lbvh).
+int or_edge_tree(void* p, unsigned long long* keys, int* child, int* parent, float* box, float* len) {
+    const EdgeTree& T = ((Scene*)p)->etree;
+    std::copy(T.keys.begin(), T.keys.end(), keys);
+    std::copy(T.child.begin(), T.child.end(), child);
+    std::copy(T.parent.begin(), T.parent.end(), parent);
+    std::copy(T.box.begin(), T.box.end(), box);
+    std::copy(T.len.begin(), T.len.end(), len);
+    return T.n;
+}
+
+// One hierarchy draw from shading point x with normal n for the counters of
+// sample i (vertex 1): the edge (or -1) and its probability.
+int or_edge_tree_sample(void* p, const double* x, const double* n, long long i, unsigned seed, float* pe) {
+    Scene* s = (Scene*)p;
+    Ctr ctr{(uint32_t)i, 0u, 0u, 3u};
+    return edge_tree_sample(*s, D3(x[0], x[1], x[2]), D3(n[0], n[1], n[2]), ctr, 1, Key{seed, s->id}, *pe);
+}
 
 // Specular lobe sampled from the visible normals (on) or from D cos(theta_h) (off, the default).
 int or_scene_set_vndf(void* p, int on) {
@@ -1817,7 +1968,7 @@ int or_backward(void* p, const double* cams, const int* res, int ncam, int spp, 
             double w[3] = {di[0] / (double)spp, di[1] / (double)spp, di[2] / (double)spp};
             Hash h;
             PRec rec;
-            SecCtx sc{{w[0], w[1], w[2]}, &G[tid], (flags & 64) != 0};
+            SecCtx sc{{w[0], w[1], w[2]}, &G[tid], (flags & 64) != 0, (flags & 256) != 0};
             pixel_sample(*s, c, view, (int)(local % c.W), (int)(local / c.W), j, spp, bounces, key, h, &rec,
                          secondary ? &sc : nullptr);
             path_gradient(*s, rec, w, interior, secondary, bounces, G[tid]);
@@ -1879,7 +2030,7 @@ double or_sample_frozen(void* p, const double* cams, const int* res, int ncam, i
     Hash h;
     PRec rec;
     Grad dummy; dummy.dV.assign(3 * (size_t)s->nv, 0.0); dummy.dM.assign(s->mat.size(), 0.0);
-    SecCtx sc{{w[0], w[1], w[2]}, &dummy, (flags & 64) != 0};
+    SecCtx sc{{w[0], w[1], w[2]}, &dummy, (flags & 64) != 0, (flags & 256) != 0};
     pixel_sample(*s, vw.cams[view], view, px, py, j, spp, bounces, key, h, &rec, (flags & 4) ? &sc : nullptr);
     PView P; P.s = s;
     for (int k = 0; k < rec.nv; ++k) P.add_vertex(rec.v[k].face, rec.v[k].tex);
@@ -1899,7 +2050,7 @@ double or_sample_grad(void* p, const double* cams, const int* res, int ncam, int
     PRec rec;
     Grad g; g.dV.assign(3 * (size_t)s->nv, 0.0); g.dM.assign(s->mat.size(), 0.0);
     // flag 8: leave out the direct edge-endpoint terms (only the replay derivative)
-    SecCtx sc{{w[0], w[1], w[2]}, (flags & 8) ? nullptr : &g, (flags & 64) != 0};
+    SecCtx sc{{w[0], w[1], w[2]}, (flags & 8) ? nullptr : &g, (flags & 64) != 0, (flags & 256) != 0};
     D3 L = pixel_sample(*s, vw.cams[view], view, px, py, j, spp, bounces, key, h, &rec,
                         (flags & 4) ? &sc : nullptr);
     rgb[0] = L.x; rgb[1] = L.y; rgb[2] = L.z;
@@ -1918,7 +2069,7 @@ double or_sample_grad(void* p, const double* cams, const int* res, int ncam, int
 // the edge endpoints receive gradient.  Used to pin the estimator against the
 // closed-form irradiance of a polygon.
 void or_secondary_term(void* p, const double* pp, const double* nn, const double* wo, int face, int budget,
-                       long long nsamples, unsigned seed, double* dV) {
+                       long long nsamples, unsigned seed, int hier, double* dV) {
     Scene* s = (Scene*)p;
     Grad g; g.dV.assign(3 * (size_t)s->nv, 0.0); g.dM.assign(s->mat.size(), 0.0);
     Key key{seed, s->id};
@@ -1928,7 +2079,17 @@ void or_secondary_term(void* p, const double* pp, const double* nn, const double
         Ctr ctr{(uint32_t)i, 0u, 0u, 3u};
         double u[4];
         draw4(ctr, 1, 3, key.k0, key.k1, u);
-        int e = cdf_find(s->ecdf.data(), (int)s->edges.size(), u[0]);
+        int e;
+        double wsel;
+        if (hier) {
+            float pe;
+            e = edge_tree_sample(*s, x, n, ctr, 1, key, pe);
+            if (e < 0) continue;
+            wsel = length(s->vert(s->edges[e].vb) - s->vert(s->edges[e].va)) / (double)pe;
+        } else {
+            e = cdf_find(s->ecdf.data(), (int)s->edges.size(), u[0]);
+            wsel = s->elen_total;
+        }
         double te = u[1];
         const Edge& E = s->edges[e];
         D3 va = s->vert(E.va), vb = s->vert(E.vb);
@@ -1955,7 +2116,7 @@ void or_secondary_term(void* p, const double* pp, const double* nn, const double
         D3 fv = brdf(ud, o, n, m);
         double cc = 0.0;
         for (int ch = 0; ch < 3; ++ch) cc += (1.0 / 3.0) * fv[ch] * cv * (Lm[ch] - Lp[ch]);
-        cc *= s->elen_total / r2 / (double)nsamples;
+        cc *= wsel / r2 / (double)nsamples;
         for (int k = 0; k < 3; ++k) {
             g.dV[3 * E.va + k] += cc * (1.0 - te) * mv[k];
             g.dV[3 * E.vb + k] += cc * te * mv[k];

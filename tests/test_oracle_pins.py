@@ -566,7 +566,8 @@ def _psa(p, n, tri):
     return abs(tot) / 2
 
 
-def test_secondary_edges_polygon_irradiance_derivative():
+@pytest.mark.parametrize("hierarchy", [False, True])
+def test_secondary_edges_polygon_irradiance_derivative(hierarchy):
     tri = np.array([[-0.3, 0.8, -0.2], [0.4, 0.9, -0.1], [0.05, 0.7, 0.45]], np.float32)
     floor = np.array([[-0.05, 0.0, -0.05], [0.05, 0.0, -0.05], [0.0, 0.0, 0.06]], np.float32)
     V = np.concatenate([floor, tri])
@@ -576,7 +577,7 @@ def test_secondary_edges_polygon_irradiance_derivative():
     p = np.array([0.0, 0.0, 0.0])
     n = np.array([0.0, 1.0, 0.0])
     wo = np.array([0.3, 1.0, 0.2]) / np.linalg.norm([0.3, 1.0, 0.2])
-    dV = sc.secondary_term(p, n, wo, face=0, budget=0, nsamples=400000, seed=2)
+    dV = sc.secondary_term(p, n, wo, face=0, budget=0, nsamples=400000, seed=2, hierarchy=hierarchy)
     # E(p) = kd/pi * L0 * (pi - PSA(triangle)), so dE/dv = -(1/pi) dPSA/dv
     T = tri.astype(float)
     ref = np.zeros((3, 3))
@@ -1065,3 +1066,97 @@ def test_vndf_samples_only_visible_normals():
             _, wi = O.bsdf_sample(u, wo, n, 0.4, True)
             h = wi + wo
             assert np.dot(wo, h / np.linalg.norm(h)) > 0.0
+
+
+# --------------------------------------------------------------------------
+# secondary-edge importance hierarchy
+# --------------------------------------------------------------------------
+
+def _node_weight(box, ln, p, nrm):
+    """The node importance written out in float32 (box lower/upper corners, total length)."""
+    f = np.float32
+    c = (box[:3] + box[3:]) * f(0.5) - p
+    e = box[3:] - box[:3]
+    reach = (c[0] * nrm[0] + c[1] * nrm[1] + c[2] * nrm[2]) + f(0.5) * ((abs(nrm[0]) * e[0] + abs(nrm[1]) * e[1])
+                                                                       + abs(nrm[2]) * e[2])
+    if not reach > 0:
+        return f(0.0)
+    return f(ln / ((c[0] * c[0] + c[1] * c[1] + c[2] * c[2]) + f(0.25) * ((e[0] * e[0] + e[1] * e[1]) + e[2] * e[2])))
+
+
+def _all_edge_probs(tree, p, nrm):
+    keys, child, parent, box, ln = tree
+    n = keys.shape[0]
+    LEAF = 0x80000000
+    probs = np.zeros(n)
+
+    def idx(code):
+        return n - 1 + (code & 0x7FFFFFFF) if code & LEAF else code
+
+    stack = [(0, 1.0)]
+    while stack:
+        node, pr = stack.pop()
+        c = [int(x) & 0xFFFFFFFF for x in child[node]]
+        w = [_node_weight(box[idx(k)], ln[idx(k)], p, nrm) for k in c]
+        tot = np.float32(w[0] + w[1])
+        if not tot > 0:
+            continue
+        for k, wk in zip(c, w):
+            q = pr * float(np.float32(wk / tot))
+            if q == 0:
+                continue
+            if k & LEAF:
+                probs[int(keys[k & 0x7FFFFFFF]) & 0xFFFFFFFF] += q
+            else:
+                stack.append((k, q))
+    return probs
+
+
+def test_edge_tree_valid():
+    V, F = S.noise_sphere(4, 0.1, noise_seed=2)
+    sc = O.OracleScene(V.astype(np.float32), F, S.uniform_materials(F.shape[0]), None, None)
+    keys, child, parent, box, ln = sc.edge_tree()
+    E = sc.edges()
+    n = E.shape[0]
+    V32 = V.astype(np.float32)
+    assert _tree_check(child, parent, box, n) > 0              # leaves once, boxes exact unions
+    leaf_len = np.sqrt(((V32[E[:, 1]].astype(np.float64) - V32[E[:, 0]].astype(np.float64)) ** 2).sum(1))
+    order = (keys & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    assert np.array_equal(ln[n - 1:], leaf_len[order].astype(np.float32))
+    LEAF = 0x80000000
+    for i in range(n - 1):
+        c = [int(x) & 0xFFFFFFFF for x in child[i]]
+        l = [ln[n - 1 + (k & 0x7FFFFFFF)] if k & LEAF else ln[k] for k in c]
+        assert ln[i] == np.float32(l[0] + l[1])
+    assert abs(ln[0] - leaf_len.sum()) < 1e-5 * leaf_len.sum()
+
+
+def test_edge_tree_sampling_matches_probabilities():
+    """Sampled edges follow the product of the per-level probabilities, which sum
+    to one over the edges; edges wholly behind the tangent plane are never drawn."""
+    from scipy import stats
+    Vs, Fs = S.noise_sphere(3, 0.1, noise_seed=5)
+    floor = np.array([[-3, -1.5, -3], [3, -1.5, -3], [3, -1.5, 3], [-3, -1.5, 3]], np.float32)
+    nv = Vs.shape[0]
+    V = np.concatenate([Vs, floor]).astype(np.float32)
+    F = np.concatenate([Fs, [[nv, nv + 2, nv + 1], [nv, nv + 3, nv + 2]]]).astype(np.int32)
+    sc = O.OracleScene(V, F, S.uniform_materials(F.shape[0]), None, None)
+    tree = sc.edge_tree()
+    E = sc.edges()
+    x = np.array([0.6, -1.5, 0.3])                      # on the floor, under the sphere
+    nrm = np.array([0.1, 0.98, 0.15]) / np.linalg.norm([0.1, 0.98, 0.15])
+    P = _all_edge_probs(tree, x.astype(np.float32), nrm.astype(np.float32))
+    assert abs(P.sum() - 1.0) < 1e-5
+    N = 40000
+    counts = np.zeros(E.shape[0])
+    for i in range(N):
+        e, pe = sc.edge_tree_sample(x, nrm, i, seed=3)
+        assert e >= 0 and abs(pe - P[e]) <= 1e-6 * P[e] + 1e-12
+        counts[e] += 1
+    behind = np.array([(np.stack([V[a], V[b]]) - x) @ nrm for a, b in E[:, :2]]).max(axis=1) < -1e-3
+    assert behind.any() and counts[behind].sum() == 0 and P[behind].sum() == 0
+    keep = P * N > 15
+    exp = P[keep] * N
+    obs = counts[keep]
+    exp *= obs.sum() / exp.sum()
+    assert stats.chisquare(obs, exp).pvalue > 1e-4
