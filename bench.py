@@ -63,6 +63,8 @@ def parse():
                     help="environment texel draw: row/column CDFs or the alias table (same distribution)")
     ap.add_argument("--bsdf-sampler", choices=["halfvector", "vndf"], default="halfvector",
                     help="specular half-vectors from D cos(theta_h) or from the visible normals")
+    ap.add_argument("--edge-sampler", choices=["cdf", "hierarchy"], default="cdf",
+                    help="secondary edges drawn by the length CDF or the importance hierarchy")
     ap.add_argument("--profile-only", action="store_true", help="one untimed step (for rocprofv3 runs)")
     ap.add_argument("--copy-reference", action="store_true",
                     help="only a plain 512 MiB device copy: the reference that scales the HBM byte counters")
@@ -180,6 +182,7 @@ def main():
     g.set_env_sampler(B.ST_ENV_SAMPLER_ALIAS if args.env_sampler == "alias" else B.ST_ENV_SAMPLER_CDF)
     g.set_bsdf_sampler(B.ST_BSDF_SAMPLER_VNDF if args.bsdf_sampler == "vndf" else B.ST_BSDF_SAMPLER_HALFVECTOR)
     cams, spp, bounces = wl.cams, wl.spp, wl.bounces
+    grads = B.ST_ALL_GRADS | (B.ST_EDGE_SECONDARY_HIERARCHY if args.edge_sampler == "hierarchy" else 0)
     npix = B.num_pixels(cams)
     n_paths = npix * spp
     dev = torch.device("cuda")
@@ -199,7 +202,7 @@ def main():
         g.update(V=Vs[i & 1])
         g.render(cams, spp, bounces, seed=i, out=img)
         d = (img - target) * scale
-        g.backward(cams, spp, bounces, d, seed=i, flags=B.ST_ALL_GRADS, dV=dV, dmat=dM)
+        g.backward(cams, spp, bounces, d, seed=i, flags=grads, dV=dV, dmat=dM)
 
     if args.profile_only:
         step(0)
@@ -235,7 +238,7 @@ def main():
     g.read_work()
     g.update(V=Vs[0])
     g.render(cams, spp, bounces, seed=100, out=img, flags=B.ST_COUNT_WORK)
-    g.backward(cams, spp, bounces, (img - target) * scale, seed=100, flags=B.ST_ALL_GRADS | B.ST_COUNT_WORK,
+    g.backward(cams, spp, bounces, (img - target) * scale, seed=100, flags=grads | B.ST_COUNT_WORK,
                dV=dV, dmat=dM)
     work = g.read_work()
     wkey = dom_name.split("<")[0]
@@ -269,7 +272,8 @@ def main():
         "config": {"workload": wl.name, "faces": int(sc.F.shape[0]), "views": len(cams), "res": args.res,
                    "spp": spp, "bounces": bounces, "path_samples_per_step": n_paths,
                    "edge_samples_per_step": B.num_edge_samples(cams, spp, 1.0, int(sc.lights.shape[0])),
-                   "envmap": "512x256", "env_sampler": args.env_sampler, "bsdf_sampler": args.bsdf_sampler},
+                   "envmap": "512x256", "env_sampler": args.env_sampler, "bsdf_sampler": args.bsdf_sampler,
+                   "edge_sampler": args.edge_sampler},
         "roofline": {"bound": "alu", "kernel": dom_name, "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": measured_traffic(dom_name),
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-scaled)",

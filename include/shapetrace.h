@@ -58,6 +58,8 @@ extern "C" {
                                            a path vertex, not only silhouettes (2 side paths per sample) */
 #define ST_BACKWARD_RETRACE 128u   /* backward: trace every main-path ray again even when hit records of
                                       the matching forward pass are held (see st_render_backward) */
+#define ST_EDGE_SECONDARY_HIERARCHY 256u  /* secondary edges drawn by an importance hierarchy instead of the
+                                             length CDF (see st_scene_edge_tree) */
 
 typedef struct st_scene st_scene;
 
@@ -242,6 +244,30 @@ int st_scene_info(const st_scene* scene, int64_t* out6);
 int st_read_work(st_scene* scene, uint64_t* out3, hipStream_t s);
 int st_scene_edges(st_scene* scene, int32_t* out_edges, hipStream_t s);
 int st_scene_lbvh(st_scene* scene, uint64_t* keys, int32_t* child, int32_t* parent, float* aabb, hipStream_t s);
+/* Secondary-edge importance hierarchy (ST_EDGE_SECONDARY_HIERARCHY; Li et al.
+ * 2018 sample silhouette edges through a hierarchy, the paper relies on their
+ * renderer): the radix tree (layout of st_scene_lbvh) over the edges' boxes,
+ * key = morton << 32 | edge, every node with the float sum of the lengths below
+ * it (a leaf: its edge's length, computed in double from the float endpoints).
+ * Every node also holds the box of the unit normals of the faces beside its
+ * edges (a boundary edge, always a silhouette, takes the cube [-1, 1]^3).  At a
+ * shading point p with normal n the edge is drawn by descending the tree, each
+ * child with probability proportional to its weight: zero when its box lies
+ * wholly behind the tangent plane of p, or, unless ST_EDGE_SECONDARY_INTERIOR
+ * is set, when the normal box proves that p sees every face below from the same
+ * side (no silhouette there), both tests with a margin of 2^-16 of the box's
+ * size plus distance; else its length sum times a cosine bound in (0, 1] over
+ * (squared distance from p to the box centre + squared half diagonal); a fresh
+ * uniform per level.  A node whose two children both weigh zero ends the draw
+ * with no edge (the sample contributes nothing; no bias, since only edges that
+ * cannot contribute are ever cut).  The point on the edge stays uniform and the
+ * sample is weighted by length / probability.  The tree is built on the first
+ * call that needs it after a scene change (allocates; not capturable).
+ * Outputs: keys uint64 [ne], child int32 [ne-1,2], parent int32 [2ne-1], box
+ * float [2ne-1,6], len float [2ne-1], nbox float [2ne-1,6] (normal box, lower
+ * then upper corner); any may be NULL. */
+int st_scene_edge_tree(st_scene* scene, uint64_t* keys, int32_t* child, int32_t* parent, float* box, float* len,
+                       float* nbox, hipStream_t s);
 int st_trace_rays(st_scene* scene, const float* o, const float* d, int32_t n, float tmin, int32_t brute,
                   int32_t* out_face, float* out_t, hipStream_t s);
 

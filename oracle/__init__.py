@@ -62,8 +62,8 @@ def lib():
         L.or_bsdf_pdf.restype = ctypes.c_double
         L.or_bsdf_sample.argtypes = [P, P, P, ctypes.c_double, ctypes.c_int, P]
         L.or_scene_set_vndf.argtypes = [P, ctypes.c_int]
-        L.or_edge_tree.argtypes = [P, P, P, P, P, P]
-        L.or_edge_tree_sample.argtypes = [P, P, P, ctypes.c_longlong, ctypes.c_uint, P]
+        L.or_edge_tree.argtypes = [P, P, P, P, P, P, P]
+        L.or_edge_tree_sample.argtypes = [P, P, P, ctypes.c_longlong, ctypes.c_uint, ctypes.c_int, P]
         L.or_erfinv.argtypes = [ctypes.c_double]
         L.or_erfinv.restype = ctypes.c_double
         L.or_beckmann_D.argtypes = [ctypes.c_double, ctypes.c_double]
@@ -278,19 +278,24 @@ class OracleScene:
         return dV
 
     def edge_tree(self):
-        """(keys, child, parent, box, len) of the secondary-edge importance tree."""
+        """(keys, child, parent, box, len, nbox) of the secondary-edge importance
+        tree; nbox bounds the unit normals of the faces beside the node's edges."""
         n = len(self.edges())
         keys = np.zeros(n, np.uint64)
         child = np.zeros((max(n - 1, 0), 2), np.int32)
         parent = np.zeros(2 * n - 1, np.int32)
         box = np.zeros((2 * n - 1, 6), np.float32)
         ln = np.zeros(2 * n - 1, np.float32)
-        lib().or_edge_tree(self.h, _p(keys), _p(child), _p(parent), _p(box), _p(ln))
-        return keys, child, parent, box, ln
+        nbox = np.zeros((2 * n - 1, 6), np.float32)
+        lib().or_edge_tree(self.h, _p(keys), _p(child), _p(parent), _p(box), _p(ln), _p(nbox))
+        return keys, child, parent, box, ln, nbox
 
-    def edge_tree_sample(self, x, n, i, seed=0):
+    def edge_tree_sample(self, x, n, i, seed=0, silhouettes=True):
+        """One hierarchy draw (edge or -1, its probability); silhouettes=False
+        keeps nodes that hold no silhouette (the interior secondary-edge mode)."""
         pe = ctypes.c_float()
-        e = lib().or_edge_tree_sample(self.h, _p(_f64(x)), _p(_f64(n)), int(i), seed, ctypes.byref(pe))
+        e = lib().or_edge_tree_sample(self.h, _p(_f64(x)), _p(_f64(n)), int(i), seed, int(bool(silhouettes)),
+                                      ctypes.byref(pe))
         return e, float(pe.value)
 
 

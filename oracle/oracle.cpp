@@ -168,6 +168,7 @@ struct EdgeTree {
     std::vector<uint64_t> keys;     // sorted morton << 32 | edge
     std::vector<int> child, parent;
     std::vector<float> box, len;    // per node (internal nodes, then leaves)
+    std::vector<float> nbox;        // per node: box of the unit normals of the edges' faces
 };
 
 struct Scene {
@@ -752,7 +753,7 @@ struct SecCtx {         // secondary-edge state of a main path (backward only)
 struct Key { uint32_t k0, k1; };
 
 static int edge_tree_sample(const Scene& s, const D3& x, const D3& nn, const Ctr& ctr, int k, const Key& key,
-                            float& pe);
+                            bool sil, float& pe);
 
 static void push_face(Hash& h, int f) { h.push(f < 0 ? 0xFFFFFFFFu : (uint32_t)f); }
 
@@ -866,7 +867,7 @@ static D3 trace_estimator(const Scene& s, D3 o, D3 d, int exclude, int nvert, bo
             double wsel;            // 1 / (probability density of the edge point per unit length)
             if (sec->hier) {
                 float pe;
-                e = edge_tree_sample(s, x, n, ctr, k, key, pe);
+                e = edge_tree_sample(s, x, n, ctr, k, key, !sec->interior, pe);
                 if (e >= 0) {
                     const Edge& Es = s.edges[e];
                     wsel = length(s.vert(Es.vb) - s.vert(Es.va)) / (double)pe;
@@ -1493,6 +1494,7 @@ static void build_edge_tree(Scene& s) {
     T.parent.assign(2 * (size_t)n - (n > 0 ? 1 : 0), -1);
     T.box.assign(6 * T.parent.size(), 0.0f);
     T.len.assign(T.parent.size(), 0.0f);
+    T.nbox.assign(6 * T.parent.size(), 0.0f);
     if (n == 0) return;
     std::vector<float> mn(3 * (size_t)n), mx(3 * (size_t)n);
     for (int e = 0; e < n; ++e)
@@ -1510,6 +1512,32 @@ static void build_edge_tree(Scene& s) {
             d2 += d * d;
         }
         T.len[(n - 1) + i] = (float)std::sqrt(d2);
+        // unit normals of the adjacent faces, from the float vertices in double,
+        // rounded to float; a boundary edge (always a silhouette) or a degenerate
+        // face takes the whole cube [-1, 1]^3, which never culls
+        float* nb = &T.nbox[6 * ((size_t)(n - 1) + i)];
+        for (int k = 0; k < 3; ++k) { nb[k] = -1.0f; nb[3 + k] = 1.0f; }
+        if (E.f2 < 0) continue;
+        float un[2][3];
+        bool ok = true;
+        for (int j = 0; j < 2; ++j) {
+            const int f = j == 0 ? E.f1 : E.f2;
+            double q[3][3];
+            for (int a = 0; a < 3; ++a)
+                for (int k = 0; k < 3; ++k) q[a][k] = (double)(float)s.V[3 * s.F[3 * f + a] + k];
+            const double e1[3] = {q[1][0] - q[0][0], q[1][1] - q[0][1], q[1][2] - q[0][2]};
+            const double e2[3] = {q[2][0] - q[0][0], q[2][1] - q[0][1], q[2][2] - q[0][2]};
+            const double c[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                                 e1[0] * e2[1] - e1[1] * e2[0]};
+            const double l = std::sqrt((c[0] * c[0] + c[1] * c[1]) + c[2] * c[2]);
+            if (!(l > 0.0) || !std::isfinite(l)) { ok = false; break; }
+            for (int k = 0; k < 3; ++k) un[j][k] = (float)(c[k] / l);
+        }
+        if (!ok) continue;
+        for (int k = 0; k < 3; ++k) {
+            nb[k] = std::min(un[0][k], un[1][k]);
+            nb[3 + k] = std::max(un[0][k], un[1][k]);
+        }
     }
     if (n < 2) return;
     const int LEAF = (int)0x80000000;
@@ -1521,11 +1549,17 @@ static void build_edge_tree(Scene& s) {
     for (auto it = order.rbegin(); it != order.rend(); ++it) {
         const int i = *it;
         float l[2];
+        size_t ci[2];
         for (int c = 0; c < 2; ++c) {
             const int ch = T.child[2 * i + c];
-            l[c] = T.len[(ch & LEAF) ? (n - 1) + (ch & 0x7FFFFFFF) : ch];
+            ci[c] = (ch & LEAF) ? (size_t)(n - 1) + (ch & 0x7FFFFFFF) : (size_t)ch;
+            l[c] = T.len[ci[c]];
         }
         T.len[i] = l[0] + l[1];
+        for (int k = 0; k < 3; ++k) {
+            T.nbox[6 * (size_t)i + k] = std::min(T.nbox[6 * ci[0] + k], T.nbox[6 * ci[1] + k]);
+            T.nbox[6 * (size_t)i + 3 + k] = std::max(T.nbox[6 * ci[0] + 3 + k], T.nbox[6 * ci[1] + 3 + k]);
+        }
     }
 }
 
@@ -1533,16 +1567,40 @@ static void build_edge_tree(Scene& s) {
 // (float, contraction off, this operation order on both implementations):
 // zero when the node's box lies wholly behind the tangent plane of p (such
 // edges contribute nothing), otherwise the node's length over the squared
-// distance to the box centre plus the squared half diagonal.
-static float edge_node_weight(const EdgeTree& T, int code, const float p[3], const float nrm[3]) {
+// distance to the box centre plus the squared half diagonal.  The plane test
+// keeps a margin of 2^-16 of the box's size plus distance, so that a box lying
+// in the plane (edges coplanar with the shading point, as on a flat floor)
+// keeps its weight whatever the rounding of p: the cut only ever keeps extra
+// boxes, whose edges then contribute zero, and never drops a contributing one.
+// With sil, the node is also zero when no edge in it can be a silhouette from
+// p: an edge is one when p lies in front of one adjacent face plane and behind
+// the other, so a node whose faces all have p on the same side (the bound
+// N.(p - q) over q in the box and N in the node's normal box keeps one sign,
+// beyond the same margin) holds none.
+static float edge_node_weight(const EdgeTree& T, int code, const float p[3], const float nrm[3], bool sil) {
     const int idx = (code & (int)0x80000000) ? (T.n - 1) + (code & 0x7FFFFFFF) : code;
     const float* bx = &T.box[6 * (size_t)idx];
     const float dx = (bx[0] + bx[3]) * 0.5f - p[0], dy = (bx[1] + bx[4]) * 0.5f - p[1], dz = (bx[2] + bx[5]) * 0.5f - p[2];
     const float ex = bx[3] - bx[0], ey = bx[4] - bx[1], ez = bx[5] - bx[2];
     const float reach = (dx * nrm[0] + dy * nrm[1] + dz * nrm[2]) +
                         0.5f * ((std::fabs(nrm[0]) * ex + std::fabs(nrm[1]) * ey) + std::fabs(nrm[2]) * ez);
-    if (!(reach > 0.0f)) return 0.0f;
-    return T.len[idx] / ((dx * dx + dy * dy + dz * dz) + 0.25f * ((ex * ex + ey * ey) + ez * ez));
+    const float tol = 0x1p-16f * (((std::fabs(dx) + std::fabs(dy)) + std::fabs(dz)) + ((ex + ey) + ez));
+    if (!(reach > -tol)) return 0.0f;
+    if (sil) {
+        const float* nb = &T.nbox[6 * (size_t)idx];
+        const float d[3] = {dx, dy, dz}, e[3] = {ex, ey, ez};
+        float lo = 0.0f, hi = 0.0f, rad = 0.0f;
+        for (int k = 0; k < 3; ++k) {
+            const float a = -nb[k] * d[k], b = -nb[3 + k] * d[k];
+            lo = lo + std::min(a, b);
+            hi = hi + std::max(a, b);
+            rad = rad + std::max(std::fabs(nb[k]), std::fabs(nb[3 + k])) * (0.5f * e[k]);
+        }
+        if (lo - rad > tol || hi + rad < -tol) return 0.0f;
+    }
+    const float dl1 = ((std::fabs(dx) + std::fabs(dy)) + std::fabs(dz)) + 0.5f * ((ex + ey) + ez);
+    const float cb = (reach + tol) / (dl1 + tol);
+    return T.len[idx] * cb / ((dx * dx + dy * dy + dz * dz) + 0.25f * ((ex * ex + ey * ey) + ez * ez));
 }
 
 // Stochastic descent of the edge tree: at every node the child is taken with
@@ -1550,7 +1608,7 @@ static float edge_node_weight(const EdgeTree& T, int code, const float p[3], con
 // uses component l % 4 of the draw of block 4 + l / 4 at vertex k).  Returns the
 // edge (canonical index) and its probability pe, or -1 when every weight is zero.
 static int edge_tree_sample(const Scene& s, const D3& x, const D3& nn, const Ctr& ctr, int k, const Key& key,
-                            float& pe) {
+                            bool sil, float& pe) {
     const EdgeTree& T = s.etree;
     pe = 1.0f;
     if (T.n <= 0) return -1;
@@ -1562,14 +1620,14 @@ static int edge_tree_sample(const Scene& s, const D3& x, const D3& nn, const Ctr
         if (level >= 128) return -1;
         if ((level & 3) == 0) draw4(ctr, k, 4 + (level >> 2), key.k0, key.k1, u);
         const int c0 = T.child[2 * code], c1 = T.child[2 * code + 1];
-        const float w0 = edge_node_weight(T, c0, p, nrm), w1 = edge_node_weight(T, c1, p, nrm);
+        const float w0 = edge_node_weight(T, c0, p, nrm, sil), w1 = edge_node_weight(T, c1, p, nrm, sil);
         const float tot = w0 + w1;
         if (!(tot > 0.0f)) return -1;
         const float p0 = w0 / tot;
         if ((float)u[level & 3] < p0) { code = c0; pe *= p0; }
         else { code = c1; pe *= w1 / tot; }
     }
-    if (T.n == 1 && !(edge_node_weight(T, LEAF, p, nrm) > 0.0f)) return -1;
+    if (T.n == 1 && !(edge_node_weight(T, LEAF, p, nrm, sil) > 0.0f)) return -1;
     return (int)(T.keys[code & 0x7FFFFFFF] & 0xFFFFFFFFu);
 }
 
@@ -1776,22 +1834,23 @@ long long or_texel_index(int r, long long t, double alpha, double beta) { return
 
 // The secondary-edge importance tree: keys [n], child [n-1,2], parent [2n-1],
 // box [2n-1,6], len [2n-1] (the layout of or_lbvh).
-int or_edge_tree(void* p, unsigned long long* keys, int* child, int* parent, float* box, float* len) {
+int or_edge_tree(void* p, unsigned long long* keys, int* child, int* parent, float* box, float* len, float* nbox) {
     const EdgeTree& T = ((Scene*)p)->etree;
     std::copy(T.keys.begin(), T.keys.end(), keys);
     std::copy(T.child.begin(), T.child.end(), child);
     std::copy(T.parent.begin(), T.parent.end(), parent);
     std::copy(T.box.begin(), T.box.end(), box);
     std::copy(T.len.begin(), T.len.end(), len);
+    std::copy(T.nbox.begin(), T.nbox.end(), nbox);
     return T.n;
 }
 
 // One hierarchy draw from shading point x with normal n for the counters of
 // sample i (vertex 1): the edge (or -1) and its probability.
-int or_edge_tree_sample(void* p, const double* x, const double* n, long long i, unsigned seed, float* pe) {
+int or_edge_tree_sample(void* p, const double* x, const double* n, long long i, unsigned seed, int sil, float* pe) {
     Scene* s = (Scene*)p;
     Ctr ctr{(uint32_t)i, 0u, 0u, 3u};
-    return edge_tree_sample(*s, D3(x[0], x[1], x[2]), D3(n[0], n[1], n[2]), ctr, 1, Key{seed, s->id}, *pe);
+    return edge_tree_sample(*s, D3(x[0], x[1], x[2]), D3(n[0], n[1], n[2]), ctr, 1, Key{seed, s->id}, sil != 0, *pe);
 }
 
 // Specular lobe sampled from the visible normals (on) or from D cos(theta_h) (off, the default).
@@ -2083,7 +2142,7 @@ void or_secondary_term(void* p, const double* pp, const double* nn, const double
         double wsel;
         if (hier) {
             float pe;
-            e = edge_tree_sample(*s, x, n, ctr, 1, key, pe);
+            e = edge_tree_sample(*s, x, n, ctr, 1, key, true, pe);
             if (e < 0) continue;
             wsel = length(s->vert(s->edges[e].vb) - s->vert(s->edges[e].va)) / (double)pe;
         } else {

@@ -26,13 +26,14 @@ ST_FORWARD_MEGAKERNEL = 16
 ST_COUNT_WORK = 32
 ST_ALL_GRADS = 15
 ST_BACKWARD_RETRACE = 128
+ST_EDGE_SECONDARY_HIERARCHY = 256
 ST_ENV_SAMPLER_CDF = 0
 ST_ENV_SAMPLER_ALIAS = 1
 ST_BSDF_SAMPLER_HALFVECTOR = 0
 ST_BSDF_SAMPLER_VNDF = 1
 
 EXPORTED = ["st_render_opts_default", "st_scene_create", "st_scene_update", "st_scene_set_mesh_colors",
-            "st_scene_mesh_colors_info", "st_scene_subdivide", "st_scene_set_env_sampler", "st_scene_env_alias_table", "st_scene_set_bsdf_sampler", "st_render", "st_render_backward",
+            "st_scene_mesh_colors_info", "st_scene_subdivide", "st_scene_set_env_sampler", "st_scene_env_alias_table", "st_scene_set_bsdf_sampler", "st_scene_edge_tree", "st_render", "st_render_backward",
             "st_render_batch", "st_autotune", "st_check_errors", "st_read_work", "st_scene_info", "st_scene_edges", "st_scene_lbvh",
             "st_trace_rays", "st_profile_enable", "st_profile_read", "st_scene_destroy", "st_last_error",
             "st_version"]
@@ -74,6 +75,7 @@ def load(path: str = LIB_PATH):
     L.st_scene_subdivide.argtypes = [P, P, P, P]
     L.st_scene_set_env_sampler.argtypes = [P, I32, P]
     L.st_scene_set_bsdf_sampler.argtypes = [P, I32, P]
+    L.st_scene_edge_tree.argtypes = [P, P, P, P, P, P, P, P]
     L.st_scene_env_alias_table.argtypes = [P, P, P]
     L.st_render.argtypes = [P, P, I32, I32, I32, U32, ctypes.POINTER(StOpts), P, P]
     L.st_render_backward.argtypes = [P, P, I32, I32, I32, U32, ctypes.POINTER(StOpts), P, P, P, P]
@@ -202,6 +204,20 @@ class GPUScene:
     def set_env_sampler(self, method: int):
         """ST_ENV_SAMPLER_CDF (default) or ST_ENV_SAMPLER_ALIAS for environment texels."""
         _check(load().st_scene_set_env_sampler(self.h, int(method), _stream()))
+
+    def edge_tree(self):
+        """(keys, child, parent, box, len, nbox) of the secondary-edge importance tree (device tensors)."""
+        import torch
+        n = self.ne
+        keys = torch.empty(n, dtype=torch.int64, device="cuda")
+        child = torch.empty((max(n - 1, 1), 2), dtype=torch.int32, device="cuda")
+        parent = torch.empty(2 * n - 1, dtype=torch.int32, device="cuda")
+        box = torch.empty((2 * n - 1, 6), dtype=torch.float32, device="cuda")
+        ln = torch.empty(2 * n - 1, dtype=torch.float32, device="cuda")
+        nbox = torch.empty((2 * n - 1, 6), dtype=torch.float32, device="cuda")
+        _check(load().st_scene_edge_tree(self.h, _ptr(keys), _ptr(child), _ptr(parent), _ptr(box), _ptr(ln),
+                                         _ptr(nbox), _stream()))
+        return keys, child[:max(n - 1, 0)], parent, box, ln, nbox
 
     def set_bsdf_sampler(self, method: int):
         """ST_BSDF_SAMPLER_HALFVECTOR (default) or ST_BSDF_SAMPLER_VNDF for the specular lobe."""

@@ -148,6 +148,7 @@ struct st_scene {
     // hit records of the last single-scene wavefront render, for its backward
     GrowBuf recbuf;
     uint64_t version = 0;              // bumped by every change of geometry, materials or sampler
+    uint64_t etree_version = ~0ull;    // scene version the edge importance tree was built for
     bool rec_valid = false;
     uint64_t rec_key = 0;
 };
@@ -556,6 +557,11 @@ int st_scene_create(const float* V, int32_t nv, const int32_t* F, int32_t nf, co
     h.ealias = nullptr;
     h.env_alias = 0;
     h.vndf = 0;
+    h.etchild = nullptr;
+    h.etbox = nullptr;
+    h.etlen = nullptr;
+    h.etnbox = nullptr;
+    h.etedge = nullptr;
     h.scene_id = scene_id;
     HIPCHK2(hipMemcpyAsync(d.dscene, &h, sizeof(DevScene), hipMemcpyHostToDevice, s));
     HIPCHK2(hipStreamSynchronize(s));
@@ -686,6 +692,58 @@ int st_scene_set_env_sampler(st_scene* sc, int32_t method, hipStream_t s) {
     return ST_OK;
 }
 
+// the secondary-edge importance tree of the scene's current vertices (built,
+// and its arrays allocated, on first use after a change)
+static int ensure_edge_tree(st_scene* sc, hipStream_t s) {
+    SceneDev& d = sc->d;
+    if (d.ne <= 0 || sc->etree_version == sc->version) return ST_OK;
+    if (!d.echild) {
+        if (g_capturing) return fail(ST_ERR_INVALID_ARG, "edge tree not built: make one uncaptured call first");
+        const size_t n = (size_t)d.ne;
+        int rc = 0;
+        auto A = [&](int r) { if (r && !rc) rc = r; };
+        A(dalloc(&d.ebmin, n)); A(dalloc(&d.ebmax, n)); A(dalloc(&d.ecen, n)); A(dalloc(&d.ebounds, 16));
+        for (int b = 0; b < 2; ++b) { A(dalloc(&d.emkeys[b], n)); A(dalloc(&d.emvals[b], n)); }
+        A(dalloc(&d.ers_hist, 256 * ((n + 1023) / 1024)));
+        A(dalloc(&d.ekeys64, n));
+        A(dalloc(&d.echild, 2 * std::max<size_t>(n - 1, 1)));
+        A(dalloc(&d.eparent, 2 * n - 1));
+        A(dalloc(&d.ecnt, n));
+        A(dalloc(&d.eaabb, 6 * (2 * n - 1)));
+        A(dalloc(&d.elen, 2 * n - 1));
+        A(dalloc(&d.enbox, 6 * (2 * n - 1)));
+        if (rc) return rc;
+    }
+    launch_edge_tree(d, s);
+    d.hscene.etchild = d.echild;
+    d.hscene.etbox = d.eaabb;
+    d.hscene.etlen = d.elen;
+    d.hscene.etnbox = d.enbox;
+    d.hscene.etedge = d.eleaf_edge;
+    HIPCHK(hipMemcpyAsync(d.dscene, &d.hscene, sizeof(DevScene), hipMemcpyHostToDevice, s));
+    HIPCHK(hipGetLastError());
+    sc->etree_version = sc->version;
+    return ST_OK;
+}
+
+int st_scene_edge_tree(st_scene* sc, uint64_t* keys, int32_t* child, int32_t* parent, float* box, float* len,
+                       float* nbox, hipStream_t s) {
+    int rc = check_scene(sc);
+    if (rc) return rc;
+    rc = ensure_edge_tree(sc, s);
+    if (rc) return rc;
+    const SceneDev& d = sc->d;
+    const size_t n = (size_t)d.ne;
+    if (n == 0) return ST_OK;
+    if (keys) HIPCHK(hipMemcpyAsync(keys, d.ekeys64, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s));
+    if (child && n > 1) HIPCHK(hipMemcpyAsync(child, d.echild, sizeof(int) * 2 * (n - 1), hipMemcpyDeviceToDevice, s));
+    if (parent) HIPCHK(hipMemcpyAsync(parent, d.eparent, sizeof(int) * (2 * n - 1), hipMemcpyDeviceToDevice, s));
+    if (box) HIPCHK(hipMemcpyAsync(box, d.eaabb, sizeof(float) * 6 * (2 * n - 1), hipMemcpyDeviceToDevice, s));
+    if (len) HIPCHK(hipMemcpyAsync(len, d.elen, sizeof(float) * (2 * n - 1), hipMemcpyDeviceToDevice, s));
+    if (nbox) HIPCHK(hipMemcpyAsync(nbox, d.enbox, sizeof(float) * 6 * (2 * n - 1), hipMemcpyDeviceToDevice, s));
+    return ST_OK;
+}
+
 int st_scene_set_bsdf_sampler(st_scene* sc, int32_t method, hipStream_t s) {
     int rc = check_scene(sc);
     if (rc) return rc;
@@ -750,6 +808,11 @@ int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_
     if (bounces < 1 || bounces > 8) return fail(ST_ERR_INVALID_ARG, "bounces must be in [1, 8]");
     st_render_opts o = opts ? *opts : st_render_opts_default();
     if (!(o.edge_spp_ratio >= 0.0f) || o.edge_spp_ratio > 64.0f) return fail(ST_ERR_INVALID_ARG, "edge_spp_ratio must be in [0, 64]");
+    if ((o.flags & ST_EDGE_SECONDARY) && (o.flags & ST_EDGE_SECONDARY_HIERARCHY)) {
+        // before the camera table: it holds a copy of the scene view with the tree
+        rc = ensure_edge_tree(sc, s);
+        if (rc) return rc;
+    }
     CamSetup cs;
     st_scene* list[1] = {sc};
     rc = setup_cams(sc, list, 1, cams, nullptr, ncam, spp, (double)o.edge_spp_ratio, s, cs);
@@ -775,7 +838,7 @@ int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_
     p.spp = spp;
     p.B = bounces;
     p.seed = seed;
-    p.flags = o.flags & (15u | ST_EDGE_SECONDARY_INTERIOR);
+    p.flags = o.flags & (15u | ST_EDGE_SECONDARY_INTERIOR | ST_EDGE_SECONDARY_HIERARCHY);
     p.d_image = d_image;
     p.path_mask = o.path_mask;
     p.edge_mask = o.edge_mask;
@@ -1023,7 +1086,8 @@ void st_scene_destroy(st_scene* sc) {
     hipDeviceSynchronize();
     SceneDev& d = sc->d;
     void* ptrs[] = {d.V, d.F, d.mat, d.lights, d.env, d.fnorm, d.bmin, d.bmax, d.cen, d.bounds, d.mkeys[0], d.mkeys[1],
-                    d.mvals[0], d.mvals[1], d.rs_hist, d.keys64, d.child, d.parent, d.aabb, d.refit_cnt, d.tcost, d.tleaves, d.nodes4, d.flag4, d.id4,
+                    d.mvals[0], d.mvals[1], d.rs_hist, d.keys64, d.child, d.parent, d.aabb, d.refit_cnt, d.tcost, d.tleaves, d.ebmin, d.ebmax, d.ecen, d.ebounds, d.emkeys[0], d.emkeys[1],
+                    d.emvals[0], d.emvals[1], d.ers_hist, d.ekeys64, d.echild, d.eparent, d.ecnt, d.eaabb, d.elen, d.enbox, d.nodes4, d.flag4, d.id4,
                     d.tri, d.edges, d.edge_w, d.eguide, d.mguide, d.cguide, d.ecdf, d.etotal_d, d.etotal_f, d.row_dom, d.rowcos, d.cond, d.marg,
                     d.env_rows, d.env_total, d.texpdf, d.err, d.work, d.dscene, d.vf_off, d.vf_idx, d.facc, d.macc, d.fe,
                     d.ealias};

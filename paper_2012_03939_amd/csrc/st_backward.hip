@@ -137,6 +137,7 @@ k_adjoint(BwdParams p, long long total) {
     TravStack st = make_trav_stack(lds, p.spill, p.err, p.work ? p.work + 3 * WORK_ADJOINT : nullptr);
     const bool want_interior = !JOBS && (p.flags & 1u), want_secondary = p.flags & 4u;
     const bool sec_interior = p.flags & ST_EDGE_SECONDARY_INTERIOR;   // creases / material edges too
+    const bool hier = p.flags & ST_EDGE_SECONDARY_HIERARCHY;           // edges from the importance tree
     const bool defer = !JOBS && p.sec_mask != nullptr;
     const long long stride = (long long)gridDim.x * blockDim.x;
     const long long count = JOBS ? (long long)*p.sec_njobs : total;
@@ -168,12 +169,12 @@ k_adjoint(BwdParams p, long long total) {
         int rf[BM], rtex[BM], rse[BM];
         uint32_t rfl[BM];
         V3 rx[BM], rwe[BM], rwi[BM], resc[BM], rbeta[BM], rsecm[BM];
-        float rden[BM], rpb[BM], rte[BM], rsecc[BM];
+        float rden[BM], rpb[BM], rte[BM], rsecc[BM], rsw[BM];
 #pragma unroll
         for (int i = 0; i < BM; ++i) {
             rf[i] = -1; rtex[i] = 0; rse[i] = -1; rfl[i] = 0;
             rx[i] = rwe[i] = rwi[i] = resc[i] = rbeta[i] = rsecm[i] = V3{0.f, 0.f, 0.f};
-            rden[i] = rpb[i] = rte[i] = rsecc[i] = 0.0f;
+            rden[i] = rpb[i] = rte[i] = rsecc[i] = rsw[i] = 0.0f;
         }
         int nvtx = 0;
         {
@@ -251,8 +252,27 @@ k_adjoint(BwdParams p, long long total) {
                 const bool continues = (k < p.B) || S.has_env;
                 if (want_secondary && continues && S.ne > 0 && *S.etotal > 0.0f) {
                     const float4 u = draw4(ctr, k, 3, key);
-                    put(rse, k - 1, cdf_guided(S.ecdf, S.ne, S.eguide, S.eglog, (double)u.x));
+                    // the edge (-2: the hierarchy found no edge in front of the tangent
+                    // plane) and 1 / (density of the edge point per unit length)
+                    int e;
+                    float wsel;
+                    if (hier) {
+                        float pe;
+                        e = edge_tree_sample(S, xh, n, ctr, k, key, !sec_interior, pe);
+                        if (e >= 0) {
+                            const int4 Eh = S.edges[e];
+                            wsel = len(ld3(S.V + 3 * Eh.y) - ld3(S.V + 3 * Eh.x)) / pe;
+                        } else {
+                            e = -2;
+                            wsel = 0.0f;
+                        }
+                    } else {
+                        e = cdf_guided(S.ecdf, S.ne, S.eguide, S.eglog, (double)u.x);
+                        wsel = *S.etotal;
+                    }
+                    put(rse, k - 1, e);
                     put(rte, k - 1, u.y);
+                    put(rsw, k - 1, wsel);
                 }
                 put(rf, k - 1, f);
                 put(rx, k - 1, xh);
@@ -282,7 +302,8 @@ k_adjoint(BwdParams p, long long total) {
             uint32_t accepted = 0;
             for (int k = 0; k < nvtx; ++k) {
                 const int e = sel(rse, k);
-                if (e < 0 || (JOBS && k != ksel)) continue;
+                if (e == -1 || (JOBS && k != ksel)) continue;
+                if (e == -2) { h.push(0xFFFFFFFFu); h.push(0u); continue; }
                 h.push((uint32_t)e);
                 const int f = sel(rf, k);
                 const V3 xh = sel(rx, k);
@@ -318,7 +339,7 @@ k_adjoint(BwdParams p, long long total) {
                 const V3 dirk = k == 0 ? d0 : sel(rwi, k - 1);
                 const Mat m = load_mat(S.mat + 7 * (size_t)texel_of(S, f, xh));
                 const V3 fv = brdf_eval(ud, -dirk, n, m);
-                const float cc = dot(mul(w, mul(sel(rbeta, k), fv)), Ls[0] - Ls[1]) * cv * (*S.etotal / r2);
+                const float cc = dot(mul(w, mul(sel(rbeta, k), fv)), Ls[0] - Ls[1]) * cv * (sel(rsw, k) / r2);
                 put(rsecc, k, cc);
                 put(rsecm, k, mv);
                 put(rfl, k, sel(rfl, k) | R_SEC);

@@ -698,6 +698,147 @@ void launch_subdivide(const SceneDev& s, float* out_V, int32_t* out_F, hipStream
 }
 
 
+// ---------------------------------------------------------------------------
+// secondary-edge importance tree: the same radix tree over the edges' boxes,
+// each node also carrying the float sum of the edge lengths below it
+// ---------------------------------------------------------------------------
+__global__ void k_edge_prep(const float* __restrict__ V, const int4* __restrict__ edges, int ne, float4* bmin,
+                            float4* bmax, float4* cen) {
+#pragma clang fp contract(off)
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ne) return;
+    const int4 E = edges[e];
+    const V3 a = ld3(V + 3 * E.x), c = ld3(V + 3 * E.y);
+    const V3 mn{fminf(a.x, c.x), fminf(a.y, c.y), fminf(a.z, c.z)};
+    const V3 mx{fmaxf(a.x, c.x), fmaxf(a.y, c.y), fmaxf(a.z, c.z)};
+    bmin[e] = make_float4(mn.x, mn.y, mn.z, 0.f);
+    bmax[e] = make_float4(mx.x, mx.y, mx.z, 0.f);
+    const float cx = mn.x + mx.x, cy = mn.y + mx.y, cz = mn.z + mx.z;
+    cen[e] = make_float4(cx * 0.5f, cy * 0.5f, cz * 0.5f, 0.f);
+}
+
+// unit normal of face f: the double cross product of the float edge vectors over
+// its double length, rounded to float; false for a degenerate face
+__device__ __forceinline__ bool unit_normal_d(const float* __restrict__ V, const int* __restrict__ F, int f,
+                                              float* un) {
+#pragma clang fp contract(off)
+    double q[3][3];
+    for (int a = 0; a < 3; ++a) {
+        const int v = F[3 * f + a];
+        for (int k = 0; k < 3; ++k) q[a][k] = (double)V[3 * v + k];
+    }
+    const double e1x = q[1][0] - q[0][0], e1y = q[1][1] - q[0][1], e1z = q[1][2] - q[0][2];
+    const double e2x = q[2][0] - q[0][0], e2y = q[2][1] - q[0][1], e2z = q[2][2] - q[0][2];
+    const double cx = e1y * e2z - e1z * e2y, cy = e1z * e2x - e1x * e2z, cz = e1x * e2y - e1y * e2x;
+    const double l = sqrt((cx * cx + cy * cy) + cz * cz);
+    if (!(l > 0.0) || !isfinite(l)) return false;
+    un[0] = (float)(cx / l); un[1] = (float)(cy / l); un[2] = (float)(cz / l);
+    return true;
+}
+
+// leaves of the edge tree in sorted order: box, length (the double-precision
+// length of the float endpoints, rounded to float) and the box of the adjacent
+// faces' unit normals (the whole cube [-1, 1]^3, which never culls, for a
+// boundary edge or a degenerate face); clears the refit counters
+__global__ void k_eleaf_init(const uint32_t* __restrict__ sedge, const float4* __restrict__ bmin,
+                             const float4* __restrict__ bmax, const int4* __restrict__ edges,
+                             const float* __restrict__ V, const int* __restrict__ F, int n, float* aabb, float* len,
+                             float* nbox, int* cnt) {
+#pragma clang fp contract(off)
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n - 1) cnt[i] = 0;
+    if (i >= n) return;
+    const int e = (int)sedge[i];
+    float* bx = aabb + 6 * ((size_t)(n - 1) + i);
+    const float4 mn = bmin[e], mx = bmax[e];
+    bx[0] = mn.x; bx[1] = mn.y; bx[2] = mn.z; bx[3] = mx.x; bx[4] = mx.y; bx[5] = mx.z;
+    const int4 E = edges[e];
+    const double dx = (double)V[3 * E.y] - (double)V[3 * E.x];
+    const double dy = (double)V[3 * E.y + 1] - (double)V[3 * E.x + 1];
+    const double dz = (double)V[3 * E.y + 2] - (double)V[3 * E.x + 2];
+    len[(size_t)(n - 1) + i] = (float)sqrt((dx * dx + dy * dy) + dz * dz);
+    float nb[6] = {-1.0f, -1.0f, -1.0f, 1.0f, 1.0f, 1.0f};
+    float n1[3], n2[3];
+    if (E.w >= 0 && unit_normal_d(V, F, E.z, n1) && unit_normal_d(V, F, E.w, n2))
+        for (int k = 0; k < 3; ++k) {
+            nb[k] = fminf(n1[k], n2[k]);
+            nb[3 + k] = fmaxf(n1[k], n2[k]);
+        }
+    float* o = nbox + 6 * ((size_t)(n - 1) + i);
+    for (int k = 0; k < 6; ++k) o[k] = nb[k];
+}
+
+// bottom-up boxes and length sums of the edge tree (second arrival at a node
+// combines its two children, as in the refit)
+__global__ void k_erefit(const int* __restrict__ parent, const int* __restrict__ child, int n, float* aabb,
+                         float* len, float* nbox, int* cnt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int node = parent[(n - 1) + i];
+    for (int depth = 0; node >= 0 && depth < 4096; ++depth) {
+        __threadfence();
+        if (atomicAdd(&cnt[node], 1) == 0) return;
+        __threadfence();
+        const int c0 = child[2 * node], c1 = child[2 * node + 1];
+        const size_t i0 = (c0 & (int)LEAF_BIT) ? (size_t)(n - 1) + (c0 & 0x7FFFFFFF) : (size_t)c0;
+        const size_t i1 = (c1 & (int)LEAF_BIT) ? (size_t)(n - 1) + (c1 & 0x7FFFFFFF) : (size_t)c1;
+        float box[6];
+        for (int k = 0; k < 3; ++k) {
+            box[k] = fminf(aload(aabb + 6 * i0 + k), aload(aabb + 6 * i1 + k));
+            box[3 + k] = fmaxf(aload(aabb + 6 * i0 + 3 + k), aload(aabb + 6 * i1 + 3 + k));
+        }
+        for (int k = 0; k < 6; ++k)
+            __hip_atomic_store((uint32_t*)(aabb + 6 * (size_t)node + k), __float_as_uint(box[k]), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        for (int k = 0; k < 3; ++k) {
+            box[k] = fminf(aload(nbox + 6 * i0 + k), aload(nbox + 6 * i1 + k));
+            box[3 + k] = fmaxf(aload(nbox + 6 * i0 + 3 + k), aload(nbox + 6 * i1 + 3 + k));
+        }
+        for (int k = 0; k < 6; ++k)
+            __hip_atomic_store((uint32_t*)(nbox + 6 * (size_t)node + k), __float_as_uint(box[k]), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        const float l = aload(len + i0) + aload(len + i1);
+        __hip_atomic_store((uint32_t*)(len + node), __float_as_uint(l), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        node = parent[node];
+    }
+}
+
+// Morton keys of n centres, stably sorted (4 LSD passes); returns the buffer
+// index that holds the sorted (key, value) pairs
+static int radix_sort_keys(const float4* cen, int n, float* bounds, uint32_t* const mk[2], uint32_t* const mv[2],
+                           uint32_t* hist, hipStream_t st) {
+    ST_LAUNCH("k_bounds", k_bounds, dim3(1), dim3(1024), 0, st, cen, n, bounds);
+    ST_LAUNCH("k_morton", k_morton, dim3(nb(n, 256)), dim3(256), 0, st, cen, n, bounds, mk[0], mv[0]);
+    const int nblocks = (n + RS_TILE - 1) / RS_TILE;
+    int cur = 0;
+    for (int shift = 0; shift < 32; shift += 8) {
+        ST_LAUNCH("k_rs_hist", k_rs_hist, dim3(nblocks), dim3(RS_THREADS), 0, st, mk[cur], n, shift, hist, nblocks);
+        ST_LAUNCH("k_rs_scan", k_rs_scan, dim3(1), dim3(1024), 0, st, hist, 256 * nblocks);
+        ST_LAUNCH("k_rs_scatter", k_rs_scatter, dim3(nblocks), dim3(RS_THREADS), 0, st, mk[cur], mv[cur], mk[cur ^ 1],
+                  mv[cur ^ 1], n, shift, hist, nblocks);
+        cur ^= 1;
+    }
+    return cur;
+}
+
+void launch_edge_tree(SceneDev& s, hipStream_t st) {
+    const int n = s.ne;
+    if (n <= 0) return;
+    ST_LAUNCH("k_edge_prep", k_edge_prep, dim3(nb(n, 256)), dim3(256), 0, st, s.V, s.edges, n, s.ebmin, s.ebmax,
+              s.ecen);
+    const int cur = radix_sort_keys(s.ecen, n, s.ebounds, s.emkeys, s.emvals, s.ers_hist, st);
+    const uint32_t* sm = s.emkeys[cur];
+    const uint32_t* se = s.emvals[cur];
+    s.eleaf_edge = se;
+    ST_LAUNCH("k_keys64", k_keys64, dim3(nb(n, 256)), dim3(256), 0, st, sm, se, n, s.ekeys64);
+    if (n > 1) ST_LAUNCH("k_karras", k_karras, dim3(nb(n - 1, 256)), dim3(256), 0, st, sm, se, n, s.echild, s.eparent);
+    ST_LAUNCH("k_eleaf_init", k_eleaf_init, dim3(nb(n, 256)), dim3(256), 0, st, se, s.ebmin, s.ebmax, s.edges, s.V,
+              s.F, n, s.eaabb, s.elen, s.enbox, s.ecnt);
+    if (n > 1)
+        ST_LAUNCH("k_erefit", k_erefit, dim3(nb(n, 256)), dim3(256), 0, st, s.eparent, s.echild, n, s.eaabb, s.elen,
+                  s.enbox, s.ecnt);
+}
+
 void launch_scene_geometry(SceneDev& s, hipStream_t st) {
     const int nf = s.nf;
     if (nf <= 0) return;

@@ -132,6 +132,11 @@ struct DevScene {
     const int* eguide;    // guide table of ecdf, 2^eglog entries
     const int* mguide;    // guide table of the env marginal CDF, 2^mglog entries
     const int* cguide;    // guide tables of the env conditional CDFs, 2^cglog entries per row
+    const int* etchild;   // secondary-edge importance tree: children [ne-1, 2]
+    const float* etbox;   // node boxes [2ne-1, 6] (internal nodes, then leaves)
+    const float* etlen;   // node length sums [2ne-1]
+    const float* etnbox;  // node boxes of the adjacent faces' unit normals [2ne-1, 6]
+    const uint32_t* etedge; // sorted leaf -> edge
     const EnvAlias* ealias; // [he*we] alias table of the texel probabilities, used when env_alias
     int env_alias;
     int vndf;             // specular lobe sampled from the visible normals
@@ -566,6 +571,68 @@ __device__ __forceinline__ int bsdf_sample(float4 u, V3 wo, V3 n, float alpha, b
     const float z = sqrtf(fmaxf(0.0f, 1.0f - u.y));
     wi = t * (r * cp) + b * (r * sp) + n * z;
     return 1;
+}
+
+// Secondary-edge importance hierarchy.  Node weight seen from the shading
+// point p with normal nrm (contraction off, this operation order): zero when the
+// node's box lies wholly behind the tangent plane of p (with a margin of 2^-16
+// of the box's size plus distance, so that a box lying in the plane keeps its
+// weight whatever the rounding of p), or (sil) when no edge in it can be a
+// silhouette from p: the bound of N.(p - q) over q in the box and N in the
+// node's box of face normals keeps one sign beyond the same margin; otherwise
+// its length sum, times a cosine factor (reach + margin) / (L1 distance + half
+// the box's edge sum + margin) in (0, 1], over (squared distance to the box
+// centre + squared half diagonal).  The descent
+// takes each child with probability proportional to its weight, by a fresh
+// uniform per level (level l: component l % 4 of the draw of block 4 + l / 4 at
+// vertex k); returns the edge and its probability pe, or -1 when all weights vanish.
+__device__ __forceinline__ float edge_node_weight(const DevScene& S, int code, V3 p, V3 nrm, bool sil) {
+#pragma clang fp contract(off)
+    const int idx = (code & (int)LEAF_BIT) ? (S.ne - 1) + (code & 0x7FFFFFFF) : code;
+    const float* bx = S.etbox + 6 * (size_t)idx;
+    const float dx = (bx[0] + bx[3]) * 0.5f - p.x, dy = (bx[1] + bx[4]) * 0.5f - p.y, dz = (bx[2] + bx[5]) * 0.5f - p.z;
+    const float ex = bx[3] - bx[0], ey = bx[4] - bx[1], ez = bx[5] - bx[2];
+    const float reach = (dx * nrm.x + dy * nrm.y + dz * nrm.z) +
+                        0.5f * ((fabsf(nrm.x) * ex + fabsf(nrm.y) * ey) + fabsf(nrm.z) * ez);
+    const float tol = 0x1p-16f * (((fabsf(dx) + fabsf(dy)) + fabsf(dz)) + ((ex + ey) + ez));
+    if (!(reach > -tol)) return 0.0f;
+    if (sil) {
+        const float* nb = S.etnbox + 6 * (size_t)idx;
+        const float a0 = -nb[0] * dx, b0 = -nb[3] * dx, a1 = -nb[1] * dy, b1 = -nb[4] * dy;
+        const float a2 = -nb[2] * dz, b2 = -nb[5] * dz;
+        const float lo = ((0.0f + fminf(a0, b0)) + fminf(a1, b1)) + fminf(a2, b2);
+        const float hi = ((0.0f + fmaxf(a0, b0)) + fmaxf(a1, b1)) + fmaxf(a2, b2);
+        const float rad = ((0.0f + fmaxf(fabsf(nb[0]), fabsf(nb[3])) * (0.5f * ex)) +
+                           fmaxf(fabsf(nb[1]), fabsf(nb[4])) * (0.5f * ey)) +
+                          fmaxf(fabsf(nb[2]), fabsf(nb[5])) * (0.5f * ez);
+        if (lo - rad > tol || hi + rad < -tol) return 0.0f;
+    }
+    const float dl1 = ((fabsf(dx) + fabsf(dy)) + fabsf(dz)) + 0.5f * ((ex + ey) + ez);
+    const float cb = (reach + tol) / (dl1 + tol);
+    return S.etlen[idx] * cb / ((dx * dx + dy * dy + dz * dz) + 0.25f * ((ex * ex + ey * ey) + ez * ez));
+}
+
+__device__ __forceinline__ int edge_tree_sample(const DevScene& S, V3 p, V3 nrm, const Ctr& ctr, int k,
+                                                const Key& key, bool sil, float& pe) {
+#pragma clang fp contract(off)
+    pe = 1.0f;
+    if (S.ne <= 0) return -1;
+    int code = S.ne == 1 ? (int)LEAF_BIT : 0;
+    float4 u = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int level = 0; !(code & (int)LEAF_BIT); ++level) {
+        if (level >= 128) return -1;
+        if ((level & 3) == 0) u = draw4(ctr, k, 4 + (level >> 2), key);
+        const int c0 = S.etchild[2 * code], c1 = S.etchild[2 * code + 1];
+        const float w0 = edge_node_weight(S, c0, p, nrm, sil), w1 = edge_node_weight(S, c1, p, nrm, sil);
+        const float tot = w0 + w1;
+        if (!(tot > 0.0f)) return -1;
+        const float p0 = w0 / tot;
+        const float ul = (level & 3) == 0 ? u.x : (level & 3) == 1 ? u.y : (level & 3) == 2 ? u.z : u.w;
+        if (ul < p0) { code = c0; pe *= p0; }
+        else { code = c1; pe *= w1 / tot; }
+    }
+    if (S.ne == 1 && !(edge_node_weight(S, (int)LEAF_BIT, p, nrm, sil) > 0.0f)) return -1;
+    return (int)S.etedge[code & 0x7FFFFFFF];
 }
 
 // Reverse-mode derivative of f(wi, wo, n, m) contracted with gf (rgb):

@@ -50,6 +50,17 @@ struct SceneDev {
     float* aabb = nullptr;                   // [(2*nf-1)*6]
     int* refit_cnt = nullptr;
     float* tcost = nullptr;                  // [nf-1] SAH cost of every internal node's subtree
+    // secondary-edge importance tree (built on demand): radix tree over the edge
+    // boxes with per-node length sums; sorted leaf -> edge in evals_sorted
+    float4 *ebmin = nullptr, *ebmax = nullptr, *ecen = nullptr;
+    float* ebounds = nullptr;
+    uint32_t* emkeys[2] = {nullptr, nullptr};
+    uint32_t* emvals[2] = {nullptr, nullptr};
+    uint32_t* ers_hist = nullptr;
+    uint64_t* ekeys64 = nullptr;
+    int *echild = nullptr, *eparent = nullptr, *ecnt = nullptr;
+    float *eaabb = nullptr, *elen = nullptr, *enbox = nullptr;
+    const uint32_t* eleaf_edge = nullptr;    // points into emkeys/emvals after the sort
     int* tleaves = nullptr;                  // [nf-1] triangles below every internal node
     float4* nodes4 = nullptr;                // [(nf-1)*8] 4-wide nodes (at most nf-1 of them)
     int* flag4 = nullptr;                    // [nf-1] even-depth flag of the binary nodes
@@ -141,6 +152,7 @@ struct FwdParams {
 };
 
 void launch_scene_geometry(SceneDev& s, hipStream_t st);
+void launch_edge_tree(SceneDev& s, hipStream_t st);
 void launch_subdivide(const SceneDev& s, float* out_V, int32_t* out_F, hipStream_t st);
 void launch_guide(const double* C, int n, size_t cstride, int rows, int* guide, int glog, hipStream_t st);
 int guide_log2(int n);

@@ -29,7 +29,7 @@ def B():
     return binding
 
 
-@pytest.mark.parametrize("flags", [4, 5, 4 | 64])
+@pytest.mark.parametrize("flags", [4, 5, 4 | 64, 4 | 256, 5 | 64 | 256])
 def test_deferred_equals_inline(B, flags):
     _say(f"case secondary edges deferred vs inline, flags={flags}")
     rng = np.random.default_rng(12)

@@ -1072,23 +1072,38 @@ def test_vndf_samples_only_visible_normals():
 # secondary-edge importance hierarchy
 # --------------------------------------------------------------------------
 
-def _node_weight(box, ln, p, nrm):
-    """The node importance written out in float32 (box lower/upper corners, total length)."""
+def _node_weight(box, ln, nb, p, nrm, sil=True):
+    """The node importance written out in float32 (box lower/upper corners, total
+    length, box of the face normals)."""
     f = np.float32
     c = (box[:3] + box[3:]) * f(0.5) - p
     e = box[3:] - box[:3]
     reach = (c[0] * nrm[0] + c[1] * nrm[1] + c[2] * nrm[2]) + f(0.5) * ((abs(nrm[0]) * e[0] + abs(nrm[1]) * e[1])
                                                                        + abs(nrm[2]) * e[2])
-    if not reach > 0:
+    tol = f(2.0 ** -16) * (((abs(c[0]) + abs(c[1])) + abs(c[2])) + ((e[0] + e[1]) + e[2]))
+    if not reach > -tol:
         return f(0.0)
-    return f(ln / ((c[0] * c[0] + c[1] * c[1] + c[2] * c[2]) + f(0.25) * ((e[0] * e[0] + e[1] * e[1]) + e[2] * e[2])))
+    if sil:
+        lo = hi = rad = f(0.0)
+        for k in range(3):
+            a, b = -nb[k] * c[k], -nb[3 + k] * c[k]
+            lo, hi = lo + min(a, b), hi + max(a, b)
+            rad = rad + max(abs(nb[k]), abs(nb[3 + k])) * (f(0.5) * e[k])
+        if lo - rad > tol or hi + rad < -tol:
+            return f(0.0)
+    dl1 = ((abs(c[0]) + abs(c[1])) + abs(c[2])) + f(0.5) * ((e[0] + e[1]) + e[2])
+    cb = (reach + tol) / (dl1 + tol)
+    return f(ln * cb / ((c[0] * c[0] + c[1] * c[1] + c[2] * c[2]) + f(0.25) * ((e[0] * e[0] + e[1] * e[1]) + e[2] * e[2])))
 
 
-def _all_edge_probs(tree, p, nrm):
-    keys, child, parent, box, ln = tree
+def _all_edge_probs(tree, p, nrm, sil=True):
+    """Probability of every edge under the descent, and of a dead end (a node
+    whose children both weigh zero); the two add up to one."""
+    keys, child, parent, box, ln, nb = tree
     n = keys.shape[0]
     LEAF = 0x80000000
     probs = np.zeros(n)
+    dead = 0.0
 
     def idx(code):
         return n - 1 + (code & 0x7FFFFFFF) if code & LEAF else code
@@ -1097,9 +1112,10 @@ def _all_edge_probs(tree, p, nrm):
     while stack:
         node, pr = stack.pop()
         c = [int(x) & 0xFFFFFFFF for x in child[node]]
-        w = [_node_weight(box[idx(k)], ln[idx(k)], p, nrm) for k in c]
+        w = [_node_weight(box[idx(k)], ln[idx(k)], nb[idx(k)], p, nrm, sil) for k in c]
         tot = np.float32(w[0] + w[1])
         if not tot > 0:
+            dead += pr
             continue
         for k, wk in zip(c, w):
             q = pr * float(np.float32(wk / tot))
@@ -1109,17 +1125,27 @@ def _all_edge_probs(tree, p, nrm):
                 probs[int(keys[k & 0x7FFFFFFF]) & 0xFFFFFFFF] += q
             else:
                 stack.append((k, q))
-    return probs
+    assert abs(probs.sum() + dead - 1.0) < 1e-5
+    return probs, dead
 
 
 def test_edge_tree_valid():
     V, F = S.noise_sphere(4, 0.1, noise_seed=2)
     sc = O.OracleScene(V.astype(np.float32), F, S.uniform_materials(F.shape[0]), None, None)
-    keys, child, parent, box, ln = sc.edge_tree()
+    keys, child, parent, box, ln, nb = sc.edge_tree()
     E = sc.edges()
     n = E.shape[0]
     V32 = V.astype(np.float32)
     assert _tree_check(child, parent, box, n) > 0              # leaves once, boxes exact unions
+    assert _tree_check(child, parent, nb, n) > 0               # normal boxes: exact unions too
+    # a leaf's normal box holds the unit normals of both faces beside its edge
+    Vd = V32.astype(np.float64)
+    for i, key in enumerate(keys):
+        e = int(key) & 0xFFFFFFFF
+        for f in E[e, 2:]:
+            nf = np.cross(Vd[F[f, 1]] - Vd[F[f, 0]], Vd[F[f, 2]] - Vd[F[f, 0]])
+            nf /= np.linalg.norm(nf)
+            assert np.all(nb[n - 1 + i, :3] <= nf + 1e-7) and np.all(nf <= nb[n - 1 + i, 3:] + 1e-7)
     leaf_len = np.sqrt(((V32[E[:, 1]].astype(np.float64) - V32[E[:, 0]].astype(np.float64)) ** 2).sum(1))
     order = (keys & np.uint64(0xFFFFFFFF)).astype(np.int64)
     assert np.array_equal(ln[n - 1:], leaf_len[order].astype(np.float32))
@@ -1132,8 +1158,9 @@ def test_edge_tree_valid():
 
 
 def test_edge_tree_sampling_matches_probabilities():
-    """Sampled edges follow the product of the per-level probabilities, which sum
-    to one over the edges; edges wholly behind the tangent plane are never drawn."""
+    """Sampled edges follow the product of the per-level probabilities (with the
+    dead ends, where both children of a node weigh zero, as one more outcome);
+    edges wholly behind the tangent plane are never drawn."""
     from scipy import stats
     Vs, Fs = S.noise_sphere(3, 0.1, noise_seed=5)
     floor = np.array([[-3, -1.5, -3], [3, -1.5, -3], [3, -1.5, 3], [-3, -1.5, 3]], np.float32)
@@ -1145,18 +1172,81 @@ def test_edge_tree_sampling_matches_probabilities():
     E = sc.edges()
     x = np.array([0.6, -1.5, 0.3])                      # on the floor, under the sphere
     nrm = np.array([0.1, 0.98, 0.15]) / np.linalg.norm([0.1, 0.98, 0.15])
-    P = _all_edge_probs(tree, x.astype(np.float32), nrm.astype(np.float32))
-    assert abs(P.sum() - 1.0) < 1e-5
+    P, dead = _all_edge_probs(tree, x.astype(np.float32), nrm.astype(np.float32))
     N = 40000
-    counts = np.zeros(E.shape[0])
+    counts = np.zeros(E.shape[0] + 1)
     for i in range(N):
         e, pe = sc.edge_tree_sample(x, nrm, i, seed=3)
-        assert e >= 0 and abs(pe - P[e]) <= 1e-6 * P[e] + 1e-12
+        assert e == -1 or abs(pe - P[e]) <= 1e-6 * P[e] + 1e-12
         counts[e] += 1
+    P = np.append(P, dead)
     behind = np.array([(np.stack([V[a], V[b]]) - x) @ nrm for a, b in E[:, :2]]).max(axis=1) < -1e-3
+    behind = np.append(behind, False)
     assert behind.any() and counts[behind].sum() == 0 and P[behind].sum() == 0
     keep = P * N > 15
     exp = P[keep] * N
     obs = counts[keep]
     exp *= obs.sum() / exp.sum()
     assert stats.chisquare(obs, exp).pvalue > 1e-4
+
+
+def _hier_scene():
+    Vs, Fs = S.noise_sphere(4, 0.2, noise_seed=9)
+    floor = np.array([[-3, -1.4, -3], [3, -1.4, -3], [3, -1.4, 3], [-3, -1.4, 3]], np.float32)
+    nv = Vs.shape[0]
+    V = np.concatenate([Vs, floor]).astype(np.float32)
+    F = np.concatenate([Fs, [[nv, nv + 2, nv + 1], [nv, nv + 3, nv + 2]]]).astype(np.int32)
+    return V, F, O.OracleScene(V, F, S.uniform_materials(F.shape[0]), None, None)
+
+
+def _could_contribute(V, F, E, e, x, n, face, silhouettes):
+    """Brute force, in float64: edge e can carry a secondary-edge sample at x when
+    it is not an edge of the shading face, is a silhouette from x (one adjacent
+    face plane with x in front, the other with x behind, or a boundary edge)
+    unless silhouettes is off, and has a point seen above the tangent plane."""
+    va, vb, f1, f2 = (int(t) for t in E[e])
+    if face in (f1, f2):
+        return False
+    Vd = V.astype(np.float64)
+    if silhouettes and f2 >= 0:
+        s = [np.dot(np.cross(Vd[F[f, 1]] - Vd[F[f, 0]], Vd[F[f, 2]] - Vd[F[f, 0]]), x - Vd[va]) for f in (f1, f2)]
+        if (s[0] > 0) == (s[1] > 0):
+            return False
+    y = Vd[va][None, :] + np.linspace(0, 1, 65)[:, None] * (Vd[vb] - Vd[va])[None, :]
+    d = y - x
+    r = np.linalg.norm(d, axis=1)
+    return bool(((d @ n) > 1e-5 * r).any())
+
+
+@pytest.mark.parametrize("silhouettes", [True, False])
+def test_edge_tree_keeps_every_contributing_edge(silhouettes):
+    """The hierarchy only ever zeroes edges that cannot contribute: at shading
+    points on a bumpy sphere and on the floor under it, every edge that passes
+    the brute-force test has a positive probability; with the silhouette bound on,
+    more of the probability lands on such edges than under the length CDF."""
+    V, F, sc = _hier_scene()
+    tree = sc.edge_tree()
+    E = sc.edges()
+    Vd = V.astype(np.float64)
+    rng = np.random.default_rng(4)
+    points = []
+    for f in rng.choice(F.shape[0] - 2, 6, replace=False):
+        b = rng.dirichlet([2.0, 2.0, 2.0])
+        x = b @ Vd[F[f]]
+        n = np.cross(Vd[F[f, 1]] - Vd[F[f, 0]], Vd[F[f, 2]] - Vd[F[f, 0]])
+        points.append((x, n / np.linalg.norm(n), int(f)))
+    points.append((np.array([0.7, -1.4, 0.2]), np.array([0.0, 1.0, 0.0]), F.shape[0] - 1))
+    points.append((np.array([-2.2, -1.4, 1.9]), np.array([0.0, 1.0, 0.0]), F.shape[0] - 2))
+    useful = []
+    for x, n, face in points:
+        P, dead = _all_edge_probs(tree, x.astype(np.float32), n.astype(np.float32), silhouettes)
+        ok = np.array([_could_contribute(V, F, E, e, x, n, face, silhouettes) for e in range(E.shape[0])])
+        assert ok.any() and (P[ok] > 0).all()
+        ln_e = np.linalg.norm(Vd[E[:, 1]] - Vd[E[:, 0]], axis=1)
+        useful.append((P[ok].sum(), ln_e[ok].sum() / ln_e.sum()))
+        for i in range(50):                              # the sampler draws from these probabilities
+            e, pe = sc.edge_tree_sample(x, n, i, seed=8, silhouettes=silhouettes)
+            assert e == -1 or abs(pe - P[e]) <= 1e-6 * P[e] + 1e-12
+    if silhouettes:                                      # more useful draws than the length CDF makes
+        h, c = np.array(useful).T
+        assert h.mean() > 2.0 * c.mean(), useful
