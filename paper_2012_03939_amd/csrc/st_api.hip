@@ -269,7 +269,7 @@ int make_queues(st_scene* sc, int cap, int nent, float* L, Queues& q) {
     // shadow entries are numbered l * n + i in a 32-bit index
     cap = (int)std::min<long long>(cap, (0x7FFFFFFFll / std::max(nent, 1)) & ~1ll);
     const size_t per = 256;
-    const size_t words = 2 * QNCOL + 2 + 3 + 4 + 7 * (size_t)std::max(nent, 1);
+    const size_t words = 2 * QNCOL + 2 + 3 + 4 + 8 * (size_t)std::max(nent, 1);
     const size_t bytes = (size_t)cap * 4 * words + (size_t)cap * std::max(nent, 1) + (words + 10) * per + 64 * 4 +
                          FETCH_INTS * sizeof(int);
     int rc = sc->qbuf.ensure(bytes);
@@ -286,6 +286,7 @@ int make_queues(st_scene* sc, int cap, int nent, float* L, Queues& q) {
     q.snext = c.take<int>(cap);
     for (int i = 0; i < 7; ++i) q.sh[i] = c.take<float>((size_t)cap * std::max(nent, 1));
     q.socc = c.take<uint8_t>((size_t)cap * std::max(nent, 1));
+    q.slist = c.take<uint32_t>((size_t)cap * std::max(nent, 1));
     q.cnt = c.take<int>(64);
     q.fetch = c.take<int>(FETCH_INTS);
     q.spill = (uint32_t*)sc->spillbuf.p;

@@ -962,6 +962,45 @@ __device__ __forceinline__ int block_reserve(bool emit, int* counter, int* lds) 
     return emit ? o : -1;
 }
 
+// Two reservations in one pass: one slot per thread with emit from *ca, and m
+// (0 <= m < 32) consecutive slots per thread from *cb.  Returns (slot or -1,
+// first of the m slots).  lds holds 2 (BS / 64 + 1) ints.
+template <int BS>
+__device__ __forceinline__ int2 block_reserve2(bool emit, int m, int* ca, int* cb, int* lds) {
+    constexpr int NW = BS / 64;
+    const uint64_t lt = lanemask_lt64();
+    const uint64_t mask = __ballot(emit);
+    int pre = 0, tot = 0;
+    for (int b = 0; b < 5; ++b) {
+        const uint64_t bm = __ballot((m >> b) & 1);
+        pre += __popcll(bm & lt) << b;
+        tot += __popcll(bm) << b;
+    }
+    const int w = (int)(threadIdx.x >> 6);
+    if (__lane_id() == 0) {
+        lds[w] = __popcll(mask);
+        lds[NW + 1 + w] = tot;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int a = 0, c = 0;
+        for (int j = 0; j < NW; ++j) {
+            const int x = lds[j], y = lds[NW + 1 + j];
+            lds[j] = a;
+            lds[NW + 1 + j] = c;
+            a += x;
+            c += y;
+        }
+        lds[NW] = a > 0 ? atomicAdd(ca, a) : 0;
+        lds[2 * NW + 1] = c > 0 ? atomicAdd(cb, c) : 0;
+    }
+    __syncthreads();
+    const int oa = lds[NW] + lds[w] + __popcll(mask & lt);
+    const int ob = lds[2 * NW + 1] + lds[NW + 1 + w] + pre;
+    __syncthreads();
+    return make_int2(emit ? oa : -1, ob);
+}
+
 // ---------------------------------------------------------------------------
 // persistent traversal of a ray queue with dynamic fetch: a wave refills its
 // idle lanes whenever at least FETCH_MIN of them are idle, so a lane whose ray

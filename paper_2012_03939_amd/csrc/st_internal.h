@@ -125,7 +125,8 @@ struct Queues {
     int* snext;              // shade record: index of the continuation in the next queue, -1 if none
     float* sh[7];            // shadow entries [entry][i]: dir xyz, tmax, contrib rgb
     uint8_t* socc;           // shadow entry outcome [entry][i]: 0 no ray, 1 occluded, 2 unoccluded
-    int* cnt;                // ray counts per bounce
+    uint32_t* slist;         // shadow entries (l * cap + i) that carry a ray, compacted per bounce
+    int* cnt;                // ray counts per bounce (k), shadow-ray counts per bounce (32 + k)
     int* fetch;              // fetch counters: slot k (shadow rays of bounce k), 16 + k (extension rays)
     uint32_t* spill;         // traversal stack spill
     float* L;                // per path sample radiance [total, 3] (processing order)

@@ -116,7 +116,7 @@ __global__ void __launch_bounds__(TRACE_BLOCK) EXTEND_OCC k_extend(FwdParams p, 
 
 // shading of bounce k: escapes, next-event set-up and BRDF continuation
 __global__ void __launch_bounds__(SHADE_BLOCK) SHADE_OCC k_shade(FwdParams p, Queues q, int k) {
-    __shared__ int resv[SHADE_BLOCK / 64 + 1];
+    __shared__ int resv[2 * (SHADE_BLOCK / 64 + 1)];
     const int n = q.cnt[k];
     float* const* r = q.ray[k & 1];
     float* const* rn = q.ray[(k + 1) & 1];
@@ -128,6 +128,7 @@ __global__ void __launch_bounds__(SHADE_BLOCK) SHADE_OCC k_shade(FwdParams p, Qu
         const int i = b0 + (int)threadIdx.x;
         const bool active = i < n;
         bool emit = false;
+        uint32_t rays = 0;          // shadow entries of this shading point that carry a ray
         V3 x{0.f, 0.f, 0.f}, wi{0.f, 0.f, 0.f}, beta{0.f, 0.f, 0.f};
         float pb = 0.0f;
         int f = -1;
@@ -184,6 +185,8 @@ __global__ void __launch_bounds__(SHADE_BLOCK) SHADE_OCC k_shade(FwdParams p, Qu
                     const size_t e = (size_t)l * q.cap + i;
                     q.sh[0][e] = wl.x; q.sh[1][e] = wl.y; q.sh[2][e] = wl.z; q.sh[3][e] = tmax;
                     q.sh[4][e] = ct.x; q.sh[5][e] = ct.y; q.sh[6][e] = ct.z;
+                    if (tmax >= 0.0f) rays |= 1u << l;
+                    else q.socc[e] = 0;
                 }
                 int tex = 0;
                 if (S.has_env) {
@@ -201,6 +204,8 @@ __global__ void __launch_bounds__(SHADE_BLOCK) SHADE_OCC k_shade(FwdParams p, Qu
                     const size_t e = (size_t)S.nl * q.cap + i;
                     q.sh[0][e] = we.x; q.sh[1][e] = we.y; q.sh[2][e] = we.z; q.sh[3][e] = tmax;
                     q.sh[4][e] = ct.x; q.sh[5][e] = ct.y; q.sh[6][e] = ct.z;
+                    if (tmax >= 0.0f) rays |= 1u << S.nl;
+                    else q.socc[e] = 0;
                 }
                 uint32_t info = 0;
                 if (k < p.B || S.has_env) {
@@ -223,8 +228,13 @@ __global__ void __launch_bounds__(SHADE_BLOCK) SHADE_OCC k_shade(FwdParams p, Qu
             }
             hv = h.h;
         }
-        // compaction of the continuing paths into the next queue
-        const int o = block_reserve<SHADE_BLOCK, 1>(emit, &q.cnt[k + 1], resv);
+        // compaction of the continuing paths into the next queue, and of the
+        // shadow entries that carry a ray (those of one shading point
+        // consecutive) into the shadow list of this bounce
+        const int2 oo = block_reserve2<SHADE_BLOCK>(emit, __popc(rays), &q.cnt[k + 1], &q.cnt[32 + k], resv);
+        const int o = oo.x;
+        for (int so = oo.y; rays; rays &= rays - 1, ++so)
+            q.slist[so] = (uint32_t)(__ffs(rays) - 1) * (uint32_t)q.cap + (uint32_t)i;
         {
             if (emit) {
                 rn[QOX][o] = x.x; rn[QOY][o] = x.y; rn[QOZ][o] = x.z;
@@ -244,25 +254,22 @@ __global__ void __launch_bounds__(SHADE_BLOCK) SHADE_OCC k_shade(FwdParams p, Qu
     }
 }
 
-// shadow rays of bounce k: entry l of shading point i is item l * n + i; one
-// outcome code per entry (0 no ray, 1 occluded, 2 unoccluded)
+// shadow rays of bounce k: the entries listed by k_shade (entry l of shading
+// point i is l * cap + i), one outcome code each (1 occluded, 2 unoccluded);
+// k_shade wrote 0 (no ray) for the others
 __global__ void __launch_bounds__(TRACE_BLOCK) SHADOW_OCC k_shadow(FwdParams p, Queues q, int k) {
     __shared__ uint32_t lds[LDS_STACK * TRACE_BLOCK];
     TravStack st = make_trav_stack(lds, q.spill, p.err, p.work ? p.work + 3 * WORK_SHADOW : nullptr);
-    const int n = q.cnt[k];
+    const int items = q.cnt[32 + k];
     float* const* r = q.ray[k & 1];
-    const long long items = (long long)n * q.nent;
-    // 64 consecutive entries per wave (one light, consecutive shading points), in lockstep
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long w = blockIdx.x * (long long)blockDim.x + threadIdx.x; w < items; w += stride) {
-        const int l = (int)(w / n), i = (int)(w - (long long)l * n);
-        const size_t e = (size_t)l * q.cap + i;
+    // 64 consecutive listed rays per wave, traced in lockstep
+    const int stride = gridDim.x * blockDim.x;
+    for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < items; w += stride) {
+        const uint32_t e = q.slist[w];
+        const int i = (int)(e % (uint32_t)q.cap);
         const int f = q.sface[i];
-        if (f < 0) continue;
         const DevScene& S = p.scenes[p.cams[qu(r, QVD, i) & 0xFFFFu].scene];
-        if (l >= S.nl + (S.has_env ? 1 : 0)) continue;      // entry unused in this scene
         const float tmax = q.sh[3][e];
-        if (!(tmax >= 0.0f)) { q.socc[e] = 0; continue; }
         const V3 o{q.sx[0][i], q.sx[1][i], q.sx[2][i]}, dd{q.sh[0][e], q.sh[1][e], q.sh[2][e]};
         q.socc[e] = trace_any(S, o, dd, TMIN, tmax, f, st) ? 1 : 2;
     }
