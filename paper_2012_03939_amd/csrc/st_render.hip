@@ -254,6 +254,9 @@ __global__ void __launch_bounds__(SHADE_BLOCK) SHADE_OCC k_shade(FwdParams p, Qu
     }
 }
 
+#ifndef ST_SHADOW_QUEUE
+#define ST_SHADOW_QUEUE 0
+#endif
 // shadow rays of bounce k: the entries listed by k_shade (entry l of shading
 // point i is l * cap + i), one outcome code each (1 occluded, 2 unoccluded);
 // k_shade wrote 0 (no ray) for the others
@@ -262,6 +265,24 @@ __global__ void __launch_bounds__(TRACE_BLOCK) SHADOW_OCC k_shadow(FwdParams p, 
     TravStack st = make_trav_stack(lds, q.spill, p.err, p.work ? p.work + 3 * WORK_SHADOW : nullptr);
     const int items = q.cnt[32 + k];
     float* const* r = q.ray[k & 1];
+    if (ST_SHADOW_QUEUE) {
+        // persistent waves refilled from the fetch counters of slot k
+        trace_queue<true>(
+            q.fetch + FETCH_SLOT_INTS * k, items, st,
+            [&](int w, RayJob& J) {
+                const uint32_t e = q.slist[w];
+                const int i = (int)(e % (uint32_t)q.cap);
+                const DevScene& S = p.scenes[p.cams[qu(r, QVD, i) & 0xFFFFu].scene];
+                J.o = V3{q.sx[0][i], q.sx[1][i], q.sx[2][i]};
+                J.d = V3{q.sh[0][e], q.sh[1][e], q.sh[2][e]};
+                J.tmax = q.sh[3][e];
+                J.excl = q.sface[i];
+                J.G = trace_geo(S);
+                return true;
+            },
+            [&](int w, int occ, float) { q.socc[q.slist[w]] = occ ? 1 : 2; });
+        return;
+    }
     // 64 consecutive listed rays per wave, traced in lockstep
     const int stride = gridDim.x * blockDim.x;
     for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < items; w += stride) {
