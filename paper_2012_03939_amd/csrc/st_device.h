@@ -35,6 +35,7 @@ constexpr float BOX_GROW = 1.0000004f;  // 1 + 2*gamma(3): conservative slab exi
 #endif
 constexpr int LDS_STACK = ST_LDS_STACK; // per-lane traversal stack entries held in LDS
 constexpr int SPILL_STACK = 64 - LDS_STACK;  // further entries spilled to HBM (64 in all)
+constexpr int TRAV_BLOCK = 256;              // threads of every block that traverses (LDS stack stride)
 constexpr uint32_t LEAF_BIT = 0x80000000u;
 constexpr int MAX_LIGHTS = 16;
 // slots of the traversal work counters (node visits, triangle tests, rays each)
@@ -156,28 +157,44 @@ typedef __attribute__((address_space(1))) uint32_t gu32;
 typedef __attribute__((address_space(3))) uint32_t lu32;
 
 struct TravStack {
-    lu32* lds;         // base of this block's LDS stack area; entry i of lane t at lds[i*bs + t]
+    lu32* lds;         // this lane's LDS stack column: entry i at lds[i * TRAV_BLOCK]
     gu32* spill;       // spill base; entry i of thread g at spill[i*gstride + g]
-    uint32_t bs, tid, gstride, gid;
+    uint32_t gstride, gid;
     uint32_t* err;
     unsigned long long* work;   // optional: node visits, triangle tests, rays
     __device__ __forceinline__ void put(int i, uint32_t v) {
-        if (i < LDS_STACK) lds[i * bs + tid] = v;
+        if (i < LDS_STACK) lds[i * TRAV_BLOCK] = v;
         else spill[(i - LDS_STACK) * gstride + gid] = v;
     }
     __device__ __forceinline__ uint32_t get(int i) const {
-        if (i < LDS_STACK) return lds[i * bs + tid];
+        if (i < LDS_STACK) return lds[i * TRAV_BLOCK];
         return spill[(i - LDS_STACK) * gstride + gid];
+    }
+    // pushes m (0..3) entries: a, then b, then c; entries beyond the m-th are
+    // written too when they stay in LDS (above the new top, so never read)
+    __device__ __forceinline__ bool push3(int& sp, int m, uint32_t a, uint32_t b, uint32_t c) {
+        if (sp + 3 <= LDS_STACK) {
+            lds[sp * TRAV_BLOCK] = a;
+            lds[(sp + 1) * TRAV_BLOCK] = b;
+            lds[(sp + 2) * TRAV_BLOCK] = c;
+            sp += m;
+            return true;
+        }
+        if (sp + m > LDS_STACK + SPILL_STACK) return false;
+        if (m > 0) put(sp++, a);
+        if (m > 1) put(sp++, b);
+        if (m > 2) put(sp++, c);
+        return true;
     }
 };
 
 __device__ __forceinline__ TravStack make_trav_stack(uint32_t* lds, uint32_t* spill, uint32_t* err,
                                                      unsigned long long* work) {
     TravStack s;
-    s.lds = (lu32*)lds;
+    // the stack layout assumes TRAV_BLOCK threads per block
+    if (blockDim.x != TRAV_BLOCK && threadIdx.x == 0) atomicOr(err, ERR_STACK);
+    s.lds = (lu32*)lds + threadIdx.x;
     s.spill = (gu32*)spill;
-    s.bs = blockDim.x;
-    s.tid = threadIdx.x;
     s.gstride = gridDim.x * blockDim.x;
     s.gid = blockIdx.x * blockDim.x + threadIdx.x;
     s.err = err;
@@ -329,15 +346,12 @@ __device__ int trace_closest(const DevScene& S, V3 o, V3 d, float tmin, int excl
         cswap(t[0], c[0], t[2], c[2]); cswap(t[1], c[1], t[3], c[3]);
         cswap(t[1], c[1], t[2], c[2]);
         if (t[0] < INF) {
-            bool overflow = false;
-#pragma unroll
-            for (int s = 3; s >= 1; --s) {
-                if (t[s] < INF) {
-                    if (sp >= LDS_STACK + SPILL_STACK) overflow = true;
-                    else st.put(sp++, c[s]);
-                }
-            }
-            if (overflow) { atomicOr(st.err, ERR_STACK); break; }
+            // the hit slots come first: push slots m-1 .. 1 (farthest first)
+            const bool h1 = t[1] < INF, h2 = t[2] < INF, h3 = t[3] < INF;
+            const int m = (int)h1 + (int)h2 + (int)h3;
+            const uint32_t a = h3 ? c[3] : (h2 ? c[2] : c[1]);
+            const uint32_t b = h3 ? c[2] : c[1];
+            if (!st.push3(sp, m, a, b, c[1])) { atomicOr(st.err, ERR_STACK); break; }
             node = c[0];
         } else {
             if (sp == 0) break;
@@ -376,18 +390,23 @@ __device__ bool trace_any_impl(const DevScene& S, V3 o, V3 d, float tmin, float 
         LeafList lv = take_leaves(t, c);
         while (lv.n > 0)
             if (leaf(lv.pop())) return true;
+        // the first hit slot is visited next, the others are pushed in slot order
         bool have = false;
-        uint32_t next = 0;
+        uint32_t next = 0, q0 = 0, q1 = 0, q2 = 0;
+        int m = 0;
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             if (t[s] < INF) {
                 if (!have) { next = c[s]; have = true; }
                 else {
-                    if (sp >= LDS_STACK + SPILL_STACK) { atomicOr(st.err, ERR_STACK); return false; }
-                    st.put(sp++, c[s]);
+                    q0 = m == 0 ? c[s] : q0;
+                    q1 = m == 1 ? c[s] : q1;
+                    q2 = m == 2 ? c[s] : q2;
+                    ++m;
                 }
             }
         }
+        if (!st.push3(sp, m, q0, q1, q2)) { atomicOr(st.err, ERR_STACK); return false; }
         if (have) {
             node = next;
         } else {

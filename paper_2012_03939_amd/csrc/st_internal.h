@@ -227,6 +227,7 @@ void launch_trace_debug(const DevScene* s, const float* o, const float* d, int n
                         int* out_face, float* out_t, uint32_t* spill, uint32_t* err, hipStream_t st);
 
 constexpr int TRACE_BLOCK = 256;
+static_assert(TRACE_BLOCK == TRAV_BLOCK, "traversal blocks size the LDS stack");
 // largest grid of the traversal kernels; the spill stack has one column per thread of it
 constexpr unsigned TRACE_GRID = 4096;
 
