@@ -20,7 +20,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic work per unit, stated once here and in the design doc:
+# Algorithmic work per unit:
 #  - a visit of a 4-wide BVH node tests four child boxes: 4 x (6 sub + 6 mul + 12 min/max) = 96 FP32 ops
 #  - a Moller-Trumbore triangle test: 2 cross (18) + 4 dot (20) + 1 rcp + 3 sub + 3 mul = 45 FP32 ops
 FLOPS_PER_VISIT = 96
@@ -166,7 +166,8 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this path tracer runs on one GPU; multi-GPU runs are not supported "
-                                   "(see DESIGN.md for how the path would shard)"}))
+                                   "(path samples would split by view, with one all-reduce of the "
+                                   "gradients per step)"}))
         sys.exit(2)
     if args.copy_reference:
         from paper_2012_03939_amd.profiling import copy_reference

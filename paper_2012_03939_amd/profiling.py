@@ -162,7 +162,7 @@ def main(argv=None):
         body = [f"# {a.title}", ""]
         if a.notes:
             body += [a.notes, ""]
-        body += ["Command (from the repository root on the GPU box):", "", "```", a.command, "```", "",
+        body += ["Command (run from the repository root):", "", "```", a.command, "```", "",
                  trace_table(a.stats), ""]
         with open(a.out, "w") as fh:
             fh.write("\n".join(body))
