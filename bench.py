@@ -29,10 +29,16 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
-    (FETCH_SIZE and WRITE_SIZE scaled by their plain-copy factors), or None when
-    the kernel sources changed after the counters were taken."""
+CU_COUNT, SIMDS_PER_CU, CLOCK_HZ = 256, 4, 2.4e9
+VALU_CYCLES_PER_WAVE_INST = 4      # a 64-lane VALU instruction occupies a 16-lane SIMD for 4 cycles
+
+
+def measured_counters(kernel: str):
+    """From the committed rocprofv3 counter summary of `kernel`: HBM bytes per
+    launch (FETCH_SIZE and WRITE_SIZE scaled by their plain-copy factors), the
+    share of SIMD cycles spent issuing VALU instructions, and the share of lanes
+    active in them; None when the kernel sources changed after the counters were
+    taken."""
     from paper_2012_03939_amd.profiling import kernel_source_hash
     path = os.path.join(ROOT, "profiles", "pmc_traversal_kernels_torus40k_16x512sq_16spp.json")
     try:
@@ -43,7 +49,14 @@ def measured_traffic(kernel: str):
     if pm.get("source_hash") != kernel_source_hash():
         return None
     k = pm["kernels"].get(kernel) or pm["kernels"].get(kernel.split("<")[0])
-    return None if k is None else k["hbm_bytes_per_dispatch"]
+    if k is None:
+        return None
+    issue = None
+    if k.get("sq_insts_valu_per_dispatch") and k.get("mean_dispatch_ms_under_counters"):
+        simd_cycles = k["mean_dispatch_ms_under_counters"] * 1e-3 * CLOCK_HZ * CU_COUNT * SIMDS_PER_CU
+        issue = k["sq_insts_valu_per_dispatch"] * VALU_CYCLES_PER_WAVE_INST / simd_cycles
+    return {"traffic": k["hbm_bytes_per_dispatch"], "valu_issue_utilisation": issue,
+            "valu_lane_utilisation": k.get("valu_lane_utilisation")}
 
 
 def parse():
@@ -256,6 +269,7 @@ def main():
         if kr:
             traversal[k] = {"rays_per_step": kr, "node_visits_per_ray": kv / kr, "tri_tests_per_ray": kt / kr,
                             "ms_per_step": kms, "rays_per_s": kr / (kms / 1e3) if kms else None}
+    mc = measured_counters(dom_name)
     out = {
         "metric": "fwd+adjoint path samples/sec at 16 views 512^2 16spp; sec per optimisation step",
         "value": value,
@@ -276,9 +290,11 @@ def main():
                    "envmap": "512x256", "env_sampler": args.env_sampler, "bsdf_sampler": args.bsdf_sampler,
                    "edge_sampler": args.edge_sampler},
         "roofline": {"bound": "alu", "kernel": dom_name, "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": measured_traffic(dom_name),
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": (mc or {}).get("traffic"),
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-scaled)",
-                     "avg_launch_ms": avg_ms, "node_visits_per_launch": visits / max(launches_per_step, 1),
+                     "avg_launch_ms": avg_ms,
+                     "valu_issue_utilisation": (mc or {}).get("valu_issue_utilisation"),
+                     "valu_lane_utilisation": (mc or {}).get("valu_lane_utilisation"), "node_visits_per_launch": visits / max(launches_per_step, 1),
                      "tri_tests_per_launch": tests / max(launches_per_step, 1),
                      "rays_per_launch": rays / max(launches_per_step, 1),
                      "rays_per_s": rays / max(launches_per_step, 1) / (avg_ms / 1e3)},
