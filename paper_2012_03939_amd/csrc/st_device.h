@@ -1001,17 +1001,18 @@ __device__ __forceinline__ int2 block_reserve2(bool emit, int m, int* ca, int* c
         lds[NW + 1 + w] = tot;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int a = 0, c = 0;
+    if (threadIdx.x < 2) {
+        // lane 0 scans and reserves for ca, lane 1 for cb: one atomic
+        // instruction, so the two round trips overlap
+        const int base = threadIdx.x == 0 ? 0 : NW + 1;
+        int acc = 0;
         for (int j = 0; j < NW; ++j) {
-            const int x = lds[j], y = lds[NW + 1 + j];
-            lds[j] = a;
-            lds[NW + 1 + j] = c;
-            a += x;
-            c += y;
+            const int x = lds[base + j];
+            lds[base + j] = acc;
+            acc += x;
         }
-        lds[NW] = a > 0 ? atomicAdd(ca, a) : 0;
-        lds[2 * NW + 1] = c > 0 ? atomicAdd(cb, c) : 0;
+        int* const ctr = threadIdx.x == 0 ? ca : cb;
+        lds[base + NW] = acc > 0 ? atomicAdd(ctr, acc) : 0;
     }
     __syncthreads();
     const int oa = lds[NW] + lds[w] + __popcll(mask & lt);
