@@ -316,7 +316,7 @@ __device__ int trace_closest(const DevScene& S, V3 o, V3 d, float tmin, int excl
     int best = -1;
     const TraceGeo G = trace_geo(S);
     if (G.nf <= 0) return -1;
-    uint32_t visits = 0, tests = 0;
+    uint32_t tests = 0;
     auto leaf = [&](uint32_t l) {
         ++tests;
         float t; int f;
@@ -328,9 +328,9 @@ __device__ int trace_closest(const DevScene& S, V3 o, V3 d, float tmin, int excl
     const V3 inv = safe_inv(d);
     uint32_t node = 0;
     int sp = 0;
-    for (int iter = 0;; ++iter) {
+    int iter = 0;
+    for (;; ++iter) {
         if (iter >= TRAVERSAL_CAP) { atomicOr(st.err, ERR_LOOP); break; }
-        ++visits;
         float t[4];
         uint32_t c[4];
         node4_test(G.nodes4, node, o, inv, tmin, tbest, t, c);
@@ -359,6 +359,8 @@ __device__ int trace_closest(const DevScene& S, V3 o, V3 d, float tmin, int excl
         }
     }
     if (st.work) {
+        // node visits: one per iteration (the cap exit visits none)
+        const uint32_t visits = (uint32_t)min(iter + 1, TRAVERSAL_CAP);
         atomicAdd(st.work, (unsigned long long)visits);
         atomicAdd(st.work + 1, (unsigned long long)tests);
         atomicAdd(st.work + 2, 1ull);
