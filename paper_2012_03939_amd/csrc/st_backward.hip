@@ -141,7 +141,10 @@ k_adjoint(BwdParams p, long long total) {
     const bool defer = !JOBS && p.sec_mask != nullptr;
     const long long stride = (long long)gridDim.x * blockDim.x;
     const long long count = JOBS ? (long long)*p.sec_njobs : total;
-    for (long long it = blockIdx.x * (long long)blockDim.x + threadIdx.x; it < count; it += stride) {
+    // the main pass gives each XCD consecutive paths (their hits share that XCD's
+    // L2: 18.1 -> 15.8 ms); the job pass keeps the hardware order
+    const long long b0 = JOBS ? (long long)blockIdx.x : (long long)grid_block();
+    for (long long it = b0 * blockDim.x + threadIdx.x; it < count; it += stride) {
         int ksel = -1;
         long long qq = it;
         if (JOBS) {

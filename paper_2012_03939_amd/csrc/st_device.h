@@ -1023,6 +1023,25 @@ __device__ __forceinline__ int2 block_reserve2(bool emit, int m, int* ca, int* c
     return make_int2(emit ? oa : -1, ob);
 }
 
+// Block index remapped so that each XCD works on one contiguous range of the
+// grid: the hardware hands block b to XCD b % 8, so XCD x receives blocks
+// x, x + 8, ...; they become x's consecutive share [x G/8, (x+1) G/8) (the
+// first G % 8 XCDs one block more), and neighbouring work shares one L2.
+constexpr unsigned NUM_XCD = 8;
+__device__ __forceinline__ unsigned xcd_block() {
+    const unsigned G = gridDim.x, b = blockIdx.x;
+    const unsigned per = G / NUM_XCD, rem = G % NUM_XCD, x = b % NUM_XCD, j = b / NUM_XCD;
+    return x < rem ? x * (per + 1) + j : rem * (per + 1) + (x - rem) * per + j;
+}
+#ifndef ST_XCD_MAP
+#define ST_XCD_MAP 1
+#endif
+// the block index the adjoint's grid-stride loop starts from (the traversal
+// kernels keep the hardware order: contiguous shares per XCD made them slower,
+// 69.8 -> 84.3 ms for k_extend, presumably because cheap and costly stretches
+// of the queue then land on different XCDs)
+__device__ __forceinline__ unsigned grid_block() { return ST_XCD_MAP ? xcd_block() : blockIdx.x; }
+
 // ---------------------------------------------------------------------------
 // persistent traversal of a ray queue with dynamic fetch: a wave refills its
 // idle lanes whenever at least FETCH_MIN of them are idle, so a lane whose ray
