@@ -114,6 +114,16 @@ __global__ void __launch_bounds__(TRACE_BLOCK) EXTEND_OCC k_extend(FwdParams p, 
     }
 }
 
+#ifndef ST_SHADOW_QUEUE
+#define ST_SHADOW_QUEUE 0
+#endif
+// With one shadow entry per shading point and no decision hashes, k_shadow adds
+// each unoccluded contribution itself and records occlusion in the hit records,
+// and k_shadow_sum is not launched (the sum over one entry is that entry).
+__host__ __device__ __forceinline__ bool shadow_fused(const FwdParams& p, const Queues& q) {
+    return !ST_SHADOW_QUEUE && q.nent == 1 && !(p.dbg_hash || p.hash_by_q);
+}
+
 // shading of bounce k: escapes, next-event set-up and BRDF continuation
 __global__ void __launch_bounds__(SHADE_BLOCK) SHADE_OCC k_shade(FwdParams p, Queues q, int k) {
     __shared__ int resv[2 * (SHADE_BLOCK / 64 + 1)];
@@ -222,6 +232,8 @@ __global__ void __launch_bounds__(SHADE_BLOCK) SHADE_OCC k_shade(FwdParams p, Qu
                 }
                 q.sface[i] = f;
                 q.sinfo[i] = info;
+                if (shadow_fused(p, q) && p.rec_occ && (vd >> 16) == 0u)
+                    p.rec_occ[(size_t)(k - 1) * p.rec_n + qu(r, QQ, i)] = 0u;
                 q.stex[i] = tex;
                 q.sx[0][i] = x.x; q.sx[1][i] = x.y; q.sx[2][i] = x.z;
                 q.snext[i] = -1;
@@ -254,9 +266,6 @@ __global__ void __launch_bounds__(SHADE_BLOCK) SHADE_OCC k_shade(FwdParams p, Qu
     }
 }
 
-#ifndef ST_SHADOW_QUEUE
-#define ST_SHADOW_QUEUE 0
-#endif
 // shadow rays of bounce k: the entries listed by k_shade (entry l of shading
 // point i is l * cap + i), one outcome code each (1 occluded, 2 unoccluded);
 // k_shade wrote 0 (no ray) for the others
@@ -283,6 +292,7 @@ __global__ void __launch_bounds__(TRACE_BLOCK) SHADOW_OCC k_shadow(FwdParams p, 
             [&](int w, int occ, float) { q.socc[q.slist[w]] = occ ? 1 : 2; });
         return;
     }
+    const bool fused = shadow_fused(p, q);
     // 64 consecutive listed rays per wave, traced in lockstep
     const int stride = gridDim.x * blockDim.x;
     for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < items; w += stride) {
@@ -292,7 +302,17 @@ __global__ void __launch_bounds__(TRACE_BLOCK) SHADOW_OCC k_shadow(FwdParams p, 
         const DevScene& S = p.scenes[p.cams[qu(r, QVD, i) & 0xFFFFu].scene];
         const float tmax = q.sh[3][e];
         const V3 o{q.sx[0][i], q.sx[1][i], q.sx[2][i]}, dd{q.sh[0][e], q.sh[1][e], q.sh[2][e]};
-        q.socc[e] = trace_any(S, o, dd, TMIN, tmax, f, st) ? 1 : 2;
+        const bool occluded = trace_any(S, o, dd, TMIN, tmax, f, st);
+        if (fused) {
+            if (occluded) {
+                if (p.rec_occ && (qu(r, QVD, i) >> 16) == 0u) p.rec_occ[(size_t)(k - 1) * p.rec_n + qu(r, QQ, i)] = 1u;
+            } else {
+                float* L = q.L + 3 * (size_t)qu(r, QQ, i);
+                L[0] += q.sh[4][e]; L[1] += q.sh[5][e]; L[2] += q.sh[6][e];
+            }
+        } else {
+            q.socc[e] = occluded ? 1 : 2;
+        }
     }
 }
 
@@ -457,7 +477,8 @@ void launch_wavefront_bounces(const FwdParams& p, Queues& q, int n, int has_env_
         ST_LAUNCH("k_shade", k_shade, dim3(grid_for(n, SHADE_BLOCK, gmax)), dim3(SHADE_BLOCK), 0, st, p, q, k);
         if (k <= p.B) {
             ST_LAUNCH("k_shadow", k_shadow, dim3(g), dim3(TRACE_BLOCK), 0, st, p, q, k);
-            ST_LAUNCH("k_shadow_sum", k_shadow_sum, dim3(grid_for(n, 256, gmax)), dim3(256), 0, st, p, q, k);
+            if (!shadow_fused(p, q))
+                ST_LAUNCH("k_shadow_sum", k_shadow_sum, dim3(grid_for(n, 256, gmax)), dim3(256), 0, st, p, q, k);
         }
     }
 }

@@ -31,11 +31,12 @@ def B():
     return binding
 
 
-def _scene(seed=3):
+def _scene(seed=3, nl=2, env=True):
     rng = np.random.default_rng(seed)
     V, F = S.noise_torus(40, 20, 0.1, noise_seed=13)
-    return S.Scene(V.astype(np.float32), F, S.random_materials(F.shape[0], rng), S.hemisphere_lights(2, rng),
-                   S.gaussian_lobe_envmap(rng, 64, 32))
+    lights = S.hemisphere_lights(nl, rng) if nl else np.zeros((0, 6), np.float32)
+    return S.Scene(V.astype(np.float32), F, S.random_materials(F.shape[0], rng), lights,
+                   S.gaussian_lobe_envmap(rng, 64, 32) if env else None)
 
 
 def _grads(B, g, cams, spp, bounces, d, seed, flags, hashes=False):
@@ -46,9 +47,12 @@ def _grads(B, g, cams, spp, bounces, d, seed, flags, hashes=False):
     return dV.cpu().numpy(), dM.cpu().numpy(), (ph.cpu().numpy().view(np.uint32) if hashes else None)
 
 
-def test_records_match_retrace_and_oracle(B):
-    _say("case hit records: torus 1600 faces, 2 lights + env, B=3, render then backward")
-    sc = _scene()
+@pytest.mark.parametrize("nl,env", [(2, True), (0, True), (1, False)])
+def test_records_match_retrace_and_oracle(B, nl, env):
+    """With one shadow entry per shading point (environment only, or one light)
+    the forward records occlusion from the shadow kernel itself."""
+    _say(f"case hit records: torus 1600 faces, {nl} lights, env {env}, B=3, render then backward")
+    sc = _scene(3, nl, env)
     g = B.GPUScene.from_scene(sc)
     o = O.OracleScene.from_scene(sc)
     cams = [S.look_at_origin((0.4, 1.2, 3.0), 32, 28), S.look_at_origin((-2.0, 1.0, 2.2), 24, 24)]
