@@ -564,8 +564,9 @@ __global__ void k_pack4(const int* __restrict__ child, const float* __restrict__
             v[0][s] = bb[0]; v[1][s] = bb[3]; v[2][s] = bb[1]; v[3][s] = bb[4]; v[4][s] = bb[2]; v[5][s] = bb[5];
             cc[s] = codes[s];
         } else {
-            v[0][s] = v[2][s] = v[4][s] = __int_as_float(0x7f800000);
-            v[1][s] = v[3][s] = v[5][s] = -__int_as_float(0x7f800000);
+            // an empty slot is a box at +infinity on every axis: its slab test
+            // gives an entry distance of +inf or an empty interval, a miss either way
+            v[0][s] = v[1][s] = v[2][s] = v[3][s] = v[4][s] = v[5][s] = __int_as_float(0x7f800000);
             cc[s] = -1;
         }
     }

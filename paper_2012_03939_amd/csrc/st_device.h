@@ -265,7 +265,7 @@ __device__ __forceinline__ void node4_test(const gfloat4* nodes4, uint32_t node,
         const float az = (lz[s] - o.z) * inv.z, bz = (hz[s] - o.z) * inv.z;
         const float t0 = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), tmin));
         const float t1 = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), tmax)) * BOX_GROW;
-        t[s] = (t0 <= t1 && c[s] != 0xFFFFFFFFu) ? t0 : __int_as_float(0x7f800000);
+        t[s] = t0 <= t1 ? t0 : __int_as_float(0x7f800000);
     }
 }
 
