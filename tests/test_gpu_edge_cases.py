@@ -1,0 +1,123 @@
+"""Degenerate and extreme inputs against the FP64 oracle, through the C ABI: a
+single-triangle mesh (the traversal's one-leaf path and three boundary edges),
+a mesh with zero-area faces, cameras that see nothing, the largest bounce count
+(8), and a 1x1 image at 1 spp.  Same bars as the main parity tests."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as O
+from paper_2012_03939_amd import scenes as S
+from parity_util import FLIP_MAX, GRAD_RTOL
+from test_gpu_parity import _backward_case, _forward_case
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2012_03939_amd import binding
+    binding.load()
+    return binding
+
+
+def _triangle_scene():
+    rng = np.random.default_rng(21)
+    V = np.array([[-1.0, -0.8, 0.0], [1.2, -0.6, 0.1], [0.1, 1.0, -0.2]], np.float32)
+    F = np.array([[0, 1, 2]], np.int32)
+    return S.Scene(V, F, S.random_materials(1, rng), S.hemisphere_lights(1, rng), S.gaussian_lobe_envmap(rng, 32, 16))
+
+
+def test_single_triangle_forward_and_backward(B):
+    _say("case single triangle, one light + env, B=2: forward and all gradient terms")
+    sc = _triangle_scene()
+    cams = [S.look_at_origin((0.3, 0.2, 3.0), 40, 36), S.look_at_origin((-2.0, 0.5, 2.0), 24, 24)]
+    fr, bad, checked, worst, img, ref = _forward_case(B, sc, cams, 4, 2)
+    _say(f"  forward flips {fr:.5f} bad {bad}/{checked} worst {worst:.2e}")
+    assert fr < FLIP_MAX and bad == 0 and (ref > 0).any()
+    d_img = np.random.default_rng(3).normal(size=(B.num_pixels(cams), 3)).astype(np.float32)
+    pf, ef, rv, rm, oV, oM = _backward_case(B, sc, cams, 4, 2, d_img, 7)
+    _say(f"  backward path flips {pf:.5f} edge flips {ef:.5f} relL2 dV {rv:.2e} dmat {rm:.2e}")
+    assert pf < FLIP_MAX and ef < FLIP_MAX and np.abs(oV).max() > 0
+    assert rv < GRAD_RTOL and rm < GRAD_RTOL
+
+
+def test_zero_area_faces(B):
+    """Two faces of a sphere collapsed to zero area (a vertex moved onto its
+    neighbour): no hit on them, no NaN, parity in the forward and backward."""
+    _say("case sphere with collapsed faces, 2 lights, B=2: forward and all gradient terms")
+    rng = np.random.default_rng(22)
+    V, F = S.noise_sphere(5, 0.1, noise_seed=4)
+    V = V.astype(np.float32).copy()
+    a, b = int(F[7, 0]), int(F[7, 1])
+    V[b] = V[a]                                      # every face with both a and b has zero area
+    sc = S.Scene(V, F, S.random_materials(F.shape[0], rng), S.hemisphere_lights(2, rng), None)
+    cams = [S.look_at_origin(tuple(3.0 * V[a] / np.linalg.norm(V[a])), 32, 32)]
+    fr, bad, checked, worst, img, ref = _forward_case(B, sc, cams, 4, 2)
+    _say(f"  forward flips {fr:.5f} bad {bad}/{checked} worst {worst:.2e}")
+    assert np.isfinite(img.cpu().numpy()).all()
+    assert fr < FLIP_MAX and bad == 0
+    d_img = np.random.default_rng(4).normal(size=(B.num_pixels(cams), 3)).astype(np.float32)
+    pf, ef, rv, rm, oV, oM = _backward_case(B, sc, cams, 4, 2, d_img, 7)
+    _say(f"  backward path flips {pf:.5f} edge flips {ef:.5f} relL2 dV {rv:.2e} dmat {rm:.2e}")
+    assert np.isfinite(oV).all()
+    assert pf < FLIP_MAX and ef < FLIP_MAX and rv < GRAD_RTOL and rm < GRAD_RTOL
+
+
+def test_cameras_that_see_nothing(B):
+    """Every camera ray misses (the object is behind the camera): the masked image
+    is zero and so are all gradients, on both sides."""
+    _say("case cameras facing away from the object, env, B=3")
+    wl = S.small_sphere()
+    sc = S.Scene(wl.scenes[0].V, wl.scenes[0].F, wl.scenes[0].mat, wl.scenes[0].lights,
+                 S.gaussian_lobe_envmap(np.random.default_rng(5), 32, 16))
+    far = [S.Camera((0.0, 0.0, 3.0), (0.0, 0.0, 6.0), (0.0, 1.0, 0.0), 45.0, 16, 12)]
+    g = B.GPUScene.from_scene(sc)
+    img = g.render(far, 2, 3, seed=1)
+    torch.cuda.synchronize()
+    ref, _ = O.OracleScene.from_scene(sc).render(far, 2, 3, 1)
+    assert float(img.abs().max()) == 0.0 and np.abs(ref).max() == 0.0
+    d = torch.ones((B.num_pixels(far), 3), dtype=torch.float32, device="cuda")
+    dV, dM = g.backward(far, 2, 3, d, seed=1, flags=7)
+    torch.cuda.synchronize()
+    g.check_errors()
+    assert float(dV.abs().max()) == 0.0 and float(dM.abs().max()) == 0.0
+
+
+def test_largest_bounce_count(B):
+    _say("case torus env, 8 bounces (the largest allowed), forward and interior gradients")
+    rng = np.random.default_rng(23)
+    V, F = S.noise_torus(24, 12, 0.1, noise_seed=13)
+    sc = S.Scene(V.astype(np.float32), F, S.random_materials(F.shape[0], rng), S.hemisphere_lights(1, rng),
+                 S.gaussian_lobe_envmap(rng, 32, 16))
+    cams = [S.look_at_origin((0.5, 2.0, 2.5), 24, 20)]
+    fr, bad, checked, worst, img, ref = _forward_case(B, sc, cams, 4, 8)
+    _say(f"  forward flips {fr:.5f} bad {bad}/{checked} worst {worst:.2e}")
+    assert fr < FLIP_MAX and bad == 0
+    d_img = np.random.default_rng(6).normal(size=(B.num_pixels(cams), 3)).astype(np.float32)
+    pf, ef, rv, rm, oV, oM = _backward_case(B, sc, cams, 4, 8, d_img, 5)
+    _say(f"  backward path flips {pf:.5f} relL2 dV {rv:.2e} dmat {rm:.2e}")
+    assert pf < FLIP_MAX and rv < GRAD_RTOL and rm < GRAD_RTOL
+
+
+def test_one_pixel_one_sample(B):
+    _say("case 1x1 image, 1 spp, sphere, point lights, B=2, all terms")
+    wl = S.small_sphere()
+    sc = wl.scenes[0]
+    cams = [S.look_at_origin((0.0, 0.2, 3.0), 1, 1)]
+    fr, bad, checked, worst, img, ref = _forward_case(B, sc, cams, 1, 2)
+    assert fr == 0 and bad == 0
+    d_img = np.ones((1, 3), np.float32)
+    pf, ef, rv, rm, oV, oM = _backward_case(B, sc, cams, 1, 2, d_img, 7)
+    _say(f"  backward path flips {pf:.5f} edge flips {ef:.5f} relL2 dV {rv:.2e} dmat {rm:.2e}")
+    assert pf == 0 and (np.abs(oV).max() == 0 or rv < GRAD_RTOL)
