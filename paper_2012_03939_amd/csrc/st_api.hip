@@ -562,6 +562,7 @@ int st_scene_create(const float* V, int32_t nv, const int32_t* F, int32_t nf, co
     h.etbox = nullptr;
     h.etlen = nullptr;
     h.etnbox = nullptr;
+    h.etnode = nullptr;
     h.etedge = nullptr;
     h.scene_id = scene_id;
     HIPCHK2(hipMemcpyAsync(d.dscene, &h, sizeof(DevScene), hipMemcpyHostToDevice, s));
@@ -713,6 +714,7 @@ static int ensure_edge_tree(st_scene* sc, hipStream_t s) {
         A(dalloc(&d.eaabb, 6 * (2 * n - 1)));
         A(dalloc(&d.elen, 2 * n - 1));
         A(dalloc(&d.enbox, 6 * (2 * n - 1)));
+        A(dalloc(&d.enode, 8 * std::max<size_t>(n - 1, 1)));
         if (rc) return rc;
     }
     launch_edge_tree(d, s);
@@ -720,6 +722,7 @@ static int ensure_edge_tree(st_scene* sc, hipStream_t s) {
     d.hscene.etbox = d.eaabb;
     d.hscene.etlen = d.elen;
     d.hscene.etnbox = d.enbox;
+    d.hscene.etnode = d.enode;
     d.hscene.etedge = d.eleaf_edge;
     HIPCHK(hipMemcpyAsync(d.dscene, &d.hscene, sizeof(DevScene), hipMemcpyHostToDevice, s));
     HIPCHK(hipGetLastError());
@@ -1088,7 +1091,7 @@ void st_scene_destroy(st_scene* sc) {
     SceneDev& d = sc->d;
     void* ptrs[] = {d.V, d.F, d.mat, d.lights, d.env, d.fnorm, d.bmin, d.bmax, d.cen, d.bounds, d.mkeys[0], d.mkeys[1],
                     d.mvals[0], d.mvals[1], d.rs_hist, d.keys64, d.child, d.parent, d.aabb, d.refit_cnt, d.tcost, d.tleaves, d.ebmin, d.ebmax, d.ecen, d.ebounds, d.emkeys[0], d.emkeys[1],
-                    d.emvals[0], d.emvals[1], d.ers_hist, d.ekeys64, d.echild, d.eparent, d.ecnt, d.eaabb, d.elen, d.enbox, d.nodes4, d.flag4, d.id4,
+                    d.emvals[0], d.emvals[1], d.ers_hist, d.ekeys64, d.echild, d.eparent, d.ecnt, d.eaabb, d.elen, d.enbox, d.enode, d.nodes4, d.flag4, d.id4,
                     d.tri, d.edges, d.edge_w, d.eguide, d.mguide, d.cguide, d.ecdf, d.etotal_d, d.etotal_f, d.row_dom, d.rowcos, d.cond, d.marg,
                     d.env_rows, d.env_total, d.texpdf, d.err, d.work, d.dscene, d.vf_off, d.vf_idx, d.facc, d.macc, d.fe,
                     d.ealias};

@@ -804,6 +804,25 @@ __global__ void k_erefit(const int* __restrict__ parent, const int* __restrict__
     }
 }
 
+// packed record of internal node i of the edge tree: for child j, float4s
+// 4j..4j+3 hold its box (lower, upper), length, normal box (lower, upper) and code
+__global__ void k_epack(const int* __restrict__ child, const float* __restrict__ aabb, const float* __restrict__ len,
+                        const float* __restrict__ nbox, int n, float4* node) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n - 1) return;
+    for (int j = 0; j < 2; ++j) {
+        const int c = child[2 * i + j];
+        const size_t k = (c & (int)LEAF_BIT) ? (size_t)(n - 1) + (c & 0x7FFFFFFF) : (size_t)c;
+        const float* b = aabb + 6 * k;
+        const float* nb = nbox + 6 * k;
+        float4* o = node + 8 * (size_t)i + 4 * j;
+        o[0] = make_float4(b[0], b[1], b[2], b[3]);
+        o[1] = make_float4(b[4], b[5], len[k], nb[0]);
+        o[2] = make_float4(nb[1], nb[2], nb[3], nb[4]);
+        o[3] = make_float4(nb[5], __int_as_float(c), 0.0f, 0.0f);
+    }
+}
+
 // Morton keys of n centres, stably sorted (4 LSD passes); returns the buffer
 // index that holds the sorted (key, value) pairs
 static int radix_sort_keys(const float4* cen, int n, float* bounds, uint32_t* const mk[2], uint32_t* const mv[2],
@@ -835,9 +854,12 @@ void launch_edge_tree(SceneDev& s, hipStream_t st) {
     if (n > 1) ST_LAUNCH("k_karras", k_karras, dim3(nb(n - 1, 256)), dim3(256), 0, st, sm, se, n, s.echild, s.eparent);
     ST_LAUNCH("k_eleaf_init", k_eleaf_init, dim3(nb(n, 256)), dim3(256), 0, st, se, s.ebmin, s.ebmax, s.edges, s.V,
               s.F, n, s.eaabb, s.elen, s.enbox, s.ecnt);
-    if (n > 1)
+    if (n > 1) {
         ST_LAUNCH("k_erefit", k_erefit, dim3(nb(n, 256)), dim3(256), 0, st, s.eparent, s.echild, n, s.eaabb, s.elen,
                   s.enbox, s.ecnt);
+        ST_LAUNCH("k_epack", k_epack, dim3(nb(n - 1, 256)), dim3(256), 0, st, s.echild, s.eaabb, s.elen, s.enbox, n,
+                  s.enode);
+    }
 }
 
 void launch_scene_geometry(SceneDev& s, hipStream_t st) {

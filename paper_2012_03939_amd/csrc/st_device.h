@@ -137,6 +137,8 @@ struct DevScene {
     const float* etbox;   // node boxes [2ne-1, 6] (internal nodes, then leaves)
     const float* etlen;   // node length sums [2ne-1]
     const float* etnbox;  // node boxes of the adjacent faces' unit normals [2ne-1, 6]
+    const float4* etnode; // per internal node, both children's box, length, normal box and code
+                          // in one 128-B record (8 float4, layout of k_epack) [ne-1]
     const uint32_t* etedge; // sorted leaf -> edge
     const EnvAlias* ealias; // [he*we] alias table of the texel probabilities, used when env_alias
     int env_alias;
@@ -607,10 +609,9 @@ __device__ __forceinline__ int bsdf_sample(float4 u, V3 wo, V3 n, float alpha, b
 // takes each child with probability proportional to its weight, by a fresh
 // uniform per level (level l: component l % 4 of the draw of block 4 + l / 4 at
 // vertex k); returns the edge and its probability pe, or -1 when all weights vanish.
-__device__ __forceinline__ float edge_node_weight(const DevScene& S, int code, V3 p, V3 nrm, bool sil) {
+__device__ __forceinline__ float edge_node_weight(const float* bx, float len, const float* nb, V3 p, V3 nrm,
+                                                  bool sil) {
 #pragma clang fp contract(off)
-    const int idx = (code & (int)LEAF_BIT) ? (S.ne - 1) + (code & 0x7FFFFFFF) : code;
-    const float* bx = S.etbox + 6 * (size_t)idx;
     const float dx = (bx[0] + bx[3]) * 0.5f - p.x, dy = (bx[1] + bx[4]) * 0.5f - p.y, dz = (bx[2] + bx[5]) * 0.5f - p.z;
     const float ex = bx[3] - bx[0], ey = bx[4] - bx[1], ez = bx[5] - bx[2];
     const float reach = (dx * nrm.x + dy * nrm.y + dz * nrm.z) +
@@ -618,7 +619,6 @@ __device__ __forceinline__ float edge_node_weight(const DevScene& S, int code, V
     const float tol = 0x1p-16f * (((fabsf(dx) + fabsf(dy)) + fabsf(dz)) + ((ex + ey) + ez));
     if (!(reach > -tol)) return 0.0f;
     if (sil) {
-        const float* nb = S.etnbox + 6 * (size_t)idx;
         const float a0 = -nb[0] * dx, b0 = -nb[3] * dx, a1 = -nb[1] * dy, b1 = -nb[4] * dy;
         const float a2 = -nb[2] * dz, b2 = -nb[5] * dz;
         const float lo = ((0.0f + fminf(a0, b0)) + fminf(a1, b1)) + fminf(a2, b2);
@@ -630,7 +630,16 @@ __device__ __forceinline__ float edge_node_weight(const DevScene& S, int code, V
     }
     const float dl1 = ((fabsf(dx) + fabsf(dy)) + fabsf(dz)) + 0.5f * ((ex + ey) + ez);
     const float cb = (reach + tol) / (dl1 + tol);
-    return S.etlen[idx] * cb / ((dx * dx + dy * dy + dz * dz) + 0.25f * ((ex * ex + ey * ey) + ez * ez));
+    return len * cb / ((dx * dx + dy * dy + dz * dz) + 0.25f * ((ex * ex + ey * ey) + ez * ez));
+}
+
+// child j (0, 1) of a packed record: box (6), length, normal box (6), code
+__device__ __forceinline__ float edge_child_weight(const float4* rec, int j, V3 p, V3 nrm, bool sil, int& code) {
+    const float4 a = rec[4 * j], b = rec[4 * j + 1], c = rec[4 * j + 2], d = rec[4 * j + 3];
+    const float bx[6] = {a.x, a.y, a.z, a.w, b.x, b.y};
+    const float nb[6] = {b.w, c.x, c.y, c.z, c.w, d.x};
+    code = __float_as_int(d.y);
+    return edge_node_weight(bx, b.z, nb, p, nrm, sil);
 }
 
 __device__ __forceinline__ int edge_tree_sample(const DevScene& S, V3 p, V3 nrm, const Ctr& ctr, int k,
@@ -643,8 +652,9 @@ __device__ __forceinline__ int edge_tree_sample(const DevScene& S, V3 p, V3 nrm,
     for (int level = 0; !(code & (int)LEAF_BIT); ++level) {
         if (level >= 128) return -1;
         if ((level & 3) == 0) u = draw4(ctr, k, 4 + (level >> 2), key);
-        const int c0 = S.etchild[2 * code], c1 = S.etchild[2 * code + 1];
-        const float w0 = edge_node_weight(S, c0, p, nrm, sil), w1 = edge_node_weight(S, c1, p, nrm, sil);
+        const float4* rec = S.etnode + 8 * (size_t)code;
+        int c0, c1;
+        const float w0 = edge_child_weight(rec, 0, p, nrm, sil, c0), w1 = edge_child_weight(rec, 1, p, nrm, sil, c1);
         const float tot = w0 + w1;
         if (!(tot > 0.0f)) return -1;
         const float p0 = w0 / tot;
@@ -652,7 +662,7 @@ __device__ __forceinline__ int edge_tree_sample(const DevScene& S, V3 p, V3 nrm,
         if (ul < p0) { code = c0; pe *= p0; }
         else { code = c1; pe *= w1 / tot; }
     }
-    if (S.ne == 1 && !(edge_node_weight(S, (int)LEAF_BIT, p, nrm, sil) > 0.0f)) return -1;
+    if (S.ne == 1 && !(edge_node_weight(S.etbox, S.etlen[0], S.etnbox, p, nrm, sil) > 0.0f)) return -1;
     return (int)S.etedge[code & 0x7FFFFFFF];
 }
 

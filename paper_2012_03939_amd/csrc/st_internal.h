@@ -60,6 +60,7 @@ struct SceneDev {
     uint64_t* ekeys64 = nullptr;
     int *echild = nullptr, *eparent = nullptr, *ecnt = nullptr;
     float *eaabb = nullptr, *elen = nullptr, *enbox = nullptr;
+    float4* enode = nullptr;                 // packed internal nodes of the edge tree (8 float4 each)
     const uint32_t* eleaf_edge = nullptr;    // points into emkeys/emvals after the sort
     int* tleaves = nullptr;                  // [nf-1] triangles below every internal node
     float4* nodes4 = nullptr;                // [(nf-1)*8] 4-wide nodes (at most nf-1 of them)
