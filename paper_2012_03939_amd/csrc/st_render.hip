@@ -132,6 +132,9 @@ __global__ void __launch_bounds__(SHADE_BLOCK) SHADE_OCC k_shade(FwdParams p, Qu
     float* const* rn = q.ray[(k + 1) & 1];
     const int stride = gridDim.x * blockDim.x;
     const bool hashing = p.dbg_hash || p.hash_by_q;
+    // with the shadow sum fused into k_shadow, the shading record keeps only what
+    // k_shadow reads (face, point)
+    const bool fused = shadow_fused(p, q);
     // every thread of a block runs the same number of iterations: the
     // compaction below reserves queue slots per block
     for (int b0 = blockIdx.x * blockDim.x; b0 < n; b0 += stride) {
@@ -153,7 +156,7 @@ __global__ void __launch_bounds__(SHADE_BLOCK) SHADE_OCC k_shade(FwdParams p, Qu
             f = q.hf[i];
             push_face(h, f);
             if (p.rec_face && (vd >> 16) == 0u) p.rec_face[(size_t)(k - 1) * p.rec_n + qu(r, QQ, i)] = f;
-            q.sface[i] = -1;
+            if (!fused) q.sface[i] = -1;
             const V3 d{r[QDX][i], r[QDY][i], r[QDZ][i]};
             if (f < 0) {
                 if (S.has_env && k > 1) {
@@ -196,7 +199,7 @@ __global__ void __launch_bounds__(SHADE_BLOCK) SHADE_OCC k_shade(FwdParams p, Qu
                     q.sh[0][e] = wl.x; q.sh[1][e] = wl.y; q.sh[2][e] = wl.z; q.sh[3][e] = tmax;
                     q.sh[4][e] = ct.x; q.sh[5][e] = ct.y; q.sh[6][e] = ct.z;
                     if (tmax >= 0.0f) rays |= 1u << l;
-                    else q.socc[e] = 0;
+                    else if (!fused) q.socc[e] = 0;
                 }
                 int tex = 0;
                 if (S.has_env) {
@@ -215,7 +218,7 @@ __global__ void __launch_bounds__(SHADE_BLOCK) SHADE_OCC k_shade(FwdParams p, Qu
                     q.sh[0][e] = we.x; q.sh[1][e] = we.y; q.sh[2][e] = we.z; q.sh[3][e] = tmax;
                     q.sh[4][e] = ct.x; q.sh[5][e] = ct.y; q.sh[6][e] = ct.z;
                     if (tmax >= 0.0f) rays |= 1u << S.nl;
-                    else q.socc[e] = 0;
+                    else if (!fused) q.socc[e] = 0;
                 }
                 uint32_t info = 0;
                 if (k < p.B || S.has_env) {
@@ -231,12 +234,12 @@ __global__ void __launch_bounds__(SHADE_BLOCK) SHADE_OCC k_shade(FwdParams p, Qu
                     }
                 }
                 q.sface[i] = f;
-                q.sinfo[i] = info;
+                if (!fused) q.sinfo[i] = info;
                 if (shadow_fused(p, q) && p.rec_occ && (vd >> 16) == 0u)
                     p.rec_occ[(size_t)(k - 1) * p.rec_n + qu(r, QQ, i)] = 0u;
-                q.stex[i] = tex;
+                if (!fused) q.stex[i] = tex;
                 q.sx[0][i] = x.x; q.sx[1][i] = x.y; q.sx[2][i] = x.z;
-                q.snext[i] = -1;
+                if (!fused) q.snext[i] = -1;
             }
             hv = h.h;
         }
@@ -259,7 +262,7 @@ __global__ void __launch_bounds__(SHADE_BLOCK) SHADE_OCC k_shade(FwdParams p, Qu
                 qu(rn, QVD, o) = qu(r, QVD, i);
                 rn[QBR][o] = beta.x; rn[QBG][o] = beta.y; rn[QBB][o] = beta.z;
                 if (hashing) qu(rn, QHASH, o) = hv;
-                q.snext[i] = o;
+                if (!fused) q.snext[i] = o;
             }
         }
         if (active && hashing) qu(r, QHASH, i) = hv;
