@@ -486,6 +486,7 @@ int st_scene_create(const float* V, int32_t nv, const int32_t* F, int32_t nf, co
     A(dalloc(&d.flag4, (size_t)std::max(nf - 1, 1)));
     A(dalloc(&d.id4, (size_t)std::max(nf - 1, 1)));
     A(dalloc(&d.tri, 3 * (size_t)nf));
+    A(dalloc(&d.fleaf, (size_t)nf));
     A(dalloc(&d.vf_off, (size_t)nv + 1));
     A(dalloc(&d.fe, 3 * (size_t)nf));
     A(dalloc(&d.vf_idx, 3 * (size_t)nf));
@@ -548,7 +549,7 @@ int st_scene_create(const float* V, int32_t nv, const int32_t* F, int32_t nf, co
     HIPCHK2(hipStreamSynchronize(s));
     d.has_env = he > 0 && etot > 0.0;
     DevScene& h = d.hscene;
-    h.V = d.V; h.F = d.F; h.mat = d.mat; h.lights = d.lights; h.fnorm = d.fnorm; h.tri = d.tri; h.nodes4 = d.nodes4;
+    h.V = d.V; h.F = d.F; h.mat = d.mat; h.lights = d.lights; h.fnorm = d.fnorm; h.tri = d.tri; h.fleaf = d.fleaf; h.nodes4 = d.nodes4;
     h.env = d.env; h.marg = d.marg; h.cond = d.cond; h.texpdf = d.texpdf; h.rowcos = d.rowcos;
     h.edges = d.edges; h.ecdf = d.ecdf; h.etotal = d.etotal_f;
     h.eguide = d.eguide; h.mguide = d.mguide; h.cguide = d.cguide;
@@ -1092,7 +1093,7 @@ void st_scene_destroy(st_scene* sc) {
     void* ptrs[] = {d.V, d.F, d.mat, d.lights, d.env, d.fnorm, d.bmin, d.bmax, d.cen, d.bounds, d.mkeys[0], d.mkeys[1],
                     d.mvals[0], d.mvals[1], d.rs_hist, d.keys64, d.child, d.parent, d.aabb, d.refit_cnt, d.tcost, d.tleaves, d.ebmin, d.ebmax, d.ecen, d.ebounds, d.emkeys[0], d.emkeys[1],
                     d.emvals[0], d.emvals[1], d.ers_hist, d.ekeys64, d.echild, d.eparent, d.ecnt, d.eaabb, d.elen, d.enbox, d.enode, d.nodes4, d.flag4, d.id4,
-                    d.tri, d.edges, d.edge_w, d.eguide, d.mguide, d.cguide, d.ecdf, d.etotal_d, d.etotal_f, d.row_dom, d.rowcos, d.cond, d.marg,
+                    d.tri, d.fleaf, d.edges, d.edge_w, d.eguide, d.mguide, d.cguide, d.ecdf, d.etotal_d, d.etotal_f, d.row_dom, d.rowcos, d.cond, d.marg,
                     d.env_rows, d.env_total, d.texpdf, d.err, d.work, d.dscene, d.vf_off, d.vf_idx, d.facc, d.macc, d.fe,
                     d.ealias};
     for (void* p : ptrs)

@@ -587,7 +587,9 @@ __global__ void __launch_bounds__(EDGE_CAM_BLOCK) k_edge_camera(BwdParams p, Que
             const V3 d = side_dir(c, es, side);
             r[QOX][s] = c.eye[0]; r[QOY][s] = c.eye[1]; r[QOZ][s] = c.eye[2];
             r[QDX][s] = d.x; r[QDY][s] = d.y; r[QDZ][s] = d.z;
-            qu(r, QEXCL, s) = 0xFFFFFFFFu;
+            // a camera ray excludes no face: the slot carries the sampled edge
+            // (top bit set), whose faces the extension tests before traversing
+            qu(r, QEXCL, s) = 0x80000000u | (uint32_t)es.e;
             r[QPPREV][s] = 0.0f;
             const uint32_t lq = (uint32_t)(2 * ge + side);
             qu(r, QQ, s) = lq;

@@ -216,11 +216,12 @@ __global__ void k_karras(const uint32_t* __restrict__ m, const uint32_t* __restr
 
 __global__ void k_leaf_init(const uint32_t* __restrict__ sface, const float4* __restrict__ bmin,
                             const float4* __restrict__ bmax, const float* __restrict__ V, const int* __restrict__ F,
-                            int n, float* aabb, float4* tri, int* cnt) {
+                            int n, float* aabb, float4* tri, int* fleaf, int* cnt) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n - 1) cnt[i] = 0;
     if (i >= n) return;
     const int f = (int)sface[i];
+    fleaf[f] = i;
     float* b = aabb + 6 * ((size_t)(n - 1) + i);
     const float4 mn = bmin[f], mx = bmax[f];
     b[0] = mn.x; b[1] = mn.y; b[2] = mn.z; b[3] = mx.x; b[4] = mx.y; b[5] = mx.z;
@@ -886,7 +887,7 @@ void launch_scene_geometry(SceneDev& s, hipStream_t st) {
     if (nf > 1)
         ST_LAUNCH("k_karras", k_karras, dim3(nb(nf - 1, 256)), dim3(256), 0, st, sm, sf, nf, s.child, s.parent);
     ST_LAUNCH("k_leaf_init", k_leaf_init, dim3(nb(nf, 256)), dim3(256), 0, st, sf, s.bmin, s.bmax, s.V, s.F, nf, s.aabb,
-                       s.tri, s.refit_cnt);
+                       s.tri, s.fleaf, s.refit_cnt);
     if (nf > 1) {
         ST_LAUNCH("k_refit", k_refit, dim3(nb(nf, 256)), dim3(256), 0, st, s.parent, s.child, nf, s.aabb,
                            s.refit_cnt);

@@ -121,6 +121,7 @@ struct DevScene {
     const float* lights;  // [nl,6]
     const float4* fnorm;  // [nf] unit geometric normal
     const float4* tri;    // [nf*3] leaf-ordered (v0, face bits) (e1) (e2)
+    const int* fleaf;     // [nf] leaf index of each face
     const float4* nodes4; // 4-wide nodes, 8 float4 each: SoA child boxes + child codes
     const float* env;     // [he,we,3]
     const double* marg;   // [he+1]
@@ -311,11 +312,14 @@ __device__ __forceinline__ void cswap(float& ta, uint32_t& ca, float& tb, uint32
     }
 }
 
-// closest hit with t in (tmin, inf) excluding one face; ties go to the smaller face id
-__device__ int trace_closest(const DevScene& S, V3 o, V3 d, float tmin, int exclude, float& thit, TravStack& st) {
+// closest hit with t in (tmin, inf) excluding one face; ties go to the smaller face id.
+// (t0, f0): a hit already known (f0 >= 0, from the same triangle test), which
+// only prunes the traversal: the result is the least (t, face) either way
+__device__ int trace_closest(const DevScene& S, V3 o, V3 d, float tmin, int exclude, float& thit, TravStack& st,
+                             float t0 = __int_as_float(0x7f800000), int f0 = -1) {
     const float INF = __int_as_float(0x7f800000);
-    float tbest = INF;
-    int best = -1;
+    float tbest = t0;
+    int best = f0;
     const TraceGeo G = trace_geo(S);
     if (G.nf <= 0) return -1;
     uint32_t tests = 0;

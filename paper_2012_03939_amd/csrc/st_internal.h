@@ -67,6 +67,7 @@ struct SceneDev {
     int* flag4 = nullptr;                    // [nf-1] even-depth flag of the binary nodes
     uint32_t* id4 = nullptr;                 // [nf-1] 4-wide node index of each even-depth node
     float4* tri = nullptr;                   // [nf*3]
+    int* fleaf = nullptr;                    // [nf] leaf index of each face
     // edges (topology fixed at creation)
     int4* edges = nullptr;
     double* edge_w = nullptr;

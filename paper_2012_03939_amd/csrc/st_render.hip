@@ -107,8 +107,28 @@ __global__ void __launch_bounds__(TRACE_BLOCK) EXTEND_OCC k_extend(FwdParams p, 
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const DevScene& S = p.scenes[p.cams[qu(r, QVD, i) & 0xFFFFu].scene];
         const V3 o{r[QOX][i], r[QOY][i], r[QOZ][i]}, d{r[QDX][i], r[QDY][i], r[QDZ][i]};
+        uint32_t ex = qu(r, QEXCL, i);
+        float t0 = __int_as_float(0x7f800000);
+        int f0 = -1;
+        if (k == 1 && ex != 0xFFFFFFFFu) {
+            // a primary-edge side ray names its edge: the edge's faces are
+            // tested first, so that the traversal starts with their hit
+            const int4 E = S.edges[ex & 0x7FFFFFFFu];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int fe = j == 0 ? E.z : E.w;
+                float th; int fh;
+                if (fe >= 0 && tri_test((const gfloat4*)S.tri, (uint32_t)S.fleaf[fe], o, d, TMIN,
+                                        __int_as_float(0x7f800000), th, fh) &&
+                    (th < t0 || (th == t0 && fh < f0))) {
+                    t0 = th;
+                    f0 = fh;
+                }
+            }
+            ex = 0xFFFFFFFFu;
+        }
         float t;
-        const int f = trace_closest(S, o, d, TMIN, (int)qu(r, QEXCL, i), t, st);
+        const int f = trace_closest(S, o, d, TMIN, (int)ex, t, st, t0, f0);
         q.ht[i] = t;
         q.hf[i] = f;
     }
