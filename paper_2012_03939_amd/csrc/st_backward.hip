@@ -585,19 +585,17 @@ __global__ void __launch_bounds__(EDGE_CAM_BLOCK) k_edge_camera(BwdParams p, Que
         for (int side = 0; side < 2; ++side) {
             const int s = o0 + side;
             const V3 d = side_dir(c, es, side);
-            r[QOX][s] = c.eye[0]; r[QOY][s] = c.eye[1]; r[QOZ][s] = c.eye[2];
+            // (origin, previous pdf, throughput and hash of a camera ray are
+            // taken from the camera by the bounce-1 kernels)
             r[QDX][s] = d.x; r[QDY][s] = d.y; r[QDZ][s] = d.z;
             // a camera ray excludes no face: the slot carries the sampled edge
             // (top bit set), whose faces the extension tests before traversing
             qu(r, QEXCL, s) = 0x80000000u | (uint32_t)es.e;
-            r[QPPREV][s] = 0.0f;
             const uint32_t lq = (uint32_t)(2 * ge + side);
             qu(r, QQ, s) = lq;
             qu(r, QC0, s) = (uint32_t)es.si;
             qu(r, QC1, s) = (uint32_t)c.rngview << 16;
             qu(r, QVD, s) = (uint32_t)es.v | (1u << 16);
-            r[QBR][s] = 1.0f; r[QBG][s] = 1.0f; r[QBB][s] = 1.0f;
-            qu(r, QHASH, s) = FNV_INIT;
             q.L[3 * (size_t)lq] = 0.0f; q.L[3 * (size_t)lq + 1] = 0.0f; q.L[3 * (size_t)lq + 2] = 0.0f;
         }
     }

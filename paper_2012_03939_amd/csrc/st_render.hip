@@ -60,16 +60,14 @@ __global__ void k_camera(FwdParams p, Queues q, long long q0, int n) {
         const Ctr ctr{(uint32_t)(y * c.W + x), ((uint32_t)c.rngview << 16) | (uint32_t)j, 0u, 0u};
         const float4 u = draw4(ctr, 0, 0, Key{p.seed, S.scene_id});
         const V3 d = cam_dir(c, (float)x + u.x, (float)y + u.y);
-        r[QOX][s] = c.eye[0]; r[QOY][s] = c.eye[1]; r[QOZ][s] = c.eye[2];
+        // origin (the eye), previous pdf, throughput and hash of a camera ray are
+        // constants that the bounce-1 kernels take from the camera themselves
         r[QDX][s] = d.x; r[QDY][s] = d.y; r[QDZ][s] = d.z;
         qu(r, QEXCL, s) = 0xFFFFFFFFu;
-        r[QPPREV][s] = 0.0f;
         qu(r, QQ, s) = (uint32_t)qq;
         qu(r, QC0, s) = ctr.c0;
         qu(r, QC1, s) = ctr.c1;
         qu(r, QVD, s) = (uint32_t)v;
-        r[QBR][s] = 1.0f; r[QBG][s] = 1.0f; r[QBB][s] = 1.0f;
-        qu(r, QHASH, s) = FNV_INIT;
         q.L[3 * (size_t)qq] = 0.0f; q.L[3 * (size_t)qq + 1] = 0.0f; q.L[3 * (size_t)qq + 2] = 0.0f;
     }
 }
@@ -88,8 +86,9 @@ __global__ void __launch_bounds__(TRACE_BLOCK) EXTEND_OCC k_extend(FwdParams p, 
         trace_queue<false>(
             q.fetch + FETCH_SLOT_INTS * (16 + k), n, st,
             [&](int i, RayJob& J) {
-                const DevScene& S = p.scenes[p.cams[qu(r, QVD, i) & 0xFFFFu].scene];
-                J.o = V3{r[QOX][i], r[QOY][i], r[QOZ][i]};
+                const DevCam& cam = p.cams[qu(r, QVD, i) & 0xFFFFu];
+                const DevScene& S = p.scenes[cam.scene];
+                J.o = k == 1 ? ld3(cam.eye) : V3{r[QOX][i], r[QOY][i], r[QOZ][i]};
                 J.d = V3{r[QDX][i], r[QDY][i], r[QDZ][i]};
                 J.tmax = __int_as_float(0x7f800000);
                 J.excl = (int)qu(r, QEXCL, i);
@@ -105,8 +104,10 @@ __global__ void __launch_bounds__(TRACE_BLOCK) EXTEND_OCC k_extend(FwdParams p, 
     // 64 consecutive queue entries per wave, traced in lockstep
     const int stride = gridDim.x * blockDim.x;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const DevScene& S = p.scenes[p.cams[qu(r, QVD, i) & 0xFFFFu].scene];
-        const V3 o{r[QOX][i], r[QOY][i], r[QOZ][i]}, d{r[QDX][i], r[QDY][i], r[QDZ][i]};
+        const DevCam& cam = p.cams[qu(r, QVD, i) & 0xFFFFu];
+        const DevScene& S = p.scenes[cam.scene];
+        const V3 o = k == 1 ? ld3(cam.eye) : V3{r[QOX][i], r[QOY][i], r[QOZ][i]};
+        const V3 d{r[QDX][i], r[QDY][i], r[QDZ][i]};
         uint32_t ex = qu(r, QEXCL, i);
         float t0 = __int_as_float(0x7f800000);
         int f0 = -1;
@@ -171,8 +172,8 @@ __global__ void __launch_bounds__(SHADE_BLOCK) SHADE_OCC k_shade(FwdParams p, Qu
             const DevScene& S = p.scenes[p.cams[vd & 0xFFFFu].scene];
             const Key key{p.seed, S.scene_id};
             const Ctr ctr{c0, c1, 0u, vd >> 16};
-            Hash h{hashing ? qu(r, QHASH, i) : 0u, hashing};
-            beta = V3{r[QBR][i], r[QBG][i], r[QBB][i]};
+            Hash h{hashing ? (k == 1 ? FNV_INIT : qu(r, QHASH, i)) : 0u, hashing};
+            beta = k == 1 ? V3{1.f, 1.f, 1.f} : V3{r[QBR][i], r[QBG][i], r[QBB][i]};
             f = q.hf[i];
             push_face(h, f);
             if (p.rec_face && (vd >> 16) == 0u) p.rec_face[(size_t)(k - 1) * p.rec_n + qu(r, QQ, i)] = f;
@@ -192,7 +193,7 @@ __global__ void __launch_bounds__(SHADE_BLOCK) SHADE_OCC k_shade(FwdParams p, Qu
             } else if (k > p.B) {
                 if (hashing) final_hash(p, r, i, h.h);
             } else {
-                const V3 o{r[QOX][i], r[QOY][i], r[QOZ][i]};
+                const V3 o = k == 1 ? ld3(p.cams[vd & 0xFFFFu].eye) : V3{r[QOX][i], r[QOY][i], r[QOZ][i]};
                 x = o + d * q.ht[i];
                 V3 n = xyz(S.fnorm[f]);
                 const V3 wo = -d;
