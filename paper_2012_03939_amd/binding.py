@@ -343,14 +343,14 @@ def profile_read(max_kernels: int = 64):
 
 
 def render_batch(scenes: Sequence[GPUScene], cams, cam_scene, spp: int, bounces: int, seed: int = 0, out=None,
-                 flags: int = 0, queue_capacity: int = 0):
+                 flags: int = 0, queue_capacity: int = 0, debug_hash=None):
     import torch
     arr = (ctypes.c_void_p * len(scenes))(*[s.h.value for s in scenes])
     cs = (ctypes.c_int32 * len(cams))(*[int(x) for x in cam_scene])
     cam = make_cameras(cams)
     if out is None:
         out = torch.empty((num_pixels(cams), 3), dtype=torch.float32, device="cuda")
-    o = make_opts(flags=flags, queue_capacity=queue_capacity)
+    o = make_opts(flags=flags, queue_capacity=queue_capacity, dbg_hash=debug_hash)
     _check(load().st_render_batch(arr, len(scenes), cam, cs, len(cams), spp, bounces, seed, ctypes.byref(o),
                                   _ptr(out), _stream()))
     return out
