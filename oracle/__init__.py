@@ -93,7 +93,7 @@ def lib():
                                      P, P, P, P]
         L.or_sample_grad.restype = ctypes.c_double
         L.or_secondary_term.argtypes = [P, P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_longlong,
-                                        ctypes.c_uint, ctypes.c_int, P]
+                                        ctypes.c_uint, ctypes.c_int, ctypes.c_int, P]
         L.or_scene_set_texels.argtypes = [P, ctypes.c_int, P]
         L.or_scene_set_texels.restype = ctypes.c_longlong
         L.or_texel_index.argtypes = [ctypes.c_int, ctypes.c_longlong, ctypes.c_double, ctypes.c_double]
@@ -271,10 +271,14 @@ class OracleScene:
         return lib().or_sample_frozen(self.h, _p(rows), _p(res), len(cams), spp, bounces, seed, flags, view, px,
                                       py, j, _p(_f64(w)), kind, index, delta)
 
-    def secondary_term(self, p, n, wo, face, budget, nsamples, seed=0, hierarchy=False):
+    def secondary_term(self, p, n, wo, face, budget, nsamples, seed=0, hierarchy=False, interior=False):
+        """Secondary edge term at one fixed shading point (the first-vertex edge
+        sample of a path, nsamples times): gradient of the loss 1/3 sum_c I_c,
+        I the reflected radiance toward wo, with respect to the vertices.
+        interior: creases and material boundaries as well as silhouettes."""
         dV = np.zeros((self.nv, 3))
         lib().or_secondary_term(self.h, _p(_f64(p)), _p(_f64(n)), _p(_f64(wo)), face, budget, nsamples, seed,
-                                int(bool(hierarchy)), _p(dV))
+                                int(bool(hierarchy)), int(bool(interior)), _p(dV))
         return dV
 
     def edge_tree(self):

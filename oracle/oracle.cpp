@@ -42,7 +42,7 @@ static const double ALPHA_MIN = 1e-3;       // roughness floor
 static const double LOBE_SPEC_P = 0.5;      // probability of sampling the specular lobe
 static const double EPS_PRIMARY = 1e-3;     // primary edge side offset, pixels
 static const double EPS_SECONDARY = 1e-4;   // secondary edge side offset, radians
-static const double ZNEAR = 1e-3;           // edges with an endpoint nearer than this are dropped
+static const double ZNEAR = 1e-3;           // primary edges are clipped at this depth
 static const double SEC_COS_MIN = 1e-5;     // secondary edge points this close to the tangent plane are skipped
 
 // --------------------------------------------------------------------------
@@ -769,6 +769,82 @@ static V3<T> plane_hit(const V3<T>& o, const V3<T>& d, const V3<T>& v0, const V3
 static D3 L_in_side(const Scene& s, const D3& x, const D3& dir, int exclude, int budget, const Ctr& ctr,
                     const Key& key, Hash& hash);
 
+// Secondary (direction-space) edge term at path vertex k: shading point x on
+// face f, normal n flipped toward wo, material row m, path throughput beta.
+// One edge is drawn (length CDF, or the importance hierarchy), a point y
+// uniform on it; the edge is taken when it is a silhouette seen from x (a
+// boundary edge, or its two faces on opposite sides of x) or, with
+// sec.interior, any edge not of face f (creases and material boundaries).  Two
+// side rays bracket the edge direction, their incoming radiance is estimated
+// with the remaining vertex budget, and the jump times the BRDF, the cosine and
+// the normal velocity of the edge on the sphere of directions is scattered to
+// the edge's endpoints (dV) with the selection weight.  The decision words go
+// to sech.
+static void secondary_edge_sample(const Scene& s, const D3& x, const D3& n, const D3& wo, int f, const double* m,
+                                  const D3& beta, int k, int budget, const Ctr& ctr, const Key& key,
+                                  const SecCtx& sec, Hash& sech, VRec* vr) {
+    double u[4];
+    draw4(ctr, k, 3, key.k0, key.k1, u);
+    int e;
+    double wsel = 0.0;      // 1 / (probability density of the edge point per unit length)
+    if (sec.hier) {
+        float pe;
+        e = edge_tree_sample(s, x, n, ctr, k, key, !sec.interior, pe);
+        if (e >= 0) {
+            const Edge& Es = s.edges[e];
+            wsel = length(s.vert(Es.vb) - s.vert(Es.va)) / (double)pe;
+        }
+    } else {
+        e = cdf_find(s.ecdf.data(), (int)s.edges.size(), u[0]);
+        wsel = s.elen_total;
+    }
+    double te = u[1];
+    if (e < 0) { sech.push(0xFFFFFFFFu); sech.push(0u); return; }
+    sech.push((uint32_t)e);
+    const Edge& E = s.edges[e];
+    D3 va = s.vert(E.va), vb = s.vert(E.vb);
+    // an edge of the shading face lies in the tangent plane (cos = 0):
+    // its direction-space contribution vanishes, so it is never taken
+    bool sil = E.f1 != f && E.f2 != f;
+    if (sil && E.f2 >= 0 && !sec.interior) {
+        double s1 = dot(face_N(s, E.f1), x - va), s2 = dot(face_N(s, E.f2), x - va);
+        sil = (s1 > 0.0) != (s2 > 0.0);
+    }
+    D3 y = va + (vb - va) * te;
+    D3 wv = y - x;
+    double r2 = dot(wv, wv);
+    if (sil && r2 > 0.0) {
+        double r = std::sqrt(r2);
+        D3 ud = wv * (1.0 / r);
+        double cv = dot(n, ud);
+        D3 eh = normalize(vb - va);
+        D3 mv = cross(ud, eh);
+        double ml = length(mv);
+        if (cv > SEC_COS_MIN && ml > 0.0) {
+            sech.push(1u);
+            D3 mm = mv * (1.0 / ml);
+            D3 wm = normalize(ud - mm * EPS_SECONDARY), wp = normalize(ud + mm * EPS_SECONDARY);
+            Ctr sc{ctr.c0, ctr.c1, (uint32_t)k << 16, 2u};
+            D3 Lm = L_in_side(s, x, wm, f, budget, sc, key, sech);
+            D3 Lp = L_in_side(s, x, wp, f, budget, sc, key, sech);
+            D3 fv = brdf(ud, wo, n, m);
+            double cc = 0.0;
+            for (int ch = 0; ch < 3; ++ch)
+                cc += sec.w[ch] * beta[ch] * fv[ch] * cv * (Lm[ch] - Lp[ch]);
+            cc *= wsel / r2;
+            if (sec.g) {
+                for (int k3 = 0; k3 < 3; ++k3) {
+                    sec.g->dV[3 * E.va + k3] += cc * (1.0 - te) * mv[k3];
+                    sec.g->dV[3 * E.vb + k3] += cc * te * mv[k3];
+                }
+            }
+            if (vr) { vr->sec = 1; vr->sec_c = cc; vr->sec_m = mv; }
+            return;
+        }
+    }
+    sech.push(0u);
+}
+
 // Radiance estimate along a ray (Sec. 3.2: R is a physically based path tracer).
 // first_escape_full: a miss on the very first segment returns the environment
 // radiance (side rays of the secondary edge term); otherwise (camera rays) a
@@ -860,70 +936,8 @@ static D3 trace_estimator(const Scene& s, D3 o, D3 d, int exclude, int nvert, bo
         }
         const bool continues = (k < nvert) || s.has_env;
         // secondary (direction-space) silhouette edge term, backward only
-        if (sec && continues && !s.edges.empty() && s.elen_total > 0.0) {
-            double u[4];
-            draw4(ctr, k, 3, key.k0, key.k1, u);
-            int e;
-            double wsel;            // 1 / (probability density of the edge point per unit length)
-            if (sec->hier) {
-                float pe;
-                e = edge_tree_sample(s, x, n, ctr, k, key, !sec->interior, pe);
-                if (e >= 0) {
-                    const Edge& Es = s.edges[e];
-                    wsel = length(s.vert(Es.vb) - s.vert(Es.va)) / (double)pe;
-                }
-            } else {
-                e = cdf_find(s.ecdf.data(), (int)s.edges.size(), u[0]);
-                wsel = s.elen_total;
-            }
-            double te = u[1];
-            if (e < 0) { sech.push(0xFFFFFFFFu); sech.push(0u); goto no_secondary; }
-            sech.push((uint32_t)e);
-            const Edge& E = s.edges[e];
-            D3 va = s.vert(E.va), vb = s.vert(E.vb);
-            // an edge of the shading face lies in the tangent plane (cos = 0):
-            // its direction-space contribution vanishes, so it is never taken
-            bool sil = E.f1 != f && E.f2 != f;
-            if (sil && E.f2 >= 0 && !sec->interior) {
-                double s1 = dot(face_N(s, E.f1), x - va), s2 = dot(face_N(s, E.f2), x - va);
-                sil = (s1 > 0.0) != (s2 > 0.0);
-            }
-            D3 y = va + (vb - va) * te;
-            D3 wv = y - x;
-            double r2 = dot(wv, wv);
-            int code = 0;
-            if (sil && r2 > 0.0) {
-                double r = std::sqrt(r2);
-                D3 ud = wv * (1.0 / r);
-                double cv = dot(n, ud);
-                D3 eh = normalize(vb - va);
-                D3 mv = cross(ud, eh);
-                double ml = length(mv);
-                if (cv > SEC_COS_MIN && ml > 0.0) {
-                    code = 1;
-                    sech.push(1u);
-                    D3 mm = mv * (1.0 / ml);
-                    D3 wm = normalize(ud - mm * EPS_SECONDARY), wp = normalize(ud + mm * EPS_SECONDARY);
-                    Ctr sc{ctr.c0, ctr.c1, (uint32_t)k << 16, 2u};
-                    D3 Lm = L_in_side(s, x, wm, f, nvert - k, sc, key, sech);
-                    D3 Lp = L_in_side(s, x, wp, f, nvert - k, sc, key, sech);
-                    D3 fv = brdf(ud, wo, n, m);
-                    double cc = 0.0;
-                    for (int ch = 0; ch < 3; ++ch)
-                        cc += sec->w[ch] * beta[ch] * fv[ch] * cv * (Lm[ch] - Lp[ch]);
-                    cc *= wsel / r2;
-                    if (sec->g) {
-                        for (int k3 = 0; k3 < 3; ++k3) {
-                            sec->g->dV[3 * E.va + k3] += cc * (1.0 - te) * mv[k3];
-                            sec->g->dV[3 * E.vb + k3] += cc * te * mv[k3];
-                        }
-                    }
-                    if (vr) { vr->sec = 1; vr->sec_c = cc; vr->sec_m = mv; }
-                }
-            }
-            if (code == 0) sech.push(0u);
-        }
-    no_secondary:
+        if (sec && continues && !s.edges.empty() && s.elen_total > 0.0)
+            secondary_edge_sample(s, x, n, wo, f, m, beta, k, nvert - k, ctr, key, *sec, sech, vr);
         // continuation by sampling the BRDF mixture
         if (!continues) break;
         double u[4];
@@ -1146,6 +1160,58 @@ static bool front_facing(const Scene& s, int f, const D3& eye) {
     return N.x * w.x + N.y * w.y + N.z * w.z > 0.0;
 }
 
+// The image of edge E in view c, as the primary edge term integrates over it.
+// Near plane: the part of the edge with depth > ZNEAR is kept; an endpoint at
+// or behind that depth is replaced by the point of the edge at depth ZNEAR,
+// sa (sb) being the fraction of the edge cut away at va (vb).  The kept
+// segment projects to the straight image segment x(t) = A + t (B - A),
+// t in [0, 1]; only its part inside the image rectangle [0, W] x [0, H]
+// (the range [t0, t1] of t, Liang-Barsky) can contribute, since points outside
+// the image have no pixel.  ok is false when nothing is left.
+struct ScreenEdge {
+    bool ok = false;
+    double ax = 0, ay = 0, bx = 0, by = 0;
+    double sa = 0, sb = 0, t0 = 0, t1 = 1;
+};
+
+static ScreenEdge screen_edge(const Scene& s, const Cam& c, const Edge& E) {
+    ScreenEdge r;
+    D3 a = s.vert(E.va), b = s.vert(E.vb);
+    double ax, ay, az, bx, by, bz;
+    project<double>(c, a, ax, ay, az);
+    project<double>(c, b, bx, by, bz);
+    if (!(az > ZNEAR) && !(bz > ZNEAR)) return r;
+    if (!(az > ZNEAR)) {
+        r.sa = (ZNEAR - az) / (bz - az);
+        D3 ac(a.x + (b.x - a.x) * r.sa, a.y + (b.y - a.y) * r.sa, a.z + (b.z - a.z) * r.sa);
+        project<double>(c, ac, ax, ay, az);
+    }
+    if (!(bz > ZNEAR)) {
+        r.sb = (ZNEAR - bz) / (az - bz);
+        D3 bc(b.x + (a.x - b.x) * r.sb, b.y + (a.y - b.y) * r.sb, b.z + (a.z - b.z) * r.sb);
+        project<double>(c, bc, bx, by, bz);
+    }
+    r.ax = ax; r.ay = ay; r.bx = bx; r.by = by;
+    const double dx = bx - ax, dy = by - ay;
+    // x(t) inside the rectangle: p t <= q for the four sides, in a fixed order
+    double t0 = 0.0, t1 = 1.0;
+    const double P[4] = {-dx, dx, -dy, dy};
+    const double Q[4] = {ax, (double)c.W - ax, ay, (double)c.H - ay};
+    for (int i = 0; i < 4; ++i) {
+        if (P[i] == 0.0) {
+            if (Q[i] < 0.0) return r;
+            continue;
+        }
+        const double q = Q[i] / P[i];
+        if (P[i] < 0.0) { if (q > t0) t0 = q; }
+        else { if (q < t1) t1 = q; }
+    }
+    if (!(t0 < t1)) return r;
+    r.t0 = t0; r.t1 = t1;
+    r.ok = true;
+    return r;
+}
+
 static EdgeView primary_cdf(const Scene& s, const Cam& c) {
     EdgeView ev;
     const size_t ne = s.edges.size();
@@ -1156,12 +1222,10 @@ static EdgeView primary_cdf(const Scene& s, const Cam& c) {
         double len = 0.0;
         bool cand = E.f2 < 0 || front_facing(s, E.f1, c.eye) || front_facing(s, E.f2, c.eye);
         if (cand) {
-            double ax, ay, az, bx, by, bz;
-            project<double>(c, s.vert(E.va), ax, ay, az);
-            project<double>(c, s.vert(E.vb), bx, by, bz);
-            if (az > ZNEAR && bz > ZNEAR) {
-                double dx = bx - ax, dy = by - ay;
-                len = std::sqrt(dx * dx + dy * dy);
+            ScreenEdge se = screen_edge(s, c, E);
+            if (se.ok) {
+                double dx = se.bx - se.ax, dy = se.by - se.ay;
+                len = (se.t1 - se.t0) * std::sqrt(dx * dx + dy * dy);
             }
         }
         acc += len;
@@ -1184,11 +1248,11 @@ static void primary_edge_sample(const Scene& s, const Cam& c, const EdgeView& ev
     draw4(ctr, 0, 3, key.k0, key.k1, u);
     // stratified over the view's ne samples: sample si takes the CDF at (si + u0) / ne
     int e = cdf_find(ev.cdf.data(), (int)s.edges.size(), ((double)si + u[0]) / (double)ne);
-    double t = u[1];
     const Edge& E = s.edges[e];
-    double ax, ay, az, bx, by, bz;
-    project<double>(c, s.vert(E.va), ax, ay, az);
-    project<double>(c, s.vert(E.vb), bx, by, bz);
+    const ScreenEdge se = screen_edge(s, c, E);     // ok: only such edges have weight
+    // the point is uniform on the visible part [t0, t1] of the image segment
+    double t = se.t0 + u[1] * (se.t1 - se.t0);
+    double ax = se.ax, ay = se.ay, bx = se.bx, by = se.by;
     double xs = (1.0 - t) * ax + t * bx, ys = (1.0 - t) * ay + t * by;
     int px = (int)std::floor(xs), py = (int)std::floor(ys);
     bool inside = xs >= 0.0 && ys >= 0.0 && px < c.W && py < c.H;
@@ -1213,16 +1277,22 @@ static void primary_edge_sample(const Scene& s, const Cam& c, const EdgeView& ev
     double cc = 0.0;
     for (int ch = 0; ch < 3; ++ch) cc += (double)dimg[ch] * (Lm[ch] - Lp[ch]);
     cc *= ev.total / (double)ne;
-    // screen-space velocity of the edge point: derivative of the projection of
-    // each endpoint, taken with 6-tangent dual numbers
-    for (int end = 0; end < 2; ++end) {
-        int vid = end == 0 ? E.va : E.vb;
-        double wgt = end == 0 ? (1.0 - t) : t;
-        D3 p = s.vert(vid);
-        V3<Dual<48>> pv(seeded<Dual<48>>(p.x, 0), seeded<Dual<48>>(p.y, 1), seeded<Dual<48>>(p.z, 2));
-        Dual<48> sx, sy, sz;
-        project<Dual<48>>(c, pv, sx, sy, sz);
-        for (int k = 0; k < 3; ++k) g.dV[3 * vid + k] += cc * wgt * (sx.d[k] * nx + sy.d[k] * ny);
+    // normal velocity of the image point x = (1 - t) pi(a') + t pi(b'), with the
+    // (near-plane) segment ends a' = va + sa (vb - va), b' = vb + sb (va - vb) and
+    // t, sa, sb held fixed (they only slide the point along the image line):
+    // 6-tangent dual numbers, slots 0..2 the coordinates of va, 3..5 of vb
+    typedef Dual<48> DD;
+    D3 pa = s.vert(E.va), pb = s.vert(E.vb);
+    V3<DD> A3(seeded<DD>(pa.x, 0), seeded<DD>(pa.y, 1), seeded<DD>(pa.z, 2));
+    V3<DD> B3(seeded<DD>(pb.x, 3), seeded<DD>(pb.y, 4), seeded<DD>(pb.z, 5));
+    V3<DD> ac = A3 + (B3 - A3) * se.sa, bc = B3 + (A3 - B3) * se.sb;
+    DD sxa, sya, sza, sxb, syb, szb;
+    project<DD>(c, ac, sxa, sya, sza);
+    project<DD>(c, bc, sxb, syb, szb);
+    DD X = sxa * (1.0 - t) + sxb * t, Y = sya * (1.0 - t) + syb * t;
+    for (int k = 0; k < 3; ++k) {
+        g.dV[3 * E.va + k] += cc * (X.d[k] * nx + Y.d[k] * ny);
+        g.dV[3 * E.vb + k] += cc * (X.d[3 + k] * nx + Y.d[3 + k] * ny);
     }
 }
 
@@ -2124,63 +2194,29 @@ double or_sample_grad(void* p, const double* cams, const int* res, int ncam, int
 
 // Secondary edge term alone at a fixed shading point p (normal n, outgoing wo,
 // material of face `face`, throughput 1, loss weight 1/3 per channel), averaged
-// over nsamples edge samples; the shading point itself is held fixed, so only
-// the edge endpoints receive gradient.  Used to pin the estimator against the
-// closed-form irradiance of a polygon.
+// over nsamples edge samples drawn exactly as at the first vertex of a path
+// (the function the backward calls); the shading point itself is held fixed,
+// so only the edge endpoints receive gradient.  interior: also creases and
+// material boundaries.  Used to pin the estimator against the closed-form
+// projected solid angle of polygons.
 void or_secondary_term(void* p, const double* pp, const double* nn, const double* wo, int face, int budget,
-                       long long nsamples, unsigned seed, int hier, double* dV) {
+                       long long nsamples, unsigned seed, int hier, int interior, double* dV) {
     Scene* s = (Scene*)p;
     Grad g; g.dV.assign(3 * (size_t)s->nv, 0.0); g.dM.assign(s->mat.size(), 0.0);
     Key key{seed, s->id};
     D3 x(pp[0], pp[1], pp[2]), n(nn[0], nn[1], nn[2]), o(wo[0], wo[1], wo[2]);
     const double* m = &s->mat[7 * texel_of(*s, face, x)];
-    for (long long i = 0; i < nsamples; ++i) {
-        Ctr ctr{(uint32_t)i, 0u, 0u, 3u};
-        double u[4];
-        draw4(ctr, 1, 3, key.k0, key.k1, u);
-        int e;
-        double wsel;
-        if (hier) {
-            float pe;
-            e = edge_tree_sample(*s, x, n, ctr, 1, key, true, pe);
-            if (e < 0) continue;
-            wsel = length(s->vert(s->edges[e].vb) - s->vert(s->edges[e].va)) / (double)pe;
-        } else {
-            e = cdf_find(s->ecdf.data(), (int)s->edges.size(), u[0]);
-            wsel = s->elen_total;
+    SecCtx sc;
+    for (int ch = 0; ch < 3; ++ch) sc.w[ch] = 1.0 / (3.0 * (double)nsamples);
+    sc.g = &g;
+    sc.interior = interior != 0;
+    sc.hier = hier != 0;
+    Hash h; h.on = false;
+    if (!s->edges.empty() && s->elen_total > 0.0)
+        for (long long i = 0; i < nsamples; ++i) {
+            Ctr ctr{(uint32_t)i, 0u, 0u, 3u};
+            secondary_edge_sample(*s, x, n, o, face, m, D3(1, 1, 1), 1, budget, ctr, key, sc, h, nullptr);
         }
-        double te = u[1];
-        const Edge& E = s->edges[e];
-        D3 va = s->vert(E.va), vb = s->vert(E.vb);
-        bool sil = true;
-        if (E.f2 >= 0) {
-            double s1 = dot(face_N(*s, E.f1), x - va), s2 = dot(face_N(*s, E.f2), x - va);
-            sil = (s1 > 0.0) != (s2 > 0.0);
-        }
-        D3 y = va + (vb - va) * te;
-        D3 wv = y - x;
-        double r2 = dot(wv, wv);
-        if (!sil || !(r2 > 0.0)) continue;
-        double r = std::sqrt(r2);
-        D3 ud = wv * (1.0 / r);
-        double cv = dot(n, ud);
-        D3 mv = cross(ud, normalize(vb - va));
-        double ml = length(mv);
-        if (!(cv > SEC_COS_MIN) || !(ml > 0.0)) continue;
-        D3 mm = mv * (1.0 / ml);
-        Hash h; h.on = false;
-        Ctr sc{(uint32_t)i, 0u, 1u << 16, 2u};
-        D3 Lm = L_in_side(*s, x, normalize(ud - mm * EPS_SECONDARY), face, budget, sc, key, h);
-        D3 Lp = L_in_side(*s, x, normalize(ud + mm * EPS_SECONDARY), face, budget, sc, key, h);
-        D3 fv = brdf(ud, o, n, m);
-        double cc = 0.0;
-        for (int ch = 0; ch < 3; ++ch) cc += (1.0 / 3.0) * fv[ch] * cv * (Lm[ch] - Lp[ch]);
-        cc *= wsel / r2 / (double)nsamples;
-        for (int k = 0; k < 3; ++k) {
-            g.dV[3 * E.va + k] += cc * (1.0 - te) * mv[k];
-            g.dV[3 * E.vb + k] += cc * te * mv[k];
-        }
-    }
     for (size_t i = 0; i < 3 * (size_t)s->nv; ++i) dV[i] = g.dV[i];
 }
 

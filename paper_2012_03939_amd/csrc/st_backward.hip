@@ -480,6 +480,59 @@ __device__ __forceinline__ bool front_facing_d(const DevScene& S, int f, const D
     return N[0] * wx + N[1] * wy + N[2] * wz > 0.0;
 }
 
+// The image of edge E in view c, as the primary edge term integrates over it:
+// the part of the edge in front of the near plane (an endpoint at depth <=
+// ZNEAR is replaced by the edge's point at depth ZNEAR; sa, sb = fraction of
+// the edge cut away at its first, second vertex), projected to the image
+// segment x(t) = A + t (B - A), and the range [t0, t1] of t inside the image
+// rectangle [0, W] x [0, H] (Liang-Barsky, sides in a fixed order).  fp64 with
+// a fixed operation order, so both implementations take the same candidates
+// and weights.  False when nothing is left.
+struct ScreenEdge {
+    double ax, ay, bx, by;
+    double sa, sb, t0, t1;
+};
+
+__device__ __forceinline__ bool screen_edge(const DevCam& c, const DevScene& S, int4 E, ScreenEdge& r) {
+#pragma clang fp contract(off)
+    const float* A = S.V + 3 * E.x;
+    const float* B = S.V + 3 * E.y;
+    const double a0 = A[0], a1 = A[1], a2 = A[2], b0 = B[0], b1 = B[1], b2 = B[2];
+    double ax, ay, az, bx, by, bz;
+    project_d(c, a0, a1, a2, ax, ay, az);
+    project_d(c, b0, b1, b2, bx, by, bz);
+    if (!(az > ZNEAR) && !(bz > ZNEAR)) return false;
+    r.sa = 0.0;
+    r.sb = 0.0;
+    if (!(az > ZNEAR)) {
+        r.sa = (ZNEAR - az) / (bz - az);
+        project_d(c, a0 + (b0 - a0) * r.sa, a1 + (b1 - a1) * r.sa, a2 + (b2 - a2) * r.sa, ax, ay, az);
+    }
+    if (!(bz > ZNEAR)) {
+        r.sb = (ZNEAR - bz) / (az - bz);
+        project_d(c, b0 + (a0 - b0) * r.sb, b1 + (a1 - b1) * r.sb, b2 + (a2 - b2) * r.sb, bx, by, bz);
+    }
+    r.ax = ax; r.ay = ay; r.bx = bx; r.by = by;
+    const double dx = bx - ax, dy = by - ay;
+    const double P[4] = {-dx, dx, -dy, dy};
+    const double Q[4] = {ax, (double)c.W - ax, ay, (double)c.H - ay};
+    double t0 = 0.0, t1 = 1.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (P[i] == 0.0) {
+            if (Q[i] < 0.0) return false;
+            continue;
+        }
+        const double q = Q[i] / P[i];
+        if (P[i] < 0.0) { if (q > t0) t0 = q; }
+        else { if (q < t1) t1 = q; }
+    }
+    if (!(t0 < t1)) return false;
+    r.t0 = t0;
+    r.t1 = t1;
+    return true;
+}
+
 __global__ void k_prim_weights(BwdParams p) {
 #pragma clang fp contract(off)
     const int v = blockIdx.y;
@@ -490,14 +543,10 @@ __global__ void k_prim_weights(BwdParams p) {
         const int4 E = S.edges[e];
         double lenv = 0.0;
         const bool cand = E.w < 0 || front_facing_d(S, E.z, c) || front_facing_d(S, E.w, c);
-        if (cand) {
-            double ax, ay, az, bx, by, bz;
-            project_d(c, S.V[3 * E.x], S.V[3 * E.x + 1], S.V[3 * E.x + 2], ax, ay, az);
-            project_d(c, S.V[3 * E.y], S.V[3 * E.y + 1], S.V[3 * E.y + 2], bx, by, bz);
-            if (az > ZNEAR && bz > ZNEAR) {
-                const double dx = bx - ax, dy = by - ay;
-                lenv = sqrt(dx * dx + dy * dy);
-            }
+        ScreenEdge se;
+        if (cand && screen_edge(c, S, E, se)) {
+            const double dx = se.bx - se.ax, dy = se.by - se.ay;
+            lenv = (se.t1 - se.t0) * sqrt(dx * dx + dy * dy);
         }
         p.pw[(size_t)v * p.ne + e] = lenv;
     }
@@ -534,11 +583,11 @@ __device__ __forceinline__ bool edge_setup(const BwdParams& p, long long ge, Edg
     // consecutive samples walk along the CDF (coherent side rays and accumulators)
     es.e = cdf_guided(p.pcdf + (size_t)es.v * (p.ne + 1), S.ne, p.pguide + ((size_t)es.v << p.pglog), p.pglog,
                       ((double)es.si + (double)u.x) / (double)c.ne);
-    es.t = u.y;
-    const int4 E = S.edges[es.e];
-    double ax, ay, az, bx, by, bz;
-    project_d(c, S.V[3 * E.x], S.V[3 * E.x + 1], S.V[3 * E.x + 2], ax, ay, az);
-    project_d(c, S.V[3 * E.y], S.V[3 * E.y + 1], S.V[3 * E.y + 2], bx, by, bz);
+    ScreenEdge se;
+    screen_edge(c, S, S.edges[es.e], se);     // true: only such edges have weight
+    // the point is uniform on the visible part [t0, t1] of the image segment
+    es.t = se.t0 + (double)u.y * (se.t1 - se.t0);
+    const double ax = se.ax, ay = se.ay, bx = se.bx, by = se.by;
     es.xs = (1.0 - es.t) * ax + es.t * bx;
     es.ys = (1.0 - es.t) * ay + es.t * by;
     es.px = (int)floor(es.xs);
@@ -672,7 +721,12 @@ __global__ void k_edge_grad(BwdParams p, const float* __restrict__ Ls, const uin
 }
 
 // d(x_s, y_s)/d(vertex) of the perspective projection, contracted with the
-// screen-space edge normal and the accumulated endpoint weights of (view, edge)
+// screen-space edge normal and the accumulated endpoint weights of (view, edge).
+// The image point is x = (1 - t) pi(a') + t pi(b') with the near-plane ends
+// a' = va + sa (vb - va), b' = vb + sb (va - vb); t, sa and sb are held fixed
+// (they only slide the point along the image line), so the Jacobians are taken
+// at a' and b' and passed to the vertices with the weights (1 - sa, sa) and
+// (sb, 1 - sb).
 __global__ void k_edge_finish(BwdParams p) {
 #pragma clang fp contract(off)
     const int v = blockIdx.y;
@@ -683,30 +737,40 @@ __global__ void k_edge_finish(BwdParams p) {
         const double w0 = acc[0], w1 = acc[1];
         if (w0 == 0.0 && w1 == 0.0) continue;
         const int4 E = S.edges[e];
-        double ax, ay, az, bx, by, bz;
-        project_d(c, S.V[3 * E.x], S.V[3 * E.x + 1], S.V[3 * E.x + 2], ax, ay, az);
-        project_d(c, S.V[3 * E.y], S.V[3 * E.y + 1], S.V[3 * E.y + 2], bx, by, bz);
-        const double dx = bx - ax, dy = by - ay;
+        ScreenEdge se;
+        if (!screen_edge(c, S, E, se)) continue;
+        const double dx = se.bx - se.ax, dy = se.by - se.ay;
         const double l = sqrt(dx * dx + dy * dy);
         const double nx = -dy / l, ny = dx / l;
+        const double pa[3] = {S.V[3 * E.x], S.V[3 * E.x + 1], S.V[3 * E.x + 2]};
+        const double pb[3] = {S.V[3 * E.y], S.V[3 * E.y + 1], S.V[3 * E.y + 2]};
+        double g[2][3];
         for (int end = 0; end < 2; ++end) {
-            const int vid = end == 0 ? E.x : E.y;
+            const double s0 = end == 0 ? se.sa : se.sb;
+            const double* P0 = end == 0 ? pa : pb;
+            const double* P1 = end == 0 ? pb : pa;
             const double wgt = end == 0 ? w0 : w1;
-            const double qx = (double)S.V[3 * vid] - c.deye[0], qy = (double)S.V[3 * vid + 1] - c.deye[1],
-                         qz = (double)S.V[3 * vid + 2] - c.deye[2];
+            const double qx = (P0[0] + (P1[0] - P0[0]) * s0) - c.deye[0];
+            const double qy = (P0[1] + (P1[1] - P0[1]) * s0) - c.deye[1];
+            const double qz = (P0[2] + (P1[2] - P0[2]) * s0) - c.deye[2];
             const double z = qx * c.df[0] + qy * c.df[1] + qz * c.df[2];
             const double aa = qx * c.dr[0] + qy * c.dr[1] + qz * c.dr[2];
             const double bb = qx * c.du[0] + qy * c.du[1] + qz * c.du[2];
             const double kx = (0.5 * c.W) / (c.dth * c.daspect) / (z * z);
             const double ky = -(0.5 * c.H) / c.dth / (z * z);
-            double gv[3];
             for (int k3 = 0; k3 < 3; ++k3) {
                 const double dsx = kx * (c.dr[k3] * z - aa * c.df[k3]);
                 const double dsy = ky * (c.du[k3] * z - bb * c.df[k3]);
-                gv[k3] = wgt * (dsx * nx + dsy * ny);
+                g[end][k3] = wgt * (dsx * nx + dsy * ny);
             }
-            atomic_add3(p.dV + 3 * (size_t)vid, V3{(float)gv[0], (float)gv[1], (float)gv[2]});
         }
+        double ga[3], gb[3];
+        for (int k3 = 0; k3 < 3; ++k3) {
+            ga[k3] = (1.0 - se.sa) * g[0][k3] + se.sb * g[1][k3];
+            gb[k3] = se.sa * g[0][k3] + (1.0 - se.sb) * g[1][k3];
+        }
+        atomic_add3(p.dV + 3 * (size_t)E.x, V3{(float)ga[0], (float)ga[1], (float)ga[2]});
+        atomic_add3(p.dV + 3 * (size_t)E.y, V3{(float)gb[0], (float)gb[1], (float)gb[2]});
     }
 }
 

@@ -121,3 +121,26 @@ def test_one_pixel_one_sample(B):
     pf, ef, rv, rm, oV, oM = _backward_case(B, sc, cams, 1, 2, d_img, 7)
     _say(f"  backward path flips {pf:.5f} edge flips {ef:.5f} relL2 dV {rv:.2e} dmat {rm:.2e}")
     assert pf == 0 and (np.abs(oV).max() == 0 or rv < GRAD_RTOL)
+
+
+def test_mesh_through_the_near_plane(B):
+    """A tetrahedron with one vertex behind the eye, an envmap and a point light:
+    the primary edges through that vertex are clipped at the near plane and to
+    the image on both sides (fp64 candidate weights), and the camera paths of the
+    forward see the part in front of the eye."""
+    _say("case tetrahedron through the near plane, light + env, B=2: forward and all gradient terms")
+    rng = np.random.default_rng(23)
+    V = np.array([[-0.6, -0.5, 0.0], [0.5, -0.6, -0.3], [0.0, 0.6, 0.2], [1.2, 0.4, 4.2]], np.float32)
+    F = np.array([[0, 1, 2], [0, 3, 1], [1, 3, 2], [2, 3, 0]], np.int32)
+    sc = S.Scene(V, F, S.random_materials(4, rng), S.hemisphere_lights(1, rng), S.gaussian_lobe_envmap(rng, 32, 16))
+    cams = [S.Camera((0.0, 0.0, 3.0), (0, 0, 0), (0, 1, 0), 45.0, 48, 40)]
+    fr, bad, checked, worst, img, ref = _forward_case(B, sc, cams, 4, 2)
+    _say(f"  forward flips {fr:.5f} bad {bad}/{checked} worst {worst:.2e}")
+    assert fr < FLIP_MAX and bad == 0 and (ref > 0).any()
+    d_img = np.random.default_rng(4).normal(size=(B.num_pixels(cams), 3)).astype(np.float32)
+    pf, ef, rv, rm, oV, oM = _backward_case(B, sc, cams, 4, 2, d_img, 2)
+    _say(f"  backward (primary edges) edge flips {ef:.5f} relL2 dV {rv:.2e}")
+    assert ef < FLIP_MAX and np.abs(oV[3]).max() > 0 and rv < GRAD_RTOL
+    pf, ef, rv, rm, oV, oM = _backward_case(B, sc, cams, 4, 2, d_img, 15)
+    _say(f"  backward (all terms) path flips {pf:.5f} edge flips {ef:.5f} relL2 dV {rv:.2e} dmat {rm:.2e}")
+    assert pf < FLIP_MAX and ef < FLIP_MAX and rv < GRAD_RTOL and rm < GRAD_RTOL

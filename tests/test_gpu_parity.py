@@ -168,7 +168,9 @@ def _backward_case(B, sc, cams, spp, bounces, d_img, flags, seed=0, edge_ratio=1
     g = B.GPUScene.from_scene(sc)
     o = O.OracleScene.from_scene(sc)
     npath = B.num_pixels(cams) * spp
-    ne = B.num_edge_samples(cams, spp, edge_ratio)
+    # primary edge samples, then (shadow-boundary term) as many per point light
+    nl = int(sc.lights.shape[0]) if flags & B.ST_EDGE_SHADOW else 0
+    ne = B.num_edge_samples(cams, spp, edge_ratio, nl)
     dt = torch.from_numpy(np.ascontiguousarray(d_img, np.float32)).cuda()
     ph = torch.zeros(npath, dtype=torch.int32, device="cuda")
     eh = torch.zeros(max(ne, 1), dtype=torch.int32, device="cuda")

@@ -551,6 +551,167 @@ def test_primary_edges_projected_area_derivative():
 
 
 # --------------------------------------------------------------------------
+# primary edge term on closed meshes: per-face albedo under a constant
+# environment, so that d(sum of the image)/dV is the derivative of the
+# albedo-weighted projected area of the front faces (silhouette edges carry the
+# object/background jump, interior edges the jump between face albedos), with
+# the mesh clipped at the near plane when it reaches behind the eye
+# --------------------------------------------------------------------------
+
+ZNEAR = 1e-3
+
+
+def _cam_frame(cam):
+    eye = np.array(cam.eye, np.float32).astype(float)
+    tg = np.array(cam.target, np.float32).astype(float)
+    up = np.array(cam.up, np.float32).astype(float)
+    f = (tg - eye) / np.linalg.norm(tg - eye)
+    r = np.cross(f, up / np.linalg.norm(up))
+    r /= np.linalg.norm(r)
+    u = np.cross(r, f)
+    th = math.tan(float(np.float32(cam.fov_y_deg)) * math.pi / 360)
+    return eye, f, r, u, th
+
+
+def _to_screen(cam, pts):
+    eye, f, r, u, th = _cam_frame(cam)
+    out = []
+    for v in pts:
+        p = v - eye
+        z = p @ f
+        out.append(((p @ r / (z * th * cam.width / cam.height) + 1) * 0.5 * cam.width,
+                    (1 - p @ u / (z * th)) * 0.5 * cam.height))
+    return out
+
+
+def _clip_near(poly, cam):
+    """Sutherland-Hodgman: the part of a 3-D polygon with depth > ZNEAR."""
+    eye, f = _cam_frame(cam)[:2]
+    d = [(v - eye) @ f - ZNEAR for v in poly]
+    out = []
+    for i in range(len(poly)):
+        j = (i + 1) % len(poly)
+        if d[i] > 0:
+            out.append(poly[i])
+        if (d[i] > 0) != (d[j] > 0):
+            out.append(poly[i] + (poly[j] - poly[i]) * (d[i] / (d[i] - d[j])))
+    return out
+
+
+def _clip_image(poly, W, H):
+    """Sutherland-Hodgman against the image rectangle [0, W] x [0, H]."""
+    for k, lim, lower in ((0, 0.0, True), (0, float(W), False), (1, 0.0, True), (1, float(H), False)):
+        out = []
+        for i in range(len(poly)):
+            a, b = poly[i], poly[(i + 1) % len(poly)]
+            ia = a[k] >= lim if lower else a[k] <= lim
+            ib = b[k] >= lim if lower else b[k] <= lim
+            if ia:
+                out.append(a)
+            if ia != ib:
+                t = (lim - a[k]) / (b[k] - a[k])
+                out.append((a[0] + t * (b[0] - a[0]), a[1] + t * (b[1] - a[1])))
+        poly = out
+        if not poly:
+            return []
+    return poly
+
+
+def _shoelace(poly):
+    if len(poly) < 3:
+        return 0.0
+    return abs(sum(poly[i][0] * poly[(i + 1) % len(poly)][1] - poly[(i + 1) % len(poly)][0] * poly[i][1]
+                   for i in range(len(poly)))) / 2
+
+
+def _front_face_weighted_area(cam, V, F, w):
+    """sum over faces facing the eye of w_f x (pixel area of the face's visible
+    image).  From outside a convex body the front faces are exactly the visible
+    surface and their images do not overlap; the visible image of a face is its
+    part in front of the near plane, projected, inside the image."""
+    eye = _cam_frame(cam)[0]
+    tot = 0.0
+    for fi, (a, b, c) in enumerate(F):
+        if np.cross(V[b] - V[a], V[c] - V[a]) @ (eye - V[a]) <= 0:
+            continue
+        poly = _clip_near([V[a], V[b], V[c]], cam)
+        if len(poly) >= 3:
+            tot += w[fi] * _shoelace(_clip_image(_to_screen(cam, poly), cam.width, cam.height))
+    return tot
+
+
+def _outward(V, F):
+    c = V.mean(0)
+    F = F.copy()
+    for i, (a, b, cc) in enumerate(F):
+        if np.cross(V[b] - V[a], V[cc] - V[a]) @ (V[a] - c) < 0:
+            F[i] = (a, cc, b)
+    return F
+
+
+def _primary_vs_closed_form(V, F, kd, cam, seeds, spp=16, ratio=4.0):
+    mat = np.zeros((F.shape[0], 7), np.float32)
+    mat[:, :3] = kd
+    mat[:, 6] = 0.3
+    sc = O.OracleScene(V, F, mat, None, np.ones((8, 16, 3), np.float32))
+    d_img = np.ones((cam.width * cam.height, 3), np.float32)
+    got = np.mean([sc.backward([cam], spp, 1, d_img, seed=s, flags=O.FLAG_PRIMARY, edge_ratio=ratio)[0]
+                   for s in seeds], axis=0)
+    # Lambertian kd, constant environment L0 = 1, one bounce, convex: every
+    # visible point has expected radiance kd (per channel); d_image = 1 on
+    # every channel sums the three albedos
+    w = kd.astype(float).sum(axis=1)
+    Vd = V.astype(float)
+    ref = np.zeros_like(Vd)
+    h = 1e-6
+    for i in range(V.shape[0]):
+        for k in range(3):
+            Vp, Vm = Vd.copy(), Vd.copy()
+            Vp[i, k] += h
+            Vm[i, k] -= h
+            ref[i, k] = (_front_face_weighted_area(cam, Vp, F, w) - _front_face_weighted_area(cam, Vm, F, w)) / (2 * h)
+    return got, ref
+
+
+def test_primary_edges_closed_convex_mesh_per_face_albedo():
+    """Closed convex hull of 14 points, 24 faces with random albedos: exercises
+    the candidate rule (an edge is sampled when one of its faces faces the eye:
+    silhouettes and front interior edges, not back edges).  Silhouette-only
+    candidates or a reversed facing test miss the interior jumps (12-13 %
+    off); the estimator is within 1 % per seed."""
+    from scipy.spatial import ConvexHull
+    rng = np.random.default_rng(3)
+    P = rng.normal(size=(14, 3))
+    P = P / np.linalg.norm(P, axis=1, keepdims=True) * np.array([0.9, 0.7, 0.8])
+    V = P.astype(np.float32)
+    F = _outward(V.astype(float), ConvexHull(P).simplices.astype(np.int32))
+    assert F.shape[0] == 24
+    kd = np.random.default_rng(4).uniform(0.1, 0.9, size=(F.shape[0], 3)).astype(np.float32)
+    cam = S.Camera((0.4, 0.5, 3.0), (0, 0, 0), (0, 1, 0), 45.0, 64, 64)
+    got, ref = _primary_vs_closed_form(V, F, kd, cam, seeds=(0, 1, 2))
+    rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    assert rel < 0.03, rel
+
+
+def test_primary_edges_near_plane_clip():
+    """A tetrahedron with one vertex behind the eye: its three edges through that
+    vertex cross the near plane and are clipped there, then to the image; their
+    visible images carry both the silhouette and the interior jumps, and the
+    vertex behind the eye still moves them (dropping such edges is 69 % off)."""
+    V = np.array([[-0.6, -0.5, 0.0], [0.5, -0.6, -0.3], [0.0, 0.6, 0.2], [1.2, 0.4, 4.2]], np.float32)
+    F = _outward(V.astype(float), np.array([[0, 2, 1], [0, 1, 3], [1, 2, 3], [2, 0, 3]], np.int32))
+    kd = np.array([[0.8, 0.8, 0.8], [0.3, 0.5, 0.7], [0.6, 0.2, 0.4], [0.9, 0.6, 0.1]], np.float32)
+    cam = S.Camera((0.0, 0.0, 3.0), (0, 0, 0), (0, 1, 0), 45.0, 48, 48)
+    eye, fwd = _cam_frame(cam)[:2]
+    assert (V[3] - eye) @ fwd < 0 and all((V[i] - eye) @ fwd > 1 for i in range(3))
+    got, ref = _primary_vs_closed_form(V, F, kd, cam, seeds=(0, 1, 2))
+    rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    assert rel < 0.03, rel
+    assert np.linalg.norm(ref[3]) > 0.1 * np.linalg.norm(ref)
+    assert np.linalg.norm(got[3] - ref[3]) < 0.05 * np.linalg.norm(ref[3])
+
+
+# --------------------------------------------------------------------------
 # secondary edge term: closed-form projected solid angle of an occluder
 # --------------------------------------------------------------------------
 
@@ -592,6 +753,54 @@ def test_secondary_edges_polygon_irradiance_derivative(hierarchy):
     rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
     assert rel < 0.05, (rel, got, ref)
     assert np.abs(dV[:3]).max() == 0.0
+
+
+@pytest.mark.parametrize("hierarchy", [False, True])
+def test_secondary_edges_crease_between_two_albedos(hierarchy):
+    """Creases and material boundaries (the interior option): a valley of two
+    Lambertian faces of different albedo above a shading point, under a constant
+    environment L0 = 1, convex as seen from below, so each face returns kd L0 in
+    expectation.  The reflected radiance is
+      I = kd_p/pi (pi - sum_faces (1 - kd_f) PSA_f),
+    PSA the projected solid angle (Lambert's polygon formula).  The shared edge is
+    no silhouette from the point, so its term (jump (kd_A - kd_B) L0) is sampled
+    only with the option: with it the estimator meets the closed form, without it
+    it is 32 % off."""
+    wall = np.array([[-0.35, 0.55, -0.3], [0.3, 0.6, 0.35], [-0.5, 0.95, 0.4], [0.45, 0.9, -0.45]], np.float32)
+    floor = np.array([[-1e-3, 0, -1e-3], [1e-3, 0, -1e-3], [0, 0, 1e-3]], np.float32)
+    V = np.concatenate([floor, wall])
+    F = np.array([[0, 2, 1], [3, 4, 5], [3, 6, 4]], np.int32)
+    kdA, kdB = np.array([0.9, 0.6, 0.2]), np.array([0.1, 0.3, 0.8])
+    mat = np.zeros((3, 7), np.float32)
+    mat[0, :3], mat[1, :3], mat[2, :3] = 1.0, kdA, kdB
+    mat[:, 6] = 0.3
+    sc = O.OracleScene(V, F, mat, None, np.ones((8, 16, 3), np.float32))
+    p, n = np.array([0.0, 0.0, 0.0]), np.array([0.0, 1.0, 0.0])
+    wo = np.array([0.3, 1.0, 0.2]) / np.linalg.norm([0.3, 1.0, 0.2])
+    kdA32, kdB32 = mat[1, :3].astype(float), mat[2, :3].astype(float)
+
+    def irradiance(W):
+        A, B = W[[3, 4, 5]], W[[3, 6, 4]]
+        return sum(np.pi - (1 - kdA32[c]) * _psa(p, n, A) - (1 - kdB32[c]) * _psa(p, n, B) for c in range(3)) / (3 * np.pi)
+
+    Vd = V.astype(float)
+    ref = np.zeros_like(Vd)
+    h = 1e-6
+    for i in range(3, 7):
+        for k in range(3):
+            Vp, Vm = Vd.copy(), Vd.copy()
+            Vp[i, k] += h
+            Vm[i, k] -= h
+            ref[i, k] = (irradiance(Vp) - irradiance(Vm)) / (2 * h)
+    with_int = sc.secondary_term(p, n, wo, face=0, budget=1, nsamples=400000, seed=2, hierarchy=hierarchy,
+                                 interior=True)
+    without = sc.secondary_term(p, n, wo, face=0, budget=1, nsamples=100000, seed=2, hierarchy=hierarchy,
+                                interior=False)
+    rel = np.linalg.norm(with_int - ref) / np.linalg.norm(ref)
+    rel_without = np.linalg.norm(without - ref) / np.linalg.norm(ref)
+    assert rel < 0.03, rel
+    assert rel_without > 0.2, rel_without
+    assert np.abs(with_int[:3]).max() == 0.0
 
 
 # --------------------------------------------------------------------------
