@@ -23,6 +23,14 @@
  *    them afterwards.  The library owns the BVH, CDFs, queues and workspace until
  *    st_scene_destroy.  Render calls may grow the library workspace (the first
  *    call with a larger shape allocates); identical later calls allocate nothing.
+ *  - Graph capture: st_render, st_render_batch and st_render_backward may be
+ *    captured (hipStreamBeginCapture / torch.cuda.graph) once an uncaptured call
+ *    with the same shapes has sized the workspace; a call that would allocate
+ *    under capture fails with ST_ERR_INVALID_ARG.  Memory a captured graph uses
+ *    stays valid until st_scene_destroy: a workspace that later grows is retired,
+ *    not freed, as are the material arrays st_scene_set_mesh_colors replaces.
+ *    Destroying a scene invalidates every graph that uses it.  Calls on one scene
+ *    (eager or replayed) must be ordered on one stream: they share its workspace.
  *  - Outputs are overwritten, never accumulated.
  *  - Return value 0 on success, a negative ST_ERR_* code otherwise; the message
  *    of the last failure on the calling thread is returned by st_last_error().
@@ -85,6 +93,11 @@ typedef struct {
     float* debug_sample_radiance;    /* device, optional (forward): per path sample rgb, same index */
     const uint8_t* path_mask;        /* device, optional (backward): 0 skips a path sample */
     const uint8_t* edge_mask;        /* device, optional (backward): 0 skips an edge sample (same index) */
+    int64_t max_workspace_bytes;     /* 0: no limit.  Otherwise a call whose library workspace (radiance
+                                        buffer, wavefront queues, traversal spill stack; backward: edge
+                                        tables, secondary-edge jobs, primary-edge side paths) would exceed
+                                        it fails with ST_ERR_OOM before launching any kernel; a forward
+                                        keeps no hit records when only they would exceed it */
 } st_render_opts;
 
 /* Default options: interior, primary and secondary edge terms and the
@@ -106,7 +119,10 @@ int st_scene_create(const float* V, int32_t nv, const int32_t* F, int32_t nf, co
                     const float* lights, int32_t nl, const float* envmap, int32_t he, int32_t we,
                     uint32_t scene_id, hipStream_t s, st_scene** out);
 
-/* Replace vertex positions (float [nv,3]) and/or materials (float [ntex,7], the
+/* One gradient-descent step's new parameters (Sec. 3.2 "Vertex optimization":
+ * the vertex positions x move every step; Sec. 3.3 "Material Optimization":
+ * the material texels likewise), with the topology of the scene kept.  Replace
+ * vertex positions (float [nv,3]) and/or materials (float [ntex,7], the
  * current material rows: one per face, or the mesh-colour texels); either may be
  * NULL.  Rebuilds the LBVH and edge CDF on the stream; allocates nothing. */
 int st_scene_update(st_scene* scene, const float* V, const float* face_materials, hipStream_t s);
@@ -186,12 +202,15 @@ int st_render(st_scene* scene, const st_camera* cams, int32_t ncam, int32_t spp,
  * sample, the face hit at every bounce and the occlusion of every shadow ray
  * (4 (2 bounces + 1) bytes per path sample, scene-owned, at most 16 GiB; scenes
  * with more than 30 point lights keep none).  When the backward's (cams, spp,
- * bounces, seed) equal those of the last such render and the scene has not
- * changed since (st_scene_update, st_scene_set_mesh_colors,
- * st_scene_set_env_sampler), the replay takes hits and occlusions from the
+ * bounces, seed) equal those of the last such render executed on the stream
+ * (eager or replayed from a graph) and the scene has not changed since
+ * (st_scene_update, st_scene_set_mesh_colors, st_scene_set_env_sampler,
+ * st_scene_set_bsdf_sampler), the replay takes hits and occlusions from the
  * records (the hit distance from the recorded face's plane) instead of tracing
- * the main path again; ST_BACKWARD_RETRACE in opts->flags disables this.  The
- * result is the same estimator either way.
+ * the main path again; the render writes the key of its pass into device memory
+ * beside the records and the adjoint compares it there, so a graph replay in
+ * between is seen.  ST_BACKWARD_RETRACE in opts->flags disables the records.
+ * The result is the same estimator either way.
  *   d_image: device float, same layout as st_render's out.
  *   out_dV: device float [nv,3]; out_dmat: device float [ntex,7] (ntex = nf unless the scene uses
  *   mesh colours, st_scene_set_mesh_colors); both overwritten. */
@@ -199,8 +218,12 @@ int st_render_backward(st_scene* scene, const st_camera* cams, int32_t ncam, int
                        uint32_t seed, const st_render_opts* opts, const float* d_image, float* out_dV,
                        float* out_dmat, hipStream_t s);
 
-/* Several independent scenes in one pass: camera i renders scene cam_scene[i]
- * (host int32 [ncam]).  Output layout as st_render over the concatenated views. */
+/* Several independent scenes in one pass (Sec. 4.1 "Reconstructing Simulated
+ * Objects" renders 32 calibrated views of each object per step; this renders
+ * the views of several objects together): camera i renders scene cam_scene[i]
+ * (host int32 [ncam]).  Each camera's random streams are numbered by its index
+ * among the cameras of its own scene, so the result equals per-scene st_render
+ * calls bit for bit.  Output layout as st_render over the concatenated views. */
 int st_render_batch(st_scene* const* scenes, int32_t nscenes, const st_camera* cams, const int32_t* cam_scene,
                     int32_t ncam, int32_t spp, int32_t bounces, uint32_t seed, const st_render_opts* opts,
                     float* out, hipStream_t s);
@@ -218,8 +241,13 @@ int st_autotune(st_scene* const* scenes, int32_t nscenes, const st_camera* cams,
                 int32_t ncam, int32_t spp, int32_t bounces, const char* cache_path, int64_t* out_queue_capacity,
                 int32_t* out_trace_grid, hipStream_t s);
 
-/* Wait for stream s and report device-side faults recorded by earlier calls on
- * this scene (traversal stack overflow): ST_ERR_DEVICE_FAULT, and clears them. */
+/* Wait for stream s and report what kernels of earlier calls on this scene
+ * recorded in its device error word, then clear it: ST_ERR_QUEUE_OVERFLOW when a
+ * wavefront queue reservation went past its capacity (the entries are dropped,
+ * not written; the queues are sized so that this does not happen),
+ * ST_ERR_DEVICE_FAULT for a traversal stack overflow or iteration cap, or a
+ * non-finite value in a rendered image or in dV / dmat (checked after every
+ * term of a backward), or several of these.  The message lists the bits. */
 int st_check_errors(st_scene* scene, hipStream_t s);
 
 /* Introspection for tests (device outputs, caller-allocated):

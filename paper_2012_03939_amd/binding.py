@@ -48,7 +48,7 @@ class StOpts(ctypes.Structure):
     _fields_ = [("flags", ctypes.c_uint32), ("edge_spp_ratio", ctypes.c_float), ("queue_capacity", ctypes.c_int64),
                 ("debug_decision_hash", ctypes.c_void_p), ("debug_edge_hash", ctypes.c_void_p),
                 ("debug_sample_radiance", ctypes.c_void_p), ("path_mask", ctypes.c_void_p),
-                ("edge_mask", ctypes.c_void_p)]
+                ("edge_mask", ctypes.c_void_p), ("max_workspace_bytes", ctypes.c_int64)]
 
 
 class StError(RuntimeError):
@@ -139,7 +139,7 @@ def num_edge_samples(cams, spp: int, ratio: float, n_shadow_lights: int = 0) -> 
 
 
 def make_opts(flags=ST_ALL_GRADS, edge_ratio=1.0, queue_capacity=0, dbg_hash=None, dbg_edge_hash=None,
-              dbg_radiance=None, path_mask=None, edge_mask=None) -> StOpts:
+              dbg_radiance=None, path_mask=None, edge_mask=None, max_workspace_bytes=0) -> StOpts:
     o = StOpts()
     o.flags = flags
     o.edge_spp_ratio = edge_ratio
@@ -149,6 +149,7 @@ def make_opts(flags=ST_ALL_GRADS, edge_ratio=1.0, queue_capacity=0, dbg_hash=Non
     o.debug_sample_radiance = _ptr(dbg_radiance)
     o.path_mask = _ptr(path_mask)
     o.edge_mask = _ptr(edge_mask)
+    o.max_workspace_bytes = int(max_workspace_bytes)
     return o
 
 
@@ -250,18 +251,19 @@ class GPUScene:
         self.version += 1
 
     def render(self, cams, spp: int, bounces: int, seed: int = 0, out=None, flags: int = 0, queue_capacity: int = 0,
-               debug_hash=None, debug_radiance=None):
+               debug_hash=None, debug_radiance=None, max_workspace_bytes: int = 0):
         import torch
         cam = make_cameras(cams)
         if out is None:
             out = torch.empty((num_pixels(cams), 3), dtype=torch.float32, device="cuda")
-        o = make_opts(flags=flags, queue_capacity=queue_capacity, dbg_hash=debug_hash, dbg_radiance=debug_radiance)
+        o = make_opts(flags=flags, queue_capacity=queue_capacity, dbg_hash=debug_hash, dbg_radiance=debug_radiance,
+                      max_workspace_bytes=max_workspace_bytes)
         _check(load().st_render(self.h, cam, len(cams), spp, bounces, seed, ctypes.byref(o), _ptr(out), _stream()))
         return out
 
     def backward(self, cams, spp: int, bounces: int, d_image, seed: int = 0, flags: int = ST_ALL_GRADS,
                  edge_ratio: float = 1.0, dV=None, dmat=None, path_mask=None, edge_mask=None, debug_hash=None,
-                 debug_edge_hash=None):
+                 debug_edge_hash=None, max_workspace_bytes: int = 0):
         import torch
         cam = make_cameras(cams)
         if dV is None:
@@ -269,7 +271,7 @@ class GPUScene:
         if dmat is None:
             dmat = torch.empty((self.ntex, 7), dtype=torch.float32, device="cuda")
         o = make_opts(flags=flags, edge_ratio=edge_ratio, dbg_hash=debug_hash, dbg_edge_hash=debug_edge_hash,
-                      path_mask=path_mask, edge_mask=edge_mask)
+                      path_mask=path_mask, edge_mask=edge_mask, max_workspace_bytes=max_workspace_bytes)
         d = d_image.contiguous()
         _check(load().st_render_backward(self.h, cam, len(cams), spp, bounces, seed, ctypes.byref(o), _ptr(d),
                                          _ptr(dV), _ptr(dmat), _stream()))

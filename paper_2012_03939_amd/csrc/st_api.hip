@@ -33,21 +33,42 @@ int fail(int code, const std::string& msg) {
 // allocation may happen then
 thread_local bool g_capturing = false;
 
+// A grow-only device workspace.  Once a buffer has been handed to kernels
+// recorded into a graph (stream capture), its memory must outlive that graph,
+// which the library cannot see: a later growth then retires the allocation
+// (freed with the scene) instead of freeing it.
 struct GrowBuf {
     void* p = nullptr;
     size_t cap = 0;
+    bool captured = false;            // p was used by a captured launch
+    std::vector<void*> retired;       // earlier allocations captured graphs may still use
     int ensure(size_t bytes) {
-        if (bytes <= cap && p) return ST_OK;
+        if (bytes <= cap && p) {
+            if (g_capturing) captured = true;
+            return ST_OK;
+        }
         if (g_capturing)
             return fail(ST_ERR_INVALID_ARG, "workspace would grow during graph capture: make one uncaptured call "
                                             "with the same shapes first");
-        if (p) { hipFree(p); p = nullptr; cap = 0; }
+        if (p) {
+            if (captured) retired.push_back(p);
+            else hipFree(p);
+            p = nullptr;
+            cap = 0;
+            captured = false;
+        }
         const size_t want = std::max<size_t>(bytes + bytes / 8, 256);
         if (hipMalloc(&p, want) != hipSuccess) { p = nullptr; return fail(ST_ERR_OOM, "device allocation failed"); }
         cap = want;
         return ST_OK;
     }
-    void release() { if (p) hipFree(p); p = nullptr; cap = 0; }
+    void release() {
+        if (p) hipFree(p);
+        for (void* q : retired) hipFree(q);
+        retired.clear();
+        p = nullptr;
+        cap = 0;
+    }
 };
 
 // carve aligned sub-arrays out of one allocation
@@ -145,12 +166,12 @@ struct st_scene {
     std::vector<CamTable> tables;
     long long tuned_cap = 0;           // autotuned wavefront chunk size (0: none)
     int tuned_grid = 0;                // autotuned traversal grid (0: none)
-    // hit records of the last single-scene wavefront render, for its backward
+    // hit records of the last single-scene wavefront render, for its backward;
+    // which forward they belong to is the device word d.rec_key
     GrowBuf recbuf;
     uint64_t version = 0;              // bumped by every change of geometry, materials or sampler
     uint64_t etree_version = ~0ull;    // scene version the edge importance tree was built for
-    bool rec_valid = false;
-    uint64_t rec_key = 0;
+    std::vector<void*> retired;        // replaced material arrays (captured graphs may still read them)
 };
 
 namespace {
@@ -246,32 +267,56 @@ int setup_cams(st_scene* owner, st_scene* const* scenes, int nscenes, const st_c
     return ST_OK;
 }
 
-// identity of a forward pass's main paths: cameras, spp, bounces, seed and the scene state
-uint64_t record_key(const st_scene* sc, const st_camera* cams, int ncam, int spp, int bounces, uint32_t seed) {
+// identity of a forward pass's main paths: cameras, spp, bounces, seed, the
+// scene state and the record buffer written (a graph captured before the
+// buffer grew writes its records into the retired one); never 0, which marks
+// "no records"
+uint64_t record_key(const st_scene* sc, const st_camera* cams, int ncam, int spp, int bounces, uint32_t seed,
+                    const void* buf) {
     uint64_t h = 1469598103934665603ull;
     auto mix = [&h](const void* src, size_t n) {
         const unsigned char* b = (const unsigned char*)src;
         for (size_t i = 0; i < n; ++i) { h ^= b[i]; h *= 1099511628211ull; }
     };
     mix(cams, sizeof(st_camera) * (size_t)ncam);
-    const long long w[5] = {ncam, spp, bounces, (long long)seed, (long long)sc->version};
+    const long long w[6] = {ncam, spp, bounces, (long long)seed, (long long)sc->version, (long long)(uintptr_t)buf};
     mix(w, sizeof(w));
-    return h;
+    return h | 1ull;
 }
 
 constexpr size_t REC_MAX_BYTES = 16ull << 30;
 
+
+// wavefront chunk capacity actually used for a requested one (shadow entries
+// are numbered l * n + i in a 32-bit index)
+int queue_cap(long long cap, int nent) {
+    return (int)std::min<long long>(cap, (0x7FFFFFFFll / std::max(nent, 1)) & ~1ll);
+}
+
+// bytes of the queue workspace of a chunk of cap paths with nent shadow entries each
+size_t queue_bytes(int cap, int nent) {
+    const size_t per = 256;
+    const size_t words = 2 * QNCOL + 2 + 3 + 4 + 8 * (size_t)std::max(nent, 1);
+    return (size_t)cap * 4 * words + (size_t)cap * std::max(nent, 1) + (words + 10) * per + 64 * 4 +
+           FETCH_INTS * sizeof(int);
+}
+
+constexpr size_t SPILL_BYTES = (size_t)SPILL_STACK * TRACE_GRID * TRACE_BLOCK * sizeof(uint32_t);
+
+int over_budget(const st_render_opts& o, size_t need) {
+    if (o.max_workspace_bytes > 0 && need > (size_t)o.max_workspace_bytes)
+        return fail(ST_ERR_OOM, "the call needs " + std::to_string(need) + " bytes of library workspace, more than "
+                                "max_workspace_bytes = " + std::to_string((long long)o.max_workspace_bytes));
+    return ST_OK;
+}
+
 int ensure_spill(st_scene* sc) {
-    return sc->spillbuf.ensure((size_t)SPILL_STACK * TRACE_GRID * TRACE_BLOCK * sizeof(uint32_t));
+    return sc->spillbuf.ensure(SPILL_BYTES);
 }
 
 int make_queues(st_scene* sc, int cap, int nent, float* L, Queues& q) {
-    // shadow entries are numbered l * n + i in a 32-bit index
-    cap = (int)std::min<long long>(cap, (0x7FFFFFFFll / std::max(nent, 1)) & ~1ll);
-    const size_t per = 256;
-    const size_t words = 2 * QNCOL + 2 + 3 + 4 + 8 * (size_t)std::max(nent, 1);
-    const size_t bytes = (size_t)cap * 4 * words + (size_t)cap * std::max(nent, 1) + (words + 10) * per + 64 * 4 +
-                         FETCH_INTS * sizeof(int);
+    cap = queue_cap(cap, nent);
+    const size_t bytes = queue_bytes(cap, nent);
     int rc = sc->qbuf.ensure(bytes);
     if (rc) return rc;
     Carver c{(char*)sc->qbuf.p};
@@ -312,6 +357,15 @@ int render_impl(st_scene* owner, st_scene* const* scenes, int nscenes, const st_
         nent = std::max(nent, scenes[i]->d.nl + (scenes[i]->d.has_env ? 1 : 0));
         has_env_any |= scenes[i]->d.has_env ? 1 : 0;
     }
+    // workspace of the call, checked against the caller's cap before any kernel
+    const bool mega = (o.flags & ST_FORWARD_MEGAKERNEL) != 0;
+    long long cap = o.queue_capacity > 0 ? o.queue_capacity : (owner->tuned_cap > 0 ? owner->tuned_cap : (1ll << 22));
+    cap = std::min<long long>(cap, std::max<long long>(cs.total_paths, 1));
+    cap = std::min<long long>(cap, 1ll << 28);
+    const size_t need = (size_t)cs.total_paths * 3 * sizeof(float) + SPILL_BYTES +
+                        (mega ? 0 : queue_bytes(queue_cap(cap, nent), nent));
+    rc = over_budget(o, need);
+    if (rc) return rc;
     rc = owner->Lbuf.ensure((size_t)cs.total_paths * 3 * sizeof(float));
     if (rc) return rc;
     rc = ensure_spill(owner);
@@ -333,30 +387,33 @@ int render_impl(st_scene* owner, st_scene* const* scenes, int nscenes, const st_
     p.rec_n = 0;
     // hit records for the backward of a single-scene wavefront render
     const size_t rec_bytes = (size_t)(2 * bounces + 1) * (size_t)cs.total_paths * sizeof(int);
-    const bool want_rec = nscenes == 1 && !(o.flags & ST_FORWARD_MEGAKERNEL) && scenes[0]->d.nl <= 30 &&
-                          rec_bytes <= REC_MAX_BYTES;
-    if (nscenes == 1) owner->rec_valid = false;
-    if (want_rec && !(g_capturing && owner->recbuf.cap < rec_bytes) && owner->recbuf.ensure(rec_bytes) == ST_OK) {
-        p.rec_face = (int*)owner->recbuf.p;
-        p.rec_occ = (uint32_t*)(p.rec_face + (size_t)(bounces + 1) * cs.total_paths);
-        p.rec_n = cs.total_paths;
-        owner->rec_valid = true;
-        owner->rec_key = record_key(owner, cams, ncam, spp, bounces, seed);
+    // (an optimisation of the backward: left out rather than exceed the cap)
+    const bool want_rec = nscenes == 1 && !mega && scenes[0]->d.nl <= 30 && rec_bytes <= REC_MAX_BYTES &&
+                          !(o.max_workspace_bytes > 0 && need + rec_bytes > (size_t)o.max_workspace_bytes);
+    uint64_t rec_key = 0;
+    if (nscenes == 1) {
+        // the records are rewritten (or left stale) from here on: no backward may
+        // take them until the key of this pass is written after the forward
+        launch_put_u64(owner->d.rec_key, 0ull, s);
+        if (want_rec && !(g_capturing && owner->recbuf.cap < rec_bytes) && owner->recbuf.ensure(rec_bytes) == ST_OK) {
+            p.rec_face = (int*)owner->recbuf.p;
+            p.rec_occ = (uint32_t*)(p.rec_face + (size_t)(bounces + 1) * cs.total_paths);
+            p.rec_n = cs.total_paths;
+            rec_key = record_key(owner, cams, ncam, spp, bounces, seed, owner->recbuf.p);
+        }
     }
     float* L = (float*)owner->Lbuf.p;
-    if (o.flags & ST_FORWARD_MEGAKERNEL) {
+    if (mega) {
         launch_forward_mega(p, L, cs.total_paths, (uint32_t*)owner->spillbuf.p, TRACE_GRID, s);
     } else {
-        long long cap = o.queue_capacity > 0 ? o.queue_capacity : (owner->tuned_cap > 0 ? owner->tuned_cap : (1ll << 22));
-        cap = std::min<long long>(cap, std::max<long long>(cs.total_paths, 1));
-        cap = std::min<long long>(cap, 1ll << 28);
         Queues q;
         rc = make_queues(owner, (int)cap, nent, L, q);
         if (rc) return rc;
         q.grid = owner->tuned_grid;
         launch_forward_wavefront(p, q, cs.total_paths, has_env_any, nent, s);
     }
-    launch_film(cs.cams, cs.pixoff, ncam, spp, L, cs.total_pix, out, s);
+    if (rec_key) launch_put_u64(owner->d.rec_key, rec_key, s);
+    launch_film(cs.cams, cs.pixoff, ncam, spp, L, cs.total_pix, out, owner->d.err, s);
     if (o.debug_sample_radiance) launch_sample_radiance(p, L, cs.total_paths, o.debug_sample_radiance, s);
     HIPCHK(hipGetLastError());
     return ST_OK;
@@ -499,6 +556,7 @@ int st_scene_create(const float* V, int32_t nv, const int32_t* F, int32_t nf, co
     A(dalloc(&d.etotal_d, 1));
     A(dalloc(&d.etotal_f, 1));
     A(dalloc(&d.err, 1));
+    A(dalloc(&d.rec_key, 1));
     A(dalloc(&d.work, 3 * WORK_SLOTS));
     A(dalloc(&d.dscene, 1));
     if (he > 0) {
@@ -526,6 +584,7 @@ int st_scene_create(const float* V, int32_t nv, const int32_t* F, int32_t nf, co
     HIPCHK2(hipMemcpyAsync(d.fe, fe.data(), sizeof(int32_t) * fe.size(), hipMemcpyHostToDevice, s));
     HIPCHK2(hipMemcpyAsync(d.vf_idx, vf_idx.data(), sizeof(int32_t) * vf_idx.size(), hipMemcpyHostToDevice, s));
     launch_fill_u32(d.err, 1, 0u, s);
+    launch_put_u64(d.rec_key, 0ull, s);
     launch_fill_u32((uint32_t*)d.work, 6 * WORK_SLOTS, 0u, s);
     std::vector<double> dom(std::max(he, 1));
     std::vector<float> rowcos(2 * (he + 1));
@@ -579,7 +638,7 @@ int st_scene_update(st_scene* sc, const float* V, const float* mat, hipStream_t 
     if (V) HIPCHK(hipMemcpyAsync(sc->d.V, V, sizeof(float) * 3 * sc->d.nv, hipMemcpyDeviceToDevice, s));
     if (mat) HIPCHK(hipMemcpyAsync(sc->d.mat, mat, sizeof(float) * 7 * (size_t)sc->d.ntex, hipMemcpyDeviceToDevice, s));
     if (V) launch_scene_geometry(sc->d, s);
-    if (V || mat) { ++sc->version; sc->rec_valid = false; }
+    if (V || mat) ++sc->version;
     HIPCHK(hipGetLastError());
     return ST_OK;
 }
@@ -610,8 +669,8 @@ int st_scene_set_mesh_colors(st_scene* sc, int32_t r, const float* texels, hipSt
     }
     HIPCHK(hipMemcpyAsync(mat, texels, sizeof(float) * 7 * (size_t)ntex, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
-    hipFree(d.mat);
-    hipFree(d.macc);
+    sc->retired.push_back(d.mat);
+    sc->retired.push_back(d.macc);
     d.mat = mat;
     d.macc = macc;
     d.tex_res = r;
@@ -619,7 +678,6 @@ int st_scene_set_mesh_colors(st_scene* sc, int32_t r, const float* texels, hipSt
     d.hscene.mat = mat;
     d.hscene.tex_res = r;
     ++sc->version;
-    sc->rec_valid = false;
     HIPCHK(hipMemcpyAsync(d.dscene, &d.hscene, sizeof(DevScene), hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
     return ST_OK;
@@ -689,7 +747,6 @@ int st_scene_set_env_sampler(st_scene* sc, int32_t method, hipStream_t s) {
     d.hscene.ealias = d.ealias;
     d.hscene.env_alias = method == ST_ENV_SAMPLER_ALIAS ? 1 : 0;
     ++sc->version;
-    sc->rec_valid = false;
     HIPCHK(hipMemcpyAsync(d.dscene, &d.hscene, sizeof(DevScene), hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
     return ST_OK;
@@ -757,7 +814,6 @@ int st_scene_set_bsdf_sampler(st_scene* sc, int32_t method, hipStream_t s) {
     SceneDev& d = sc->d;
     d.hscene.vndf = method == ST_BSDF_SAMPLER_VNDF ? 1 : 0;
     ++sc->version;
-    sc->rec_valid = false;
     HIPCHK(hipMemcpyAsync(d.dscene, &d.hscene, sizeof(DevScene), hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
     return ST_OK;
@@ -822,8 +878,6 @@ int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_
     st_scene* list[1] = {sc};
     rc = setup_cams(sc, list, 1, cams, nullptr, ncam, spp, (double)o.edge_spp_ratio, s, cs);
     if (rc) return rc;
-    rc = ensure_spill(sc);
-    if (rc) return rc;
     const int ne = sc->d.ne;
     const int pglog = guide_log2(ne);
     const int nls = (o.flags & ST_EDGE_SHADOW) ? sc->d.nl : 0;     // lights with shadow-edge tables
@@ -831,6 +885,27 @@ int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_
                           sizeof(int) * ((size_t)ncam << pglog) + sizeof(double) * 2 * (size_t)ncam * ne +
                           sizeof(double) * ((size_t)nls * ne + (size_t)nls * (ne + 1) + nls) +
                           sizeof(int) * ((size_t)nls << pglog) + 9 * 256;
+    // workspace of the call, checked against the caller's cap before any kernel:
+    // spill stack, edge tables, deferred secondary-edge jobs and, for the primary
+    // edges, the side paths' radiance (and hashes) and their wavefront queues
+    const bool defer_sec = (o.flags & ST_EDGE_SECONDARY) && !o.debug_decision_hash && cs.total_paths > 0 && ne > 0;
+    const bool prim = (o.flags & ST_EDGE_PRIMARY) && cs.total_edges > 0 && ne > 0;
+    const int nent_side = sc->d.nl + (sc->d.has_env ? 1 : 0);
+    long long side_cap = o.queue_capacity > 0 ? o.queue_capacity : (sc->tuned_cap > 0 ? sc->tuned_cap : (1ll << 22));
+    side_cap = std::min<long long>(side_cap, std::max<long long>(2 * cs.total_edges, 2));
+    side_cap = std::min<long long>(side_cap, 1ll << 28) & ~1ll;
+    if (prim && 2 * cs.total_edges >= (1ll << 32)) return fail(ST_ERR_INVALID_ARG, "too many primary edge samples");
+    {
+        size_t need = SPILL_BYTES + pbytes + (defer_sec ? sec_workspace_bytes(cs.total_paths, bounces) : 0);
+        if (prim)
+            need += (size_t)cs.total_edges * 6 * sizeof(float) +
+                    (o.debug_edge_hash ? (size_t)cs.total_edges * 2 * sizeof(uint32_t) : 0) +
+                    queue_bytes(queue_cap(side_cap, nent_side), nent_side);
+        rc = over_budget(o, need);
+        if (rc) return rc;
+    }
+    rc = ensure_spill(sc);
+    if (rc) return rc;
     rc = sc->primbuf.ensure(pbytes);
     if (rc) return rc;
     Carver c{(char*)sc->primbuf.p};
@@ -870,17 +945,22 @@ int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_
     p.vf_off = sc->d.vf_off;
     p.vf_idx = sc->d.vf_idx;
     p.ne = ne;
-    const bool use_rec = sc->rec_valid && !(o.flags & ST_BACKWARD_RETRACE) &&
-                         sc->rec_key == record_key(sc, cams, ncam, spp, bounces, seed);
-    p.rec_face = use_rec ? (const int*)sc->recbuf.p : nullptr;
-    p.rec_occ = use_rec ? (const uint32_t*)((const int*)sc->recbuf.p + (size_t)(bounces + 1) * cs.total_paths) : nullptr;
-    p.rec_n = use_rec ? cs.total_paths : 0;
+    // the records are offered when they can hold this pass's paths; the adjoint
+    // takes them only if the key its forward wrote on the device matches
+    const size_t rec_bytes = (size_t)(2 * bounces + 1) * (size_t)cs.total_paths * sizeof(int);
+    const bool offer_rec = !(o.flags & ST_BACKWARD_RETRACE) && sc->recbuf.p && sc->recbuf.cap >= rec_bytes &&
+                           sc->recbuf.ensure(rec_bytes) == ST_OK;
+    p.rec_face = offer_rec ? (const int*)sc->recbuf.p : nullptr;
+    p.rec_occ = offer_rec ? (const uint32_t*)((const int*)sc->recbuf.p + (size_t)(bounces + 1) * cs.total_paths) : nullptr;
+    p.rec_n = offer_rec ? cs.total_paths : 0;
+    p.rec_key_dev = sc->d.rec_key;
+    p.rec_key = record_key(sc, cams, ncam, spp, bounces, seed, sc->recbuf.p);
     // secondary edges deferred to a job pass (not when decision hashes are asked for:
     // those follow the inline order)
     p.sec_mask = nullptr;
     p.sec_jobs = nullptr;
     p.sec_njobs = nullptr;
-    if ((p.flags & ST_EDGE_SECONDARY) && !o.debug_decision_hash && cs.total_paths > 0 && sc->d.ne > 0) {
+    if (defer_sec) {
         rc = sc->secbuf.ensure(sec_workspace_bytes(cs.total_paths, bounces));
         if (rc) return rc;
         carve_sec_workspace(p, sc->secbuf.p, cs.total_paths);
@@ -890,9 +970,8 @@ int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_
     if (o.debug_decision_hash) launch_fill_u32(o.debug_decision_hash, cs.total_paths, 0u, s);
     if (o.debug_edge_hash) launch_fill_u32(o.debug_edge_hash, cs.total_edges * (1 + nls), 0u, s);
     launch_backward(p, sc->d.nv, sc->d.nf, cs.total_paths, cs.total_edges, TRACE_GRID, s);
-    if ((p.flags & ST_EDGE_PRIMARY) && cs.total_edges > 0 && ne > 0) {
+    if (prim) {
         // side paths of the primary edge samples run through the wavefront kernels
-        if (2 * cs.total_edges >= (1ll << 32)) return fail(ST_ERR_INVALID_ARG, "too many primary edge samples");
         rc = sc->sidebuf.ensure((size_t)cs.total_edges * 6 * sizeof(float));
         if (rc) return rc;
         uint32_t* hside = nullptr;
@@ -901,12 +980,8 @@ int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_
             if (rc) return rc;
             hside = (uint32_t*)sc->sidehash.p;
         }
-        long long cap = o.queue_capacity > 0 ? o.queue_capacity : (sc->tuned_cap > 0 ? sc->tuned_cap : (1ll << 22));
-        cap = std::min<long long>(cap, std::max<long long>(2 * cs.total_edges, 2));
-        cap = std::min<long long>(cap, 1ll << 28) & ~1ll;
-        const int nent = sc->d.nl + (sc->d.has_env ? 1 : 0);
         Queues q;
-        rc = make_queues(sc, (int)cap, nent, (float*)sc->sidebuf.p, q);
+        rc = make_queues(sc, (int)side_cap, nent_side, (float*)sc->sidebuf.p, q);
         if (rc) return rc;
         q.grid = sc->tuned_grid;
         FwdParams fp;
@@ -927,6 +1002,8 @@ int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_
         launch_primary_edges(p, fp, q, (float*)sc->sidebuf.p, hside, cs.total_edges, sc->d.has_env ? 1 : 0, s);
     }
     if (nls > 0) launch_shadow_edges(p, cs.total_edges, nls, s);
+    // every term has been added: a non-finite gradient sets the error word
+    launch_check_finite(out_dV, 3ll * sc->d.nv, out_dmat, 7ll * sc->d.ntex, sc->d.err, s);
     HIPCHK(hipGetLastError());
     return ST_OK;
 }
@@ -1027,7 +1104,11 @@ int st_check_errors(st_scene* sc, hipStream_t s) {
     if (e) {
         launch_fill_u32(sc->d.err, 1, 0u, s);
         HIPCHK(hipStreamSynchronize(s));
-        return fail(ST_ERR_DEVICE_FAULT, "device error word " + std::to_string(e) + " (1: traversal stack overflow, 8: traversal iteration cap)");
+        const std::string what = "device error word " + std::to_string(e) +
+                                 " (1: traversal stack overflow, 2: non-finite image or gradient value, "
+                                 "4: queue reservation past its capacity, 8: traversal iteration cap)";
+        if (e == ERR_QUEUE) return fail(ST_ERR_QUEUE_OVERFLOW, what);
+        return fail(ST_ERR_DEVICE_FAULT, what);
     }
     return ST_OK;
 }
@@ -1095,11 +1176,12 @@ void st_scene_destroy(st_scene* sc) {
                     d.emvals[0], d.emvals[1], d.ers_hist, d.ekeys64, d.echild, d.eparent, d.ecnt, d.eaabb, d.elen, d.enbox, d.enode, d.nodes4, d.flag4, d.id4,
                     d.tri, d.fleaf, d.edges, d.edge_w, d.eguide, d.mguide, d.cguide, d.ecdf, d.etotal_d, d.etotal_f, d.row_dom, d.rowcos, d.cond, d.marg,
                     d.env_rows, d.env_total, d.texpdf, d.err, d.work, d.dscene, d.vf_off, d.vf_idx, d.facc, d.macc, d.fe,
-                    d.ealias};
+                    d.ealias, d.rec_key};
     for (void* p : ptrs)
         if (p) hipFree(p);
     sc->Lbuf.release(); sc->qbuf.release(); sc->spillbuf.release(); sc->primbuf.release(); sc->recbuf.release();
     sc->sidebuf.release(); sc->sidehash.release(); sc->secbuf.release();
+    for (void* q : sc->retired) hipFree(q);
     for (auto& t : sc->tables) {
         if (t.dev) hipFree(t.dev);
         if (t.pinned) hipHostFree(t.pinned);

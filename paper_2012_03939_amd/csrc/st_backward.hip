@@ -139,6 +139,10 @@ k_adjoint(BwdParams p, long long total) {
     const bool sec_interior = p.flags & ST_EDGE_SECONDARY_INTERIOR;   // creases / material edges too
     const bool hier = p.flags & ST_EDGE_SECONDARY_HIERARCHY;           // edges from the importance tree
     const bool defer = !JOBS && p.sec_mask != nullptr;
+    // hit records only when they belong to this pass's forward (same on every lane)
+    const bool recs = p.rec_face != nullptr && *p.rec_key_dev == p.rec_key;
+    const int* const rec_face = recs ? p.rec_face : nullptr;
+    const uint32_t* const rec_occ = recs ? p.rec_occ : nullptr;
     const long long stride = (long long)gridDim.x * blockDim.x;
     const long long count = JOBS ? (long long)*p.sec_njobs : total;
     // the main pass gives each XCD consecutive paths (their hits share that XCD's
@@ -188,8 +192,8 @@ k_adjoint(BwdParams p, long long total) {
                 float t;
                 const size_t ri = (size_t)(k - 1) * p.rec_n + qq;
                 int f;
-                if (p.rec_face) {
-                    f = p.rec_face[ri];
+                if (rec_face) {
+                    f = rec_face[ri];
                     t = f >= 0 ? face_hit_t(S, f, o, d) : __int_as_float(0x7f800000);
                 } else {
                     f = trace_closest(S, o, d, TMIN, excl, t, st);
@@ -214,7 +218,7 @@ k_adjoint(BwdParams p, long long total) {
                 const int tx = texel_of(S, f, xh);
                 if (S.tex_res) h.push((uint32_t)tx);
                 const Mat m = load_mat(S.mat + 7 * (size_t)tx);
-                const uint32_t rocc = p.rec_occ ? p.rec_occ[ri] : 0u;
+                const uint32_t rocc = rec_occ ? rec_occ[ri] : 0u;
                 for (int l = 0; l < S.nl; ++l) {
                     const float* lt = S.lights + 6 * l;
                     const V3 dl = ld3(lt) - xh;
@@ -224,7 +228,7 @@ k_adjoint(BwdParams p, long long total) {
                         const float rr = sqrtf(r2);
                         const V3 wl = dl * (1.0f / rr);
                         if (dot(n, wl) > 0.0f) {
-                            const bool occ = p.rec_occ ? ((rocc >> l) & 1u) != 0u
+                            const bool occ = rec_occ ? ((rocc >> l) & 1u) != 0u
                                                        : trace_any(S, xh, wl, TMIN, rr * (1.0f - SHADOW_SHRINK), f, st);
                             code = occ ? 1u : 2u;
                             if (!occ) fl |= 1u << (8 + l);
@@ -240,7 +244,7 @@ k_adjoint(BwdParams p, long long total) {
                     const float ce = dot(n, we);
                     uint32_t code = 0;
                     if (ce > 0.0f && pe > 0.0f) {
-                        const bool occ = p.rec_occ ? ((rocc >> S.nl) & 1u) != 0u
+                        const bool occ = rec_occ ? ((rocc >> S.nl) & 1u) != 0u
                                                    : trace_any(S, xh, we, TMIN, __int_as_float(0x7f800000), f, st);
                         code = occ ? 1u : 2u;
                         if (!occ) {
@@ -630,6 +634,10 @@ __global__ void __launch_bounds__(EDGE_CAM_BLOCK) k_edge_camera(BwdParams p, Que
         }
         const int o0 = block_reserve<EDGE_CAM_BLOCK, 2>(active, &q.cnt[1], resv);
         if (!active) continue;
+        if (o0 + 2 > q.cap) {               // the chunk holds both side rays of every sample
+            atomicOr(p.err, ERR_QUEUE);
+            continue;
+        }
         const DevCam& c = p.cams[es.v];
         for (int side = 0; side < 2; ++side) {
             const int s = o0 + side;
@@ -1026,7 +1034,7 @@ void launch_primary_edges(const BwdParams& p, const FwdParams& fp, Queues& q, fl
 // (path, vertex) jobs of the marked secondary edge samples, in blocks of 256
 // paths with one counter reservation per block and bit
 __global__ void __launch_bounds__(256) k_sec_jobs(const uint8_t* __restrict__ mask, long long total, int B,
-                                                 int2* jobs, int* njobs) {
+                                                 int2* jobs, int* njobs, uint32_t* err) {
     __shared__ int resv[256 / 64 + 1];
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long b0 = (long long)blockIdx.x * blockDim.x; b0 < total; b0 += stride) {
@@ -1035,7 +1043,10 @@ __global__ void __launch_bounds__(256) k_sec_jobs(const uint8_t* __restrict__ ma
         for (int k = 0; k < B; ++k) {
             const bool emit = (m >> k) & 1u;
             const int o = block_reserve<256, 1>(emit, njobs, resv);
-            if (emit) jobs[o] = make_int2((int)i, k);
+            if (emit) {
+                if ((long long)o < total * B) jobs[o] = make_int2((int)i, k);   // at most B per path
+                else atomicOr(err, ERR_QUEUE);
+            }
         }
     }
 }
@@ -1062,7 +1073,7 @@ static void launch_adjoint(const BwdParams& p, long long total_paths, int grid, 
     ST_LAUNCH(name, (k_adjoint<BM, false>), gd, bd, 0, st, p, total_paths);
     if (p.sec_mask) {
         ST_LAUNCH("k_sec_jobs", k_sec_jobs, dim3(gridb(total_paths, 256, 1 << 14)), dim3(256), 0, st, p.sec_mask,
-                  total_paths, p.B, p.sec_jobs, p.sec_njobs);
+                  total_paths, p.B, p.sec_jobs, p.sec_njobs, p.err);
         // the job count stays on the device: a fixed grid strides over it
         ST_LAUNCH(name_jobs, (k_adjoint<BM, true>), dim3(1024), bd, 0, st, p, 0ll);
     }

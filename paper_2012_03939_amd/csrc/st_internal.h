@@ -87,6 +87,7 @@ struct SceneDev {
     float* texpdf = nullptr;
     EnvAlias* ealias = nullptr;              // [he*we], built on the first request for alias sampling
     uint32_t* err = nullptr;                 // device error word
+    unsigned long long* rec_key = nullptr;   // key of the forward pass whose hit records the scene holds (0: none)
     unsigned long long* work = nullptr;      // traversal work counters [3]
     DevScene* dscene = nullptr;              // device copy of the kernel view
     DevScene hscene;                         // host copy of the kernel view
@@ -166,7 +167,9 @@ void launch_forward_wavefront(const FwdParams& p, Queues& q, long long total, in
 void launch_wavefront_bounces(const FwdParams& p, Queues& q, int n, int has_env_any, hipStream_t st);
 void launch_forward_mega(const FwdParams& p, float* L, long long total, uint32_t* spill, int grid, hipStream_t st);
 void launch_film(const DevCam* cams, const long long* pixoff, int ncam, int spp, const float* L,
-                 long long npix, float* out, hipStream_t st);
+                 long long npix, float* out, uint32_t* err, hipStream_t st);
+// sets ERR_NAN in *err when a[0..na) or b[0..nb) holds a non-finite value
+void launch_check_finite(const float* a, long long na, const float* b, long long nb, uint32_t* err, hipStream_t st);
 void launch_sample_radiance(const FwdParams& p, const float* L, long long total, float* out, hipStream_t st);
 
 struct BwdParams {
@@ -203,9 +206,14 @@ struct BwdParams {
     int ntex;
     const int* vf_off;       // vertex -> (face, corner) CSR of the scene
     const int* vf_idx;
-    const int* rec_face;     // hit records of the matching forward pass, or null (trace again)
+    const int* rec_face;     // hit records held by the scene, or null (trace again)
     const uint32_t* rec_occ;
     long long rec_n;
+    // the records are used only when the key the forward wrote next to them
+    // (device word, stream-ordered, so also right after graph replays) equals the
+    // key of this backward's cameras, spp, bounces, seed and scene version
+    const unsigned long long* rec_key_dev;
+    unsigned long long rec_key;
     // deferred secondary edges (null: traced inline): accepted vertices per path
     // (bit k), then the compacted (path, vertex) jobs and their count
     uint8_t* sec_mask;
@@ -225,6 +233,7 @@ void launch_primary_edges(const BwdParams& p, const FwdParams& fp, Queues& q, fl
                           long long total_edges, int has_env_any, hipStream_t st);
 void launch_fill_f32(float* p, long long n, float v, hipStream_t st);
 void launch_fill_u32(uint32_t* p, long long n, uint32_t v, hipStream_t st);
+void launch_put_u64(unsigned long long* p, unsigned long long v, hipStream_t st);
 void launch_trace_debug(const DevScene* s, const float* o, const float* d, int n, float tmin, int brute,
                         int* out_face, float* out_t, uint32_t* spill, uint32_t* err, hipStream_t st);
 

@@ -269,6 +269,14 @@ __global__ void __launch_bounds__(SHADE_BLOCK) SHADE_OCC k_shade(FwdParams p, Qu
         // consecutive) into the shadow list of this bounce
         const int2 oo = block_reserve2<SHADE_BLOCK>(emit, __popc(rays), &q.cnt[k + 1], &q.cnt[32 + k], resv);
         const int o = oo.x;
+        // the next queue holds one continuation per path of the chunk and the
+        // shadow list nent entries per shading point, so this never trips; a
+        // reservation past either is reported (ST_ERR_QUEUE_OVERFLOW), not written
+        if ((emit && o >= q.cap) || (rays && (long long)oo.y + __popc(rays) > (long long)q.cap * max(q.nent, 1))) {
+            atomicOr(p.err, ERR_QUEUE);
+            emit = false;
+            rays = 0;
+        }
         for (int so = oo.y; rays; rays &= rays - 1, ++so)
             q.slist[so] = (uint32_t)(__ffs(rays) - 1) * (uint32_t)q.cap + (uint32_t)i;
         {
@@ -404,7 +412,7 @@ __global__ void __launch_bounds__(TRACE_BLOCK) k_forward_mega(FwdParams p, float
 
 // film: average the spp samples of each pixel in sample order
 __global__ void k_film(const DevCam* __restrict__ cams, const long long* __restrict__ pixoff, int ncam, int spp,
-                       const float* __restrict__ L, long long npix, float* out) {
+                       const float* __restrict__ L, long long npix, float* out, uint32_t* err) {
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < npix; g += stride) {
         const int v = find_view(pixoff, ncam, g);
@@ -422,6 +430,7 @@ __global__ void k_film(const DevCam* __restrict__ cams, const long long* __restr
         }
         const float inv = 1.0f / (float)spp;
         out[3 * g] = a * inv; out[3 * g + 1] = b * inv; out[3 * g + 2] = cc * inv;
+        if (!isfinite(a + b + cc)) atomicOr(err, ERR_NAN);
     }
 }
 
@@ -514,9 +523,9 @@ void launch_forward_mega(const FwdParams& p, float* L, long long total, uint32_t
 }
 
 void launch_film(const DevCam* cams, const long long* pixoff, int ncam, int spp, const float* L, long long npix,
-                 float* out, hipStream_t st) {
+                 float* out, uint32_t* err, hipStream_t st) {
     ST_LAUNCH("k_film", k_film, dim3(grid_for(npix, 256, 1u << 16)), dim3(256), 0, st, cams, pixoff, ncam, spp, L,
-                       npix, out);
+                       npix, out, err);
 }
 
 void launch_sample_radiance(const FwdParams& p, const float* L, long long total, float* out, hipStream_t st) {
@@ -527,6 +536,30 @@ void launch_sample_radiance(const FwdParams& p, const float* L, long long total,
 void launch_fill_f32(float* ptr, long long n, float v, hipStream_t st) {
     if (n > 0) ST_LAUNCH("k_fill_f32", k_fill_f32, dim3(grid_for(n, 256, 1u << 16)), dim3(256), 0, st, ptr, n, v);
 }
+// non-finite values among a[0..na) and b[0..nb) set ERR_NAN
+__global__ void k_check_finite(const float* __restrict__ a, long long na, const float* __restrict__ b, long long nb,
+                               uint32_t* err) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    bool bad = false;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < na + nb; i += stride)
+        bad |= !isfinite(i < na ? a[i] : b[i - na]);
+    if (__ballot(bad) && __lane_id() == 0) atomicOr(err, ERR_NAN);
+}
+
+void launch_check_finite(const float* a, long long na, const float* b, long long nb, uint32_t* err, hipStream_t st) {
+    if (na + nb > 0)
+        ST_LAUNCH("k_check_finite", k_check_finite, dim3(grid_for(na + nb, 256, 1u << 12)), dim3(256), 0, st, a, na, b,
+                  nb, err);
+}
+
+__global__ void k_put_u64(unsigned long long* p, unsigned long long v) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *p = v;
+}
+
+void launch_put_u64(unsigned long long* ptr, unsigned long long v, hipStream_t st) {
+    ST_LAUNCH("k_put_u64", k_put_u64, dim3(1), dim3(64), 0, st, ptr, v);
+}
+
 void launch_fill_u32(uint32_t* ptr, long long n, uint32_t v, hipStream_t st) {
     if (n > 0) ST_LAUNCH("k_fill_u32", k_fill_u32, dim3(grid_for(n, 256, 1u << 16)), dim3(256), 0, st, ptr, n, v);
 }

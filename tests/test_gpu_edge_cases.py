@@ -144,3 +144,75 @@ def test_mesh_through_the_near_plane(B):
     pf, ef, rv, rm, oV, oM = _backward_case(B, sc, cams, 4, 2, d_img, 15)
     _say(f"  backward (all terms) path flips {pf:.5f} edge flips {ef:.5f} relL2 dV {rv:.2e} dmat {rm:.2e}")
     assert pf < FLIP_MAX and ef < FLIP_MAX and rv < GRAD_RTOL and rm < GRAD_RTOL
+
+
+def test_non_finite_gradient_sets_the_error_word(B):
+    """A NaN in the row of d_image of a pixel that sees the mesh makes the
+    backward's gradients non-finite;
+    the final check of the backward records it and st_check_errors reports
+    ST_ERR_DEVICE_FAULT (then the word is clear again)."""
+    _say("case NaN in d_image -> ST_ERR_DEVICE_FAULT")
+    sc = _triangle_scene()
+    g = B.GPUScene.from_scene(sc)
+    cams = [S.look_at_origin((0.3, 0.2, 3.0), 24, 20)]
+    g.check_errors()
+    img = g.render(cams, 2, 2, seed=0)
+    d = torch.zeros((B.num_pixels(cams), 3), device="cuda")
+    d[int(torch.argmax(img.sum(dim=1)))] = float("nan")     # a pixel whose paths hit the triangle
+    g.backward(cams, 2, 2, d, 0, B.ST_ALL_GRADS)
+    with pytest.raises(B.StError, match="error -5"):
+        g.check_errors()
+    g.check_errors()                             # cleared
+    g.backward(cams, 2, 2, torch.ones_like(d), 0, B.ST_ALL_GRADS)
+    g.check_errors()                             # finite input, no report
+
+
+def test_max_workspace_bytes(B):
+    """A cap below the call's workspace fails with ST_ERR_OOM before any launch
+    (the output buffer is left untouched); a cap that leaves out only the hit
+    records renders the same image, and the backward then traces again."""
+    _say("case max_workspace_bytes: OOM before launch, records left out under a tight cap")
+    sc = _triangle_scene()
+    g = B.GPUScene.from_scene(sc)
+    cams = [S.look_at_origin((0.3, 0.2, 3.0), 32, 32)]
+    spp, bounces = 4, 2
+    ref = g.render(cams, spp, bounces, seed=1).clone()
+    out = torch.full_like(ref, 7.0)
+    with pytest.raises(B.StError, match="error -3"):
+        g.render(cams, spp, bounces, seed=1, out=out, max_workspace_bytes=1 << 20)
+    torch.cuda.synchronize()
+    assert bool((out == 7.0).all())
+    d = torch.ones_like(ref)
+    with pytest.raises(B.StError, match="error -3"):
+        g.backward(cams, spp, bounces, d, 1, B.ST_ALL_GRADS, max_workspace_bytes=1 << 20)
+    # the forward's own need (radiance, queues, spill stack) without the records
+    # (4 (2B + 1) bytes per path sample)
+    npath = B.num_pixels(cams) * spp
+    big = 1 << 40
+    g.render(cams, spp, bounces, seed=1, out=out, max_workspace_bytes=big)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+
+    def adjoint_rays(extra=0):
+        g.read_work()
+        g.backward(cams, spp, bounces, d, 1, B.ST_ALL_GRADS | B.ST_COUNT_WORK | extra)
+        return g.read_work()["k_adjoint"][2]
+
+    full = adjoint_rays(B.ST_BACKWARD_RETRACE)
+    assert adjoint_rays() < full                  # records kept under a large cap
+    # find the smallest cap the render accepts, then check it keeps no records
+    lo, hi = 1, big
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        try:
+            g.render(cams, spp, bounces, seed=1, out=out, max_workspace_bytes=mid)
+            hi = mid
+        except B.StError:
+            lo = mid
+    g.render(cams, spp, bounces, seed=1, out=out, max_workspace_bytes=hi)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+    assert adjoint_rays() == full                 # no records under the tight cap
+    g.render(cams, spp, bounces, seed=1, out=out, max_workspace_bytes=hi + 4 * (2 * bounces + 1) * npath)
+    assert adjoint_rays() < full                  # room for them again
+    g.check_errors()

@@ -32,6 +32,8 @@ def test_host_side_validation_without_gpu():
     assert L.st_version() == 1
     o = L.st_render_opts_default()
     assert o.flags == 15 and abs(o.edge_spp_ratio - 1.0) < 1e-7 and o.queue_capacity == 0
+    # the last field of the options struct: the binding's layout matches the header's
+    assert o.max_workspace_bytes == 0 and not o.path_mask and not o.edge_mask
     out = ctypes.c_void_p()
     rc = L.st_scene_create(None, 0, None, 0, None, None, 0, None, 0, 0, 0, None, ctypes.byref(out))
     assert rc == -1 and b"non-NULL" in L.st_last_error()
