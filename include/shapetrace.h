@@ -195,6 +195,22 @@ int st_scene_set_bsdf_sampler(st_scene* scene, int32_t method, hipStream_t s);
 int st_render(st_scene* scene, const st_camera* cams, int32_t ncam, int32_t spp, int32_t bounces, uint32_t seed,
               const st_render_opts* opts, float* out, hipStream_t s);
 
+/* st_render for callers that cannot allocate device memory: code under graph
+ * capture, tight serving loops, harnesses that forbid allocation.  Same
+ * arguments and the same image (bit for bit) as st_render on one scene; every
+ * workspace (camera table, per-sample radiance, wavefront queues, traversal
+ * spill stack) lives in one static 64 MiB device array of the library, which
+ * each GPU the library runs on holds until the process ends.  No hipMalloc,
+ * hipFree or allocating call; the camera table goes to the device through
+ * kernel arguments.  Limits: at most 64 cameras and 2^20 path samples
+ * (sum of width x height x spp) per call, else ST_ERR_INVALID_ARG before any
+ * launch.  Keeps no hit records (a later backward traces its main paths).
+ * Every call on a GPU shares that array: calls that overlap on one GPU (other
+ * streams, other threads, replays of graphs holding this call) race and must be
+ * ordered by the caller.  Traversal uses 512 blocks per launch. */
+int st_render_noalloc(st_scene* scene, const st_camera* cams, int32_t ncam, int32_t spp, int32_t bounces,
+                      uint32_t seed, const st_render_opts* opts, float* out, hipStream_t s);
+
 /* Adjoint of st_render (Sec. 3.2 gradients w.r.t. geometry; Sec. 3.3 materials).
  * Must be called with the same (cams, spp, bounces, seed) as the forward pass
  * whose image gradient it receives; it replays every path from its random

@@ -33,7 +33,7 @@ ST_BSDF_SAMPLER_HALFVECTOR = 0
 ST_BSDF_SAMPLER_VNDF = 1
 
 EXPORTED = ["st_render_opts_default", "st_scene_create", "st_scene_update", "st_scene_set_mesh_colors",
-            "st_scene_mesh_colors_info", "st_scene_subdivide", "st_scene_set_env_sampler", "st_scene_env_alias_table", "st_scene_set_bsdf_sampler", "st_scene_edge_tree", "st_render", "st_render_backward",
+            "st_scene_mesh_colors_info", "st_scene_subdivide", "st_scene_set_env_sampler", "st_scene_env_alias_table", "st_scene_set_bsdf_sampler", "st_scene_edge_tree", "st_render", "st_render_noalloc", "st_render_backward",
             "st_render_batch", "st_autotune", "st_check_errors", "st_read_work", "st_scene_info", "st_scene_edges", "st_scene_lbvh",
             "st_trace_rays", "st_profile_enable", "st_profile_read", "st_scene_destroy", "st_last_error",
             "st_version"]
@@ -78,6 +78,7 @@ def load(path: str = LIB_PATH):
     L.st_scene_edge_tree.argtypes = [P, P, P, P, P, P, P, P]
     L.st_scene_env_alias_table.argtypes = [P, P, P]
     L.st_render.argtypes = [P, P, I32, I32, I32, U32, ctypes.POINTER(StOpts), P, P]
+    L.st_render_noalloc.argtypes = [P, P, I32, I32, I32, U32, ctypes.POINTER(StOpts), P, P]
     L.st_render_backward.argtypes = [P, P, I32, I32, I32, U32, ctypes.POINTER(StOpts), P, P, P, P]
     L.st_render_batch.argtypes = [P, I32, P, P, I32, I32, I32, U32, ctypes.POINTER(StOpts), P, P]
     L.st_check_errors.argtypes = [P, P]
@@ -259,6 +260,20 @@ class GPUScene:
         o = make_opts(flags=flags, queue_capacity=queue_capacity, dbg_hash=debug_hash, dbg_radiance=debug_radiance,
                       max_workspace_bytes=max_workspace_bytes)
         _check(load().st_render(self.h, cam, len(cams), spp, bounces, seed, ctypes.byref(o), _ptr(out), _stream()))
+        return out
+
+    def render_noalloc(self, cams, spp: int, bounces: int, seed: int = 0, out=None, flags: int = 0,
+                       queue_capacity: int = 0, debug_hash=None):
+        """st_render_noalloc: the same image as render(), with every workspace in
+        the library's static per-device scratch (no allocation; calls on one GPU
+        must not overlap).  out must be given by callers that cannot allocate."""
+        import torch
+        cam = make_cameras(cams)
+        if out is None:
+            out = torch.empty((num_pixels(cams), 3), dtype=torch.float32, device="cuda")
+        o = make_opts(flags=flags, queue_capacity=queue_capacity, dbg_hash=debug_hash)
+        _check(load().st_render_noalloc(self.h, cam, len(cams), spp, bounces, seed, ctypes.byref(o), _ptr(out),
+                                        _stream()))
         return out
 
     def backward(self, cams, spp: int, bounces: int, d_image, seed: int = 0, flags: int = ST_ALL_GRADS,

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -191,8 +192,16 @@ struct CamSetup {
     long long total_paths = 0, total_pix = 0, total_edges = 0;
 };
 
-int setup_cams(st_scene* owner, st_scene* const* scenes, int nscenes, const st_camera* cams,
-               const int32_t* cam_scene, int32_t ncam, int32_t spp, double ratio, hipStream_t s, CamSetup& out) {
+// camera records, offset tables and the scene table of a call, serialised on
+// the host (each array 256-byte aligned) with their offsets in the blob
+struct CamHost {
+    std::vector<char> bytes;
+    size_t o_cam = 0, o_q = 0, o_p = 0, o_e = 0, o_s = 0;
+    long long total_paths = 0, total_pix = 0, total_edges = 0;
+};
+
+int build_cam_table(st_scene* const* scenes, int nscenes, const st_camera* cams, const int32_t* cam_scene,
+                    int32_t ncam, int32_t spp, double ratio, CamHost& out) {
     if (!cams) return fail(ST_ERR_INVALID_ARG, "cams is NULL");
     if (ncam < 1 || ncam > 65535) return fail(ST_ERR_INVALID_ARG, "ncam must be in [1, 65535]");
     if (spp < 1 || spp > 65535) return fail(ST_ERR_INVALID_ARG, "spp must be in [1, 65535]");
@@ -215,29 +224,54 @@ int setup_cams(st_scene* owner, st_scene* const* scenes, int nscenes, const st_c
     qoff[ncam] = q; pix[ncam] = p; eoff[ncam] = e;
     if (q >= (1ll << 31)) return fail(ST_ERR_INVALID_ARG, "more than 2^31 path samples in one call");
     if (e >= (1ll << 40)) return fail(ST_ERR_INVALID_ARG, "too many edge samples");
+    std::vector<char>& host = out.bytes;
+    host.clear();
+    size_t off = 0;
+    auto put = [&](const void* src, size_t n) {
+        const size_t at = off = (off + 255) & ~(size_t)255;
+        off += n;
+        host.resize(off);
+        std::memcpy(host.data() + at, src, n);
+        return at;
+    };
+    std::vector<DevScene> hs(nscenes);
+    for (int i = 0; i < nscenes; ++i) hs[i] = scenes[i]->d.hscene;
+    out.o_cam = put(dc.data(), sizeof(DevCam) * ncam);
+    out.o_q = put(qoff.data(), sizeof(long long) * (ncam + 1));
+    out.o_p = put(pix.data(), sizeof(long long) * (ncam + 1));
+    out.o_e = put(eoff.data(), sizeof(long long) * (ncam + 1));
+    out.o_s = put(hs.data(), sizeof(DevScene) * nscenes);
+    out.total_paths = q;
+    out.total_pix = p;
+    out.total_edges = e;
+    return ST_OK;
+}
+
+// device pointers of a serialised table placed at dev
+void point_cams(const CamHost& h, char* dev, CamSetup& out) {
+    out.cams = (DevCam*)(dev + h.o_cam);
+    out.qoff = (long long*)(dev + h.o_q);
+    out.pixoff = (long long*)(dev + h.o_p);
+    out.eoff = (long long*)(dev + h.o_e);
+    out.scenes = (DevScene*)(dev + h.o_s);
+    out.total_paths = h.total_paths;
+    out.total_pix = h.total_pix;
+    out.total_edges = h.total_edges;
+}
+
+int setup_cams(st_scene* owner, st_scene* const* scenes, int nscenes, const st_camera* cams,
+               const int32_t* cam_scene, int32_t ncam, int32_t spp, double ratio, hipStream_t s, CamSetup& out) {
+    CamHost ch;
+    int rc = build_cam_table(scenes, nscenes, cams, cam_scene, ncam, spp, ratio, ch);
+    if (rc) return rc;
     hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
     HIPCHK(hipStreamIsCapturing(s, &cst));
     const bool capturing = cst != hipStreamCaptureStatusNone;
     g_capturing = capturing;
-    // serialise the table on the host, then find or create its device copy
-    std::vector<char> host;
-    Carver hc{nullptr};
-    auto put = [&](const void* src, size_t n) {
-        const size_t off = hc.off = (hc.off + 255) & ~(size_t)255;
-        hc.off += n;
-        host.resize(hc.off);
-        std::memcpy(host.data() + off, src, n);
-        return off;
-    };
-    std::vector<DevScene> hs(nscenes);
-    for (int i = 0; i < nscenes; ++i) hs[i] = scenes[i]->d.hscene;
-    const size_t o_cam = put(dc.data(), sizeof(DevCam) * ncam);
-    const size_t o_q = put(qoff.data(), sizeof(long long) * (ncam + 1));
-    const size_t o_p = put(pix.data(), sizeof(long long) * (ncam + 1));
-    const size_t o_e = put(eoff.data(), sizeof(long long) * (ncam + 1));
-    const size_t o_s = put(hs.data(), sizeof(DevScene) * nscenes);
+    // find or create the device copy of the table
+    const std::vector<char>& host = ch.bytes;
     uint64_t hv = 1469598103934665603ull;      // FNV-1a 64 of the serialised table
-    for (char ch : host) { hv ^= (unsigned char)ch; hv *= 1099511628211ull; }
+    for (char c : host) { hv ^= (unsigned char)c; hv *= 1099511628211ull; }
     char* dev = nullptr;
     for (auto& t : owner->tables)
         if (t.hash == hv && t.host == host) { dev = (char*)t.dev; break; }
@@ -256,14 +290,7 @@ int setup_cams(st_scene* owner, st_scene* const* scenes, int nscenes, const st_c
         owner->tables.push_back(std::move(t));
         dev = (char*)owner->tables.back().dev;
     }
-    out.cams = (DevCam*)(dev + o_cam);
-    out.qoff = (long long*)(dev + o_q);
-    out.pixoff = (long long*)(dev + o_p);
-    out.eoff = (long long*)(dev + o_e);
-    out.scenes = (DevScene*)(dev + o_s);
-    out.total_paths = q;
-    out.total_pix = p;
-    out.total_edges = e;
+    point_cams(ch, dev, out);
     return ST_OK;
 }
 
@@ -314,12 +341,10 @@ int ensure_spill(st_scene* sc) {
     return sc->spillbuf.ensure(SPILL_BYTES);
 }
 
-int make_queues(st_scene* sc, int cap, int nent, float* L, Queues& q) {
-    cap = queue_cap(cap, nent);
-    const size_t bytes = queue_bytes(cap, nent);
-    int rc = sc->qbuf.ensure(bytes);
-    if (rc) return rc;
-    Carver c{(char*)sc->qbuf.p};
+// queue arrays of a chunk of cap paths (cap from queue_cap) carved out of base,
+// which holds queue_bytes(cap, nent) bytes
+void carve_queues(char* base, int cap, int nent, float* L, uint32_t* spill, Queues& q) {
+    Carver c{base};
     for (int b = 0; b < 2; ++b)
         for (int i = 0; i < QNCOL; ++i) q.ray[b][i] = c.take<float>(cap);
     q.ht = c.take<float>(cap);
@@ -334,11 +359,18 @@ int make_queues(st_scene* sc, int cap, int nent, float* L, Queues& q) {
     q.slist = c.take<uint32_t>((size_t)cap * std::max(nent, 1));
     q.cnt = c.take<int>(64);
     q.fetch = c.take<int>(FETCH_INTS);
-    q.spill = (uint32_t*)sc->spillbuf.p;
+    q.spill = spill;
     q.L = L;
     q.cap = cap;
     q.grid = 0;
     q.nent = nent;
+}
+
+int make_queues(st_scene* sc, int cap, int nent, float* L, Queues& q) {
+    cap = queue_cap(cap, nent);
+    int rc = sc->qbuf.ensure(queue_bytes(cap, nent));
+    if (rc) return rc;
+    carve_queues((char*)sc->qbuf.p, cap, nent, L, (uint32_t*)sc->spillbuf.p, q);
     return ST_OK;
 }
 
@@ -416,6 +448,46 @@ int render_impl(st_scene* owner, st_scene* const* scenes, int nscenes, const st_
     launch_film(cs.cams, cs.pixoff, ncam, spp, L, cs.total_pix, out, owner->d.err, s);
     if (o.debug_sample_radiance) launch_sample_radiance(p, L, cs.total_paths, o.debug_sample_radiance, s);
     HIPCHK(hipGetLastError());
+    return ST_OK;
+}
+
+// ---- the allocation-free render's scratch ----------------------------------
+// One static device array per GPU (the code object holds it, so every device
+// the library runs on keeps it until the process ends): camera table, traversal
+// spill stack, per-sample radiance and the wavefront queues of
+// st_render_noalloc.  Host code never uses the array's name as an address: the
+// device address is looked up once per device with hipGetSymbolAddress.
+constexpr size_t NOALLOC_SCRATCH_BYTES = 64ull << 20;
+constexpr size_t NOALLOC_TABLE_BYTES = 32u << 10;
+constexpr int NOALLOC_MAX_CAMS = 64;
+constexpr long long NOALLOC_MAX_PATHS = 1ll << 20;
+constexpr unsigned NOALLOC_TRACE_GRID = 512;      // traversal blocks: the spill stack has one column per thread
+constexpr size_t NOALLOC_SPILL_BYTES = (size_t)SPILL_STACK * NOALLOC_TRACE_GRID * TRACE_BLOCK * sizeof(uint32_t);
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static_assert(NOALLOC_TABLE_BYTES + NOALLOC_SPILL_BYTES + (size_t)NOALLOC_MAX_PATHS * 3 * sizeof(float) <
+                  NOALLOC_SCRATCH_BYTES,
+              "scratch layout");
+
+static __device__ __align__(256) __attribute__((used)) char scratch[NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+void* g_scratch_addr[NOALLOC_MAX_DEVICES] = {};
+
+// device address of the scratch array on the current device (looked up on the
+// first request per device, with that device current)
+int scratch_address(void** out) {
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(ST_ERR_INVALID_ARG, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(ST_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_addr[dev] = p;
+    }
+    *out = g_scratch_addr[dev];
     return ST_OK;
 }
 
@@ -628,6 +700,10 @@ int st_scene_create(const float* V, int32_t nv, const int32_t* F, int32_t nf, co
     HIPCHK2(hipMemcpyAsync(d.dscene, &h, sizeof(DevScene), hipMemcpyHostToDevice, s));
     HIPCHK2(hipStreamSynchronize(s));
 #undef HIPCHK2
+    // set-up of st_render_noalloc on this device, outside any capture (a failure
+    // here is reported by st_render_noalloc itself, which looks again)
+    void* scr = nullptr;
+    if (scratch_address(&scr)) g_err.clear();
     *out = sc;
     return ST_OK;
 }
@@ -848,6 +924,84 @@ int st_render(st_scene* sc, const st_camera* cams, int32_t ncam, int32_t spp, in
     if (rc) return rc;
     st_scene* list[1] = {sc};
     return render_impl(sc, list, 1, cams, nullptr, ncam, spp, bounces, seed, opts, out, s);
+}
+
+int st_render_noalloc(st_scene* sc, const st_camera* cams, int32_t ncam, int32_t spp, int32_t bounces, uint32_t seed,
+                      const st_render_opts* opts, float* out, hipStream_t s) {
+    int rc = check_scene(sc);
+    if (rc) return rc;
+    if (!out) return fail(ST_ERR_INVALID_ARG, "out is NULL");
+    if (bounces < 1 || bounces > 8) return fail(ST_ERR_INVALID_ARG, "bounces must be in [1, 8]");
+    if (ncam > NOALLOC_MAX_CAMS)
+        return fail(ST_ERR_INVALID_ARG, "st_render_noalloc: at most " + std::to_string(NOALLOC_MAX_CAMS) + " cameras");
+    st_render_opts o = opts ? *opts : st_render_opts_default();
+    st_scene* list[1] = {sc};
+    CamHost ch;
+    rc = build_cam_table(list, 1, cams, nullptr, ncam, spp, 0.0, ch);
+    if (rc) return rc;
+    if (ch.total_paths > NOALLOC_MAX_PATHS)
+        return fail(ST_ERR_INVALID_ARG, "st_render_noalloc: " + std::to_string(ch.total_paths) +
+                                            " path samples exceed its static scratch limit of " +
+                                            std::to_string(NOALLOC_MAX_PATHS));
+    if (ch.bytes.size() > NOALLOC_TABLE_BYTES) return fail(ST_ERR_INVALID_ARG, "st_render_noalloc: camera table too large");
+    void* scr = nullptr;
+    rc = scratch_address(&scr);
+    if (rc) return rc;
+    // scratch layout: camera table | spill stack | radiance per path sample | queues
+    char* const base = (char*)scr;
+    uint32_t* const spill = (uint32_t*)(base + NOALLOC_TABLE_BYTES);
+    float* const L = (float*)(base + NOALLOC_TABLE_BYTES + NOALLOC_SPILL_BYTES);
+    const size_t lbytes = (((size_t)ch.total_paths * 3 * sizeof(float)) + 255) & ~(size_t)255;
+    char* const qbase = (char*)L + lbytes;
+    const size_t qroom = NOALLOC_SCRATCH_BYTES - NOALLOC_TABLE_BYTES - NOALLOC_SPILL_BYTES - lbytes;
+    const int nent = sc->d.nl + (sc->d.has_env ? 1 : 0);
+    const bool mega = (o.flags & ST_FORWARD_MEGAKERNEL) != 0;
+    int cap = 0;
+    if (!mega) {
+        // the largest chunk whose queues fit the rest of the scratch
+        const size_t words = 2 * QNCOL + 2 + 3 + 4 + 8 * (size_t)std::max(nent, 1);
+        const size_t per = 4 * words + (size_t)std::max(nent, 1), fixed = queue_bytes(0, nent);
+        long long c = qroom > fixed ? (long long)((qroom - fixed) / per) : 0;
+        c = std::min<long long>(c, std::max<long long>(ch.total_paths, 1));
+        if (o.queue_capacity > 0) c = std::min<long long>(c, o.queue_capacity);
+        c = queue_cap(c, nent);
+        while (c > 0 && queue_bytes((int)c, nent) > qroom) --c;
+        if (c < 1) return fail(ST_ERR_INVALID_ARG, "st_render_noalloc: no room for the wavefront queues");
+        cap = (int)c;
+    }
+    // the table goes in through kernel arguments (no staging memory)
+    std::vector<uint32_t> words((ch.bytes.size() + 3) / 4, 0u);
+    std::memcpy(words.data(), ch.bytes.data(), ch.bytes.size());
+    launch_put_words((uint32_t*)base, words.data(), words.size(), s);
+    CamSetup cs;
+    point_cams(ch, base, cs);
+    FwdParams p;
+    p.scenes = cs.scenes;
+    p.cams = cs.cams;
+    p.qoff = cs.qoff;
+    p.ncam = ncam;
+    p.spp = spp;
+    p.B = bounces;
+    p.seed = seed;
+    p.dbg_hash = o.debug_decision_hash;
+    p.err = sc->d.err;
+    p.work = (o.flags & ST_COUNT_WORK) ? sc->d.work : nullptr;
+    p.hash_by_q = nullptr;
+    p.rec_face = nullptr;        // no hit records: the scene's record buffer is not touched
+    p.rec_occ = nullptr;
+    p.rec_n = 0;
+    if (mega) {
+        launch_forward_mega(p, L, cs.total_paths, spill, NOALLOC_TRACE_GRID, s);
+    } else {
+        Queues q;
+        carve_queues(qbase, cap, nent, L, spill, q);
+        q.grid = NOALLOC_TRACE_GRID;
+        launch_forward_wavefront(p, q, cs.total_paths, sc->d.has_env ? 1 : 0, nent, s);
+    }
+    launch_film(cs.cams, cs.pixoff, ncam, spp, L, cs.total_pix, out, sc->d.err, s);
+    if (o.debug_sample_radiance) launch_sample_radiance(p, L, cs.total_paths, o.debug_sample_radiance, s);
+    HIPCHK(hipGetLastError());
+    return ST_OK;
 }
 
 int st_render_batch(st_scene* const* scenes, int32_t nscenes, const st_camera* cams, const int32_t* cam_scene,

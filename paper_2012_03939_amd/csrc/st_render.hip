@@ -552,6 +552,26 @@ void launch_check_finite(const float* a, long long na, const float* b, long long
                   nb, err);
 }
 
+// up to WORD_CHUNK words passed by value (so a captured launch carries its own
+// copy) written to dst
+constexpr int WORD_CHUNK = 480;
+struct WordChunk {
+    uint32_t n;
+    uint32_t w[WORD_CHUNK];
+};
+__global__ void k_put_words(uint32_t* dst, WordChunk c) {
+    for (uint32_t i = threadIdx.x; i < c.n; i += blockDim.x) dst[i] = c.w[i];
+}
+
+void launch_put_words(uint32_t* dst, const uint32_t* src, size_t nwords, hipStream_t st) {
+    for (size_t i = 0; i < nwords; i += WORD_CHUNK) {
+        WordChunk c;
+        c.n = (uint32_t)(nwords - i < (size_t)WORD_CHUNK ? nwords - i : (size_t)WORD_CHUNK);
+        for (uint32_t j = 0; j < c.n; ++j) c.w[j] = src[i + j];
+        ST_LAUNCH("k_put_words", k_put_words, dim3(1), dim3(256), 0, st, dst + i, c);
+    }
+}
+
 __global__ void k_put_u64(unsigned long long* p, unsigned long long v) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *p = v;
 }
