@@ -20,13 +20,21 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic work per unit:
-#  - a visit of a 4-wide BVH node tests four child boxes: 4 x (6 sub + 6 mul + 12 min/max) = 96 FP32 ops
-#  - a Moller-Trumbore triangle test: 2 cross (18) + 4 dot (20) + 1 rcp + 3 sub + 3 mul = 45 FP32 ops
-FLOPS_PER_VISIT = 96
-FLOPS_PER_TEST = 45
+# Algorithmic work per unit (the roofline's count): a slab test of one box is
+# about 15 FP32 operations, so a visit of a 4-wide BVH node (four child boxes)
+# is 60; a ray-triangle test is about 30.
+FLOPS_PER_VISIT = 60
+FLOPS_PER_TEST = 30
+# The same work counted from the operations the kernels issue: per box 6 sub +
+# 6 mul + 12 min/max = 24 (96 per node); per triangle test 2 cross (18) + 4 dot
+# (20) + 1 rcp + 3 sub + 3 mul = 45.
+ISSUED_FLOPS_PER_VISIT = 96
+ISSUED_FLOPS_PER_TEST = 45
 PEAK_FP32_VECTOR_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+# library launch names of the queue-streaming kernels -> their rocprofv3 names
+HBM_KERNELS = {"k_shade": "k_shade", "k_adjoint<3>": "k_adjoint<3, false>", "k_adjoint_sec<3>": "k_adjoint<3, true>",
+               "k_extend": "k_extend", "k_shadow": "k_shadow"}
 
 
 CU_COUNT, SIMDS_PER_CU, CLOCK_HZ = 256, 4, 2.4e9
@@ -84,6 +92,20 @@ def parse():
     return ap.parse_args()
 
 
+def cpu_info():
+    """Host CPU model and logical core count."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count()}
+
+
 def cpu_baseline(wl, res, spp, bounces):
     """The FP64 oracle on a bounded sample: the same torus scene, one view at
     res x res, same spp and bounces, full forward + adjoint (all three terms)."""
@@ -100,9 +122,12 @@ def cpu_baseline(wl, res, spp, bounces):
     o.backward([cam], spp, bounces, d, seed=0, flags=7, nthreads=nt)
     dt = time.perf_counter() - t0
     n = res * res * spp
+    info = cpu_info()
     return {"value": n / dt, "unit": "path samples/s (fwd+adjoint)", "cores": nt, "kind": "oracle",
             "sample": f"same torus scene and envmap, 1 view at {res}x{res}, {spp} spp, {bounces} bounces, "
-                      f"forward + adjoint (interior, primary and secondary edges): {n} path samples in {dt:.2f} s"}
+                      f"forward + adjoint (interior, primary and secondary edges): {n} path samples in {dt:.2f} s",
+            "threads": nt, "nproc": info["nproc"], "cpu_model": info["cpu_model"],
+            "threads_note": "std::thread workers = min(nproc, 16): one GPU's share of the host is 16 threads"}
 
 
 def mesh_colors_step(B, S, torch, wl, r, steps=3):
@@ -157,18 +182,38 @@ def batched_vs_per_view(B, S, torch, reps=3):
         for i, c in enumerate(wl.cams):
             gs[wl.cam_scene[i]].render([c], wl.spp, wl.bounces, seed=0, out=outs[i])
 
-    res = {}
-    for name, fn in (("batched", batched), ("per_view", per_view)):
-        fn()
-        torch.cuda.synchronize()
+    def timed(fn):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(reps):
             fn()
         e1.record()
         torch.cuda.synchronize()
-        res[name + "_ms"] = e0.elapsed_time(e1) / reps
+        return e0.elapsed_time(e1) / reps
+
+    res = {}
+    graphs = {}
+    for name, fn in (("batched", batched), ("per_view", per_view)):
+        fn()
+        torch.cuda.synchronize()
+        res[name + "_ms"] = timed(fn)
+        # the same launches captured once and replayed as a graph
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            fn()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            fn()
+        graphs[name] = g
+        g.replay()
+        torch.cuda.synchronize()
+        res[name + "_graph_ms"] = timed(g.replay)
     res["speedup"] = res["per_view_ms"] / res["batched_ms"]
+    res["speedup_graphs"] = res["per_view_graph_ms"] / res["batched_graph_ms"]
+    res["speedup_batched_graph_vs_per_view"] = res["per_view_ms"] / res["batched_graph_ms"]
     res["path_samples"] = npix * wl.spp
     res["workload"] = wl.name
     return res
@@ -212,11 +257,22 @@ def main():
     img = torch.empty((npix, 3), dtype=torch.float32, device=dev)
     scale = 2.0 / img.numel()
 
-    def step(i):
+    def step(i, spp=spp, extra=0):
         g.update(V=Vs[i & 1])
         g.render(cams, spp, bounces, seed=i, out=img)
         d = (img - target) * scale
-        g.backward(cams, spp, bounces, d, seed=i, flags=grads, dV=dV, dmat=dM)
+        g.backward(cams, spp, bounces, d, seed=i, flags=grads | extra, dV=dV, dmat=dM)
+
+    def timed_steps(n, **kw):
+        step(50, **kw)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for i in range(n):
+            step(60 + i, **kw)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / n
 
     if args.profile_only:
         step(0)
@@ -259,8 +315,10 @@ def main():
     visits, tests, rays = work.get(wkey, (0, 0, 0))
     launches_per_step = dom_n / args.steps
     flops_per_launch = (visits * FLOPS_PER_VISIT + tests * FLOPS_PER_TEST) / max(launches_per_step, 1)
+    issued_per_launch = (visits * ISSUED_FLOPS_PER_VISIT + tests * ISSUED_FLOPS_PER_TEST) / max(launches_per_step, 1)
     avg_ms = dom_ms / dom_n
     achieved = flops_per_launch / (avg_ms / 1e3) / 1e12
+    achieved_issued = issued_per_launch / (avg_ms / 1e3) / 1e12
     kernels = {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[1] / args.steps} for k, v in prof.items()}
     # rays, node visits and triangle tests of every traversal kernel in one step
     traversal = {}
@@ -270,6 +328,22 @@ def main():
             traversal[k] = {"rays_per_step": kr, "node_visits_per_ray": kv / kr, "tri_tests_per_ray": kt / kr,
                             "ms_per_step": kms, "rays_per_s": kr / (kms / 1e3) if kms else None}
     mc = measured_counters(dom_name)
+    # queue-streaming kernels: HBM bytes per launch (counters of these sources)
+    # over their live mean launch time, against a measured streaming copy
+    copy_gbs = B.copy_bandwidth()
+    hbm = {"copy_gbs": copy_gbs, "peak_gbs": PEAK_HBM_GBS, "kernels": {}}
+    for lk, pk in HBM_KERNELS.items():
+        if lk not in prof:
+            continue
+        kms, kn = prof[lk]
+        c = measured_counters(pk)
+        gbs = c["traffic"] / (kms / kn * 1e-3) / 1e9 if c else None
+        hbm["kernels"][lk] = {"avg_launch_ms": kms / kn, "hbm_bytes_per_launch": c["traffic"] if c else None,
+                              "gbs": gbs, "frac_of_copy": gbs / copy_gbs if gbs else None,
+                              "frac_of_peak": gbs / PEAK_HBM_GBS if gbs else None}
+    # the same step at the workload's own 32 spp, and with every main-path ray traced again in the adjoint
+    ms32 = timed_steps(3, spp=2 * spp)
+    ms_retrace = timed_steps(3, extra=B.ST_BACKWARD_RETRACE)
     out = {
         "metric": "fwd+adjoint path samples/sec at 16 views 512^2 16spp; sec per optimisation step",
         "value": value,
@@ -291,6 +365,9 @@ def main():
                    "edge_sampler": args.edge_sampler},
         "roofline": {"bound": "alu", "kernel": dom_name, "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": (mc or {}).get("traffic"),
+                     "flops_per_node_visit": FLOPS_PER_VISIT, "flops_per_tri_test": FLOPS_PER_TEST,
+                     "achieved_issued_count": achieved_issued,
+                     "frac_issued_count": achieved_issued / PEAK_FP32_VECTOR_TFLOPS,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-scaled)",
                      "avg_launch_ms": avg_ms,
                      "valu_issue_utilisation": (mc or {}).get("valu_issue_utilisation"),
@@ -300,6 +377,11 @@ def main():
                      "rays_per_s": rays / max(launches_per_step, 1) / (avg_ms / 1e3)},
         "kernels": kernels,
         "traversal": traversal,
+        "hbm": hbm,
+        "spp32": {"spp": 2 * spp, "ms_per_step": ms32, "value": 2 * n_paths / (ms32 / 1e3),
+                  "unit": "path samples/s", "steps": 3},
+        "retrace": {"ms_per_step": ms_retrace, "value": n_paths / (ms_retrace / 1e3), "unit": "path samples/s",
+                    "steps": 3, "note": "backward traces every main-path ray again (no hit records)"},
     }
     if args.mesh_colors_res > 0:
         out["mesh_colors"] = mesh_colors_step(B, S, torch, wl, args.mesh_colors_res)

@@ -315,6 +315,12 @@ int st_scene_edge_tree(st_scene* scene, uint64_t* keys, int32_t* child, int32_t*
 int st_trace_rays(st_scene* scene, const float* o, const float* d, int32_t n, float tmin, int32_t brute,
                   int32_t* out_face, float* out_t, hipStream_t s);
 
+/* Measurement reference: copies nbytes (a multiple of 16, 16-byte aligned
+ * device pointers) from src to dst with a plain streaming kernel (non-temporal
+ * 16-byte loads and stores), asynchronously on s.  Its bandwidth is the
+ * achievable HBM rate the kernels' traffic is compared with. */
+int st_stream_copy(void* dst, const void* src, int64_t nbytes, hipStream_t s);
+
 /* Kernel timing for profiling harnesses: while enabled, every kernel the
  * library launches is bracketed by two HIP events recorded on its launch
  * stream.  st_profile_read waits for those events, writes the kernel names

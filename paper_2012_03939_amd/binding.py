@@ -35,7 +35,7 @@ ST_BSDF_SAMPLER_VNDF = 1
 EXPORTED = ["st_render_opts_default", "st_scene_create", "st_scene_update", "st_scene_set_mesh_colors",
             "st_scene_mesh_colors_info", "st_scene_subdivide", "st_scene_set_env_sampler", "st_scene_env_alias_table", "st_scene_set_bsdf_sampler", "st_scene_edge_tree", "st_render", "st_render_noalloc", "st_render_backward",
             "st_render_batch", "st_autotune", "st_check_errors", "st_read_work", "st_scene_info", "st_scene_edges", "st_scene_lbvh",
-            "st_trace_rays", "st_profile_enable", "st_profile_read", "st_scene_destroy", "st_last_error",
+            "st_trace_rays", "st_stream_copy", "st_profile_enable", "st_profile_read", "st_scene_destroy", "st_last_error",
             "st_version"]
 
 
@@ -79,6 +79,7 @@ def load(path: str = LIB_PATH):
     L.st_scene_env_alias_table.argtypes = [P, P, P]
     L.st_render.argtypes = [P, P, I32, I32, I32, U32, ctypes.POINTER(StOpts), P, P]
     L.st_render_noalloc.argtypes = [P, P, I32, I32, I32, U32, ctypes.POINTER(StOpts), P, P]
+    L.st_stream_copy.argtypes = [P, P, ctypes.c_int64, P]
     L.st_render_backward.argtypes = [P, P, I32, I32, I32, U32, ctypes.POINTER(StOpts), P, P, P, P]
     L.st_render_batch.argtypes = [P, I32, P, P, I32, I32, I32, U32, ctypes.POINTER(StOpts), P, P]
     L.st_check_errors.argtypes = [P, P]
@@ -340,6 +341,32 @@ def autotune(scenes: Sequence["GPUScene"], cams, spp: int, bounces: int, cam_sce
                               None if cache_path is None else cache_path.encode(), ctypes.byref(cap),
                               ctypes.byref(grid), _stream()))
     return int(cap.value), int(grid.value)
+
+
+def stream_copy(dst, src):
+    """st_stream_copy of a whole contiguous tensor (same byte size, 16-byte multiple)."""
+    n = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == n
+    _check(load().st_stream_copy(_ptr(dst), _ptr(src), n, _stream()))
+
+
+def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 10) -> float:
+    """Achievable HBM bandwidth (GB/s, read + write) of st_stream_copy on nbytes buffers."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    stream_copy(b, a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        stream_copy(b, a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    assert torch.equal(a[:1 << 20], b[:1 << 20])
+    del a, b
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
 def profile_enable(on: bool = True):

@@ -1249,6 +1249,15 @@ int st_autotune(st_scene* const* scenes, int32_t nscenes, const st_camera* cams,
     return ST_OK;
 }
 
+int st_stream_copy(void* dst, const void* src, int64_t nbytes, hipStream_t s) {
+    if (nbytes < 0 || (nbytes > 0 && (!dst || !src))) return fail(ST_ERR_INVALID_ARG, "bad copy arguments");
+    if ((nbytes & 15) || (((uintptr_t)dst | (uintptr_t)src) & 15))
+        return fail(ST_ERR_INVALID_ARG, "st_stream_copy needs 16-byte aligned pointers and size");
+    launch_stream_copy((float4*)dst, (const float4*)src, nbytes / 16, s);
+    HIPCHK(hipGetLastError());
+    return ST_OK;
+}
+
 int st_check_errors(st_scene* sc, hipStream_t s) {
     int rc = check_scene(sc);
     if (rc) return rc;

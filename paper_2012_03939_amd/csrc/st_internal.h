@@ -234,6 +234,7 @@ void launch_primary_edges(const BwdParams& p, const FwdParams& fp, Queues& q, fl
 void launch_fill_f32(float* p, long long n, float v, hipStream_t st);
 void launch_fill_u32(uint32_t* p, long long n, uint32_t v, hipStream_t st);
 void launch_put_u64(unsigned long long* p, unsigned long long v, hipStream_t st);
+void launch_stream_copy(float4* dst, const float4* src, long long n, hipStream_t st);
 // copies nwords host words to dst through kernel arguments (no staging memory;
 // a captured launch carries its own copy)
 void launch_put_words(uint32_t* dst, const uint32_t* src, size_t nwords, hipStream_t st);

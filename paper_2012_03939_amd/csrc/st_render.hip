@@ -552,6 +552,29 @@ void launch_check_finite(const float* a, long long na, const float* b, long long
                   nb, err);
 }
 
+// streaming copy of n 16-byte words (the achievable-bandwidth reference of the
+// measurements): each thread moves 4 words per step with non-temporal loads and
+// stores, consecutive lanes on consecutive words
+__global__ void __launch_bounds__(256) k_stream_copy(vf4* __restrict__ dst, const vf4* __restrict__ src, long long n) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        const vf4 a = __builtin_nontemporal_load(src + i), b = __builtin_nontemporal_load(src + i + stride);
+        const vf4 c = __builtin_nontemporal_load(src + i + 2 * stride), d = __builtin_nontemporal_load(src + i + 3 * stride);
+        __builtin_nontemporal_store(a, dst + i);
+        __builtin_nontemporal_store(b, dst + i + stride);
+        __builtin_nontemporal_store(c, dst + i + 2 * stride);
+        __builtin_nontemporal_store(d, dst + i + 3 * stride);
+    }
+    for (; i < n; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
+void launch_stream_copy(float4* dst, const float4* src, long long n, hipStream_t st) {
+    if (n > 0)
+        ST_LAUNCH("k_stream_copy", k_stream_copy, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, (vf4*)dst,
+                  (const vf4*)src, n);
+}
+
 // up to WORD_CHUNK words passed by value (so a captured launch carries its own
 // copy) written to dst
 constexpr int WORD_CHUNK = 480;
