@@ -87,6 +87,9 @@ def parse():
     ap.add_argument("--edge-sampler", choices=["cdf", "hierarchy"], default="cdf",
                     help="secondary edges drawn by the length CDF or the importance hierarchy")
     ap.add_argument("--profile-only", action="store_true", help="one untimed step (for rocprofv3 runs)")
+    ap.add_argument("--batched-trace", action="store_true",
+                    help="one per-view pass, then one batched pass of the 4-scene workload, 0.3 s apart (for "
+                         "rocprofv3 kernel traces)")
     ap.add_argument("--copy-reference", action="store_true",
                     help="only a plain 512 MiB device copy: the reference that scales the HBM byte counters")
     return ap.parse_args()
@@ -219,6 +222,32 @@ def batched_vs_per_view(B, S, torch, reps=3):
     return res
 
 
+def batched_trace(B, S, torch):
+    """The two modes of the batched comparison once each, separated by idle
+    time so that a kernel trace splits into the two phases."""
+    wl = S.batched_uneven()
+    gs = [B.GPUScene.from_scene(s) for s in wl.scenes]
+    out = torch.empty((B.num_pixels(wl.cams), 3), dtype=torch.float32, device="cuda")
+    outs = [torch.empty((c.width * c.height, 3), dtype=torch.float32, device="cuda") for c in wl.cams]
+
+    def per_view():
+        for i, c in enumerate(wl.cams):
+            gs[wl.cam_scene[i]].render([c], wl.spp, wl.bounces, seed=0, out=outs[i])
+
+    def batched():
+        B.render_batch(gs, wl.cams, wl.cam_scene, wl.spp, wl.bounces, seed=0, out=out)
+
+    per_view()
+    batched()                       # workspaces sized outside the traced phases
+    torch.cuda.synchronize()
+    for fn in (per_view, batched):
+        time.sleep(0.3)
+        fn()
+        torch.cuda.synchronize()
+    time.sleep(0.3)
+    print(json.dumps({"batched_trace": wl.name, "phases": ["per_view", "batched"]}))
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -235,6 +264,9 @@ def main():
     import torch
     from paper_2012_03939_amd import binding as B, scenes as S
 
+    if args.batched_trace:
+        batched_trace(B, S, torch)
+        return
     wl = S.torus_envmap(res=args.res, nviews=args.views, spp=args.spp, bounces=3)
     sc = wl.scenes[0]
     g = B.GPUScene.from_scene(sc)

@@ -422,17 +422,17 @@ int render_impl(st_scene* owner, st_scene* const* scenes, int nscenes, const st_
     // (an optimisation of the backward: left out rather than exceed the cap)
     const bool want_rec = nscenes == 1 && !mega && scenes[0]->d.nl <= 30 && rec_bytes <= REC_MAX_BYTES &&
                           !(o.max_workspace_bytes > 0 && need + rec_bytes > (size_t)o.max_workspace_bytes);
+    // the records' key (device word) is cleared by the first camera kernel of a
+    // render that rewrites them and set by k_film once they are complete; a
+    // render that keeps none leaves the records and their key as they are
     uint64_t rec_key = 0;
-    if (nscenes == 1) {
-        // the records are rewritten (or left stale) from here on: no backward may
-        // take them until the key of this pass is written after the forward
-        launch_put_u64(owner->d.rec_key, 0ull, s);
-        if (want_rec && !(g_capturing && owner->recbuf.cap < rec_bytes) && owner->recbuf.ensure(rec_bytes) == ST_OK) {
-            p.rec_face = (int*)owner->recbuf.p;
-            p.rec_occ = (uint32_t*)(p.rec_face + (size_t)(bounces + 1) * cs.total_paths);
-            p.rec_n = cs.total_paths;
-            rec_key = record_key(owner, cams, ncam, spp, bounces, seed, owner->recbuf.p);
-        }
+    p.rec_key_dev = nullptr;
+    if (want_rec && !(g_capturing && owner->recbuf.cap < rec_bytes) && owner->recbuf.ensure(rec_bytes) == ST_OK) {
+        p.rec_face = (int*)owner->recbuf.p;
+        p.rec_occ = (uint32_t*)(p.rec_face + (size_t)(bounces + 1) * cs.total_paths);
+        p.rec_n = cs.total_paths;
+        p.rec_key_dev = owner->d.rec_key;
+        rec_key = record_key(owner, cams, ncam, spp, bounces, seed, owner->recbuf.p);
     }
     float* L = (float*)owner->Lbuf.p;
     if (mega) {
@@ -444,8 +444,8 @@ int render_impl(st_scene* owner, st_scene* const* scenes, int nscenes, const st_
         q.grid = owner->tuned_grid;
         launch_forward_wavefront(p, q, cs.total_paths, has_env_any, nent, s);
     }
-    if (rec_key) launch_put_u64(owner->d.rec_key, rec_key, s);
-    launch_film(cs.cams, cs.pixoff, ncam, spp, L, cs.total_pix, out, owner->d.err, s);
+    launch_film(cs.cams, cs.pixoff, ncam, spp, L, cs.total_pix, out, owner->d.err, s,
+                rec_key ? owner->d.rec_key : nullptr, rec_key);
     if (o.debug_sample_radiance) launch_sample_radiance(p, L, cs.total_paths, o.debug_sample_radiance, s);
     HIPCHK(hipGetLastError());
     return ST_OK;
@@ -990,6 +990,7 @@ int st_render_noalloc(st_scene* sc, const st_camera* cams, int32_t ncam, int32_t
     p.rec_face = nullptr;        // no hit records: the scene's record buffer is not touched
     p.rec_occ = nullptr;
     p.rec_n = 0;
+    p.rec_key_dev = nullptr;
     if (mega) {
         launch_forward_mega(p, L, cs.total_paths, spill, NOALLOC_TRACE_GRID, s);
     } else {
@@ -1153,6 +1154,7 @@ int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_
         fp.rec_face = nullptr;
         fp.rec_occ = nullptr;
         fp.rec_n = 0;
+        fp.rec_key_dev = nullptr;
         launch_primary_edges(p, fp, q, (float*)sc->sidebuf.p, hside, cs.total_edges, sc->d.has_env ? 1 : 0, s);
     }
     if (nls > 0) launch_shadow_edges(p, cs.total_edges, nls, s);

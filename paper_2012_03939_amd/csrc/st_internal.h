@@ -153,6 +153,7 @@ struct FwdParams {
     int* rec_face;           // optional hit records of the main paths: face of bounce k at [(k-1) rec_n + path]
     uint32_t* rec_occ;       // occluded shadow entries (bit l) of bounce k at [(k-1) rec_n + path]
     long long rec_n;
+    unsigned long long* rec_key_dev;  // with rec_face: the records' key word, cleared by the first camera kernel
 };
 
 void launch_scene_geometry(SceneDev& s, hipStream_t st);
@@ -166,8 +167,10 @@ void launch_forward_wavefront(const FwdParams& p, Queues& q, long long total, in
                               hipStream_t st);
 void launch_wavefront_bounces(const FwdParams& p, Queues& q, int n, int has_env_any, hipStream_t st);
 void launch_forward_mega(const FwdParams& p, float* L, long long total, uint32_t* spill, int grid, hipStream_t st);
+// key_dev (optional): receives key before the film is written (the forward is complete)
 void launch_film(const DevCam* cams, const long long* pixoff, int ncam, int spp, const float* L,
-                 long long npix, float* out, uint32_t* err, hipStream_t st);
+                 long long npix, float* out, uint32_t* err, hipStream_t st, unsigned long long* key_dev = nullptr,
+                 unsigned long long key = 0);
 // sets ERR_NAN in *err when a[0..na) or b[0..nb) holds a non-finite value
 void launch_check_finite(const float* a, long long na, const float* b, long long nb, uint32_t* err, hipStream_t st);
 void launch_sample_radiance(const FwdParams& p, const float* L, long long total, float* out, hipStream_t st);

@@ -48,6 +48,8 @@ __device__ __forceinline__ void final_hash(const FwdParams& p, float* const* r, 
 __global__ void k_camera(FwdParams p, Queues q, long long q0, int n) {
     const int stride = gridDim.x * blockDim.x;
     if (blockIdx.x == 0 && threadIdx.x < 64) q.cnt[threadIdx.x] = threadIdx.x == 1 ? n : 0;
+    // the hit records are rewritten from here on: their key is cleared until k_film
+    if (q0 == 0 && blockIdx.x == 0 && threadIdx.x == 0 && p.rec_key_dev) *p.rec_key_dev = 0ull;
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < FETCH_INTS; j += stride) q.fetch[j] = 0;
     float* const* r = q.ray[1];
     for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += stride) {
@@ -412,7 +414,9 @@ __global__ void __launch_bounds__(TRACE_BLOCK) k_forward_mega(FwdParams p, float
 
 // film: average the spp samples of each pixel in sample order
 __global__ void k_film(const DevCam* __restrict__ cams, const long long* __restrict__ pixoff, int ncam, int spp,
-                       const float* __restrict__ L, long long npix, float* out, uint32_t* err) {
+                       const float* __restrict__ L, long long npix, float* out, uint32_t* err,
+                       unsigned long long* key_dev, unsigned long long key) {
+    if (key_dev && blockIdx.x == 0 && threadIdx.x == 0) *key_dev = key;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < npix; g += stride) {
         const int v = find_view(pixoff, ncam, g);
@@ -523,9 +527,9 @@ void launch_forward_mega(const FwdParams& p, float* L, long long total, uint32_t
 }
 
 void launch_film(const DevCam* cams, const long long* pixoff, int ncam, int spp, const float* L, long long npix,
-                 float* out, uint32_t* err, hipStream_t st) {
+                 float* out, uint32_t* err, hipStream_t st, unsigned long long* key_dev, unsigned long long key) {
     ST_LAUNCH("k_film", k_film, dim3(grid_for(npix, 256, 1u << 16)), dim3(256), 0, st, cams, pixoff, ncam, spp, L,
-                       npix, out, err);
+                       npix, out, err, key_dev, key);
 }
 
 void launch_sample_radiance(const FwdParams& p, const float* L, long long total, float* out, hipStream_t st) {

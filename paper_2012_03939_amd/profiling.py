@@ -135,6 +135,45 @@ def trace_table(stats_csv: str, top: int = 24):
     return "\n".join(lines)
 
 
+def busy_phases(trace_csv: str, gap_ms: float = 100.0):
+    """Split a rocprofv3 kernel trace at idle gaps longer than gap_ms and report,
+    per phase, the wall time from its first kernel start to its last kernel end,
+    the time during which at least one kernel ran (union of the intervals), the
+    summed kernel durations, the launch count and the kernels by summed time."""
+    ev = []
+    with open(trace_csv) as fh:
+        for r in csv.DictReader(fh):
+            ev.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), _short(r["Kernel_Name"])))
+    ev.sort()
+    phases, cur, last_end = [], [], None
+    for e in ev:
+        if cur and e[0] - last_end > gap_ms * 1e6:
+            phases.append(cur)
+            cur = []
+        cur.append(e)
+        last_end = e[1] if last_end is None or not cur[:-1] else max(last_end, e[1])
+    if cur:
+        phases.append(cur)
+    out = []
+    for ph in phases:
+        busy, s0, e0 = 0, None, None
+        for a, b, _ in ph:
+            if e0 is None or a > e0:
+                if e0 is not None:
+                    busy += e0 - s0
+                s0, e0 = a, b
+            else:
+                e0 = max(e0, b)
+        busy += e0 - s0
+        per = collections.defaultdict(float)
+        for a, b, n in ph:
+            per[n] += (b - a) / 1e6
+        out.append({"wall_ms": (max(b for _, b, _ in ph) - ph[0][0]) / 1e6, "busy_ms": busy / 1e6,
+                    "kernel_sum_ms": sum((b - a) for a, b, _ in ph) / 1e6, "launches": len(ph),
+                    "kernels": dict(sorted(per.items(), key=lambda kv: -kv[1]))})
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -150,7 +189,13 @@ def main(argv=None):
     t.add_argument("--title", default="Kernel times")
     t.add_argument("--command", default="")
     t.add_argument("--notes", default="")
+    b = sub.add_parser("busy")
+    b.add_argument("--trace", required=True, help="run_kernel_trace.csv of a --kernel-trace run")
+    b.add_argument("--gap-ms", type=float, default=100.0)
     a = ap.parse_args(argv)
+    if a.cmd == "busy":
+        print(json.dumps(busy_phases(a.trace, a.gap_ms), indent=1))
+        return 0
     if a.cmd == "copyref":
         copy_reference()
     elif a.cmd == "pmc":
