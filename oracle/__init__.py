@@ -22,7 +22,11 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.cpp")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# ORACLE_SANITIZE=1 selects the AddressSanitizer + UndefinedBehaviorSanitizer
+# build (run with the ASan runtime preloaded into the Python process:
+# LD_PRELOAD=$(gcc -print-file-name=libasan.so) ASAN_OPTIONS=detect_leaks=0)
+SANITIZE = os.environ.get("ORACLE_SANITIZE", "") == "1"
+_LIB = os.path.join(_HERE, "liboracle_san.so" if SANITIZE else "liboracle.so")
 _lib = None
 
 FLAG_INTERIOR = 1
@@ -31,10 +35,13 @@ FLAG_SECONDARY = 4
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with g++ (double precision, no FP contraction)."""
+    """Compile the oracle with g++ (double precision, no FP contraction); the
+    sanitizer build adds -fsanitize=address,undefined and stops at the first
+    undefined-behaviour report."""
     if force or not os.path.exists(_LIB):
-        cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off", "-pthread",
-               _SRC, "-o", _LIB + ".tmp"]
+        san = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-g"]
+        cmd = ["g++", "-O1" if SANITIZE else "-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off", "-pthread",
+               *(san if SANITIZE else []), _SRC, "-o", _LIB + ".tmp"]
         subprocess.check_call(cmd)
         os.replace(_LIB + ".tmp", _LIB)
     return _LIB

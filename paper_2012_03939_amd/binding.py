@@ -14,8 +14,10 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-# SHAPETRACE_LIB selects another build of the same library (tuning variants)
-LIB_PATH = os.environ.get("SHAPETRACE_LIB", os.path.join(_HERE, "libshapetrace.so"))
+# SHAPETRACE_LIB selects another build of the same library (tuning variants);
+# SHAPETRACE_SANITIZE=1 the host-sanitized build (build(sanitize=True))
+LIB_PATH = os.environ.get("SHAPETRACE_LIB", os.path.join(
+    _HERE, "libshapetrace_san.so" if os.environ.get("SHAPETRACE_SANITIZE", "") == "1" else "libshapetrace.so"))
 
 ST_GRAD_INTERIOR = 1
 ST_EDGE_PRIMARY = 2

@@ -131,3 +131,24 @@ def test_short_optimisation_reduces_loss(B):
     r = run(steps=25, nviews=8, res=64, spp=4, bounces=2, target_spp=16)
     _say(f"  {r}")
     assert r["image_l2_last"] < 0.9 * r["image_l2_first"]
+
+
+def test_optimisation_resumes_from_a_checkpoint(B):
+    """3 steps with a checkpoint, then a resumed run to 6 steps, against 6 steps
+    without interruption (same per-step seeds and Adam state; the adjoint's float
+    atomics may sum in another order)."""
+    import os
+    import tempfile
+    from paper_2012_03939_amd.optimise import load_checkpoint, run
+    print("case optimisation checkpoint: 3 steps + resume to 6 vs 6 uninterrupted", flush=True)
+    kw = dict(nviews=4, res=48, spp=4, bounces=2, target_spp=8)
+    path = os.path.join(tempfile.mkdtemp(), "opt.pt")
+    run(steps=3, checkpoint=path, checkpoint_every=3, **kw)
+    assert load_checkpoint(path)["step"] == 2
+    resumed = run(steps=6, checkpoint=path, resume=True, return_params=True, **kw)
+    plain = run(steps=6, return_params=True, **kw)
+    dv = (resumed["V"] - plain["V"]).abs().max().item()
+    dm = (resumed["M"] - plain["M"]).abs().max().item()
+    print(f"  max |dV| {dv:.2e} max |dM| {dm:.2e}", flush=True)
+    assert dv < 1e-5 and dm < 1e-4
+    assert abs(resumed["image_l2_last"] - plain["image_l2_last"]) < 1e-4 * plain["image_l2_last"]
