@@ -90,6 +90,8 @@ def parse():
     ap.add_argument("--batched-trace", action="store_true",
                     help="one per-view pass, then one batched pass of the 4-scene workload, 0.3 s apart (for "
                          "rocprofv3 kernel traces)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip st_autotune (wavefront chunk size and traversal grid) before the warm-up")
     ap.add_argument("--copy-reference", action="store_true",
                     help="only a plain 512 MiB device copy: the reference that scales the HBM byte counters")
     return ap.parse_args()
@@ -306,6 +308,10 @@ def main():
         torch.cuda.synchronize()
         return a.elapsed_time(b) / n
 
+    # the library's autotuner picks the wavefront chunk size and the traversal
+    # grid for this workload (timed renders, before the warm-up); later renders
+    # and backward passes of the scene use them
+    tuned = (None, None) if args.no_autotune else B.autotune([g], cams, spp, bounces)
     if args.profile_only:
         step(0)
         torch.cuda.synchronize()
@@ -394,7 +400,8 @@ def main():
                    "spp": spp, "bounces": bounces, "path_samples_per_step": n_paths,
                    "edge_samples_per_step": B.num_edge_samples(cams, spp, 1.0, int(sc.lights.shape[0])),
                    "envmap": "512x256", "env_sampler": args.env_sampler, "bsdf_sampler": args.bsdf_sampler,
-                   "edge_sampler": args.edge_sampler},
+                   "edge_sampler": args.edge_sampler, "autotuned_queue_capacity": tuned[0],
+                   "autotuned_trace_grid": tuned[1]},
         "roofline": {"bound": "alu", "kernel": dom_name, "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": (mc or {}).get("traffic"),
                      "flops_per_node_visit": FLOPS_PER_VISIT, "flops_per_tri_test": FLOPS_PER_TEST,

@@ -83,7 +83,8 @@ typedef struct {
     uint32_t flags;                  /* ST_GRAD_* | ST_EDGE_* | ST_FORWARD_MEGAKERNEL */
     float edge_spp_ratio;            /* primary edge samples per (pixel x spp) of each view; with
                                         ST_EDGE_SHADOW as many shadow-edge samples per (view, light) */
-    int64_t queue_capacity;          /* wavefront chunk size in path samples (0: library default) */
+    int64_t queue_capacity;          /* wavefront chunk size in path samples (0: the scene's autotuned value,
+                                        else 2^24) */
     uint32_t* debug_decision_hash;   /* device, optional: one FNV-1a hash of the discrete decisions per
                                         path sample, index ((pixel offset of view + y*W + x) * spp + j) */
     uint32_t* debug_edge_hash;       /* device, optional (backward): one hash per primary edge sample,
@@ -246,7 +247,7 @@ int st_render_batch(st_scene* const* scenes, int32_t nscenes, const st_camera* c
 
 /* Autotuner: times st_render of this exact workload (same arguments as
  * st_render_batch; cam_scene may be NULL for one scene) over wavefront chunk
- * sizes {2^20..2^24} x traversal grids {1024, 2048, 4096} blocks and keeps the
+ * sizes {2^20..2^26} x traversal grids {1024, 2048, 4096} blocks and keeps the
  * fastest on every scene in the list; later renders and backward passes of
  * those scenes use it unless opts->queue_capacity is set.  cache_path (may be
  * NULL): JSON-lines file keyed by device and workload signature; a matching

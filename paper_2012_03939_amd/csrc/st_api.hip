@@ -312,6 +312,10 @@ uint64_t record_key(const st_scene* sc, const st_camera* cams, int ncam, int spp
 }
 
 constexpr size_t REC_MAX_BYTES = 16ull << 30;
+// wavefront chunk (paths per pass of the bounce kernels) without tuning: each
+// launch ends in a drain where its longest rays run alone, so larger chunks
+// waste less; 2^24 paths hold about 3.3 GB of queues with one shadow entry
+constexpr long long DEFAULT_QUEUE_CAP = 1ll << 24;
 
 
 // wavefront chunk capacity actually used for a requested one (shadow entries
@@ -391,7 +395,7 @@ int render_impl(st_scene* owner, st_scene* const* scenes, int nscenes, const st_
     }
     // workspace of the call, checked against the caller's cap before any kernel
     const bool mega = (o.flags & ST_FORWARD_MEGAKERNEL) != 0;
-    long long cap = o.queue_capacity > 0 ? o.queue_capacity : (owner->tuned_cap > 0 ? owner->tuned_cap : (1ll << 22));
+    long long cap = o.queue_capacity > 0 ? o.queue_capacity : (owner->tuned_cap > 0 ? owner->tuned_cap : DEFAULT_QUEUE_CAP);
     cap = std::min<long long>(cap, std::max<long long>(cs.total_paths, 1));
     cap = std::min<long long>(cap, 1ll << 28);
     const size_t need = (size_t)cs.total_paths * 3 * sizeof(float) + SPILL_BYTES +
@@ -1046,7 +1050,7 @@ int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_
     const bool defer_sec = (o.flags & ST_EDGE_SECONDARY) && !o.debug_decision_hash && cs.total_paths > 0 && ne > 0;
     const bool prim = (o.flags & ST_EDGE_PRIMARY) && cs.total_edges > 0 && ne > 0;
     const int nent_side = sc->d.nl + (sc->d.has_env ? 1 : 0);
-    long long side_cap = o.queue_capacity > 0 ? o.queue_capacity : (sc->tuned_cap > 0 ? sc->tuned_cap : (1ll << 22));
+    long long side_cap = o.queue_capacity > 0 ? o.queue_capacity : (sc->tuned_cap > 0 ? sc->tuned_cap : DEFAULT_QUEUE_CAP);
     side_cap = std::min<long long>(side_cap, std::max<long long>(2 * cs.total_edges, 2));
     side_cap = std::min<long long>(side_cap, 1ll << 28) & ~1ll;
     if (prim && 2 * cs.total_edges >= (1ll << 32)) return fail(ST_ERR_INVALID_ARG, "too many primary edge samples");
@@ -1209,7 +1213,7 @@ int st_autotune(st_scene* const* scenes, int32_t nscenes, const st_camera* cams,
         hipEvent_t e0, e1;
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
-        const long long caps[] = {1ll << 24, 1ll << 23, 1ll << 22, 1ll << 21, 1ll << 20};
+        const long long caps[] = {1ll << 26, 1ll << 25, 1ll << 24, 1ll << 23, 1ll << 22, 1ll << 21, 1ll << 20};
         const int grids[] = {4096, 2048, 1024};
         float best_ms = 1e30f;
         st_render_opts o = st_render_opts_default();
