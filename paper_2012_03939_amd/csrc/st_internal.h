@@ -140,6 +140,33 @@ struct Queues {
 
 __device__ __forceinline__ uint32_t& qu(float* const* cols, int c, int i) { return ((uint32_t*)cols[c])[i]; }
 
+// Queue streams (rays, hits, shading records, shadow entries) are written once
+// and read once or twice per bounce, gigabytes per pass: with ST_QUEUE_NT they
+// move with non-temporal hints, so that they do not evict the data the
+// kernels do reuse from the caches (BVH nodes, triangles, materials, the
+// environment map and its sampling tables).
+#ifndef ST_QUEUE_NT
+#define ST_QUEUE_NT 1
+#endif
+template <class T> __device__ __forceinline__ T qld(const T* p) {
+#if ST_QUEUE_NT
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
+template <class T> __device__ __forceinline__ void qst(T* p, T v) {
+#if ST_QUEUE_NT
+    __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
+}
+__device__ __forceinline__ float qf(float* const* cols, int c, int i) { return qld(cols[c] + i); }
+__device__ __forceinline__ uint32_t qu_ld(float* const* cols, int c, int i) { return qld((const uint32_t*)cols[c] + i); }
+__device__ __forceinline__ void qf_st(float* const* cols, int c, int i, float v) { qst(cols[c] + i, v); }
+__device__ __forceinline__ void qu_st(float* const* cols, int c, int i, uint32_t v) { qst((uint32_t*)cols[c] + i, v); }
+
 struct FwdParams {
     const DevScene* scenes;
     const DevCam* cams;

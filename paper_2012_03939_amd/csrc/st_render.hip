@@ -64,12 +64,12 @@ __global__ void k_camera(FwdParams p, Queues q, long long q0, int n) {
         const V3 d = cam_dir(c, (float)x + u.x, (float)y + u.y);
         // origin (the eye), previous pdf, throughput and hash of a camera ray are
         // constants that the bounce-1 kernels take from the camera themselves
-        r[QDX][s] = d.x; r[QDY][s] = d.y; r[QDZ][s] = d.z;
-        qu(r, QEXCL, s) = 0xFFFFFFFFu;
-        qu(r, QQ, s) = (uint32_t)qq;
-        qu(r, QC0, s) = ctr.c0;
-        qu(r, QC1, s) = ctr.c1;
-        qu(r, QVD, s) = (uint32_t)v;
+        qf_st(r, QDX, s, d.x); qf_st(r, QDY, s, d.y); qf_st(r, QDZ, s, d.z);
+        qu_st(r, QEXCL, s, 0xFFFFFFFFu);
+        qu_st(r, QQ, s, (uint32_t)qq);
+        qu_st(r, QC0, s, ctr.c0);
+        qu_st(r, QC1, s, ctr.c1);
+        qu_st(r, QVD, s, (uint32_t)v);
         q.L[3 * (size_t)qq] = 0.0f; q.L[3 * (size_t)qq + 1] = 0.0f; q.L[3 * (size_t)qq + 2] = 0.0f;
     }
 }
@@ -88,12 +88,12 @@ __global__ void __launch_bounds__(TRACE_BLOCK) EXTEND_OCC k_extend(FwdParams p, 
         trace_queue<false>(
             q.fetch + FETCH_SLOT_INTS * (16 + k), n, st,
             [&](int i, RayJob& J) {
-                const DevCam& cam = p.cams[qu(r, QVD, i) & 0xFFFFu];
+                const DevCam& cam = p.cams[qu_ld(r, QVD, i) & 0xFFFFu];
                 const DevScene& S = p.scenes[cam.scene];
-                J.o = k == 1 ? ld3(cam.eye) : V3{r[QOX][i], r[QOY][i], r[QOZ][i]};
-                J.d = V3{r[QDX][i], r[QDY][i], r[QDZ][i]};
+                J.o = k == 1 ? ld3(cam.eye) : V3{qf(r, QOX, i), qf(r, QOY, i), qf(r, QOZ, i)};
+                J.d = V3{qf(r, QDX, i), qf(r, QDY, i), qf(r, QDZ, i)};
                 J.tmax = __int_as_float(0x7f800000);
-                J.excl = (int)qu(r, QEXCL, i);
+                J.excl = (int)qu_ld(r, QEXCL, i);
                 J.G = trace_geo(S);
                 return true;
             },
@@ -106,11 +106,11 @@ __global__ void __launch_bounds__(TRACE_BLOCK) EXTEND_OCC k_extend(FwdParams p, 
     // 64 consecutive queue entries per wave, traced in lockstep
     const int stride = gridDim.x * blockDim.x;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const DevCam& cam = p.cams[qu(r, QVD, i) & 0xFFFFu];
+        const DevCam& cam = p.cams[qu_ld(r, QVD, i) & 0xFFFFu];
         const DevScene& S = p.scenes[cam.scene];
-        const V3 o = k == 1 ? ld3(cam.eye) : V3{r[QOX][i], r[QOY][i], r[QOZ][i]};
-        const V3 d{r[QDX][i], r[QDY][i], r[QDZ][i]};
-        uint32_t ex = qu(r, QEXCL, i);
+        const V3 o = k == 1 ? ld3(cam.eye) : V3{qf(r, QOX, i), qf(r, QOY, i), qf(r, QOZ, i)};
+        const V3 d{qf(r, QDX, i), qf(r, QDY, i), qf(r, QDZ, i)};
+        uint32_t ex = qu_ld(r, QEXCL, i);
         float t0 = __int_as_float(0x7f800000);
         int f0 = -1;
         if (k == 1 && ex != 0xFFFFFFFFu) {
@@ -132,8 +132,8 @@ __global__ void __launch_bounds__(TRACE_BLOCK) EXTEND_OCC k_extend(FwdParams p, 
         }
         float t;
         const int f = trace_closest(S, o, d, TMIN, (int)ex, t, st, t0, f0);
-        q.ht[i] = t;
-        q.hf[i] = f;
+        qst(q.ht + i, t);
+        qst(q.hf + i, f);
     }
 }
 
@@ -169,34 +169,39 @@ __global__ void __launch_bounds__(SHADE_BLOCK) SHADE_OCC k_shade(FwdParams p, Qu
         float pb = 0.0f;
         int f = -1;
         uint32_t hv = 0;
+        // path identity (slot, counters, camera | domain), carried to the continuation
+        uint32_t pq = 0, c0 = 0, c1 = 0, vd = 0;
         if (active) {
-            const uint32_t c0 = qu(r, QC0, i), c1 = qu(r, QC1, i), vd = qu(r, QVD, i);
+            pq = qu_ld(r, QQ, i);
+            c0 = qu_ld(r, QC0, i);
+            c1 = qu_ld(r, QC1, i);
+            vd = qu_ld(r, QVD, i);
             const DevScene& S = p.scenes[p.cams[vd & 0xFFFFu].scene];
             const Key key{p.seed, S.scene_id};
             const Ctr ctr{c0, c1, 0u, vd >> 16};
-            Hash h{hashing ? (k == 1 ? FNV_INIT : qu(r, QHASH, i)) : 0u, hashing};
-            beta = k == 1 ? V3{1.f, 1.f, 1.f} : V3{r[QBR][i], r[QBG][i], r[QBB][i]};
-            f = q.hf[i];
+            Hash h{hashing ? (k == 1 ? FNV_INIT : qu_ld(r, QHASH, i)) : 0u, hashing};
+            beta = k == 1 ? V3{1.f, 1.f, 1.f} : V3{qf(r, QBR, i), qf(r, QBG, i), qf(r, QBB, i)};
+            f = qld(q.hf + i);
             push_face(h, f);
-            if (p.rec_face && (vd >> 16) == 0u) p.rec_face[(size_t)(k - 1) * p.rec_n + qu(r, QQ, i)] = f;
+            if (p.rec_face && (vd >> 16) == 0u) p.rec_face[(size_t)(k - 1) * p.rec_n + pq] = f;
             if (!fused) q.sface[i] = -1;
-            const V3 d{r[QDX][i], r[QDY][i], r[QDZ][i]};
+            const V3 d{qf(r, QDX, i), qf(r, QDY, i), qf(r, QDZ, i)};
             if (f < 0) {
                 if (S.has_env && k > 1) {
                     const int tex = env_texel_of(S, d);
                     h.push((uint32_t)tex);
-                    const float pp = r[QPPREV][i];
+                    const float pp = qf(r, QPPREV, i);
                     const float w = pp / (pp + S.texpdf[tex]);
                     const V3 c = mul(beta, env_rgb(S, tex)) * w;
-                    float* L = q.L + 3 * (size_t)qu(r, QQ, i);
+                    float* L = q.L + 3 * (size_t)pq;
                     L[0] += c.x; L[1] += c.y; L[2] += c.z;
                 }
                 if (hashing) final_hash(p, r, i, h.h);
             } else if (k > p.B) {
                 if (hashing) final_hash(p, r, i, h.h);
             } else {
-                const V3 o = k == 1 ? ld3(p.cams[vd & 0xFFFFu].eye) : V3{r[QOX][i], r[QOY][i], r[QOZ][i]};
-                x = o + d * q.ht[i];
+                const V3 o = k == 1 ? ld3(p.cams[vd & 0xFFFFu].eye) : V3{qf(r, QOX, i), qf(r, QOY, i), qf(r, QOZ, i)};
+                x = o + d * qld(q.ht + i);
                 V3 n = xyz(S.fnorm[f]);
                 const V3 wo = -d;
                 if (dot(n, wo) < 0.0f) n = -n;
@@ -219,8 +224,8 @@ __global__ void __launch_bounds__(SHADE_BLOCK) SHADE_OCC k_shade(FwdParams p, Qu
                         }
                     }
                     const size_t e = (size_t)l * q.cap + i;
-                    q.sh[0][e] = wl.x; q.sh[1][e] = wl.y; q.sh[2][e] = wl.z; q.sh[3][e] = tmax;
-                    q.sh[4][e] = ct.x; q.sh[5][e] = ct.y; q.sh[6][e] = ct.z;
+                    qst(q.sh[0] + e, wl.x); qst(q.sh[1] + e, wl.y); qst(q.sh[2] + e, wl.z); qst(q.sh[3] + e, tmax);
+                    qst(q.sh[4] + e, ct.x); qst(q.sh[5] + e, ct.y); qst(q.sh[6] + e, ct.z);
                     if (tmax >= 0.0f) rays |= 1u << l;
                     else if (!fused) q.socc[e] = 0;
                 }
@@ -238,8 +243,8 @@ __global__ void __launch_bounds__(SHADE_BLOCK) SHADE_OCC k_shade(FwdParams p, Qu
                         ct = mul(beta, mul(env_rgb(S, tex), brdf_eval(we, wo, n, m))) * (c / den);
                     }
                     const size_t e = (size_t)S.nl * q.cap + i;
-                    q.sh[0][e] = we.x; q.sh[1][e] = we.y; q.sh[2][e] = we.z; q.sh[3][e] = tmax;
-                    q.sh[4][e] = ct.x; q.sh[5][e] = ct.y; q.sh[6][e] = ct.z;
+                    qst(q.sh[0] + e, we.x); qst(q.sh[1] + e, we.y); qst(q.sh[2] + e, we.z); qst(q.sh[3] + e, tmax);
+                    qst(q.sh[4] + e, ct.x); qst(q.sh[5] + e, ct.y); qst(q.sh[6] + e, ct.z);
                     if (tmax >= 0.0f) rays |= 1u << S.nl;
                     else if (!fused) q.socc[e] = 0;
                 }
@@ -256,12 +261,12 @@ __global__ void __launch_bounds__(SHADE_BLOCK) SHADE_OCC k_shade(FwdParams p, Qu
                         beta = mul(beta, brdf_eval(wi, wo, n, m)) * (ci / pb);
                     }
                 }
-                q.sface[i] = f;
+                qst(q.sface + i, f);
                 if (!fused) q.sinfo[i] = info;
                 if (shadow_fused(p, q) && p.rec_occ && (vd >> 16) == 0u)
-                    p.rec_occ[(size_t)(k - 1) * p.rec_n + qu(r, QQ, i)] = 0u;
+                    p.rec_occ[(size_t)(k - 1) * p.rec_n + pq] = 0u;
                 if (!fused) q.stex[i] = tex;
-                q.sx[0][i] = x.x; q.sx[1][i] = x.y; q.sx[2][i] = x.z;
+                qst(q.sx[0] + i, x.x); qst(q.sx[1] + i, x.y); qst(q.sx[2] + i, x.z);
                 if (!fused) q.snext[i] = -1;
             }
             hv = h.h;
@@ -280,19 +285,19 @@ __global__ void __launch_bounds__(SHADE_BLOCK) SHADE_OCC k_shade(FwdParams p, Qu
             rays = 0;
         }
         for (int so = oo.y; rays; rays &= rays - 1, ++so)
-            q.slist[so] = (uint32_t)(__ffs(rays) - 1) * (uint32_t)q.cap + (uint32_t)i;
+            qst(q.slist + so, (uint32_t)(__ffs(rays) - 1) * (uint32_t)q.cap + (uint32_t)i);
         {
             if (emit) {
-                rn[QOX][o] = x.x; rn[QOY][o] = x.y; rn[QOZ][o] = x.z;
-                rn[QDX][o] = wi.x; rn[QDY][o] = wi.y; rn[QDZ][o] = wi.z;
-                qu(rn, QEXCL, o) = (uint32_t)f;
-                rn[QPPREV][o] = pb;
-                qu(rn, QQ, o) = qu(r, QQ, i);
-                qu(rn, QC0, o) = qu(r, QC0, i);
-                qu(rn, QC1, o) = qu(r, QC1, i);
-                qu(rn, QVD, o) = qu(r, QVD, i);
-                rn[QBR][o] = beta.x; rn[QBG][o] = beta.y; rn[QBB][o] = beta.z;
-                if (hashing) qu(rn, QHASH, o) = hv;
+                qf_st(rn, QOX, o, x.x); qf_st(rn, QOY, o, x.y); qf_st(rn, QOZ, o, x.z);
+                qf_st(rn, QDX, o, wi.x); qf_st(rn, QDY, o, wi.y); qf_st(rn, QDZ, o, wi.z);
+                qu_st(rn, QEXCL, o, (uint32_t)f);
+                qf_st(rn, QPPREV, o, pb);
+                qu_st(rn, QQ, o, pq);
+                qu_st(rn, QC0, o, c0);
+                qu_st(rn, QC1, o, c1);
+                qu_st(rn, QVD, o, vd);
+                qf_st(rn, QBR, o, beta.x); qf_st(rn, QBG, o, beta.y); qf_st(rn, QBB, o, beta.z);
+                if (hashing) qu_st(rn, QHASH, o, hv);
                 if (!fused) q.snext[i] = o;
             }
         }
@@ -315,7 +320,7 @@ __global__ void __launch_bounds__(TRACE_BLOCK) SHADOW_OCC k_shadow(FwdParams p, 
             [&](int w, RayJob& J) {
                 const uint32_t e = q.slist[w];
                 const int i = (int)(e % (uint32_t)q.cap);
-                const DevScene& S = p.scenes[p.cams[qu(r, QVD, i) & 0xFFFFu].scene];
+                const DevScene& S = p.scenes[p.cams[qu_ld(r, QVD, i) & 0xFFFFu].scene];
                 J.o = V3{q.sx[0][i], q.sx[1][i], q.sx[2][i]};
                 J.d = V3{q.sh[0][e], q.sh[1][e], q.sh[2][e]};
                 J.tmax = q.sh[3][e];
@@ -330,19 +335,19 @@ __global__ void __launch_bounds__(TRACE_BLOCK) SHADOW_OCC k_shadow(FwdParams p, 
     // 64 consecutive listed rays per wave, traced in lockstep
     const int stride = gridDim.x * blockDim.x;
     for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < items; w += stride) {
-        const uint32_t e = q.slist[w];
+        const uint32_t e = qld(q.slist + w);
         const int i = (int)(e % (uint32_t)q.cap);
-        const int f = q.sface[i];
-        const DevScene& S = p.scenes[p.cams[qu(r, QVD, i) & 0xFFFFu].scene];
-        const float tmax = q.sh[3][e];
-        const V3 o{q.sx[0][i], q.sx[1][i], q.sx[2][i]}, dd{q.sh[0][e], q.sh[1][e], q.sh[2][e]};
+        const int f = qld(q.sface + i);
+        const DevScene& S = p.scenes[p.cams[qu_ld(r, QVD, i) & 0xFFFFu].scene];
+        const float tmax = qld(q.sh[3] + e);
+        const V3 o{qld(q.sx[0] + i), qld(q.sx[1] + i), qld(q.sx[2] + i)}, dd{qld(q.sh[0] + e), qld(q.sh[1] + e), qld(q.sh[2] + e)};
         const bool occluded = trace_any(S, o, dd, TMIN, tmax, f, st);
         if (fused) {
             if (occluded) {
-                if (p.rec_occ && (qu(r, QVD, i) >> 16) == 0u) p.rec_occ[(size_t)(k - 1) * p.rec_n + qu(r, QQ, i)] = 1u;
+                if (p.rec_occ && (qu_ld(r, QVD, i) >> 16) == 0u) p.rec_occ[(size_t)(k - 1) * p.rec_n + qu_ld(r, QQ, i)] = 1u;
             } else {
-                float* L = q.L + 3 * (size_t)qu(r, QQ, i);
-                L[0] += q.sh[4][e]; L[1] += q.sh[5][e]; L[2] += q.sh[6][e];
+                float* L = q.L + 3 * (size_t)qu_ld(r, QQ, i);
+                L[0] += qld(q.sh[4] + e); L[1] += qld(q.sh[5] + e); L[2] += qld(q.sh[6] + e);
             }
         } else {
             q.socc[e] = occluded ? 1 : 2;
