@@ -143,6 +143,7 @@ def mesh_colors_step(B, S, torch, wl, r, steps=3):
     g = B.GPUScene.from_scene(sc)
     tex = torch.from_numpy(S.mesh_color_texels(sc.mat, r, np.random.default_rng(8))).cuda()
     g.set_mesh_colors(r, tex)
+    B.autotune([g], wl.cams, wl.spp, wl.bounces)
     npix = B.num_pixels(wl.cams)
     img = torch.empty((npix, 3), dtype=torch.float32, device="cuda")
     dV = torch.empty((g.nv, 3), dtype=torch.float32, device="cuda")

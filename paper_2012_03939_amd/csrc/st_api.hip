@@ -317,6 +317,16 @@ constexpr size_t REC_MAX_BYTES = 16ull << 30;
 // waste less; 2^24 paths hold about 3.3 GB of queues with one shadow entry
 constexpr long long DEFAULT_QUEUE_CAP = 1ll << 24;
 
+// chunk size for n items with at most cap per chunk: the same number of chunks,
+// of equal size (rounded up to an even multiple of 256), so that no chunk is a
+// small remainder paying a full set of launches
+long long balanced_chunk(long long n, long long cap) {
+    if (n <= cap) return std::max<long long>(n, 1);
+    const long long chunks = (n + cap - 1) / cap;
+    const long long c = ((n + chunks - 1) / chunks + 255) & ~255ll;
+    return std::min(c, cap);
+}
+
 
 // wavefront chunk capacity actually used for a requested one (shadow entries
 // are numbered l * n + i in a 32-bit index)
@@ -396,8 +406,8 @@ int render_impl(st_scene* owner, st_scene* const* scenes, int nscenes, const st_
     // workspace of the call, checked against the caller's cap before any kernel
     const bool mega = (o.flags & ST_FORWARD_MEGAKERNEL) != 0;
     long long cap = o.queue_capacity > 0 ? o.queue_capacity : (owner->tuned_cap > 0 ? owner->tuned_cap : DEFAULT_QUEUE_CAP);
-    cap = std::min<long long>(cap, std::max<long long>(cs.total_paths, 1));
     cap = std::min<long long>(cap, 1ll << 28);
+    cap = balanced_chunk(cs.total_paths, cap);
     const size_t need = (size_t)cs.total_paths * 3 * sizeof(float) + SPILL_BYTES +
                         (mega ? 0 : queue_bytes(queue_cap(cap, nent), nent));
     rc = over_budget(o, need);
@@ -1051,8 +1061,8 @@ int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_
     const bool prim = (o.flags & ST_EDGE_PRIMARY) && cs.total_edges > 0 && ne > 0;
     const int nent_side = sc->d.nl + (sc->d.has_env ? 1 : 0);
     long long side_cap = o.queue_capacity > 0 ? o.queue_capacity : (sc->tuned_cap > 0 ? sc->tuned_cap : DEFAULT_QUEUE_CAP);
-    side_cap = std::min<long long>(side_cap, std::max<long long>(2 * cs.total_edges, 2));
-    side_cap = std::min<long long>(side_cap, 1ll << 28) & ~1ll;
+    side_cap = std::min<long long>(side_cap, 1ll << 28);
+    side_cap = balanced_chunk(2 * cs.total_edges, side_cap) & ~1ll;     // two side paths per edge sample
     if (prim && 2 * cs.total_edges >= (1ll << 32)) return fail(ST_ERR_INVALID_ARG, "too many primary edge samples");
     {
         size_t need = SPILL_BYTES + pbytes + (defer_sec ? sec_workspace_bytes(cs.total_paths, bounces) : 0);

@@ -193,7 +193,7 @@ k_adjoint(BwdParams p, long long total) {
                 const size_t ri = (size_t)(k - 1) * p.rec_n + qq;
                 int f;
                 if (rec_face) {
-                    f = rec_face[ri];
+                    f = qld(rec_face + ri);
                     t = f >= 0 ? face_hit_t(S, f, o, d) : __int_as_float(0x7f800000);
                 } else {
                     f = trace_closest(S, o, d, TMIN, excl, t, st);
@@ -218,7 +218,7 @@ k_adjoint(BwdParams p, long long total) {
                 const int tx = texel_of(S, f, xh);
                 if (S.tex_res) h.push((uint32_t)tx);
                 const Mat m = load_mat(S.mat + 7 * (size_t)tx);
-                const uint32_t rocc = rec_occ ? rec_occ[ri] : 0u;
+                const uint32_t rocc = rec_occ ? qld(rec_occ + ri) : 0u;
                 for (int l = 0; l < S.nl; ++l) {
                     const float* lt = S.lights + 6 * l;
                     const V3 dl = ld3(lt) - xh;
@@ -695,9 +695,12 @@ __global__ void k_edge_grad(BwdParams p, const float* __restrict__ Ls, const uin
                         p.dbg_edge_hash[ge] = h.h;
                     }
                     const float* lm = Ls + 6 * ge;
-                    const double cc = ((double)di[0] * ((double)lm[0] - lm[3]) +
-                                       (double)di[1] * ((double)lm[1] - lm[4]) +
-                                       (double)di[2] * ((double)lm[2] - lm[5])) * (p.ptotal[es.v] / (double)c.ne);
+                    float lv[6];
+#pragma unroll
+                    for (int m = 0; m < 6; ++m) lv[m] = qld(lm + m);
+                    const double cc = ((double)di[0] * ((double)lv[0] - lv[3]) +
+                                       (double)di[1] * ((double)lv[1] - lv[4]) +
+                                       (double)di[2] * ((double)lv[2] - lv[5])) * (p.ptotal[es.v] / (double)c.ne);
                     a0 = cc * (1.0 - es.t);
                     a1 = cc * es.t;
                     key = (long long)es.v * p.ne + es.e;

@@ -183,7 +183,7 @@ __global__ void __launch_bounds__(SHADE_BLOCK) SHADE_OCC k_shade(FwdParams p, Qu
             beta = k == 1 ? V3{1.f, 1.f, 1.f} : V3{qf(r, QBR, i), qf(r, QBG, i), qf(r, QBB, i)};
             f = qld(q.hf + i);
             push_face(h, f);
-            if (p.rec_face && (vd >> 16) == 0u) p.rec_face[(size_t)(k - 1) * p.rec_n + pq] = f;
+            if (p.rec_face && (vd >> 16) == 0u) qst(p.rec_face + (size_t)(k - 1) * p.rec_n + pq, f);
             if (!fused) q.sface[i] = -1;
             const V3 d{qf(r, QDX, i), qf(r, QDY, i), qf(r, QDZ, i)};
             if (f < 0) {
@@ -435,7 +435,7 @@ __global__ void k_film(const DevCam* __restrict__ cams, const long long* __restr
         float a = 0.f, b = 0.f, cc = 0.f;
         for (int j = 0; j < spp; ++j) {
             const long long qq = c.qoff + (long long)j * hw + pt;
-            a += L[3 * qq]; b += L[3 * qq + 1]; cc += L[3 * qq + 2];
+            a += qld(L + 3 * qq); b += qld(L + 3 * qq + 1); cc += qld(L + 3 * qq + 2);
         }
         const float inv = 1.0f / (float)spp;
         out[3 * g] = a * inv; out[3 * g + 1] = b * inv; out[3 * g + 2] = cc * inv;
