@@ -92,9 +92,17 @@ def parse():
                          "rocprofv3 kernel traces)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip st_autotune (wavefront chunk size and traversal grid) before the warm-up")
+    ap.add_argument("--autotune-cache", default=None,
+                    help="JSON-lines cache of st_autotune: a workload found there is not timed again (profiling "
+                         "runs reuse the choice of an earlier run)")
     ap.add_argument("--copy-reference", action="store_true",
                     help="only a plain 512 MiB device copy: the reference that scales the HBM byte counters")
     return ap.parse_args()
+
+
+def progress(msg: str) -> None:
+    """One line on stderr when a phase of the run ends (the JSON line stays alone on stdout)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
 def cpu_info():
@@ -312,7 +320,7 @@ def main():
     # the library's autotuner picks the wavefront chunk size and the traversal
     # grid for this workload (timed renders, before the warm-up); later renders
     # and backward passes of the scene use them
-    tuned = (None, None) if args.no_autotune else B.autotune([g], cams, spp, bounces)
+    tuned = (None, None) if args.no_autotune else B.autotune([g], cams, spp, bounces, cache_path=args.autotune_cache)
     if args.profile_only:
         step(0)
         torch.cuda.synchronize()
@@ -320,10 +328,12 @@ def main():
         print(json.dumps({"profile_only": True, "n_paths": n_paths}))
         return
 
+    progress(f"autotuned queue capacity {tuned[0]}, trace grid {tuned[1]}")
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
     g.check_errors()
+    progress(f"{args.warmup} warm-up steps done")
     B.profile_read()
     B.profile_enable(True)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -340,6 +350,7 @@ def main():
     g.check_errors()
     ms = e0.elapsed_time(e1)
     ms_per_step = ms / args.steps
+    progress(f"{args.steps} timed steps: {ms_per_step:.2f} ms per step")
     value = n_paths * args.steps / (ms / 1e3)
 
     # dominant kernel and its algorithmic work, counted on device in one extra (untimed) step
@@ -382,7 +393,9 @@ def main():
                               "frac_of_peak": gbs / PEAK_HBM_GBS if gbs else None}
     # the same step at the workload's own 32 spp, and with every main-path ray traced again in the adjoint
     ms32 = timed_steps(3, spp=2 * spp)
+    progress(f"{2 * spp} spp step: {ms32:.2f} ms")
     ms_retrace = timed_steps(3, extra=B.ST_BACKWARD_RETRACE)
+    progress(f"re-tracing step: {ms_retrace:.2f} ms")
     out = {
         "metric": "fwd+adjoint path samples/sec at 16 views 512^2 16spp; sec per optimisation step",
         "value": value,
@@ -425,13 +438,17 @@ def main():
     }
     if args.mesh_colors_res > 0:
         out["mesh_colors"] = mesh_colors_step(B, S, torch, wl, args.mesh_colors_res)
+        progress(f"mesh-colour step: {out['mesh_colors']['ms_per_step']:.2f} ms")
     if not args.no_batched:
         out["batched"] = batched_vs_per_view(B, S, torch)
+        progress(f"batched speed-up {out['batched']['speedup']:.2f}")
     if args.opt_steps > 0:
         # second half of the metric: seconds per optimisation step (Adam through torch.autograd)
         from paper_2012_03939_amd.optimise import run as optimise
         out["optimisation"] = optimise(steps=args.opt_steps)
+        progress("optimisation loop done")
     if not args.no_cpu_baseline:
+        progress("oracle baseline on the host cores")
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_baseline_res, spp, bounces)
     print(json.dumps(out))
 

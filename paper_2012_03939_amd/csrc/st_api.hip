@@ -1223,7 +1223,7 @@ int st_autotune(st_scene* const* scenes, int32_t nscenes, const st_camera* cams,
         hipEvent_t e0, e1;
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
-        const long long caps[] = {1ll << 26, 1ll << 25, 1ll << 24, 1ll << 23, 1ll << 22, 1ll << 21, 1ll << 20};
+        const long long caps[] = {1ll << 27, 1ll << 26, 1ll << 25, 1ll << 24, 1ll << 23, 1ll << 22, 1ll << 21, 1ll << 20};
         const int grids[] = {4096, 2048, 1024};
         float best_ms = 1e30f;
         st_render_opts o = st_render_opts_default();
