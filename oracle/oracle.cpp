@@ -1270,8 +1270,20 @@ static void primary_edge_sample(const Scene& s, const Cam& c, const EdgeView& ev
     // each side path hashes its own decisions; the sample hash takes both results
     Hash hm, hp;
     hm.on = hp.on = h.on;
-    D3 Lm = trace_estimator(s, c.eye, dm, -1, bounces, false, ctr, key, hm, nullptr, nullptr);
-    D3 Lp = trace_estimator(s, c.eye, dp, -1, bounces, false, ctr, key, hp, nullptr, nullptr);
+    // When the first surface both side rays meet is the same face, the edge
+    // point is hidden behind it: the image has no jump there, and the two paths
+    // would differ only by the smooth change of the integrand across 2 eps (plus
+    // the noise of decisions that flip between them).  Both sides count as zero.
+    double tm, tp;
+    const int fm = closest_hit(s, c.eye, dm, TMIN, -1, tm), fp = closest_hit(s, c.eye, dp, TMIN, -1, tp);
+    D3 Lm(0, 0, 0), Lp(0, 0, 0);
+    if (fm == fp) {
+        push_face(hm, fm);
+        push_face(hp, fp);
+    } else {
+        Lm = trace_estimator(s, c.eye, dm, -1, bounces, false, ctr, key, hm, nullptr, nullptr);
+        Lp = trace_estimator(s, c.eye, dp, -1, bounces, false, ctr, key, hp, nullptr, nullptr);
+    }
     h.push(hm.h);
     h.push(hp.h);
     double cc = 0.0;

@@ -633,8 +633,8 @@ int st_scene_create(const float* V, int32_t nv, const int32_t* F, int32_t nf, co
     A(dalloc(&d.vf_off, (size_t)nv + 1));
     A(dalloc(&d.fe, 3 * (size_t)nf));
     A(dalloc(&d.vf_idx, 3 * (size_t)nf));
-    A(dalloc(&d.facc, 9 * (size_t)nf));
-    A(dalloc(&d.macc, 7 * (size_t)nf));
+    A(dalloc(&d.facc, FACC_STRIDE * (size_t)nf));
+    A(dalloc(&d.macc, MACC_STRIDE));     // per-texel material slots exist only with mesh colours
     A(dalloc(&d.edges, edges.size()));
     A(dalloc(&d.edge_w, edges.size()));
     A(dalloc(&d.eguide, (size_t)1 << guide_log2((int)edges.size())));
@@ -752,7 +752,7 @@ int st_scene_set_mesh_colors(st_scene* sc, int32_t r, const float* texels, hipSt
     if (7 * ntex >= (1ll << 31)) return fail(ST_ERR_INVALID_ARG, "too many texels (7 nf (r+1)(r+2)/2 must be < 2^31)");
     HIPCHK(hipStreamSynchronize(s));
     float *mat = nullptr, *macc = nullptr;
-    if (dalloc(&mat, 7 * (size_t)ntex) || dalloc(&macc, 7 * (size_t)ntex)) {
+    if (dalloc(&mat, 7 * (size_t)ntex) || dalloc(&macc, MACC_STRIDE * (size_t)(r > 0 ? ntex : 1))) {
         if (mat) hipFree(mat);
         if (macc) hipFree(macc);
         return fail(ST_ERR_OOM, "texel arrays");

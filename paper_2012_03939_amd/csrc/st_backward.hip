@@ -78,15 +78,20 @@ constexpr uint32_t R_FLIP = 1u, R_ENV = 2u, R_CONT = 4u, R_ESC = 8u, R_SEC = 16u
 #endif
 constexpr bool FACE_REDUCE = ST_FACE_REDUCE != 0;   // wave-level reduction of the primary-vertex gradients
 
+// material slots of texel tx on face f (face-major accumulators)
+__device__ __forceinline__ float* mat_slots(float* facc, float* macc, bool texels, int f, int tx) {
+    return texels ? macc + (size_t)MACC_STRIDE * tx : facc + (size_t)FACC_STRIDE * f + FACC_MAT;
+}
+
 // Adds vals to the accumulators of face f (slots 0..8: the three corners) and
 // of its texel tx (slots 9..15: the material) with one set of atomics per
 // (texel, wave): lanes of the wave with the same texel (hence the same face)
 // are summed first, peeling one texel per round; partner lanes add into the
 // leader's LDS row.  Primary hits of a wave are the 64 pixels of a tile, so few
 // texels cover most lanes.  Lanes with !has contribute nothing.
-// red: this wave's FACC floats of LDS.  Accumulators are slot-major.
+// red: this wave's FACC floats of LDS.
 __device__ __forceinline__ void face_reduce_add(bool has, int f, int tx, const float (&vals)[FACC], float* facc,
-                                                int nf, float* macc, int ntex, float* red) {
+                                                float* macc, bool texels, float* red) {
     bool pending = has;
     for (;;) {
         const uint64_t m = __ballot(pending);
@@ -107,10 +112,12 @@ __device__ __forceinline__ void face_reduce_add(bool has, int f, int tx, const f
         }
         if (lead) {
             const bool single = grp == (1ull << leader);
+            float* const fa = facc + (size_t)FACC_STRIDE * lf;
+            float* const ma = mat_slots(facc, macc, texels, lf, lt);
 #pragma unroll
-            for (int j = 0; j < 9; ++j) atomicAdd(facc + (size_t)j * nf + lf, single ? vals[j] : red[j]);
+            for (int j = 0; j < 9; ++j) atomicAdd(fa + j, single ? vals[j] : red[j]);
 #pragma unroll
-            for (int j = 0; j < 7; ++j) atomicAdd(macc + (size_t)j * ntex + lt, single ? vals[9 + j] : red[9 + j]);
+            for (int j = 0; j < 7; ++j) atomicAdd(ma + j, single ? vals[9 + j] : red[9 + j]);
         }
         pending = pending && !mine;
     }
@@ -449,12 +456,14 @@ k_adjoint(BwdParams p, long long total) {
                     gxnext = go;
                 }
                 if (k == 0 && FACE_REDUCE) {
-                    face_reduce_add(has, f, tx, vals, p.facc, S.nf, p.macc, p.ntex, red);
+                    face_reduce_add(has, f, tx, vals, p.facc, p.macc, S.tex_res > 0, red);
                 } else if (has) {
+                    float* const fa = p.facc + (size_t)FACC_STRIDE * f;
+                    float* const ma = mat_slots(p.facc, p.macc, S.tex_res > 0, f, tx);
 #pragma unroll
-                    for (int j = 0; j < 9; ++j) atomicAdd(p.facc + (size_t)j * S.nf + f, vals[j]);
+                    for (int j = 0; j < 9; ++j) atomicAdd(fa + j, vals[j]);
 #pragma unroll
-                    for (int j = 0; j < 7; ++j) atomicAdd(p.macc + (size_t)j * p.ntex + tx, vals[9 + j]);
+                    for (int j = 0; j < 7; ++j) atomicAdd(ma + j, vals[9 + j]);
                 }
             }
         }
@@ -785,9 +794,9 @@ __global__ void k_edge_finish(BwdParams p) {
     }
 }
 
-// per-face corner accumulators (slot-major: slot j of face f at j nf + f) to
-// dV (vertex gather over the incidence CSR, fixed order); per-texel material
-// accumulators (slot j of texel t at j ntex + t) to dmat [ntex, 7]
+// per-face corner accumulators (corner c of face f at facc[16 f + 3 c]) to dV
+// (vertex gather over the incidence CSR, fixed order); material accumulators
+// (per face, or per texel with mesh colours) to dmat [ntex, 7]
 __global__ void k_face_gather(BwdParams p) {
     const DevScene& S = p.scenes[0];
     const int stride = gridDim.x * blockDim.x;
@@ -795,16 +804,19 @@ __global__ void k_face_gather(BwdParams p) {
         float sx = 0.f, sy = 0.f, sz = 0.f;
         for (int j = p.vf_off[v]; j < p.vf_off[v + 1]; ++j) {
             const int e = p.vf_idx[j];
-            const float* a = p.facc + (size_t)(3 * (e % 3)) * S.nf + e / 3;
-            sx += a[0]; sy += a[S.nf]; sz += a[2 * (size_t)S.nf];
+            const float* a = p.facc + (size_t)FACC_STRIDE * (e / 3) + 3 * (e % 3);
+            sx += a[0]; sy += a[1]; sz += a[2];
         }
         p.dV[3 * (size_t)v] += sx;
         p.dV[3 * (size_t)v + 1] += sy;
         p.dV[3 * (size_t)v + 2] += sz;
     }
-    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < p.ntex; t += stride)
+    const bool texels = S.tex_res > 0;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < p.ntex; t += stride) {
+        const float* a = mat_slots(p.facc, p.macc, texels, t, t);
 #pragma unroll
-        for (int i = 0; i < 7; ++i) p.dmat[7 * (size_t)t + i] = p.macc[(size_t)i * p.ntex + t];
+        for (int i = 0; i < 7; ++i) p.dmat[7 * (size_t)t + i] = a[i];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1085,8 +1097,8 @@ static void launch_adjoint(const BwdParams& p, long long total_paths, int grid, 
 void launch_backward(const BwdParams& p, int nv, int nf, long long total_paths, long long total_edges, int grid,
                      hipStream_t st) {
     if ((p.flags & 5u) && total_paths > 0) {
-        launch_fill_u32((uint32_t*)p.facc, 9ll * nf, 0u, st);
-        launch_fill_u32((uint32_t*)p.macc, 7ll * p.ntex, 0u, st);
+        launch_fill_u32((uint32_t*)p.facc, (long long)FACC_STRIDE * nf, 0u, st);
+        if (p.ntex != nf) launch_fill_u32((uint32_t*)p.macc, (long long)MACC_STRIDE * p.ntex, 0u, st);
         if (p.B <= 1) launch_adjoint<1>(p, total_paths, grid, "k_adjoint<1>", "k_adjoint_sec<1>", st);
         else if (p.B <= 2) launch_adjoint<2>(p, total_paths, grid, "k_adjoint<2>", "k_adjoint_sec<2>", st);
         else if (p.B <= 3) launch_adjoint<3>(p, total_paths, grid, "k_adjoint<3>", "k_adjoint_sec<3>", st);

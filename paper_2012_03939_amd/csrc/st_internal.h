@@ -21,6 +21,11 @@ extern bool g_prof_on;
 // every device allocation of one scene (library-owned)
 constexpr int TREELET_ROUNDS = 2;   // bottom-up treelet-restructuring passes over the Karras tree
 constexpr int FACC = 16;   // gradient slots of one vertex: 3 corners x xyz, then the 7 material parameters
+// Gradient accumulators are face-major, so that the slots one shading point adds
+// to share a cache line: face f owns facc[16 f .. 16 f + 15] (corners in 0..8;
+// without mesh colours its material in 9..15), and with mesh colours texel t owns
+// macc[8 t .. 8 t + 6].
+constexpr int FACC_STRIDE = 16, MACC_STRIDE = 8, FACC_MAT = 9;
 
 struct SceneDev {
     int nv = 0, nf = 0, nl = 0, he = 0, we = 0, ne = 0;

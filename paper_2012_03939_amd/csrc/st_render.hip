@@ -199,6 +199,12 @@ __global__ void __launch_bounds__(SHADE_BLOCK) SHADE_OCC k_shade(FwdParams p, Qu
                 if (hashing) final_hash(p, r, i, h.h);
             } else if (k > p.B) {
                 if (hashing) final_hash(p, r, i, h.h);
+            } else if (k == 1 && (vd >> 16) == 1u && qld(q.hf + (i ^ 1)) == f) {
+                // the two side rays of a primary edge sample (queue slots 2j and
+                // 2j + 1 at bounce 1) met the same face first: the edge point is
+                // hidden behind it, there is no jump to measure, and both side
+                // paths end here with zero radiance
+                if (hashing) final_hash(p, r, i, h.h);
             } else {
                 const V3 o = k == 1 ? ld3(p.cams[vd & 0xFFFFu].eye) : V3{qf(r, QOX, i), qf(r, QOY, i), qf(r, QOZ, i)};
                 x = o + d * qld(q.ht + i);

@@ -216,3 +216,28 @@ def test_max_workspace_bytes(B):
     g.render(cams, spp, bounces, seed=2, out=out, max_workspace_bytes=hi + 4 * (2 * bounces + 1) * npath)
     assert adjoint_rays(2) < full2                # room for them again
     g.check_errors()
+
+
+def test_hidden_triangle_primary_edges(B):
+    """A triangle wholly behind a larger one under a point light on the camera
+    side: every sampled point of its edges is hidden (both side rays meet the
+    occluder), so the primary edge term gives its vertices exactly zero on both
+    implementations, and the visible triangle's gradient matches the oracle."""
+    _say("case hidden triangle behind an occluder, B=2: primary edge term")
+    front = np.array([[-0.8, -0.7, 0.5], [0.9, -0.6, 0.4], [0.0, 0.9, 0.5]], np.float32)
+    back = np.array([[-0.2, -0.2, -0.5], [0.25, -0.15, -0.6], [0.0, 0.25, -0.5]], np.float32)
+    V = np.concatenate([front, back])
+    F = np.array([[0, 1, 2], [3, 4, 5]], np.int32)
+    lights = np.array([[0.3, 0.4, 2.5, 6.0, 6.0, 6.0]], np.float32)
+    sc = S.Scene(V, F, S.random_materials(2, np.random.default_rng(23)), lights, None)
+    cams = [S.Camera((0.0, 0.0, 3.0), (0, 0, 0), (0, 1, 0), 45.0, 40, 40)]
+    d_img = np.random.default_rng(5).normal(size=(B.num_pixels(cams), 3)).astype(np.float32)
+    g = B.GPUScene.from_scene(sc)
+    dV, _ = g.backward(cams, 8, 2, torch.from_numpy(d_img).cuda(), seed=3, flags=B.ST_EDGE_PRIMARY)
+    g.check_errors()
+    gv = dV.cpu().numpy()
+    assert np.all(gv[3:] == 0.0), gv[3:]
+    pf, ef, rv, rm, oV, oM = _backward_case(B, sc, cams, 8, 2, d_img, 2)
+    _say(f"  backward edge flips {ef:.5f} relL2 dV {rv:.2e}")
+    assert ef < FLIP_MAX and rv < GRAD_RTOL
+    assert np.all(oV[3:] == 0.0) and np.abs(oV[:3]).max() > 0

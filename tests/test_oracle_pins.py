@@ -550,6 +550,44 @@ def test_primary_edges_projected_area_derivative():
     assert np.all(dM == 0)
 
 
+def test_primary_edges_hidden_triangle_contributes_nothing():
+    """A triangle wholly behind a larger one, lit by a point light on the camera
+    side: its edges are candidates (front-facing) and are sampled, but at every
+    sampled point both side rays meet the occluder first, so the edge term gives
+    its vertices exactly zero (what moving a hidden triangle does to the image).
+    The two side paths would otherwise differ by the light's change over 2 eps on
+    the occluder, an error that does not vanish with more samples.  The visible
+    triangle's own edges still carry their jump."""
+    front = np.array([[-0.8, -0.7, 0.5], [0.9, -0.6, 0.4], [0.0, 0.9, 0.5]], np.float32)
+    back = np.array([[-0.2, -0.2, -0.5], [0.25, -0.15, -0.6], [0.0, 0.25, -0.5]], np.float32)
+    V = np.concatenate([front, back])
+    F = np.array([[0, 1, 2], [3, 4, 5]], np.int32)
+    mat = S.uniform_materials(2, kd=1.0, ks=0.0, rough=0.3)
+    lights = np.array([[0.3, 0.4, 2.5, 6.0, 6.0, 6.0]], np.float32)
+    sc = O.OracleScene(V, F, mat, lights, None)
+    cam = S.Camera((0.0, 0.0, 3.0), (0, 0, 0), (0, 1, 0), 45.0, 48, 48)
+    # the back triangle projects inside the front one
+    eye, fwd, r, u, th = _cam_frame(cam)
+
+    def px(v):
+        q = v.astype(float) - eye
+        return np.array([q @ r / (q @ fwd), q @ u / (q @ fwd)])
+
+    def inside(p, tri):
+        a, b, c = (px(t) for t in tri)
+        def cr(e, w):
+            return e[0] * w[1] - e[1] * w[0]
+
+        d = [cr(b - a, p - a), cr(c - b, p - b), cr(a - c, p - c)]
+        return all(x > 0 for x in d) or all(x < 0 for x in d)
+
+    assert all(inside(px(v), front) for v in back)
+    d_img = np.ones((48 * 48, 3), np.float32)
+    dV, _, _, eh = sc.backward([cam], 16, 1, d_img, seed=5, flags=O.FLAG_PRIMARY)
+    assert np.all(dV[3:] == 0.0), dV[3:]
+    assert np.linalg.norm(dV[:3]) > 1.0
+
+
 # --------------------------------------------------------------------------
 # primary edge term on closed meshes: per-face albedo under a constant
 # environment, so that d(sum of the image)/dV is the derivative of the
