@@ -173,6 +173,12 @@ struct st_scene {
     uint64_t version = 0;              // bumped by every change of geometry, materials or sampler
     uint64_t etree_version = ~0ull;    // scene version the edge importance tree was built for
     std::vector<void*> retired;        // replaced material arrays (captured graphs may still read them)
+    // the adjoint of a backward runs on aux (forked from and joined back into the
+    // caller's stream) while the primary edges' side paths run on the caller's
+    // stream; its traversal stacks spill into spill_aux
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    GrowBuf spill_aux;
 };
 
 namespace {
@@ -607,6 +613,12 @@ int st_scene_create(const float* V, int32_t nv, const int32_t* F, int32_t nf, co
     }
 
     st_scene* sc = new st_scene();
+    if (hipStreamCreateWithFlags(&sc->aux, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&sc->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&sc->ev_join, hipEventDisableTiming) != hipSuccess) {
+        st_scene_destroy(sc);
+        return fail(ST_ERR_HIP, "stream or event creation failed");
+    }
     SceneDev& d = sc->d;
     d.nv = nv; d.nf = nf; d.nl = nl; d.he = he; d.we = we; d.ne = (int)edges.size(); d.scene_id = scene_id;
     d.tex_res = 0; d.ntex = nf;
@@ -1138,21 +1150,47 @@ int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_
     launch_fill_f32(out_dmat, 7ll * sc->d.ntex, 0.0f, s);
     if (o.debug_decision_hash) launch_fill_u32(o.debug_decision_hash, cs.total_paths, 0u, s);
     if (o.debug_edge_hash) launch_fill_u32(o.debug_edge_hash, cs.total_edges * (1 + nls), 0u, s);
-    launch_backward(p, sc->d.nv, sc->d.nf, cs.total_paths, cs.total_edges, TRACE_GRID, s);
+    // The adjoint (latency-bound: dependent gathers at four waves per SIMD) and the
+    // primary edges' side paths (issue-bound traversal) share nothing but atomics
+    // into dV, so outside graph capture the adjoint runs on the scene's second
+    // stream, with its own traversal spill region, while the side paths run here;
+    // the per-face gather into dV waits for both.
+    const bool adjoint = (p.flags & 5u) && cs.total_paths > 0;
+    const bool overlap = adjoint && prim && !g_capturing;
+    // every workspace first: between the fork and the join nothing may fail
+    uint32_t* hside = nullptr;
+    Queues q;
     if (prim) {
-        // side paths of the primary edge samples run through the wavefront kernels
         rc = sc->sidebuf.ensure((size_t)cs.total_edges * 6 * sizeof(float));
         if (rc) return rc;
-        uint32_t* hside = nullptr;
         if (o.debug_edge_hash) {
             rc = sc->sidehash.ensure((size_t)cs.total_edges * 2 * sizeof(uint32_t));
             if (rc) return rc;
             hside = (uint32_t*)sc->sidehash.p;
         }
-        Queues q;
         rc = make_queues(sc, (int)side_cap, nent_side, (float*)sc->sidebuf.p, q);
         if (rc) return rc;
         q.grid = sc->tuned_grid;
+    }
+    if (overlap) {
+        rc = sc->spill_aux.ensure(SPILL_BYTES);
+        if (rc) return rc;
+    }
+    if (overlap) {
+        BwdParams pa = p;
+        pa.spill = (uint32_t*)sc->spill_aux.p;
+        const hipError_t e = hipEventRecord(sc->ev_fork, s);
+        if (e != hipSuccess) return fail(ST_ERR_HIP, std::string("hipEventRecord: ") + hipGetErrorString(e));
+        // a wait that fails leaves aux unordered after s: the adjoint then runs here
+        if (hipStreamWaitEvent(sc->aux, sc->ev_fork, 0) == hipSuccess)
+            launch_backward(pa, sc->d.nv, sc->d.nf, cs.total_paths, cs.total_edges, TRACE_GRID, sc->aux);
+        else
+            launch_backward(p, sc->d.nv, sc->d.nf, cs.total_paths, cs.total_edges, TRACE_GRID, s);
+    } else if (adjoint) {
+        launch_backward(p, sc->d.nv, sc->d.nf, cs.total_paths, cs.total_edges, TRACE_GRID, s);
+    }
+    if (prim) {
+        // side paths of the primary edge samples run through the wavefront kernels
         FwdParams fp;
         fp.scenes = cs.scenes;
         fp.cams = cs.cams;
@@ -1172,6 +1210,12 @@ int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_
         launch_primary_edges(p, fp, q, (float*)sc->sidebuf.p, hside, cs.total_edges, sc->d.has_env ? 1 : 0, s);
     }
     if (nls > 0) launch_shadow_edges(p, cs.total_edges, nls, s);
+    if (overlap) {
+        // the join (an event recorded on aux after its last kernel, waited on here)
+        HIPCHK(hipEventRecord(sc->ev_join, sc->aux));
+        HIPCHK(hipStreamWaitEvent(s, sc->ev_join, 0));
+    }
+    if (adjoint) launch_face_gather(p, sc->d.nv, s);
     // every term has been added: a non-finite gradient sets the error word
     launch_check_finite(out_dV, 3ll * sc->d.nv, out_dmat, 7ll * sc->d.ntex, sc->d.err, s);
     HIPCHK(hipGetLastError());
@@ -1359,7 +1403,10 @@ void st_scene_destroy(st_scene* sc) {
     for (void* p : ptrs)
         if (p) hipFree(p);
     sc->Lbuf.release(); sc->qbuf.release(); sc->spillbuf.release(); sc->primbuf.release(); sc->recbuf.release();
-    sc->sidebuf.release(); sc->sidehash.release(); sc->secbuf.release();
+    sc->sidebuf.release(); sc->sidehash.release(); sc->secbuf.release(); sc->spill_aux.release();
+    if (sc->ev_fork) hipEventDestroy(sc->ev_fork);
+    if (sc->ev_join) hipEventDestroy(sc->ev_join);
+    if (sc->aux) hipStreamDestroy(sc->aux);
     for (void* q : sc->retired) hipFree(q);
     for (auto& t : sc->tables) {
         if (t.dev) hipFree(t.dev);

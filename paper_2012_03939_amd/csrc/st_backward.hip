@@ -1094,8 +1094,12 @@ static void launch_adjoint(const BwdParams& p, long long total_paths, int grid, 
     }
 }
 
+// the interior and secondary-edge terms into the per-face accumulators (and
+// secondary-edge atomics into dV); launch_face_gather adds them to dV and dmat
 void launch_backward(const BwdParams& p, int nv, int nf, long long total_paths, long long total_edges, int grid,
                      hipStream_t st) {
+    (void)nv;
+    (void)total_edges;
     if ((p.flags & 5u) && total_paths > 0) {
         launch_fill_u32((uint32_t*)p.facc, (long long)FACC_STRIDE * nf, 0u, st);
         if (p.ntex != nf) launch_fill_u32((uint32_t*)p.macc, (long long)MACC_STRIDE * p.ntex, 0u, st);
@@ -1103,10 +1107,14 @@ void launch_backward(const BwdParams& p, int nv, int nf, long long total_paths, 
         else if (p.B <= 2) launch_adjoint<2>(p, total_paths, grid, "k_adjoint<2>", "k_adjoint_sec<2>", st);
         else if (p.B <= 3) launch_adjoint<3>(p, total_paths, grid, "k_adjoint<3>", "k_adjoint_sec<3>", st);
         else launch_adjoint<8>(p, total_paths, grid, "k_adjoint<8>", "k_adjoint_sec<8>", st);
-        ST_LAUNCH("k_face_gather", k_face_gather, dim3(gridb(std::max<long long>(nv, p.ntex), 256, 4096)), dim3(256), 0,
-                  st, p);
     }
+}
 
+// dV += the per-face corner accumulators gathered per vertex (a plain add: after
+// every other writer of dV), dmat = the material accumulators
+void launch_face_gather(const BwdParams& p, int nv, hipStream_t st) {
+    ST_LAUNCH("k_face_gather", k_face_gather, dim3(gridb(std::max<long long>(nv, p.ntex), 256, 4096)), dim3(256), 0, st,
+              p);
 }
 
 void launch_shadow_edges(const BwdParams& p, long long total_edges, int nl, hipStream_t st) {

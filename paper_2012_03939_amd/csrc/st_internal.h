@@ -258,6 +258,7 @@ struct BwdParams {
 
 void launch_backward(const BwdParams& p, int nv, int nf, long long total_paths, long long total_edges, int grid,
                      hipStream_t st);
+void launch_face_gather(const BwdParams& p, int nv, hipStream_t st);
 // bytes of the deferred secondary-edge workspace for total_paths paths of B bounces
 size_t sec_workspace_bytes(long long total_paths, int B);
 void carve_sec_workspace(BwdParams& p, void* base, long long total_paths);

@@ -229,11 +229,16 @@ __global__ void __launch_bounds__(SHADE_BLOCK) SHADE_OCC k_shade(FwdParams p, Qu
                             ct = mul(beta, mul(ld3(lt + 3), brdf_eval(wl, wo, n, m))) * (c / r2);
                         }
                     }
+                    // an entry is read only when it carries a ray (listed for k_shadow;
+                    // k_shadow_sum reads the contribution of an unoccluded one)
                     const size_t e = (size_t)l * q.cap + i;
-                    qst(q.sh[0] + e, wl.x); qst(q.sh[1] + e, wl.y); qst(q.sh[2] + e, wl.z); qst(q.sh[3] + e, tmax);
-                    qst(q.sh[4] + e, ct.x); qst(q.sh[5] + e, ct.y); qst(q.sh[6] + e, ct.z);
-                    if (tmax >= 0.0f) rays |= 1u << l;
-                    else if (!fused) q.socc[e] = 0;
+                    if (tmax >= 0.0f) {
+                        qst(q.sh[0] + e, wl.x); qst(q.sh[1] + e, wl.y); qst(q.sh[2] + e, wl.z); qst(q.sh[3] + e, tmax);
+                        qst(q.sh[4] + e, ct.x); qst(q.sh[5] + e, ct.y); qst(q.sh[6] + e, ct.z);
+                        rays |= 1u << l;
+                    } else if (!fused) {
+                        q.socc[e] = 0;
+                    }
                 }
                 int tex = 0;
                 if (S.has_env) {
@@ -249,10 +254,13 @@ __global__ void __launch_bounds__(SHADE_BLOCK) SHADE_OCC k_shade(FwdParams p, Qu
                         ct = mul(beta, mul(env_rgb(S, tex), brdf_eval(we, wo, n, m))) * (c / den);
                     }
                     const size_t e = (size_t)S.nl * q.cap + i;
-                    qst(q.sh[0] + e, we.x); qst(q.sh[1] + e, we.y); qst(q.sh[2] + e, we.z); qst(q.sh[3] + e, tmax);
-                    qst(q.sh[4] + e, ct.x); qst(q.sh[5] + e, ct.y); qst(q.sh[6] + e, ct.z);
-                    if (tmax >= 0.0f) rays |= 1u << S.nl;
-                    else if (!fused) q.socc[e] = 0;
+                    if (tmax >= 0.0f) {
+                        qst(q.sh[0] + e, we.x); qst(q.sh[1] + e, we.y); qst(q.sh[2] + e, we.z); qst(q.sh[3] + e, tmax);
+                        qst(q.sh[4] + e, ct.x); qst(q.sh[5] + e, ct.y); qst(q.sh[6] + e, ct.z);
+                        rays |= 1u << S.nl;
+                    } else if (!fused) {
+                        q.socc[e] = 0;
+                    }
                 }
                 uint32_t info = 0;
                 if (k < p.B || S.has_env) {
@@ -267,12 +275,16 @@ __global__ void __launch_bounds__(SHADE_BLOCK) SHADE_OCC k_shade(FwdParams p, Qu
                         beta = mul(beta, brdf_eval(wi, wo, n, m)) * (ci / pb);
                     }
                 }
-                qst(q.sface + i, f);
+                // the shading record: the shadow rays' origin and excluded face (fused:
+                // read only through the listed entries)
+                if (!fused || rays) {
+                    qst(q.sface + i, f);
+                    qst(q.sx[0] + i, x.x); qst(q.sx[1] + i, x.y); qst(q.sx[2] + i, x.z);
+                }
                 if (!fused) q.sinfo[i] = info;
                 if (shadow_fused(p, q) && p.rec_occ && (vd >> 16) == 0u)
                     p.rec_occ[(size_t)(k - 1) * p.rec_n + pq] = 0u;
                 if (!fused) q.stex[i] = tex;
-                qst(q.sx[0] + i, x.x); qst(q.sx[1] + i, x.y); qst(q.sx[2] + i, x.z);
                 if (!fused) q.snext[i] = -1;
             }
             hv = h.h;

