@@ -1146,6 +1146,9 @@ int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_
         if (rc) return rc;
         carve_sec_workspace(p, sc->secbuf.p, cs.total_paths);
     }
+    // records offered and no inline secondary-edge side paths: the main pass of
+    // the adjoint runs first without traversal (see k_adjoint)
+    p.rec_split = p.rec_face != nullptr && (p.sec_mask != nullptr || !(p.flags & 4u)) ? 1 : 0;
     launch_fill_f32(out_dV, 3ll * sc->d.nv, 0.0f, s);
     launch_fill_f32(out_dmat, 7ll * sc->d.ntex, 0.0f, s);
     if (o.debug_decision_hash) launch_fill_u32(o.debug_decision_hash, cs.total_paths, 0u, s);

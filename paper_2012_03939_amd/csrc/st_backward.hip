@@ -135,7 +135,12 @@ __device__ __forceinline__ void face_reduce_add(bool has, int f, int tx, const f
 // which replays the path with the interior term off and processes that vertex
 // alone.  Accepted samples are rare, so inline they would hold whole waves for
 // one lane's side paths; as jobs they fill the lanes.
-template <int BM, bool JOBS>
+// REC = true: the main pass of a backward that holds the hit records of its
+// forward and defers secondary edges, compiled without any traversal (which
+// leaves the compiler far fewer values to spill); it does nothing when the
+// records turn out stale on the device, and the REC = false pass launched after
+// it then traces (that pass returns at once when the records pass ran).
+template <int BM, bool JOBS, bool REC = false>
 __global__ void __launch_bounds__(TRACE_BLOCK) __attribute__((amdgpu_waves_per_eu(ST_ADJ_WAVES)))
 k_adjoint(BwdParams p, long long total) {
     __shared__ uint32_t lds[LDS_STACK * TRACE_BLOCK];
@@ -145,9 +150,11 @@ k_adjoint(BwdParams p, long long total) {
     const bool want_interior = !JOBS && (p.flags & 1u), want_secondary = p.flags & 4u;
     const bool sec_interior = p.flags & ST_EDGE_SECONDARY_INTERIOR;   // creases / material edges too
     const bool hier = p.flags & ST_EDGE_SECONDARY_HIERARCHY;           // edges from the importance tree
-    const bool defer = !JOBS && p.sec_mask != nullptr;
+    const bool defer = REC || (!JOBS && p.sec_mask != nullptr);
     // hit records only when they belong to this pass's forward (same on every lane)
     const bool recs = p.rec_face != nullptr && *p.rec_key_dev == p.rec_key;
+    if (REC && !recs) return;
+    if (!REC && !JOBS && p.rec_split && recs) return;
     const int* const rec_face = recs ? p.rec_face : nullptr;
     const uint32_t* const rec_occ = recs ? p.rec_occ : nullptr;
     const long long stride = (long long)gridDim.x * blockDim.x;
@@ -199,7 +206,7 @@ k_adjoint(BwdParams p, long long total) {
                 float t;
                 const size_t ri = (size_t)(k - 1) * p.rec_n + qq;
                 int f;
-                if (rec_face) {
+                if (REC || rec_face) {
                     f = qld(rec_face + ri);
                     t = f >= 0 ? face_hit_t(S, f, o, d) : __int_as_float(0x7f800000);
                 } else {
@@ -225,7 +232,7 @@ k_adjoint(BwdParams p, long long total) {
                 const int tx = texel_of(S, f, xh);
                 if (S.tex_res) h.push((uint32_t)tx);
                 const Mat m = load_mat(S.mat + 7 * (size_t)tx);
-                const uint32_t rocc = rec_occ ? qld(rec_occ + ri) : 0u;
+                const uint32_t rocc = (REC || rec_occ) ? qld(rec_occ + ri) : 0u;
                 for (int l = 0; l < S.nl; ++l) {
                     const float* lt = S.lights + 6 * l;
                     const V3 dl = ld3(lt) - xh;
@@ -235,7 +242,7 @@ k_adjoint(BwdParams p, long long total) {
                         const float rr = sqrtf(r2);
                         const V3 wl = dl * (1.0f / rr);
                         if (dot(n, wl) > 0.0f) {
-                            const bool occ = rec_occ ? ((rocc >> l) & 1u) != 0u
+                            const bool occ = (REC || rec_occ) ? ((rocc >> l) & 1u) != 0u
                                                        : trace_any(S, xh, wl, TMIN, rr * (1.0f - SHADOW_SHRINK), f, st);
                             code = occ ? 1u : 2u;
                             if (!occ) fl |= 1u << (8 + l);
@@ -251,7 +258,7 @@ k_adjoint(BwdParams p, long long total) {
                     const float ce = dot(n, we);
                     uint32_t code = 0;
                     if (ce > 0.0f && pe > 0.0f) {
-                        const bool occ = rec_occ ? ((rocc >> S.nl) & 1u) != 0u
+                        const bool occ = (REC || rec_occ) ? ((rocc >> S.nl) & 1u) != 0u
                                                    : trace_any(S, xh, we, TMIN, __int_as_float(0x7f800000), f, st);
                         code = occ ? 1u : 2u;
                         if (!occ) {
@@ -1085,6 +1092,8 @@ static void launch_adjoint(const BwdParams& p, long long total_paths, int grid, 
         launch_fill_u32((uint32_t*)p.sec_njobs, 1, 0u, st);
         launch_fill_u32((uint32_t*)p.sec_mask, (total_paths + 3) / 4, 0u, st);
     }
+    if (p.rec_split) ST_LAUNCH(name, (k_adjoint<BM, false, true>), gd, bd, 0, st, p, total_paths);
+    // (returns at once when the records pass above found its records valid)
     ST_LAUNCH(name, (k_adjoint<BM, false>), gd, bd, 0, st, p, total_paths);
     if (p.sec_mask) {
         ST_LAUNCH("k_sec_jobs", k_sec_jobs, dim3(gridb(total_paths, 256, 1 << 14)), dim3(256), 0, st, p.sec_mask,

@@ -208,6 +208,7 @@ void launch_check_finite(const float* a, long long na, const float* b, long long
 void launch_sample_radiance(const FwdParams& p, const float* L, long long total, float* out, hipStream_t st);
 
 struct BwdParams {
+    int rec_split;           // the main pass is split: a records-only pass, then one that traces if they are stale
     const DevScene* scenes;
     const DevCam* cams;
     const long long* qoff;   // [ncam+1] path offsets (processing order)

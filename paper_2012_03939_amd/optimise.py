@@ -113,6 +113,8 @@ def run(steps: int = 200, nviews: int = 32, res: int = 256, spp: int = 8, bounce
                                start_sc.scene_id)
             g.close()
         g = B.GPUScene.from_scene(start_sc)
+        # wavefront chunk size and traversal grid for this workload (timed renders)
+        B.autotune([g], cams, spp, bounces)
         V = torch.tensor(start_sc.V, device=dev, requires_grad=True)
         mat0 = start_sc.mat
         if from_ck:
