@@ -135,21 +135,23 @@ __device__ __forceinline__ void face_reduce_add(bool has, int f, int tx, const f
 // which replays the path with the interior term off and processes that vertex
 // alone.  Accepted samples are rare, so inline they would hold whole waves for
 // one lane's side paths; as jobs they fill the lanes.
-// REC = true: the main pass of a backward that holds the hit records of its
+// RECM > 0: the main pass of a backward that holds the hit records of its
 // forward and defers secondary edges, compiled without any traversal (which
-// leaves the compiler far fewer values to spill); it does nothing when the
-// records turn out stale on the device, and the REC = false pass launched after
+// leaves the compiler far fewer values to spill; RECM = 1 also without the
+// secondary-edge hierarchy's descent, RECM = 2 with it); it does nothing when
+// the records turn out stale on the device, and the RECM = 0 pass launched after
 // it then traces (that pass returns at once when the records pass ran).
-template <int BM, bool JOBS, bool REC = false>
+template <int BM, bool JOBS, int RECM = 0>
 __global__ void __launch_bounds__(TRACE_BLOCK) __attribute__((amdgpu_waves_per_eu(ST_ADJ_WAVES)))
 k_adjoint(BwdParams p, long long total) {
+    constexpr bool REC = RECM > 0;
     __shared__ uint32_t lds[LDS_STACK * TRACE_BLOCK];
     __shared__ float red_s[TRACE_BLOCK / 64][FACC];
     float* const red = red_s[threadIdx.x >> 6];
     TravStack st = make_trav_stack(lds, p.spill, p.err, p.work ? p.work + 3 * WORK_ADJOINT : nullptr);
     const bool want_interior = !JOBS && (p.flags & 1u), want_secondary = p.flags & 4u;
     const bool sec_interior = p.flags & ST_EDGE_SECONDARY_INTERIOR;   // creases / material edges too
-    const bool hier = p.flags & ST_EDGE_SECONDARY_HIERARCHY;           // edges from the importance tree
+    const bool hier = RECM != 1 && (p.flags & ST_EDGE_SECONDARY_HIERARCHY);   // edges from the importance tree
     const bool defer = REC || (!JOBS && p.sec_mask != nullptr);
     // hit records only when they belong to this pass's forward (same on every lane)
     const bool recs = p.rec_face != nullptr && *p.rec_key_dev == p.rec_key;
@@ -1092,7 +1094,10 @@ static void launch_adjoint(const BwdParams& p, long long total_paths, int grid, 
         launch_fill_u32((uint32_t*)p.sec_njobs, 1, 0u, st);
         launch_fill_u32((uint32_t*)p.sec_mask, (total_paths + 3) / 4, 0u, st);
     }
-    if (p.rec_split) ST_LAUNCH(name, (k_adjoint<BM, false, true>), gd, bd, 0, st, p, total_paths);
+    if (p.rec_split && (p.flags & ST_EDGE_SECONDARY_HIERARCHY))
+        ST_LAUNCH(name, (k_adjoint<BM, false, 2>), gd, bd, 0, st, p, total_paths);
+    else if (p.rec_split)
+        ST_LAUNCH(name, (k_adjoint<BM, false, 1>), gd, bd, 0, st, p, total_paths);
     // (returns at once when the records pass above found its records valid)
     ST_LAUNCH(name, (k_adjoint<BM, false>), gd, bd, 0, st, p, total_paths);
     if (p.sec_mask) {
