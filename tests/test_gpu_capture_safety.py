@@ -114,3 +114,36 @@ def test_workspace_growth_keeps_captured_buffers(B):
     assert rays == rays_full
     assert rel_l2(dV, rV) < 1e-5 and rel_l2(dM, rM) < 1e-5
     g.check_errors()
+
+
+def test_captured_backward_matches_eager(B):
+    """Eagerly the adjoint runs on the scene's second stream beside the primary
+    edges' side paths; under capture every kernel runs in order on the caller's
+    stream.  Replays of a captured backward (records, all gradient terms), with
+    eager work and synchronisation between them, equal the eager backward up to
+    the order of float atomics."""
+    _say("case captured backward (all terms) replayed 3 times against eager backwards")
+    sc = _scene()
+    g = B.GPUScene.from_scene(sc)
+    cams = [S.look_at_origin((0.4, 1.2, 3.2), 64, 48), S.look_at_origin((-2.5, 0.8, 2.0), 48, 48)]
+    spp, bounces, seed = 4, 2, 9
+    img = g.render(cams, spp, bounces, seed).clone()
+    d = torch.from_numpy(np.random.default_rng(3).normal(size=tuple(img.shape)).astype(np.float32)).cuda()
+    dV = torch.empty((g.nv, 3), dtype=torch.float32, device="cuda")
+    dM = torch.empty((g.nf, 7), dtype=torch.float32, device="cuda")
+
+    def bwd():
+        g.backward(cams, spp, bounces, d, seed, B.ST_ALL_GRADS, dV=dV, dmat=dM)
+
+    graph = _capture(bwd)
+    for rep in range(3):
+        g.render(cams, spp, bounces, seed)          # eager work between replays (same records key)
+        bwd()
+        torch.cuda.synchronize()
+        eV, eM = dV.cpu().numpy().copy(), dM.cpu().numpy().copy()
+        graph.replay()
+        torch.cuda.synchronize()
+        rv, rm = rel_l2(dV.cpu().numpy(), eV), rel_l2(dM.cpu().numpy(), eM)
+        _say(f"  replay {rep}: relL2 dV {rv:.2e} dmat {rm:.2e}")
+        assert np.abs(eV).max() > 0 and rv < 1e-5 and rm < 1e-5
+    g.check_errors()
