@@ -275,7 +275,7 @@ int st_check_errors(st_scene* scene, hipStream_t s);
  *    box), child int32 [nf-1,2] (bit 31 marks a leaf index), parent int32
  *    [2nf-1] (internal nodes, then leaves; -1 at the root), aabb float [2nf-1,6]
  *    (min xyz, max xyz).  The tree is the Karras radix tree over the keys after
- *    two bottom-up passes of treelet restructuring (7-entry treelets re-arranged
+ *    one bottom-up pass of treelet restructuring (7-entry treelets re-arranged
  *    to their least SAH cost, triangle cost = box area, internal node cost =
  *    1.2 x box area + children); leaves and the root box are those of the radix
  *    tree.  Deterministic: a function of the mesh alone.

@@ -389,7 +389,7 @@ def project(cam, v):
     return out
 
 
-TREELET_ROUNDS = 2      # restructuring passes the GPU builder applies to the Karras tree
+TREELET_ROUNDS = 1      # restructuring passes the GPU builder applies to the Karras tree
 
 
 def lbvh(V, F, treelet_rounds=0):
