@@ -1035,7 +1035,7 @@ static inline unsigned gridb(long long n, int bs, int cap) {
 }
 
 void launch_primary_edges(const BwdParams& p, const FwdParams& fp, Queues& q, float* Lside, uint32_t* hside,
-                          long long total_edges, int has_env_any, hipStream_t st) {
+                          long long total_edges, int has_env_any, hipStream_t st, LaunchHook* hook) {
     if (total_edges <= 0 || p.ne <= 0) return;
     ST_LAUNCH("k_prim_weights", k_prim_weights, dim3(gridb(p.ne, 256, 1024), p.ncam), dim3(256), 0, st, p);
     ST_LAUNCH("k_prim_cdf", k_prim_cdf, dim3(p.ncam), dim3(1024), 0, st, p);
@@ -1047,7 +1047,8 @@ void launch_primary_edges(const BwdParams& p, const FwdParams& fp, Queues& q, fl
         launch_fill_u32((uint32_t*)q.fetch, FETCH_INTS, 0u, st);
         ST_LAUNCH("k_edge_camera", k_edge_camera, dim3(gridb(n, EDGE_CAM_BLOCK, 1 << 20)), dim3(EDGE_CAM_BLOCK), 0, st,
                   p, q, e0, n);
-        launch_wavefront_bounces(fp, q, 2 * n, has_env_any, st);
+        if (hook) hook->tick();
+        launch_wavefront_bounces(fp, q, 2 * n, has_env_any, st, hook);
     }
     launch_fill_u32((uint32_t*)p.pacc, 4ll * p.ncam * p.ne, 0u, st);      // +0.0 doubles
     ST_LAUNCH("k_edge_grad", k_edge_grad, dim3(gridb(total_edges, 256, 1 << 16)), dim3(256), 0, st, p, Lside, hside,

@@ -4,6 +4,8 @@
 #include "st_device.h"
 #include "../../include/shapetrace.h"
 
+#include <functional>
+
 namespace st {
 
 // optional per-kernel timing with HIP events recorded on the launch stream
@@ -198,7 +200,16 @@ void launch_env_build(SceneDev& s, hipStream_t st);
 
 void launch_forward_wavefront(const FwdParams& p, Queues& q, long long total, int has_env_any, int nent,
                               hipStream_t st);
-void launch_wavefront_bounces(const FwdParams& p, Queues& q, int n, int has_env_any, hipStream_t st);
+// an action run once, after the at-th launch of a sequence that ticks it
+struct LaunchHook {
+    int at = -1, count = 0;
+    std::function<void()> fn;
+    void tick() {
+        if (++count == at && fn) fn();
+    }
+};
+void launch_wavefront_bounces(const FwdParams& p, Queues& q, int n, int has_env_any, hipStream_t st,
+                              LaunchHook* hook = nullptr);
 void launch_forward_mega(const FwdParams& p, float* L, long long total, uint32_t* spill, int grid, hipStream_t st);
 // key_dev (optional): receives key before the film is written (the forward is complete)
 void launch_film(const DevCam* cams, const long long* pixoff, int ncam, int spp, const float* L,
@@ -268,7 +279,7 @@ void carve_sec_workspace(BwdParams& p, void* base, long long total_paths);
 // point-light shadow boundaries (ST_EDGE_SHADOW); total_edges = primary edge samples
 void launch_shadow_edges(const BwdParams& p, long long total_edges, int nl, hipStream_t st);
 void launch_primary_edges(const BwdParams& p, const FwdParams& fp, Queues& q, float* Lside, uint32_t* hside,
-                          long long total_edges, int has_env_any, hipStream_t st);
+                          long long total_edges, int has_env_any, hipStream_t st, LaunchHook* hook = nullptr);
 void launch_fill_f32(float* p, long long n, float v, hipStream_t st);
 void launch_fill_u32(uint32_t* p, long long n, uint32_t v, hipStream_t st);
 void launch_put_u64(unsigned long long* p, unsigned long long v, hipStream_t st);

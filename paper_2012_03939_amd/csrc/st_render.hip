@@ -528,15 +528,19 @@ void launch_forward_wavefront(const FwdParams& p, Queues& q, long long total, in
 
 // extension / shading / shadow kernels of every bounce for a chunk whose first
 // ray queue (queue 1) and count cnt[1] have been filled; n bounds the count
-void launch_wavefront_bounces(const FwdParams& p, Queues& q, int n, int has_env_any, hipStream_t st) {
+void launch_wavefront_bounces(const FwdParams& p, Queues& q, int n, int has_env_any, hipStream_t st,
+                              LaunchHook* hook) {
     const unsigned gmax = (q.grid > 0 && (unsigned)q.grid < TRACE_GRID) ? (unsigned)q.grid : TRACE_GRID;
     const unsigned g = grid_for(n, TRACE_BLOCK, gmax);
     const int last = p.B + (has_env_any ? 1 : 0);
     for (int k = 1; k <= last; ++k) {
         ST_LAUNCH("k_extend", k_extend, dim3(g), dim3(TRACE_BLOCK), 0, st, p, q, k);
+        if (hook) hook->tick();
         ST_LAUNCH("k_shade", k_shade, dim3(grid_for(n, SHADE_BLOCK, gmax)), dim3(SHADE_BLOCK), 0, st, p, q, k);
+        if (hook) hook->tick();
         if (k <= p.B) {
             ST_LAUNCH("k_shadow", k_shadow, dim3(g), dim3(TRACE_BLOCK), 0, st, p, q, k);
+            if (hook) hook->tick();
             if (!shadow_fused(p, q))
                 ST_LAUNCH("k_shadow_sum", k_shadow_sum, dim3(grid_for(n, 256, gmax)), dim3(256), 0, st, p, q, k);
         }
