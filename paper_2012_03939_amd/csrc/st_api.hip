@@ -179,6 +179,7 @@ struct st_scene {
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     GrowBuf spill_aux;
+    GrowBuf adjbuf;                    // the adjoint's list of paths that have a vertex
 };
 
 namespace {
@@ -1082,8 +1083,18 @@ int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_
     side_cap = std::min<long long>(side_cap, 1ll << 28);
     side_cap = balanced_chunk(2 * cs.total_edges, side_cap) & ~1ll;     // two side paths per edge sample
     if (prim && 2 * cs.total_edges >= (1ll << 32)) return fail(ST_ERR_INVALID_ARG, "too many primary edge samples");
+    // hit records of this pass's forward, when the scene holds them in a buffer
+    // large enough (the adjoint still checks on the device that they are this
+    // pass's); with them and no inline secondary-edge side paths, the adjoint's
+    // records pass walks a list of the paths that have a vertex (not with
+    // decision hashes, which every path writes)
+    const size_t rec_bytes = (size_t)(2 * bounces + 1) * (size_t)cs.total_paths * sizeof(int);
+    const bool recs_fit = !(o.flags & ST_BACKWARD_RETRACE) && sc->recbuf.p && sc->recbuf.cap >= rec_bytes;
+    const bool adj_listed = recs_fit && (defer_sec || !(o.flags & ST_EDGE_SECONDARY)) && !o.debug_decision_hash &&
+                            cs.total_paths > 0 && cs.total_paths < (1ll << 31);
     {
-        size_t need = SPILL_BYTES + pbytes + (defer_sec ? sec_workspace_bytes(cs.total_paths, bounces) : 0);
+        size_t need = SPILL_BYTES + pbytes + (defer_sec ? sec_workspace_bytes(cs.total_paths, bounces) : 0) +
+                      (adj_listed ? adj_list_bytes(cs.total_paths) : 0);
         if (prim)
             need += (size_t)cs.total_edges * 6 * sizeof(float) +
                     (o.debug_edge_hash ? (size_t)cs.total_edges * 2 * sizeof(uint32_t) : 0) +
@@ -1134,9 +1145,7 @@ int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_
     p.ne = ne;
     // the records are offered when they can hold this pass's paths; the adjoint
     // takes them only if the key its forward wrote on the device matches
-    const size_t rec_bytes = (size_t)(2 * bounces + 1) * (size_t)cs.total_paths * sizeof(int);
-    const bool offer_rec = !(o.flags & ST_BACKWARD_RETRACE) && sc->recbuf.p && sc->recbuf.cap >= rec_bytes &&
-                           sc->recbuf.ensure(rec_bytes) == ST_OK;
+    const bool offer_rec = recs_fit && sc->recbuf.ensure(rec_bytes) == ST_OK;
     p.rec_face = offer_rec ? (const int*)sc->recbuf.p : nullptr;
     p.rec_occ = offer_rec ? (const uint32_t*)((const int*)sc->recbuf.p + (size_t)(bounces + 1) * cs.total_paths) : nullptr;
     p.rec_n = offer_rec ? cs.total_paths : 0;
@@ -1155,6 +1164,14 @@ int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_
     // records offered and no inline secondary-edge side paths: the main pass of
     // the adjoint runs first without traversal (see k_adjoint)
     p.rec_split = p.rec_face != nullptr && (p.sec_mask != nullptr || !(p.flags & 4u)) ? 1 : 0;
+    p.adj_list = nullptr;
+    p.adj_n = nullptr;
+    if (p.rec_split && adj_listed) {
+        rc = sc->adjbuf.ensure(adj_list_bytes(cs.total_paths));
+        if (rc) return rc;
+        p.adj_n = (int*)sc->adjbuf.p;
+        p.adj_list = (uint32_t*)((char*)sc->adjbuf.p + 256);
+    }
     launch_fill_f32(out_dV, 3ll * sc->d.nv, 0.0f, s);
     launch_fill_f32(out_dmat, 7ll * sc->d.ntex, 0.0f, s);
     if (o.debug_decision_hash) launch_fill_u32(o.debug_decision_hash, cs.total_paths, 0u, s);
@@ -1424,6 +1441,7 @@ void st_scene_destroy(st_scene* sc) {
         if (p) hipFree(p);
     sc->Lbuf.release(); sc->qbuf.release(); sc->spillbuf.release(); sc->primbuf.release(); sc->recbuf.release();
     sc->sidebuf.release(); sc->sidehash.release(); sc->secbuf.release(); sc->spill_aux.release();
+    sc->adjbuf.release();
     if (sc->ev_fork) hipEventDestroy(sc->ev_fork);
     if (sc->ev_join) hipEventDestroy(sc->ev_join);
     if (sc->aux) hipStreamDestroy(sc->aux);

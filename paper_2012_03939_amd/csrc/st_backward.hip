@@ -160,7 +160,9 @@ k_adjoint(BwdParams p, long long total) {
     const int* const rec_face = recs ? p.rec_face : nullptr;
     const uint32_t* const rec_occ = recs ? p.rec_occ : nullptr;
     const long long stride = (long long)gridDim.x * blockDim.x;
-    const long long count = JOBS ? (long long)*p.sec_njobs : total;
+    // the records pass walks the list of paths that have a vertex when it is given
+    const bool listed = REC && !JOBS && p.adj_list != nullptr;
+    const long long count = JOBS ? (long long)*p.sec_njobs : listed ? (long long)*p.adj_n : total;
     // the main pass gives each XCD consecutive paths (their hits share that XCD's
     // L2: 18.1 -> 15.8 ms); the job pass keeps the hardware order
     const long long b0 = JOBS ? (long long)blockIdx.x : (long long)grid_block();
@@ -171,6 +173,8 @@ k_adjoint(BwdParams p, long long total) {
             const int2 jb = p.sec_jobs[it];
             qq = jb.x;
             ksel = jb.y;
+        } else if (listed) {
+            qq = (long long)p.adj_list[it];
         }
         const int vw = find_view(p.qoff, p.ncam, qq);
         const DevCam& c = p.cams[vw];
@@ -1056,6 +1060,23 @@ void launch_primary_edges(const BwdParams& p, const FwdParams& fp, Queues& q, fl
     ST_LAUNCH("k_edge_finish", k_edge_finish, dim3(gridb(p.ne, 256, 1024), p.ncam), dim3(256), 0, st, p);
 }
 
+// Paths whose camera ray hit a face, in blocks of 256 consecutive paths (one
+// counter reservation per block, so the list keeps neighbouring pixels
+// together).  A path whose camera ray escaped has no vertex: its adjoint adds
+// nothing (the environment seen directly depends on neither the vertices nor
+// the materials), and its lanes would idle through the replay of the others.
+__global__ void __launch_bounds__(256) k_adj_list(const int* __restrict__ rec_face, long long total, uint32_t* list,
+                                                  int* n) {
+    __shared__ int resv[256 / 64 + 1];
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long b0 = (long long)blockIdx.x * blockDim.x; b0 < total; b0 += stride) {
+        const long long i = b0 + threadIdx.x;
+        const bool emit = i < total && qld(rec_face + i) >= 0;
+        const int o = block_reserve<256, 1>(emit, n, resv);
+        if (emit) list[o] = (uint32_t)i;
+    }
+}
+
 // (path, vertex) jobs of the marked secondary edge samples, in blocks of 256
 // paths with one counter reservation per block and bit
 __global__ void __launch_bounds__(256) k_sec_jobs(const uint8_t* __restrict__ mask, long long total, int B,
@@ -1094,6 +1115,11 @@ static void launch_adjoint(const BwdParams& p, long long total_paths, int grid, 
     if (p.sec_mask) {
         launch_fill_u32((uint32_t*)p.sec_njobs, 1, 0u, st);
         launch_fill_u32((uint32_t*)p.sec_mask, (total_paths + 3) / 4, 0u, st);
+    }
+    if (p.rec_split && p.adj_list) {
+        launch_fill_u32((uint32_t*)p.adj_n, 1, 0u, st);
+        ST_LAUNCH("k_adj_list", k_adj_list, dim3(gridb(total_paths, 256, 1 << 14)), dim3(256), 0, st, p.rec_face,
+                  total_paths, p.adj_list, p.adj_n);
     }
     if (p.rec_split && (p.flags & ST_EDGE_SECONDARY_HIERARCHY))
         ST_LAUNCH(name, (k_adjoint<BM, false, 2>), gd, bd, 0, st, p, total_paths);

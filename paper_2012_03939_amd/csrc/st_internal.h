@@ -267,6 +267,10 @@ struct BwdParams {
     uint8_t* sec_mask;
     int2* sec_jobs;
     int* sec_njobs;
+    // paths whose camera ray hit a face (the records pass of the adjoint walks
+    // only these), or null
+    uint32_t* adj_list;
+    int* adj_n;
 };
 
 void launch_backward(const BwdParams& p, int nv, int nf, long long total_paths, long long total_edges, int grid,
@@ -274,6 +278,8 @@ void launch_backward(const BwdParams& p, int nv, int nf, long long total_paths, 
 void launch_face_gather(const BwdParams& p, int nv, hipStream_t st);
 // bytes of the deferred secondary-edge workspace for total_paths paths of B bounces
 size_t sec_workspace_bytes(long long total_paths, int B);
+// the adjoint's path list: a counter (256 B) and one 32-bit path index per path
+inline size_t adj_list_bytes(long long total_paths) { return 256 + sizeof(uint32_t) * (size_t)total_paths; }
 void carve_sec_workspace(BwdParams& p, void* base, long long total_paths);
 // primary edges with their side paths traced by the wavefront kernels
 // point-light shadow boundaries (ST_EDGE_SHADOW); total_edges = primary edge samples
