@@ -35,7 +35,11 @@ PEAK_HBM_GBS = 8000.0
 # library launch names of the queue-streaming kernels -> their rocprofv3 names
 HBM_KERNELS = {"k_shade": "k_shade", "k_adjoint<3>": "k_adjoint<3, false, 1>",
                "k_adjoint_sec<3>": "k_adjoint<3, true, 0>",
-               "k_extend": "k_extend", "k_shadow": "k_shadow"}
+               "k_extend": "k_extend", "k_trace_pair": "k_trace_pair", "k_shadow": "k_shadow"}
+# Work-counter rows (st_read_work) that belong to one launch name alone: the
+# extension and shadow rows count those rays wherever they are traced, which
+# is also inside k_trace_pair once it runs.
+OWN_WORK = ("k_trace_pair", "k_adjoint", "k_forward_mega")
 
 
 CU_COUNT, SIMDS_PER_CU, CLOCK_HZ = 256, 4, 2.4e9
@@ -354,14 +358,27 @@ def main():
     progress(f"{args.steps} timed steps: {ms_per_step:.2f} ms per step")
     value = n_paths * args.steps / (ms / 1e3)
 
-    # dominant kernel and its algorithmic work, counted on device in one extra (untimed) step
-    dom_name, (dom_ms, dom_n) = max(prof.items(), key=lambda kv: kv[1][0])
+    # the dominant traversal kernel and its algorithmic work, counted on device in
+    # one extra (untimed) step; a kernel qualifies when a work-counter row is its own
+    own = OWN_WORK if "k_trace_pair" in prof else OWN_WORK + ("k_extend", "k_shadow")
+    dom_name, (dom_ms, dom_n) = max(((k, v) for k, v in prof.items() if k.split("<")[0] in own),
+                                    key=lambda kv: kv[1][0])
     g.read_work()
     g.update(V=Vs[0])
     g.render(cams, spp, bounces, seed=100, out=img, flags=B.ST_COUNT_WORK)
+    fwork = g.read_work()
     g.backward(cams, spp, bounces, (img - target) * scale, seed=100, flags=grads | B.ST_COUNT_WORK,
                dV=dV, dmat=dM)
-    work = g.read_work()
+    work = {k: tuple(a + b for a, b in zip(v, fwork[k])) for k, v in g.read_work().items()}
+    # The same kernel in a forward render alone: in the step, the backward's
+    # launches share the GPU with the adjoint on the second stream, which
+    # lengthens their durations; a forward runs on one stream only.
+    B.profile_read()
+    B.profile_enable(True)
+    for i in range(3):
+        g.render(cams, spp, bounces, seed=100, out=img)
+    B.profile_enable(False)
+    fprof = B.profile_read()
     wkey = dom_name.split("<")[0]
     visits, tests, rays = work.get(wkey, (0, 0, 0))
     launches_per_step = dom_n / args.steps
@@ -370,14 +387,31 @@ def main():
     avg_ms = dom_ms / dom_n
     achieved = flops_per_launch / (avg_ms / 1e3) / 1e12
     achieved_issued = issued_per_launch / (avg_ms / 1e3) / 1e12
+    alone = None
+    if dom_name in fprof and fwork.get(wkey, (0, 0, 0))[2]:
+        fms, fn = fprof[dom_name]
+        fv, ft, fr = fwork[wkey]
+        fper = fn / 3
+        fflops = (fv * FLOPS_PER_VISIT + ft * FLOPS_PER_TEST) / fper
+        alone = {"avg_launch_ms": fms / fn, "launches_per_render": fper, "node_visits_per_launch": fv / fper,
+                 "tri_tests_per_launch": ft / fper, "rays_per_launch": fr / fper,
+                 "achieved": fflops / (fms / fn / 1e3) / 1e12,
+                 "frac": fflops / (fms / fn / 1e3) / 1e12 / PEAK_FP32_VECTOR_TFLOPS,
+                 "note": "forward renders alone (one stream), 3 renders after the timed region"}
     kernels = {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[1] / args.steps} for k, v in prof.items()}
-    # rays, node visits and triangle tests of every traversal kernel in one step
+    # rays, node visits and triangle tests of one step: per ray kind (extension
+    # and shadow rays wherever traced), and per launch name where the row is its
+    # own (time and rate only there)
     traversal = {}
     for k, (kv, kt, kr) in work.items():
-        kms = sum(v["ms_per_step"] for n, v in kernels.items() if n.split("<")[0] == k)
-        if kr:
-            traversal[k] = {"rays_per_step": kr, "node_visits_per_ray": kv / kr, "tri_tests_per_ray": kt / kr,
-                            "ms_per_step": kms, "rays_per_s": kr / (kms / 1e3) if kms else None}
+        if not kr:
+            continue
+        e = {"rays_per_step": kr, "node_visits_per_ray": kv / kr, "tri_tests_per_ray": kt / kr}
+        if k in own:
+            # (the adjoint's row covers its job pass, launched as k_adjoint_sec)
+            kms = sum(v["ms_per_step"] for n, v in kernels.items() if n.split("<")[0].startswith(k))
+            e.update({"ms_per_step": kms, "rays_per_s": kr / (kms / 1e3) if kms else None})
+        traversal[{"k_extend": "extension_rays", "k_shadow": "shadow_rays"}.get(k, k)] = e
     mc = measured_counters(dom_name)
     # queue-streaming kernels: HBM bytes per launch (counters of these sources)
     # over their live mean launch time, against a measured streaming copy
@@ -428,7 +462,8 @@ def main():
                      "valu_lane_utilisation": (mc or {}).get("valu_lane_utilisation"), "node_visits_per_launch": visits / max(launches_per_step, 1),
                      "tri_tests_per_launch": tests / max(launches_per_step, 1),
                      "rays_per_launch": rays / max(launches_per_step, 1),
-                     "rays_per_s": rays / max(launches_per_step, 1) / (avg_ms / 1e3)},
+                     "rays_per_s": rays / max(launches_per_step, 1) / (avg_ms / 1e3),
+                     "forward_alone": alone},
         "kernels": kernels,
         "traversal": traversal,
         "hbm": hbm,

@@ -283,9 +283,12 @@ int st_check_errors(st_scene* scene, hipStream_t s);
  *    the BVH or by brute force; out_face int32 [n] (-1 miss), out_t float [n]. */
 int st_scene_info(const st_scene* scene, int64_t* out6);
 /* Traversal work counted by calls made with ST_COUNT_WORK since the last read:
- * host uint64 [4][3] = for the extension-ray kernel, the shadow-ray kernel, the
- * adjoint replay kernel and the single-kernel forward: BVH node visits,
- * triangle tests, rays traced.  Waits for s and resets the counters. */
+ * host uint64 [5][3] = for the extension rays and the shadow rays of the
+ * wavefront forward (wherever launched), the adjoint replay kernel, the
+ * single-kernel forward, and the paired launch that traces the extension rays
+ * of one bounce with the shadow rays of the bounce before (its rays are also
+ * in the first two rows): BVH node visits, triangle tests, rays traced.
+ * Waits for s and resets the counters. */
 int st_read_work(st_scene* scene, uint64_t* out3, hipStream_t s);
 int st_scene_edges(st_scene* scene, int32_t* out_edges, hipStream_t s);
 int st_scene_lbvh(st_scene* scene, uint64_t* keys, int32_t* child, int32_t* parent, float* aabb, hipStream_t s);

@@ -298,7 +298,7 @@ class GPUScene:
     def check_errors(self):
         _check(load().st_check_errors(self.h, _stream()))
 
-    WORK_KERNELS = ("k_extend", "k_shadow", "k_adjoint", "k_forward_mega")
+    WORK_KERNELS = ("k_extend", "k_shadow", "k_adjoint", "k_forward_mega", "k_trace_pair")
 
     def read_work(self):
         """{kernel: (node visits, triangle tests, rays)} counted by ST_COUNT_WORK calls since the last read."""

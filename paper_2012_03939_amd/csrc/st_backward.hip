@@ -1060,20 +1060,36 @@ void launch_primary_edges(const BwdParams& p, const FwdParams& fp, Queues& q, fl
     ST_LAUNCH("k_edge_finish", k_edge_finish, dim3(gridb(p.ne, 256, 1024), p.ncam), dim3(256), 0, st, p);
 }
 
-// Paths whose camera ray hit a face, in blocks of 256 consecutive paths (one
-// counter reservation per block, so the list keeps neighbouring pixels
-// together).  A path whose camera ray escaped has no vertex: its adjoint adds
-// nothing (the environment seen directly depends on neither the vertices nor
-// the materials), and its lanes would idle through the replay of the others.
+// Paths whose camera ray hit a face, in path order within each block's span.
+// A path whose camera ray escaped has no vertex: its adjoint adds nothing (the
+// environment seen directly depends on neither the vertices nor the
+// materials), and its lanes would idle through the replay of the others.  Each
+// thread looks at 16 consecutive paths, so a block reserves list slots once per
+// 4,096 paths: all blocks share the one counter, and a reservation per 256
+// paths kept the kernel waiting on it.
+constexpr int ADJ_LIST_PER = 16;
 __global__ void __launch_bounds__(256) k_adj_list(const int* __restrict__ rec_face, long long total, uint32_t* list,
                                                   int* n) {
-    __shared__ int resv[256 / 64 + 1];
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long b0 = (long long)blockIdx.x * blockDim.x; b0 < total; b0 += stride) {
-        const long long i = b0 + threadIdx.x;
-        const bool emit = i < total && qld(rec_face + i) >= 0;
-        const int o = block_reserve<256, 1>(emit, n, resv);
-        if (emit) list[o] = (uint32_t)i;
+    __shared__ int resv[2 * (256 / 64 + 1)];
+    constexpr long long span = 256ll * ADJ_LIST_PER;
+    for (long long b0 = (long long)blockIdx.x * span; b0 < total; b0 += (long long)gridDim.x * span) {
+        const long long i0 = b0 + (long long)threadIdx.x * ADJ_LIST_PER;
+        uint32_t m = 0;
+        if (i0 + ADJ_LIST_PER <= total) {
+            // rec_face is 256-B aligned and i0 a multiple of 16: four 16-B loads
+            const int4* v = (const int4*)(rec_face + i0);
+#pragma unroll
+            for (int j = 0; j < ADJ_LIST_PER / 4; ++j) {
+                const int4 a = v[j];
+                m |= (uint32_t)(a.x >= 0) << (4 * j) | (uint32_t)(a.y >= 0) << (4 * j + 1) |
+                     (uint32_t)(a.z >= 0) << (4 * j + 2) | (uint32_t)(a.w >= 0) << (4 * j + 3);
+            }
+        } else {
+            for (int j = 0; j < ADJ_LIST_PER && i0 + j < total; ++j) m |= (uint32_t)(rec_face[i0 + j] >= 0) << j;
+        }
+        // every thread of the block calls it (it synchronises the block)
+        int o = block_reserve2<256>(false, __popc(m), n, n, resv).y;
+        for (; m; m &= m - 1, ++o) list[o] = (uint32_t)(i0 + __ffs(m) - 1);
     }
 }
 
@@ -1118,8 +1134,8 @@ static void launch_adjoint(const BwdParams& p, long long total_paths, int grid, 
     }
     if (p.rec_split && p.adj_list) {
         launch_fill_u32((uint32_t*)p.adj_n, 1, 0u, st);
-        ST_LAUNCH("k_adj_list", k_adj_list, dim3(gridb(total_paths, 256, 1 << 14)), dim3(256), 0, st, p.rec_face,
-                  total_paths, p.adj_list, p.adj_n);
+        ST_LAUNCH("k_adj_list", k_adj_list, dim3(gridb(total_paths, 256 * ADJ_LIST_PER, 1 << 12)), dim3(256), 0, st,
+                  p.rec_face, total_paths, p.adj_list, p.adj_n);
     }
     if (p.rec_split && (p.flags & ST_EDGE_SECONDARY_HIERARCHY))
         ST_LAUNCH(name, (k_adjoint<BM, false, 2>), gd, bd, 0, st, p, total_paths);

@@ -38,8 +38,10 @@ constexpr int SPILL_STACK = 64 - LDS_STACK;  // further entries spilled to HBM (
 constexpr int TRAV_BLOCK = 256;              // threads of every block that traverses (LDS stack stride)
 constexpr uint32_t LEAF_BIT = 0x80000000u;
 constexpr int MAX_LIGHTS = 16;
-// slots of the traversal work counters (node visits, triangle tests, rays each)
-constexpr int WORK_EXTEND = 0, WORK_SHADOW = 1, WORK_ADJOINT = 2, WORK_MEGA = 3, WORK_SLOTS = 4;
+// slots of the traversal work counters (node visits, triangle tests, rays each):
+// extension rays and shadow rays wherever traced, the adjoint, the single-kernel
+// forward, and (counted a second time) the rays of the paired launch
+constexpr int WORK_EXTEND = 0, WORK_SHADOW = 1, WORK_ADJOINT = 2, WORK_MEGA = 3, WORK_PAIR = 4, WORK_SLOTS = 5;
 
 // error word bits (device -> host)
 constexpr uint32_t ERR_STACK = 1u;
@@ -165,6 +167,7 @@ struct TravStack {
     uint32_t gstride, gid;
     uint32_t* err;
     unsigned long long* work;   // optional: node visits, triangle tests, rays
+    unsigned long long* work2;  // optional: a second set of the same counters
     __device__ __forceinline__ void put(int i, uint32_t v) {
         if (i < LDS_STACK) lds[i * TRAV_BLOCK] = v;
         else spill[(i - LDS_STACK) * gstride + gid] = v;
@@ -202,6 +205,7 @@ __device__ __forceinline__ TravStack make_trav_stack(uint32_t* lds, uint32_t* sp
     s.gid = blockIdx.x * blockDim.x + threadIdx.x;
     s.err = err;
     s.work = work;
+    s.work2 = nullptr;
     return s;
 }
 
@@ -364,13 +368,14 @@ __device__ int trace_closest(const DevScene& S, V3 o, V3 d, float tmin, int excl
             node = st.get(--sp);
         }
     }
-    if (st.work) {
-        // node visits: one per iteration (the cap exit visits none)
-        const uint32_t visits = (uint32_t)min(iter + 1, TRAVERSAL_CAP);
-        atomicAdd(st.work, (unsigned long long)visits);
-        atomicAdd(st.work + 1, (unsigned long long)tests);
-        atomicAdd(st.work + 2, 1ull);
-    }
+    // node visits: one per iteration (the cap exit visits none)
+    const uint32_t visits = (uint32_t)min(iter + 1, TRAVERSAL_CAP);
+    for (unsigned long long* w : {st.work, st.work2})
+        if (w) {
+            atomicAdd(w, (unsigned long long)visits);
+            atomicAdd(w + 1, (unsigned long long)tests);
+            atomicAdd(w + 2, 1ull);
+        }
     thit = tbest;
     return best;
 }
@@ -428,11 +433,12 @@ __device__ __forceinline__ bool trace_any(const DevScene& S, V3 o, V3 d, float t
                                           TravStack& st) {
     uint32_t visits = 0, tests = 0;
     const bool r = trace_any_impl(S, o, d, tmin, tmax, exclude, st, visits, tests);
-    if (st.work) {
-        atomicAdd(st.work, (unsigned long long)visits);
-        atomicAdd(st.work + 1, (unsigned long long)tests);
-        atomicAdd(st.work + 2, 1ull);
-    }
+    for (unsigned long long* w : {st.work, st.work2})
+        if (w) {
+            atomicAdd(w, (unsigned long long)visits);
+            atomicAdd(w + 1, (unsigned long long)tests);
+            atomicAdd(w + 2, 1ull);
+        }
     return r;
 }
 

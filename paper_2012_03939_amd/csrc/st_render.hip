@@ -74,6 +74,39 @@ __global__ void k_camera(FwdParams p, Queues q, long long q0, int n) {
     }
 }
 
+// closest hit of queue entry i of bounce k
+__device__ __forceinline__ void extend_one(const FwdParams& p, const Queues& q, int k, float* const* r, int i,
+                                           TravStack& st) {
+    const DevCam& cam = p.cams[qu_ld(r, QVD, i) & 0xFFFFu];
+    const DevScene& S = p.scenes[cam.scene];
+    const V3 o = k == 1 ? ld3(cam.eye) : V3{qf(r, QOX, i), qf(r, QOY, i), qf(r, QOZ, i)};
+    const V3 d{qf(r, QDX, i), qf(r, QDY, i), qf(r, QDZ, i)};
+    uint32_t ex = qu_ld(r, QEXCL, i);
+    float t0 = __int_as_float(0x7f800000);
+    int f0 = -1;
+    if (k == 1 && ex != 0xFFFFFFFFu) {
+        // a primary-edge side ray names its edge: the edge's faces are
+        // tested first, so that the traversal starts with their hit
+        const int4 E = S.edges[ex & 0x7FFFFFFFu];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int fe = j == 0 ? E.z : E.w;
+            float th; int fh;
+            if (fe >= 0 && tri_test((const gfloat4*)S.tri, (uint32_t)S.fleaf[fe], o, d, TMIN,
+                                    __int_as_float(0x7f800000), th, fh) &&
+                (th < t0 || (th == t0 && fh < f0))) {
+                t0 = th;
+                f0 = fh;
+            }
+        }
+        ex = 0xFFFFFFFFu;
+    }
+    float t;
+    const int f = trace_closest(S, o, d, TMIN, (int)ex, t, st, t0, f0);
+    qst(q.ht + i, t);
+    qst(q.hf + i, f);
+}
+
 // closest hit for every queued ray of bounce k (queue k & 1)
 #ifndef ST_EXTEND_QUEUE
 #define ST_EXTEND_QUEUE 0
@@ -105,40 +138,14 @@ __global__ void __launch_bounds__(TRACE_BLOCK) EXTEND_OCC k_extend(FwdParams p, 
     }
     // 64 consecutive queue entries per wave, traced in lockstep
     const int stride = gridDim.x * blockDim.x;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const DevCam& cam = p.cams[qu_ld(r, QVD, i) & 0xFFFFu];
-        const DevScene& S = p.scenes[cam.scene];
-        const V3 o = k == 1 ? ld3(cam.eye) : V3{qf(r, QOX, i), qf(r, QOY, i), qf(r, QOZ, i)};
-        const V3 d{qf(r, QDX, i), qf(r, QDY, i), qf(r, QDZ, i)};
-        uint32_t ex = qu_ld(r, QEXCL, i);
-        float t0 = __int_as_float(0x7f800000);
-        int f0 = -1;
-        if (k == 1 && ex != 0xFFFFFFFFu) {
-            // a primary-edge side ray names its edge: the edge's faces are
-            // tested first, so that the traversal starts with their hit
-            const int4 E = S.edges[ex & 0x7FFFFFFFu];
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int fe = j == 0 ? E.z : E.w;
-                float th; int fh;
-                if (fe >= 0 && tri_test((const gfloat4*)S.tri, (uint32_t)S.fleaf[fe], o, d, TMIN,
-                                        __int_as_float(0x7f800000), th, fh) &&
-                    (th < t0 || (th == t0 && fh < f0))) {
-                    t0 = th;
-                    f0 = fh;
-                }
-            }
-            ex = 0xFFFFFFFFu;
-        }
-        float t;
-        const int f = trace_closest(S, o, d, TMIN, (int)ex, t, st, t0, f0);
-        qst(q.ht + i, t);
-        qst(q.hf + i, f);
-    }
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) extend_one(p, q, k, r, i, st);
 }
 
 #ifndef ST_SHADOW_QUEUE
 #define ST_SHADOW_QUEUE 0
+#endif
+#ifndef ST_PAIR_TRACE
+#define ST_PAIR_TRACE 1
 #endif
 // With one shadow entry per shading point and no decision hashes, k_shadow adds
 // each unoccluded contribution itself and records occlusion in the hit records,
@@ -323,6 +330,29 @@ __global__ void __launch_bounds__(SHADE_BLOCK) SHADE_OCC k_shade(FwdParams p, Qu
     }
 }
 
+// shadow ray w of the list of bounce k: occlusion code, or (fused) the
+// unoccluded contribution added and the occlusion recorded
+__device__ __forceinline__ void shadow_one(const FwdParams& p, const Queues& q, int k, float* const* r, int w,
+                                           bool fused, TravStack& st) {
+    const uint32_t e = qld(q.slist + w);
+    const int i = (int)(e % (uint32_t)q.cap);
+    const int f = qld(q.sface + i);
+    const DevScene& S = p.scenes[p.cams[qu_ld(r, QVD, i) & 0xFFFFu].scene];
+    const float tmax = qld(q.sh[3] + e);
+    const V3 o{qld(q.sx[0] + i), qld(q.sx[1] + i), qld(q.sx[2] + i)}, dd{qld(q.sh[0] + e), qld(q.sh[1] + e), qld(q.sh[2] + e)};
+    const bool occluded = trace_any(S, o, dd, TMIN, tmax, f, st);
+    if (fused) {
+        if (occluded) {
+            if (p.rec_occ && (qu_ld(r, QVD, i) >> 16) == 0u) p.rec_occ[(size_t)(k - 1) * p.rec_n + qu_ld(r, QQ, i)] = 1u;
+        } else {
+            float* L = q.L + 3 * (size_t)qu_ld(r, QQ, i);
+            L[0] += qld(q.sh[4] + e); L[1] += qld(q.sh[5] + e); L[2] += qld(q.sh[6] + e);
+        }
+    } else {
+        q.socc[e] = occluded ? 1 : 2;
+    }
+}
+
 // shadow rays of bounce k: the entries listed by k_shade (entry l of shading
 // point i is l * cap + i), one outcome code each (1 occluded, 2 unoccluded);
 // k_shade wrote 0 (no ray) for the others
@@ -352,23 +382,37 @@ __global__ void __launch_bounds__(TRACE_BLOCK) SHADOW_OCC k_shadow(FwdParams p, 
     const bool fused = shadow_fused(p, q);
     // 64 consecutive listed rays per wave, traced in lockstep
     const int stride = gridDim.x * blockDim.x;
-    for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < items; w += stride) {
-        const uint32_t e = qld(q.slist + w);
-        const int i = (int)(e % (uint32_t)q.cap);
-        const int f = qld(q.sface + i);
-        const DevScene& S = p.scenes[p.cams[qu_ld(r, QVD, i) & 0xFFFFu].scene];
-        const float tmax = qld(q.sh[3] + e);
-        const V3 o{qld(q.sx[0] + i), qld(q.sx[1] + i), qld(q.sx[2] + i)}, dd{qld(q.sh[0] + e), qld(q.sh[1] + e), qld(q.sh[2] + e)};
-        const bool occluded = trace_any(S, o, dd, TMIN, tmax, f, st);
-        if (fused) {
-            if (occluded) {
-                if (p.rec_occ && (qu_ld(r, QVD, i) >> 16) == 0u) p.rec_occ[(size_t)(k - 1) * p.rec_n + qu_ld(r, QQ, i)] = 1u;
-            } else {
-                float* L = q.L + 3 * (size_t)qu_ld(r, QQ, i);
-                L[0] += qld(q.sh[4] + e); L[1] += qld(q.sh[5] + e); L[2] += qld(q.sh[6] + e);
+    for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < items; w += stride) shadow_one(p, q, k, r, w, fused, st);
+}
+
+// One launch for the extension rays of bounce k + 1 and the shadow rays of
+// bounce k: both start at the shading points of bounce k and neither reads
+// what the other writes (hits of the next queue; radiance, occlusion records
+// or outcome codes of this bounce), so the two traversals share one grid and
+// one drain at the end instead of two.  Waves take the extension rays first
+// (their count rounded up to whole waves), then the listed shadow rays.
+__global__ void __launch_bounds__(TRACE_BLOCK) EXTEND_OCC k_trace_pair(FwdParams p, Queues q, int k) {
+    __shared__ uint32_t lds[LDS_STACK * TRACE_BLOCK];
+    TravStack st = make_trav_stack(lds, q.spill, p.err, nullptr);
+    st.work2 = p.work ? p.work + 3 * WORK_PAIR : nullptr;
+    unsigned long long* const wext = p.work ? p.work + 3 * WORK_EXTEND : nullptr;
+    unsigned long long* const wsh = p.work ? p.work + 3 * WORK_SHADOW : nullptr;
+    const int n = q.cnt[k + 1];
+    const int n64 = (n + 63) & ~63;
+    const int items = q.cnt[32 + k];
+    float* const* rn = q.ray[(k + 1) & 1];
+    float* const* r = q.ray[k & 1];
+    const bool fused = shadow_fused(p, q);
+    const int stride = gridDim.x * blockDim.x;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n64 + items; i += stride) {
+        if (i < n64) {
+            if (i < n) {
+                st.work = wext;
+                extend_one(p, q, k + 1, rn, i, st);
             }
         } else {
-            q.socc[e] = occluded ? 1 : 2;
+            st.work = wsh;
+            shadow_one(p, q, k, r, i - n64, fused, st);
         }
     }
 }
@@ -533,17 +577,30 @@ void launch_wavefront_bounces(const FwdParams& p, Queues& q, int n, int has_env_
     const unsigned gmax = (q.grid > 0 && (unsigned)q.grid < TRACE_GRID) ? (unsigned)q.grid : TRACE_GRID;
     const unsigned g = grid_for(n, TRACE_BLOCK, gmax);
     const int last = p.B + (has_env_any ? 1 : 0);
+    const bool fused = shadow_fused(p, q);
+    ST_LAUNCH("k_extend", k_extend, dim3(g), dim3(TRACE_BLOCK), 0, st, p, q, 1);
+    if (hook) hook->tick();
     for (int k = 1; k <= last; ++k) {
-        ST_LAUNCH("k_extend", k_extend, dim3(g), dim3(TRACE_BLOCK), 0, st, p, q, k);
-        if (hook) hook->tick();
+        // bounce k is traced: shade it, then trace its shadow rays together with
+        // the extension rays of bounce k + 1
         ST_LAUNCH("k_shade", k_shade, dim3(grid_for(n, SHADE_BLOCK, gmax)), dim3(SHADE_BLOCK), 0, st, p, q, k);
         if (hook) hook->tick();
-        if (k <= p.B) {
-            ST_LAUNCH("k_shadow", k_shadow, dim3(g), dim3(TRACE_BLOCK), 0, st, p, q, k);
+        const bool shadow = k <= p.B, next = k < last;
+        if (ST_PAIR_TRACE && shadow && next) {
+            ST_LAUNCH("k_trace_pair", k_trace_pair, dim3(g), dim3(TRACE_BLOCK), 0, st, p, q, k);
             if (hook) hook->tick();
-            if (!shadow_fused(p, q))
-                ST_LAUNCH("k_shadow_sum", k_shadow_sum, dim3(grid_for(n, 256, gmax)), dim3(256), 0, st, p, q, k);
+        } else {
+            if (shadow) {
+                ST_LAUNCH("k_shadow", k_shadow, dim3(g), dim3(TRACE_BLOCK), 0, st, p, q, k);
+                if (hook) hook->tick();
+            }
+            if (next) {
+                ST_LAUNCH("k_extend", k_extend, dim3(g), dim3(TRACE_BLOCK), 0, st, p, q, k + 1);
+                if (hook) hook->tick();
+            }
         }
+        if (shadow && !fused)
+            ST_LAUNCH("k_shadow_sum", k_shadow_sum, dim3(grid_for(n, 256, gmax)), dim3(256), 0, st, p, q, k);
     }
 }
 
