@@ -399,6 +399,13 @@ def main():
                  "frac": fflops / (fms / fn / 1e3) / 1e12 / PEAK_FP32_VECTOR_TFLOPS,
                  "note": "forward renders alone (one stream), 3 renders after the timed region"}
     kernels = {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[1] / args.steps} for k, v in prof.items()}
+    # every forward-style traversal launch of the step together (camera, extension
+    # and shadow rays of the main paths and of the primary-edge side paths)
+    trav_ms = sum(kernels[k]["ms_per_step"] for k in ("k_extend", "k_trace_pair", "k_shadow") if k in kernels)
+    trav_flops = sum(work[k][0] * FLOPS_PER_VISIT + work[k][1] * FLOPS_PER_TEST for k in ("k_extend", "k_shadow"))
+    traversal_all = {"kernels": ["k_extend", "k_trace_pair", "k_shadow"], "ms_per_step": trav_ms,
+                     "achieved": trav_flops / (trav_ms / 1e3) / 1e12 if trav_ms else None,
+                     "frac": trav_flops / (trav_ms / 1e3) / 1e12 / PEAK_FP32_VECTOR_TFLOPS if trav_ms else None}
     # rays, node visits and triangle tests of one step: per ray kind (extension
     # and shadow rays wherever traced), and per launch name where the row is its
     # own (time and rate only there)
@@ -463,7 +470,7 @@ def main():
                      "tri_tests_per_launch": tests / max(launches_per_step, 1),
                      "rays_per_launch": rays / max(launches_per_step, 1),
                      "rays_per_s": rays / max(launches_per_step, 1) / (avg_ms / 1e3),
-                     "forward_alone": alone},
+                     "forward_alone": alone, "traversal_all": traversal_all},
         "kernels": kernels,
         "traversal": traversal,
         "hbm": hbm,
