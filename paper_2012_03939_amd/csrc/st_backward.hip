@@ -84,14 +84,29 @@ __device__ __forceinline__ float* mat_slots(float* facc, float* macc, bool texel
 }
 
 // Adds vals to the accumulators of face f (slots 0..8: the three corners) and
-// of its texel tx (slots 9..15: the material) with one set of atomics per
-// (texel, wave): lanes of the wave with the same texel (hence the same face)
-// are summed first, peeling one texel per round; partner lanes add into the
-// leader's LDS row.  Primary hits of a wave are the 64 pixels of a tile, so few
-// texels cover most lanes.  Lanes with !has contribute nothing.
-// red: this wave's FACC floats of LDS.
+// of its texel tx (slots 9..15: the material) with one atomic instruction per
+// (texel, wave): every lane stores its 16 values in its own LDS row, then for
+// each texel of the wave (one per round, the first pending lane's) the active
+// lanes sum the 16 slots over the lanes of that texel (the r-th active lane
+// slots r, r + n, ... of n active lanes: one slot each in a full wave) and add
+// the sums with one atomic instruction.  Primary hits of a wave are
+// neighbouring pixels, so few texels cover most lanes.  Lanes with !has
+// contribute nothing; any subset of the wave's lanes may call it together.
+// red: this wave's 64 x FACC floats of LDS.
 __device__ __forceinline__ void face_reduce_add(bool has, int f, int tx, const float (&vals)[FACC], float* facc,
                                                 float* macc, bool texels, float* red) {
+    const int lane = (int)__lane_id();
+    const uint64_t act = __ballot(true);
+    const int nact = __popcll(act);
+    const int rank = __popcll(act & lanemask_lt64());
+    float4* const row = (float4*)(red + lane * FACC);
+#pragma unroll
+    for (int j = 0; j < FACC / 4; ++j) row[j] = make_float4(vals[4 * j], vals[4 * j + 1], vals[4 * j + 2], vals[4 * j + 3]);
+    // the rows are read by other lanes of this wave: LDS accesses of one wave
+    // complete in order; this keeps the compiler from moving the reads up
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     bool pending = has;
     for (;;) {
         const uint64_t m = __ballot(pending);
@@ -100,27 +115,18 @@ __device__ __forceinline__ void face_reduce_add(bool has, int f, int tx, const f
         const int lt = __builtin_amdgcn_readlane(tx, leader);
         const int lf = __builtin_amdgcn_readlane(f, leader);
         const bool mine = pending && tx == lt;
-        const bool lead = (int)__lane_id() == leader;
         const uint64_t grp = __ballot(mine);
-        if (grp != (1ull << leader)) {
-            if (lead)
-#pragma unroll
-                for (int j = 0; j < FACC; ++j) red[j] = vals[j];
-            if (mine && !lead)
-#pragma unroll
-                for (int j = 0; j < FACC; ++j) atomicAdd(red + j, vals[j]);
-        }
-        if (lead) {
-            const bool single = grp == (1ull << leader);
-            float* const fa = facc + (size_t)FACC_STRIDE * lf;
-            float* const ma = mat_slots(facc, macc, texels, lf, lt);
-#pragma unroll
-            for (int j = 0; j < 9; ++j) atomicAdd(fa + j, single ? vals[j] : red[j]);
-#pragma unroll
-            for (int j = 0; j < 7; ++j) atomicAdd(ma + j, single ? vals[9 + j] : red[9 + j]);
+        for (int j = rank; j < FACC; j += nact) {
+            float acc = 0.0f;
+            for (uint64_t g = grp; g; g &= g - 1) acc += red[(__ffsll((long long)g) - 1) * FACC + j];
+            float* const dst = j < FACC_MAT ? facc + (size_t)FACC_STRIDE * lf + j
+                                            : mat_slots(facc, macc, texels, lf, lt) + (j - FACC_MAT);
+            atomicAdd(dst, acc);
         }
         pending = pending && !mine;
     }
+    // the next call rewrites the rows
+    __builtin_amdgcn_wave_barrier();
 }
 
 // occupancy target of the adjoint (waves per SIMD): the register budget the
@@ -146,7 +152,7 @@ __global__ void __launch_bounds__(TRACE_BLOCK) __attribute__((amdgpu_waves_per_e
 k_adjoint(BwdParams p, long long total) {
     constexpr bool REC = RECM > 0;
     __shared__ uint32_t lds[LDS_STACK * TRACE_BLOCK];
-    __shared__ float red_s[TRACE_BLOCK / 64][FACC];
+    __shared__ float red_s[TRACE_BLOCK / 64][64 * FACC];
     float* const red = red_s[threadIdx.x >> 6];
     TravStack st = make_trav_stack(lds, p.spill, p.err, p.work ? p.work + 3 * WORK_ADJOINT : nullptr);
     const bool want_interior = !JOBS && (p.flags & 1u), want_secondary = p.flags & 4u;
