@@ -1076,7 +1076,7 @@ void launch_primary_edges(const BwdParams& p, const FwdParams& fp, Queues& q, fl
 constexpr int ADJ_LIST_PER = 16;
 __global__ void __launch_bounds__(256) k_adj_list(const int* __restrict__ rec_face, long long total, uint32_t* list,
                                                   int* n) {
-    __shared__ int resv[2 * (256 / 64 + 1)];
+    __shared__ int resv[256 / 64 + 1];
     constexpr long long span = 256ll * ADJ_LIST_PER;
     for (long long b0 = (long long)blockIdx.x * span; b0 < total; b0 += (long long)gridDim.x * span) {
         const long long i0 = b0 + (long long)threadIdx.x * ADJ_LIST_PER;
@@ -1094,25 +1094,43 @@ __global__ void __launch_bounds__(256) k_adj_list(const int* __restrict__ rec_fa
             for (int j = 0; j < ADJ_LIST_PER && i0 + j < total; ++j) m |= (uint32_t)(rec_face[i0 + j] >= 0) << j;
         }
         // every thread of the block calls it (it synchronises the block)
-        int o = block_reserve2<256>(false, __popc(m), n, n, resv).y;
+        int o = block_reserve_n<256, 5>(__popc(m), n, resv);
         for (; m; m &= m - 1, ++o) list[o] = (uint32_t)(i0 + __ffs(m) - 1);
     }
 }
 
-// (path, vertex) jobs of the marked secondary edge samples, in blocks of 256
-// paths with one counter reservation per block and bit
+// (path, vertex) jobs of the marked secondary edge samples, in path and vertex
+// order within each block's span: each thread reads the marks of 16
+// consecutive paths (one 16-byte load), and a block reserves job slots once
+// per 4,096 paths (all blocks share the one counter; a reservation per 256
+// paths and bit kept the kernel waiting on it)
+constexpr int SEC_JOBS_PER = 16;
 __global__ void __launch_bounds__(256) k_sec_jobs(const uint8_t* __restrict__ mask, long long total, int B,
                                                  int2* jobs, int* njobs, uint32_t* err) {
     __shared__ int resv[256 / 64 + 1];
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long b0 = (long long)blockIdx.x * blockDim.x; b0 < total; b0 += stride) {
-        const long long i = b0 + threadIdx.x;
-        const uint32_t m = i < total ? mask[i] : 0u;
-        for (int k = 0; k < B; ++k) {
-            const bool emit = (m >> k) & 1u;
-            const int o = block_reserve<256, 1>(emit, njobs, resv);
-            if (emit) {
-                if ((long long)o < total * B) jobs[o] = make_int2((int)i, k);   // at most B per path
+    constexpr long long span = 256ll * SEC_JOBS_PER;
+    const uint32_t keep = 0x01010101u * ((1u << B) - 1u);     // the B vertex bits of each byte
+    for (long long b0 = (long long)blockIdx.x * span; b0 < total; b0 += (long long)gridDim.x * span) {
+        const long long i0 = b0 + (long long)threadIdx.x * SEC_JOBS_PER;
+        uint32_t w[4] = {0u, 0u, 0u, 0u};
+        if (i0 + SEC_JOBS_PER <= total) {
+            // mask is 16-B aligned and i0 a multiple of 16
+            const uint4 v = *(const uint4*)(mask + i0);
+            w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+        } else {
+            for (int j = 0; j < SEC_JOBS_PER && i0 + j < total; ++j) w[j >> 2] |= (uint32_t)mask[i0 + j] << (8 * (j & 3));
+        }
+        int cnt = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            w[q] &= keep;
+            cnt += __popc(w[q]);
+        }
+        // every thread of the block calls it (it synchronises the block); at most 16 x 8 jobs
+        int o = block_reserve_n<256, 8>(cnt, njobs, resv);
+        for (int j = 0; j < SEC_JOBS_PER; ++j) {
+            for (uint32_t m = (w[j >> 2] >> (8 * (j & 3))) & 0xFFu; m; m &= m - 1, ++o) {
+                if ((long long)o < total * B) jobs[o] = make_int2((int)(i0 + j), __ffs(m) - 1);   // at most B per path
                 else atomicOr(err, ERR_QUEUE);
             }
         }
@@ -1150,7 +1168,7 @@ static void launch_adjoint(const BwdParams& p, long long total_paths, int grid, 
     // (returns at once when the records pass above found its records valid)
     ST_LAUNCH(name, (k_adjoint<BM, false>), gd, bd, 0, st, p, total_paths);
     if (p.sec_mask) {
-        ST_LAUNCH("k_sec_jobs", k_sec_jobs, dim3(gridb(total_paths, 256, 1 << 14)), dim3(256), 0, st, p.sec_mask,
+        ST_LAUNCH("k_sec_jobs", k_sec_jobs, dim3(gridb(total_paths, 256 * SEC_JOBS_PER, 1 << 12)), dim3(256), 0, st, p.sec_mask,
                   total_paths, p.B, p.sec_jobs, p.sec_njobs, p.err);
         // the job count stays on the device: a fixed grid strides over it
         ST_LAUNCH(name_jobs, (k_adjoint<BM, true>), dim3(1024), bd, 0, st, p, 0ll);

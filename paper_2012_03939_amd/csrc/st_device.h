@@ -1003,6 +1003,37 @@ __device__ __forceinline__ int block_reserve(bool emit, int* counter, int* lds) 
     return emit ? o : -1;
 }
 
+// m (0 <= m < 2^BITS) consecutive slots per thread from *counter, in thread
+// order within the block, with one atomic per block; every thread of the block
+// calls it (it synchronises the block).  lds holds BS / 64 + 1 ints.
+template <int BS, int BITS>
+__device__ __forceinline__ int block_reserve_n(int m, int* counter, int* lds) {
+    constexpr int NW = BS / 64;
+    const uint64_t lt = lanemask_lt64();
+    int pre = 0, tot = 0;
+    for (int b = 0; b < BITS; ++b) {
+        const uint64_t bm = __ballot((m >> b) & 1);
+        pre += __popcll(bm & lt) << b;
+        tot += __popcll(bm) << b;
+    }
+    const int w = (int)(threadIdx.x >> 6);
+    if (__lane_id() == 0) lds[w] = tot;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int j = 0; j < NW; ++j) {
+            const int x = lds[j];
+            lds[j] = acc;
+            acc += x;
+        }
+        lds[NW] = acc > 0 ? atomicAdd(counter, acc) : 0;
+    }
+    __syncthreads();
+    const int o = lds[NW] + lds[w] + pre;
+    __syncthreads();
+    return o;
+}
+
 // Two reservations in one pass: one slot per thread with emit from *ca, and m
 // (0 <= m < 32) consecutive slots per thread from *cb.  Returns (slot or -1,
 // first of the m slots).  lds holds 2 (BS / 64 + 1) ints.
