@@ -403,16 +403,18 @@ __global__ void __launch_bounds__(TRACE_BLOCK) EXTEND_OCC k_trace_pair(FwdParams
     float* const* rn = q.ray[(k + 1) & 1];
     float* const* r = q.ray[k & 1];
     const bool fused = shadow_fused(p, q);
-    const int stride = gridDim.x * blockDim.x;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n64 + items; i += stride) {
-        if (i < n64) {
-            if (i < n) {
+    // unsigned: with many lights the two counts together can pass 2^31 (each is
+    // below 2^31, the grid below 2^21, so the sum and the next index fit 32 bits)
+    const uint32_t stride = gridDim.x * blockDim.x, all = (uint32_t)n64 + (uint32_t)items;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < all; i += stride) {
+        if (i < (uint32_t)n64) {
+            if (i < (uint32_t)n) {
                 st.work = wext;
-                extend_one(p, q, k + 1, rn, i, st);
+                extend_one(p, q, k + 1, rn, (int)i, st);
             }
         } else {
             st.work = wsh;
-            shadow_one(p, q, k, r, i - n64, fused, st);
+            shadow_one(p, q, k, r, (int)(i - (uint32_t)n64), fused, st);
         }
     }
 }
