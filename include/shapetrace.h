@@ -248,7 +248,8 @@ int st_render_batch(st_scene* const* scenes, int32_t nscenes, const st_camera* c
 /* Autotuner: times st_render of this exact workload (same arguments as
  * st_render_batch; cam_scene may be NULL for one scene) over wavefront chunk
  * sizes {2^20..2^27} x traversal grids {1024, 2048, 4096} blocks and keeps the
- * fastest on every scene in the list; later renders and backward passes of
+ * fastest on every scene in the list (a smaller chunk or grid must be 3 %
+ * faster than a larger one to be chosen); later renders and backward passes of
  * those scenes use it unless opts->queue_capacity is set.  cache_path (may be
  * NULL): JSON-lines file keyed by device and workload signature; a matching
  * line is used without timing, a new result is appended.  Synchronises s and
