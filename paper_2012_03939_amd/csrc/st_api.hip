@@ -647,6 +647,8 @@ int st_scene_create(const float* V, int32_t nv, const int32_t* F, int32_t nf, co
     A(dalloc(&d.nodes4, 8 * (size_t)std::max(nf - 1, 1)));
     A(dalloc(&d.flag4, (size_t)std::max(nf - 1, 1)));
     A(dalloc(&d.id4, (size_t)std::max(nf - 1, 1)));
+    A(dalloc(&d.ccost, (size_t)std::max(nf - 1, 1)));
+    A(dalloc(&d.cdec, (size_t)std::max(nf - 1, 1)));
     A(dalloc(&d.tri, 3 * (size_t)nf));
     A(dalloc(&d.fleaf, (size_t)nf));
     A(dalloc(&d.vf_off, (size_t)nv + 1));
@@ -1437,7 +1439,7 @@ void st_scene_destroy(st_scene* sc) {
     SceneDev& d = sc->d;
     void* ptrs[] = {d.V, d.F, d.mat, d.lights, d.env, d.fnorm, d.bmin, d.bmax, d.cen, d.bounds, d.mkeys[0], d.mkeys[1],
                     d.mvals[0], d.mvals[1], d.rs_hist, d.keys64, d.child, d.parent, d.aabb, d.refit_cnt, d.tcost, d.tleaves, d.ebmin, d.ebmax, d.ecen, d.ebounds, d.emkeys[0], d.emkeys[1],
-                    d.emvals[0], d.emvals[1], d.ers_hist, d.ekeys64, d.echild, d.eparent, d.ecnt, d.eaabb, d.elen, d.enbox, d.enode, d.nodes4, d.flag4, d.id4,
+                    d.emvals[0], d.emvals[1], d.ers_hist, d.ekeys64, d.echild, d.eparent, d.ecnt, d.eaabb, d.elen, d.enbox, d.enode, d.nodes4, d.flag4, d.id4, d.ccost, d.cdec,
                     d.tri, d.fleaf, d.edges, d.edge_w, d.eguide, d.mguide, d.cguide, d.ecdf, d.etotal_d, d.etotal_f, d.row_dom, d.rowcos, d.cond, d.marg,
                     d.env_rows, d.env_total, d.texpdf, d.err, d.work, d.dscene, d.vf_off, d.vf_idx, d.facc, d.macc, d.fe,
                     d.ealias, d.rec_key};

@@ -524,46 +524,149 @@ __global__ __launch_bounds__(TL_BLOCK) void k_treelet(int* child, int* parent, f
     if (guard == TL_GUARD && active) atomicOr(err, ERR_LOOP);
 }
 
-// depth of every internal node of the binary tree, and the flag "starts a
-// 4-wide node" (even depth)
-__global__ void k_depth(const int* __restrict__ parent, int n, int* flag) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n - 1) return;
-    int d = 0, x = i;
-    for (int guard = 0; guard < TL_GUARD && parent[x] >= 0; ++guard) { x = parent[x]; ++d; }
-    flag[i] = (d & 1) ? 0 : 1;
+// Collapse of the binary tree into 4-wide nodes with the least summed box area
+// of the 4-wide nodes (under the surface-area measure, the expected number of
+// node visits of a ray that meets the root box; every triangle stays one leaf
+// slot, so triangle tests do not depend on the collapse).  Bottom-up, like the
+// refit, every internal node x with children l, r gets
+//   D[x][1] = A(x) + min over a, b >= 1, a + b <= 4 of D[l][a] + D[r][b]
+//             (x heads a 4-wide node; as a slot of its parent it is one slot)
+//   D[x][k] = min(D[x][k - 1], min over a + b = k of D[l][a] + D[r][b]),  k = 2..4
+//             (x opened: its subtree fills up to k slots of the enclosing node)
+// with D = 0 for a leaf.  Ties keep the first candidate in the order written,
+// so the tree is a function of the binary tree alone.  cdec[x]: bits 0-1 and
+// 2-3 hold a - 1 and b - 1 of the first line; bits 4 + 2 (k - 2), two per k,
+// the a of the second line (0: k - 1 slots).
+__device__ __forceinline__ float box_area(const float* b) {
+    const float dx = b[3] - b[0], dy = b[4] - b[1], dz = b[5] - b[2];
+    return 2.0f * (dx * dy + dy * dz + dz * dx);
 }
 
-// 4-wide node of an even-depth binary node: its children, with every internal
-// child replaced by that child's own two children (8 float4: min x, max x,
-// min y, max y, min z, max z of the 4 slots, child codes, pad)
+__global__ void k_collapse_cost(const int* __restrict__ parent, const int* __restrict__ child,
+                                const float* __restrict__ aabb, int n, int* cnt, float* cost, uint32_t* dec) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int node = parent[(n - 1) + i];
+    for (int depth = 0; node >= 0 && depth < 128; ++depth) {
+        __threadfence();
+        if (atomicAdd(&cnt[node], 1) == 0) return;    // the other child is not done yet
+        __threadfence();
+        float D[2][5];
+        for (int j = 0; j < 2; ++j) {
+            const int c = child[2 * node + j];
+            D[j][0] = 0.0f;
+            for (int k = 1; k <= 4; ++k) D[j][k] = (c & (int)LEAF_BIT) ? 0.0f : aload(cost + 4 * (size_t)c + (k - 1));
+        }
+        float head = __int_as_float(0x7f800000);
+        uint32_t d = 0;
+        for (int a = 1; a <= 3; ++a)
+            for (int b = 1; a + b <= 4; ++b)
+                if (D[0][a] + D[1][b] < head) {
+                    head = D[0][a] + D[1][b];
+                    d = (uint32_t)(a - 1) | ((uint32_t)(b - 1) << 2);
+                }
+        float Dx[5];
+        Dx[1] = box_area(aabb + 6 * (size_t)node) + head;
+        for (int k = 2; k <= 4; ++k) {
+            float v = Dx[k - 1];
+            uint32_t choice = 0;
+            for (int a = 1; a < k; ++a)
+                if (D[0][a] + D[1][k - a] < v) {
+                    v = D[0][a] + D[1][k - a];
+                    choice = (uint32_t)a;
+                }
+            Dx[k] = v;
+            d |= choice << (4 + 2 * (k - 2));
+        }
+        for (int k = 1; k <= 4; ++k)
+            __hip_atomic_store((uint32_t*)(cost + 4 * (size_t)node + (k - 1)), __float_as_uint(Dx[k]), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        dec[node] = d;
+        node = parent[node];
+    }
+}
+
+// the number of slots (1..k) that node x's subtree takes in the enclosing 4-wide
+// node when offered k: fewer while its choice for k is "k - 1 slots"
+__device__ __forceinline__ int collapse_slots(uint32_t dx, int k) {
+    while (k >= 2 && ((dx >> (4 + 2 * (k - 2))) & 3u) == 0u) --k;
+    return k;
+}
+
+// flag[x] = 1 when internal node x heads a 4-wide node: the choices of its
+// ancestors, replayed from the root down, leave it one slot (the root heads the
+// tree).  The path is read upwards into a bit string first.
+__global__ void k_collapse_flag(const int* __restrict__ parent, const int* __restrict__ child,
+                                const uint32_t* __restrict__ dec, int n, int* flag, uint32_t* err) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n - 1) return;
+    uint64_t bits[2] = {0ull, 0ull};   // bit j: the node at depth j + 1 on the path is a right child
+    int depth = 0;
+    for (int x = i; parent[x] >= 0; x = parent[x]) {
+        if (depth >= 128) {
+            // deeper than any radix tree over 64-bit keys: head a node (fewer slots
+            // for the parent, never more)
+            atomicOr(err, ERR_LOOP);
+            flag[i] = 1;
+            return;
+        }
+        const int px = parent[x];
+        const uint64_t right = child[2 * px + 1] == x ? 1ull : 0ull;
+        bits[depth >> 6] |= right << (depth & 63);
+        ++depth;
+    }
+    // bits hold the path from i upwards: bit depth - 1 is the root's child
+    int v = 0, k = 1;      // node on the path and its slot budget (1: heads a 4-wide node)
+    for (int lvl = depth - 1; lvl >= 0; --lvl) {
+        const uint32_t dv = dec[v];
+        int a, b;
+        if (k == 1) {
+            a = (int)(dv & 3u) + 1;
+            b = (int)((dv >> 2) & 3u) + 1;
+        } else {
+            a = (int)((dv >> (4 + 2 * (k - 2))) & 3u);
+            b = k - a;
+        }
+        const int right = (int)((bits[lvl >> 6] >> (lvl & 63)) & 1ull);
+        const int c = child[2 * v + right];
+        k = collapse_slots(dec[c], right ? b : a);
+        v = c;
+    }
+    flag[i] = k == 1 ? 1 : 0;
+}
+
+// 4-wide node of a binary node x that heads one: its children, every internal
+// one that does not head a node replaced by its own two children until only
+// leaves and heads remain (at most 4 by the costs above), in tree order (8
+// float4: min x, max x, min y, max y, min z, max z of the 4 slots, child codes,
+// pad)
 __global__ void k_pack4(const int* __restrict__ child, const float* __restrict__ aabb, const int* __restrict__ flag,
-                        const uint32_t* __restrict__ id4, int n, float4* nodes4) {
+                        const uint32_t* __restrict__ id4, int n, float4* nodes4, uint32_t* err) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n - 1 || !flag[i]) return;
-    int codes[4];
-    size_t box[4];
-    int m = 0;
-    for (int a = 0; a < 2; ++a) {
-        const int c = child[2 * i + a];
-        if (c & (int)LEAF_BIT) {
-            codes[m] = c;
-            box[m++] = (size_t)(n - 1) + (c & 0x7FFFFFFF);
-        } else {
-            for (int b = 0; b < 2; ++b) {
-                const int g = child[2 * c + b];
-                if (g & (int)LEAF_BIT) { codes[m] = g; box[m++] = (size_t)(n - 1) + (g & 0x7FFFFFFF); }
-                else { codes[m] = (int)id4[g]; box[m++] = (size_t)g; }
-            }
-        }
+    int sl[4] = {child[2 * i], child[2 * i + 1], 0, 0};
+    int m = 2;
+    for (int pass = 0; pass < 3; ++pass) {
+        int at = -1;
+        for (int s = 0; s < m; ++s)
+            if (at < 0 && !(sl[s] & (int)LEAF_BIT) && !flag[sl[s]]) at = s;
+        if (at < 0) break;
+        if (m == 4) { atomicOr(err, ERR_LOOP); break; }   // cannot happen: the costs allow at most 4 slots
+        const int x = sl[at];
+        for (int s = m; s > at + 1; --s) sl[s] = sl[s - 1];
+        sl[at] = child[2 * x];
+        sl[at + 1] = child[2 * x + 1];
+        ++m;
     }
     float v[6][4];
     int cc[4];
     for (int s = 0; s < 4; ++s) {
         if (s < m) {
-            const float* bb = aabb + 6 * box[s];
+            const int c = sl[s];
+            const size_t bi = (c & (int)LEAF_BIT) ? (size_t)(n - 1) + (c & 0x7FFFFFFF) : (size_t)c;
+            const float* bb = aabb + 6 * bi;
             v[0][s] = bb[0]; v[1][s] = bb[3]; v[2][s] = bb[1]; v[3][s] = bb[4]; v[4][s] = bb[2]; v[5][s] = bb[5];
-            cc[s] = codes[s];
+            cc[s] = (c & (int)LEAF_BIT) ? c : (int)id4[c];
         } else {
             // an empty slot is a box at +infinity on every axis: its slab test
             // gives an entry distance of +inf or an empty interval, a miss either way
@@ -896,11 +999,15 @@ void launch_scene_geometry(SceneDev& s, hipStream_t st) {
             ST_LAUNCH("k_treelet", k_treelet, dim3(nb(nf, TL_BLOCK)), dim3(TL_BLOCK), 0, st, s.child, s.parent, s.aabb,
                       s.tcost, s.tleaves, s.refit_cnt, nf, s.err);
         }
-        ST_LAUNCH("k_depth", k_depth, dim3(nb(nf - 1, 256)), dim3(256), 0, st, s.parent, nf, s.flag4);
+        launch_fill_u32((uint32_t*)s.refit_cnt, nf - 1, 0u, st);
+        ST_LAUNCH("k_collapse_cost", k_collapse_cost, dim3(nb(nf, 256)), dim3(256), 0, st, s.parent, s.child, s.aabb,
+                  nf, s.refit_cnt, (float*)s.ccost, s.cdec);
+        ST_LAUNCH("k_collapse_flag", k_collapse_flag, dim3(nb(nf - 1, 256)), dim3(256), 0, st, s.parent, s.child,
+                  s.cdec, nf, s.flag4, s.err);
         hipMemcpyAsync(s.id4, s.flag4, sizeof(int) * (nf - 1), hipMemcpyDeviceToDevice, st);
         ST_LAUNCH("k_rs_scan", k_rs_scan, dim3(1), dim3(1024), 0, st, s.id4, nf - 1);
         ST_LAUNCH("k_pack4", k_pack4, dim3(nb(nf - 1, 256)), dim3(256), 0, st, s.child, s.aabb, s.flag4, s.id4, nf,
-                  s.nodes4);
+                  s.nodes4, s.err);
     }
     if (s.ne > 0) {
         ST_LAUNCH("k_edge_len", k_edge_len, dim3(nb(s.ne, 256)), dim3(256), 0, st, s.edges, s.ne, s.V, s.edge_w);

@@ -72,8 +72,10 @@ struct SceneDev {
     const uint32_t* eleaf_edge = nullptr;    // points into emkeys/emvals after the sort
     int* tleaves = nullptr;                  // [nf-1] triangles below every internal node
     float4* nodes4 = nullptr;                // [(nf-1)*8] 4-wide nodes (at most nf-1 of them)
-    int* flag4 = nullptr;                    // [nf-1] even-depth flag of the binary nodes
-    uint32_t* id4 = nullptr;                 // [nf-1] 4-wide node index of each even-depth node
+    int* flag4 = nullptr;                    // [nf-1] binary node starts a 4-wide node
+    uint32_t* id4 = nullptr;                 // [nf-1] 4-wide node index of each such node
+    float4* ccost = nullptr;                 // [nf-1] collapse cost of a subtree in 1..4 slots
+    uint32_t* cdec = nullptr;                // [nf-1] collapse decisions (bit fields, see k_collapse_cost)
     float4* tri = nullptr;                   // [nf*3]
     int* fleaf = nullptr;                    // [nf] leaf index of each face
     // edges (topology fixed at creation)
