@@ -180,6 +180,7 @@ struct st_scene {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     GrowBuf spill_aux;
     GrowBuf adjbuf;                    // the adjoint's list of paths that have a vertex
+    GrowBuf vrecbuf;                   // the adjoint's per-vertex replay records
 };
 
 namespace {
@@ -1096,7 +1097,8 @@ int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_
                             cs.total_paths > 0 && cs.total_paths < (1ll << 31);
     {
         size_t need = SPILL_BYTES + pbytes + (defer_sec ? sec_workspace_bytes(cs.total_paths, bounces) : 0) +
-                      (adj_listed ? adj_list_bytes(cs.total_paths) : 0);
+                      (adj_listed ? adj_list_bytes(cs.total_paths) : 0) +
+                      ((o.flags & 5u) && cs.total_paths > 0 ? adj_vrec_bytes(bounces) : 0);
         if (prim)
             need += (size_t)cs.total_edges * 6 * sizeof(float) +
                     (o.debug_edge_hash ? (size_t)cs.total_edges * 2 * sizeof(uint32_t) : 0) +
@@ -1185,6 +1187,12 @@ int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_
     // the per-face gather into dV waits for both.
     const bool adjoint = (p.flags & 5u) && cs.total_paths > 0;
     const bool overlap = adjoint && prim && !g_capturing;
+    p.vrec = nullptr;
+    if (adjoint) {
+        rc = sc->vrecbuf.ensure(adj_vrec_bytes(bounces));
+        if (rc) return rc;
+        p.vrec = (float*)sc->vrecbuf.p;
+    }
     // every workspace first: between the fork and the join nothing may fail
     uint32_t* hside = nullptr;
     Queues q;
@@ -1448,6 +1456,7 @@ void st_scene_destroy(st_scene* sc) {
     sc->Lbuf.release(); sc->qbuf.release(); sc->spillbuf.release(); sc->primbuf.release(); sc->recbuf.release();
     sc->sidebuf.release(); sc->sidehash.release(); sc->secbuf.release(); sc->spill_aux.release();
     sc->adjbuf.release();
+    sc->vrecbuf.release();
     if (sc->ev_fork) hipEventDestroy(sc->ev_fork);
     if (sc->ev_join) hipEventDestroy(sc->ev_join);
     if (sc->aux) hipStreamDestroy(sc->aux);

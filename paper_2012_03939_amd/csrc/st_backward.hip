@@ -38,6 +38,41 @@ template <class T, int N> __device__ __forceinline__ void put(T (&a)[N], int k, 
         if (i == k) a[i] = v;
 }
 
+// Per-vertex records of a path replay, in a per-thread region of global memory:
+// slot s of thread g at base[s * gstride + g] (a wave's 64 threads in 256
+// consecutive bytes).  As private arrays they sat in scratch memory anyway (the
+// sweep indexes them by a loop counter), and were cleared for every path; here
+// an entry is written only when the replay reaches its vertex and read only
+// then.  A field of type T for BM vertices takes BM * W slots from s0 on (W = 3
+// for a vector).
+struct RecMem {
+    float* base;
+    size_t gstride, gid;
+    __device__ __forceinline__ float& at(int slot) const { return base[(size_t)slot * gstride + gid]; }
+};
+template <class T, int BM> struct RecField {
+    const RecMem* m;
+    int s0;
+};
+template <int BM> __device__ __forceinline__ V3 sel(const RecField<V3, BM>& f, int k) {
+    const int s = f.s0 + 3 * k;
+    return V3{f.m->at(s), f.m->at(s + 1), f.m->at(s + 2)};
+}
+template <int BM> __device__ __forceinline__ void put(const RecField<V3, BM>& f, int k, const V3& v) {
+    const int s = f.s0 + 3 * k;
+    f.m->at(s) = v.x; f.m->at(s + 1) = v.y; f.m->at(s + 2) = v.z;
+}
+template <int BM> __device__ __forceinline__ float sel(const RecField<float, BM>& f, int k) { return f.m->at(f.s0 + k); }
+template <int BM> __device__ __forceinline__ void put(const RecField<float, BM>& f, int k, float v) { f.m->at(f.s0 + k) = v; }
+template <class T, int BM> __device__ __forceinline__ T sel(const RecField<T, BM>& f, int k) {
+    static_assert(sizeof(T) == 4, "32-bit fields");
+    return (T)__float_as_uint(f.m->at(f.s0 + k));
+}
+template <class T, int BM> __device__ __forceinline__ void put(const RecField<T, BM>& f, int k, const T& v) {
+    static_assert(sizeof(T) == 4, "32-bit fields");
+    f.m->at(f.s0 + k) = __uint_as_float((uint32_t)v);
+}
+
 __device__ __forceinline__ void atomic_add3(float* p, V3 g) {
     atomicAdd(p, g.x);
     atomicAdd(p + 1, g.y);
@@ -155,6 +190,7 @@ k_adjoint(BwdParams p, long long total) {
     __shared__ float red_s[TRACE_BLOCK / 64][64 * FACC];
     float* const red = red_s[threadIdx.x >> 6];
     TravStack st = make_trav_stack(lds, p.spill, p.err, p.work ? p.work + 3 * WORK_ADJOINT : nullptr);
+    const RecMem rm{p.vrec, (size_t)gridDim.x * blockDim.x, (size_t)blockIdx.x * blockDim.x + threadIdx.x};
     const bool want_interior = !JOBS && (p.flags & 1u), want_secondary = p.flags & 4u;
     const bool sec_interior = p.flags & ST_EDGE_SECONDARY_INTERIOR;   // creases / material edges too
     const bool hier = RECM != 1 && (p.flags & ST_EDGE_SECONDARY_HIERARCHY);   // edges from the importance tree
@@ -199,16 +235,15 @@ k_adjoint(BwdParams p, long long total) {
         Hash h{FNV_INIT, p.dbg_hash != nullptr};
 
         // ---- replay, recording each vertex --------------------------------
-        int rf[BM], rtex[BM], rse[BM];
-        uint32_t rfl[BM];
-        V3 rx[BM], rwe[BM], rwi[BM], resc[BM], rbeta[BM], rsecm[BM];
-        float rden[BM], rpb[BM], rte[BM], rsecc[BM], rsw[BM];
-#pragma unroll
-        for (int i = 0; i < BM; ++i) {
-            rf[i] = -1; rtex[i] = 0; rse[i] = -1; rfl[i] = 0;
-            rx[i] = rwe[i] = rwi[i] = resc[i] = rbeta[i] = rsecm[i] = V3{0.f, 0.f, 0.f};
-            rden[i] = rpb[i] = rte[i] = rsecc[i] = rsw[i] = 0.0f;
-        }
+        // Entries of a vertex are written when the replay reaches it and read only
+        // for k < nvtx under the flag that marks them (R_ENV: rwe, rden, rtex;
+        // R_CONT: rwi, rpb; R_ESC: resc; R_SEC: rsecm, rsecc; rse >= 0: rte, rsw).
+        const RecField<int, BM> rf{&rm, 0}, rtex{&rm, BM}, rse{&rm, 2 * BM};
+        const RecField<uint32_t, BM> rfl{&rm, 3 * BM};
+        const RecField<V3, BM> rx{&rm, 4 * BM}, rwe{&rm, 7 * BM}, rwi{&rm, 10 * BM}, resc{&rm, 13 * BM},
+            rbeta{&rm, 16 * BM}, rsecm{&rm, 19 * BM};
+        const RecField<float, BM> rden{&rm, 22 * BM}, rpb{&rm, 23 * BM}, rte{&rm, 24 * BM}, rsecc{&rm, 25 * BM},
+            rsw{&rm, 26 * BM};
         int nvtx = 0;
         {
             V3 o = ld3(c.eye), d = d0, beta{1.f, 1.f, 1.f};
@@ -283,6 +318,7 @@ k_adjoint(BwdParams p, long long total) {
                     h.push(code);
                 }
                 const bool continues = (k < p.B) || S.has_env;
+                put(rse, k - 1, -1);
                 if (want_secondary && continues && S.ne > 0 && *S.etotal > 0.0f) {
                     const float4 u = draw4(ctr, k, 3, key);
                     // the edge (-2: the hierarchy found no edge in front of the tangent

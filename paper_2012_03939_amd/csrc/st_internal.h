@@ -223,6 +223,7 @@ void launch_sample_radiance(const FwdParams& p, const float* L, long long total,
 
 struct BwdParams {
     int rec_split;           // the main pass is split: a records-only pass, then one that traces if they are stale
+    float* vrec;             // the adjoint's per-vertex replay records (adj_vrec_bytes)
     const DevScene* scenes;
     const DevCam* cams;
     const long long* qoff;   // [ncam+1] path offsets (processing order)
@@ -302,5 +303,12 @@ constexpr int TRACE_BLOCK = 256;
 static_assert(TRACE_BLOCK == TRAV_BLOCK, "traversal blocks size the LDS stack");
 // largest grid of the traversal kernels; the spill stack has one column per thread of it
 constexpr unsigned TRACE_GRID = 4096;
+// the adjoint's per-vertex replay records: 27 slots per vertex of BM vertices
+// for every thread of a grid of at most TRACE_GRID blocks of TRACE_BLOCK
+constexpr int ADJ_VREC_SLOTS = 27;
+inline int adj_bm(int B) { return B <= 1 ? 1 : B <= 2 ? 2 : B <= 3 ? 3 : 8; }
+inline size_t adj_vrec_bytes(int B) {
+    return sizeof(float) * (size_t)ADJ_VREC_SLOTS * adj_bm(B) * TRACE_GRID * TRACE_BLOCK;
+}
 
 } // namespace st
