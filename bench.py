@@ -33,7 +33,7 @@ ISSUED_FLOPS_PER_TEST = 45
 PEAK_FP32_VECTOR_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 # library launch names of the queue-streaming kernels -> their rocprofv3 names
-HBM_KERNELS = {"k_shade": "k_shade", "k_adjoint<3>": "k_adjoint<3, false, 1>",
+HBM_KERNELS = {"k_shade": "k_shade<false>", "k_adjoint<3>": "k_adjoint<3, false, 1>",
                "k_adjoint_sec<3>": "k_adjoint<3, true, 0>",
                "k_extend": "k_extend", "k_trace_pair": "k_trace_pair", "k_shadow": "k_shadow"}
 # Work-counter rows (st_read_work) that belong to one launch name alone: the

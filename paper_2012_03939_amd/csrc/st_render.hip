@@ -154,14 +154,17 @@ __host__ __device__ __forceinline__ bool shadow_fused(const FwdParams& p, const 
     return !ST_SHADOW_QUEUE && q.nent == 1 && !(p.dbg_hash || p.hash_by_q);
 }
 
-// shading of bounce k: escapes, next-event set-up and BRDF continuation
+// shading of bounce k: escapes, next-event set-up and BRDF continuation.
+// HASH: decision hashes are asked for (p.dbg_hash or p.hash_by_q); compiled
+// apart, because the hash state alone made the compiler spill 11 more dwords.
+template <bool HASH>
 __global__ void __launch_bounds__(SHADE_BLOCK) SHADE_OCC k_shade(FwdParams p, Queues q, int k) {
     __shared__ int resv[2 * (SHADE_BLOCK / 64 + 1)];
     const int n = q.cnt[k];
     float* const* r = q.ray[k & 1];
     float* const* rn = q.ray[(k + 1) & 1];
     const int stride = gridDim.x * blockDim.x;
-    const bool hashing = p.dbg_hash || p.hash_by_q;
+    constexpr bool hashing = HASH;
     // with the shadow sum fused into k_shadow, the shading record keeps only what
     // k_shadow reads (face, point)
     const bool fused = shadow_fused(p, q);
@@ -585,7 +588,10 @@ void launch_wavefront_bounces(const FwdParams& p, Queues& q, int n, int has_env_
     for (int k = 1; k <= last; ++k) {
         // bounce k is traced: shade it, then trace its shadow rays together with
         // the extension rays of bounce k + 1
-        ST_LAUNCH("k_shade", k_shade, dim3(grid_for(n, SHADE_BLOCK, gmax)), dim3(SHADE_BLOCK), 0, st, p, q, k);
+        if (p.dbg_hash || p.hash_by_q)
+            ST_LAUNCH("k_shade", k_shade<true>, dim3(grid_for(n, SHADE_BLOCK, gmax)), dim3(SHADE_BLOCK), 0, st, p, q, k);
+        else
+            ST_LAUNCH("k_shade", k_shade<false>, dim3(grid_for(n, SHADE_BLOCK, gmax)), dim3(SHADE_BLOCK), 0, st, p, q, k);
         if (hook) hook->tick();
         const bool shadow = k <= p.B, next = k < last;
         if (ST_PAIR_TRACE && shadow && next) {
