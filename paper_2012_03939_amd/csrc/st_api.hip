@@ -1226,6 +1226,8 @@ int st_render_backward(st_scene* sc, const st_camera* cams, int32_t ncam, int32_
         else
             launch_backward(p, sc->d.nv, sc->d.nf, cs.total_paths, cs.total_edges, TRACE_GRID, s);
     };
+    // the adjoint's preparation runs on this stream in either case, before any fork
+    if (adjoint) launch_backward_prep(p, sc->d.nf, cs.total_paths, s);
     LaunchHook hook;
     if (overlap) {
         if (FORK_AFTER_LAUNCHES <= 0) fork();

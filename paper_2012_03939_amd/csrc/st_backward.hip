@@ -1188,15 +1188,6 @@ template <int BM>
 static void launch_adjoint(const BwdParams& p, long long total_paths, int grid, const char* name,
                            const char* name_jobs, hipStream_t st) {
     const dim3 gd(gridb(total_paths, TRACE_BLOCK, grid)), bd(TRACE_BLOCK);
-    if (p.sec_mask) {
-        launch_fill_u32((uint32_t*)p.sec_njobs, 1, 0u, st);
-        launch_fill_u32((uint32_t*)p.sec_mask, (total_paths + 3) / 4, 0u, st);
-    }
-    if (p.rec_split && p.adj_list) {
-        launch_fill_u32((uint32_t*)p.adj_n, 1, 0u, st);
-        ST_LAUNCH("k_adj_list", k_adj_list, dim3(gridb(total_paths, 256 * ADJ_LIST_PER, 1 << 12)), dim3(256), 0, st,
-                  p.rec_face, total_paths, p.adj_list, p.adj_n);
-    }
     if (p.rec_split && (p.flags & ST_EDGE_SECONDARY_HIERARCHY))
         ST_LAUNCH(name, (k_adjoint<BM, false, 2>), gd, bd, 0, st, p, total_paths);
     else if (p.rec_split)
@@ -1211,15 +1202,34 @@ static void launch_adjoint(const BwdParams& p, long long total_paths, int grid, 
     }
 }
 
+// What the adjoint passes start from: cleared accumulators and job counters,
+// and the list of paths with a vertex.  Small kernels, launched on the caller's
+// stream before the adjoint forks to the second stream: there they would wait
+// for room behind the side paths' traversal, and the adjoint with them.
+void launch_backward_prep(const BwdParams& p, int nf, long long total_paths, hipStream_t st) {
+    if (!((p.flags & 5u) && total_paths > 0)) return;
+    launch_fill_u32((uint32_t*)p.facc, (long long)FACC_STRIDE * nf, 0u, st);
+    if (p.ntex != nf) launch_fill_u32((uint32_t*)p.macc, (long long)MACC_STRIDE * p.ntex, 0u, st);
+    if (p.sec_mask) {
+        launch_fill_u32((uint32_t*)p.sec_njobs, 1, 0u, st);
+        launch_fill_u32((uint32_t*)p.sec_mask, (total_paths + 3) / 4, 0u, st);
+    }
+    if (p.rec_split && p.adj_list) {
+        launch_fill_u32((uint32_t*)p.adj_n, 1, 0u, st);
+        ST_LAUNCH("k_adj_list", k_adj_list, dim3(gridb(total_paths, 256 * ADJ_LIST_PER, 1 << 12)), dim3(256), 0, st,
+                  p.rec_face, total_paths, p.adj_list, p.adj_n);
+    }
+}
+
 // the interior and secondary-edge terms into the per-face accumulators (and
-// secondary-edge atomics into dV); launch_face_gather adds them to dV and dmat
+// secondary-edge atomics into dV), after launch_backward_prep on the same
+// stream or one ordered after it; launch_face_gather adds them to dV and dmat
 void launch_backward(const BwdParams& p, int nv, int nf, long long total_paths, long long total_edges, int grid,
                      hipStream_t st) {
     (void)nv;
+    (void)nf;
     (void)total_edges;
     if ((p.flags & 5u) && total_paths > 0) {
-        launch_fill_u32((uint32_t*)p.facc, (long long)FACC_STRIDE * nf, 0u, st);
-        if (p.ntex != nf) launch_fill_u32((uint32_t*)p.macc, (long long)MACC_STRIDE * p.ntex, 0u, st);
         if (p.B <= 1) launch_adjoint<1>(p, total_paths, grid, "k_adjoint<1>", "k_adjoint_sec<1>", st);
         else if (p.B <= 2) launch_adjoint<2>(p, total_paths, grid, "k_adjoint<2>", "k_adjoint_sec<2>", st);
         else if (p.B <= 3) launch_adjoint<3>(p, total_paths, grid, "k_adjoint<3>", "k_adjoint_sec<3>", st);

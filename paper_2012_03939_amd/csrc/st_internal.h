@@ -276,6 +276,7 @@ struct BwdParams {
     int* adj_n;
 };
 
+void launch_backward_prep(const BwdParams& p, int nf, long long total_paths, hipStream_t st);
 void launch_backward(const BwdParams& p, int nv, int nf, long long total_paths, long long total_edges, int grid,
                      hipStream_t st);
 void launch_face_gather(const BwdParams& p, int nv, hipStream_t st);
