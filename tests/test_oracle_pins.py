@@ -1,6 +1,7 @@
 """Pins of the FP64 oracle against facts that do not come from the oracle itself:
 numpy's Philox, quadrature identities of the microfacet model, the closed-form
-radiance of a Lambertian plane under a point light, the white furnace, brute
+radiance of a Lambertian plane under a point light, the white furnace, the
+hemisphere integral of a plane under a non-constant environment, brute
 force intersection, central finite differences, and closed-form edge
 derivatives (projected triangle area, projected solid angle of a polygon).
 CPU only."""
@@ -431,6 +432,74 @@ def test_white_furnace(bounces, kd):
     m = vals.mean(axis=0)
     se = vals.std(axis=0) / math.sqrt(vals.shape[0])
     assert np.all(np.abs(m - kd) < 4 * se + 1e-9), (m, se)
+
+
+# --------------------------------------------------------------------------
+# environment sample and BRDF sample combined (balance heuristic) under a
+# non-constant map: one bounce off a plane that sees only the upper hemisphere.
+# The expectation is the hemisphere integral of BRDF x map x cosine, so any
+# weight or pdf that is off for some directions (a wrong texel, a missing
+# Jacobian, weights not summing to one) biases the mean; the constant map of
+# the furnace test cannot show that.
+# --------------------------------------------------------------------------
+
+def _sky_integral(env, wo, m, sub):
+    """sum over the texels above the horizon of L * int f(wi, wo) cos dwi,
+    midpoint rule on sub x sub cells of exact solid angle (rows at
+    theta = pi r / he, columns at phi = 2 pi c / we, y up)."""
+    he, we = env.shape[:2]
+    n = np.array([0.0, 1.0, 0.0])
+    dph = 2 * np.pi / we / sub
+    tot = np.zeros(3)
+    for r in range(he // 2):
+        for i in range(sub):
+            ta = np.pi * (r + i / sub) / he
+            tb = np.pi * (r + (i + 1) / sub) / he
+            th = 0.5 * (ta + tb)
+            dom = dph * (math.cos(ta) - math.cos(tb))
+            for c in range(we):
+                for j in range(sub):
+                    ph = 2 * np.pi * (c + (j + 0.5) / sub) / we
+                    wi = np.array([math.sin(th) * math.sin(ph), math.cos(th), math.sin(th) * math.cos(ph)])
+                    tot += env[r, c].astype(np.float64) * O.brdf(wi, wo, n, m) * wi[1] * dom
+    return tot
+
+
+@pytest.mark.parametrize("kind,sampler", [("lambert", ""), ("glossy", ""), ("glossy", "vndf"), ("lambert", "alias")])
+def test_environment_estimator_matches_hemisphere_integral(kind, sampler):
+    rng = np.random.default_rng(21)
+    env = S.gaussian_lobe_envmap(rng, 16, 8, nlobes=8, base=0.1)
+    he, we = env.shape[:2]
+    sky = env[: he // 2].astype(np.float64).mean(axis=2)
+    assert sky.max() > 5 * sky.min()     # the map varies where the plane looks
+    if kind == "lambert":
+        m = np.array([0.8, 0.6, 0.4, 0.0, 0.0, 0.0, 0.3])
+        to = math.radians(20.0)
+    else:
+        m = np.array([0.05, 0.05, 0.05, 0.8, 0.6, 0.4, 0.25])
+        to = math.radians(50.0)
+    V = np.array([[-5, 0, -5], [5, 0, -5], [5, 0, 5], [-5, 0, 5]], np.float32)
+    F = np.array([[0, 2, 1], [0, 3, 2]], np.int32)          # normal +y
+    sc = O.OracleScene(V, F, np.tile(m.astype(np.float32), (2, 1)), None, env)
+    sc.set_vndf(sampler == "vndf")
+    sc.set_env_alias(sampler == "alias")
+    # a narrow camera: every sample leaves the plane towards the same wo
+    wo = np.array([0.0, math.cos(to), math.sin(to)])
+    cam = S.Camera(tuple(3.0 * wo), (0, 0, 0), (0, 1, 0), 0.2, 4, 4)
+    rgb, _ = sc.render_samples([cam], 65536, 1, seed=5)
+    vals = rgb.reshape(-1, 3)
+    mean = vals.mean(axis=0)
+    se = vals.std(axis=0) / math.sqrt(vals.shape[0])
+    if kind == "lambert":
+        # closed form: kd / pi * sum L_t * int_texel cos = dphi (sin^2 tb - sin^2 ta) / 2
+        thr = np.pi * np.arange(he // 2 + 1) / he
+        w_row = (2 * np.pi / we) * 0.5 * (np.sin(thr[1:]) ** 2 - np.sin(thr[:-1]) ** 2)
+        expect = m[:3] / np.pi * (env[: he // 2].astype(np.float64) * w_row[:, None, None]).sum(axis=(0, 1))
+        assert np.allclose(_sky_integral(env, wo, m, 8), expect, rtol=1e-3, atol=0)
+    else:
+        expect = _sky_integral(env, wo, m, 12)
+    assert np.all(se < 0.01 * expect), (se, expect)
+    assert np.all(np.abs(mean - expect) < 4 * se), (mean, expect, se)
 
 
 # --------------------------------------------------------------------------
