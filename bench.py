@@ -69,7 +69,8 @@ def measured_counters(kernel: str):
         simd_cycles = k["mean_dispatch_ms_under_counters"] * 1e-3 * CLOCK_HZ * CU_COUNT * SIMDS_PER_CU
         issue = k["sq_insts_valu_per_dispatch"] * VALU_CYCLES_PER_WAVE_INST / simd_cycles
     return {"traffic": k["hbm_bytes_per_dispatch"], "valu_issue_utilisation": issue,
-            "valu_lane_utilisation": k.get("valu_lane_utilisation")}
+            "valu_lane_utilisation": k.get("valu_lane_utilisation"),
+            "ms_under_counters": k.get("mean_dispatch_ms_under_counters")}
 
 
 def parse():
@@ -421,7 +422,10 @@ def main():
         traversal[{"k_extend": "extension_rays", "k_shadow": "shadow_rays"}.get(k, k)] = e
     mc = measured_counters(dom_name)
     # queue-streaming kernels: HBM bytes per launch (counters of these sources)
-    # over their live mean launch time, against a measured streaming copy
+    # over their live mean launch time, against a measured streaming copy; and
+    # the same bytes over the mean dispatch time in the counter run, where
+    # rocprofv3 serialises the dispatches (no kernel shares the GPU with another,
+    # as the adjoint and the side paths do in the step)
     copy_gbs = B.copy_bandwidth()
     hbm = {"copy_gbs": copy_gbs, "peak_gbs": PEAK_HBM_GBS, "kernels": {}}
     for lk, pk in HBM_KERNELS.items():
@@ -433,6 +437,11 @@ def main():
         hbm["kernels"][lk] = {"avg_launch_ms": kms / kn, "hbm_bytes_per_launch": c["traffic"] if c else None,
                               "gbs": gbs, "frac_of_copy": gbs / copy_gbs if gbs else None,
                               "frac_of_peak": gbs / PEAK_HBM_GBS if gbs else None}
+        rms = c.get("ms_under_counters") if c else None
+        if rms:
+            rg = c["traffic"] / (rms * 1e-3) / 1e9
+            hbm["kernels"][lk].update({"rocprof_ms": rms, "rocprof_gbs": rg, "rocprof_frac_of_copy": rg / copy_gbs,
+                                       "rocprof_frac_of_peak": rg / PEAK_HBM_GBS})
     # the same step at the workload's own 32 spp, and with every main-path ray traced again in the adjoint
     ms32 = timed_steps(3, spp=2 * spp)
     progress(f"{2 * spp} spp step: {ms32:.2f} ms")
